@@ -1,0 +1,229 @@
+/*
+ * vplmc -- sparse sampling and completion of VPL lighting matrices on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Huo, Wang, Liu, Bao, "Sparse Sampling and Completion for Light
+ * Transport in VPL-based Rendering", arXiv 2202.12567.
+ *
+ * The lighting matrix A has one row per surface point (pixel) and one
+ * column per light; the image is the sum of its columns (Sec. 3).  The
+ * rows are partitioned into slices and the columns of each slice are the
+ * nodes of a light cut (Sec. 3, steps 1-3).  For every slice the library
+ * samples entries in two passes (Sec. 5), evaluates them with shadow rays,
+ * completes the slice matrix by non-negative ADM factorisation M = X Y
+ * (Appendix A) and renders I(s) = X (Y e) (Sec. 3, step 5).
+ *
+ * Conventions for every call:
+ *  - Return 0 on success or a negative VPLMC_E* code; no exception crosses
+ *    this boundary and nothing aborts.  The message of the last failure on
+ *    the calling thread is returned by vplmc_last_error().
+ *  - Pointers are DEVICE pointers on the context's device unless a comment
+ *    says HOST.  Arrays are contiguous structure-of-arrays, float32 / int32.
+ *  - The caller owns every buffer it passes (inputs, outputs, workspace).
+ *    The library owns only what its create calls return (context, plan)
+ *    and the occluder BVH it uploads in vplmc_set_occluders.
+ *  - All device work is enqueued on the context's stream.  Only calls that
+ *    fill HOST outputs synchronise that stream.
+ *  - Arguments are validated on the host before anything is launched.
+ */
+#ifndef VPLMC_H
+#define VPLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VPLMC_VERSION 100
+
+#define VPLMC_OK 0
+#define VPLMC_EINVAL (-1)       /* invalid argument or shape                  */
+#define VPLMC_ENOMEM (-2)       /* host or device allocation failed           */
+#define VPLMC_EHIP (-3)         /* a HIP runtime call failed                  */
+#define VPLMC_EUNSUPPORTED (-4) /* valid request this build cannot serve      */
+
+/* Limits of one slice (packed entry index (i << 16) | j, Appendix A ranks). */
+#define VPLMC_MAX_ROWS 65535
+#define VPLMC_MAX_COLS 65535
+#define VPLMC_MAX_RANK 32
+
+/* vplmc_params.flags */
+#define VPLMC_FIXED_ITERS 1     /* ignore tol: run exactly max_iter ADM iterations */
+
+/* per-slice result flags (vplmc_read_stats) -- outcomes, not errors */
+#define VPLMC_SLICE_ALL_ZERO 1      /* every sampled entry is 0: radiance 0      */
+#define VPLMC_SLICE_NOT_CONVERGED 2 /* ADM stopped at max_iter above tol         */
+#define VPLMC_SLICE_SHORTFALL 4     /* second pass hit its attempt cap           */
+
+/* Surface points: rows of the lighting matrix (Sec. 3).  Position, unit
+ * normal, diffuse albedo; ks / phong_e (normalised Phong specular albedo and
+ * exponent) may both be NULL for Lambertian points; vx/vy/vz (unit direction
+ * to the viewer) may all be NULL for +z. */
+typedef struct {
+    int32_t m;
+    const float *px, *py, *pz;
+    const float *nx, *ny, *nz;
+    const float *kd_r, *kd_g, *kd_b;
+    const float *ks, *phong_e;
+    const float *vx, *vy, *vz;
+} vplmc_points;
+
+/* Point lights: VPLs, or the representatives of light-cut clusters.
+ * Position, unit emission normal, RGB intensity. */
+typedef struct {
+    int32_t n;
+    const float *x, *y, *z;
+    const float *nx, *ny, *nz;
+    const float *ir, *ig, *ib;
+} vplmc_lights;
+
+/* Light cut: cluster c holds VPLs members[offsets[c] .. offsets[c+1]). */
+typedef struct {
+    int32_t n_clusters;
+    const int32_t *offsets; /* n_clusters + 1 */
+    const int32_t *members; /* offsets[n_clusters] VPL ids */
+} vplmc_cut;
+
+/* Method parameters (Sec. 5 rates, Appendix A constants). */
+typedef struct {
+    uint64_t seed;        /* key of every random draw                          */
+    int32_t pass1_ppm;    /* first-pass rate, parts per million of m' n'       */
+    int32_t pass2_ppm;    /* second-pass rate, parts per million of m' n'      */
+    int32_t max_iter;     /* ADM iteration cap (paper: 100)                    */
+    int32_t flags;        /* VPLMC_FIXED_ITERS                                 */
+    float tol;            /* ADM stop: relative residual on the samples        */
+    float alpha0, beta0;  /* penalties alpha = alpha0 3n'/q, beta = beta0 m'/q */
+    float gamma;          /* multiplier step, in (0, 1.618)                    */
+    float r_min;          /* distance clamp of the geometry term               */
+    float ray_eps;        /* shadow-ray origin offset along the normal         */
+} vplmc_params;
+
+typedef struct vplmc_ctx vplmc_ctx;
+typedef struct vplmc_plan vplmc_plan;
+
+/* Per-slice layout of one frame's intermediate data inside the workspace
+ * (byte offsets are relative to the start of each region). */
+typedef struct {
+    int32_t m, n, q;         /* rows, cut columns, rank                           */
+    int32_t N1, N2;          /* first-pass count and second-pass target           */
+    int64_t off1, off2;      /* element offsets into OMEGA1/VAL1, OMEGA2/VAL2     */
+    int64_t off_omega;       /* element offset into CSR_* / CSC_* (N1 + N2 each)  */
+    int64_t off_col;         /* element offset into per-column regions            */
+    int64_t off_row;         /* element offset into ROW_PTR (m + 1 each)          */
+    int64_t off_colptr;      /* element offset into COL_PTR (n + 1 each)          */
+    int64_t off_x;           /* element offset into X / XP / LAMBDA (m q each)    */
+    int64_t off_y;           /* element offset into Y / YP / PI (n 3 q each)      */
+} vplmc_slice_info;
+
+/* Workspace regions readable after vplmc_render (for inspection and tests). */
+enum {
+    VPLMC_R_LIGHTS = 0,   /* float[9][n_clusters]: x y z nx ny nz ir ig ib of the cluster lights */
+    VPLMC_R_REP,          /* int32[n_clusters]: representative VPL                         */
+    VPLMC_R_BBOX,         /* float[6][n_clusters]: member bbox lo xyz, hi xyz              */
+    VPLMC_R_OMEGA1,       /* uint32 (i << 16 | j): first-pass entries, draw order          */
+    VPLMC_R_VAL1,         /* float[3] per first-pass entry                                 */
+    VPLMC_R_OMEGA2,       /* uint32: second-pass entries, acceptance order                 */
+    VPLMC_R_VAL2,         /* float[3] per second-pass entry                                */
+    VPLMC_R_WEIGHTS,      /* uint32 per (slice, column): quantised importance g            */
+    VPLMC_R_COLMIN,       /* float per (slice, column): min of R+G+B over the first pass   */
+    VPLMC_R_COLMAX,       /* float per (slice, column): max                                */
+    VPLMC_R_COLCNT,       /* int32 per (slice, column): first-pass observations            */
+    VPLMC_R_ROW_PTR,      /* int32[m + 1] per slice: CSR row pointers                      */
+    VPLMC_R_CSR_COL,      /* int32 per entry: column, CSR order (row-major)                */
+    VPLMC_R_CSR_VAL,      /* float[3] per entry, CSR order                                 */
+    VPLMC_R_COL_PTR,      /* int32[n + 1] per slice: CSC column pointers                   */
+    VPLMC_R_CSC_ROW,      /* int32 per entry: row, CSC order (column-major)                */
+    VPLMC_R_CSC_VAL,      /* float[3] per entry, CSC order                                 */
+    VPLMC_R_X,            /* float[m][q] per slice: final X (initial X when max_iter = 0)  */
+    VPLMC_R_Y,            /* float[n][3][q] per slice: final Y (row c n + j of the paper's Y^T) */
+    VPLMC_R_SLICE_SCALE,  /* float per slice: s0, the mean sampled value M is divided by   */
+    VPLMC_R_COUNT
+};
+
+/* ---- library ---------------------------------------------------------- */
+int vplmc_version(void);
+const char *vplmc_last_error(void);
+/* Paper defaults: 5% + 5%, max_iter 100, tol 1e-3, alpha0 = beta0 = 0.1,
+ * gamma 1.6, r_min 0.05, ray_eps 1e-4, seed 1. */
+int vplmc_default_params(vplmc_params *out /* HOST */);
+
+/* ---- context: device + stream ---------------------------------------- */
+/* stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream), or
+ * NULL for the null stream. */
+int vplmc_create(int device, void *stream, vplmc_ctx **out /* HOST */);
+int vplmc_destroy(vplmc_ctx *ctx);
+int vplmc_set_stream(vplmc_ctx *ctx, void *stream);
+
+/* Occluder spheres (centre, radius; HOST arrays).  Builds a BVH on the host
+ * and uploads it; shadow rays of every later call test against it
+ * (Sec. 6 ray casting; spheres stand in for the paper's triangles).
+ * n = 0 removes all occluders. */
+int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float *cy,
+                        const float *cz, const float *r);
+
+/* ---- frame plan (host only: no device work) ---------------------------- */
+/* Slice s owns points pt_ids[pt_offsets[s] .. pt_offsets[s+1]) and cut
+ * clusters cl_ids[cl_offsets[s] .. cl_offsets[s+1]) and completes at rank
+ * rank[s].  All three arrays are HOST (n_slices + 1, n_slices + 1, n_slices).
+ * Rejects m' > VPLMC_MAX_ROWS, n' > VPLMC_MAX_COLS, q < 1,
+ * q > min(VPLMC_MAX_RANK, m', n'), rates outside [0, 10^6] or summing above it. */
+int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t *cl_offsets,
+                      const int32_t *rank, int32_t n_clusters, const vplmc_params *params,
+                      vplmc_plan **out /* HOST */);
+int vplmc_plan_destroy(vplmc_plan *plan);
+int vplmc_workspace_size(const vplmc_plan *plan, size_t *bytes /* HOST */);
+int vplmc_plan_slice(const vplmc_plan *plan, int32_t s, vplmc_slice_info *out /* HOST */);
+int vplmc_plan_region(const vplmc_plan *plan, int32_t region, size_t *offset /* HOST */,
+                      size_t *bytes /* HOST */);
+
+/* ---- the method ---------------------------------------------------------
+ * One frame (Sec. 3 steps 4-5, Sec. 5, Appendix A):
+ *   cluster table of the cut (Sec. 4: I_f = sum of member intensities,
+ *   position/normal of one member) -> first pass (uniform distinct entries)
+ *   -> entries with shadow rays -> g(j) = max - min of the first pass ->
+ *   second pass by g -> CSR/CSC of all samples -> ADM completion of the
+ *   stacked m' x 3n' slice matrix [M_R | M_G | M_B] -> I(s) = X (Y e).
+ * pt_ids / cl_ids: DEVICE int32 arrays of the layout given to the plan.
+ * workspace: DEVICE, at least vplmc_workspace_size bytes, 256-byte aligned.
+ * radiance: DEVICE float[m][3]; points outside every slice are set to 0.
+ * params must equal, in its rates, the params given to the plan. */
+int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points,
+                 const vplmc_lights *vpls, const vplmc_cut *cut, const int32_t *pt_ids,
+                 const int32_t *cl_ids, const vplmc_params *params, void *workspace,
+                 size_t workspace_bytes, float *radiance);
+
+/* Per-slice outcome of the last vplmc_render on this workspace (synchronises).
+ * HOST arrays of n_slices each; any may be NULL. */
+int vplmc_read_stats(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace,
+                     int32_t *iters, int32_t *flags, float *resid, int32_t *n2_accepted);
+
+/* ---- building blocks used by the frame, exposed for tests and tools ---- */
+/* Cluster table (Sec. 4): rep[c], lights float[9][n_clusters] (x y z nx ny nz
+ * ir ig ib), bbox float[6][n_clusters].  All DEVICE outputs. */
+int vplmc_cluster_table(vplmc_ctx *ctx, const vplmc_lights *vpls, const vplmc_cut *cut,
+                        uint64_t seed, int32_t *rep, float *lights, float *bbox);
+
+/* Entries A(point_ids[k], light_ids[k]) (Sec. 3) for n_pairs pairs, with
+ * shadow rays against the occluders: out float[n_pairs][3]. */
+int vplmc_eval_pairs(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lights *lights,
+                     int64_t n_pairs, const int32_t *point_ids, const int32_t *light_ids,
+                     const vplmc_params *params, float *out);
+
+/* Brute-force column sum over every light (the paper's reference images,
+ * Sec. 6): out double[n_out][3] for points point_ids[0 .. n_out) (or points
+ * 0 .. n_out-1 if point_ids is NULL).  FP32 entries, FP64 sums. */
+int vplmc_brute_force(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lights *lights,
+                      int32_t n_out, const int32_t *point_ids, const vplmc_params *params,
+                      double *out);
+
+/* Philox4x64-10 (Salmon et al., SC'11): out[4k .. 4k+3] =
+ * Philox(key, ctr[4k .. 4k+3]); ctr/out DEVICE uint64[4 n]. */
+int vplmc_philox4x64(vplmc_ctx *ctx, uint64_t key0, uint64_t key1, const uint64_t *ctr,
+                     int64_t n, uint64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VPLMC_H */

@@ -1,0 +1,210 @@
+"""Python binding of libvplmc (include/vplmc.h).
+
+Argument marshalling only: PyTorch provides device memory and the stream,
+and every step of the method runs in the library's HIP kernels.  The
+function names follow the C entry points without the ``vplmc_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as N
+from ._native import check
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else int(t.data_ptr()))
+
+
+def version():
+    return N.load().vplmc_version()
+
+
+def default_params(**kw):
+    p = N.Params()
+    check(N.load().vplmc_default_params(ctypes.byref(p)))
+    for k, v in kw.items():
+        if k == "fixed_iters":
+            p.flags = (p.flags | N.FIXED_ITERS) if v else (p.flags & ~N.FIXED_ITERS)
+            continue
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+class Context:
+    """Device + stream (vplmc_create).  The stream defaults to torch's current stream."""
+
+    def __init__(self, device=0, stream=None):
+        lib = N.load()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        check(lib.vplmc_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def set_occluders(self, spheres):
+        cx, cy, cz, r = (np.ascontiguousarray(spheres[k], dtype=np.float32) for k in ("cx", "cy", "cz", "r"))
+        f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        check(N.load().vplmc_set_occluders(self.h, int(cx.shape[0]), f(cx), f(cy), f(cz), f(r)))
+
+    def close(self):
+        if self.h:
+            N.load().vplmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceScene:
+    """Device copies of a scene's arrays plus the C structs that point at them."""
+
+    POINT_KEYS = ("px", "py", "pz", "nx", "ny", "nz", "kd_r", "kd_g", "kd_b", "ks", "phong_e")
+    LIGHT_KEYS = ("x", "y", "z", "nx", "ny", "nz", "ir", "ig", "ib")
+
+    def __init__(self, scene, device):
+        dev = torch.device(device)
+        t = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+        self.scene = scene
+        self.pts = {k: t(scene.points[k]) for k in self.POINT_KEYS}
+        self.vpl = {k: t(scene.vpls[k]) for k in self.LIGHT_KEYS}
+        self.cut_offsets = t(scene.cut_offsets, torch.int32)
+        self.cut_members = t(scene.cut_members, torch.int32)
+        self.pt_ids = t(scene.pt_ids, torch.int32)
+        self.cl_ids = t(scene.cl_ids, torch.int32)
+        self.m = scene.m
+        self.n_vpls = scene.n
+        self.n_clusters = scene.n_clusters
+        self.points_c = N.Points(self.m, *[_ptr(self.pts[k]) for k in self.POINT_KEYS], None, None, None)
+        self.vpls_c = lights_struct(self.vpl)
+        self.cut_c = N.Cut(self.n_clusters, _ptr(self.cut_offsets), _ptr(self.cut_members))
+
+
+def lights_struct(d):
+    """C struct for a dict of 9 light planes (x y z nx ny nz ir ig ib) or a (9, n) tensor."""
+    if isinstance(d, torch.Tensor):
+        d = {k: d[i] for i, k in enumerate(DeviceScene.LIGHT_KEYS)}
+    n = int(d["x"].shape[0])
+    return N.Lights(n, *[_ptr(d[k]) for k in DeviceScene.LIGHT_KEYS])
+
+
+class Plan:
+    """Frame plan (vplmc_plan_create): host-only layout of every slice."""
+
+    def __init__(self, scene, params):
+        lib = N.load()
+        self.n_slices = scene.n_slices
+        self.n_clusters = scene.n_clusters
+        pt = np.ascontiguousarray(scene.pt_offsets, dtype=np.int32)
+        cl = np.ascontiguousarray(scene.cl_offsets, dtype=np.int32)
+        rk = np.ascontiguousarray(scene.rank, dtype=np.int32)
+        h = ctypes.c_void_p()
+        f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        check(lib.vplmc_plan_create(self.n_slices, f(pt), f(cl), f(rk), self.n_clusters, ctypes.byref(params),
+                                    ctypes.byref(h)))
+        self.h = h
+        sz = ctypes.c_size_t()
+        check(lib.vplmc_workspace_size(h, ctypes.byref(sz)))
+        self.workspace_bytes = int(sz.value)
+
+    def slice_info(self, s):
+        info = N.SliceInfo()
+        check(N.load().vplmc_plan_slice(self.h, s, ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in N.SliceInfo._fields_}
+
+    def region(self, name):
+        off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+        check(N.load().vplmc_plan_region(self.h, N.R[name], ctypes.byref(off), ctypes.byref(nb)))
+        return int(off.value), int(nb.value)
+
+    def close(self):
+        if self.h:
+            N.load().vplmc_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace(plan, device):
+    return torch.empty(max(plan.workspace_bytes, 256), dtype=torch.uint8, device=device)
+
+
+def region_view(plan, ws, name, dtype):
+    off, nb = plan.region(name)
+    return ws[off:off + nb].view(dtype)
+
+
+def render(ctx, plan, ds, params, ws, radiance=None):
+    """One frame (vplmc_render); returns radiance float32 [m, 3] on the device."""
+    if radiance is None:
+        radiance = torch.empty((ds.m, 3), dtype=torch.float32, device=ws.device)
+    check(N.load().vplmc_render(ctx.h, plan.h, ctypes.byref(ds.points_c), ctypes.byref(ds.vpls_c),
+                                ctypes.byref(ds.cut_c), _ptr(ds.pt_ids), _ptr(ds.cl_ids), ctypes.byref(params),
+                                _ptr(ws), ws.numel(), _ptr(radiance)))
+    return radiance
+
+
+def read_stats(ctx, plan, ws):
+    S = plan.n_slices
+    iters = np.zeros(S, np.int32)
+    flags = np.zeros(S, np.int32)
+    resid = np.zeros(S, np.float32)
+    n2 = np.zeros(S, np.int32)
+    f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    check(N.load().vplmc_read_stats(ctx.h, plan.h, _ptr(ws), f(iters), f(flags), f(resid), f(n2)))
+    return dict(iters=iters, flags=flags, resid=resid, n2=n2)
+
+
+def cluster_table(ctx, ds, seed):
+    nc = ds.n_clusters
+    dev = ds.pt_ids.device
+    rep = torch.empty(nc, dtype=torch.int32, device=dev)
+    lights = torch.empty((9, nc), dtype=torch.float32, device=dev)
+    bbox = torch.empty((6, nc), dtype=torch.float32, device=dev)
+    check(N.load().vplmc_cluster_table(ctx.h, ctypes.byref(ds.vpls_c), ctypes.byref(ds.cut_c), int(seed),
+                                       _ptr(rep), _ptr(lights), _ptr(bbox)))
+    return rep, lights, bbox
+
+
+def eval_pairs(ctx, ds, lights, point_ids, light_ids, params):
+    n = int(point_ids.shape[0])
+    out = torch.empty((n, 3), dtype=torch.float32, device=point_ids.device)
+    L = lights_struct(lights)
+    check(N.load().vplmc_eval_pairs(ctx.h, ctypes.byref(ds.points_c), ctypes.byref(L), n, _ptr(point_ids),
+                                    _ptr(light_ids), ctypes.byref(params), _ptr(out)))
+    return out
+
+
+def brute_force(ctx, ds, lights, params, point_ids=None, n_out=None):
+    dev = ds.pt_ids.device
+    if point_ids is not None:
+        n_out = int(point_ids.shape[0])
+    elif n_out is None:
+        n_out = ds.m
+    out = torch.empty((n_out, 3), dtype=torch.float64, device=dev)
+    L = lights_struct(lights)
+    check(N.load().vplmc_brute_force(ctx.h, ctypes.byref(ds.points_c), ctypes.byref(L), n_out,
+                                     _ptr(point_ids), ctypes.byref(params), _ptr(out)))
+    return out
+
+
+def philox4x64(ctx, key0, key1, ctr):
+    """ctr: int64 tensor (n, 4) holding uint64 bit patterns; returns the same layout."""
+    n = int(ctr.shape[0])
+    out = torch.empty_like(ctr)
+    check(N.load().vplmc_philox4x64(ctx.h, key0, key1, _ptr(ctr), n, _ptr(out)))
+    return out

@@ -1,0 +1,504 @@
+// C ABI of the library: argument validation (host only, before any launch),
+// frame planning and workspace layout, and the launch sequence of a frame.
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "vplmc_internal.h"
+
+namespace vplmc {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+int set_error(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_error(hipError_t e, const char *what) {
+    return set_error(VPLMC_EHIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+namespace {
+
+int64_t count_from_ppm(int64_t ppm, int64_t D) { return (ppm * D + 500000) / 1000000; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool bad_ptrs_points(const vplmc_points *p) {
+    if (!p->px || !p->py || !p->pz || !p->nx || !p->ny || !p->nz || !p->kd_r || !p->kd_g || !p->kd_b) return true;
+    if ((p->ks == nullptr) != (p->phong_e == nullptr)) return true;
+    if (!((p->vx && p->vy && p->vz) || (!p->vx && !p->vy && !p->vz))) return true;
+    return false;
+}
+
+bool bad_ptrs_lights(const vplmc_lights *l) {
+    return !l->x || !l->y || !l->z || !l->nx || !l->ny || !l->nz || !l->ir || !l->ig || !l->ib;
+}
+
+int check_params(const vplmc_params *p) {
+    if (!p) return set_error(VPLMC_EINVAL, "params is NULL");
+    if (p->pass1_ppm < 0 || p->pass2_ppm < 0 || p->pass1_ppm > 1000000 || p->pass2_ppm > 1000000 ||
+        (int64_t)p->pass1_ppm + p->pass2_ppm > 1000000)
+        return set_error(VPLMC_EINVAL, "sampling rates must be in [0, 1e6] ppm and sum to at most 1e6 (got %d + %d)",
+                         p->pass1_ppm, p->pass2_ppm);
+    if (p->max_iter < 0) return set_error(VPLMC_EINVAL, "max_iter must be >= 0 (got %d)", p->max_iter);
+    if (!(p->alpha0 > 0.f) || !(p->beta0 > 0.f))
+        return set_error(VPLMC_EINVAL, "alpha0 and beta0 must be > 0");
+    if (!(p->gamma > 0.f && p->gamma < 1.618034f))
+        return set_error(VPLMC_EINVAL, "gamma must be in (0, 1.618) (got %g)", (double)p->gamma);
+    if (!(p->tol >= 0.f)) return set_error(VPLMC_EINVAL, "tol must be >= 0");
+    if (!(p->r_min > 0.f) || !(p->ray_eps >= 0.f)) return set_error(VPLMC_EINVAL, "r_min must be > 0, ray_eps >= 0");
+    if (p->flags & ~VPLMC_FIXED_ITERS) return set_error(VPLMC_EINVAL, "unknown flags 0x%x", p->flags);
+    return VPLMC_OK;
+}
+
+int rank_bucket(int q) {
+    switch (q) {
+        case 4: return 0;
+        case 8: return 1;
+        case 16: return 2;
+        case 32: return 3;
+        default: return -1;
+    }
+}
+
+template <typename T>
+T *region(void *ws, const vplmc_plan *plan, int r) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + plan->layout.off[r]);
+}
+
+}  // namespace
+}  // namespace vplmc
+
+using namespace vplmc;
+
+extern "C" {
+
+int vplmc_version(void) { return VPLMC_VERSION; }
+
+const char *vplmc_last_error(void) { return g_err; }
+
+int vplmc_default_params(vplmc_params *out) {
+    if (!out) return set_error(VPLMC_EINVAL, "out is NULL");
+    memset(out, 0, sizeof(*out));
+    out->seed = 1;
+    out->pass1_ppm = 50000;
+    out->pass2_ppm = 50000;
+    out->max_iter = 100;
+    out->flags = 0;
+    out->tol = 1e-3f;
+    out->alpha0 = 0.1f;
+    out->beta0 = 0.1f;
+    out->gamma = 1.6f;
+    out->r_min = 0.05f;
+    out->ray_eps = 1e-4f;
+    return VPLMC_OK;
+}
+
+int vplmc_create(int device, void *stream, vplmc_ctx **out) {
+    if (!out) return set_error(VPLMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return set_error(VPLMC_EHIP, "no HIP device available");
+    if (device < 0 || device >= count) return set_error(VPLMC_EINVAL, "device %d out of range [0, %d)", device, count);
+    VPLMC_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    VPLMC_HIP(hipGetDeviceProperties(&prop, device));
+    vplmc_ctx *ctx = new (std::nothrow) vplmc_ctx();
+    if (!ctx) return set_error(VPLMC_ENOMEM, "context allocation failed");
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    ctx->n_cu = prop.multiProcessorCount;
+    *out = ctx;
+    return VPLMC_OK;
+}
+
+int vplmc_destroy(vplmc_ctx *ctx) {
+    if (!ctx) return VPLMC_OK;
+    if (ctx->bvh_mem) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->bvh_mem);
+    }
+    delete ctx;
+    return VPLMC_OK;
+}
+
+int vplmc_set_stream(vplmc_ctx *ctx, void *stream) {
+    if (!ctx) return set_error(VPLMC_EINVAL, "ctx is NULL");
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return VPLMC_OK;
+}
+
+int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float *cy, const float *cz,
+                        const float *r) {
+    if (!ctx) return set_error(VPLMC_EINVAL, "ctx is NULL");
+    if (n < 0) return set_error(VPLMC_EINVAL, "n must be >= 0");
+    if (n > 0 && (!cx || !cy || !cz || !r)) return set_error(VPLMC_EINVAL, "sphere arrays must be non-NULL");
+    for (int k = 0; k < n; ++k)
+        if (!(r[k] > 0.f) || !std::isfinite(cx[k]) || !std::isfinite(cy[k]) || !std::isfinite(cz[k]))
+            return set_error(VPLMC_EINVAL, "sphere %d: radius must be > 0 and centre finite", k);
+    std::vector<BvhNode> nodes;
+    std::vector<float> sph;
+    build_bvh(n, cx, cy, cz, r, nodes, sph);
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    if (ctx->bvh_mem) {
+        VPLMC_HIP(hipStreamSynchronize(ctx->stream));
+        VPLMC_HIP(hipFree(ctx->bvh_mem));
+        ctx->bvh_mem = nullptr;
+    }
+    ctx->bvh = Bvh{};
+    if (n == 0) return VPLMC_OK;
+    const size_t nb = align256(nodes.size() * sizeof(BvhNode));
+    const size_t sb = sph.size() * sizeof(float);
+    void *mem = nullptr;
+    if (hipMalloc(&mem, nb + sb) != hipSuccess) return set_error(VPLMC_ENOMEM, "BVH allocation failed");
+    ctx->bvh_mem = mem;
+    VPLMC_HIP(hipMemcpy(mem, nodes.data(), nodes.size() * sizeof(BvhNode), hipMemcpyHostToDevice));
+    VPLMC_HIP(hipMemcpy(static_cast<char *>(mem) + nb, sph.data(), sb, hipMemcpyHostToDevice));
+    ctx->bvh.nodes = static_cast<const BvhNode *>(mem);
+    ctx->bvh.spheres = reinterpret_cast<const float4 *>(static_cast<char *>(mem) + nb);
+    ctx->bvh.n_nodes = (int32_t)nodes.size();
+    ctx->bvh.n_spheres = n;
+    return VPLMC_OK;
+}
+
+int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t *cl_offsets, const int32_t *rank,
+                      int32_t n_clusters, const vplmc_params *params, vplmc_plan **out) {
+    if (!out) return set_error(VPLMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_slices < 0) return set_error(VPLMC_EINVAL, "n_slices must be >= 0");
+    if (n_slices > 0 && (!pt_offsets || !cl_offsets || !rank))
+        return set_error(VPLMC_EINVAL, "slice layout arrays must be non-NULL");
+    if (n_clusters < 0) return set_error(VPLMC_EINVAL, "n_clusters must be >= 0");
+    int rc = check_params(params);
+    if (rc) return rc;
+    if (n_slices > 0 && (pt_offsets[0] != 0 || cl_offsets[0] != 0))
+        return set_error(VPLMC_EINVAL, "pt_offsets[0] and cl_offsets[0] must be 0");
+    vplmc_plan *plan = new (std::nothrow) vplmc_plan();
+    if (!plan) return set_error(VPLMC_ENOMEM, "plan allocation failed");
+    plan->n_slices = n_slices;
+    plan->n_clusters = n_clusters;
+    plan->pass1_ppm = params->pass1_ppm;
+    plan->pass2_ppm = params->pass2_ppm;
+    plan->desc.resize(n_slices);
+    int64_t o1 = 0, o2 = 0, oo = 0, oc = 0, orow = 0, ocp = 0, ox = 0, oy = 0, obm = 0, obmt = 0, summ = 0;
+    for (int s = 0; s < n_slices; ++s) {
+        const int64_t m = (int64_t)pt_offsets[s + 1] - pt_offsets[s];
+        const int64_t n = (int64_t)cl_offsets[s + 1] - cl_offsets[s];
+        const int q = rank[s];
+        if (m < 1 || m > VPLMC_MAX_ROWS || n < 1 || n > VPLMC_MAX_COLS) {
+            delete plan;
+            return set_error(VPLMC_EINVAL, "slice %d: %lld rows x %lld columns outside [1, 65535]", s, (long long)m,
+                             (long long)n);
+        }
+        if (q < 1 || q > VPLMC_MAX_RANK || q > m || q > n) {
+            delete plan;
+            return set_error(VPLMC_EINVAL, "slice %d: rank %d must be in [1, min(32, %lld, %lld)]", s, q,
+                             (long long)m, (long long)n);
+        }
+        const int bucket = rank_bucket(q);
+        if (bucket < 0) {
+            delete plan;
+            return set_error(VPLMC_EUNSUPPORTED, "slice %d: rank %d (this build completes at ranks 4, 8, 16, 32)", s, q);
+        }
+        const int64_t D = m * n;
+        const int64_t N1 = count_from_ppm(params->pass1_ppm, D);
+        int64_t N2 = count_from_ppm(params->pass2_ppm, D);
+        if (N2 > D - N1) N2 = D - N1;
+        SliceDesc &d = plan->desc[s];
+        memset(&d, 0, sizeof(d));
+        d.m = (int32_t)m;
+        d.n = (int32_t)n;
+        d.q = q;
+        d.N1 = (int32_t)N1;
+        d.N2 = (int32_t)N2;
+        d.pt_off = pt_offsets[s];
+        d.cl_off = cl_offsets[s];
+        d.words_row = (int32_t)((n + 31) / 32);
+        d.words_col = (int32_t)((m + 31) / 32);
+        d.off1 = o1;
+        d.off2 = o2;
+        d.off_omega = oo;
+        d.off_col = oc;
+        d.off_row = orow;
+        d.off_colptr = ocp;
+        d.off_x = ox;
+        d.off_y = oy;
+        d.off_bm = obm;
+        d.off_bmt = obmt;
+        o1 += N1;
+        o2 += N2;
+        oo += N1 + N2;
+        oc += n;
+        orow += m + 1;
+        ocp += n + 1;
+        ox += m * q;
+        oy += 3 * n * q;
+        obm += m * d.words_row;
+        obmt += n * d.words_col;
+        summ += m;
+        plan->slices_by_q[bucket].push_back(s);
+        plan->max_m = std::max<int64_t>(plan->max_m, m);
+    }
+    plan->tot1 = o1;
+    plan->tot2 = o2;
+    plan->tot_omega = oo;
+    plan->tot_col = oc;
+    plan->tot_row = orow;
+    plan->tot_x = ox;
+    plan->tot_y = oy;
+    plan->tot_bm = obm;
+    plan->tot_bmt = obmt;
+    plan->sum_m = summ;
+    plan->ids.clear();
+    for (int b = 0; b < 4; ++b) plan->ids.insert(plan->ids.end(), plan->slices_by_q[b].begin(), plan->slices_by_q[b].end());
+
+    Layout &L = plan->layout;
+    memset(&L, 0, sizeof(L));
+    const int64_t S = n_slices, NC = n_clusters;
+    size_t bytes[R_INTERNAL_END] = {};
+    bytes[VPLMC_R_LIGHTS] = 9 * NC * 4;
+    bytes[VPLMC_R_REP] = NC * 4;
+    bytes[VPLMC_R_BBOX] = 6 * NC * 4;
+    bytes[VPLMC_R_OMEGA1] = o1 * 4;
+    bytes[VPLMC_R_VAL1] = 3 * o1 * 4;
+    bytes[VPLMC_R_OMEGA2] = o2 * 4;
+    bytes[VPLMC_R_VAL2] = 3 * o2 * 4;
+    bytes[VPLMC_R_WEIGHTS] = oc * 4;
+    bytes[VPLMC_R_COLMIN] = oc * 4;
+    bytes[VPLMC_R_COLMAX] = oc * 4;
+    bytes[VPLMC_R_COLCNT] = oc * 4;
+    bytes[VPLMC_R_ROW_PTR] = orow * 4;
+    bytes[VPLMC_R_CSR_COL] = oo * 4;
+    bytes[VPLMC_R_CSR_VAL] = 3 * oo * 4;
+    bytes[VPLMC_R_COL_PTR] = ocp * 4;
+    bytes[VPLMC_R_CSC_ROW] = oo * 4;
+    bytes[VPLMC_R_CSC_VAL] = 3 * oo * 4;
+    bytes[VPLMC_R_X] = ox * 4;
+    bytes[VPLMC_R_Y] = oy * 4;
+    bytes[VPLMC_R_SLICE_SCALE] = S * 4;
+    bytes[R_DESC] = S * sizeof(SliceDesc) + S * 4;
+    bytes[R_COLW_PREFIX] = oc * 8;
+    bytes[R_BITMAP] = obm * 4;
+    bytes[R_BITMAPT] = obmt * 4;
+    bytes[R_WPRE] = obm * 2;
+    bytes[R_WPRET] = obmt * 2;
+    bytes[R_XNEXT] = ox * 4;
+    bytes[R_XP] = ox * 4;
+    bytes[R_LAMBDA] = ox * 4;
+    bytes[R_YP] = oy * 4;
+    bytes[R_PI] = oy * 4;
+    bytes[R_SLICE_STATS] = S * 16;
+    size_t off = 0;
+    for (int r = 0; r < R_INTERNAL_END; ++r) {
+        L.off[r] = off;
+        L.bytes[r] = bytes[r];
+        off = align256(off + bytes[r]);
+    }
+    L.total = off;
+    // host staging copy of the descriptor table followed by the bucketed slice ids
+    plan->upload.resize(bytes[R_DESC]);
+    if (n_slices > 0) {
+        memcpy(plan->upload.data(), plan->desc.data(), S * sizeof(SliceDesc));
+        memcpy(plan->upload.data() + S * sizeof(SliceDesc), plan->ids.data(), S * 4);
+    }
+    *out = plan;
+    return VPLMC_OK;
+}
+
+int vplmc_plan_destroy(vplmc_plan *plan) {
+    delete plan;
+    return VPLMC_OK;
+}
+
+int vplmc_workspace_size(const vplmc_plan *plan, size_t *bytes) {
+    if (!plan || !bytes) return set_error(VPLMC_EINVAL, "plan and bytes must be non-NULL");
+    *bytes = plan->layout.total;
+    return VPLMC_OK;
+}
+
+int vplmc_plan_slice(const vplmc_plan *plan, int32_t s, vplmc_slice_info *out) {
+    if (!plan || !out) return set_error(VPLMC_EINVAL, "plan and out must be non-NULL");
+    if (s < 0 || s >= plan->n_slices) return set_error(VPLMC_EINVAL, "slice %d out of range", s);
+    const SliceDesc &d = plan->desc[s];
+    out->m = d.m;
+    out->n = d.n;
+    out->q = d.q;
+    out->N1 = d.N1;
+    out->N2 = d.N2;
+    out->off1 = d.off1;
+    out->off2 = d.off2;
+    out->off_omega = d.off_omega;
+    out->off_col = d.off_col;
+    out->off_row = d.off_row;
+    out->off_colptr = d.off_colptr;
+    out->off_x = d.off_x;
+    out->off_y = d.off_y;
+    return VPLMC_OK;
+}
+
+int vplmc_plan_region(const vplmc_plan *plan, int32_t region, size_t *offset, size_t *bytes) {
+    if (!plan || !offset || !bytes) return set_error(VPLMC_EINVAL, "plan, offset and bytes must be non-NULL");
+    if (region < 0 || region >= VPLMC_R_COUNT) return set_error(VPLMC_EINVAL, "unknown region %d", region);
+    *offset = plan->layout.off[region];
+    *bytes = plan->layout.bytes[region];
+    return VPLMC_OK;
+}
+
+int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points, const vplmc_lights *vpls,
+                 const vplmc_cut *cut, const int32_t *pt_ids, const int32_t *cl_ids, const vplmc_params *params,
+                 void *workspace, size_t workspace_bytes, float *radiance) {
+    if (!ctx || !plan || !points || !vpls || !cut || !params)
+        return set_error(VPLMC_EINVAL, "ctx, plan, points, vpls, cut and params must be non-NULL");
+    int rc = check_params(params);
+    if (rc) return rc;
+    if (params->pass1_ppm != plan->pass1_ppm || params->pass2_ppm != plan->pass2_ppm)
+        return set_error(VPLMC_EINVAL, "params rates differ from the plan's");
+    if (points->m < 0 || bad_ptrs_points(points)) return set_error(VPLMC_EINVAL, "incomplete points arrays");
+    if (vpls->n < 1 || bad_ptrs_lights(vpls)) return set_error(VPLMC_EINVAL, "incomplete VPL arrays");
+    if (cut->n_clusters != plan->n_clusters || !cut->offsets || !cut->members)
+        return set_error(VPLMC_EINVAL, "cut does not match the plan (%d clusters planned)", plan->n_clusters);
+    if (plan->n_slices > 0 && (!pt_ids || !cl_ids)) return set_error(VPLMC_EINVAL, "pt_ids and cl_ids must be non-NULL");
+    if (!radiance) return set_error(VPLMC_EINVAL, "radiance is NULL");
+    if (!workspace || workspace_bytes < plan->layout.total)
+        return set_error(VPLMC_EINVAL, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes,
+                         plan->layout.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return set_error(VPLMC_EINVAL, "workspace must be 256-byte aligned");
+    if (plan->sum_m > points->m) return set_error(VPLMC_EINVAL, "slices hold more rows than there are points");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    void *ws = workspace;
+    const int S = plan->n_slices;
+
+    SliceDesc *desc = region<SliceDesc>(ws, plan, R_DESC);
+    const int32_t *ids = reinterpret_cast<const int32_t *>(desc + S);
+    if (S > 0)
+        VPLMC_HIP(hipMemcpyAsync(desc, plan->upload.data(), plan->upload.size(), hipMemcpyHostToDevice, st));
+
+    uint32_t *bm = region<uint32_t>(ws, plan, R_BITMAP);
+    uint32_t *bmt = region<uint32_t>(ws, plan, R_BITMAPT);
+    int32_t *cnt = region<int32_t>(ws, plan, VPLMC_R_COLCNT);
+    uint32_t *mn = region<uint32_t>(ws, plan, VPLMC_R_COLMIN);
+    uint32_t *mx = region<uint32_t>(ws, plan, VPLMC_R_COLMAX);
+    int32_t *stats = region<int32_t>(ws, plan, R_SLICE_STATS);
+    if ((rc = launch_fill_u32(st, bm, plan->tot_bm, 0u))) return rc;
+    if ((rc = launch_fill_u32(st, bmt, plan->tot_bmt, 0u))) return rc;
+    if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(cnt), plan->tot_col, 0u))) return rc;
+    if ((rc = launch_fill_u32(st, mn, plan->tot_col, 0x7F800000u))) return rc;
+    if ((rc = launch_fill_u32(st, mx, plan->tot_col, 0u))) return rc;
+    if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(stats), 4 * (size_t)S, 0u))) return rc;
+    if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(radiance), 3 * (size_t)points->m, 0u))) return rc;
+
+    float *lights = region<float>(ws, plan, VPLMC_R_LIGHTS);
+    if ((rc = launch_cluster_table(st, *vpls, *cut, params->seed, region<int32_t>(ws, plan, VPLMC_R_REP), lights,
+                                   region<float>(ws, plan, VPLMC_R_BBOX))))
+        return rc;
+    uint32_t *omega1 = region<uint32_t>(ws, plan, VPLMC_R_OMEGA1);
+    float *val1 = region<float>(ws, plan, VPLMC_R_VAL1);
+    uint32_t *omega2 = region<uint32_t>(ws, plan, VPLMC_R_OMEGA2);
+    float *val2 = region<float>(ws, plan, VPLMC_R_VAL2);
+    if ((rc = launch_pass1(st, *plan, desc, params->seed, omega1, bm, bmt))) return rc;
+    if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_clusters, desc, S, pt_ids, cl_ids, omega1,
+                                plan->tot1, 0, stats, *params, val1)))
+        return rc;
+    if ((rc = launch_colstats(st, *plan, desc, omega1, val1, cnt, mn, mx))) return rc;
+    uint64_t *prefix = region<uint64_t>(ws, plan, R_COLW_PREFIX);
+    if ((rc = launch_weights(st, *plan, desc, cnt, reinterpret_cast<const float *>(mn),
+                             reinterpret_cast<const float *>(mx), region<uint32_t>(ws, plan, VPLMC_R_WEIGHTS), prefix)))
+        return rc;
+    if ((rc = launch_pass2(st, *plan, desc, params->seed, prefix, bm, bmt, omega2, stats))) return rc;
+    if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_clusters, desc, S, pt_ids, cl_ids, omega2,
+                                plan->tot2, 1, stats, *params, val2)))
+        return rc;
+    int32_t *row_ptr = region<int32_t>(ws, plan, VPLMC_R_ROW_PTR);
+    int32_t *col_ptr = region<int32_t>(ws, plan, VPLMC_R_COL_PTR);
+    int32_t *csr_col = region<int32_t>(ws, plan, VPLMC_R_CSR_COL);
+    float *csr_val = region<float>(ws, plan, VPLMC_R_CSR_VAL);
+    int32_t *csc_row = region<int32_t>(ws, plan, VPLMC_R_CSC_ROW);
+    float *csc_val = region<float>(ws, plan, VPLMC_R_CSC_VAL);
+    if ((rc = launch_sort(st, *plan, desc, bm, bmt, region<uint16_t>(ws, plan, R_WPRE), region<uint16_t>(ws, plan, R_WPRET),
+                          row_ptr, col_ptr, omega1, val1, omega2, val2, stats, csr_col, csr_val, csc_row, csc_val)))
+        return rc;
+    float *X = region<float>(ws, plan, VPLMC_R_X);
+    float *Y = region<float>(ws, plan, VPLMC_R_Y);
+    float *scale = region<float>(ws, plan, VPLMC_R_SLICE_SCALE);
+    if ((rc = launch_adm(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X,
+                         region<float>(ws, plan, R_XNEXT), region<float>(ws, plan, R_XP),
+                         region<float>(ws, plan, R_LAMBDA), Y, region<float>(ws, plan, R_YP),
+                         region<float>(ws, plan, R_PI), scale, stats)))
+        return rc;
+    return launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, radiance);
+}
+
+int vplmc_read_stats(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace, int32_t *iters, int32_t *flags,
+                     float *resid, int32_t *n2_accepted) {
+    if (!ctx || !plan || !workspace) return set_error(VPLMC_EINVAL, "ctx, plan and workspace must be non-NULL");
+    const int S = plan->n_slices;
+    std::vector<int32_t> h(4 * (size_t)S);
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    if (S > 0) {
+        VPLMC_HIP(hipMemcpyAsync(h.data(), static_cast<const char *>(workspace) + plan->layout.off[R_SLICE_STATS],
+                                 h.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    VPLMC_HIP(hipStreamSynchronize(ctx->stream));
+    for (int s = 0; s < S; ++s) {
+        if (iters) iters[s] = h[4 * s];
+        if (flags) flags[s] = h[4 * s + 1];
+        if (resid) memcpy(&resid[s], &h[4 * s + 2], 4);
+        if (n2_accepted) n2_accepted[s] = h[4 * s + 3];
+    }
+    return VPLMC_OK;
+}
+
+int vplmc_cluster_table(vplmc_ctx *ctx, const vplmc_lights *vpls, const vplmc_cut *cut, uint64_t seed, int32_t *rep,
+                        float *lights, float *bbox) {
+    if (!ctx || !vpls || !cut || !rep || !lights || !bbox) return set_error(VPLMC_EINVAL, "NULL argument");
+    if (vpls->n < 1 || bad_ptrs_lights(vpls)) return set_error(VPLMC_EINVAL, "incomplete VPL arrays");
+    if (cut->n_clusters < 0 || (cut->n_clusters > 0 && (!cut->offsets || !cut->members)))
+        return set_error(VPLMC_EINVAL, "invalid cut");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    return launch_cluster_table(ctx->stream, *vpls, *cut, seed, rep, lights, bbox);
+}
+
+int vplmc_eval_pairs(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lights *lights, int64_t n_pairs,
+                     const int32_t *point_ids, const int32_t *light_ids, const vplmc_params *params, float *out) {
+    if (!ctx || !points || !lights || !params) return set_error(VPLMC_EINVAL, "NULL argument");
+    if (n_pairs < 0) return set_error(VPLMC_EINVAL, "n_pairs must be >= 0");
+    if (n_pairs > 0 && (!point_ids || !light_ids || !out)) return set_error(VPLMC_EINVAL, "NULL pair arrays");
+    if (bad_ptrs_points(points) || bad_ptrs_lights(lights)) return set_error(VPLMC_EINVAL, "incomplete arrays");
+    int rc = check_params(params);
+    if (rc) return rc;
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    return launch_eval_pairs(ctx->stream, ctx->bvh, *points, *lights, n_pairs, point_ids, light_ids, *params, out);
+}
+
+int vplmc_brute_force(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lights *lights, int32_t n_out,
+                      const int32_t *point_ids, const vplmc_params *params, double *out) {
+    if (!ctx || !points || !lights || !params) return set_error(VPLMC_EINVAL, "NULL argument");
+    if (n_out < 0 || (n_out > 0 && !out)) return set_error(VPLMC_EINVAL, "invalid output");
+    if (!point_ids && n_out > points->m) return set_error(VPLMC_EINVAL, "n_out exceeds the number of points");
+    if (bad_ptrs_points(points) || bad_ptrs_lights(lights)) return set_error(VPLMC_EINVAL, "incomplete arrays");
+    int rc = check_params(params);
+    if (rc) return rc;
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    return launch_brute_force(ctx->stream, ctx->bvh, *points, *lights, n_out, point_ids, *params, out);
+}
+
+int vplmc_philox4x64(vplmc_ctx *ctx, uint64_t key0, uint64_t key1, const uint64_t *ctr, int64_t n, uint64_t *out) {
+    if (!ctx) return set_error(VPLMC_EINVAL, "ctx is NULL");
+    if (n < 0 || (n > 0 && (!ctr || !out))) return set_error(VPLMC_EINVAL, "invalid counter/output arrays");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    return launch_philox(ctx->stream, key0, key1, ctr, n, out);
+}
+
+}  // extern "C"

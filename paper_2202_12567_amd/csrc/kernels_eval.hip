@@ -1,0 +1,249 @@
+// Lighting-matrix entries A(i, j) (Sec. 3): the contribution of a point
+// light to a surface point, with a shadow ray against the occluder BVH
+// (visibility is the most expensive part of an entry, Sec. 2 and Sec. 6).
+//
+//   d = y - x, w = d / |d|, c_x = n_x . w, c_y = -n_y . w (0, no ray, if either <= 0)
+//   G = c_x c_y / max(|d|^2, r_min^2)
+//   f = kd / pi + ks (e + 2) / (2 pi) max(0, w_r . w_o)^e,  w_r = 2 c_x n_x - w
+//   A = f * I * G * V
+// V = 0 iff the segment from x + eps n_x to y passes within the radius of a
+// sphere (closest point of the segment to the centre), found by an any-hit
+// traversal of a bounding-volume hierarchy with a short register stack.
+
+#include "vplmc_internal.h"
+
+namespace vplmc {
+namespace {
+
+constexpr float INV_PI = 0.318309886183790671538f;
+
+struct P3 {
+    float x, y, z;
+};
+__device__ __forceinline__ P3 sub(P3 a, P3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ float dot(P3 a, P3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+
+// any hit on the open segment o + t D, t in (0, 1)
+__device__ __forceinline__ bool occluded(const Bvh &bvh, P3 o, P3 D) {
+    if (bvh.n_nodes == 0) return false;
+    const float dd = dot(D, D);
+    const float inv_dd = 1.0f / dd;
+    const float ix = 1.0f / (fabsf(D.x) > 1e-20f ? D.x : copysignf(1e-20f, D.x));
+    const float iy = 1.0f / (fabsf(D.y) > 1e-20f ? D.y : copysignf(1e-20f, D.y));
+    const float iz = 1.0f / (fabsf(D.z) > 1e-20f ? D.z : copysignf(1e-20f, D.z));
+    int stack[40];
+    int sp = 0;
+    int node = 0;
+    while (true) {
+        const BvhNode nd = bvh.nodes[node];
+        const float tx0 = (nd.lo[0] - o.x) * ix, tx1 = (nd.hi[0] - o.x) * ix;
+        const float ty0 = (nd.lo[1] - o.y) * iy, ty1 = (nd.hi[1] - o.y) * iy;
+        const float tz0 = (nd.lo[2] - o.z) * iz, tz1 = (nd.hi[2] - o.z) * iz;
+        const float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+        const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), 1.0f));
+        if (tmin <= tmax) {
+            if (nd.right_or_count > 0) {
+                const int first = nd.left_or_first, cnt = nd.right_or_count;
+                for (int k = 0; k < cnt; ++k) {
+                    const float4 sp4 = bvh.spheres[first + k];
+                    const P3 oc = {sp4.x - o.x, sp4.y - o.y, sp4.z - o.z};
+                    const float t = fminf(fmaxf(dot(oc, D) * inv_dd, 0.0f), 1.0f);
+                    const P3 p = {oc.x - t * D.x, oc.y - t * D.y, oc.z - t * D.z};
+                    if (dot(p, p) < sp4.w * sp4.w) return true;
+                }
+            } else {
+                stack[sp++] = -nd.right_or_count - 1;
+                node = nd.left_or_first;
+                continue;
+            }
+        }
+        if (sp == 0) return false;
+        node = stack[--sp];
+    }
+}
+
+struct PointData {
+    P3 x, n, wo;
+    float kd0, kd1, kd2, ks, e;
+};
+
+__device__ __forceinline__ PointData load_point(const vplmc_points &p, int i) {
+    PointData q;
+    q.x = {p.px[i], p.py[i], p.pz[i]};
+    q.n = {p.nx[i], p.ny[i], p.nz[i]};
+    q.kd0 = p.kd_r[i];
+    q.kd1 = p.kd_g[i];
+    q.kd2 = p.kd_b[i];
+    q.ks = p.ks ? p.ks[i] : 0.0f;
+    q.e = p.phong_e ? p.phong_e[i] : 1.0f;
+    q.wo = p.vx ? P3{p.vx[i], p.vy[i], p.vz[i]} : P3{0.0f, 0.0f, 1.0f};
+    return q;
+}
+
+struct Light {
+    P3 y, n;
+    float i0, i1, i2;
+};
+
+// entry of one (point, light) pair; returns false (and zeros) when no ray is needed
+__device__ __forceinline__ void shade(const Bvh &bvh, const PointData &q, const Light &L, float r_min2,
+                                      float eps, float &o0, float &o1, float &o2) {
+    o0 = o1 = o2 = 0.0f;
+    const P3 d = sub(L.y, q.x);
+    const float r2 = dot(d, d);
+    const float inv_r = 1.0f / sqrtf(r2);
+    const P3 w = {d.x * inv_r, d.y * inv_r, d.z * inv_r};
+    const float cx = dot(q.n, w);
+    const float cy = -dot(L.n, w);
+    if (!(cx > 0.0f && cy > 0.0f)) return;
+    const float G = cx * cy / fmaxf(r2, r_min2);
+    float spec = 0.0f;
+    if (q.ks > 0.0f) {
+        const P3 wr = {2.0f * cx * q.n.x - w.x, 2.0f * cx * q.n.y - w.y, 2.0f * cx * q.n.z - w.z};
+        const float cr = fmaxf(0.0f, dot(wr, q.wo));
+        spec = q.ks * (q.e + 2.0f) * (0.5f * INV_PI) * powf(cr, q.e);
+    }
+    const P3 o = {fmaf(eps, q.n.x, q.x.x), fmaf(eps, q.n.y, q.x.y), fmaf(eps, q.n.z, q.x.z)};
+    if (occluded(bvh, o, sub(L.y, o))) return;
+    o0 = fmaf(q.kd0, INV_PI, spec) * L.i0 * G;
+    o1 = fmaf(q.kd1, INV_PI, spec) * L.i1 * G;
+    o2 = fmaf(q.kd2, INV_PI, spec) * L.i2 * G;
+}
+
+__device__ __forceinline__ int slice_of_off(const SliceDesc *__restrict__ desc, int S, int64_t g, int which) {
+    int lo = 0, hi = S;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        const int64_t o = which ? desc[mid].off2 : desc[mid].off1;
+        if (o <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// entries of one pass's samples (draw order), lights = cluster table planes
+__global__ __launch_bounds__(256) void k_eval_omega(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
+                                                    int32_t n_lights, const SliceDesc *__restrict__ desc, int S,
+                                                    const int32_t *__restrict__ pt_ids,
+                                                    const int32_t *__restrict__ cl_ids,
+                                                    const uint32_t *__restrict__ keys, int64_t n_keys,
+                                                    int which, const int32_t *__restrict__ stats, float r_min2,
+                                                    float eps, float *__restrict__ vals) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= n_keys) return;
+    const int s = slice_of_off(desc, S, g, which);
+    const SliceDesc d = desc[s];
+    if (which && g - d.off2 >= stats[4 * s + 3]) return;
+    const uint32_t key = keys[g];
+    const int i = (int)(key >> 16), j = (int)(key & 0xFFFFu);
+    const int pid = pt_ids[d.pt_off + i];
+    const int c = cl_ids[d.cl_off + j];
+    const size_t N = (size_t)n_lights;
+    const Light L = {{lights[c], lights[N + c], lights[2 * N + c]},
+                     {lights[3 * N + c], lights[4 * N + c], lights[5 * N + c]},
+                     lights[6 * N + c], lights[7 * N + c], lights[8 * N + c]};
+    const PointData q = load_point(pts, pid);
+    float o0, o1, o2;
+    shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+    vals[3 * g] = o0;
+    vals[3 * g + 1] = o1;
+    vals[3 * g + 2] = o2;
+}
+
+__global__ __launch_bounds__(256) void k_eval_pairs(Bvh bvh, vplmc_points pts, vplmc_lights l, int64_t n,
+                                                    const int32_t *__restrict__ pid,
+                                                    const int32_t *__restrict__ lid, float r_min2, float eps,
+                                                    float *__restrict__ out) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int c = lid[g];
+    const Light L = {{l.x[c], l.y[c], l.z[c]}, {l.nx[c], l.ny[c], l.nz[c]}, l.ir[c], l.ig[c], l.ib[c]};
+    const PointData q = load_point(pts, pid[g]);
+    float o0, o1, o2;
+    shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+    out[3 * g] = o0;
+    out[3 * g + 1] = o1;
+    out[3 * g + 2] = o2;
+}
+
+// Brute-force column sum: one thread per point, lights staged through LDS,
+// FP32 entries summed in FP64.
+constexpr int BF_TILE = 256;
+__global__ __launch_bounds__(256) void k_brute_force(Bvh bvh, vplmc_points pts, vplmc_lights l, int32_t n_out,
+                                                     const int32_t *__restrict__ pid, float r_min2, float eps,
+                                                     double *__restrict__ out) {
+    __shared__ float sl[9][BF_TILE];
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = g < n_out;
+    PointData q{};
+    if (active) q = load_point(pts, pid ? pid[g] : g);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int b = 0; b < l.n; b += BF_TILE) {
+        const int c = b + threadIdx.x;
+        if (c < l.n) {
+            sl[0][threadIdx.x] = l.x[c];
+            sl[1][threadIdx.x] = l.y[c];
+            sl[2][threadIdx.x] = l.z[c];
+            sl[3][threadIdx.x] = l.nx[c];
+            sl[4][threadIdx.x] = l.ny[c];
+            sl[5][threadIdx.x] = l.nz[c];
+            sl[6][threadIdx.x] = l.ir[c];
+            sl[7][threadIdx.x] = l.ig[c];
+            sl[8][threadIdx.x] = l.ib[c];
+        }
+        __syncthreads();
+        const int cnt = min(BF_TILE, l.n - b);
+        if (active) {
+            for (int k = 0; k < cnt; ++k) {
+                const Light L = {{sl[0][k], sl[1][k], sl[2][k]}, {sl[3][k], sl[4][k], sl[5][k]}, sl[6][k], sl[7][k],
+                                 sl[8][k]};
+                float o0, o1, o2;
+                shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+                a0 += (double)o0;
+                a1 += (double)o1;
+                a2 += (double)o2;
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
+        out[3 * (size_t)g] = a0;
+        out[3 * (size_t)g + 1] = a1;
+        out[3 * (size_t)g + 2] = a2;
+    }
+}
+
+unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+}  // namespace
+
+int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
+                      int32_t n_lights, const SliceDesc *desc, int32_t n_slices, const int32_t *pt_ids,
+                      const int32_t *cl_ids, const uint32_t *keys, int64_t n_keys, int which,
+                      const int32_t *stats, const vplmc_params &prm, float *vals) {
+    if (n_keys <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_eval_omega, dim3(blocks_for(n_keys, 256)), dim3(256), 0, st, bvh, pts, lights, n_lights,
+                       desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats, prm.r_min * prm.r_min,
+                       prm.ray_eps, vals);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_eval_pairs(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l, int64_t n,
+                      const int32_t *pid, const int32_t *lid, const vplmc_params &prm, float *out) {
+    if (n <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_eval_pairs, dim3(blocks_for(n, 256)), dim3(256), 0, st, bvh, pts, l, n, pid, lid,
+                       prm.r_min * prm.r_min, prm.ray_eps, out);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_brute_force(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,
+                       int32_t n_out, const int32_t *pid, const vplmc_params &prm, double *out) {
+    if (n_out <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_brute_force, dim3(blocks_for(n_out, 256)), dim3(256), 0, st, bvh, pts, l, n_out, pid,
+                       prm.r_min * prm.r_min, prm.ray_eps, out);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+}  // namespace vplmc

@@ -1,0 +1,558 @@
+// Cluster table of the cut (Sec. 4), the two sampling passes (Sec. 5) and
+// the CSR / CSC ordering of every slice's samples.
+//
+// Sampled entries of slice s are packed as (i << 16) | j (row i < m',
+// column j < n').  Each slice keeps two occupancy bitmaps of its m' x n'
+// matrix: row-major (words_row = ceil(n'/32) words per row) and
+// column-major (words_col = ceil(m'/32) words per column).  They make the
+// second pass's "not sampled yet" test a single bit probe and turn the CSR
+// and CSC orderings into popcount prefix sums: the position of (i, j) in
+// row-major order is the number of set bits before it.
+
+#include "vplmc_internal.h"
+
+namespace vplmc {
+namespace {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ int slice_of(const SliceDesc *__restrict__ desc, int S, int64_t g, int which) {
+    // last slice whose start offset is <= g (which: 0 off1, 1 off2, 2 row base, 3 col base)
+    int lo = 0, hi = S;   // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        int64_t o;
+        switch (which) {
+            case 0: o = desc[mid].off1; break;
+            case 1: o = desc[mid].off2; break;
+            case 2: o = desc[mid].off_row - mid; break;      // rows before slice mid
+            default: o = desc[mid].off_colptr - mid; break;  // columns before slice mid
+        }
+        if (o <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Keyed balanced Feistel permutation of [0, 2^(2h)): 4 rounds,
+// F_r(R) = Philox(key = (seed, s), ctr = (R, r, TAG_PASS1, 0)).a & (2^h - 1).
+__device__ __forceinline__ uint64_t feistel(uint64_t x, uint64_t seed, uint64_t s, int h) {
+    const uint64_t mask = (1ull << h) - 1ull;
+    uint64_t L = x >> h, R = x & mask;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t F = philox(seed, s, R, (uint64_t)r, TAG_PASS1, 0).a & mask;
+        const uint64_t nL = R;
+        R = L ^ F;
+        L = nL;
+    }
+    return (L << h) | R;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, WAVE);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// exclusive scan over a 256-thread block; returns the block total in *total
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total, uint32_t *sm) {
+    const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+    const uint32_t incl = wave_incl_scan(v, lane);
+    if (lane == WAVE - 1) sm[w] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int k = 0; k < (int)(blockDim.x / WAVE); ++k) {
+        if (k < w) base += sm[k];
+        tot += sm[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+__global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_philox(uint64_t k0, uint64_t k1, const uint64_t *ctr, int64_t n, uint64_t *out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const U64x4 r = philox(k0, k1, ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
+    out[4 * i] = r.a;
+    out[4 * i + 1] = r.b;
+    out[4 * i + 2] = r.c;
+    out[4 * i + 3] = r.d;
+}
+
+// One thread per cluster: representative drawn with probability ~ quantised
+// member intensity, intensity = FP64 member sum, bbox of member positions.
+__global__ void k_cluster_table(vplmc_lights v, vplmc_cut cut, uint64_t seed, int32_t *rep_out,
+                                float *lights, float *bbox) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc = cut.n_clusters;
+    if (c >= nc) return;
+    const int b = cut.offsets[c], e = cut.offsets[c + 1];
+    double smax = 0.0;
+    for (int k = b; k < e; ++k) {
+        const int id = cut.members[k];
+        const double sk = ((double)v.ir[id] + (double)v.ig[id]) + (double)v.ib[id];
+        smax = sk > smax ? sk : smax;
+    }
+    uint64_t total = 0;
+    for (int k = b; k < e; ++k) {
+        const int id = cut.members[k];
+        const double sk = ((double)v.ir[id] + (double)v.ig[id]) + (double)v.ib[id];
+        uint64_t w = 1;
+        if (smax > 0.0) {
+            const double f = floor((16777216.0 * sk) / smax);
+            w = f > 1.0 ? (uint64_t)f : 1ull;
+        }
+        total += w;
+    }
+    int rep = e > b ? cut.members[b] : -1;
+    if (e > b) {
+        const uint64_t u = mulhi64(philox(seed, 0, (uint64_t)c, 0, TAG_REP, 0).a, total);
+        uint64_t acc = 0;
+        for (int k = b; k < e; ++k) {
+            const int id = cut.members[k];
+            const double sk = ((double)v.ir[id] + (double)v.ig[id]) + (double)v.ib[id];
+            uint64_t w = 1;
+            if (smax > 0.0) {
+                const double f = floor((16777216.0 * sk) / smax);
+                w = f > 1.0 ? (uint64_t)f : 1ull;
+            }
+            acc += w;
+            if (acc > u) {
+                rep = id;
+                break;
+            }
+        }
+    }
+    double sr = 0.0, sg = 0.0, sb = 0.0;
+    float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+    for (int k = b; k < e; ++k) {
+        const int id = cut.members[k];
+        sr += (double)v.ir[id];
+        sg += (double)v.ig[id];
+        sb += (double)v.ib[id];
+        lo0 = fminf(lo0, v.x[id]); hi0 = fmaxf(hi0, v.x[id]);
+        lo1 = fminf(lo1, v.y[id]); hi1 = fmaxf(hi1, v.y[id]);
+        lo2 = fminf(lo2, v.z[id]); hi2 = fmaxf(hi2, v.z[id]);
+    }
+    rep_out[c] = rep;
+    const int r = rep < 0 ? 0 : rep;
+    const size_t N = (size_t)nc;
+    lights[0 * N + c] = v.x[r];
+    lights[1 * N + c] = v.y[r];
+    lights[2 * N + c] = v.z[r];
+    lights[3 * N + c] = v.nx[r];
+    lights[4 * N + c] = v.ny[r];
+    lights[5 * N + c] = v.nz[r];
+    lights[6 * N + c] = (float)sr;
+    lights[7 * N + c] = (float)sg;
+    lights[8 * N + c] = (float)sb;
+    bbox[0 * N + c] = lo0;
+    bbox[1 * N + c] = lo1;
+    bbox[2 * N + c] = lo2;
+    bbox[3 * N + c] = hi0;
+    bbox[4 * N + c] = hi1;
+    bbox[5 * N + c] = hi2;
+}
+
+// First pass: sample k of slice s is walk(k) of the keyed permutation.
+__global__ void k_pass1(const SliceDesc *__restrict__ desc, int S, int64_t total, uint64_t seed,
+                        uint32_t *omega1, uint32_t *bm, uint32_t *bmt) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int s = slice_of(desc, S, g, 0);
+    const SliceDesc d = desc[s];
+    const uint64_t k = (uint64_t)(g - d.off1);
+    const uint64_t D = (uint64_t)d.m * (uint64_t)d.n;
+    int b = D > 1 ? 64 - __clzll((long long)(D - 1)) : 0;
+    b = b < 2 ? 2 : b;
+    const int h = (b + 1) / 2;
+    uint64_t e = feistel(k, seed, (uint64_t)s, h);
+    while (e >= D) e = feistel(e, seed, (uint64_t)s, h);   // cycle-walking; ends in k's cycle
+    const uint32_t i = (uint32_t)(e / (uint64_t)d.n), j = (uint32_t)(e % (uint64_t)d.n);
+    omega1[g] = (i << 16) | j;
+    atomicOr(bm + d.off_bm + (int64_t)i * d.words_row + (j >> 5), 1u << (j & 31));
+    atomicOr(bmt + d.off_bmt + (int64_t)j * d.words_col + (i >> 5), 1u << (i & 31));
+}
+
+// Per-(slice, column) count, min and max of t = R + G + B over the first pass.
+__global__ void k_colstats(const SliceDesc *__restrict__ desc, int S, int64_t total,
+                           const uint32_t *__restrict__ omega1, const float *__restrict__ val1,
+                           int32_t *cnt, uint32_t *mn, uint32_t *mx) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int s = slice_of(desc, S, g, 0);
+    const SliceDesc d = desc[s];
+    const uint32_t j = omega1[g] & 0xFFFFu;
+    const float tv = (val1[3 * g] + val1[3 * g + 1]) + val1[3 * g + 2];   // >= 0: bit order = value order
+    const int64_t o = d.off_col + j;
+    atomicAdd(cnt + o, 1);
+    atomicMin(mn + o, __float_as_uint(tv));
+    atomicMax(mx + o, __float_as_uint(tv));
+}
+
+// g(j) = max - min (Sec. 5, f(i) = 1) quantised to w_j = max(1, floor(2^24 g / max g))
+// (0 where g = 0; all 1 if every g is 0) and its inclusive uint64 prefix.
+__global__ __launch_bounds__(256) void k_weights(const SliceDesc *__restrict__ desc, const int32_t *cnt,
+                                                 const float *mn, const float *mx, uint32_t *w,
+                                                 uint64_t *prefix) {
+    __shared__ uint32_t sm[8];
+    __shared__ float smax[4];
+    __shared__ uint64_t carry_s;
+    const int s = blockIdx.x;
+    const SliceDesc d = desc[s];
+    const int t = threadIdx.x, lane = t % WAVE, wv = t / WAVE;
+    float gmax = 0.f;
+    for (int j = t; j < d.n; j += 256) {
+        const int64_t o = d.off_col + j;
+        const float gj = cnt[o] > 0 ? mx[o] - mn[o] : 0.f;
+        gmax = fmaxf(gmax, gj);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o, WAVE));
+    if (lane == 0) smax[wv] = gmax;
+    __syncthreads();
+    gmax = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
+    const bool uniform = !(gmax > 0.f);
+    if (t == 0) carry_s = 0;
+    __syncthreads();
+    for (int j0 = 0; j0 < d.n; j0 += 256) {
+        const int j = j0 + t;
+        uint32_t wj = 0;
+        if (j < d.n) {
+            if (uniform) {
+                wj = 1;
+            } else {
+                const int64_t o = d.off_col + j;
+                const float gj = cnt[o] > 0 ? mx[o] - mn[o] : 0.f;
+                if (gj > 0.f) {
+                    const double f = floor((16777216.0 * (double)gj) / (double)gmax);
+                    wj = f > 1.0 ? (uint32_t)f : 1u;
+                }
+            }
+            w[d.off_col + j] = wj;
+        }
+        // inclusive uint64 prefix: weights are <= 2^24, a 256-chunk sum fits in 32 bits
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(wj, &tot, sm);
+        const uint64_t carry = carry_s;
+        if (j < d.n) prefix[d.off_col + j] = carry + (uint64_t)ex + wj;
+        __syncthreads();
+        if (t == 0) carry_s = carry + tot;
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ uint32_t load_word(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Second pass (Sec. 5): attempt t draws column j by the integer CDF of w and
+// row i uniformly, and is accepted iff (i, j) is not sampled yet.  A block
+// tests 256 consecutive attempts at once; an attempt is accepted iff its
+// entry is not in the bitmap and no earlier attempt of the same batch drew
+// it, which is exactly the sequential rule.  Stops after N2 acceptances or
+// 64 N2 + 65536 attempts.
+constexpr int P2_LDS = 6144;   // prefix entries staged in LDS (48 KiB)
+
+__global__ __launch_bounds__(256) void k_pass2(const SliceDesc *__restrict__ desc, uint64_t seed,
+                                               const uint64_t *__restrict__ prefix_all, uint32_t *bm,
+                                               uint32_t *bmt, uint32_t *omega2, int32_t *stats) {
+    __shared__ uint64_t P[P2_LDS];
+    __shared__ uint32_t keys[256];
+    __shared__ uint32_t sm[8];
+    __shared__ int accepted_s;
+    const int s = blockIdx.x;
+    const SliceDesc d = desc[s];
+    const int t = threadIdx.x;
+    const int m = d.m, n = d.n;
+    const int64_t D = (int64_t)m * n;
+    const int N2 = d.N2;
+    uint32_t *out = omega2 + d.off2;
+    uint32_t *bmr = bm + d.off_bm;
+    uint32_t *bmc = bmt + d.off_bmt;
+    if (t == 0) accepted_s = 0;
+    __syncthreads();
+    if (N2 > 0 && (int64_t)d.N1 + N2 == D) {
+        // every remaining entry, row-major: scan the row-major bitmap in word order
+        const int64_t words = (int64_t)m * d.words_row;
+        for (int64_t w0 = 0; w0 < words; w0 += 256) {
+            const int64_t w = w0 + t;
+            uint32_t freeb = 0;
+            int i = 0, jb = 0;
+            if (w < words) {
+                i = (int)(w / d.words_row);
+                jb = (int)(w % d.words_row) * 32;
+                const int valid = n - jb >= 32 ? 32 : n - jb;
+                const uint32_t vmask = valid == 32 ? 0xFFFFFFFFu : ((1u << valid) - 1u);
+                freeb = ~load_word(bmr + w) & vmask;
+            }
+            uint32_t tot;
+            const uint32_t base = block_excl_scan(__popc(freeb), &tot, sm);
+            const int a0 = accepted_s;
+            uint32_t pos = (uint32_t)a0 + base;
+            while (freeb) {
+                const int b = __ffs(freeb) - 1;
+                freeb &= freeb - 1;
+                const uint32_t j = (uint32_t)(jb + b);
+                out[pos++] = ((uint32_t)i << 16) | j;
+                atomicOr(bmr + w, 1u << b);
+                atomicOr(bmc + (int64_t)j * d.words_col + (i >> 5), 1u << (i & 31));
+            }
+            __syncthreads();
+            if (t == 0) accepted_s = a0 + (int)tot;
+            __syncthreads();
+        }
+    } else if (N2 > 0) {
+        const uint64_t *pre = prefix_all + d.off_col;
+        const bool in_lds = n <= P2_LDS;
+        if (in_lds)
+            for (int j = t; j < n; j += 256) P[j] = pre[j];
+        __syncthreads();
+        const uint64_t totalw = pre[n - 1];
+        const int64_t cap = 64 * (int64_t)N2 + 65536;
+        for (int64_t tb = 0; tb < cap; tb += 256) {
+            const int acc0 = accepted_s;
+            if (acc0 >= N2) break;
+            const int64_t at = tb + t;
+            bool cand = false;
+            uint32_t key = 0xFFFFFFFFu, i = 0, j = 0;
+            if (at < cap) {
+                const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)at, 0, TAG_PASS2, 0);
+                const uint64_t u = mulhi64(r.a, totalw);
+                int lo = 0, hi = n - 1;      // least j with P[j] > u
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const uint64_t pm = in_lds ? P[mid] : pre[mid];
+                    if (pm > u) hi = mid; else lo = mid + 1;
+                }
+                j = (uint32_t)lo;
+                i = (uint32_t)mulhi64(r.b, (uint64_t)m);
+                const uint32_t word = load_word(bmr + (int64_t)i * d.words_row + (j >> 5));
+                cand = ((word >> (j & 31)) & 1u) == 0u;
+                key = (i << 16) | j;
+            }
+            keys[t] = cand ? key : 0xFFFFFFFFu;
+            __syncthreads();
+            bool dup = false;
+            if (cand)
+                for (int l = 0; l < t; ++l) dup |= keys[l] == key;
+            const bool acc = cand && !dup;
+            uint32_t tot;
+            const uint32_t rank = block_excl_scan(acc ? 1u : 0u, &tot, sm);
+            if (acc && acc0 + (int)rank < N2) {
+                out[acc0 + rank] = key;
+                atomicOr(bmr + (int64_t)i * d.words_row + (j >> 5), 1u << (j & 31));
+                atomicOr(bmc + (int64_t)j * d.words_col + (i >> 5), 1u << (i & 31));
+            }
+            __syncthreads();
+            if (t == 0) accepted_s = min(N2, acc0 + (int)tot);
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        stats[4 * s + 3] = accepted_s;
+        if (accepted_s < N2) stats[4 * s + 1] |= VPLMC_SLICE_SHORTFALL;
+    }
+}
+
+// Popcount prefix of each bitmap row (one wavefront per row): wpre[w] = set
+// bits before word w within the row; the row total goes to ptr[row + 1].
+__global__ void k_rowscan(const SliceDesc *__restrict__ desc, int S, int64_t total_rows, int cols,
+                          const uint32_t *__restrict__ bm, uint16_t *wpre, int32_t *ptr) {
+    const int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (g >= total_rows) return;
+    const int s = slice_of(desc, S, g, cols ? 3 : 2);
+    const SliceDesc d = desc[s];
+    int64_t r, words, base_word, ptr_base;
+    if (!cols) {
+        r = g - (d.off_row - s);
+        words = d.words_row;
+        base_word = d.off_bm;
+        ptr_base = d.off_row;
+    } else {
+        r = g - (d.off_colptr - s);
+        words = d.words_col;
+        base_word = d.off_bmt;
+        ptr_base = d.off_colptr;
+    }
+    const uint32_t *row = bm + base_word + r * words;
+    uint16_t *pre = wpre + base_word + r * words;
+    uint32_t run = 0;
+    for (int64_t w0 = 0; w0 < words; w0 += WAVE) {
+        const int64_t w = w0 + lane;
+        const uint32_t c = w < words ? (uint32_t)__popc(row[w]) : 0u;
+        const uint32_t incl = wave_incl_scan(c, lane);
+        if (w < words) pre[w] = (uint16_t)(run + incl - c);
+        run += __shfl(incl, WAVE - 1, WAVE);
+    }
+    if (lane == 0) ptr[ptr_base + r + 1] = (int32_t)run;
+}
+
+// ptr[0] = 0, ptr[k + 1] = ptr[k] + count[k]: in-place inclusive scan per slice.
+__global__ __launch_bounds__(256) void k_ptrscan(const SliceDesc *__restrict__ desc, int cols, int32_t *ptr) {
+    __shared__ uint32_t sm[8];
+    __shared__ uint32_t carry_s;
+    const int s = blockIdx.x;
+    const SliceDesc d = desc[s];
+    const int64_t base = cols ? d.off_colptr : d.off_row;
+    const int len = cols ? d.n : d.m;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        ptr[base] = 0;
+        carry_s = 0;
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < len; k0 += 256) {
+        const int k = k0 + t;
+        const uint32_t v = k < len ? (uint32_t)ptr[base + k + 1] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, &tot, sm);
+        const uint32_t carry = carry_s;
+        if (k < len) ptr[base + k + 1] = (int32_t)(carry + ex + v);
+        __syncthreads();
+        if (t == 0) carry_s = carry + tot;
+        __syncthreads();
+    }
+}
+
+// Scatter one pass's samples to their CSR and CSC positions.
+__global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t total, int which,
+                          const int32_t *__restrict__ stats, const uint32_t *__restrict__ keys,
+                          const float *__restrict__ vals, const uint32_t *__restrict__ bm,
+                          const uint32_t *__restrict__ bmt, const uint16_t *__restrict__ wpre,
+                          const uint16_t *__restrict__ wpret, const int32_t *__restrict__ row_ptr,
+                          const int32_t *__restrict__ col_ptr, int32_t *csr_col, float *csr_val,
+                          int32_t *csc_row, float *csc_val) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int s = slice_of(desc, S, g, which);
+    const SliceDesc d = desc[s];
+    const int64_t k = g - (which ? d.off2 : d.off1);
+    if (which && k >= stats[4 * s + 3]) return;
+    const uint32_t key = keys[g];
+    const uint32_t i = key >> 16, j = key & 0xFFFFu;
+    const int64_t wr = d.off_bm + (int64_t)i * d.words_row + (j >> 5);
+    const int64_t pr = row_ptr[d.off_row + i] + wpre[wr] + __popc(bm[wr] & ((1u << (j & 31)) - 1u));
+    const int64_t wc = d.off_bmt + (int64_t)j * d.words_col + (i >> 5);
+    const int64_t pc = col_ptr[d.off_colptr + j] + wpret[wc] + __popc(bmt[wc] & ((1u << (i & 31)) - 1u));
+    const float v0 = vals[3 * g], v1 = vals[3 * g + 1], v2 = vals[3 * g + 2];
+    const int64_t o = d.off_omega;
+    csr_col[o + pr] = (int32_t)j;
+    csr_val[3 * (o + pr)] = v0;
+    csr_val[3 * (o + pr) + 1] = v1;
+    csr_val[3 * (o + pr) + 2] = v2;
+    csc_row[o + pc] = (int32_t)i;
+    csc_val[3 * (o + pc)] = v0;
+    csc_val[3 * (o + pc) + 1] = v1;
+    csc_val[3 * (o + pc) + 2] = v2;
+}
+
+unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+}  // namespace
+
+int launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v) {
+    if (n == 0) return VPLMC_OK;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_philox(hipStream_t st, uint64_t k0, uint64_t k1, const uint64_t *ctr, int64_t n, uint64_t *out) {
+    if (n <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_philox, dim3(blocks_for(n, 256)), dim3(256), 0, st, k0, k1, ctr, n, out);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_cluster_table(hipStream_t st, const vplmc_lights &v, const vplmc_cut &cut, uint64_t seed,
+                         int32_t *rep, float *lights, float *bbox) {
+    if (cut.n_clusters <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_cluster_table, dim3(blocks_for(cut.n_clusters, 64)), dim3(64), 0, st, v, cut, seed,
+                       rep, lights, bbox);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_pass1(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, uint64_t seed,
+                 uint32_t *omega1, uint32_t *bm, uint32_t *bmt) {
+    if (plan.tot1 <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_pass1, dim3(blocks_for(plan.tot1, 256)), dim3(256), 0, st, desc, plan.n_slices,
+                       plan.tot1, seed, omega1, bm, bmt);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_colstats(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *omega1,
+                    const float *val1, int32_t *cnt, uint32_t *mn, uint32_t *mx) {
+    if (plan.tot1 <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_colstats, dim3(blocks_for(plan.tot1, 256)), dim3(256), 0, st, desc, plan.n_slices,
+                       plan.tot1, omega1, val1, cnt, mn, mx);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_weights(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *cnt,
+                   const float *mn, const float *mx, uint32_t *w, uint64_t *prefix) {
+    if (plan.n_slices <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_weights, dim3(plan.n_slices), dim3(256), 0, st, desc, cnt, mn, mx, w, prefix);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_pass2(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, uint64_t seed,
+                 const uint64_t *prefix, uint32_t *bm, uint32_t *bmt, uint32_t *omega2, int32_t *stats) {
+    if (plan.n_slices <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_pass2, dim3(plan.n_slices), dim3(256), 0, st, desc, seed, prefix, bm, bmt, omega2,
+                       stats);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *bm,
+                const uint32_t *bmt, uint16_t *wpre, uint16_t *wpret, int32_t *row_ptr, int32_t *col_ptr,
+                const uint32_t *omega1, const float *val1, const uint32_t *omega2, const float *val2,
+                const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, float *csc_val) {
+    if (plan.n_slices <= 0) return VPLMC_OK;
+    const int S = plan.n_slices;
+    const int64_t rows = plan.tot_row - S;     // sum of m
+    const int64_t cols = plan.tot_col;         // sum of n
+    hipLaunchKernelGGL(k_rowscan, dim3(blocks_for(rows * WAVE, 256)), dim3(256), 0, st, desc, S, rows, 0, bm,
+                       wpre, row_ptr);
+    VPLMC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_rowscan, dim3(blocks_for(cols * WAVE, 256)), dim3(256), 0, st, desc, S, cols, 1, bmt,
+                       wpret, col_ptr);
+    VPLMC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ptrscan, dim3(S), dim3(256), 0, st, desc, 0, row_ptr);
+    VPLMC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ptrscan, dim3(S), dim3(256), 0, st, desc, 1, col_ptr);
+    VPLMC_HIP(hipGetLastError());
+    if (plan.tot1 > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(plan.tot1, 256)), dim3(256), 0, st, desc, S, plan.tot1, 0,
+                           stats, omega1, val1, bm, bmt, wpre, wpret, row_ptr, col_ptr, csr_col, csr_val, csc_row,
+                           csc_val);
+        VPLMC_HIP(hipGetLastError());
+    }
+    if (plan.tot2 > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(plan.tot2, 256)), dim3(256), 0, st, desc, S, plan.tot2, 1,
+                           stats, omega2, val2, bm, bmt, wpre, wpret, row_ptr, col_ptr, csr_col, csr_val, csc_row,
+                           csc_val);
+        VPLMC_HIP(hipGetLastError());
+    }
+    return VPLMC_OK;
+}
+
+}  // namespace vplmc

@@ -1,0 +1,181 @@
+// Internal declarations shared by the host API and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vplmc.h"
+
+namespace vplmc {
+
+// ---------------------------------------------------------------- errors
+int set_error(int code, const char *fmt, ...);
+int hip_error(hipError_t e, const char *what);
+
+#define VPLMC_HIP(call)                                      \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return ::vplmc::hip_error(e_, #call); \
+    } while (0)
+
+// ------------------------------------------------------- random numbers
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).  One round maps
+// (c0, c1, c2, c3) to (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1,
+// lo(M0 c0)); the key is bumped by (W0, W1) between rounds.
+constexpr uint64_t PHILOX_M0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t PHILOX_M1 = 0xCA5A826395121157ull;
+constexpr uint64_t PHILOX_W0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t PHILOX_W1 = 0xBB67AE8584CAA73Bull;
+
+// Counter tags: the third counter word separates the method's streams.
+constexpr uint64_t TAG_PASS1 = 1;
+constexpr uint64_t TAG_PASS2 = 2;
+constexpr uint64_t TAG_INITX = 3;
+constexpr uint64_t TAG_INITY = 4;
+constexpr uint64_t TAG_REP = 5;
+
+struct U64x4 {
+    uint64_t a, b, c, d;
+};
+
+__device__ __forceinline__ U64x4 philox(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1,
+                                        uint64_t c2, uint64_t c3) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        const uint64_t lo0 = PHILOX_M0 * c0, hi0 = __umul64hi(PHILOX_M0, c0);
+        const uint64_t lo1 = PHILOX_M1 * c2, hi1 = __umul64hi(PHILOX_M1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0;
+        const uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return U64x4{c0, c1, c2, c3};
+}
+
+// floor(r * n / 2^64): a uniform 64-bit word mapped onto [0, n).
+__device__ __forceinline__ uint64_t mulhi64(uint64_t r, uint64_t n) { return __umul64hi(r, n); }
+
+// ------------------------------------------------------------ geometry
+struct BvhNode {            // 32 bytes; leaves: count > 0 spheres from first
+    float lo[3];
+    int32_t left_or_first;  // inner: index of the left child (right = left + 1 is NOT assumed)
+    float hi[3];
+    int32_t right_or_count; // inner: -(right child) - 1 ; leaf: sphere count
+};
+
+struct Bvh {
+    const BvhNode *nodes = nullptr;
+    const float4 *spheres = nullptr;   // (cx, cy, cz, r) in node order
+    int32_t n_nodes = 0;
+    int32_t n_spheres = 0;
+};
+
+// host build: spheres -> nodes + reordered spheres
+void build_bvh(int32_t n, const float *cx, const float *cy, const float *cz, const float *r,
+               std::vector<BvhNode> &nodes, std::vector<float> &sph4);
+
+// --------------------------------------------------------- frame layout
+// Device copy of one slice's layout (offsets in elements).
+struct SliceDesc {
+    int32_t m, n, q, N1;
+    int32_t N2, pt_off, cl_off, words_row;     // words_row = ceil(n / 32)
+    int32_t words_col, pad0, pad1, pad2;       // words_col = ceil(m / 32)
+    int64_t off1, off2, off_omega, off_col;
+    int64_t off_row, off_colptr, off_x, off_y;
+    int64_t off_bm, off_bmt;                   // bitmap word offsets (row- and column-major)
+};
+
+// Regions of the workspace: byte offsets.
+struct Layout {
+    size_t off[VPLMC_R_COUNT + 16];
+    size_t bytes[VPLMC_R_COUNT + 16];
+    size_t total;
+};
+
+// extra (internal) regions, after the public ones
+enum {
+    R_DESC = VPLMC_R_COUNT,
+    R_COLW_PREFIX,   // uint64 per (slice, column): inclusive prefix of the weights
+    R_BITMAP,        // uint32 words, row-major per slice
+    R_BITMAPT,       // uint32 words, column-major per slice
+    R_WPRE,          // uint16 per row-major word: popcount prefix within the row
+    R_WPRET,         // uint16 per column-major word
+    R_XNEXT,         // float[m][q]: second X buffer
+    R_XP,            // float[m][q]
+    R_LAMBDA,        // float[m][q]
+    R_YP,            // float[n][3][q]
+    R_PI,            // float[n][3][q]
+    R_SLICE_STATS,   // int32 iters, int32 flags, float resid, int32 n2 per slice
+    R_INTERNAL_END
+};
+
+}  // namespace vplmc
+
+struct vplmc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    vplmc::Bvh bvh;
+    void *bvh_mem = nullptr;   // owned device allocation holding nodes + spheres
+    int n_cu = 256;
+};
+
+struct vplmc_plan {
+    int32_t n_slices = 0;
+    int32_t n_clusters = 0;
+    int32_t pass1_ppm = 0, pass2_ppm = 0;
+    int64_t sum_m = 0, max_m = 0;
+    std::vector<vplmc::SliceDesc> desc;
+    std::vector<int32_t> slices_by_q[4];   // slice ids of rank bucket 4, 8, 16, 32
+    vplmc::Layout layout;
+    int64_t tot1 = 0, tot2 = 0, tot_omega = 0, tot_col = 0, tot_row = 0, tot_x = 0, tot_y = 0;
+    int64_t tot_bm = 0, tot_bmt = 0;
+    std::vector<int32_t> ids;                  // slice ids grouped by rank bucket
+    std::vector<char> upload;                  // descriptor table + ids, as copied to the workspace
+};
+
+namespace vplmc {
+// kernel launchers (kernels_*.hip)
+int launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v);
+int launch_cluster_table(hipStream_t st, const vplmc_lights &v, const vplmc_cut &cut, uint64_t seed,
+                         int32_t *rep, float *lights, float *bbox);
+int launch_philox(hipStream_t st, uint64_t k0, uint64_t k1, const uint64_t *ctr, int64_t n,
+                  uint64_t *out);
+int launch_pass1(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, uint64_t seed,
+                 uint32_t *omega1, uint32_t *bm, uint32_t *bmt);
+int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
+                      int32_t n_lights, const SliceDesc *desc, int32_t n_slices, const int32_t *pt_ids,
+                      const int32_t *cl_ids, const uint32_t *keys, int64_t n_keys, int which_pass,
+                      const int32_t *stats, const vplmc_params &prm, float *vals);
+int launch_colstats(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *omega1,
+                    const float *val1, int32_t *cnt, uint32_t *mn, uint32_t *mx);
+int launch_weights(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *cnt,
+                   const float *mn, const float *mx, uint32_t *w, uint64_t *prefix);
+int launch_pass2(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, uint64_t seed,
+                 const uint64_t *prefix, uint32_t *bm, uint32_t *bmt, uint32_t *omega2, int32_t *stats);
+int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *bm,
+                const uint32_t *bmt, uint16_t *wpre, uint16_t *wpret, int32_t *row_ptr, int32_t *col_ptr,
+                const uint32_t *omega1, const float *val1, const uint32_t *omega2, const float *val2,
+                const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, float *csc_val);
+int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
+               const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
+               const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, float *X, float *Xn,
+               float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale, int32_t *stats);
+int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,
+                  const float *X, const float *Y, const float *scale, float *radiance);
+int launch_eval_pairs(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,
+                      int64_t n, const int32_t *pid, const int32_t *lid, const vplmc_params &prm, float *out);
+int launch_brute_force(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,
+                       int32_t n_out, const int32_t *pid, const vplmc_params &prm, double *out);
+}  // namespace vplmc

@@ -1,0 +1,103 @@
+"""The C-ABI library loads, exports every symbol include/vplmc.h declares,
+and validates its arguments on the host (no GPU is touched here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2202_12567_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vplmc.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(N.LIB_PATH), reason="libvplmc.so not built")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(vplmc_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(N.LIB_PATH)
+    names = declared_symbols()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(N.SIG), "binding signatures and header disagree"
+
+
+def test_version_and_defaults():
+    lib = N.load()
+    assert lib.vplmc_version() == 100
+    p = N.Params()
+    assert lib.vplmc_default_params(ctypes.byref(p)) == 0
+    assert (p.pass1_ppm, p.pass2_ppm, p.max_iter) == (50000, 50000, 100)
+    assert abs(p.gamma - 1.6) < 1e-6 and abs(p.tol - 1e-3) < 1e-9
+    assert ctypes.sizeof(N.Params) == 48
+
+
+def plan(pt, cl, rank, nc=8, **kw):
+    lib = N.load()
+    p = N.Params()
+    lib.vplmc_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    pt = np.asarray(pt, np.int32)
+    cl = np.asarray(cl, np.int32)
+    rank = np.asarray(rank, np.int32)
+    h = ctypes.c_void_p()
+    f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rc = lib.vplmc_plan_create(len(rank), f(pt), f(cl), f(rank), nc, ctypes.byref(p), ctypes.byref(h))
+    return rc, h
+
+
+def test_plan_layout_and_counts():
+    lib = N.load()
+    rc, h = plan([0, 256, 512], [0, 1024, 2048], [8, 16], nc=1024)
+    assert rc == 0
+    info = N.SliceInfo()
+    assert lib.vplmc_plan_slice(h, 1, ctypes.byref(info)) == 0
+    assert (info.m, info.n, info.q) == (256, 1024, 16)
+    assert info.N1 == (50000 * 256 * 1024 + 500000) // 1000000
+    assert info.off1 == info.N1 and info.off_omega == info.N1 + info.N2 and info.off_x == 256 * 8
+    sz = ctypes.c_size_t()
+    assert lib.vplmc_workspace_size(h, ctypes.byref(sz)) == 0 and sz.value > 0
+    off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+    for r in range(len(N.REGIONS)):
+        assert lib.vplmc_plan_region(h, r, ctypes.byref(off), ctypes.byref(nb)) == 0
+        assert off.value % 256 == 0 and off.value + nb.value <= sz.value
+    assert lib.vplmc_plan_region(h, len(N.REGIONS), ctypes.byref(off), ctypes.byref(nb)) == N.EINVAL
+    assert lib.vplmc_plan_slice(h, 2, ctypes.byref(info)) == N.EINVAL
+    lib.vplmc_plan_destroy(h)
+
+
+@pytest.mark.parametrize("args,code,needle", [
+    (([0, 0], [0, 8], [4]), N.EINVAL, "rows"),
+    (([0, 70000], [0, 8], [4]), N.EINVAL, "rows"),
+    (([0, 64], [0, 8], [16]), N.EINVAL, "rank"),
+    (([0, 64], [0, 64], [33]), N.EINVAL, "rank"),
+    (([0, 64], [0, 64], [12]), N.EUNSUPPORTED, "rank"),
+    (([1, 64], [0, 64], [4]), N.EINVAL, "must be 0"),
+])
+def test_plan_rejects_bad_shapes(args, code, needle):
+    rc, _ = plan(*args)
+    assert rc == code
+    assert needle in N.load().vplmc_last_error().decode()
+
+
+@pytest.mark.parametrize("kw", [dict(pass1_ppm=-1), dict(pass1_ppm=600000, pass2_ppm=500000),
+                                dict(gamma=1.7), dict(alpha0=0.0), dict(max_iter=-1), dict(flags=8)])
+def test_plan_rejects_bad_params(kw):
+    rc, _ = plan([0, 64], [0, 64], [4], **kw)
+    assert rc == N.EINVAL
+
+
+def test_calls_without_a_context_fail_cleanly():
+    lib = N.load()
+    assert lib.vplmc_destroy(None) == 0
+    assert lib.vplmc_set_stream(None, None) == N.EINVAL
+    assert lib.vplmc_philox4x64(None, 0, 0, None, 0, None) == N.EINVAL
+    assert lib.vplmc_render(None, None, None, None, None, None, None, None, None, 0, None) == N.EINVAL
