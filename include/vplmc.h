@@ -199,6 +199,28 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
 int vplmc_read_stats(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace,
                      int32_t *iters, int32_t *flags, float *resid, int32_t *n2_accepted);
 
+/* ---- phase timing ---------------------------------------------------------
+ * Between begin and end, every vplmc_render on this context records HIP
+ * events on its stream around each phase (at most max_frames frames; later
+ * frames are not recorded).  end synchronises the stream and returns the
+ * summed milliseconds per phase (HOST double[VPLMC_N_PHASES]) and the
+ * number of frames recorded. */
+#define VPLMC_N_PHASES 10
+enum {
+    VPLMC_PH_SETUP = 0,   /* descriptor upload and buffer clears     */
+    VPLMC_PH_CLUSTER,     /* cluster table                           */
+    VPLMC_PH_PASS1,       /* first-pass sampling                     */
+    VPLMC_PH_EVAL1,       /* entries of the first pass               */
+    VPLMC_PH_WEIGHTS,     /* column statistics and importance        */
+    VPLMC_PH_PASS2,       /* second-pass sampling                    */
+    VPLMC_PH_EVAL2,       /* entries of the second pass              */
+    VPLMC_PH_SORT,        /* CSR / CSC ordering                      */
+    VPLMC_PH_ADM,         /* ADM completion                          */
+    VPLMC_PH_REDUCE       /* factorised column sum                   */
+};
+int vplmc_profile_begin(vplmc_ctx *ctx, int32_t max_frames);
+int vplmc_profile_end(vplmc_ctx *ctx, double *ms /* HOST */, int32_t *frames /* HOST */);
+
 /* ---- building blocks used by the frame, exposed for tests and tools ---- */
 /* Cluster table (Sec. 4): rep[c], lights float[9][n_clusters] (x y z nx ny nz
  * ir ig ib), bbox float[6][n_clusters].  All DEVICE outputs. */
@@ -213,7 +235,9 @@ int vplmc_eval_pairs(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lig
 
 /* Brute-force column sum over every light (the paper's reference images,
  * Sec. 6): out double[n_out][3] for points point_ids[0 .. n_out) (or points
- * 0 .. n_out-1 if point_ids is NULL).  FP32 entries, FP64 sums. */
+ * 0 .. n_out-1 if point_ids is NULL).  FP32 entries, FP64 sums; partial sums
+ * over chunks of 2048 lights are combined with FP64 atomics, so the last
+ * bits may vary between runs. */
 int vplmc_brute_force(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lights *lights,
                       int32_t n_out, const int32_t *point_ids, const vplmc_params *params,
                       double *out);

@@ -71,7 +71,11 @@ SIG = {
     "vplmc_brute_force": (I32, [P, ctypes.POINTER(Points), ctypes.POINTER(Lights), I32, P,
                                 ctypes.POINTER(Params), P]),
     "vplmc_philox4x64": (I32, [P, U64, U64, P, I64, P]),
+    "vplmc_profile_begin": (I32, [P, I32]),
+    "vplmc_profile_end": (I32, [P, P, P]),
 }
+N_PHASES = 10
+PHASES = ["setup", "cluster", "pass1", "eval1", "weights", "pass2", "eval2", "sort", "adm", "reduce"]
 
 _lib = None
 

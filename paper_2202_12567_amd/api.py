@@ -208,3 +208,15 @@ def philox4x64(ctx, key0, key1, ctr):
     out = torch.empty_like(ctr)
     check(N.load().vplmc_philox4x64(ctx.h, key0, key1, _ptr(ctr), n, _ptr(out)))
     return out
+
+
+def profile_begin(ctx, max_frames):
+    check(N.load().vplmc_profile_begin(ctx.h, int(max_frames)))
+
+
+def profile_end(ctx):
+    """Summed ms per phase (dict) over the recorded frames, and the frame count."""
+    ms = np.zeros(N.N_PHASES, np.float64)
+    fr = np.zeros(1, np.int32)
+    check(N.load().vplmc_profile_end(ctx.h, ms.ctypes.data_as(ctypes.c_void_p), fr.ctypes.data_as(ctypes.c_void_p)))
+    return dict(zip(N.PHASES, ms.tolist())), int(fr[0])

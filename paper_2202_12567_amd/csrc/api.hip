@@ -70,6 +70,23 @@ int rank_bucket(int q) {
     }
 }
 
+// records the boundary event `b` (0 .. VPLMC_N_PHASES) of the current frame
+struct PhaseMarks {
+    vplmc_ctx *ctx;
+    hipEvent_t *ev = nullptr;
+    explicit PhaseMarks(vplmc_ctx *c) : ctx(c) {
+        if (c->prof_on && c->prof_frames < c->prof_max_frames)
+            ev = &c->prof_events[(size_t)c->prof_frames * (VPLMC_N_PHASES + 1)];
+    }
+    int mark(int b) {
+        if (ev) VPLMC_HIP(hipEventRecord(ev[b], ctx->stream));
+        return VPLMC_OK;
+    }
+    void done() {
+        if (ev) ctx->prof_frames++;
+    }
+};
+
 template <typename T>
 T *region(void *ws, const vplmc_plan *plan, int r) {
     return reinterpret_cast<T *>(static_cast<char *>(ws) + plan->layout.off[r]);
@@ -124,11 +141,10 @@ int vplmc_create(int device, void *stream, vplmc_ctx **out) {
 
 int vplmc_destroy(vplmc_ctx *ctx) {
     if (!ctx) return VPLMC_OK;
-    if (ctx->bvh_mem) {
-        (void)hipSetDevice(ctx->device);
-        (void)hipStreamSynchronize(ctx->stream);
-        (void)hipFree(ctx->bvh_mem);
-    }
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->bvh_mem) (void)hipFree(ctx->bvh_mem);
+    for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
     delete ctx;
     return VPLMC_OK;
 }
@@ -379,6 +395,8 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     hipStream_t st = ctx->stream;
     void *ws = workspace;
     const int S = plan->n_slices;
+    PhaseMarks ph(ctx);
+    if ((rc = ph.mark(VPLMC_PH_SETUP))) return rc;
 
     SliceDesc *desc = region<SliceDesc>(ws, plan, R_DESC);
     const int32_t *ids = reinterpret_cast<const int32_t *>(desc + S);
@@ -399,6 +417,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(stats), 4 * (size_t)S, 0u))) return rc;
     if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(radiance), 3 * (size_t)points->m, 0u))) return rc;
 
+    if ((rc = ph.mark(VPLMC_PH_CLUSTER))) return rc;
     float *lights = region<float>(ws, plan, VPLMC_R_LIGHTS);
     if ((rc = launch_cluster_table(st, *vpls, *cut, params->seed, region<int32_t>(ws, plan, VPLMC_R_REP), lights,
                                    region<float>(ws, plan, VPLMC_R_BBOX))))
@@ -407,19 +426,25 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     float *val1 = region<float>(ws, plan, VPLMC_R_VAL1);
     uint32_t *omega2 = region<uint32_t>(ws, plan, VPLMC_R_OMEGA2);
     float *val2 = region<float>(ws, plan, VPLMC_R_VAL2);
+    if ((rc = ph.mark(VPLMC_PH_PASS1))) return rc;
     if ((rc = launch_pass1(st, *plan, desc, params->seed, omega1, bm, bmt))) return rc;
+    if ((rc = ph.mark(VPLMC_PH_EVAL1))) return rc;
     if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_clusters, desc, S, pt_ids, cl_ids, omega1,
                                 plan->tot1, 0, stats, *params, val1)))
         return rc;
+    if ((rc = ph.mark(VPLMC_PH_WEIGHTS))) return rc;
     if ((rc = launch_colstats(st, *plan, desc, omega1, val1, cnt, mn, mx))) return rc;
     uint64_t *prefix = region<uint64_t>(ws, plan, R_COLW_PREFIX);
     if ((rc = launch_weights(st, *plan, desc, cnt, reinterpret_cast<const float *>(mn),
                              reinterpret_cast<const float *>(mx), region<uint32_t>(ws, plan, VPLMC_R_WEIGHTS), prefix)))
         return rc;
+    if ((rc = ph.mark(VPLMC_PH_PASS2))) return rc;
     if ((rc = launch_pass2(st, *plan, desc, params->seed, prefix, bm, bmt, omega2, stats))) return rc;
+    if ((rc = ph.mark(VPLMC_PH_EVAL2))) return rc;
     if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_clusters, desc, S, pt_ids, cl_ids, omega2,
                                 plan->tot2, 1, stats, *params, val2)))
         return rc;
+    if ((rc = ph.mark(VPLMC_PH_SORT))) return rc;
     int32_t *row_ptr = region<int32_t>(ws, plan, VPLMC_R_ROW_PTR);
     int32_t *col_ptr = region<int32_t>(ws, plan, VPLMC_R_COL_PTR);
     int32_t *csr_col = region<int32_t>(ws, plan, VPLMC_R_CSR_COL);
@@ -432,12 +457,52 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     float *X = region<float>(ws, plan, VPLMC_R_X);
     float *Y = region<float>(ws, plan, VPLMC_R_Y);
     float *scale = region<float>(ws, plan, VPLMC_R_SLICE_SCALE);
+    if ((rc = ph.mark(VPLMC_PH_ADM))) return rc;
     if ((rc = launch_adm(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X,
                          region<float>(ws, plan, R_XNEXT), region<float>(ws, plan, R_XP),
                          region<float>(ws, plan, R_LAMBDA), Y, region<float>(ws, plan, R_YP),
                          region<float>(ws, plan, R_PI), scale, stats)))
         return rc;
-    return launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, radiance);
+    if ((rc = ph.mark(VPLMC_PH_REDUCE))) return rc;
+    if ((rc = launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, radiance))) return rc;
+    if ((rc = ph.mark(VPLMC_N_PHASES))) return rc;
+    ph.done();
+    return VPLMC_OK;
+}
+
+int vplmc_profile_begin(vplmc_ctx *ctx, int32_t max_frames) {
+    if (!ctx) return set_error(VPLMC_EINVAL, "ctx is NULL");
+    if (max_frames < 1 || max_frames > 4096) return set_error(VPLMC_EINVAL, "max_frames must be in [1, 4096]");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    const size_t need = (size_t)max_frames * (VPLMC_N_PHASES + 1);
+    while (ctx->prof_events.size() < need) {
+        hipEvent_t e;
+        VPLMC_HIP(hipEventCreate(&e));
+        ctx->prof_events.push_back(e);
+    }
+    ctx->prof_max_frames = max_frames;
+    ctx->prof_frames = 0;
+    ctx->prof_on = true;
+    return VPLMC_OK;
+}
+
+int vplmc_profile_end(vplmc_ctx *ctx, double *ms, int32_t *frames) {
+    if (!ctx || !ms || !frames) return set_error(VPLMC_EINVAL, "ctx, ms and frames must be non-NULL");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    VPLMC_HIP(hipStreamSynchronize(ctx->stream));
+    for (int p = 0; p < VPLMC_N_PHASES; ++p) ms[p] = 0.0;
+    for (int f = 0; f < ctx->prof_frames; ++f) {
+        hipEvent_t *ev = &ctx->prof_events[(size_t)f * (VPLMC_N_PHASES + 1)];
+        for (int p = 0; p < VPLMC_N_PHASES; ++p) {
+            float t = 0.f;
+            VPLMC_HIP(hipEventElapsedTime(&t, ev[p], ev[p + 1]));
+            ms[p] += t;
+        }
+    }
+    *frames = ctx->prof_frames;
+    ctx->prof_on = false;
+    ctx->prof_frames = 0;
+    return VPLMC_OK;
 }
 
 int vplmc_read_stats(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace, int32_t *iters, int32_t *flags,

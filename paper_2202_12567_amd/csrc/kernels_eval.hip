@@ -165,9 +165,11 @@ __global__ __launch_bounds__(256) void k_eval_pairs(Bvh bvh, vplmc_points pts, v
     out[3 * g + 2] = o2;
 }
 
-// Brute-force column sum: one thread per point, lights staged through LDS,
-// FP32 entries summed in FP64.
+// Brute-force column sum: one thread per point and light chunk (grid.y),
+// lights staged through LDS; FP32 entries summed in FP64, chunk partial sums
+// added to the zeroed output with FP64 atomics.
 constexpr int BF_TILE = 256;
+constexpr int BF_CHUNK = 2048;
 __global__ __launch_bounds__(256) void k_brute_force(Bvh bvh, vplmc_points pts, vplmc_lights l, int32_t n_out,
                                                      const int32_t *__restrict__ pid, float r_min2, float eps,
                                                      double *__restrict__ out) {
@@ -177,9 +179,11 @@ __global__ __launch_bounds__(256) void k_brute_force(Bvh bvh, vplmc_points pts, 
     PointData q{};
     if (active) q = load_point(pts, pid ? pid[g] : g);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int b = 0; b < l.n; b += BF_TILE) {
+    const int c0 = blockIdx.y * BF_CHUNK;
+    const int c1 = min(l.n, c0 + BF_CHUNK);
+    for (int b = c0; b < c1; b += BF_TILE) {
         const int c = b + threadIdx.x;
-        if (c < l.n) {
+        if (c < c1) {
             sl[0][threadIdx.x] = l.x[c];
             sl[1][threadIdx.x] = l.y[c];
             sl[2][threadIdx.x] = l.z[c];
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(256) void k_brute_force(Bvh bvh, vplmc_points pts, 
             sl[8][threadIdx.x] = l.ib[c];
         }
         __syncthreads();
-        const int cnt = min(BF_TILE, l.n - b);
+        const int cnt = min(BF_TILE, c1 - b);
         if (active) {
             for (int k = 0; k < cnt; ++k) {
                 const Light L = {{sl[0][k], sl[1][k], sl[2][k]}, {sl[3][k], sl[4][k], sl[5][k]}, sl[6][k], sl[7][k],
@@ -206,10 +210,15 @@ __global__ __launch_bounds__(256) void k_brute_force(Bvh bvh, vplmc_points pts, 
         __syncthreads();
     }
     if (active) {
-        out[3 * (size_t)g] = a0;
-        out[3 * (size_t)g + 1] = a1;
-        out[3 * (size_t)g + 2] = a2;
+        atomicAdd(out + 3 * (size_t)g, a0);
+        atomicAdd(out + 3 * (size_t)g + 1, a1);
+        atomicAdd(out + 3 * (size_t)g + 2, a2);
     }
+}
+
+__global__ void k_zero_f64(double *p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
 }
 
 unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
@@ -240,8 +249,13 @@ int launch_eval_pairs(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, c
 int launch_brute_force(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,
                        int32_t n_out, const int32_t *pid, const vplmc_params &prm, double *out) {
     if (n_out <= 0) return VPLMC_OK;
-    hipLaunchKernelGGL(k_brute_force, dim3(blocks_for(n_out, 256)), dim3(256), 0, st, bvh, pts, l, n_out, pid,
-                       prm.r_min * prm.r_min, prm.ray_eps, out);
+    const size_t nz = 3 * (size_t)n_out;
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)std::min<size_t>((nz + 255) / 256, 65536)), dim3(256), 0, st, out, nz);
+    VPLMC_HIP(hipGetLastError());
+    if (l.n <= 0) return VPLMC_OK;
+    const unsigned chunks = (unsigned)((l.n + BF_CHUNK - 1) / BF_CHUNK);
+    hipLaunchKernelGGL(k_brute_force, dim3(blocks_for(n_out, 256), chunks), dim3(256), 0, st, bvh, pts, l, n_out,
+                       pid, prm.r_min * prm.r_min, prm.ray_eps, out);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }

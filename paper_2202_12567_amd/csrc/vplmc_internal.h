@@ -129,6 +129,11 @@ struct vplmc_ctx {
     vplmc::Bvh bvh;
     void *bvh_mem = nullptr;   // owned device allocation holding nodes + spheres
     int n_cu = 256;
+    // phase timing: events[frame][phase boundary]
+    std::vector<hipEvent_t> prof_events;
+    int prof_max_frames = 0;
+    int prof_frames = 0;
+    bool prof_on = false;
 };
 
 struct vplmc_plan {
