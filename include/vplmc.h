@@ -108,6 +108,7 @@ typedef struct vplmc_plan vplmc_plan;
 typedef struct {
     int32_t m, n, q;         /* rows, cut columns, rank                           */
     int32_t N1, N2;          /* first-pass count and second-pass target           */
+    int32_t adm_in_lds;      /* 1: the ADM kernel keeps X in LDS; 0: in global memory */
     int64_t off1, off2;      /* element offsets into OMEGA1/VAL1, OMEGA2/VAL2     */
     int64_t off_omega;       /* element offset into CSR_* / CSC_* (N1 + N2 each)  */
     int64_t off_col;         /* element offset into per-column regions            */

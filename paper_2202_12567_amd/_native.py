@@ -33,7 +33,7 @@ class Params(ctypes.Structure):
 
 class SliceInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("q", ctypes.c_int32), ("N1", ctypes.c_int32),
-                ("N2", ctypes.c_int32), ("off1", ctypes.c_int64), ("off2", ctypes.c_int64),
+                ("N2", ctypes.c_int32), ("adm_in_lds", ctypes.c_int32), ("off1", ctypes.c_int64), ("off2", ctypes.c_int64),
                 ("off_omega", ctypes.c_int64), ("off_col", ctypes.c_int64), ("off_row", ctypes.c_int64),
                 ("off_colptr", ctypes.c_int64), ("off_x", ctypes.c_int64), ("off_y", ctypes.c_int64)]
 

@@ -263,7 +263,9 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         obm += m * d.words_row;
         obmt += n * d.words_col;
         summ += m;
-        plan->slices_by_q[bucket].push_back(s);
+        const int grp = 2 * bucket + (adm_fits_lds(q, (int)m) ? 0 : 1);
+        plan->groups[grp].push_back(s);
+        plan->group_max_m[grp] = std::max<int32_t>(plan->group_max_m[grp], (int32_t)m);
         plan->max_m = std::max<int64_t>(plan->max_m, m);
     }
     plan->tot1 = o1;
@@ -277,7 +279,7 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     plan->tot_bmt = obmt;
     plan->sum_m = summ;
     plan->ids.clear();
-    for (int b = 0; b < 4; ++b) plan->ids.insert(plan->ids.end(), plan->slices_by_q[b].begin(), plan->slices_by_q[b].end());
+    for (int g = 0; g < 8; ++g) plan->ids.insert(plan->ids.end(), plan->groups[g].begin(), plan->groups[g].end());
 
     Layout &L = plan->layout;
     memset(&L, 0, sizeof(L));
@@ -352,6 +354,7 @@ int vplmc_plan_slice(const vplmc_plan *plan, int32_t s, vplmc_slice_info *out) {
     out->q = d.q;
     out->N1 = d.N1;
     out->N2 = d.N2;
+    out->adm_in_lds = adm_fits_lds(d.q, d.m) ? 1 : 0;
     out->off1 = d.off1;
     out->off2 = d.off2;
     out->off_omega = d.off_omega;

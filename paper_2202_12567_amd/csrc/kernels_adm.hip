@@ -24,6 +24,8 @@
 // iteration; rows and columns are then multiplied by the FP64 inverse.
 // Every reduction has a fixed order: results are bitwise reproducible.
 
+#include <type_traits>
+
 #include "vplmc_internal.h"
 
 namespace vplmc {
@@ -36,6 +38,11 @@ __device__ __forceinline__ float wave_sum(float v) {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
     return v;
 }
+// a wavefront-uniform value kept in a scalar register
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
@@ -463,6 +470,439 @@ __global__ __launch_bounds__(THREADS) void k_adm(
     }
 }
 
+// ---------------------------------------------------------------------------
+// LDS-resident variant for ranks 4, 8, 16: both X buffers live in LDS and
+// both phases stream the slice's samples in column-major (CSC) order, so the
+// only gathers are LDS reads.  A wavefront is four groups of 16 lanes (one
+// DPP row each); a group owns one column at a time and lane k of the group
+// owns rank component k, so Y_j, the X+^T R accumulators and a row of the
+// new Gram are three, three and q registers per lane.  Samples are loaded 32
+// at a time, two per lane, and handed to the whole group with DPP row
+// broadcasts; the dot product X_i . Y_j is a four-step DPP row reduction.
+//   phase A: residual with X_k (LDS), R Y^T added into the other LDS buffer
+//     with one LDS float atomic per lane and sample;
+//   X update: t = R Y^T + a U - L staged in LDS, X+ = X (GY Inv) + t Inv in
+//     FP64, written through a global staging buffer;
+//   phase B: residuals from (X_k, Y_k), X+^T R accumulated in lane k, Y+_j
+//     solved in FP64 with the inverse applied across the group by DPP
+//     broadcasts, Y+ Y+^T accumulated per lane and added into the Gram with
+//     LDS atomics.
+// The next round's column metadata, Y row and first sample batch are loaded
+// while the current round is processed.  The atomics make the FP summation
+// order, and hence the last bits of the result, vary between runs.
+constexpr int GRP = 16;   // lanes per column group = one DPP row
+constexpr int PBK = 1;    // samples per lane in one batch
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+// sum over the 16 lanes of a DPP row, result in every lane of the row
+__device__ __forceinline__ float row_sum16(float v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return v;
+}
+// value of lane S of the row, in every lane of the row (row_newbcast)
+template <int S>
+__device__ __forceinline__ float row_bcast(float v) { return dpp_mov<0x150 + S>(v); }
+template <int S>
+__device__ __forceinline__ int row_bcast_i(int v) { return dpp_mov_i<0x150 + S>(v); }
+
+template <int S, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (S < N) {
+        f(std::integral_constant<int, S>{});
+        static_for<S + 1, N>(f);
+    }
+}
+
+struct Batch {
+    int i[PBK];
+    float m0[PBK], m1[PBK], m2[PBK];
+};
+
+__device__ __forceinline__ void load_batch(const int32_t *__restrict__ csc_row, const float *__restrict__ csc_val,
+                                           int p0, int end, int gl, float inv_s0, Batch &b) {
+#pragma unroll
+    for (int u = 0; u < PBK; ++u) {
+        const int p = p0 + u * GRP + gl;
+        const bool ok = p < end;
+        const int pc = ok ? p : 0;
+        b.i[u] = ok ? csc_row[pc] : 0;
+        b.m0[u] = ok ? csc_val[3 * pc] * inv_s0 : 0.f;
+        b.m1[u] = ok ? csc_val[3 * pc + 1] * inv_s0 : 0.f;
+        b.m2[u] = ok ? csc_val[3 * pc + 2] * inv_s0 : 0.f;
+    }
+}
+
+// one batch of phase A: cnt valid samples of the batch (uniform in the group)
+template <int Q>
+__device__ __forceinline__ void batchA(const Batch &b, int cnt, int kk, const float *XA, float *XB, float y0,
+                                       float y1, float y2, double &e2) {
+    const bool kact = kk < Q;
+    const int kc = kact ? kk : 0;
+#pragma unroll
+    for (int u = 0; u < PBK; ++u) {
+        static_for<0, GRP>([&](auto sc) {
+            constexpr int S = decltype(sc)::value;
+            if (u * GRP + S < cnt) {
+                const int i = row_bcast_i<S>(b.i[u]);
+                const float m0 = row_bcast<S>(b.m0[u]), m1 = row_bcast<S>(b.m1[u]), m2 = row_bcast<S>(b.m2[u]);
+                const float x = kact ? XA[i * Q + kc] : 0.f;
+                const float d0 = row_sum16(x * y0), d1 = row_sum16(x * y1), d2 = row_sum16(x * y2);
+                const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
+                if (kk == 0) e2 += (double)(r0 * r0) + (double)(r1 * r1) + (double)(r2 * r2);
+                if (kact) atomicAdd(XB + i * Q + kc, fmaf(r0, y0, fmaf(r1, y1, r2 * y2)));
+            }
+        });
+    }
+}
+
+// one batch of phase B
+template <int Q>
+__device__ __forceinline__ void batchB(const Batch &b, int cnt, int kk, const float *XA, const float *XB, float y0,
+                                       float y1, float y2, float &a0, float &a1, float &a2) {
+    const bool kact = kk < Q;
+    const int kc = kact ? kk : 0;
+#pragma unroll
+    for (int u = 0; u < PBK; ++u) {
+        static_for<0, GRP>([&](auto sc) {
+            constexpr int S = decltype(sc)::value;
+            if (u * GRP + S < cnt) {
+                const int i = row_bcast_i<S>(b.i[u]);
+                const float m0 = row_bcast<S>(b.m0[u]), m1 = row_bcast<S>(b.m1[u]), m2 = row_bcast<S>(b.m2[u]);
+                const float xo = kact ? XA[i * Q + kc] : 0.f;
+                const float xn = kact ? XB[i * Q + kc] : 0.f;
+                const float r0 = m0 - row_sum16(xo * y0);
+                const float r1 = m1 - row_sum16(xo * y1);
+                const float r2 = m2 - row_sum16(xo * y2);
+                a0 = fmaf(xn, r0, a0);
+                a1 = fmaf(xn, r1, a1);
+                a2 = fmaf(xn, r2, a2);
+            }
+        });
+    }
+}
+
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_adm_lds(
+    const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, uint64_t seed,
+    int32_t max_iter, int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma,
+    const int32_t *__restrict__ col_ptr_all, const int32_t *__restrict__ csc_row_all,
+    const float *__restrict__ csc_val_all, float *X_all, float *Xn_all, float *Xp_all, float *Lam_all,
+    float *Y_all, float *Yp_all, float *Pi_all, float *scale_all, int32_t *stats_all) {
+    static_assert(Q <= GRP, "one lane per rank component");
+    constexpr int NW = THREADS / WAVE;
+    constexpr int NG = THREADS / GRP;                  // column groups per workgroup
+    constexpr int BS = PBK * GRP;                      // samples per group batch
+    extern __shared__ float dyn[];
+    __shared__ AdmShared<Q> sh;
+    __shared__ float red2[THREADS];
+
+    const int s = slice_list[blockIdx.x];
+    const SliceDesc d = desc[s];
+    const int m = d.m, n = d.n;
+    const int t = threadIdx.x, lane = t % WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
+    const int gl = lane % GRP;                         // lane in its group = rank component
+    const int grp = t / GRP;
+    const bool kact = gl < Q;
+    const int kc = kact ? gl : 0;
+    float *XA = dyn;
+    float *XB = dyn + (size_t)m * Q;
+
+    const int32_t *col_ptr = col_ptr_all + d.off_colptr;
+    const int32_t *csc_row = csc_row_all + d.off_omega;
+    const float *csc_val = csc_val_all + 3 * d.off_omega;
+    float *Xg = X_all + d.off_x;
+    float *Xs = Xn_all + d.off_x;     // staging of X+
+    float *Xp = Xp_all + d.off_x;
+    float *Lam = Lam_all + d.off_x;
+    float *Y = Y_all + d.off_y;
+    float *Yp = Yp_all + d.off_y;
+    float *Pi = Pi_all + d.off_y;
+    int32_t *st = stats_all + 4 * s;
+    const int nnz = col_ptr[n];
+
+    double sum = 0.0, sumsq = 0.0;
+    for (int p = t; p < 3 * nnz; p += THREADS) {
+        const double v = (double)csc_val[p];
+        sum += v;
+        sumsq += v * v;
+    }
+    sum = wave_sum_d(sum);
+    sumsq = wave_sum_d(sumsq);
+    if (lane == 0) {
+        sh.red[wave] = sum;
+        sh.red[16 + wave] = sumsq;
+    }
+    __syncthreads();
+    double tot = 0.0, totsq = 0.0;
+    for (int w = 0; w < NW; ++w) {
+        tot += sh.red[w];
+        totsq += sh.red[16 + w];
+    }
+    __syncthreads();
+    if (!(nnz > 0 && tot > 0.0)) {
+        for (int e = t; e < m * Q; e += THREADS) Xg[e] = 0.f;
+        for (int e = t; e < 3 * n * Q; e += THREADS) Y[e] = 0.f;
+        if (t == 0) {
+            scale_all[s] = 0.f;
+            st[0] = 0;
+            st[1] |= VPLMC_SLICE_ALL_ZERO;
+            st[2] = __float_as_int(0.f);
+        }
+        return;
+    }
+    const double s0 = tot / (3.0 * (double)nnz);
+    const float inv_s0 = (float)(1.0 / s0);
+    const double normM = sqrt(totsq) / s0;
+    if (t == 0) scale_all[s] = (float)s0;
+
+    const float cq = (float)(2.0 / sqrt((double)Q));
+    for (int e = t; e < m * Q; e += THREADS) {
+        const int i = e / Q, k = e % Q;
+        const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
+        const float v = __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq);
+        XA[e] = v;
+        Xp[e] = v;
+        Lam[e] = 0.f;
+    }
+    for (int e = t; e < 3 * n * Q; e += THREADS) {
+        const int j = e / (3 * Q), c = (e / Q) % 3, k = e % Q;
+        const uint64_t col = (uint64_t)c * (uint64_t)n + (uint64_t)j;
+        const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)k, col, TAG_INITY, 0);
+        const float v = __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq);
+        Y[e] = v;
+        Yp[e] = v;
+        Pi[e] = 0.f;
+    }
+    __threadfence_block();
+    __syncthreads();
+    gram_rows<Q>(sh, Y, 3 * n, red2);
+
+    const double alpha = (double)alpha0 * (3.0 * n) / Q;
+    const double beta = (double)beta0 * (double)m / Q;
+    const float alpha_f = (float)alpha, beta_f = (float)beta;
+    const float ga = (float)((double)gamma * alpha), gb = (float)((double)gamma * beta);
+    const float inv_alpha = (float)(1.0 / alpha), inv_beta = (float)(1.0 / beta);
+
+    // column metadata of a group's round: j = rd * NG + grp
+    auto col_range = [&](int j, int &b, int &e) {
+        if (j < n) {
+            b = col_ptr[j];
+            e = col_ptr[j + 1];
+        } else {
+            b = e = 0;
+        }
+    };
+    auto load_y = [&](int j, float &y0, float &y1, float &y2) {
+        const float *yj = Y + (size_t)(j < n ? j : 0) * 3 * Q;
+        y0 = (kact && j < n) ? yj[kc] : 0.f;
+        y1 = (kact && j < n) ? yj[Q + kc] : 0.f;
+        y2 = (kact && j < n) ? yj[2 * Q + kc] : 0.f;
+    };
+
+    int iters = max_iter;
+    double err = 0.0;
+    for (int it = 0; it < max_iter; ++it) {
+        // ---- phase A: R Y^T added into XB, residual norm ----
+        for (int e = t; e < m * Q; e += THREADS) XB[e] = 0.f;
+        __syncthreads();
+        double e2 = 0.0;
+        {
+            int j = grp, beg, end, begn, endn;
+            float y0, y1, y2, z0, z1, z2;
+            Batch bc, bn, bx;
+            col_range(j, beg, end);
+            load_y(j, y0, y1, y2);
+            load_batch(csc_row, csc_val, beg, end, gl, inv_s0, bc);
+            for (; j < n; j += NG) {
+                const int jn = j + NG;
+                col_range(jn, begn, endn);
+                load_y(jn, z0, z1, z2);
+                load_batch(csc_row, csc_val, begn, endn, gl, inv_s0, bn);
+                for (int p0 = beg; p0 < end; p0 += BS) {
+                    const bool more = p0 + BS < end;
+                    if (more) load_batch(csc_row, csc_val, p0 + BS, end, gl, inv_s0, bx);
+                    batchA<Q>(bc, end - p0, gl, XA, XB, y0, y1, y2, e2);
+                    if (more) bc = bx;
+                }
+                bc = bn;
+                y0 = z0; y1 = z1; y2 = z2;
+                beg = begn;
+                end = endn;
+            }
+        }
+        e2 = wave_sum_d(e2);
+        if (lane == 0) sh.red[wave] = e2;
+        __syncthreads();
+        double e2t = 0.0;
+        for (int w = 0; w < NW; ++w) e2t += sh.red[w];
+        err = sqrt(e2t) / normM;
+        if (!fixed_iters && err < (double)tol) {
+            iters = it;
+            break;
+        }
+
+        // ---- X update: t = RX + a U - L (in XB), X+ = X (GY Inv) + t Inv ----
+        for (int e = t; e < m * Q; e += THREADS) XB[e] += alpha_f * Xp[e] - Lam[e];
+        spd_inverse<Q>(sh, alpha);           // begins and ends with a barrier
+        for (int e = t; e < Q * Q; e += THREADS) {
+            const int a = e / Q, b = e % Q;
+            double v = 0.0;
+            for (int l = 0; l < Q; ++l) v += (double)sh.G[a * Q + l] * sh.Inv[l * Q + b];
+            sh.F[e] = v;
+        }
+        __syncthreads();
+        for (int e = t; e < m * Q; e += THREADS) {
+            const int i = e / Q, k = e % Q;
+            const float *xa = XA + i * Q;
+            const float *tb = XB + i * Q;
+            double v = 0.0;
+#pragma unroll 4
+            for (int l = 0; l < Q; ++l) v += (double)xa[l] * sh.F[l * Q + k] + (double)tb[l] * sh.Inv[l * Q + k];
+            Xs[e] = (float)v;
+        }
+        __threadfence_block();
+        __syncthreads();
+        for (int e = t; e < m * Q; e += THREADS) {
+            const float xn = Xs[e];
+            const float lam = Lam[e];
+            const float u = fmaxf(0.f, xn + lam * inv_alpha);
+            Xp[e] = u;
+            Lam[e] = lam + ga * (xn - u);
+            XB[e] = xn;
+        }
+        __syncthreads();
+        // Grams GX = X+^T X+ and C = X+^T X over the rows (fixed order)
+        {
+            constexpr int P = Q * Q;
+            const int groups = THREADS / P, g = t / P, pp = t % P;
+            const int a = pp / Q, b = pp % Q;
+            float gx = 0.f, cc = 0.f;
+            for (int r = g; r < m; r += groups) {
+                const float xa = XB[r * Q + a];
+                gx = fmaf(xa, XB[r * Q + b], gx);
+                cc = fmaf(xa, XA[r * Q + b], cc);
+            }
+            red2[t] = gx;
+            __syncthreads();
+            if (t < P) {
+                float v = 0.f;
+                for (int gg = 0; gg < groups; ++gg) v += red2[gg * P + t];
+                sh.G[t] = v;
+            }
+            __syncthreads();
+            red2[t] = cc;
+            __syncthreads();
+            if (t < P) {
+                float v = 0.f;
+                for (int gg = 0; gg < groups; ++gg) v += red2[gg * P + t];
+                sh.C[t] = v;
+            }
+        }
+        // ---- Y system: Inv = (GX + b I)^-1, F^T = (Inv C)^T ----
+        spd_inverse<Q>(sh, beta);
+        for (int e = t; e < Q * Q; e += THREADS) {
+            const int a = e / Q, b = e % Q;
+            double v = 0.0;
+            for (int l = 0; l < Q; ++l) v += sh.Inv[a * Q + l] * (double)sh.C[l * Q + b];
+            sh.F[b * Q + a] = v;
+        }
+        for (int e = t; e < Q * Q; e += THREADS) sh.G[e] = 0.f;
+        __syncthreads();
+
+        // ---- phase B ----
+        float gyrow[Q];
+#pragma unroll
+        for (int b = 0; b < Q; ++b) gyrow[b] = 0.f;
+        {
+            int j = grp, beg, end, begn, endn;
+            float y0, y1, y2, z0, z1, z2;
+            Batch bc, bn, bx;
+            col_range(j, beg, end);
+            load_y(j, y0, y1, y2);
+            load_batch(csc_row, csc_val, beg, end, gl, inv_s0, bc);
+            for (; j < n; j += NG) {
+                const int jn = j + NG;
+                col_range(jn, begn, endn);
+                load_y(jn, z0, z1, z2);
+                load_batch(csc_row, csc_val, begn, endn, gl, inv_s0, bn);
+                float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+                for (int p0 = beg; p0 < end; p0 += BS) {
+                    const bool more = p0 + BS < end;
+                    if (more) load_batch(csc_row, csc_val, p0 + BS, end, gl, inv_s0, bx);
+                    batchB<Q>(bc, end - p0, gl, XA, XB, y0, y1, y2, a0, a1, a2);
+                    if (more) bc = bx;
+                }
+                // Y+ (c, k) = sum_l F[k][l] y(c, l) + Inv[k][l] t(c, l), lane k of the group
+                float *ypj = Yp + (size_t)j * 3 * Q;
+                float *pij = Pi + (size_t)j * 3 * Q;
+                const float p0v = kact ? pij[kc] : 0.f, p1v = kact ? pij[Q + kc] : 0.f, p2v = kact ? pij[2 * Q + kc] : 0.f;
+                const float t0 = kact ? a0 + beta_f * ypj[kc] - p0v : 0.f;
+                const float t1 = kact ? a1 + beta_f * ypj[Q + kc] - p1v : 0.f;
+                const float t2 = kact ? a2 + beta_f * ypj[2 * Q + kc] - p2v : 0.f;
+                double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+                static_for<0, Q>([&](auto lc) {
+                    constexpr int L = decltype(lc)::value;
+                    const double f = sh.F[L * Q + kc], iv = sh.Inv[L * Q + kc];
+                    v0 += f * (double)row_bcast<L>(y0) + iv * (double)row_bcast<L>(t0);
+                    v1 += f * (double)row_bcast<L>(y1) + iv * (double)row_bcast<L>(t1);
+                    v2 += f * (double)row_bcast<L>(y2) + iv * (double)row_bcast<L>(t2);
+                });
+                const float n0 = kact ? (float)v0 : 0.f, n1 = kact ? (float)v1 : 0.f, n2 = kact ? (float)v2 : 0.f;
+                if (kact) {
+                    const float u0 = fmaxf(0.f, n0 + p0v * inv_beta);
+                    const float u1 = fmaxf(0.f, n1 + p1v * inv_beta);
+                    const float u2 = fmaxf(0.f, n2 + p2v * inv_beta);
+                    ypj[kc] = u0;
+                    ypj[Q + kc] = u1;
+                    ypj[2 * Q + kc] = u2;
+                    pij[kc] = p0v + gb * (n0 - u0);
+                    pij[Q + kc] = p1v + gb * (n1 - u1);
+                    pij[2 * Q + kc] = p2v + gb * (n2 - u2);
+                    float *yw = Y + (size_t)j * 3 * Q;
+                    yw[kc] = n0;
+                    yw[Q + kc] = n1;
+                    yw[2 * Q + kc] = n2;
+                }
+                // row kc of Y+ Y+^T for this column
+                static_for<0, Q>([&](auto bc2) {
+                    constexpr int B = decltype(bc2)::value;
+                    gyrow[B] = fmaf(n0, row_bcast<B>(n0), fmaf(n1, row_bcast<B>(n1), fmaf(n2, row_bcast<B>(n2), gyrow[B])));
+                });
+                bc = bn;
+                y0 = z0; y1 = z1; y2 = z2;
+                beg = begn;
+                end = endn;
+            }
+        }
+        if (kact) {
+#pragma unroll
+            for (int b = 0; b < Q; ++b) atomicAdd(&sh.G[kc * Q + b], gyrow[b]);
+        }
+        __threadfence_block();
+        __syncthreads();
+        float *tmp = XA;
+        XA = XB;
+        XB = tmp;
+    }
+    for (int e = t; e < m * Q; e += THREADS) Xg[e] = XA[e];
+    if (t == 0) {
+        st[0] = iters;
+        if (!fixed_iters && iters >= max_iter) st[1] |= VPLMC_SLICE_NOT_CONVERGED;
+        st[2] = __float_as_int((float)err);
+    }
+}
+
 // I^c_i = s0 sum_k X_ik (sum_j Y[j][c][k]), FP64 accumulation; one workgroup per slice.
 __global__ __launch_bounds__(256) void k_reduce(const SliceDesc *__restrict__ desc,
                                                  const int32_t *__restrict__ pt_ids,
@@ -510,15 +950,32 @@ __global__ __launch_bounds__(256) void k_reduce(const SliceDesc *__restrict__ de
 }
 
 template <int Q, int THREADS>
-int launch_adm_q(hipStream_t st, const std::vector<int32_t> &ids, const int32_t *ids_dev,
-                 const SliceDesc *desc, const vplmc_params &prm, const int32_t *row_ptr,
-                 const int32_t *csr_col, const float *csr_val, const int32_t *col_ptr,
-                 const int32_t *csc_row, const float *csc_val, float *X, float *Xn, float *Xp,
-                 float *Lam, float *Y, float *Yp, float *Pi, float *scale, int32_t *stats) {
-    if (ids.empty()) return VPLMC_OK;
-    hipLaunchKernelGGL((k_adm<Q, THREADS>), dim3((unsigned)ids.size()), dim3(THREADS), 0, st, desc,
-                       ids_dev, prm.seed, prm.max_iter, (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0,
-                       prm.tol, prm.alpha0, prm.beta0, prm.gamma, row_ptr, csr_col, csr_val, col_ptr,
+int launch_adm_global(hipStream_t st, size_t count, const int32_t *ids_dev, const SliceDesc *desc,
+                      const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
+                      const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, float *X, float *Xn,
+                      float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale, int32_t *stats) {
+    if (count == 0) return VPLMC_OK;
+    hipLaunchKernelGGL((k_adm<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, desc, ids_dev, prm.seed,
+                       prm.max_iter, (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0,
+                       prm.gamma, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi,
+                       scale, stats);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+template <int Q>
+int launch_adm_lds(hipStream_t st, size_t count, int max_m, const int32_t *ids_dev, const SliceDesc *desc,
+                   const vplmc_params &prm, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
+                   float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale,
+                   int32_t *stats) {
+    if (count == 0) return VPLMC_OK;
+    constexpr int T = adm_lds_threads(Q);
+    const size_t dyn = adm_lds_dynamic_bytes(Q, max_m);
+    auto kern = k_adm_lds<Q, T>;
+    VPLMC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    hipLaunchKernelGGL(kern, dim3((unsigned)count), dim3(T), dyn, st, desc, ids_dev, prm.seed, prm.max_iter,
+                       (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0, prm.gamma, col_ptr,
                        csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
@@ -530,24 +987,29 @@ int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, co
                const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
                const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, float *X, float *Xn,
                float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale, int32_t *stats) {
-    // ids_dev holds the slice ids grouped by rank bucket 4, 8, 16, 32 (in that order)
-    size_t base = 0;
+    // ids_dev holds the slice ids of groups 0..7 in order (2 * rank bucket + variant)
+    size_t base[9] = {0};
+    for (int g = 0; g < 8; ++g) base[g + 1] = base[g] + plan.groups[g].size();
+    const int32_t *id[8];
+    for (int g = 0; g < 8; ++g) id[g] = ids_dev + base[g];
     int rc;
-    const std::vector<int32_t> *b = plan.slices_by_q;
-    rc = launch_adm_q<4, 1024>(st, b[0], ids_dev + base, desc, prm, row_ptr, csr_col, csr_val, col_ptr,
-                               csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
-    if (rc) return rc;
-    base += b[0].size();
-    rc = launch_adm_q<8, 512>(st, b[1], ids_dev + base, desc, prm, row_ptr, csr_col, csr_val, col_ptr,
-                               csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
-    if (rc) return rc;
-    base += b[1].size();
-    rc = launch_adm_q<16, 512>(st, b[2], ids_dev + base, desc, prm, row_ptr, csr_col, csr_val, col_ptr,
-                               csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
-    if (rc) return rc;
-    base += b[2].size();
-    return launch_adm_q<32, 256>(st, b[3], ids_dev + base, desc, prm, row_ptr, csr_col, csr_val, col_ptr,
-                                 csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
+#define VPLMC_ADM_PAIR(B, Q, TG)                                                                                   \
+    if ((rc = launch_adm_lds<Q>(st, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], desc, prm,       \
+                                col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats)))               \
+        return rc;                                                                                                 \
+    if ((rc = launch_adm_global<Q, TG>(st, plan.groups[2 * B + 1].size(), id[2 * B + 1], desc, prm, row_ptr,      \
+                                       csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi,      \
+                                       scale, stats)))                                                             \
+        return rc;
+    VPLMC_ADM_PAIR(0, 4, 1024)
+    VPLMC_ADM_PAIR(1, 8, 512)
+    VPLMC_ADM_PAIR(2, 16, 512)
+    if ((rc = launch_adm_global<32, 256>(st, plan.groups[6].size() + plan.groups[7].size(), id[6], desc, prm, row_ptr,
+                                         csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi,
+                                         scale, stats)))
+        return rc;
+#undef VPLMC_ADM_PAIR
+    return VPLMC_OK;
 }
 
 int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,

@@ -142,7 +142,10 @@ struct vplmc_plan {
     int32_t pass1_ppm = 0, pass2_ppm = 0;
     int64_t sum_m = 0, max_m = 0;
     std::vector<vplmc::SliceDesc> desc;
-    std::vector<int32_t> slices_by_q[4];   // slice ids of rank bucket 4, 8, 16, 32
+    // slice ids by ADM kernel group: 2 * bucket + variant, bucket = rank 4, 8, 16, 32,
+    // variant 0 = X resident in LDS, 1 = X in global memory
+    std::vector<int32_t> groups[8];
+    int32_t group_max_m[8] = {};
     vplmc::Layout layout;
     int64_t tot1 = 0, tot2 = 0, tot_omega = 0, tot_col = 0, tot_row = 0, tot_x = 0, tot_y = 0;
     int64_t tot_bm = 0, tot_bmt = 0;
@@ -151,6 +154,17 @@ struct vplmc_plan {
 };
 
 namespace vplmc {
+// LDS budget of the LDS-resident ADM kernel (gfx950: 160 KiB per workgroup)
+constexpr size_t LDS_BYTES = 160 * 1024;
+constexpr int adm_lds_threads(int q) { return q == 32 ? 0 : 1024; }
+constexpr size_t adm_lds_static_bytes(int q) {
+    return (size_t)(4 * q * q * 8 + 2 * q * q * 4 + 32 * 8) + (size_t)adm_lds_threads(q) * 4 + 1024;
+}
+constexpr size_t adm_lds_dynamic_bytes(int q, int m) { return (size_t)2 * m * q * 4; }
+inline bool adm_fits_lds(int q, int m) {
+    return q <= 16 && adm_lds_static_bytes(q) + adm_lds_dynamic_bytes(q, m) <= LDS_BYTES;
+}
+
 // kernel launchers (kernels_*.hip)
 int launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v);
 int launch_cluster_table(hipStream_t st, const vplmc_lights &v, const vplmc_cut &cut, uint64_t seed,
