@@ -51,11 +51,14 @@ extern "C" {
 
 /* vplmc_params.flags */
 #define VPLMC_FIXED_ITERS 1     /* ignore tol: run exactly max_iter ADM iterations */
+#define VPLMC_LEARNED 2         /* second pass by the learned proposal (vplmc_set_proposal) */
+#define VPLMC_FEATURES 4        /* compute the proposal features even with the plain proposal */
 
 /* per-slice result flags (vplmc_read_stats) -- outcomes, not errors */
 #define VPLMC_SLICE_ALL_ZERO 1      /* every sampled entry is 0: radiance 0      */
 #define VPLMC_SLICE_NOT_CONVERGED 2 /* ADM stopped at max_iter above tol         */
 #define VPLMC_SLICE_SHORTFALL 4     /* second pass hit its attempt cap           */
+#define VPLMC_SLICE_FALLBACK 8      /* learned proposal gave a non-finite logit: plain weights used */
 
 /* Surface points: rows of the lighting matrix (Sec. 3).  Position, unit
  * normal, diffuse albedo; ks / phong_e (normalised Phong specular albedo and
@@ -140,6 +143,8 @@ enum {
     VPLMC_R_X,            /* float[m][q] per slice: final X (initial X when max_iter = 0)  */
     VPLMC_R_Y,            /* float[n][3][q] per slice: final Y (row c n + j of the paper's Y^T) */
     VPLMC_R_SLICE_SCALE,  /* float per slice: s0, the mean sampled value M is divided by   */
+    VPLMC_R_FEATURES,     /* float[12] per (slice, column): proposal features (learned mode) */
+    VPLMC_R_LOGITS,       /* float per (slice, column): proposal log-density (learned mode) */
     VPLMC_R_COUNT
 };
 
@@ -242,6 +247,43 @@ int vplmc_eval_pairs(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lig
 int vplmc_brute_force(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lights *lights,
                       int32_t n_out, const int32_t *point_ids, const vplmc_params *params,
                       double *out);
+
+/* ---- learned second-pass proposal ------------------------------------------
+ * A 12 -> 128 -> 128 -> 1 GELU network predicting the log sampling density
+ * of each (slice, column) from first-pass statistics and geometry; it
+ * replaces g(j) = max C_j - min C_j (Sec. 5) as the column pdf when
+ * params.flags has VPLMC_LEARNED.  Parameters are one FP32 vector of
+ * vplmc_mlp_param_count() values, in the order W1[128][12], b1[128],
+ * W2[128][128], b2[128], W3[128], b3; the kernels use the weights rounded to
+ * bfloat16 and round both hidden activations to bfloat16.
+ * Column weights become max(1, floor(2^24 exp(y_j - max y))) (FP64 from the
+ * FP32 logits); a slice with a non-finite logit keeps the g weights and gets
+ * VPLMC_SLICE_FALLBACK. */
+int vplmc_mlp_param_count(void);
+/* params: DEVICE, owned by the caller, must stay valid while renders use it; NULL removes the model. */
+int vplmc_set_proposal(vplmc_ctx *ctx, const float *params);
+/* y[r] for rows of 12 features (DEVICE float[rows][12] -> float[rows]). */
+int vplmc_mlp_forward(vplmc_ctx *ctx, const float *params, int64_t rows, const float *features, float *y);
+/* DEVICE scratch needed by vplmc_mlp_grad / vplmc_mlp_train_step for `rows` rows. */
+int vplmc_mlp_scratch_size(int64_t rows, size_t *bytes /* HOST */);
+/* grad = d(sum_r dy[r] y[r]) / d params (DEVICE float[param_count]). */
+int vplmc_mlp_grad(vplmc_ctx *ctx, const float *params, int64_t rows, const float *features, const float *dy,
+                   void *scratch, size_t scratch_bytes, float *grad);
+/* One Adam step (lr, 0.9, 0.999, 1e-8, bias-corrected; step counts from 1) on params with moments m, v. */
+int vplmc_mlp_adam(vplmc_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t step, float lr);
+/* Forward, loss sum over groups of KL(pstar || softmax(y)) (groups = rows
+ * [group_offsets[g], group_offsets[g+1]), DEVICE int32), backward and Adam.
+ * loss: DEVICE float, overwritten. */
+int vplmc_mlp_train_step(vplmc_ctx *ctx, float *params, float *m, float *v, int32_t step, float lr, int64_t rows,
+                         const float *features, const float *pstar, int32_t n_groups, const int32_t *group_offsets,
+                         void *scratch, size_t scratch_bytes, float *loss);
+/* Training targets from fully evaluated slices: pstar per (slice, column) in
+ * the plan's column layout, p*_j ~ sigma_j + 0.01 mean(sigma), sigma_j the
+ * standard deviation of R+G+B over the column.  lights: DEVICE float[9][n_clusters]
+ * (vplmc_cluster_table); the workspace is used as scratch. */
+int vplmc_proposal_targets(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points, const float *lights,
+                           const int32_t *pt_ids, const int32_t *cl_ids, const vplmc_params *params, void *workspace,
+                           size_t workspace_bytes, float *pstar);
 
 /* Philox4x64-10 (Salmon et al., SC'11): out[4k .. 4k+3] =
  * Philox(key, ctr[4k .. 4k+3]); ctr/out DEVICE uint64[4 n]. */

@@ -39,10 +39,11 @@ class SliceInfo(ctypes.Structure):
 
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
-FIXED_ITERS = 1
-SLICE_ALL_ZERO, SLICE_NOT_CONVERGED, SLICE_SHORTFALL = 1, 2, 4
+FIXED_ITERS, LEARNED, FEATURES = 1, 2, 4
+SLICE_ALL_ZERO, SLICE_NOT_CONVERGED, SLICE_SHORTFALL, SLICE_FALLBACK = 1, 2, 4, 8
 REGIONS = ["LIGHTS", "REP", "BBOX", "OMEGA1", "VAL1", "OMEGA2", "VAL2", "WEIGHTS", "COLMIN", "COLMAX",
-           "COLCNT", "ROW_PTR", "CSR_COL", "CSR_VAL", "COL_PTR", "CSC_ROW", "CSC_VAL", "X", "Y", "SLICE_SCALE"]
+           "COLCNT", "ROW_PTR", "CSR_COL", "CSR_VAL", "COL_PTR", "CSC_ROW", "CSC_VAL", "X", "Y", "SLICE_SCALE",
+           "FEATURES", "LOGITS"]
 R = {name: k for k, name in enumerate(REGIONS)}
 
 P = ctypes.c_void_p
@@ -71,6 +72,15 @@ SIG = {
     "vplmc_brute_force": (I32, [P, ctypes.POINTER(Points), ctypes.POINTER(Lights), I32, P,
                                 ctypes.POINTER(Params), P]),
     "vplmc_philox4x64": (I32, [P, U64, U64, P, I64, P]),
+    "vplmc_mlp_param_count": (I32, []),
+    "vplmc_set_proposal": (I32, [P, P]),
+    "vplmc_mlp_forward": (I32, [P, P, I64, P, P]),
+    "vplmc_mlp_scratch_size": (I32, [I64, ctypes.POINTER(ctypes.c_size_t)]),
+    "vplmc_mlp_grad": (I32, [P, P, I64, P, P, P, ctypes.c_size_t, P]),
+    "vplmc_mlp_adam": (I32, [P, P, P, P, P, I32, ctypes.c_float]),
+    "vplmc_mlp_train_step": (I32, [P, P, P, P, I32, ctypes.c_float, I64, P, P, I32, P, P, ctypes.c_size_t, P]),
+    "vplmc_proposal_targets": (I32, [P, P, ctypes.POINTER(Points), P, P, P, ctypes.POINTER(Params), P,
+                                     ctypes.c_size_t, P]),
     "vplmc_profile_begin": (I32, [P, I32]),
     "vplmc_profile_end": (I32, [P, P, P]),
 }

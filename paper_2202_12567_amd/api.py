@@ -23,16 +23,17 @@ def version():
     return N.load().vplmc_version()
 
 
-def default_params(**kw):
+def default_params(fixed_iters=None, learned=None, features=None, **kw):
+    """vplmc_default_params with overrides; booleans toggle the flag bits."""
     p = N.Params()
     check(N.load().vplmc_default_params(ctypes.byref(p)))
     for k, v in kw.items():
-        if k == "fixed_iters":
-            p.flags = (p.flags | N.FIXED_ITERS) if v else (p.flags & ~N.FIXED_ITERS)
-            continue
         if not hasattr(p, k):
             raise AttributeError(k)
         setattr(p, k, v)
+    for bit, on in ((N.FIXED_ITERS, fixed_iters), (N.LEARNED, learned), (N.FEATURES, features)):
+        if on is not None:
+            p.flags = (p.flags | bit) if on else (p.flags & ~bit)
     return p
 
 
@@ -220,3 +221,57 @@ def profile_end(ctx):
     fr = np.zeros(1, np.int32)
     check(N.load().vplmc_profile_end(ctx.h, ms.ctypes.data_as(ctypes.c_void_p), fr.ctypes.data_as(ctypes.c_void_p)))
     return dict(zip(N.PHASES, ms.tolist())), int(fr[0])
+
+
+# ---- learned proposal -------------------------------------------------------
+
+def mlp_param_count():
+    return N.load().vplmc_mlp_param_count()
+
+
+def set_proposal(ctx, params):
+    """params: device float32 tensor of mlp_param_count() values, or None."""
+    check(N.load().vplmc_set_proposal(ctx.h, _ptr(params) if params is not None else None))
+    ctx._proposal = params
+
+
+def mlp_forward(ctx, params, features):
+    rows = int(features.shape[0])
+    y = torch.empty(rows, dtype=torch.float32, device=features.device)
+    check(N.load().vplmc_mlp_forward(ctx.h, _ptr(params), rows, _ptr(features), _ptr(y)))
+    return y
+
+
+def mlp_scratch(rows, device):
+    sz = ctypes.c_size_t()
+    check(N.load().vplmc_mlp_scratch_size(int(rows), ctypes.byref(sz)))
+    return torch.empty(int(sz.value), dtype=torch.uint8, device=device)
+
+
+def mlp_grad(ctx, params, features, dy, scratch=None):
+    rows = int(features.shape[0])
+    scratch = mlp_scratch(rows, features.device) if scratch is None else scratch
+    g = torch.empty(mlp_param_count(), dtype=torch.float32, device=features.device)
+    check(N.load().vplmc_mlp_grad(ctx.h, _ptr(params), rows, _ptr(features), _ptr(dy), _ptr(scratch),
+                                  scratch.numel(), _ptr(g)))
+    return g
+
+
+def mlp_adam(ctx, params, grad, m, v, step, lr):
+    check(N.load().vplmc_mlp_adam(ctx.h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr)))
+
+
+def mlp_train_step(ctx, params, m, v, step, lr, features, pstar, group_offsets, scratch, loss):
+    rows = int(features.shape[0])
+    check(N.load().vplmc_mlp_train_step(ctx.h, _ptr(params), _ptr(m), _ptr(v), int(step), float(lr), rows,
+                                        _ptr(features), _ptr(pstar), int(group_offsets.shape[0] - 1),
+                                        _ptr(group_offsets), _ptr(scratch), scratch.numel(), _ptr(loss)))
+
+
+def proposal_targets(ctx, plan, ds, lights, params, ws):
+    """p* per (slice, column) in the plan's column layout (device float32)."""
+    n = int(plan.region("WEIGHTS")[1] // 4)
+    out = torch.empty(n, dtype=torch.float32, device=ws.device)
+    check(N.load().vplmc_proposal_targets(ctx.h, plan.h, ctypes.byref(ds.points_c), _ptr(lights), _ptr(ds.pt_ids),
+                                          _ptr(ds.cl_ids), ctypes.byref(params), _ptr(ws), ws.numel(), _ptr(out)))
+    return out

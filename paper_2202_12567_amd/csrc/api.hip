@@ -56,7 +56,8 @@ int check_params(const vplmc_params *p) {
         return set_error(VPLMC_EINVAL, "gamma must be in (0, 1.618) (got %g)", (double)p->gamma);
     if (!(p->tol >= 0.f)) return set_error(VPLMC_EINVAL, "tol must be >= 0");
     if (!(p->r_min > 0.f) || !(p->ray_eps >= 0.f)) return set_error(VPLMC_EINVAL, "r_min must be > 0, ray_eps >= 0");
-    if (p->flags & ~VPLMC_FIXED_ITERS) return set_error(VPLMC_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(VPLMC_FIXED_ITERS | VPLMC_LEARNED | VPLMC_FEATURES))
+        return set_error(VPLMC_EINVAL, "unknown flags 0x%x", p->flags);
     return VPLMC_OK;
 }
 
@@ -317,6 +318,14 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     bytes[R_YP] = oy * 4;
     bytes[R_PI] = oy * 4;
     bytes[R_SLICE_STATS] = S * 16;
+    bytes[R_COLSUM] = oc * 8;
+    bytes[R_COLSUMSQ] = oc * 8;
+    bytes[R_COLZERO] = oc * 4;
+    bytes[R_SLICE_GEO] = S * 8 * 4;
+    bytes[R_CSC_COL] = oo * 4;
+    bytes[R_RESID] = 3 * oo * 4;
+    bytes[VPLMC_R_FEATURES] = oc * MLP_IN * 4;
+    bytes[VPLMC_R_LOGITS] = oc * 4;
     size_t off = 0;
     for (int r = 0; r < R_INTERNAL_END; ++r) {
         L.off[r] = off;
@@ -409,14 +418,11 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     uint32_t *bm = region<uint32_t>(ws, plan, R_BITMAP);
     uint32_t *bmt = region<uint32_t>(ws, plan, R_BITMAPT);
     int32_t *cnt = region<int32_t>(ws, plan, VPLMC_R_COLCNT);
-    uint32_t *mn = region<uint32_t>(ws, plan, VPLMC_R_COLMIN);
-    uint32_t *mx = region<uint32_t>(ws, plan, VPLMC_R_COLMAX);
+    float *mn = region<float>(ws, plan, VPLMC_R_COLMIN);
+    float *mx = region<float>(ws, plan, VPLMC_R_COLMAX);
     int32_t *stats = region<int32_t>(ws, plan, R_SLICE_STATS);
     if ((rc = launch_fill_u32(st, bm, plan->tot_bm, 0u))) return rc;
     if ((rc = launch_fill_u32(st, bmt, plan->tot_bmt, 0u))) return rc;
-    if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(cnt), plan->tot_col, 0u))) return rc;
-    if ((rc = launch_fill_u32(st, mn, plan->tot_col, 0x7F800000u))) return rc;
-    if ((rc = launch_fill_u32(st, mx, plan->tot_col, 0u))) return rc;
     if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(stats), 4 * (size_t)S, 0u))) return rc;
     if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(radiance), 3 * (size_t)points->m, 0u))) return rc;
 
@@ -436,10 +442,36 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
                                 plan->tot1, 0, stats, *params, val1)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_WEIGHTS))) return rc;
-    if ((rc = launch_colstats(st, *plan, desc, omega1, val1, cnt, mn, mx))) return rc;
+    int32_t *col_ptr = region<int32_t>(ws, plan, VPLMC_R_COL_PTR);
+    int32_t *csc_row = region<int32_t>(ws, plan, VPLMC_R_CSC_ROW);
+    float *csc_val = region<float>(ws, plan, VPLMC_R_CSC_VAL);
+    double *csum = region<double>(ws, plan, R_COLSUM);
+    double *csumsq = region<double>(ws, plan, R_COLSUMSQ);
+    int32_t *czero = region<int32_t>(ws, plan, R_COLZERO);
+    if ((rc = launch_colstats(st, *plan, desc, omega1, val1, bmt, region<uint16_t>(ws, plan, R_WPRET), col_ptr, csc_row,
+                              csc_val, cnt, mn, mx, csum, csumsq, czero)))
+        return rc;
+    const bool learned = (params->flags & VPLMC_LEARNED) != 0;
+    const float *logits = nullptr;
+    if (learned || (params->flags & VPLMC_FEATURES)) {
+        float *feat = region<float>(ws, plan, VPLMC_R_FEATURES);
+        if ((rc = launch_features(st, *plan, desc, *points, pt_ids, cl_ids, lights, region<float>(ws, plan, VPLMC_R_BBOX),
+                                  *cut, cnt, mn, mx, csum, csumsq, czero, region<float>(ws, plan, R_SLICE_GEO), feat)))
+            return rc;
+        if (learned) {
+            float *lg = region<float>(ws, plan, VPLMC_R_LOGITS);
+            if (ctx->mlp) {
+                if ((rc = launch_mlp_forward(st, ctx->mlp, plan->tot_col, feat, lg))) return rc;
+            } else {
+                // no model: every logit non-finite, every slice falls back to the g weights
+                if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(lg), plan->tot_col, 0x7FC00000u))) return rc;
+            }
+            logits = lg;
+        }
+    }
     uint64_t *prefix = region<uint64_t>(ws, plan, R_COLW_PREFIX);
-    if ((rc = launch_weights(st, *plan, desc, cnt, reinterpret_cast<const float *>(mn),
-                             reinterpret_cast<const float *>(mx), region<uint32_t>(ws, plan, VPLMC_R_WEIGHTS), prefix)))
+    if ((rc = launch_weights(st, *plan, desc, cnt, mn, mx, logits, region<uint32_t>(ws, plan, VPLMC_R_WEIGHTS), prefix,
+                             stats)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_PASS2))) return rc;
     if ((rc = launch_pass2(st, *plan, desc, params->seed, prefix, bm, bmt, omega2, stats))) return rc;
@@ -449,19 +481,18 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
         return rc;
     if ((rc = ph.mark(VPLMC_PH_SORT))) return rc;
     int32_t *row_ptr = region<int32_t>(ws, plan, VPLMC_R_ROW_PTR);
-    int32_t *col_ptr = region<int32_t>(ws, plan, VPLMC_R_COL_PTR);
     int32_t *csr_col = region<int32_t>(ws, plan, VPLMC_R_CSR_COL);
     float *csr_val = region<float>(ws, plan, VPLMC_R_CSR_VAL);
-    int32_t *csc_row = region<int32_t>(ws, plan, VPLMC_R_CSC_ROW);
-    float *csc_val = region<float>(ws, plan, VPLMC_R_CSC_VAL);
     if ((rc = launch_sort(st, *plan, desc, bm, bmt, region<uint16_t>(ws, plan, R_WPRE), region<uint16_t>(ws, plan, R_WPRET),
-                          row_ptr, col_ptr, omega1, val1, omega2, val2, stats, csr_col, csr_val, csc_row, csc_val)))
+                          row_ptr, col_ptr, omega1, val1, omega2, val2, stats, csr_col, csr_val, csc_row,
+                          region<int32_t>(ws, plan, R_CSC_COL), csc_val)))
         return rc;
     float *X = region<float>(ws, plan, VPLMC_R_X);
     float *Y = region<float>(ws, plan, VPLMC_R_Y);
     float *scale = region<float>(ws, plan, VPLMC_R_SLICE_SCALE);
     if ((rc = ph.mark(VPLMC_PH_ADM))) return rc;
-    if ((rc = launch_adm(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X,
+    if ((rc = launch_adm(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row,
+                         region<int32_t>(ws, plan, R_CSC_COL), csc_val, region<float>(ws, plan, R_RESID), X,
                          region<float>(ws, plan, R_XNEXT), region<float>(ws, plan, R_XP),
                          region<float>(ws, plan, R_LAMBDA), Y, region<float>(ws, plan, R_YP),
                          region<float>(ws, plan, R_PI), scale, stats)))
@@ -560,6 +591,94 @@ int vplmc_brute_force(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_li
     if (rc) return rc;
     VPLMC_HIP(hipSetDevice(ctx->device));
     return launch_brute_force(ctx->stream, ctx->bvh, *points, *lights, n_out, point_ids, *params, out);
+}
+
+int vplmc_set_proposal(vplmc_ctx *ctx, const float *params) {
+    if (!ctx) return set_error(VPLMC_EINVAL, "ctx is NULL");
+    ctx->mlp = params;
+    return VPLMC_OK;
+}
+
+int vplmc_mlp_param_count(void) { return MLP_PARAMS; }
+
+int vplmc_mlp_scratch_size(int64_t rows, size_t *bytes) {
+    if (rows < 0 || !bytes) return set_error(VPLMC_EINVAL, "rows must be >= 0 and bytes non-NULL");
+    *bytes = (size_t)rows * 4 * (2 + 4 * MLP_HID) + (size_t)MLP_PARAMS * 4 + 256;
+    return VPLMC_OK;
+}
+
+static int mlp_scratch(int64_t rows, void *scratch, size_t scratch_bytes, float **y, float **dy, float **cache,
+                       float **grad) {
+    size_t need = 0;
+    vplmc_mlp_scratch_size(rows, &need);
+    if (!scratch || scratch_bytes < need)
+        return set_error(VPLMC_EINVAL, "scratch of %zu bytes is smaller than the %zu required", scratch_bytes, need);
+    float *p = static_cast<float *>(scratch);
+    *grad = p;
+    p += MLP_PARAMS;
+    *y = p;
+    p += rows;
+    *dy = p;
+    p += rows;
+    *cache = p;
+    return VPLMC_OK;
+}
+
+int vplmc_mlp_forward(vplmc_ctx *ctx, const float *params, int64_t rows, const float *features, float *y) {
+    if (!ctx || !params || rows < 0 || (rows > 0 && (!features || !y))) return set_error(VPLMC_EINVAL, "invalid arguments");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    return launch_mlp_forward(ctx->stream, params, rows, features, y);
+}
+
+int vplmc_mlp_grad(vplmc_ctx *ctx, const float *params, int64_t rows, const float *features, const float *dy_in,
+                   void *scratch, size_t scratch_bytes, float *grad) {
+    if (!ctx || !params || !grad || rows < 0 || (rows > 0 && (!features || !dy_in)))
+        return set_error(VPLMC_EINVAL, "invalid arguments");
+    float *y, *dy, *cache, *g;
+    int rc = mlp_scratch(rows, scratch, scratch_bytes, &y, &dy, &cache, &g);
+    if (rc) return rc;
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    return launch_mlp_grad(ctx->stream, params, rows, features, dy_in, grad, y, cache);
+}
+
+int vplmc_mlp_adam(vplmc_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t step, float lr) {
+    if (!ctx || !params || !grad || !m || !v || step < 1 || !(lr > 0.f)) return set_error(VPLMC_EINVAL, "invalid arguments");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    return launch_mlp_adam(ctx->stream, params, grad, m, v, step, lr);
+}
+
+int vplmc_mlp_train_step(vplmc_ctx *ctx, float *params, float *m, float *v, int32_t step, float lr, int64_t rows,
+                         const float *features, const float *pstar, int32_t n_groups, const int32_t *group_offsets,
+                         void *scratch, size_t scratch_bytes, float *loss) {
+    if (!ctx || !params || !m || !v || step < 1 || !(lr > 0.f) || rows < 0 || n_groups < 0 || !loss ||
+        (rows > 0 && (!features || !pstar || !group_offsets)))
+        return set_error(VPLMC_EINVAL, "invalid arguments");
+    float *y, *dy, *cache, *g;
+    int rc = mlp_scratch(rows, scratch, scratch_bytes, &y, &dy, &cache, &g);
+    if (rc) return rc;
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    return launch_mlp_train_step(ctx->stream, params, m, v, step, lr, rows, features, pstar, n_groups, group_offsets, y,
+                                 dy, g, loss, cache);
+}
+
+int vplmc_proposal_targets(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points, const float *lights,
+                           const int32_t *pt_ids, const int32_t *cl_ids, const vplmc_params *params, void *workspace,
+                           size_t workspace_bytes, float *pstar) {
+    if (!ctx || !plan || !points || !lights || !params || !pstar) return set_error(VPLMC_EINVAL, "NULL argument");
+    if (bad_ptrs_points(points)) return set_error(VPLMC_EINVAL, "incomplete points arrays");
+    if (plan->n_slices > 0 && (!pt_ids || !cl_ids)) return set_error(VPLMC_EINVAL, "pt_ids and cl_ids must be non-NULL");
+    if (!workspace || workspace_bytes < plan->layout.total)
+        return set_error(VPLMC_EINVAL, "workspace smaller than vplmc_workspace_size");
+    int rc = check_params(params);
+    if (rc) return rc;
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    SliceDesc *desc = region<SliceDesc>(workspace, plan, R_DESC);
+    if (plan->n_slices > 0)
+        VPLMC_HIP(hipMemcpyAsync(desc, plan->upload.data(), plan->upload.size(), hipMemcpyHostToDevice, ctx->stream));
+    // the first-pass moment regions serve as FP64 scratch (2 x columns doubles)
+    double *moments = region<double>(workspace, plan, R_COLSUM);
+    return launch_targets(ctx->stream, *plan, desc, ctx->bvh, *points, lights, plan->n_clusters, pt_ids, cl_ids,
+                          *params, moments, pstar);
 }
 
 int vplmc_philox4x64(vplmc_ctx *ctx, uint64_t key0, uint64_t key1, const uint64_t *ctr, int64_t n, uint64_t *out) {

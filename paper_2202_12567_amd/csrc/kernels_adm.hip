@@ -473,23 +473,26 @@ __global__ __launch_bounds__(THREADS) void k_adm(
 // ---------------------------------------------------------------------------
 // LDS-resident variant for ranks 4, 8, 16: both X buffers live in LDS and
 // both phases stream the slice's samples in column-major (CSC) order, so the
-// only gathers are LDS reads.  A wavefront is four groups of 16 lanes (one
-// DPP row each); a group owns one column at a time and lane k of the group
-// owns rank component k, so Y_j, the X+^T R accumulators and a row of the
-// new Gram are three, three and q registers per lane.  Samples are loaded 32
-// at a time, two per lane, and handed to the whole group with DPP row
-// broadcasts; the dot product X_i . Y_j is a four-step DPP row reduction.
-//   phase A: residual with X_k (LDS), R Y^T added into the other LDS buffer
-//     with one LDS float atomic per lane and sample;
-//   X update: t = R Y^T + a U - L staged in LDS, X+ = X (GY Inv) + t Inv in
-//     FP64, written through a global staging buffer;
-//   phase B: residuals from (X_k, Y_k), X+^T R accumulated in lane k, Y+_j
-//     solved in FP64 with the inverse applied across the group by DPP
-//     broadcasts, Y+ Y+^T accumulated per lane and added into the Gram with
-//     LDS atomics.
-// The next round's column metadata, Y row and first sample batch are loaded
-// while the current round is processed.  The atomics make the FP summation
-// order, and hence the last bits of the result, vary between runs.
+// only gathers are LDS reads and reads of Y rows that neighbouring lanes
+// share.
+//   phase A, one lane per sampled entry: X_i (LDS) and Y_j (global, 3q
+//     floats) in registers, the three dots X_i . Y_j^c, the residual r,
+//     which is also stored for phase B, and the q components of
+//     sum_c r_c Y_j^c added into the R Y^T accumulator in the other LDS
+//     buffer with LDS float atomics.  The accumulator's rows are rotated by
+//     their index, (i, k) at i q + (k + i) mod q, so that the lanes of one
+//     atomic instruction (same k, random i) spread over the banks;
+//   X update, one thread per row: t = R Y^T + a U - L un-rotated in place,
+//     X+ = X (GY Inv) + t Inv in FP64, written through a global staging buffer;
+//   phase B, a wavefront is four groups of 16 lanes (one DPP row each); a
+//     group owns one column at a time and lane k owns rank component k.
+//     The stored residuals of the column arrive 16 at a time, one per lane,
+//     and are handed to the group by DPP row broadcasts; X+^T R is
+//     accumulated in lane k, Y+_j solved in FP64 with the inverse applied
+//     across the group by DPP broadcasts, and Y+ Y+^T accumulated per lane
+//     and added into the Gram with LDS atomics.
+// The LDS atomics make the FP summation order, and hence the last bits of
+// the result, vary between runs.
 constexpr int GRP = 16;   // lanes per column group = one DPP row
 constexpr int PBK = 1;    // samples per lane in one batch
 
@@ -528,24 +531,78 @@ struct Batch {
     float m0[PBK], m1[PBK], m2[PBK];
 };
 
-__device__ __forceinline__ void load_batch(const int32_t *__restrict__ csc_row, const float *__restrict__ csc_val,
-                                           int p0, int end, int gl, float inv_s0, Batch &b) {
+__device__ __forceinline__ void load_batch(const int32_t *__restrict__ csc_row, const float *__restrict__ resid,
+                                           int p0, int end, int gl, Batch &b) {
 #pragma unroll
     for (int u = 0; u < PBK; ++u) {
         const int p = p0 + u * GRP + gl;
         const bool ok = p < end;
         const int pc = ok ? p : 0;
         b.i[u] = ok ? csc_row[pc] : 0;
-        b.m0[u] = ok ? csc_val[3 * pc] * inv_s0 : 0.f;
-        b.m1[u] = ok ? csc_val[3 * pc + 1] * inv_s0 : 0.f;
-        b.m2[u] = ok ? csc_val[3 * pc + 2] * inv_s0 : 0.f;
+        b.m0[u] = ok ? resid[3 * pc] : 0.f;
+        b.m1[u] = ok ? resid[3 * pc + 1] : 0.f;
+        b.m2[u] = ok ? resid[3 * pc + 2] : 0.f;
     }
 }
 
-// one batch of phase A: cnt valid samples of the batch (uniform in the group)
+// phase A for sampled entry p = (i, j) with scaled values m0..m2.  The
+// q components of sum_c r_c Y_j^c, times 2^S, are rounded to integers and
+// added into row i of the fixed-point accumulator (row stride q + 1, so the
+// lanes' rows fall in different banks); integer sums do not depend on the
+// order of the additions.
 template <int Q>
-__device__ __forceinline__ void batchA(const Batch &b, int cnt, int kk, const float *XA, float *XB, float y0,
-                                       float y1, float y2, double &e2) {
+__device__ __forceinline__ void entryA(int p, int i, int j, float m0, float m1, float m2, const float *XA,
+                                       int32_t *RXI, const float *__restrict__ Y, float *__restrict__ resid,
+                                       float fxs, double &e2, float &rsmax) {
+    float y[3 * Q], x[Q];
+    const float4 *y4 = reinterpret_cast<const float4 *>(Y + (size_t)j * 3 * Q);
+#pragma unroll
+    for (int v = 0; v < 3 * Q / 4; ++v) {
+        const float4 a = y4[v];
+        y[4 * v] = a.x;
+        y[4 * v + 1] = a.y;
+        y[4 * v + 2] = a.z;
+        y[4 * v + 3] = a.w;
+    }
+    const float4 *x4 = reinterpret_cast<const float4 *>(XA + i * Q);
+#pragma unroll
+    for (int v = 0; v < Q / 4; ++v) {
+        const float4 a = x4[v];
+        x[4 * v] = a.x;
+        x[4 * v + 1] = a.y;
+        x[4 * v + 2] = a.z;
+        x[4 * v + 3] = a.w;
+    }
+    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        d0 = fmaf(x[k], y[k], d0);
+        d1 = fmaf(x[k], y[Q + k], d1);
+        d2 = fmaf(x[k], y[2 * Q + k], d2);
+    }
+    const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
+    e2 += (double)(r0 * r0) + (double)(r1 * r1) + (double)(r2 * r2);
+    rsmax = fmaxf(rsmax, fabsf(r0) + fabsf(r1) + fabsf(r2));
+    resid[3 * p] = r0;
+    resid[3 * p + 1] = r1;
+    resid[3 * p + 2] = r2;
+    const float s0 = r0 * fxs, s1 = r1 * fxs, s2 = r2 * fxs;
+    int32_t *row = RXI + i * (Q + 1);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) atomicAdd(row + k, __float2int_rn(fmaf(s0, y[k], fmaf(s1, y[Q + k], s2 * y[2 * Q + k]))));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// one batch of phase B: cnt valid samples (uniform in the group); the batch
+// holds the stored residuals
+template <int Q>
+__device__ __forceinline__ void batchB(const Batch &b, int cnt, int kk, const float *XB, float &a0, float &a1,
+                                       float &a2) {
     const bool kact = kk < Q;
     const int kc = kact ? kk : 0;
 #pragma unroll
@@ -554,35 +611,8 @@ __device__ __forceinline__ void batchA(const Batch &b, int cnt, int kk, const fl
             constexpr int S = decltype(sc)::value;
             if (u * GRP + S < cnt) {
                 const int i = row_bcast_i<S>(b.i[u]);
-                const float m0 = row_bcast<S>(b.m0[u]), m1 = row_bcast<S>(b.m1[u]), m2 = row_bcast<S>(b.m2[u]);
-                const float x = kact ? XA[i * Q + kc] : 0.f;
-                const float d0 = row_sum16(x * y0), d1 = row_sum16(x * y1), d2 = row_sum16(x * y2);
-                const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
-                if (kk == 0) e2 += (double)(r0 * r0) + (double)(r1 * r1) + (double)(r2 * r2);
-                if (kact) atomicAdd(XB + i * Q + kc, fmaf(r0, y0, fmaf(r1, y1, r2 * y2)));
-            }
-        });
-    }
-}
-
-// one batch of phase B
-template <int Q>
-__device__ __forceinline__ void batchB(const Batch &b, int cnt, int kk, const float *XA, const float *XB, float y0,
-                                       float y1, float y2, float &a0, float &a1, float &a2) {
-    const bool kact = kk < Q;
-    const int kc = kact ? kk : 0;
-#pragma unroll
-    for (int u = 0; u < PBK; ++u) {
-        static_for<0, GRP>([&](auto sc) {
-            constexpr int S = decltype(sc)::value;
-            if (u * GRP + S < cnt) {
-                const int i = row_bcast_i<S>(b.i[u]);
-                const float m0 = row_bcast<S>(b.m0[u]), m1 = row_bcast<S>(b.m1[u]), m2 = row_bcast<S>(b.m2[u]);
-                const float xo = kact ? XA[i * Q + kc] : 0.f;
+                const float r0 = row_bcast<S>(b.m0[u]), r1 = row_bcast<S>(b.m1[u]), r2 = row_bcast<S>(b.m2[u]);
                 const float xn = kact ? XB[i * Q + kc] : 0.f;
-                const float r0 = m0 - row_sum16(xo * y0);
-                const float r1 = m1 - row_sum16(xo * y1);
-                const float r2 = m2 - row_sum16(xo * y2);
                 a0 = fmaf(xn, r0, a0);
                 a1 = fmaf(xn, r1, a1);
                 a2 = fmaf(xn, r2, a2);
@@ -591,18 +621,35 @@ __device__ __forceinline__ void batchB(const Batch &b, int cnt, int kk, const fl
     }
 }
 
+// block-wide maximum of per-thread values; every thread calls it and gets the result
+__device__ __forceinline__ float block_max(float v, float *red) {
+    const int nw = blockDim.x / WAVE, lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    v = wave_max(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    float r = red[0];
+    for (int k = 1; k < nw; ++k) r = fmaxf(r, red[k]);
+    __syncthreads();
+    return r;
+}
+
+// elements per thread of the fixed-point to float pass (m q <= ADM_CVT_MAX * threads)
+constexpr int ADM_CVT_MAX = 18;
+
 template <int Q, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_adm_lds(
     const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, uint64_t seed,
     int32_t max_iter, int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma,
     const int32_t *__restrict__ col_ptr_all, const int32_t *__restrict__ csc_row_all,
-    const float *__restrict__ csc_val_all, float *X_all, float *Xn_all, float *Xp_all, float *Lam_all,
-    float *Y_all, float *Yp_all, float *Pi_all, float *scale_all, int32_t *stats_all) {
+    const int32_t *__restrict__ csc_col_all, const float *__restrict__ csc_val_all, float *resid_all, float *X_all,
+    float *Xn_all, float *Xp_all, float *Lam_all, float *Y_all, float *Yp_all, float *Pi_all, float *scale_all,
+    int32_t *stats_all) {
     static_assert(Q <= GRP, "one lane per rank component");
     constexpr int NW = THREADS / WAVE;
     constexpr int NG = THREADS / GRP;                  // column groups per workgroup
     constexpr int BS = PBK * GRP;                      // samples per group batch
-    extern __shared__ float dyn[];
+    extern __shared__ __align__(16) float dyn[];
     __shared__ AdmShared<Q> sh;
     __shared__ float red2[THREADS];
 
@@ -615,12 +662,18 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
     const int grp = t / GRP;
     const bool kact = gl < Q;
     const int kc = kact ? gl : 0;
+    // two buffers of m (q + 1) words: X_k (row stride q) and the other one,
+    // which holds the fixed-point R Y^T (row stride q + 1) in phase A and X+
+    // (row stride q) from the X update on; they swap every iteration
     float *XA = dyn;
-    float *XB = dyn + (size_t)m * Q;
+    float *XB = dyn + (size_t)m * (Q + 1);
+    __shared__ float redf[NW];
 
     const int32_t *col_ptr = col_ptr_all + d.off_colptr;
     const int32_t *csc_row = csc_row_all + d.off_omega;
+    const int32_t *csc_col = csc_col_all + d.off_omega;
     const float *csc_val = csc_val_all + 3 * d.off_omega;
+    float *resid = resid_all + 3 * d.off_omega;
     float *Xg = X_all + d.off_x;
     float *Xs = Xn_all + d.off_x;     // staging of X+
     float *Xp = Xp_all + d.off_x;
@@ -667,6 +720,7 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
     if (t == 0) scale_all[s] = (float)s0;
 
     const float cq = (float)(2.0 / sqrt((double)Q));
+    float ym0 = 0.f;
     for (int e = t; e < m * Q; e += THREADS) {
         const int i = e / Q, k = e % Q;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
@@ -683,10 +737,47 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
         Y[e] = v;
         Yp[e] = v;
         Pi[e] = 0.f;
+        ym0 = fmaxf(ym0, v);
     }
     __threadfence_block();
     __syncthreads();
     gram_rows<Q>(sh, Y, 3 * n, red2);
+
+    // bounds for the fixed-point scale: K = most samples in one row, the
+    // largest sum_c |M| of a sample, the largest row 1-norm of X_0
+    int32_t *cntr = reinterpret_cast<int32_t *>(XB);
+    for (int e = t; e < m; e += THREADS) cntr[e] = 0;
+    __syncthreads();
+    float msum = 0.f;
+    for (int p = t; p < nnz; p += THREADS) {
+        atomicAdd(cntr + csc_row[p], 1);
+        msum = fmaxf(msum, fabsf(csc_val[3 * p]) + fabsf(csc_val[3 * p + 1]) + fabsf(csc_val[3 * p + 2]));
+    }
+    __syncthreads();
+    float kmx = 0.f, x1 = 0.f;
+    for (int i = t; i < m; i += THREADS) {
+        kmx = fmaxf(kmx, (float)cntr[i]);
+        float a = 0.f;
+        for (int k = 0; k < Q; ++k) a += fabsf(XA[i * Q + k]);
+        x1 = fmaxf(x1, a);
+    }
+    const double Krow = (double)block_max(kmx, redf);
+    const double msum_max = (double)block_max(msum, redf) * (double)inv_s0;
+    const double x1max = (double)block_max(x1, redf);
+    double ymax = (double)block_max(ym0, redf);
+    // a-priori bound on sum_c |r_c| for the first iteration
+    double rs_est = (msum_max + 3.0 * x1max * ymax) * (1.0 + 1e-5);
+    // scale 2^S with K (rs ymax 2^S + 1/2) < 2^31 - 1, taken near 2^30 / (K rs ymax)
+    auto fits = [&](int S, double rs) {
+        return Krow * (rs * ymax * ldexp(1.0, S) + 0.5) < 2147483647.0;
+    };
+    auto pick_scale = [&](double rs) {
+        const double b = Krow * rs * ymax;
+        int S = b > 0.0 ? (int)floor(log2(1073741824.0 / b)) : 60;
+        S = S > 60 ? 60 : (S < -60 ? -60 : S);
+        while (S > -60 && !fits(S, rs)) --S;
+        return S;
+    };
 
     const double alpha = (double)alpha0 * (3.0 * n) / Q;
     const double beta = (double)beta0 * (double)m / Q;
@@ -713,47 +804,92 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
     int iters = max_iter;
     double err = 0.0;
     for (int it = 0; it < max_iter; ++it) {
-        // ---- phase A: R Y^T added into XB, residual norm ----
-        for (int e = t; e < m * Q; e += THREADS) XB[e] = 0.f;
-        __syncthreads();
-        double e2 = 0.0;
-        {
-            int j = grp, beg, end, begn, endn;
-            float y0, y1, y2, z0, z1, z2;
-            Batch bc, bn, bx;
-            col_range(j, beg, end);
-            load_y(j, y0, y1, y2);
-            load_batch(csc_row, csc_val, beg, end, gl, inv_s0, bc);
-            for (; j < n; j += NG) {
-                const int jn = j + NG;
-                col_range(jn, begn, endn);
-                load_y(jn, z0, z1, z2);
-                load_batch(csc_row, csc_val, begn, endn, gl, inv_s0, bn);
-                for (int p0 = beg; p0 < end; p0 += BS) {
-                    const bool more = p0 + BS < end;
-                    if (more) load_batch(csc_row, csc_val, p0 + BS, end, gl, inv_s0, bx);
-                    batchA<Q>(bc, end - p0, gl, XA, XB, y0, y1, y2, e2);
-                    if (more) bc = bx;
-                }
-                bc = bn;
-                y0 = z0; y1 = z1; y2 = z2;
-                beg = begn;
-                end = endn;
-            }
-        }
-        e2 = wave_sum_d(e2);
-        if (lane == 0) sh.red[wave] = e2;
-        __syncthreads();
+        // ---- phase A: residuals, 2^S R Y^T added into XB (fixed point) ----
+        int32_t *RXI = reinterpret_cast<int32_t *>(XB);
+        int S = pick_scale(rs_est);
         double e2t = 0.0;
-        for (int w = 0; w < NW; ++w) e2t += sh.red[w];
+        float rsc = 0.f;
+        for (;;) {
+            const float fxs = ldexpf(1.f, S);
+            for (int e = t; e < m * (Q + 1); e += THREADS) RXI[e] = 0;
+            __syncthreads();
+            double e2 = 0.0;
+            float rsm = 0.f;
+            int p = t;
+            int i = 0, j = 0;
+            float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+            if (p < nnz) {
+                i = csc_row[p];
+                j = csc_col[p];
+                m0 = csc_val[3 * p] * inv_s0;
+                m1 = csc_val[3 * p + 1] * inv_s0;
+                m2 = csc_val[3 * p + 2] * inv_s0;
+            }
+            while (p < nnz) {
+                const int pn = p + THREADS;
+                int in = 0, jn = 0;
+                float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+                if (pn < nnz) {
+                    in = csc_row[pn];
+                    jn = csc_col[pn];
+                    n0 = csc_val[3 * pn] * inv_s0;
+                    n1 = csc_val[3 * pn + 1] * inv_s0;
+                    n2 = csc_val[3 * pn + 2] * inv_s0;
+                }
+                entryA<Q>(p, i, j, m0, m1, m2, XA, RXI, Y, resid, fxs, e2, rsm);
+                p = pn;
+                i = in;
+                j = jn;
+                m0 = n0;
+                m1 = n1;
+                m2 = n2;
+            }
+            e2 = wave_sum_d(e2);
+            rsm = wave_max(rsm);
+            if (lane == 0) {
+                sh.red[wave] = e2;
+                redf[wave] = rsm;
+            }
+            __syncthreads();
+            e2t = 0.0;
+            rsc = 0.f;
+            for (int w = 0; w < NW; ++w) {
+                e2t += sh.red[w];
+                rsc = fmaxf(rsc, redf[w]);
+            }
+            __syncthreads();
+            // every integer sum provably fits, or the residuals are not finite
+            const double rsb = (double)rsc * (1.0 + 1e-5);
+            if (!(rsb < 1e300) || fits(S, rsb) || S <= -60) break;
+            S = pick_scale(rsb);
+        }
+        rs_est = 2.0 * (double)rsc;
         err = sqrt(e2t) / normM;
         if (!fixed_iters && err < (double)tol) {
             iters = it;
             break;
         }
 
-        // ---- X update: t = RX + a U - L (in XB), X+ = X (GY Inv) + t Inv ----
-        for (int e = t; e < m * Q; e += THREADS) XB[e] += alpha_f * Xp[e] - Lam[e];
+        // ---- X update: t = RX + a U - L (in XB, row stride q), X+ = X (GY Inv) + t Inv ----
+        {
+            const float ifx = ldexpf(1.f, -S);
+            float tv[ADM_CVT_MAX];
+#pragma unroll
+            for (int u = 0; u < ADM_CVT_MAX; ++u) {
+                const int e = t + u * THREADS;
+                tv[u] = 0.f;
+                if (e < m * Q) {
+                    const int i = e / Q, k = e % Q;
+                    tv[u] = (float)RXI[i * (Q + 1) + k] * ifx + (alpha_f * Xp[e] - Lam[e]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < ADM_CVT_MAX; ++u) {
+                const int e = t + u * THREADS;
+                if (e < m * Q) XB[e] = tv[u];
+            }
+        }
         spd_inverse<Q>(sh, alpha);           // begins and ends with a barrier
         for (int e = t; e < Q * Q; e += THREADS) {
             const int a = e / Q, b = e % Q;
@@ -821,6 +957,7 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
         __syncthreads();
 
         // ---- phase B ----
+        float ymx = 0.f;
         float gyrow[Q];
 #pragma unroll
         for (int b = 0; b < Q; ++b) gyrow[b] = 0.f;
@@ -830,17 +967,17 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
             Batch bc, bn, bx;
             col_range(j, beg, end);
             load_y(j, y0, y1, y2);
-            load_batch(csc_row, csc_val, beg, end, gl, inv_s0, bc);
+            load_batch(csc_row, resid, beg, end, gl, bc);
             for (; j < n; j += NG) {
                 const int jn = j + NG;
                 col_range(jn, begn, endn);
                 load_y(jn, z0, z1, z2);
-                load_batch(csc_row, csc_val, begn, endn, gl, inv_s0, bn);
+                load_batch(csc_row, resid, begn, endn, gl, bn);
                 float a0 = 0.f, a1 = 0.f, a2 = 0.f;
                 for (int p0 = beg; p0 < end; p0 += BS) {
                     const bool more = p0 + BS < end;
-                    if (more) load_batch(csc_row, csc_val, p0 + BS, end, gl, inv_s0, bx);
-                    batchB<Q>(bc, end - p0, gl, XA, XB, y0, y1, y2, a0, a1, a2);
+                    if (more) load_batch(csc_row, resid, p0 + BS, end, gl, bx);
+                    batchB<Q>(bc, end - p0, gl, XB, a0, a1, a2);
                     if (more) bc = bx;
                 }
                 // Y+ (c, k) = sum_l F[k][l] y(c, l) + Inv[k][l] t(c, l), lane k of the group
@@ -873,6 +1010,7 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
                     yw[kc] = n0;
                     yw[Q + kc] = n1;
                     yw[2 * Q + kc] = n2;
+                    ymx = fmaxf(ymx, fmaxf(fabsf(n0), fmaxf(fabsf(n1), fabsf(n2))));
                 }
                 // row kc of Y+ Y+^T for this column
                 static_for<0, Q>([&](auto bc2) {
@@ -890,7 +1028,7 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
             for (int b = 0; b < Q; ++b) atomicAdd(&sh.G[kc * Q + b], gyrow[b]);
         }
         __threadfence_block();
-        __syncthreads();
+        ymax = (double)block_max(ymx, redf);   // ends with a barrier
         float *tmp = XA;
         XA = XB;
         XB = tmp;
@@ -965,9 +1103,9 @@ int launch_adm_global(hipStream_t st, size_t count, const int32_t *ids_dev, cons
 
 template <int Q>
 int launch_adm_lds(hipStream_t st, size_t count, int max_m, const int32_t *ids_dev, const SliceDesc *desc,
-                   const vplmc_params &prm, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
-                   float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale,
-                   int32_t *stats) {
+                   const vplmc_params &prm, const int32_t *col_ptr, const int32_t *csc_row, const int32_t *csc_col,
+                   const float *csc_val, float *resid, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp,
+                   float *Pi, float *scale, int32_t *stats) {
     if (count == 0) return VPLMC_OK;
     constexpr int T = adm_lds_threads(Q);
     const size_t dyn = adm_lds_dynamic_bytes(Q, max_m);
@@ -976,7 +1114,7 @@ int launch_adm_lds(hipStream_t st, size_t count, int max_m, const int32_t *ids_d
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     hipLaunchKernelGGL(kern, dim3((unsigned)count), dim3(T), dyn, st, desc, ids_dev, prm.seed, prm.max_iter,
                        (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0, prm.gamma, col_ptr,
-                       csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
+                       csc_row, csc_col, csc_val, resid, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
@@ -985,8 +1123,9 @@ int launch_adm_lds(hipStream_t st, size_t count, int max_m, const int32_t *ids_d
 
 int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
                const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
-               const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, float *X, float *Xn,
-               float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale, int32_t *stats) {
+               const int32_t *col_ptr, const int32_t *csc_row, const int32_t *csc_col, const float *csc_val,
+               float *resid, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale,
+               int32_t *stats) {
     // ids_dev holds the slice ids of groups 0..7 in order (2 * rank bucket + variant)
     size_t base[9] = {0};
     for (int g = 0; g < 8; ++g) base[g + 1] = base[g] + plan.groups[g].size();
@@ -995,7 +1134,8 @@ int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, co
     int rc;
 #define VPLMC_ADM_PAIR(B, Q, TG)                                                                                   \
     if ((rc = launch_adm_lds<Q>(st, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], desc, prm,       \
-                                col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats)))               \
+                                col_ptr, csc_row, csc_col, csc_val, resid, X, Xn, Xp, Lam, Y, Yp, Pi, scale,      \
+                                stats)))                                                                           \
         return rc;                                                                                                 \
     if ((rc = launch_adm_global<Q, TG>(st, plan.groups[2 * B + 1].size(), id[2 * B + 1], desc, prm, row_ptr,      \
                                        csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi,      \

@@ -221,9 +221,85 @@ __global__ void k_zero_f64(double *p, size_t n) {
         p[i] = 0.0;
 }
 
+// Training targets of the learned proposal from fully evaluated slices: per
+// (slice, column) the mean and mean square of t = R + G + B over every row
+// (one thread per column, FP64 sums in row order), then per slice
+// p*_j ~ sigma_j + 0.01 mean(sigma).
+__global__ __launch_bounds__(256) void k_target_moments(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
+                                                        int32_t n_lights, const SliceDesc *__restrict__ desc, int S,
+                                                        int64_t total_cols, const int32_t *__restrict__ pt_ids,
+                                                        const int32_t *__restrict__ cl_ids, float r_min2, float eps,
+                                                        double *__restrict__ m1, double *__restrict__ m2) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= total_cols) return;
+    int lo = 0, hi = S;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (desc[mid].off_colptr - mid <= g) lo = mid; else hi = mid;
+    }
+    const int s = lo;
+    const SliceDesc d = desc[s];
+    const int64_t j = g - (d.off_colptr - s);
+    const int c = cl_ids[d.cl_off + j];
+    const size_t N = (size_t)n_lights;
+    const Light L = {{lights[c], lights[N + c], lights[2 * N + c]},
+                     {lights[3 * N + c], lights[4 * N + c], lights[5 * N + c]},
+                     lights[6 * N + c], lights[7 * N + c], lights[8 * N + c]};
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < d.m; ++i) {
+        const PointData q = load_point(pts, pt_ids[d.pt_off + i]);
+        float o0, o1, o2;
+        shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+        const double tv = (double)((o0 + o1) + o2);
+        s1 += tv;
+        s2 += tv * tv;
+    }
+    m1[d.off_col + j] = s1 / d.m;
+    m2[d.off_col + j] = s2 / d.m;
+}
+
+__global__ __launch_bounds__(256) void k_target_norm(const SliceDesc *__restrict__ desc, const double *__restrict__ m1,
+                                                     const double *__restrict__ m2, float *__restrict__ pstar) {
+    __shared__ double red[256];
+    const int s = blockIdx.x, t = threadIdx.x;
+    const SliceDesc d = desc[s];
+    double a = 0.0;
+    for (int j = t; j < d.n; j += 256) {
+        const int64_t o = d.off_col + j;
+        a += sqrt(fmax(0.0, m2[o] - m1[o] * m1[o]));
+    }
+    red[t] = a;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    const double mean = red[0] / d.n;
+    const double add = 0.01 * (mean > 0.0 ? mean : 1.0);
+    const double total = red[0] + add * d.n;
+    for (int j = t; j < d.n; j += 256) {
+        const int64_t o = d.off_col + j;
+        pstar[o] = (float)((sqrt(fmax(0.0, m2[o] - m1[o] * m1[o])) + add) / total);
+    }
+}
+
 unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 }  // namespace
+
+int launch_targets(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const Bvh &bvh,
+                   const vplmc_points &pts, const float *lights, int32_t n_lights, const int32_t *pt_ids,
+                   const int32_t *cl_ids, const vplmc_params &prm, double *moments, float *pstar) {
+    if (plan.n_slices <= 0) return VPLMC_OK;
+    const int64_t cols = plan.tot_col;
+    hipLaunchKernelGGL(k_target_moments, dim3(blocks_for(cols, 256)), dim3(256), 0, st, bvh, pts, lights, n_lights,
+                       desc, plan.n_slices, cols, pt_ids, cl_ids, prm.r_min * prm.r_min, prm.ray_eps, moments,
+                       moments + cols);
+    VPLMC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_target_norm, dim3(plan.n_slices), dim3(256), 0, st, desc, moments, moments + cols, pstar);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
 
 int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
                       int32_t n_lights, const SliceDesc *desc, int32_t n_slices, const int32_t *pt_ids,

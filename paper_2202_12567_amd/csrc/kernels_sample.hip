@@ -183,44 +183,80 @@ __global__ void k_pass1(const SliceDesc *__restrict__ desc, int S, int64_t total
     atomicOr(bmt + d.off_bmt + (int64_t)j * d.words_col + (i >> 5), 1u << (i & 31));
 }
 
-// Per-(slice, column) count, min and max of t = R + G + B over the first pass.
-__global__ void k_colstats(const SliceDesc *__restrict__ desc, int S, int64_t total,
-                           const uint32_t *__restrict__ omega1, const float *__restrict__ val1,
-                           int32_t *cnt, uint32_t *mn, uint32_t *mx) {
+// Per-(slice, column) statistics of t = R + G + B over the first pass, one
+// thread per column walking the column's first-pass entries in row order
+// (a CSC ordering of the first pass alone), so every sum has a fixed order.
+__global__ void k_colstats(const SliceDesc *__restrict__ desc, int S, int64_t total_cols,
+                           const int32_t *__restrict__ col_ptr, const float *__restrict__ csc_val,
+                           int32_t *cnt, float *mn, float *mx, double *sum, double *sumsq, int32_t *zeros) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const int s = slice_of(desc, S, g, 0);
+    if (g >= total_cols) return;
+    const int s = slice_of(desc, S, g, 3);
     const SliceDesc d = desc[s];
-    const uint32_t j = omega1[g] & 0xFFFFu;
-    const float tv = (val1[3 * g] + val1[3 * g + 1]) + val1[3 * g + 2];   // >= 0: bit order = value order
+    const int64_t j = g - (d.off_colptr - s);
+    const int b = col_ptr[d.off_colptr + j], e = col_ptr[d.off_colptr + j + 1];
+    float lo = INFINITY, hi = 0.f;
+    double s1 = 0.0, s2 = 0.0;
+    int z = 0;
+    for (int p = b; p < e; ++p) {
+        const float *v = csc_val + 3 * (d.off_omega + p);
+        const float tv = (v[0] + v[1]) + v[2];
+        lo = fminf(lo, tv);
+        hi = fmaxf(hi, tv);
+        s1 += (double)tv;
+        s2 += (double)tv * (double)tv;
+        z += tv == 0.f;
+    }
     const int64_t o = d.off_col + j;
-    atomicAdd(cnt + o, 1);
-    atomicMin(mn + o, __float_as_uint(tv));
-    atomicMax(mx + o, __float_as_uint(tv));
+    cnt[o] = e - b;
+    mn[o] = e > b ? lo : 0.f;
+    mx[o] = e > b ? hi : 0.f;
+    sum[o] = s1;
+    sumsq[o] = s2;
+    zeros[o] = z;
 }
 
 // g(j) = max - min (Sec. 5, f(i) = 1) quantised to w_j = max(1, floor(2^24 g / max g))
 // (0 where g = 0; all 1 if every g is 0) and its inclusive uint64 prefix.
+// With logits (the learned proposal), w_j = max(1, floor(2^24 exp(y_j - max y)))
+// in FP64 from the FP32 logits instead; a slice with any non-finite logit
+// keeps the g weights and is flagged.
 __global__ __launch_bounds__(256) void k_weights(const SliceDesc *__restrict__ desc, const int32_t *cnt,
-                                                 const float *mn, const float *mx, uint32_t *w,
-                                                 uint64_t *prefix) {
+                                                 const float *mn, const float *mx, const float *logits,
+                                                 uint32_t *w, uint64_t *prefix, int32_t *stats) {
     __shared__ uint32_t sm[8];
     __shared__ float smax[4];
+    __shared__ int bad_s;
     __shared__ uint64_t carry_s;
     const int s = blockIdx.x;
     const SliceDesc d = desc[s];
     const int t = threadIdx.x, lane = t % WAVE, wv = t / WAVE;
-    float gmax = 0.f;
+    if (t == 0) bad_s = 0;
+    __syncthreads();
+    float gmax = 0.f, ymax = -INFINITY;
     for (int j = t; j < d.n; j += 256) {
         const int64_t o = d.off_col + j;
         const float gj = cnt[o] > 0 ? mx[o] - mn[o] : 0.f;
         gmax = fmaxf(gmax, gj);
+        if (logits) {
+            const float y = logits[o];
+            if (!isfinite(y)) bad_s = 1;
+            ymax = fmaxf(ymax, y);
+        }
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o, WAVE));
     if (lane == 0) smax[wv] = gmax;
     __syncthreads();
     gmax = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
+    __syncthreads();
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) ymax = fmaxf(ymax, __shfl_xor(ymax, o, WAVE));
+    if (lane == 0) smax[wv] = ymax;
+    __syncthreads();
+    ymax = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
+    const bool learned = logits != nullptr && !bad_s;
+    if (logits && bad_s && t == 0) stats[4 * s + 1] |= VPLMC_SLICE_FALLBACK;
     const bool uniform = !(gmax > 0.f);
     if (t == 0) carry_s = 0;
     __syncthreads();
@@ -228,10 +264,13 @@ __global__ __launch_bounds__(256) void k_weights(const SliceDesc *__restrict__ d
         const int j = j0 + t;
         uint32_t wj = 0;
         if (j < d.n) {
-            if (uniform) {
+            const int64_t o = d.off_col + j;
+            if (learned) {
+                const double f = floor(16777216.0 * exp((double)logits[o] - (double)ymax));
+                wj = f > 1.0 ? (uint32_t)f : 1u;
+            } else if (uniform) {
                 wj = 1;
             } else {
-                const int64_t o = d.off_col + j;
                 const float gj = cnt[o] > 0 ? mx[o] - mn[o] : 0.f;
                 if (gj > 0.f) {
                     const double f = floor((16777216.0 * (double)gj) / (double)gmax);
@@ -433,7 +472,7 @@ __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t tot
                           const uint32_t *__restrict__ bmt, const uint16_t *__restrict__ wpre,
                           const uint16_t *__restrict__ wpret, const int32_t *__restrict__ row_ptr,
                           const int32_t *__restrict__ col_ptr, int32_t *csr_col, float *csr_val,
-                          int32_t *csc_row, float *csc_val) {
+                          int32_t *csc_row, int32_t *csc_col, float *csc_val) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= total) return;
     const int s = slice_of(desc, S, g, which);
@@ -443,16 +482,19 @@ __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t tot
     const uint32_t key = keys[g];
     const uint32_t i = key >> 16, j = key & 0xFFFFu;
     const int64_t wr = d.off_bm + (int64_t)i * d.words_row + (j >> 5);
-    const int64_t pr = row_ptr[d.off_row + i] + wpre[wr] + __popc(bm[wr] & ((1u << (j & 31)) - 1u));
+    const int64_t pr = csr_col ? row_ptr[d.off_row + i] + wpre[wr] + __popc(bm[wr] & ((1u << (j & 31)) - 1u)) : 0;
     const int64_t wc = d.off_bmt + (int64_t)j * d.words_col + (i >> 5);
     const int64_t pc = col_ptr[d.off_colptr + j] + wpret[wc] + __popc(bmt[wc] & ((1u << (i & 31)) - 1u));
     const float v0 = vals[3 * g], v1 = vals[3 * g + 1], v2 = vals[3 * g + 2];
     const int64_t o = d.off_omega;
-    csr_col[o + pr] = (int32_t)j;
-    csr_val[3 * (o + pr)] = v0;
-    csr_val[3 * (o + pr) + 1] = v1;
-    csr_val[3 * (o + pr) + 2] = v2;
+    if (csr_col) {
+        csr_col[o + pr] = (int32_t)j;
+        csr_val[3 * (o + pr)] = v0;
+        csr_val[3 * (o + pr) + 1] = v1;
+        csr_val[3 * (o + pr) + 2] = v2;
+    }
     csc_row[o + pc] = (int32_t)i;
+    if (csc_col) csc_col[o + pc] = (int32_t)j;
     csc_val[3 * (o + pc)] = v0;
     csc_val[3 * (o + pc) + 1] = v1;
     csc_val[3 * (o + pc) + 2] = v2;
@@ -497,18 +539,35 @@ int launch_pass1(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, 
 }
 
 int launch_colstats(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *omega1,
-                    const float *val1, int32_t *cnt, uint32_t *mn, uint32_t *mx) {
-    if (plan.tot1 <= 0) return VPLMC_OK;
-    hipLaunchKernelGGL(k_colstats, dim3(blocks_for(plan.tot1, 256)), dim3(256), 0, st, desc, plan.n_slices,
-                       plan.tot1, omega1, val1, cnt, mn, mx);
+                    const float *val1, const uint32_t *bmt, uint16_t *wpret, int32_t *col_ptr, int32_t *csc_row,
+                    float *csc_val, int32_t *cnt, float *mn, float *mx, double *sum, double *sumsq, int32_t *zeros) {
+    if (plan.n_slices <= 0) return VPLMC_OK;
+    const int S = plan.n_slices;
+    const int64_t cols = plan.tot_col;
+    // CSC ordering of the first pass alone (the column-major bitmap holds only it now)
+    hipLaunchKernelGGL(k_rowscan, dim3(blocks_for(cols * WAVE, 256)), dim3(256), 0, st, desc, S, cols, 1, bmt, wpret,
+                       col_ptr);
+    VPLMC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ptrscan, dim3(S), dim3(256), 0, st, desc, 1, col_ptr);
+    VPLMC_HIP(hipGetLastError());
+    if (plan.tot1 > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(plan.tot1, 256)), dim3(256), 0, st, desc, S, plan.tot1, 0,
+                           (const int32_t *)nullptr, omega1, val1, (const uint32_t *)nullptr, bmt,
+                           (const uint16_t *)nullptr, wpret, (const int32_t *)nullptr, col_ptr, (int32_t *)nullptr,
+                           (float *)nullptr, csc_row, (int32_t *)nullptr, csc_val);
+        VPLMC_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_colstats, dim3(blocks_for(cols, 256)), dim3(256), 0, st, desc, S, cols, col_ptr, csc_val,
+                       cnt, mn, mx, sum, sumsq, zeros);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
 
 int launch_weights(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *cnt,
-                   const float *mn, const float *mx, uint32_t *w, uint64_t *prefix) {
+                   const float *mn, const float *mx, const float *logits, uint32_t *w, uint64_t *prefix,
+                   int32_t *stats) {
     if (plan.n_slices <= 0) return VPLMC_OK;
-    hipLaunchKernelGGL(k_weights, dim3(plan.n_slices), dim3(256), 0, st, desc, cnt, mn, mx, w, prefix);
+    hipLaunchKernelGGL(k_weights, dim3(plan.n_slices), dim3(256), 0, st, desc, cnt, mn, mx, logits, w, prefix, stats);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
@@ -525,7 +584,8 @@ int launch_pass2(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, 
 int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *bm,
                 const uint32_t *bmt, uint16_t *wpre, uint16_t *wpret, int32_t *row_ptr, int32_t *col_ptr,
                 const uint32_t *omega1, const float *val1, const uint32_t *omega2, const float *val2,
-                const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, float *csc_val) {
+                const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, int32_t *csc_col,
+                float *csc_val) {
     if (plan.n_slices <= 0) return VPLMC_OK;
     const int S = plan.n_slices;
     const int64_t rows = plan.tot_row - S;     // sum of m
@@ -543,13 +603,13 @@ int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, c
     if (plan.tot1 > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(plan.tot1, 256)), dim3(256), 0, st, desc, S, plan.tot1, 0,
                            stats, omega1, val1, bm, bmt, wpre, wpret, row_ptr, col_ptr, csr_col, csr_val, csc_row,
-                           csc_val);
+                           csc_col, csc_val);
         VPLMC_HIP(hipGetLastError());
     }
     if (plan.tot2 > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(plan.tot2, 256)), dim3(256), 0, st, desc, S, plan.tot2, 1,
                            stats, omega2, val2, bm, bmt, wpre, wpret, row_ptr, col_ptr, csr_col, csr_val, csc_row,
-                           csc_val);
+                           csc_col, csc_val);
         VPLMC_HIP(hipGetLastError());
     }
     return VPLMC_OK;

@@ -99,8 +99,8 @@ struct SliceDesc {
 
 // Regions of the workspace: byte offsets.
 struct Layout {
-    size_t off[VPLMC_R_COUNT + 16];
-    size_t bytes[VPLMC_R_COUNT + 16];
+    size_t off[VPLMC_R_COUNT + 24];
+    size_t bytes[VPLMC_R_COUNT + 24];
     size_t total;
 };
 
@@ -118,6 +118,12 @@ enum {
     R_YP,            // float[n][3][q]
     R_PI,            // float[n][3][q]
     R_SLICE_STATS,   // int32 iters, int32 flags, float resid, int32 n2 per slice
+    R_COLSUM,        // double per (slice, column): sum of t over the first pass
+    R_COLSUMSQ,      // double per (slice, column): sum of t^2
+    R_COLZERO,       // int32 per (slice, column): observations with t = 0
+    R_SLICE_GEO,     // float[8] per slice: centroid xyz, bbox diagonal, mean normal xyz, -
+    R_CSC_COL,       // int32 per sampled entry, CSC order: its column
+    R_RESID,         // float[3] per sampled entry, CSC order: residual of the current iterate
     R_INTERNAL_END
 };
 
@@ -129,6 +135,7 @@ struct vplmc_ctx {
     vplmc::Bvh bvh;
     void *bvh_mem = nullptr;   // owned device allocation holding nodes + spheres
     int n_cu = 256;
+    const float *mlp = nullptr;   // learned-proposal parameters (device), or none
     // phase timing: events[frame][phase boundary]
     std::vector<hipEvent_t> prof_events;
     int prof_max_frames = 0;
@@ -160,9 +167,11 @@ constexpr int adm_lds_threads(int q) { return q == 32 ? 0 : 1024; }
 constexpr size_t adm_lds_static_bytes(int q) {
     return (size_t)(4 * q * q * 8 + 2 * q * q * 4 + 32 * 8) + (size_t)adm_lds_threads(q) * 4 + 1024;
 }
-constexpr size_t adm_lds_dynamic_bytes(int q, int m) { return (size_t)2 * m * q * 4; }
+// two LDS buffers of m (q + 1) words (X_k and R Y^T / X+)
+constexpr size_t adm_lds_dynamic_bytes(int q, int m) { return (size_t)2 * m * (q + 1) * 4; }
 inline bool adm_fits_lds(int q, int m) {
-    return q <= 16 && adm_lds_static_bytes(q) + adm_lds_dynamic_bytes(q, m) <= LDS_BYTES;
+    return q <= 16 && (int64_t)m * q <= 18 * 1024 &&
+           adm_lds_static_bytes(q) + adm_lds_dynamic_bytes(q, m) <= LDS_BYTES;
 }
 
 // kernel launchers (kernels_*.hip)
@@ -178,19 +187,40 @@ int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, c
                       const int32_t *cl_ids, const uint32_t *keys, int64_t n_keys, int which_pass,
                       const int32_t *stats, const vplmc_params &prm, float *vals);
 int launch_colstats(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *omega1,
-                    const float *val1, int32_t *cnt, uint32_t *mn, uint32_t *mx);
+                    const float *val1, const uint32_t *bmt, uint16_t *wpret, int32_t *col_ptr, int32_t *csc_row,
+                    float *csc_val, int32_t *cnt, float *mn, float *mx, double *sum, double *sumsq, int32_t *zeros);
 int launch_weights(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *cnt,
-                   const float *mn, const float *mx, uint32_t *w, uint64_t *prefix);
+                   const float *mn, const float *mx, const float *logits, uint32_t *w, uint64_t *prefix,
+                   int32_t *stats);
+// learned proposal (kernels_mlp.hip)
+constexpr int MLP_IN = 12, MLP_HID = 128;
+constexpr int MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_HID + 1;
+int launch_features(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const vplmc_points &pts,
+                    const int32_t *pt_ids, const int32_t *cl_ids, const float *lights, const float *bbox,
+                    const vplmc_cut &cut, const int32_t *cnt, const float *mn, const float *mx, const double *sum,
+                    const double *sumsq, const int32_t *zeros, float *slice_geo, float *features);
+int launch_mlp_forward(hipStream_t st, const float *params, int64_t rows, const float *features, float *y);
+int launch_mlp_train_step(hipStream_t st, float *params, float *m, float *v, int32_t step, float lr, int64_t rows,
+                          const float *features, const float *pstar, int32_t n_groups, const int32_t *group_off,
+                          float *y, float *dy, float *grad, float *loss, float *cache);
+int launch_mlp_grad(hipStream_t st, const float *params, int64_t rows, const float *features, const float *dy,
+                    float *grad, float *y, float *cache);
+int launch_mlp_adam(hipStream_t st, float *params, const float *grad, float *m, float *v, int32_t step, float lr);
+int launch_targets(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const Bvh &bvh,
+                   const vplmc_points &pts, const float *lights, int32_t n_lights, const int32_t *pt_ids,
+                   const int32_t *cl_ids, const vplmc_params &prm, double *moments, float *pstar);
 int launch_pass2(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, uint64_t seed,
                  const uint64_t *prefix, uint32_t *bm, uint32_t *bmt, uint32_t *omega2, int32_t *stats);
 int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *bm,
                 const uint32_t *bmt, uint16_t *wpre, uint16_t *wpret, int32_t *row_ptr, int32_t *col_ptr,
                 const uint32_t *omega1, const float *val1, const uint32_t *omega2, const float *val2,
-                const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, float *csc_val);
+                const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, int32_t *csc_col,
+                float *csc_val);
 int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
                const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
-               const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, float *X, float *Xn,
-               float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale, int32_t *stats);
+               const int32_t *col_ptr, const int32_t *csc_row, const int32_t *csc_col, const float *csc_val,
+               float *resid, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale,
+               int32_t *stats);
 int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,
                   const float *X, const float *Y, const float *scale, float *radiance);
 int launch_eval_pairs(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,

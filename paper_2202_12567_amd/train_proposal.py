@@ -1,0 +1,151 @@
+"""Train the learned second-pass proposal on the GPU with the library's own
+kernels, on lighting matrices the method itself evaluates.
+
+    python -m paper_2202_12567_amd.train_proposal --out proposal_mlp.npy
+
+For every training scene (seeded, "learned" workload shape: 64x64 points,
+1,024 VPL clusters, 16 slices of 256) one frame is run with the plain
+proposal and VPLMC_FEATURES to obtain the first-pass features, and
+vplmc_proposal_targets evaluates every entry of every slice to form the
+target density p*_j ~ sigma_j + 0.01 mean(sigma).  Training minimises the
+summed per-slice KL(p* || softmax(y)) with vplmc_mlp_train_step (forward,
+softmax-KL, backward, Adam).  Held-out evaluation compares, at the same
+sample budget, the frame's pixel RMSE against the brute-force sum with the
+plain and the learned proposal.
+"""
+import argparse
+import time
+
+import numpy as np
+import torch
+
+from . import api
+
+TRAIN_SEEDS = range(1000, 1200)
+VALID_SEEDS = range(1200, 1220)
+TEST_SEEDS = range(2000, 2020)
+
+
+def frame_data(ctx, scene, params_plain, device):
+    """(features [rows, 12], p* [rows], group offsets [S + 1]) of one scene."""
+    ds = api.DeviceScene(scene, device)
+    ctx.set_occluders(scene.spheres)
+    plan = api.Plan(scene, params_plain)
+    ws = api.workspace(plan, device)
+    api.render(ctx, plan, ds, params_plain, ws)
+    feats = api.region_view(plan, ws, "FEATURES", torch.float32).view(-1, 12).clone()
+    lights = api.region_view(plan, ws, "LIGHTS", torch.float32).view(9, -1).clone()
+    pstar = api.proposal_targets(ctx, plan, ds, lights, params_plain, ws)
+    offs = [0]
+    for s in range(scene.n_slices):
+        offs.append(offs[-1] + plan.slice_info(s)["n"])
+    return feats, pstar.clone(), np.asarray(offs, np.int32)
+
+
+def build_dataset(ctx, seeds, cfg="learned", ppm=50000, device="cuda"):
+    from scenegen import make_scene
+    prm = api.default_params(pass1_ppm=ppm, pass2_ppm=ppm, max_iter=0, fixed_iters=True, features=True)
+    F, Pst, offs = [], [], [0]
+    for seed in seeds:
+        sc = make_scene(cfg, seed)
+        prm.seed = seed
+        f, p, o = frame_data(ctx, sc, prm, device)
+        F.append(f)
+        Pst.append(p)
+        offs.extend((o[1:] + offs[-1]).tolist())
+    return torch.cat(F), torch.cat(Pst), torch.as_tensor(np.asarray(offs, np.int32), device=device)
+
+
+def kl_per_group(y, pstar, offs):
+    """Summed KL(p* || softmax(y)) over groups (host, FP64)."""
+    y = y.double().cpu().numpy()
+    p = pstar.double().cpu().numpy()
+    o = offs.cpu().numpy()
+    tot = 0.0
+    for g in range(o.shape[0] - 1):
+        ys, ps = y[o[g]:o[g + 1]], p[o[g]:o[g + 1]]
+        lq = ys - (ys.max() + np.log(np.exp(ys - ys.max()).sum()))
+        nz = ps > 0
+        tot += float(np.sum(ps[nz] * (np.log(ps[nz]) - lq[nz])))
+    return tot / (o.shape[0] - 1)
+
+
+def init_params(seed, device):
+    """He-style initial weights, flattened in the library's order (W1 b1 W2 b2 W3 b3)."""
+    rng = np.random.default_rng(seed)
+    h, k = 128, 12
+    parts = [rng.normal(0, np.sqrt(2.0 / k), h * k), np.zeros(h), rng.normal(0, np.sqrt(2.0 / h), h * h),
+             np.zeros(h), rng.normal(0, np.sqrt(1.0 / h), h), np.zeros(1)]
+    v = np.concatenate(parts).astype(np.float32)
+    assert v.shape[0] == api.mlp_param_count()
+    return torch.as_tensor(v, device=device).contiguous()
+
+
+def train(ctx, F, P, offs, steps=300, batch_groups=128, lr=1e-3, seed=0, log=print):
+    dev = F.device
+    params = init_params(seed, dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    loss = torch.zeros(1, device=dev)
+    G = offs.shape[0] - 1
+    o = offs.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    rows_max = int(np.max(np.diff(o))) * batch_groups
+    scratch = api.mlp_scratch(rows_max, dev)
+    hist = []
+    for step in range(1, steps + 1):
+        g0 = int(rng.integers(0, max(1, G - batch_groups + 1)))
+        g1 = min(G, g0 + batch_groups)
+        a, b = int(o[g0]), int(o[g1])
+        goff = torch.as_tensor(o[g0:g1 + 1] - a, device=dev, dtype=torch.int32)
+        api.mlp_train_step(ctx, params, m, v, step, lr, F[a:b], P[a:b], goff, scratch, loss)
+        if step % 25 == 0 or step == 1:
+            l = float(loss.item()) / (g1 - g0)
+            hist.append((step, l))
+            log(f"step {step}: KL per slice {l:.4f}")
+    return params, hist
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default="proposal_mlp.npy")
+    ap.add_argument("--steps", type=int, default=600)
+    ap.add_argument("--train-scenes", type=int, default=200)
+    args = ap.parse_args()
+    dev = torch.device("cuda", 0)
+    ctx = api.Context(0)
+    t0 = time.time()
+    F, P, offs = build_dataset(ctx, list(TRAIN_SEEDS)[: args.train_scenes])
+    Fv, Pv, offv = build_dataset(ctx, VALID_SEEDS)
+    print(f"dataset: {F.shape[0]} rows ({offs.shape[0] - 1} slices), {time.time() - t0:.1f} s", flush=True)
+    params, hist = train(ctx, F, P, offs, steps=args.steps)
+    yv = api.mlp_forward(ctx, params, Fv)
+    print(f"validation KL per slice: {kl_per_group(yv, Pv, offv):.4f}", flush=True)
+    np.save(args.out, params.cpu().numpy())
+    print(f"saved {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()
+
+
+def rmse_gain(ctx, params, seeds, cfg="learned", ppm=50000, device="cuda"):
+    """Mean relative pixel RMSE against the brute-force VPL sum, plain vs
+    learned proposal, same seeds and sample budget (ADM to its tolerance)."""
+    from scenegen import make_scene
+    dev = torch.device(device)
+    api.set_proposal(ctx, params)
+    out = {"plain": [], "learned": []}
+    for seed in seeds:
+        sc = make_scene(cfg, seed)
+        ctx.set_occluders(sc.spheres)
+        ds = api.DeviceScene(sc, dev)
+        ref = api.brute_force(ctx, ds, ds.vpl, api.default_params(seed=seed)).double()
+        for name, learned in (("plain", False), ("learned", True)):
+            prm = api.default_params(seed=seed, pass1_ppm=ppm, pass2_ppm=ppm, learned=learned)
+            plan = api.Plan(sc, prm)
+            ws = api.workspace(plan, dev)
+            rad = api.render(ctx, plan, ds, prm, ws).double()
+            out[name].append(float(torch.linalg.norm(rad - ref) / torch.linalg.norm(ref)))
+    api.set_proposal(ctx, None)
+    return {k: float(np.mean(v)) for k, v in out.items()}

@@ -81,9 +81,9 @@ CONFIGS = {
     # log-uniform [256, 2048], ranks in {4, 8, 16, 32}; 5% sampling.
     "batch": SceneConfig("batch", 1920, 1080, 16.0 / 9.0, 2048, 300000, 2048, 1.0, 0, "batch",
                          batch_slices=1024, pass1_ppm=25000, pass2_ppm=25000),
-    # 16 slices of 256 points per scene, like "tiny" but with a mix of
-    # materials; the learned-proposal training and held-out scenes.
-    "learned": SceneConfig("learned", 64, 64, 1.0, 32, 1024, 1024, 0.0, 8, "equal",
+    # 16 slices of 256 points per scene, like "tiny" but half of the objects
+    # Phong; the learned-proposal training, validation and held-out scenes.
+    "learned": SceneConfig("learned", 64, 64, 1.0, 32, 1024, 1024, 0.5, 8, "equal",
                            n_slices=16, pass1_ppm=50000, pass2_ppm=50000),
     # 1920x1080, 2,048 spheres, 300,000 VPLs cut to 16,384 clusters, uneven
     # slices of at most 1,024 points, all Phong, rank 32 (16 below 512 rows).

@@ -14,6 +14,7 @@ REGION_DTYPES = {
     "COLMIN": torch.float32, "COLMAX": torch.float32, "COLCNT": torch.int32, "ROW_PTR": torch.int32,
     "CSR_COL": torch.int32, "CSR_VAL": torch.float32, "COL_PTR": torch.int32, "CSC_ROW": torch.int32,
     "CSC_VAL": torch.float32, "X": torch.float32, "Y": torch.float32, "SLICE_SCALE": torch.float32,
+    "FEATURES": torch.float32, "LOGITS": torch.float32,
 }
 
 

@@ -1,0 +1,195 @@
+"""The learned second-pass proposal on the GPU against the FP64 oracle:
+features, MLP forward (BF16 MFMA) and gradients (FP32 training kernels), one
+Adam step, bit-exact learned weights and second pass given the GPU logits,
+the fallback without a model, training that lowers the loss, and what a
+trained network gains over the plain g(j) proposal on held-out scenes."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from _gpu_common import keys_to_ij, log, run_frame  # noqa: E402
+from oracle import mlp as omlp  # noqa: E402
+from oracle import render as orender  # noqa: E402
+from oracle.sampling import column_stats, pass2  # noqa: E402
+from paper_2202_12567_amd import api, train_proposal  # noqa: E402
+from scenegen import make_scene  # noqa: E402
+
+SEED = 1200
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TRAINED = os.path.join(ROOT, "paper_2202_12567_amd", "proposal_mlp.npy")
+
+
+def random_params(seed):
+    return omlp.flatten(omlp.init_params(seed))
+
+
+@pytest.fixture(scope="module")
+def scene():
+    return make_scene("learned", SEED)
+
+
+@pytest.fixture(scope="module")
+def feat_run(scene):
+    prm = api.default_params(seed=SEED, max_iter=5, fixed_iters=True, features=True)
+    return run_frame(scene, prm, label="learned features")
+
+
+def oracle_features(scene, s, seed):
+    """Oracle features of slice s from the oracle's own first pass."""
+    L = orender.cluster_lights(scene, seed)
+    p = orender.Params(seed=seed)
+    i1, j1, A1, _, _ = orender.slice_first_pass(scene, L, s, p)
+    cols = scene.slice_cols(s)
+    n = cols.shape[0]
+    t = A1.sum(axis=1)
+    cnt, mean, var, mn, mx = column_stats(j1, t, n)
+    stats = dict(count=cnt, sum=np.bincount(j1, weights=t, minlength=n),
+                 sumsq=np.bincount(j1, weights=t * t, minlength=n),
+                 min=mn, max=mx, zeros=np.bincount(j1, weights=(t == 0).astype(float), minlength=n))
+    rows = scene.slice_rows(s)
+    P = scene.points
+    pos = np.stack([P["px"][rows], P["py"][rows], P["pz"][rows]], 1).astype(np.float64)
+    nrm = np.stack([P["nx"][rows], P["ny"][rows], P["nz"][rows]], 1).astype(np.float64)
+    geo = dict(centroid=pos.mean(0), diag=np.linalg.norm(pos.max(0) - pos.min(0)), mean_normal=nrm.mean(0))
+    inten = L["intensity"].astype(np.float64)
+    clusters = dict(pos=L["pos"], nrm=L["nrm"], intensity=(inten[:, 0] + inten[:, 1]) + inten[:, 2],
+                    bbox_diag=np.linalg.norm(L["hi"].astype(np.float64) - L["lo"], axis=1),
+                    members=np.diff(scene.cut_offsets))
+    return omlp.features(stats, geo, clusters, cols, i1.shape[0])
+
+
+def col_range(run, s):
+    info = run["info"][s]
+    return info["off_col"], info["off_col"] + info["n"]
+
+
+def test_features_match_oracle(scene, feat_run):
+    F = feat_run["r"]["FEATURES"].reshape(-1, 12)
+    for s in (0, 9):
+        a, b = col_range(feat_run, s)
+        o = oracle_features(scene, s, SEED)
+        np.testing.assert_allclose(F[a:b], o, rtol=1e-4, atol=1e-4, err_msg=f"slice {s}")
+
+
+def test_mlp_forward_matches_oracle(feat_run):
+    F = torch.as_tensor(feat_run["r"]["FEATURES"].reshape(-1, 12)).cuda()
+    pv = random_params(7)
+    y = api.mlp_forward(feat_run["ctx"], torch.as_tensor(pv).cuda(), F).cpu().numpy()
+    yo, _ = omlp.forward(omlp.unflatten(pv), F.cpu().numpy(), rounding=True)
+    err = np.abs(y - yo).max() / (np.abs(yo).max() + 1e-12)
+    log(f"MLP forward (MFMA) max error {err:.2e} of max |y|")
+    assert err < 1e-2
+
+
+def test_mlp_gradient_matches_oracle(feat_run):
+    Fn = feat_run["r"]["FEATURES"].reshape(-1, 12)[:3000]
+    pv = random_params(11)
+    dy = np.random.default_rng(1).normal(0, 1, Fn.shape[0]).astype(np.float32)
+    g = api.mlp_grad(feat_run["ctx"], torch.as_tensor(pv).cuda(), torch.as_tensor(Fn).cuda(),
+                     torch.as_tensor(dy).cuda()).cpu().numpy()
+    _, c = omlp.forward(omlp.unflatten(pv), Fn, rounding=True)
+    go = omlp.flatten(omlp.backward(c, dy))
+    gu, gou = omlp.unflatten(g), omlp.unflatten(go)
+    for k in omlp.PARAM_ORDER:
+        rel = np.linalg.norm(gu[k] - gou[k]) / (np.linalg.norm(gou[k]) + 1e-12)
+        log(f"grad {k}: relative error {rel:.2e}")
+        assert rel < 1e-2, k
+
+
+def test_adam_step_matches_oracle(feat_run):
+    rng = np.random.default_rng(3)
+    n = api.mlp_param_count()
+    p, g, m, v = (rng.normal(0, 1, n).astype(np.float32) for _ in range(4))
+    v = np.abs(v)
+    tp, tg, tm, tv = (torch.as_tensor(a).cuda() for a in (p, g, m, v))
+    api.mlp_adam(feat_run["ctx"], tp, tg, tm, tv, 3, 1e-3)
+    po, mo, vo = omlp.adam_step(omlp.unflatten(p), omlp.unflatten(g), omlp.unflatten(m), omlp.unflatten(v), 3)
+    np.testing.assert_allclose(tp.cpu().numpy(), omlp.flatten(po), rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(tm.cpu().numpy(), omlp.flatten(mo), rtol=1e-5, atol=1e-7)
+
+
+def test_learned_weights_and_second_pass_bit_exact(scene):
+    pv = torch.as_tensor(random_params(5)).cuda()
+    prm = api.default_params(seed=SEED, max_iter=5, fixed_iters=True, learned=True)
+    ctx = api.Context(0)
+    api.set_proposal(ctx, pv)
+    ctx.set_occluders(scene.spheres)
+    ds = api.DeviceScene(scene, torch.device("cuda", 0))
+    plan = api.Plan(scene, prm)
+    ws = api.workspace(plan, torch.device("cuda", 0))
+    api.render(ctx, plan, ds, prm, ws)
+    torch.cuda.synchronize()
+    lg = api.region_view(plan, ws, "LOGITS", torch.float32).cpu().numpy()
+    w = api.region_view(plan, ws, "WEIGHTS", torch.int32).cpu().numpy().astype(np.uint64)
+    om1 = api.region_view(plan, ws, "OMEGA1", torch.int32).cpu().numpy()
+    om2 = api.region_view(plan, ws, "OMEGA2", torch.int32).cpu().numpy()
+    st = api.read_stats(ctx, plan, ws)
+    assert not (st["flags"] & 8).any()
+    for s in range(scene.n_slices):
+        info = plan.slice_info(s)
+        a, b = info["off_col"], info["off_col"] + info["n"]
+        assert np.array_equal(w[a:b], omlp.weights_from_logits(lg[a:b])), f"slice {s}"
+        m, n = info["m"], info["n"]
+        i1, j1 = keys_to_ij(om1[info["off1"]: info["off1"] + info["N1"]])
+        taken = np.zeros(m * n, bool)
+        taken[i1 * n + j1] = True
+        i2, j2, _ = pass2(SEED, s, m, n, info["N1"], prm.pass2_ppm, w[a:b], taken)
+        gi2, gj2 = keys_to_ij(om2[info["off2"]: info["off2"] + int(st["n2"][s])])
+        assert np.array_equal(gi2, i2) and np.array_equal(gj2, j2)
+
+
+def test_learned_without_model_falls_back(scene):
+    prm_l = api.default_params(seed=SEED, max_iter=3, fixed_iters=True, learned=True)
+    prm_p = api.default_params(seed=SEED, max_iter=3, fixed_iters=True)
+    rl = run_frame(scene, prm_l, label="learned, no model")
+    rp = run_frame(scene, prm_p, label="plain")
+    assert (rl["stats"]["flags"] & 8).all()
+    assert np.array_equal(rl["r"]["WEIGHTS"], rp["r"]["WEIGHTS"])
+    assert np.array_equal(rl["r"]["OMEGA2"], rp["r"]["OMEGA2"])
+    # the completion's LDS atomics sum in a run-dependent order: same samples,
+    # radiance equal up to rounding
+    scale = np.abs(rp["radiance"]).max()
+    assert np.abs(rl["radiance"] - rp["radiance"]).max() <= 1e-4 * scale
+
+
+def test_training_lowers_the_loss():
+    ctx = api.Context(0)
+    F, P, offs = train_proposal.build_dataset(ctx, range(1000, 1012))
+    params, hist = train_proposal.train(ctx, F, P, offs, steps=100, batch_groups=64, lr=2e-3, log=log)
+    assert hist[-1][1] < 0.8 * hist[0][1], hist
+
+
+def test_trained_network_gain_on_held_out_scenes():
+    """Held-out scenes: (1) how well the learned and the plain g(j) densities
+    match the full-matrix target density p* (KL), (2) the frame's pixel RMSE
+    against the brute-force sum at the same sample budget with either."""
+    if not os.path.exists(TRAINED):
+        pytest.skip("no trained proposal weights (python -m paper_2202_12567_amd.train_proposal)")
+    params = torch.as_tensor(np.load(TRAINED)).cuda()
+    ctx = api.Context(0)
+    seeds = list(train_proposal.TEST_SEEDS)[:8]
+    F, P, offs = train_proposal.build_dataset(ctx, seeds)
+    y = api.mlp_forward(ctx, params, F)
+    kl_learned = train_proposal.kl_per_group(y, P, offs)
+    # the plain density: g smoothed like the target, from the same first passes
+    g = []
+    for seed in seeds:
+        sc = make_scene("learned", seed)
+        r = run_frame(sc, api.default_params(seed=seed, max_iter=0, fixed_iters=True), label=f"plain {seed}")
+        g.append(np.where(r["r"]["COLCNT"] > 0, r["r"]["COLMAX"] - r["r"]["COLMIN"], 0.0))
+    g = np.concatenate(g)
+    o = offs.cpu().numpy()
+    lg = np.zeros_like(g)
+    for k in range(o.shape[0] - 1):
+        gs = g[o[k]:o[k + 1]]
+        lg[o[k]:o[k + 1]] = np.log(gs + 0.01 * max(gs.mean(), 1e-30))
+    kl_plain = train_proposal.kl_per_group(torch.as_tensor(lg), P, offs)
+    gains = train_proposal.rmse_gain(ctx, params, seeds[:4])
+    log(f"held-out KL(p*||q): learned {kl_learned:.4f}, plain g {kl_plain:.4f}; pixel RMSE vs full sum "
+        f"plain {gains['plain']:.4f} learned {gains['learned']:.4f}")
+    assert kl_learned < kl_plain
