@@ -209,6 +209,7 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     plan->pass2_ppm = params->pass2_ppm;
     plan->desc.resize(n_slices);
     int64_t o1 = 0, o2 = 0, oo = 0, oc = 0, orow = 0, ocp = 0, ox = 0, oy = 0, obm = 0, obmt = 0, summ = 0;
+    int64_t ogrp = 0, oell = 0, nell = 0;
     for (int s = 0; s < n_slices; ++s) {
         const int64_t m = (int64_t)pt_offsets[s + 1] - pt_offsets[s];
         const int64_t n = (int64_t)cl_offsets[s + 1] - cl_offsets[s];
@@ -253,6 +254,17 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         d.off_y = oy;
         d.off_bm = obm;
         d.off_bmt = obmt;
+        const bool in_lds = adm_fits_lds(q, (int)m);
+        d.ell = in_lds ? 1 : 0;
+        d.off_grp = (int32_t)ogrp;
+        d.off_ell = oell;
+        d.off_red = (int64_t)s * ADM_RED_FLOATS;
+        ogrp += (n + 63) / 64 + 1;
+        if (in_lds) {
+            // the columns' padded lengths sum to at most |Omega| + 64 m (counts sorted descending)
+            oell += N1 + N2 + 64 * m;
+            ++nell;
+        }
         o1 += N1;
         o2 += N2;
         oo += N1 + N2;
@@ -264,7 +276,7 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         obm += m * d.words_row;
         obmt += n * d.words_col;
         summ += m;
-        const int grp = 2 * bucket + (adm_fits_lds(q, (int)m) ? 0 : 1);
+        const int grp = 2 * bucket + (in_lds ? 0 : 1);
         plan->groups[grp].push_back(s);
         plan->group_max_m[grp] = std::max<int32_t>(plan->group_max_m[grp], (int32_t)m);
         plan->max_m = std::max<int64_t>(plan->max_m, m);
@@ -278,6 +290,13 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     plan->tot_y = oy;
     plan->tot_bm = obm;
     plan->tot_bmt = obmt;
+    plan->tot_grp = ogrp;
+    plan->tot_ell = oell;
+    plan->n_ell = nell;
+    if (ogrp > INT32_MAX) {
+        delete plan;
+        return set_error(VPLMC_EINVAL, "too many column groups (%lld)", (long long)ogrp);
+    }
     plan->sum_m = summ;
     plan->ids.clear();
     for (int g = 0; g < 8; ++g) plan->ids.insert(plan->ids.end(), plan->groups[g].begin(), plan->groups[g].end());
@@ -322,8 +341,15 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     bytes[R_COLSUMSQ] = oc * 8;
     bytes[R_COLZERO] = oc * 4;
     bytes[R_SLICE_GEO] = S * 8 * 4;
-    bytes[R_CSC_COL] = oo * 4;
-    bytes[R_RESID] = 3 * oo * 4;
+    bytes[R_ELL_PERM] = oc * 4;
+    bytes[R_ELL_POS] = oc * 4;
+    bytes[R_ELL_GRP] = plan->tot_grp * 4;
+    bytes[R_ELL_ROW] = plan->tot_ell * 4;
+    bytes[R_ELL_VAL] = 3 * plan->tot_ell * 4;
+    bytes[R_ELL_RES] = 3 * plan->tot_ell * 4;
+    bytes[R_YT] = oy * 4;
+    bytes[R_ADM_RED] = S * ADM_RED_FLOATS * 4;
+    bytes[R_E2COL] = oc * 8;
     bytes[VPLMC_R_FEATURES] = oc * MLP_IN * 4;
     bytes[VPLMC_R_LOGITS] = oc * 4;
     size_t off = 0;
@@ -483,19 +509,26 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     int32_t *row_ptr = region<int32_t>(ws, plan, VPLMC_R_ROW_PTR);
     int32_t *csr_col = region<int32_t>(ws, plan, VPLMC_R_CSR_COL);
     float *csr_val = region<float>(ws, plan, VPLMC_R_CSR_VAL);
+    EllView ell;
+    ell.perm = region<int32_t>(ws, plan, R_ELL_PERM);
+    ell.pos = region<int32_t>(ws, plan, R_ELL_POS);
+    ell.grp = region<int32_t>(ws, plan, R_ELL_GRP);
+    ell.row = plan->tot_ell > 0 ? region<int32_t>(ws, plan, R_ELL_ROW) : nullptr;
+    ell.val = region<float>(ws, plan, R_ELL_VAL);
+    ell.res = region<float>(ws, plan, R_ELL_RES);
     if ((rc = launch_sort(st, *plan, desc, bm, bmt, region<uint16_t>(ws, plan, R_WPRE), region<uint16_t>(ws, plan, R_WPRET),
-                          row_ptr, col_ptr, omega1, val1, omega2, val2, stats, csr_col, csr_val, csc_row,
-                          region<int32_t>(ws, plan, R_CSC_COL), csc_val)))
+                          row_ptr, col_ptr, omega1, val1, omega2, val2, stats, csr_col, csr_val, csc_row, csc_val,
+                          ell)))
         return rc;
     float *X = region<float>(ws, plan, VPLMC_R_X);
     float *Y = region<float>(ws, plan, VPLMC_R_Y);
     float *scale = region<float>(ws, plan, VPLMC_R_SLICE_SCALE);
     if ((rc = ph.mark(VPLMC_PH_ADM))) return rc;
-    if ((rc = launch_adm(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row,
-                         region<int32_t>(ws, plan, R_CSC_COL), csc_val, region<float>(ws, plan, R_RESID), X,
+    if ((rc = launch_adm(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X,
                          region<float>(ws, plan, R_XNEXT), region<float>(ws, plan, R_XP),
                          region<float>(ws, plan, R_LAMBDA), Y, region<float>(ws, plan, R_YP),
-                         region<float>(ws, plan, R_PI), scale, stats)))
+                         region<float>(ws, plan, R_PI), region<float>(ws, plan, R_YT),
+                         region<float>(ws, plan, R_ADM_RED), region<double>(ws, plan, R_E2COL), scale, stats)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_REDUCE))) return rc;
     if ((rc = launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, radiance))) return rc;

@@ -471,154 +471,50 @@ __global__ __launch_bounds__(THREADS) void k_adm(
 }
 
 // ---------------------------------------------------------------------------
-// LDS-resident variant for ranks 4, 8, 16: both X buffers live in LDS and
-// both phases stream the slice's samples in column-major (CSC) order, so the
-// only gathers are LDS reads and reads of Y rows that neighbouring lanes
-// share.
-//   phase A, one lane per sampled entry: X_i (LDS) and Y_j (global, 3q
-//     floats) in registers, the three dots X_i . Y_j^c, the residual r,
-//     which is also stored for phase B, and the q components of
-//     sum_c r_c Y_j^c added into the R Y^T accumulator in the other LDS
-//     buffer with LDS float atomics.  The accumulator's rows are rotated by
-//     their index, (i, k) at i q + (k + i) mod q, so that the lanes of one
-//     atomic instruction (same k, random i) spread over the banks;
-//   X update, one thread per row: t = R Y^T + a U - L un-rotated in place,
-//     X+ = X (GY Inv) + t Inv in FP64, written through a global staging buffer;
-//   phase B, a wavefront is four groups of 16 lanes (one DPP row each); a
-//     group owns one column at a time and lane k owns rank component k.
-//     The stored residuals of the column arrive 16 at a time, one per lane,
-//     and are handed to the group by DPP row broadcasts; X+^T R is
-//     accumulated in lane k, Y+_j solved in FP64 with the inverse applied
-//     across the group by DPP broadcasts, and Y+ Y+^T accumulated per lane
-//     and added into the Gram with LDS atomics.
-// The LDS atomics make the FP summation order, and hence the last bits of
-// the result, vary between runs.
-constexpr int GRP = 16;   // lanes per column group = one DPP row
-constexpr int PBK = 1;    // samples per lane in one batch
+// LDS-resident variant for ranks 4, 8, 16 (m (q + 1) words of X_k and one
+// more buffer in LDS).  The samples are read from the slice's ELL copy, in
+// which one lane walks one column and every load of a wavefront covers 64
+// consecutive entries.
+//   phase A, lane = column j: Y_j (3q floats) in registers, X_i from LDS;
+//     the residual r is stored in the ELL copy and the q components of
+//     sum_c r_c Y_j^c, times 2^S and rounded, are added into row i of a
+//     fixed-point R Y^T accumulator with integer LDS atomics (LDS float
+//     atomics serialise per lane on this chip).  Integer sums do not depend
+//     on the order of the additions.  2^S is the largest power of two with
+//     K (rs |Y|max 2^S + 1/2) < 2^31, K = most samples of a row, rs = the
+//     largest sum_c |r_c| (a bound of the first iterate, then twice the
+//     previous iterate's); if the iterate's own rs breaks the bound the
+//     phase is run again with the smaller scale, so no sum overflows.
+//   X update: T = R Y^T + a U - L, then X+ = X (GY Inv) + T Inv as FP64
+//     16 x 16 x 4 MFMA products per 16 rows (FP32 operands widened, the
+//     FP64 factors of the q x q solve, one rounding to FP32), with U, L and
+//     the FP32 MFMA Grams X+^T X+ and X+^T X on the rounded rows.
+//   phase B, lane = column j: X+^T R_j from the stored residuals and X+
+//     (LDS), then T_j = X+^T R_j + b V_j - P_j (global staging).
+//   Y update: Y+ = Y (Inv C)^T + T Inv as FP64 MFMA products per 16 rows of
+//     the 3n x q matrix, with V, P and the Gram Y+^T Y+.
+// Per-wavefront partial Grams are summed in a fixed order through the
+// slice's global scratch.  The run is reproducible bit for bit.
 
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ int dpp_mov_i(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-// sum over the 16 lanes of a DPP row, result in every lane of the row
-__device__ __forceinline__ float row_sum16(float v) {
-    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141>(v);   // row_half_mirror
-    v += dpp_mov<0x140>(v);   // row_mirror
-    return v;
-}
-// value of lane S of the row, in every lane of the row (row_newbcast)
-template <int S>
-__device__ __forceinline__ float row_bcast(float v) { return dpp_mov<0x150 + S>(v); }
-template <int S>
-__device__ __forceinline__ int row_bcast_i(int v) { return dpp_mov_i<0x150 + S>(v); }
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <int S, int N, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (S < N) {
-        f(std::integral_constant<int, S>{});
-        static_for<S + 1, N>(f);
-    }
+// v_mfma_f32_16x16x4_f32 on one wavefront: lane l holds A[l % 16][l / 16] of
+// the 16 x 4 left operand and B[l / 16][l % 16] of the 4 x 16 right one;
+// register v of lane l of the result holds D[4 (l / 16) + v][l % 16].
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
-
-struct Batch {
-    int i[PBK];
-    float m0[PBK], m1[PBK], m2[PBK];
-};
-
-__device__ __forceinline__ void load_batch(const int32_t *__restrict__ csc_row, const float *__restrict__ resid,
-                                           int p0, int end, int gl, Batch &b) {
-#pragma unroll
-    for (int u = 0; u < PBK; ++u) {
-        const int p = p0 + u * GRP + gl;
-        const bool ok = p < end;
-        const int pc = ok ? p : 0;
-        b.i[u] = ok ? csc_row[pc] : 0;
-        b.m0[u] = ok ? resid[3 * pc] : 0.f;
-        b.m1[u] = ok ? resid[3 * pc + 1] : 0.f;
-        b.m2[u] = ok ? resid[3 * pc + 2] : 0.f;
-    }
-}
-
-// phase A for sampled entry p = (i, j) with scaled values m0..m2.  The
-// q components of sum_c r_c Y_j^c, times 2^S, are rounded to integers and
-// added into row i of the fixed-point accumulator (row stride q + 1, so the
-// lanes' rows fall in different banks); integer sums do not depend on the
-// order of the additions.
-template <int Q>
-__device__ __forceinline__ void entryA(int p, int i, int j, float m0, float m1, float m2, const float *XA,
-                                       int32_t *RXI, const float *__restrict__ Y, float *__restrict__ resid,
-                                       float fxs, double &e2, float &rsmax) {
-    float y[3 * Q], x[Q];
-    const float4 *y4 = reinterpret_cast<const float4 *>(Y + (size_t)j * 3 * Q);
-#pragma unroll
-    for (int v = 0; v < 3 * Q / 4; ++v) {
-        const float4 a = y4[v];
-        y[4 * v] = a.x;
-        y[4 * v + 1] = a.y;
-        y[4 * v + 2] = a.z;
-        y[4 * v + 3] = a.w;
-    }
-    const float4 *x4 = reinterpret_cast<const float4 *>(XA + i * Q);
-#pragma unroll
-    for (int v = 0; v < Q / 4; ++v) {
-        const float4 a = x4[v];
-        x[4 * v] = a.x;
-        x[4 * v + 1] = a.y;
-        x[4 * v + 2] = a.z;
-        x[4 * v + 3] = a.w;
-    }
-    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-        d0 = fmaf(x[k], y[k], d0);
-        d1 = fmaf(x[k], y[Q + k], d1);
-        d2 = fmaf(x[k], y[2 * Q + k], d2);
-    }
-    const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
-    e2 += (double)(r0 * r0) + (double)(r1 * r1) + (double)(r2 * r2);
-    rsmax = fmaxf(rsmax, fabsf(r0) + fabsf(r1) + fabsf(r2));
-    resid[3 * p] = r0;
-    resid[3 * p + 1] = r1;
-    resid[3 * p + 2] = r2;
-    const float s0 = r0 * fxs, s1 = r1 * fxs, s2 = r2 * fxs;
-    int32_t *row = RXI + i * (Q + 1);
-#pragma unroll
-    for (int k = 0; k < Q; ++k) atomicAdd(row + k, __float2int_rn(fmaf(s0, y[k], fmaf(s1, y[Q + k], s2 * y[2 * Q + k]))));
+// The FP64 form (v_mfma_f64_16x16x4_f64) takes its operands in the same
+// lanes, but register v of lane l of its result holds D[l / 16 + 4 v][l % 16].
+typedef double d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ d4 mfma16d(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
     return v;
-}
-
-// one batch of phase B: cnt valid samples (uniform in the group); the batch
-// holds the stored residuals
-template <int Q>
-__device__ __forceinline__ void batchB(const Batch &b, int cnt, int kk, const float *XB, float &a0, float &a1,
-                                       float &a2) {
-    const bool kact = kk < Q;
-    const int kc = kact ? kk : 0;
-#pragma unroll
-    for (int u = 0; u < PBK; ++u) {
-        static_for<0, GRP>([&](auto sc) {
-            constexpr int S = decltype(sc)::value;
-            if (u * GRP + S < cnt) {
-                const int i = row_bcast_i<S>(b.i[u]);
-                const float r0 = row_bcast<S>(b.m0[u]), r1 = row_bcast<S>(b.m1[u]), r2 = row_bcast<S>(b.m2[u]);
-                const float xn = kact ? XB[i * Q + kc] : 0.f;
-                a0 = fmaf(xn, r0, a0);
-                a1 = fmaf(xn, r1, a1);
-                a2 = fmaf(xn, r2, a2);
-            }
-        });
-    }
 }
 
 // block-wide maximum of per-thread values; every thread calls it and gets the result
@@ -634,56 +530,78 @@ __device__ __forceinline__ float block_max(float v, float *red) {
     return r;
 }
 
+// Sum over the wavefronts of two per-wavefront 16 x 16 partials (result
+// layout of mfma16) in wavefront order, through global scratch `red`; the
+// q x q corners land in out0 and out1 (out1 may be null).  All threads call.
+template <int Q, int NW>
+__device__ void sum_partials(const f4 &p0, const f4 &p1, float *red, float *out0, float *out1) {
+    const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+    const int rr = 4 * (lane / 16), cc = lane % 16;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        red[(2 * w) * 256 + (rr + v) * 16 + cc] = p0[v];
+        red[(2 * w + 1) * 256 + (rr + v) * 16 + cc] = p1[v];
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (t < 2 * Q * Q) {
+        const int which = t / (Q * Q), e = t % (Q * Q), a = e / Q, b = e % Q;
+        float sum = 0.f;
+        for (int k = 0; k < NW; ++k) sum += red[(2 * k + which) * 256 + a * 16 + b];
+        if (which == 0) out0[e] = sum;
+        else if (out1) out1[e] = sum;
+    }
+    __syncthreads();
+}
+
 // elements per thread of the fixed-point to float pass (m q <= ADM_CVT_MAX * threads)
 constexpr int ADM_CVT_MAX = 18;
 
 template <int Q, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_adm_lds(
-    const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, uint64_t seed,
-    int32_t max_iter, int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma,
-    const int32_t *__restrict__ col_ptr_all, const int32_t *__restrict__ csc_row_all,
-    const int32_t *__restrict__ csc_col_all, const float *__restrict__ csc_val_all, float *resid_all, float *X_all,
-    float *Xn_all, float *Xp_all, float *Lam_all, float *Y_all, float *Yp_all, float *Pi_all, float *scale_all,
-    int32_t *stats_all) {
-    static_assert(Q <= GRP, "one lane per rank component");
+__global__ __launch_bounds__(THREADS) void k_adm_ell(
+    const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, uint64_t seed, int32_t max_iter,
+    int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma, const int32_t *__restrict__ col_ptr_all,
+    const int32_t *__restrict__ csc_row_all, const float *__restrict__ csc_val_all, EllView ell, float *X_all,
+    float *Xp_all, float *Lam_all, float *Y_all, float *Yp_all, float *Pi_all, float *Yt_all, float *red_all,
+    double *e2col_all, float *scale_all, int32_t *stats_all) {
+    static_assert(Q % 4 == 0 && Q <= 16, "ranks 4, 8, 16");
     constexpr int NW = THREADS / WAVE;
-    constexpr int NG = THREADS / GRP;                  // column groups per workgroup
-    constexpr int BS = PBK * GRP;                      // samples per group batch
+    constexpr int QV = Q / 4;                         // MFMA steps over the rank
     extern __shared__ __align__(16) float dyn[];
     __shared__ AdmShared<Q> sh;
-    __shared__ float red2[THREADS];
+    __shared__ float redf[NW];
 
     const int s = slice_list[blockIdx.x];
     const SliceDesc d = desc[s];
     const int m = d.m, n = d.n;
     const int t = threadIdx.x, lane = t % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
-    const int gl = lane % GRP;                         // lane in its group = rank component
-    const int grp = t / GRP;
-    const bool kact = gl < Q;
-    const int kc = kact ? gl : 0;
-    // two buffers of m (q + 1) words: X_k (row stride q) and the other one,
-    // which holds the fixed-point R Y^T (row stride q + 1) in phase A and X+
-    // (row stride q) from the X update on; they swap every iteration
-    float *XA = dyn;
-    float *XB = dyn + (size_t)m * (Q + 1);
-    __shared__ float redf[NW];
+    float *XA = dyn;                                  // X_k, row stride q
+    float *XB = dyn + (size_t)m * (Q + 1);            // fixed-point R Y^T (stride q + 1), then T and X+ (stride q)
 
     const int32_t *col_ptr = col_ptr_all + d.off_colptr;
     const int32_t *csc_row = csc_row_all + d.off_omega;
-    const int32_t *csc_col = csc_col_all + d.off_omega;
     const float *csc_val = csc_val_all + 3 * d.off_omega;
-    float *resid = resid_all + 3 * d.off_omega;
+    const int32_t *perm = ell.perm + d.off_col;
+    const int32_t *grp = ell.grp + d.off_grp;
+    const int32_t *erow = ell.row + d.off_ell;
+    const float *eval = ell.val + 3 * d.off_ell;
+    float *eres = ell.res + 3 * d.off_ell;
     float *Xg = X_all + d.off_x;
-    float *Xs = Xn_all + d.off_x;     // staging of X+
     float *Xp = Xp_all + d.off_x;
     float *Lam = Lam_all + d.off_x;
     float *Y = Y_all + d.off_y;
     float *Yp = Yp_all + d.off_y;
     float *Pi = Pi_all + d.off_y;
+    float *Yt = Yt_all + d.off_y;
+    float *red = red_all + d.off_red;
+    double *e2col = e2col_all + d.off_col;
     int32_t *st = stats_all + 4 * s;
     const int nnz = col_ptr[n];
+    const int G = (n + 63) / 64;
+    const int R3 = 3 * n;
 
+    // ---- scale s0 = mean sampled value; ||P_Omega M|| ----
     double sum = 0.0, sumsq = 0.0;
     for (int p = t; p < 3 * nnz; p += THREADS) {
         const double v = (double)csc_val[p];
@@ -719,8 +637,8 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
     const double normM = sqrt(totsq) / s0;
     if (t == 0) scale_all[s] = (float)s0;
 
+    // ---- initial factors: fp32(u24(Philox) * fp32(2 / sqrt q)) ----
     const float cq = (float)(2.0 / sqrt((double)Q));
-    float ym0 = 0.f;
     for (int e = t; e < m * Q; e += THREADS) {
         const int i = e / Q, k = e % Q;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
@@ -729,6 +647,7 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
         Xp[e] = v;
         Lam[e] = 0.f;
     }
+    float ym0 = 0.f;
     for (int e = t; e < 3 * n * Q; e += THREADS) {
         const int j = e / (3 * Q), c = (e / Q) % 3, k = e % Q;
         const uint64_t col = (uint64_t)c * (uint64_t)n + (uint64_t)j;
@@ -741,10 +660,21 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
     }
     __threadfence_block();
     __syncthreads();
-    gram_rows<Q>(sh, Y, 3 * n, red2);
 
-    // bounds for the fixed-point scale: K = most samples in one row, the
-    // largest sum_c |M| of a sample, the largest row 1-norm of X_0
+    // ---- GY = Y0^T Y0 ----
+    {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        const f4 zero = {0.f, 0.f, 0.f, 0.f};
+        for (int r0 = 4 * wave; r0 < R3; r0 += 4 * NW) {
+            const int r = r0 + lane / 16, c = lane % 16;
+            const float v = (r < R3 && c < Q) ? Y[(size_t)r * Q + c] : 0.f;
+            acc = mfma16(v, v, acc);
+        }
+        sum_partials<Q, NW>(acc, zero, red, sh.G, nullptr);
+    }
+
+    // ---- bounds for the fixed-point scale: K, the largest sum_c |M| of a
+    // sample, the largest row 1-norm of X_0 ----
     int32_t *cntr = reinterpret_cast<int32_t *>(XB);
     for (int e = t; e < m; e += THREADS) cntr[e] = 0;
     __syncthreads();
@@ -765,18 +695,25 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
     const double msum_max = (double)block_max(msum, redf) * (double)inv_s0;
     const double x1max = (double)block_max(x1, redf);
     double ymax = (double)block_max(ym0, redf);
-    // a-priori bound on sum_c |r_c| for the first iteration
-    double rs_est = (msum_max + 3.0 * x1max * ymax) * (1.0 + 1e-5);
-    // scale 2^S with K (rs ymax 2^S + 1/2) < 2^31 - 1, taken near 2^30 / (K rs ymax)
-    auto fits = [&](int S, double rs) {
-        return Krow * (rs * ymax * ldexp(1.0, S) + 0.5) < 2147483647.0;
-    };
-    auto pick_scale = [&](double rs) {
-        const double b = Krow * rs * ymax;
-        int S = b > 0.0 ? (int)floor(log2(1073741824.0 / b)) : 60;
+    // Two fixed-point scales per iteration.  Word q of each accumulator row
+    // sums ceil(2^Sr sum_c |r_c|) over the row's samples (an upper bound of
+    // the row's L1 residual sum RS_i); words 0..q-1 sum round(2^S c_k) with
+    // |c_k| <= sum_c |r_c| |Y|max.  Row sums fit in 32 bits when
+    //   K (rs 2^Sr + 1) < 2^32 - 1      (rs = the largest sum_c |r_c|)
+    //   RS |Y|max 2^S + K / 2 < 2^31 - 1 (RS = the largest RS_i),
+    // the integer sums being exact modulo 2^32.  Estimates come from the
+    // previous iterate (x2); phase A runs again if a bound fails.
+    double rs_est = (msum_max + 3.0 * x1max * ymax) * (1.0 + 1e-5);   // a-priori bound for the first iterate
+    double RS_est = Krow * rs_est;
+    auto pow2_below = [](double lim, double b) {       // largest S in [-60, 60] with b 2^S <= lim
+        int S = b > 0.0 ? (int)floor(log2(lim / b)) : 60;
         S = S > 60 ? 60 : (S < -60 ? -60 : S);
-        while (S > -60 && !fits(S, rs)) --S;
+        while (S > -60 && b * ldexp(1.0, S) > lim) --S;
         return S;
+    };
+    auto rs_fits = [&](int Sr, double rs) { return Krow * (rs * ldexp(1.0, Sr) + 1.0) < 4294967295.0; };
+    auto rx_fits = [&](int S, double RS) {   // 1e-5: FP32 rounding of the contributions
+        return RS * ymax * ldexp(1.0, S) * (1.0 + 1e-5) + 0.5 * Krow < 2147483647.0;
     };
 
     const double alpha = (double)alpha0 * (3.0 * n) / Q;
@@ -784,93 +721,162 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
     const float alpha_f = (float)alpha, beta_f = (float)beta;
     const float ga = (float)((double)gamma * alpha), gb = (float)((double)gamma * beta);
     const float inv_alpha = (float)(1.0 / alpha), inv_beta = (float)(1.0 / beta);
-
-    // column metadata of a group's round: j = rd * NG + grp
-    auto col_range = [&](int j, int &b, int &e) {
-        if (j < n) {
-            b = col_ptr[j];
-            e = col_ptr[j + 1];
-        } else {
-            b = e = 0;
-        }
+    // lane's column in group g: sorted position 64 g + lane
+    auto column = [&](int g, int &j, int &cnt) {
+        const int sp = 64 * g + lane;
+        j = sp < n ? perm[sp] : 0;
+        cnt = sp < n ? col_ptr[j + 1] - col_ptr[j] : 0;
     };
-    auto load_y = [&](int j, float &y0, float &y1, float &y2) {
-        const float *yj = Y + (size_t)(j < n ? j : 0) * 3 * Q;
-        y0 = (kact && j < n) ? yj[kc] : 0.f;
-        y1 = (kact && j < n) ? yj[Q + kc] : 0.f;
-        y2 = (kact && j < n) ? yj[2 * Q + kc] : 0.f;
+    // right-hand operands of the dense updates: F[l][k] and Inv[l][k] (FP64),
+    // zero outside q x q; lane holds row 4 v + lane / 16, column lane % 16
+    auto load_rhs = [&](double *b1, double *b2) {
+        const int c = lane % 16;
+#pragma unroll
+        for (int v = 0; v < QV; ++v) {
+            const int l = 4 * v + lane / 16;
+            b1[v] = c < Q ? sh.F[l * Q + c] : 0.0;
+            b2[v] = c < Q ? sh.Inv[l * Q + c] : 0.0;
+        }
     };
 
     int iters = max_iter;
     double err = 0.0;
     for (int it = 0; it < max_iter; ++it) {
-        // ---- phase A: residuals, 2^S R Y^T added into XB (fixed point) ----
+        // ---- phase A: residuals, 2^S R Y^T into XB ----
         int32_t *RXI = reinterpret_cast<int32_t *>(XB);
-        int S = pick_scale(rs_est);
-        double e2t = 0.0;
+        int Sr = pow2_below(2147483648.0, Krow * rs_est);
+        int S = pow2_below(1073741824.0, RS_est * ymax);
+        double e2t = 0.0, RSc = 0.0;
         float rsc = 0.f;
         for (;;) {
-            const float fxs = ldexpf(1.f, S);
+            const float fxs = ldexpf(1.f, S), fxr = ldexpf(1.f, Sr);
             for (int e = t; e < m * (Q + 1); e += THREADS) RXI[e] = 0;
             __syncthreads();
-            double e2 = 0.0;
             float rsm = 0.f;
-            int p = t;
-            int i = 0, j = 0;
-            float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-            if (p < nnz) {
-                i = csc_row[p];
-                j = csc_col[p];
-                m0 = csc_val[3 * p] * inv_s0;
-                m1 = csc_val[3 * p + 1] * inv_s0;
-                m2 = csc_val[3 * p + 2] * inv_s0;
-            }
-            while (p < nnz) {
-                const int pn = p + THREADS;
-                int in = 0, jn = 0;
-                float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-                if (pn < nnz) {
-                    in = csc_row[pn];
-                    jn = csc_col[pn];
-                    n0 = csc_val[3 * pn] * inv_s0;
-                    n1 = csc_val[3 * pn + 1] * inv_s0;
-                    n2 = csc_val[3 * pn + 2] * inv_s0;
+            for (int g = wave; g < G; g += NW) {
+                int j, cnt;
+                column(g, j, cnt);
+                const int base = grp[g];
+                const int len = (grp[g + 1] - base) >> 6;
+                double e2 = 0.0;
+                float y[3 * Q];
+                const float4 *y4 = reinterpret_cast<const float4 *>(Y + (size_t)j * 3 * Q);
+#pragma unroll
+                for (int v = 0; v < 3 * Q / 4; ++v) {
+                    const float4 a = cnt > 0 ? y4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    y[4 * v] = a.x;
+                    y[4 * v + 1] = a.y;
+                    y[4 * v + 2] = a.z;
+                    y[4 * v + 3] = a.w;
                 }
-                entryA<Q>(p, i, j, m0, m1, m2, XA, RXI, Y, resid, fxs, e2, rsm);
-                p = pn;
-                i = in;
-                j = jn;
-                m0 = n0;
-                m1 = n1;
-                m2 = n2;
+                int i = 0;
+                float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+                if (cnt > 0) {
+                    const int e = base + lane;
+                    i = erow[e];
+                    m0 = eval[3 * e] * inv_s0;
+                    m1 = eval[3 * e + 1] * inv_s0;
+                    m2 = eval[3 * e + 2] * inv_s0;
+                }
+                for (int k = 0; k < len; ++k) {
+                    const bool act = k < cnt;
+                    int in = 0;
+                    float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+                    if (k + 1 < cnt) {
+                        const int e = base + 64 * (k + 1) + lane;
+                        in = erow[e];
+                        n0 = eval[3 * e] * inv_s0;
+                        n1 = eval[3 * e + 1] * inv_s0;
+                        n2 = eval[3 * e + 2] * inv_s0;
+                    }
+                    if (act) {
+                        float x[Q];
+                        const float4 *x4 = reinterpret_cast<const float4 *>(XA + i * Q);
+#pragma unroll
+                        for (int v = 0; v < QV; ++v) {
+                            const float4 a = x4[v];
+                            x[4 * v] = a.x;
+                            x[4 * v + 1] = a.y;
+                            x[4 * v + 2] = a.z;
+                            x[4 * v + 3] = a.w;
+                        }
+                        float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+#pragma unroll
+                        for (int kk = 0; kk < Q; ++kk) {
+                            d0 = fmaf(x[kk], y[kk], d0);
+                            d1 = fmaf(x[kk], y[Q + kk], d1);
+                            d2 = fmaf(x[kk], y[2 * Q + kk], d2);
+                        }
+                        const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
+                        e2 += (double)(r0 * r0) + (double)(r1 * r1) + (double)(r2 * r2);
+                        const int e = base + 64 * k + lane;
+                        eres[3 * e] = r0;
+                        eres[3 * e + 1] = r1;
+                        eres[3 * e + 2] = r2;
+                        const float rsa = fabsf(r0) + fabsf(r1) + fabsf(r2);
+                        rsm = fmaxf(rsm, rsa);
+                        const float s0r = r0 * fxs, s1r = r1 * fxs, s2r = r2 * fxs;
+                        int32_t *row = RXI + i * (Q + 1);
+#pragma unroll
+                        for (int kk = 0; kk < Q; ++kk)
+                            atomicAdd(row + kk, __float2int_rn(fmaf(s0r, y[kk], fmaf(s1r, y[Q + kk], s2r * y[2 * Q + kk]))));
+                        atomicAdd(reinterpret_cast<uint32_t *>(row + Q), __float2uint_ru(rsa * fxr));
+                    }
+                    i = in;
+                    m0 = n0;
+                    m1 = n1;
+                    m2 = n2;
+                }
+                if (64 * g + lane < n) e2col[j] = e2;
             }
+            // sum of the columns' squared residuals in column order
+            __threadfence_block();
+            __syncthreads();
+            double e2 = 0.0;
+            for (int j = t; j < n; j += THREADS) e2 += e2col[j];
+            uint32_t rsw = 0;
+            for (int i = t; i < m; i += THREADS) rsw = max(rsw, reinterpret_cast<const uint32_t *>(RXI)[i * (Q + 1) + Q]);
             e2 = wave_sum_d(e2);
             rsm = wave_max(rsm);
+            const float rswf = wave_max((float)rsw);
             if (lane == 0) {
                 sh.red[wave] = e2;
                 redf[wave] = rsm;
+                sh.red[16 + wave] = (double)rswf;
             }
             __syncthreads();
             e2t = 0.0;
             rsc = 0.f;
+            double rsw_max = 0.0;
             for (int w = 0; w < NW; ++w) {
                 e2t += sh.red[w];
                 rsc = fmaxf(rsc, redf[w]);
+                rsw_max = fmax(rsw_max, sh.red[16 + w]);
             }
             __syncthreads();
             // every integer sum provably fits, or the residuals are not finite
             const double rsb = (double)rsc * (1.0 + 1e-5);
-            if (!(rsb < 1e300) || fits(S, rsb) || S <= -60) break;
-            S = pick_scale(rsb);
+            if (!(rsb < 1e300)) break;
+            if (!rs_fits(Sr, rsb)) {                  // row L1 sums may have wrapped: redo with safe scales
+                Sr = pow2_below(2147483648.0, Krow * rsb);
+                S = pow2_below(1073741824.0, Krow * rsb * ymax);
+                if (Sr <= -60) break;
+                continue;
+            }
+            // (float) of the 32-bit word rounds by at most 2^-24 relative
+            RSc = rsw_max * (1.0 + 1e-6) * ldexp(1.0, -Sr);
+            if (rx_fits(S, RSc) || S <= -60) break;
+            S = pow2_below(1073741824.0, RSc * ymax);
         }
         rs_est = 2.0 * (double)rsc;
+        RS_est = 2.0 * RSc;
         err = sqrt(e2t) / normM;
         if (!fixed_iters && err < (double)tol) {
             iters = it;
             break;
         }
 
-        // ---- X update: t = RX + a U - L (in XB, row stride q), X+ = X (GY Inv) + t Inv ----
+        // ---- T = 2^-S RX + a U - L into XB (row stride q) ----
         {
             const float ifx = ldexpf(1.f, -S);
             float tv[ADM_CVT_MAX];
@@ -890,6 +896,7 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
                 if (e < m * Q) XB[e] = tv[u];
             }
         }
+        // ---- X system: Inv = (GY + a I)^-1, F = GY Inv ----
         spd_inverse<Q>(sh, alpha);           // begins and ends with a barrier
         for (int e = t; e < Q * Q; e += THREADS) {
             const int a = e / Q, b = e % Q;
@@ -898,54 +905,43 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
             sh.F[e] = v;
         }
         __syncthreads();
-        for (int e = t; e < m * Q; e += THREADS) {
-            const int i = e / Q, k = e % Q;
-            const float *xa = XA + i * Q;
-            const float *tb = XB + i * Q;
-            double v = 0.0;
-#pragma unroll 4
-            for (int l = 0; l < Q; ++l) v += (double)xa[l] * sh.F[l * Q + k] + (double)tb[l] * sh.Inv[l * Q + k];
-            Xs[e] = (float)v;
-        }
-        __threadfence_block();
-        __syncthreads();
-        for (int e = t; e < m * Q; e += THREADS) {
-            const float xn = Xs[e];
-            const float lam = Lam[e];
-            const float u = fmaxf(0.f, xn + lam * inv_alpha);
-            Xp[e] = u;
-            Lam[e] = lam + ga * (xn - u);
-            XB[e] = xn;
-        }
-        __syncthreads();
-        // Grams GX = X+^T X+ and C = X+^T X over the rows (fixed order)
+        // ---- X+ = X F + T Inv (FP64 MFMA), U, L, Grams X+^T X+ and X+^T X ----
         {
-            constexpr int P = Q * Q;
-            const int groups = THREADS / P, g = t / P, pp = t % P;
-            const int a = pp / Q, b = pp % Q;
-            float gx = 0.f, cc = 0.f;
-            for (int r = g; r < m; r += groups) {
-                const float xa = XB[r * Q + a];
-                gx = fmaf(xa, XB[r * Q + b], gx);
-                cc = fmaf(xa, XA[r * Q + b], cc);
+            double b1[QV], b2[QV];
+            load_rhs(b1, b2);
+            f4 gx = {0.f, 0.f, 0.f, 0.f}, cx = {0.f, 0.f, 0.f, 0.f};
+            for (int r0 = 16 * wave; r0 < m; r0 += 16 * NW) {
+                const int ra = r0 + lane % 16;
+                d4 D = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int v = 0; v < QV; ++v) {
+                    const int kk = 4 * v + lane / 16;
+                    const double a1 = ra < m ? (double)XA[ra * Q + kk] : 0.0;
+                    const double a2 = ra < m ? (double)XB[ra * Q + kk] : 0.0;
+                    D = mfma16d(a1, b1[v], D);
+                    D = mfma16d(a2, b2[v], D);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = r0 + lane / 16 + 4 * v, c = lane % 16;   // FP64 result layout
+                    const bool ok = r < m && c < Q;
+                    const float xn = ok ? (float)D[v] : 0.f;
+                    const float xk = ok ? XA[r * Q + c] : 0.f;
+                    if (ok) {
+                        const int e = r * Q + c;
+                        const float lam = Lam[e];
+                        const float u = fmaxf(0.f, xn + lam * inv_alpha);
+                        Xp[e] = u;
+                        Lam[e] = lam + ga * (xn - u);
+                        XB[e] = xn;
+                    }
+                    gx = mfma16(xn, xn, gx);
+                    cx = mfma16(xn, xk, cx);
+                }
             }
-            red2[t] = gx;
-            __syncthreads();
-            if (t < P) {
-                float v = 0.f;
-                for (int gg = 0; gg < groups; ++gg) v += red2[gg * P + t];
-                sh.G[t] = v;
-            }
-            __syncthreads();
-            red2[t] = cc;
-            __syncthreads();
-            if (t < P) {
-                float v = 0.f;
-                for (int gg = 0; gg < groups; ++gg) v += red2[gg * P + t];
-                sh.C[t] = v;
-            }
+            sum_partials<Q, NW>(gx, cx, red, sh.G, sh.C);
         }
-        // ---- Y system: Inv = (GX + b I)^-1, F^T = (Inv C)^T ----
+        // ---- Y system: Inv = (GX + b I)^-1, F[l][k] = (Inv C)[k][l] ----
         spd_inverse<Q>(sh, beta);
         for (int e = t; e < Q * Q; e += THREADS) {
             const int a = e / Q, b = e % Q;
@@ -953,82 +949,111 @@ __global__ __launch_bounds__(THREADS) void k_adm_lds(
             for (int l = 0; l < Q; ++l) v += sh.Inv[a * Q + l] * (double)sh.C[l * Q + b];
             sh.F[b * Q + a] = v;
         }
-        for (int e = t; e < Q * Q; e += THREADS) sh.G[e] = 0.f;
         __syncthreads();
-
-        // ---- phase B ----
-        float ymx = 0.f;
-        float gyrow[Q];
+        // ---- phase B: T_j = X+^T R_j + b V_j - P_j ----
+        for (int g = wave; g < G; g += NW) {
+            int j, cnt;
+            column(g, j, cnt);
+            const int base = grp[g];
+            const int len = (grp[g + 1] - base) >> 6;
+            float acc[3 * Q];
 #pragma unroll
-        for (int b = 0; b < Q; ++b) gyrow[b] = 0.f;
-        {
-            int j = grp, beg, end, begn, endn;
-            float y0, y1, y2, z0, z1, z2;
-            Batch bc, bn, bx;
-            col_range(j, beg, end);
-            load_y(j, y0, y1, y2);
-            load_batch(csc_row, resid, beg, end, gl, bc);
-            for (; j < n; j += NG) {
-                const int jn = j + NG;
-                col_range(jn, begn, endn);
-                load_y(jn, z0, z1, z2);
-                load_batch(csc_row, resid, begn, endn, gl, bn);
-                float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-                for (int p0 = beg; p0 < end; p0 += BS) {
-                    const bool more = p0 + BS < end;
-                    if (more) load_batch(csc_row, resid, p0 + BS, end, gl, bx);
-                    batchB<Q>(bc, end - p0, gl, XB, a0, a1, a2);
-                    if (more) bc = bx;
+            for (int kk = 0; kk < 3 * Q; ++kk) acc[kk] = 0.f;
+            int i = 0;
+            float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+            if (cnt > 0) {
+                const int e = base + lane;
+                i = erow[e];
+                r0 = eres[3 * e];
+                r1 = eres[3 * e + 1];
+                r2 = eres[3 * e + 2];
+            }
+            for (int k = 0; k < len; ++k) {
+                const bool act = k < cnt;
+                int in = 0;
+                float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+                if (k + 1 < cnt) {
+                    const int e = base + 64 * (k + 1) + lane;
+                    in = erow[e];
+                    n0 = eres[3 * e];
+                    n1 = eres[3 * e + 1];
+                    n2 = eres[3 * e + 2];
                 }
-                // Y+ (c, k) = sum_l F[k][l] y(c, l) + Inv[k][l] t(c, l), lane k of the group
-                float *ypj = Yp + (size_t)j * 3 * Q;
-                float *pij = Pi + (size_t)j * 3 * Q;
-                const float p0v = kact ? pij[kc] : 0.f, p1v = kact ? pij[Q + kc] : 0.f, p2v = kact ? pij[2 * Q + kc] : 0.f;
-                const float t0 = kact ? a0 + beta_f * ypj[kc] - p0v : 0.f;
-                const float t1 = kact ? a1 + beta_f * ypj[Q + kc] - p1v : 0.f;
-                const float t2 = kact ? a2 + beta_f * ypj[2 * Q + kc] - p2v : 0.f;
-                double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-                static_for<0, Q>([&](auto lc) {
-                    constexpr int L = decltype(lc)::value;
-                    const double f = sh.F[L * Q + kc], iv = sh.Inv[L * Q + kc];
-                    v0 += f * (double)row_bcast<L>(y0) + iv * (double)row_bcast<L>(t0);
-                    v1 += f * (double)row_bcast<L>(y1) + iv * (double)row_bcast<L>(t1);
-                    v2 += f * (double)row_bcast<L>(y2) + iv * (double)row_bcast<L>(t2);
-                });
-                const float n0 = kact ? (float)v0 : 0.f, n1 = kact ? (float)v1 : 0.f, n2 = kact ? (float)v2 : 0.f;
-                if (kact) {
-                    const float u0 = fmaxf(0.f, n0 + p0v * inv_beta);
-                    const float u1 = fmaxf(0.f, n1 + p1v * inv_beta);
-                    const float u2 = fmaxf(0.f, n2 + p2v * inv_beta);
-                    ypj[kc] = u0;
-                    ypj[Q + kc] = u1;
-                    ypj[2 * Q + kc] = u2;
-                    pij[kc] = p0v + gb * (n0 - u0);
-                    pij[Q + kc] = p1v + gb * (n1 - u1);
-                    pij[2 * Q + kc] = p2v + gb * (n2 - u2);
-                    float *yw = Y + (size_t)j * 3 * Q;
-                    yw[kc] = n0;
-                    yw[Q + kc] = n1;
-                    yw[2 * Q + kc] = n2;
-                    ymx = fmaxf(ymx, fmaxf(fabsf(n0), fmaxf(fabsf(n1), fabsf(n2))));
+                if (act) {
+                    const float4 *x4 = reinterpret_cast<const float4 *>(XB + i * Q);
+#pragma unroll
+                    for (int v = 0; v < QV; ++v) {
+                        const float4 a = x4[v];
+                        const float xs[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            acc[4 * v + u] = fmaf(r0, xs[u], acc[4 * v + u]);
+                            acc[Q + 4 * v + u] = fmaf(r1, xs[u], acc[Q + 4 * v + u]);
+                            acc[2 * Q + 4 * v + u] = fmaf(r2, xs[u], acc[2 * Q + 4 * v + u]);
+                        }
+                    }
                 }
-                // row kc of Y+ Y+^T for this column
-                static_for<0, Q>([&](auto bc2) {
-                    constexpr int B = decltype(bc2)::value;
-                    gyrow[B] = fmaf(n0, row_bcast<B>(n0), fmaf(n1, row_bcast<B>(n1), fmaf(n2, row_bcast<B>(n2), gyrow[B])));
-                });
-                bc = bn;
-                y0 = z0; y1 = z1; y2 = z2;
-                beg = begn;
-                end = endn;
+                i = in;
+                r0 = n0;
+                r1 = n1;
+                r2 = n2;
+            }
+            if (64 * g + lane < n) {
+                const size_t o = (size_t)j * 3 * Q;
+#pragma unroll
+                for (int v = 0; v < 3 * Q / 4; ++v) {
+                    const float4 yp = reinterpret_cast<const float4 *>(Yp + o)[v];
+                    const float4 pi = reinterpret_cast<const float4 *>(Pi + o)[v];
+                    float4 tt;
+                    tt.x = acc[4 * v] + (beta_f * yp.x - pi.x);
+                    tt.y = acc[4 * v + 1] + (beta_f * yp.y - pi.y);
+                    tt.z = acc[4 * v + 2] + (beta_f * yp.z - pi.z);
+                    tt.w = acc[4 * v + 3] + (beta_f * yp.w - pi.w);
+                    reinterpret_cast<float4 *>(Yt + o)[v] = tt;
+                }
             }
         }
-        if (kact) {
-#pragma unroll
-            for (int b = 0; b < Q; ++b) atomicAdd(&sh.G[kc * Q + b], gyrow[b]);
-        }
         __threadfence_block();
-        ymax = (double)block_max(ymx, redf);   // ends with a barrier
+        __syncthreads();
+        // ---- Y+ = Y F + T Inv (FP64 MFMA) over the 3n rows, V, P, Gram Y+^T Y+ ----
+        {
+            double b1[QV], b2[QV];
+            load_rhs(b1, b2);
+            f4 gy = {0.f, 0.f, 0.f, 0.f};
+            const f4 zero = {0.f, 0.f, 0.f, 0.f};
+            float ymx = 0.f;
+            for (int r0 = 16 * wave; r0 < R3; r0 += 16 * NW) {
+                const int ra = r0 + lane % 16;
+                d4 D = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int v = 0; v < QV; ++v) {
+                    const int kk = 4 * v + lane / 16;
+                    const double a1 = ra < R3 ? (double)Y[(size_t)ra * Q + kk] : 0.0;
+                    const double a2 = ra < R3 ? (double)Yt[(size_t)ra * Q + kk] : 0.0;
+                    D = mfma16d(a1, b1[v], D);
+                    D = mfma16d(a2, b2[v], D);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = r0 + lane / 16 + 4 * v, c = lane % 16;   // FP64 result layout
+                    const bool ok = r < R3 && c < Q;
+                    const float yn = ok ? (float)D[v] : 0.f;
+                    if (ok) {
+                        const size_t e = (size_t)r * Q + c;
+                        const float pi = Pi[e];
+                        const float u = fmaxf(0.f, yn + pi * inv_beta);
+                        Yp[e] = u;
+                        Pi[e] = pi + gb * (yn - u);
+                        Y[e] = yn;
+                        ymx = fmaxf(ymx, fabsf(yn));
+                    }
+                    gy = mfma16(yn, yn, gy);
+                }
+            }
+            __threadfence_block();
+            sum_partials<Q, NW>(gy, zero, red, sh.G, nullptr);
+            ymax = (double)block_max(ymx, redf);
+        }
         float *tmp = XA;
         XA = XB;
         XB = tmp;
@@ -1102,19 +1127,19 @@ int launch_adm_global(hipStream_t st, size_t count, const int32_t *ids_dev, cons
 }
 
 template <int Q>
-int launch_adm_lds(hipStream_t st, size_t count, int max_m, const int32_t *ids_dev, const SliceDesc *desc,
-                   const vplmc_params &prm, const int32_t *col_ptr, const int32_t *csc_row, const int32_t *csc_col,
-                   const float *csc_val, float *resid, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp,
-                   float *Pi, float *scale, int32_t *stats) {
+int launch_adm_ell(hipStream_t st, size_t count, int max_m, const int32_t *ids_dev, const SliceDesc *desc,
+                   const vplmc_params &prm, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
+                   const EllView &ell, float *X, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt,
+                   float *red, double *e2col, float *scale, int32_t *stats) {
     if (count == 0) return VPLMC_OK;
     constexpr int T = adm_lds_threads(Q);
     const size_t dyn = adm_lds_dynamic_bytes(Q, max_m);
-    auto kern = k_adm_lds<Q, T>;
+    auto kern = k_adm_ell<Q, T>;
     VPLMC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     hipLaunchKernelGGL(kern, dim3((unsigned)count), dim3(T), dyn, st, desc, ids_dev, prm.seed, prm.max_iter,
                        (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0, prm.gamma, col_ptr,
-                       csc_row, csc_col, csc_val, resid, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
+                       csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2col, scale, stats);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
@@ -1123,9 +1148,9 @@ int launch_adm_lds(hipStream_t st, size_t count, int max_m, const int32_t *ids_d
 
 int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
                const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
-               const int32_t *col_ptr, const int32_t *csc_row, const int32_t *csc_col, const float *csc_val,
-               float *resid, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale,
-               int32_t *stats) {
+               const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, const EllView &ell, float *X,
+               float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt, float *red, double *e2col,
+               float *scale, int32_t *stats) {
     // ids_dev holds the slice ids of groups 0..7 in order (2 * rank bucket + variant)
     size_t base[9] = {0};
     for (int g = 0; g < 8; ++g) base[g + 1] = base[g] + plan.groups[g].size();
@@ -1133,8 +1158,8 @@ int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, co
     for (int g = 0; g < 8; ++g) id[g] = ids_dev + base[g];
     int rc;
 #define VPLMC_ADM_PAIR(B, Q, TG)                                                                                   \
-    if ((rc = launch_adm_lds<Q>(st, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], desc, prm,       \
-                                col_ptr, csc_row, csc_col, csc_val, resid, X, Xn, Xp, Lam, Y, Yp, Pi, scale,      \
+    if ((rc = launch_adm_ell<Q>(st, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], desc, prm,       \
+                                col_ptr, csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2col, scale,       \
                                 stats)))                                                                           \
         return rc;                                                                                                 \
     if ((rc = launch_adm_global<Q, TG>(st, plan.groups[2 * B + 1].size(), id[2 * B + 1], desc, prm, row_ptr,      \

@@ -472,7 +472,7 @@ __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t tot
                           const uint32_t *__restrict__ bmt, const uint16_t *__restrict__ wpre,
                           const uint16_t *__restrict__ wpret, const int32_t *__restrict__ row_ptr,
                           const int32_t *__restrict__ col_ptr, int32_t *csr_col, float *csr_val,
-                          int32_t *csc_row, int32_t *csc_col, float *csc_val) {
+                          int32_t *csc_row, float *csc_val, EllView ell) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= total) return;
     const int s = slice_of(desc, S, g, which);
@@ -494,10 +494,70 @@ __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t tot
         csr_val[3 * (o + pr) + 2] = v2;
     }
     csc_row[o + pc] = (int32_t)i;
-    if (csc_col) csc_col[o + pc] = (int32_t)j;
     csc_val[3 * (o + pc)] = v0;
     csc_val[3 * (o + pc) + 1] = v1;
     csc_val[3 * (o + pc) + 2] = v2;
+    if (ell.row && d.ell) {
+        const int64_t k2 = pc - col_ptr[d.off_colptr + j];
+        const int32_t sp = ell.pos[d.off_col + j];
+        const int64_t e = d.off_ell + ell.grp[d.off_grp + (sp >> 6)] + 64 * k2 + (sp & 63);
+        ell.row[e] = (int32_t)i;
+        ell.val[3 * e] = v0;
+        ell.val[3 * e + 1] = v1;
+        ell.val[3 * e + 2] = v2;
+    }
+}
+
+// Columns of an ELL slice sorted by sample count, descending (counting sort
+// over the counts; the order among equal counts is immaterial), and the
+// offsets of the 64-column groups: a group takes 64 x the count of its first
+// (largest) column.
+__global__ __launch_bounds__(1024) void k_colsort(const SliceDesc *__restrict__ desc,
+                                                  const int32_t *__restrict__ col_ptr, EllView ell) {
+    __shared__ uint32_t hist[ELL_MAX_M + 1];
+    __shared__ uint32_t sm[1024 / WAVE];
+    const SliceDesc d = desc[blockIdx.x];
+    if (!d.ell) return;
+    const int m = d.m, n = d.n, t = threadIdx.x;
+    const int32_t *cp = col_ptr + d.off_colptr;
+    for (int c = t; c <= m; c += 1024) hist[c] = 0;
+    __syncthreads();
+    for (int j = t; j < n; j += 1024) atomicAdd(&hist[cp[j + 1] - cp[j]], 1u);
+    __syncthreads();
+    // bins in the order m, m - 1, ..., 0; thread t owns C consecutive ones
+    const int B = m + 1, C = (B + 1023) / 1024;
+    uint32_t loc = 0;
+    for (int u = 0; u < C; ++u) {
+        const int r = t * C + u;
+        if (r < B) loc += hist[m - r];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(loc, &tot, sm);
+    for (int u = 0; u < C; ++u) {
+        const int r = t * C + u;
+        if (r < B) {
+            const uint32_t h = hist[m - r];
+            hist[m - r] = run;
+            run += h;
+        }
+    }
+    __syncthreads();
+    for (int j = t; j < n; j += 1024) {
+        const uint32_t p = atomicAdd(&hist[cp[j + 1] - cp[j]], 1u);
+        ell.perm[d.off_col + p] = j;
+        ell.pos[d.off_col + j] = (int32_t)p;
+    }
+    __threadfence_block();
+    __syncthreads();
+    const int G = (n + 63) / 64;   // <= 1024
+    uint32_t len = 0;
+    if (t < G) {
+        const int j = ell.perm[d.off_col + 64 * t];
+        len = 64u * (uint32_t)(cp[j + 1] - cp[j]);
+    }
+    const uint32_t off = block_excl_scan(len, &tot, sm);
+    if (t < G) ell.grp[d.off_grp + t] = (int32_t)off;
+    if (t == 0) ell.grp[d.off_grp + G] = (int32_t)tot;
 }
 
 unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
@@ -554,7 +614,7 @@ int launch_colstats(hipStream_t st, const vplmc_plan &plan, const SliceDesc *des
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(plan.tot1, 256)), dim3(256), 0, st, desc, S, plan.tot1, 0,
                            (const int32_t *)nullptr, omega1, val1, (const uint32_t *)nullptr, bmt,
                            (const uint16_t *)nullptr, wpret, (const int32_t *)nullptr, col_ptr, (int32_t *)nullptr,
-                           (float *)nullptr, csc_row, (int32_t *)nullptr, csc_val);
+                           (float *)nullptr, csc_row, csc_val, EllView{});
         VPLMC_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_colstats, dim3(blocks_for(cols, 256)), dim3(256), 0, st, desc, S, cols, col_ptr, csc_val,
@@ -584,8 +644,8 @@ int launch_pass2(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, 
 int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *bm,
                 const uint32_t *bmt, uint16_t *wpre, uint16_t *wpret, int32_t *row_ptr, int32_t *col_ptr,
                 const uint32_t *omega1, const float *val1, const uint32_t *omega2, const float *val2,
-                const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, int32_t *csc_col,
-                float *csc_val) {
+                const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, float *csc_val,
+                const EllView &ell) {
     if (plan.n_slices <= 0) return VPLMC_OK;
     const int S = plan.n_slices;
     const int64_t rows = plan.tot_row - S;     // sum of m
@@ -600,16 +660,20 @@ int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, c
     VPLMC_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_ptrscan, dim3(S), dim3(256), 0, st, desc, 1, col_ptr);
     VPLMC_HIP(hipGetLastError());
+    if (plan.n_ell > 0) {
+        hipLaunchKernelGGL(k_colsort, dim3(S), dim3(1024), 0, st, desc, col_ptr, ell);
+        VPLMC_HIP(hipGetLastError());
+    }
     if (plan.tot1 > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(plan.tot1, 256)), dim3(256), 0, st, desc, S, plan.tot1, 0,
                            stats, omega1, val1, bm, bmt, wpre, wpret, row_ptr, col_ptr, csr_col, csr_val, csc_row,
-                           csc_col, csc_val);
+                           csc_val, ell);
         VPLMC_HIP(hipGetLastError());
     }
     if (plan.tot2 > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(plan.tot2, 256)), dim3(256), 0, st, desc, S, plan.tot2, 1,
                            stats, omega2, val2, bm, bmt, wpre, wpret, row_ptr, col_ptr, csr_col, csr_val, csc_row,
-                           csc_col, csc_val);
+                           csc_val, ell);
         VPLMC_HIP(hipGetLastError());
     }
     return VPLMC_OK;

@@ -91,18 +91,29 @@ void build_bvh(int32_t n, const float *cx, const float *cy, const float *cz, con
 struct SliceDesc {
     int32_t m, n, q, N1;
     int32_t N2, pt_off, cl_off, words_row;     // words_row = ceil(n / 32)
-    int32_t words_col, pad0, pad1, pad2;       // words_col = ceil(m / 32)
+    int32_t words_col, off_grp, ell, pad0;     // words_col = ceil(m / 32); ell: completed from the ELL copy
     int64_t off1, off2, off_omega, off_col;
     int64_t off_row, off_colptr, off_x, off_y;
     int64_t off_bm, off_bmt;                   // bitmap word offsets (row- and column-major)
+    int64_t off_ell, off_red;                  // ELL entry offset; cross-wave reduction scratch (floats)
 };
 
-// Regions of the workspace: byte offsets.
-struct Layout {
-    size_t off[VPLMC_R_COUNT + 24];
-    size_t bytes[VPLMC_R_COUNT + 24];
-    size_t total;
+// Column-major ELL copy of a slice's samples for the LDS-resident completion:
+// the columns sorted by sample count (descending) are cut into groups of 64;
+// sample k (CSC order) of the column at sorted position 64 g + l is entry
+// grp[g] + 64 k + l, so that one load instruction of a wavefront whose lane l
+// walks that column reads 64 consecutive entries.  Entries past a column's
+// count are padding and never read.
+struct EllView {
+    int32_t *perm;   // per (slice, sorted position): column
+    int32_t *pos;    // per (slice, column): sorted position
+    int32_t *grp;    // per slice: ceil(n / 64) + 1 group offsets, relative to off_ell
+    int32_t *row;    // per entry: row of the sample
+    float *val;      // 3 per entry: sampled values
+    float *res;      // 3 per entry: residual of the current iterate
 };
+constexpr int ELL_MAX_M = 8192;   // rows of a slice that may use the ELL copy (histogram bins)
+constexpr int ADM_RED_FLOATS = 16 * 2 * 256;   // per slice: 16 wavefronts x two 16 x 16 partial Grams
 
 // extra (internal) regions, after the public ones
 enum {
@@ -122,9 +133,23 @@ enum {
     R_COLSUMSQ,      // double per (slice, column): sum of t^2
     R_COLZERO,       // int32 per (slice, column): observations with t = 0
     R_SLICE_GEO,     // float[8] per slice: centroid xyz, bbox diagonal, mean normal xyz, -
-    R_CSC_COL,       // int32 per sampled entry, CSC order: its column
-    R_RESID,         // float[3] per sampled entry, CSC order: residual of the current iterate
+    R_ELL_PERM,      // int32 per (slice, column)
+    R_ELL_POS,       // int32 per (slice, column)
+    R_ELL_GRP,       // int32 per slice: ceil(n / 64) + 1
+    R_ELL_ROW,       // int32 per ELL entry
+    R_ELL_VAL,       // float[3] per ELL entry
+    R_ELL_RES,       // float[3] per ELL entry
+    R_YT,            // float[n][3][q]: staging of the right-hand sides of the Y update
+    R_ADM_RED,       // float per slice: ADM_RED_FLOATS
+    R_E2COL,         // double per (slice, column): squared residual over the column's samples
     R_INTERNAL_END
+};
+
+// Regions of the workspace: byte offsets.
+struct Layout {
+    size_t off[R_INTERNAL_END];
+    size_t bytes[R_INTERNAL_END];
+    size_t total;
 };
 
 }  // namespace vplmc
@@ -156,6 +181,7 @@ struct vplmc_plan {
     vplmc::Layout layout;
     int64_t tot1 = 0, tot2 = 0, tot_omega = 0, tot_col = 0, tot_row = 0, tot_x = 0, tot_y = 0;
     int64_t tot_bm = 0, tot_bmt = 0;
+    int64_t tot_grp = 0, tot_ell = 0, n_ell = 0;   // ELL group table entries, ELL entries, ELL slices
     std::vector<int32_t> ids;                  // slice ids grouped by rank bucket
     std::vector<char> upload;                  // descriptor table + ids, as copied to the workspace
 };
@@ -165,12 +191,12 @@ namespace vplmc {
 constexpr size_t LDS_BYTES = 160 * 1024;
 constexpr int adm_lds_threads(int q) { return q == 32 ? 0 : 1024; }
 constexpr size_t adm_lds_static_bytes(int q) {
-    return (size_t)(4 * q * q * 8 + 2 * q * q * 4 + 32 * 8) + (size_t)adm_lds_threads(q) * 4 + 1024;
+    return (size_t)(4 * q * q * 8 + 2 * q * q * 4 + 32 * 8) + 2 * 256 * 4 + 1024;
 }
 // two LDS buffers of m (q + 1) words (X_k and R Y^T / X+)
 constexpr size_t adm_lds_dynamic_bytes(int q, int m) { return (size_t)2 * m * (q + 1) * 4; }
 inline bool adm_fits_lds(int q, int m) {
-    return q <= 16 && (int64_t)m * q <= 18 * 1024 &&
+    return q <= 16 && m <= ELL_MAX_M && (int64_t)m * q <= 18 * 1024 &&
            adm_lds_static_bytes(q) + adm_lds_dynamic_bytes(q, m) <= LDS_BYTES;
 }
 
@@ -214,13 +240,13 @@ int launch_pass2(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, 
 int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *bm,
                 const uint32_t *bmt, uint16_t *wpre, uint16_t *wpret, int32_t *row_ptr, int32_t *col_ptr,
                 const uint32_t *omega1, const float *val1, const uint32_t *omega2, const float *val2,
-                const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, int32_t *csc_col,
-                float *csc_val);
+                const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, float *csc_val,
+                const EllView &ell);
 int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
                const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
-               const int32_t *col_ptr, const int32_t *csc_row, const int32_t *csc_col, const float *csc_val,
-               float *resid, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale,
-               int32_t *stats);
+               const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, const EllView &ell, float *X,
+               float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt, float *red, double *e2col,
+               float *scale, int32_t *stats);
 int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,
                   const float *X, const float *Y, const float *scale, float *radiance);
 int launch_eval_pairs(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,

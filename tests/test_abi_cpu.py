@@ -74,6 +74,41 @@ def test_plan_layout_and_counts():
     lib.vplmc_plan_destroy(h)
 
 
+def test_public_region_sizes_follow_their_definitions():
+    """Every public region's byte count, from the slice shapes alone, and no
+    two regions overlap."""
+    lib = N.load()
+    pt, cl, rank, nc = [0, 256, 600, 1000], [0, 1024, 1324, 2024], [8, 16, 4], 777
+    rc, h = plan(pt, cl, rank, nc=nc)
+    assert rc == 0
+    infos = []
+    for s in range(3):
+        info = N.SliceInfo()
+        assert lib.vplmc_plan_slice(h, s, ctypes.byref(info)) == 0
+        infos.append(info)
+    m = np.diff(pt)
+    n = np.diff(cl)
+    q = np.asarray(rank)
+    N1 = sum(i.N1 for i in infos)
+    N2 = sum(i.N2 for i in infos)
+    want = {"LIGHTS": 9 * nc * 4, "REP": nc * 4, "BBOX": 6 * nc * 4, "OMEGA1": N1 * 4, "VAL1": 3 * N1 * 4,
+            "OMEGA2": N2 * 4, "VAL2": 3 * N2 * 4, "WEIGHTS": n.sum() * 4, "COLMIN": n.sum() * 4,
+            "COLMAX": n.sum() * 4, "COLCNT": n.sum() * 4, "ROW_PTR": (m + 1).sum() * 4,
+            "CSR_COL": (N1 + N2) * 4, "CSR_VAL": 3 * (N1 + N2) * 4, "COL_PTR": (n + 1).sum() * 4,
+            "CSC_ROW": (N1 + N2) * 4, "CSC_VAL": 3 * (N1 + N2) * 4, "X": (m * q).sum() * 4,
+            "Y": (3 * n * q).sum() * 4, "SLICE_SCALE": 3 * 4, "FEATURES": n.sum() * 12 * 4, "LOGITS": n.sum() * 4}
+    assert set(want) == set(N.REGIONS)
+    spans = []
+    off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+    for name, r in N.R.items():
+        assert lib.vplmc_plan_region(h, r, ctypes.byref(off), ctypes.byref(nb)) == 0
+        assert nb.value == want[name], name
+        spans.append((off.value, off.value + nb.value))
+    spans.sort()
+    assert all(a[1] <= b[0] for a, b in zip(spans, spans[1:]))
+    lib.vplmc_plan_destroy(h)
+
+
 @pytest.mark.parametrize("args,code,needle", [
     (([0, 0], [0, 8], [4]), N.EINVAL, "rows"),
     (([0, 70000], [0, 8], [4]), N.EINVAL, "rows"),
