@@ -209,7 +209,7 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     plan->pass2_ppm = params->pass2_ppm;
     plan->desc.resize(n_slices);
     int64_t o1 = 0, o2 = 0, oo = 0, oc = 0, orow = 0, ocp = 0, ox = 0, oy = 0, obm = 0, obmt = 0, summ = 0;
-    int64_t ogrp = 0, oell = 0, nell = 0;
+    int64_t ogrp = 0, oell = 0, nell = 0, opart = 0;
     for (int s = 0; s < n_slices; ++s) {
         const int64_t m = (int64_t)pt_offsets[s + 1] - pt_offsets[s];
         const int64_t n = (int64_t)cl_offsets[s + 1] - cl_offsets[s];
@@ -259,10 +259,14 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         d.off_grp = (int32_t)ogrp;
         d.off_ell = oell;
         d.off_red = (int64_t)s * ADM_RED_FLOATS;
-        ogrp += (n + 63) / 64 + 1;
+        d.off_part = opart;
         if (in_lds) {
-            // the columns' padded lengths sum to at most |Omega| + 64 m (counts sorted descending)
-            oell += N1 + N2 + 64 * m;
+            // parts: sum_j max(1, ceil(c_j / LMAX)) <= n + |Omega| / LMAX; the padded
+            // lengths sum to at most |Omega| + 64 LMAX (lengths sorted descending)
+            const int64_t parts = n + (N1 + N2) / ELL_LMAX + 1;
+            opart += parts;
+            ogrp += (parts + 63) / 64 + 1;
+            oell += N1 + N2 + 64 * ELL_LMAX;
             ++nell;
         }
         o1 += N1;
@@ -291,6 +295,7 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     plan->tot_bm = obm;
     plan->tot_bmt = obmt;
     plan->tot_grp = ogrp;
+    plan->tot_part = opart;
     plan->tot_ell = oell;
     plan->n_ell = nell;
     if (ogrp > INT32_MAX) {
@@ -341,15 +346,19 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     bytes[R_COLSUMSQ] = oc * 8;
     bytes[R_COLZERO] = oc * 4;
     bytes[R_SLICE_GEO] = S * 8 * 4;
-    bytes[R_ELL_PERM] = oc * 4;
-    bytes[R_ELL_POS] = oc * 4;
+    bytes[R_ELL_PART] = plan->tot_part * 4;
+    bytes[R_ELL_PPOS] = plan->tot_part * 4;
+    bytes[R_ELL_PBASE] = ocp * 4;
+    bytes[R_ELL_PARTIAL] = plan->tot_part * 48 * 4;
     bytes[R_ELL_GRP] = plan->tot_grp * 4;
+    bytes[R_ELL_SPLIT] = oc * 4;
+    bytes[R_ELL_NSPLIT] = S * 4;
     bytes[R_ELL_ROW] = plan->tot_ell * 4;
     bytes[R_ELL_VAL] = 3 * plan->tot_ell * 4;
     bytes[R_ELL_RES] = 3 * plan->tot_ell * 4;
     bytes[R_YT] = oy * 4;
     bytes[R_ADM_RED] = S * ADM_RED_FLOATS * 4;
-    bytes[R_E2COL] = oc * 8;
+    bytes[R_E2PART] = plan->tot_part * 8;
     bytes[VPLMC_R_FEATURES] = oc * MLP_IN * 4;
     bytes[VPLMC_R_LOGITS] = oc * 4;
     size_t off = 0;
@@ -510,9 +519,13 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     int32_t *csr_col = region<int32_t>(ws, plan, VPLMC_R_CSR_COL);
     float *csr_val = region<float>(ws, plan, VPLMC_R_CSR_VAL);
     EllView ell;
-    ell.perm = region<int32_t>(ws, plan, R_ELL_PERM);
-    ell.pos = region<int32_t>(ws, plan, R_ELL_POS);
+    ell.part = region<int32_t>(ws, plan, R_ELL_PART);
+    ell.ppos = region<int32_t>(ws, plan, R_ELL_PPOS);
+    ell.pbase = region<int32_t>(ws, plan, R_ELL_PBASE);
+    ell.partial = region<float>(ws, plan, R_ELL_PARTIAL);
     ell.grp = region<int32_t>(ws, plan, R_ELL_GRP);
+    ell.split = region<int32_t>(ws, plan, R_ELL_SPLIT);
+    ell.nsplit = region<int32_t>(ws, plan, R_ELL_NSPLIT);
     ell.row = plan->tot_ell > 0 ? region<int32_t>(ws, plan, R_ELL_ROW) : nullptr;
     ell.val = region<float>(ws, plan, R_ELL_VAL);
     ell.res = region<float>(ws, plan, R_ELL_RES);
@@ -528,7 +541,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
                          region<float>(ws, plan, R_XNEXT), region<float>(ws, plan, R_XP),
                          region<float>(ws, plan, R_LAMBDA), Y, region<float>(ws, plan, R_YP),
                          region<float>(ws, plan, R_PI), region<float>(ws, plan, R_YT),
-                         region<float>(ws, plan, R_ADM_RED), region<double>(ws, plan, R_E2COL), scale, stats)))
+                         region<float>(ws, plan, R_ADM_RED), region<double>(ws, plan, R_E2PART), scale, stats)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_REDUCE))) return rc;
     if ((rc = launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, radiance))) return rc;

@@ -473,9 +473,10 @@ __global__ __launch_bounds__(THREADS) void k_adm(
 // ---------------------------------------------------------------------------
 // LDS-resident variant for ranks 4, 8, 16 (m (q + 1) words of X_k and one
 // more buffer in LDS).  The samples are read from the slice's ELL copy, in
-// which one lane walks one column and every load of a wavefront covers 64
-// consecutive entries.
-//   phase A, lane = column j: Y_j (3q floats) in registers, X_i from LDS;
+// which one lane walks one part of a column (at most ELL_LMAX samples; the
+// parts of a 64-lane group have nearly equal lengths) and every load of a
+// wavefront covers 64 consecutive entries.
+//   phase A, lane = part of column j: Y_j (3q floats) in registers, X_i from LDS;
 //     the residual r is stored in the ELL copy and the q components of
 //     sum_c r_c Y_j^c, times 2^S and rounded, are added into row i of a
 //     fixed-point R Y^T accumulator with integer LDS atomics (LDS float
@@ -485,14 +486,17 @@ __global__ __launch_bounds__(THREADS) void k_adm(
 //     largest sum_c |r_c| (a bound of the first iterate, then twice the
 //     previous iterate's); if the iterate's own rs breaks the bound the
 //     phase is run again with the smaller scale, so no sum overflows.
-//   X update: T = R Y^T + a U - L, then X+ = X (GY Inv) + T Inv as FP64
-//     16 x 16 x 4 MFMA products per 16 rows (FP32 operands widened, the
-//     FP64 factors of the q x q solve, one rounding to FP32), with U, L and
-//     the FP32 MFMA Grams X+^T X+ and X+^T X on the rounded rows.
-//   phase B, lane = column j: X+^T R_j from the stored residuals and X+
-//     (LDS), then T_j = X+^T R_j + b V_j - P_j (global staging).
-//   Y update: Y+ = Y (Inv C)^T + T Inv as FP64 MFMA products per 16 rows of
+//   X update: T = R Y^T + a U - L, then X+ = X (GY Inv) + T Inv as FP32
+//     16 x 16 x 4 MFMA products per 16 rows (the FP64 factors of the q x q
+//     solve rounded to FP32), with U, L and the Grams X+^T X+ and X+^T X
+//     fused on the product's output registers.
+//   phase B, lane = part of column j: X+^T R over the part from the stored
+//     residuals and X+ (LDS); T_j = X+^T R_j + b V_j - P_j (global staging),
+//     the partial sums of a column of several parts added in part order.
+//   Y update: Y+ = Y (Inv C)^T + T Inv as FP32 MFMA products per 16 rows of
 //     the 3n x q matrix, with V, P and the Gram Y+^T Y+.
+// Rows of X in LDS keep their 4-float chunks rotated (xpos), which spreads the
+// 128-bit reads of a wavefront over the banks.
 // Per-wavefront partial Grams are summed in a fixed order through the
 // slice's global scratch.  The run is reproducible bit for bit.
 
@@ -503,12 +507,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // register v of lane l of the result holds D[4 (l / 16) + v][l % 16].
 __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-// The FP64 form (v_mfma_f64_16x16x4_f64) takes its operands in the same
-// lanes, but register v of lane l of its result holds D[l / 16 + 4 v][l % 16].
-typedef double d4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ d4 mfma16d(double a, double b, d4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -554,8 +552,24 @@ __device__ void sum_partials(const f4 &p0, const f4 &p1, float *red, float *out0
     __syncthreads();
 }
 
-// elements per thread of the fixed-point to float pass (m q <= ADM_CVT_MAX * threads)
-constexpr int ADM_CVT_MAX = 18;
+// Word of X(i, k) in an LDS buffer of X: row i at i q, its 4-float chunks
+// rotated by (i q) / 64, so that the 128-bit row reads of a wavefront (lanes
+// with unrelated rows, same chunk) start on all 16 bank quadruples.
+template <int Q>
+__device__ __forceinline__ int xpos(int i, int k) {
+    return i * Q + ((((k >> 2) + ((i * Q) >> 6)) % (Q / 4)) << 2) + (k & 3);
+}
+// the 16-byte chunk c of row i
+template <int Q>
+__device__ __forceinline__ const float4 *xchunk(const float *X, int i, int c) {
+    return reinterpret_cast<const float4 *>(X + i * Q + (((c + ((i * Q) >> 6)) % (Q / 4)) << 2));
+}
+
+// elements of the fixed-point to float pass (m q <= ADM_CVT_ELEMS)
+constexpr int ADM_CVT_ELEMS = 18 * 1024;
+// ELL entries a lane loads at once in phase A and in phase B
+constexpr int ADM_DA = 4;
+constexpr int ADM_DB = 8;
 
 template <int Q, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_adm_ell(
@@ -563,7 +577,7 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
     int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma, const int32_t *__restrict__ col_ptr_all,
     const int32_t *__restrict__ csc_row_all, const float *__restrict__ csc_val_all, EllView ell, float *X_all,
     float *Xp_all, float *Lam_all, float *Y_all, float *Yp_all, float *Pi_all, float *Yt_all, float *red_all,
-    double *e2col_all, float *scale_all, int32_t *stats_all) {
+    double *e2part_all, float *scale_all, int32_t *stats_all) {
     static_assert(Q % 4 == 0 && Q <= 16, "ranks 4, 8, 16");
     constexpr int NW = THREADS / WAVE;
     constexpr int QV = Q / 4;                         // MFMA steps over the rank
@@ -582,8 +596,10 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
     const int32_t *col_ptr = col_ptr_all + d.off_colptr;
     const int32_t *csc_row = csc_row_all + d.off_omega;
     const float *csc_val = csc_val_all + 3 * d.off_omega;
-    const int32_t *perm = ell.perm + d.off_col;
+    const int32_t *part = ell.part + d.off_part;
+    const int32_t *pbase = ell.pbase + d.off_colptr;
     const int32_t *grp = ell.grp + d.off_grp;
+    float *partial = ell.partial + 48 * d.off_part;
     const int32_t *erow = ell.row + d.off_ell;
     const float *eval = ell.val + 3 * d.off_ell;
     float *eres = ell.res + 3 * d.off_ell;
@@ -595,10 +611,11 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
     float *Pi = Pi_all + d.off_y;
     float *Yt = Yt_all + d.off_y;
     float *red = red_all + d.off_red;
-    double *e2col = e2col_all + d.off_col;
+    double *e2part = e2part_all + d.off_part;
     int32_t *st = stats_all + 4 * s;
     const int nnz = col_ptr[n];
-    const int G = (n + 63) / 64;
+    const int P = pbase[n];               // parts
+    const int G = (P + 63) / 64;          // groups of 64 parts
     const int R3 = 3 * n;
 
     // ---- scale s0 = mean sampled value; ||P_Omega M|| ----
@@ -643,7 +660,7 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
         const int i = e / Q, k = e % Q;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
         const float v = __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq);
-        XA[e] = v;
+        XA[xpos<Q>(i, k)] = v;
         Xp[e] = v;
         Lam[e] = 0.f;
     }
@@ -721,21 +738,34 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
     const float alpha_f = (float)alpha, beta_f = (float)beta;
     const float ga = (float)((double)gamma * alpha), gb = (float)((double)gamma * beta);
     const float inv_alpha = (float)(1.0 / alpha), inv_beta = (float)(1.0 / beta);
-    // lane's column in group g: sorted position 64 g + lane
-    auto column = [&](int g, int &j, int &cnt) {
+    // lane's part in group g (sorted position 64 g + lane): column j, part u,
+    // its length cnt, its number pc in column order and the column's part count np
+    auto part_of = [&](int g, int &j, int &cnt, int &pc, int &np) {
         const int sp = 64 * g + lane;
-        j = sp < n ? perm[sp] : 0;
-        cnt = sp < n ? col_ptr[j + 1] - col_ptr[j] : 0;
+        j = 0;
+        cnt = 0;
+        pc = 0;
+        np = 1;
+        if (sp < P) {
+            const int v = part[sp];
+            j = v & 0xFFFF;
+            const int u = v >> 16;
+            const int c = col_ptr[j + 1] - col_ptr[j];
+            np = c > ELL_LMAX ? (c + ELL_LMAX - 1) / ELL_LMAX : 1;
+            const int l = (c + np - 1) / np;
+            cnt = min(l, c - u * l);
+            pc = pbase[j] + u;
+        }
     };
     // right-hand operands of the dense updates: F[l][k] and Inv[l][k] (FP64),
     // zero outside q x q; lane holds row 4 v + lane / 16, column lane % 16
-    auto load_rhs = [&](double *b1, double *b2) {
+    auto load_rhs = [&](float *b1, float *b2) {
         const int c = lane % 16;
 #pragma unroll
         for (int v = 0; v < QV; ++v) {
             const int l = 4 * v + lane / 16;
-            b1[v] = c < Q ? sh.F[l * Q + c] : 0.0;
-            b2[v] = c < Q ? sh.Inv[l * Q + c] : 0.0;
+            b1[v] = c < Q ? (float)sh.F[l * Q + c] : 0.f;
+            b2[v] = c < Q ? (float)sh.Inv[l * Q + c] : 0.f;
         }
     };
 
@@ -754,8 +784,8 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
             __syncthreads();
             float rsm = 0.f;
             for (int g = wave; g < G; g += NW) {
-                int j, cnt;
-                column(g, j, cnt);
+                int j, cnt, pc, np;
+                part_of(g, j, cnt, pc, np);
                 const int base = grp[g];
                 const int len = (grp[g + 1] - base) >> 6;
                 double e2 = 0.0;
@@ -769,71 +799,63 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
                     y[4 * v + 2] = a.z;
                     y[4 * v + 3] = a.w;
                 }
-                int i = 0;
-                float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-                if (cnt > 0) {
-                    const int e = base + lane;
-                    i = erow[e];
-                    m0 = eval[3 * e] * inv_s0;
-                    m1 = eval[3 * e + 1] * inv_s0;
-                    m2 = eval[3 * e + 2] * inv_s0;
-                }
-                for (int k = 0; k < len; ++k) {
-                    const bool act = k < cnt;
-                    int in = 0;
-                    float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-                    if (k + 1 < cnt) {
-                        const int e = base + 64 * (k + 1) + lane;
-                        in = erow[e];
-                        n0 = eval[3 * e] * inv_s0;
-                        n1 = eval[3 * e + 1] * inv_s0;
-                        n2 = eval[3 * e + 2] * inv_s0;
+                for (int k0 = 0; k0 < len; k0 += ADM_DA) {
+                    int ib[ADM_DA];
+                    float mb0[ADM_DA], mb1[ADM_DA], mb2[ADM_DA];
+#pragma unroll
+                    for (int u = 0; u < ADM_DA; ++u) {
+                        const bool act = k0 + u < cnt;
+                        const int e = base + 64 * (k0 + u) + lane;
+                        ib[u] = act ? erow[e] : -1;
+                        mb0[u] = act ? eval[3 * e] * inv_s0 : 0.f;
+                        mb1[u] = act ? eval[3 * e + 1] * inv_s0 : 0.f;
+                        mb2[u] = act ? eval[3 * e + 2] * inv_s0 : 0.f;
                     }
-                    if (act) {
-                        float x[Q];
-                        const float4 *x4 = reinterpret_cast<const float4 *>(XA + i * Q);
 #pragma unroll
-                        for (int v = 0; v < QV; ++v) {
-                            const float4 a = x4[v];
-                            x[4 * v] = a.x;
-                            x[4 * v + 1] = a.y;
-                            x[4 * v + 2] = a.z;
-                            x[4 * v + 3] = a.w;
+                    for (int u = 0; u < ADM_DA; ++u) {
+                        const int i = ib[u];
+                        if (i >= 0) {
+                            float x[Q];
+#pragma unroll
+                            for (int v = 0; v < QV; ++v) {
+                                const float4 a4 = *xchunk<Q>(XA, i, v);
+                                x[4 * v] = a4.x;
+                                x[4 * v + 1] = a4.y;
+                                x[4 * v + 2] = a4.z;
+                                x[4 * v + 3] = a4.w;
+                            }
+                            float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+#pragma unroll
+                            for (int kk = 0; kk < Q; ++kk) {
+                                d0 = fmaf(x[kk], y[kk], d0);
+                                d1 = fmaf(x[kk], y[Q + kk], d1);
+                                d2 = fmaf(x[kk], y[2 * Q + kk], d2);
+                            }
+                            const float r0 = mb0[u] - d0, r1 = mb1[u] - d1, r2 = mb2[u] - d2;
+                            e2 += (double)(r0 * r0) + (double)(r1 * r1) + (double)(r2 * r2);
+                            const int e = base + 64 * (k0 + u) + lane;
+                            eres[3 * e] = r0;
+                            eres[3 * e + 1] = r1;
+                            eres[3 * e + 2] = r2;
+                            const float rsa = fabsf(r0) + fabsf(r1) + fabsf(r2);
+                            rsm = fmaxf(rsm, rsa);
+                            const float s0r = r0 * fxs, s1r = r1 * fxs, s2r = r2 * fxs;
+                            int32_t *row = RXI + i * (Q + 1);
+#pragma unroll
+                            for (int kk = 0; kk < Q; ++kk)
+                                atomicAdd(row + kk,
+                                          __float2int_rn(fmaf(s0r, y[kk], fmaf(s1r, y[Q + kk], s2r * y[2 * Q + kk]))));
+                            atomicAdd(reinterpret_cast<uint32_t *>(row + Q), __float2uint_ru(rsa * fxr));
                         }
-                        float d0 = 0.f, d1 = 0.f, d2 = 0.f;
-#pragma unroll
-                        for (int kk = 0; kk < Q; ++kk) {
-                            d0 = fmaf(x[kk], y[kk], d0);
-                            d1 = fmaf(x[kk], y[Q + kk], d1);
-                            d2 = fmaf(x[kk], y[2 * Q + kk], d2);
-                        }
-                        const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
-                        e2 += (double)(r0 * r0) + (double)(r1 * r1) + (double)(r2 * r2);
-                        const int e = base + 64 * k + lane;
-                        eres[3 * e] = r0;
-                        eres[3 * e + 1] = r1;
-                        eres[3 * e + 2] = r2;
-                        const float rsa = fabsf(r0) + fabsf(r1) + fabsf(r2);
-                        rsm = fmaxf(rsm, rsa);
-                        const float s0r = r0 * fxs, s1r = r1 * fxs, s2r = r2 * fxs;
-                        int32_t *row = RXI + i * (Q + 1);
-#pragma unroll
-                        for (int kk = 0; kk < Q; ++kk)
-                            atomicAdd(row + kk, __float2int_rn(fmaf(s0r, y[kk], fmaf(s1r, y[Q + kk], s2r * y[2 * Q + kk]))));
-                        atomicAdd(reinterpret_cast<uint32_t *>(row + Q), __float2uint_ru(rsa * fxr));
                     }
-                    i = in;
-                    m0 = n0;
-                    m1 = n1;
-                    m2 = n2;
                 }
-                if (64 * g + lane < n) e2col[j] = e2;
+                if (64 * g + lane < P) e2part[pc] = e2;
             }
-            // sum of the columns' squared residuals in column order
+            // sum of the parts' squared residuals in column order
             __threadfence_block();
             __syncthreads();
             double e2 = 0.0;
-            for (int j = t; j < n; j += THREADS) e2 += e2col[j];
+            for (int u = t; u < P; u += THREADS) e2 += e2part[u];
             uint32_t rsw = 0;
             for (int i = t; i < m; i += THREADS) rsw = max(rsw, reinterpret_cast<const uint32_t *>(RXI)[i * (Q + 1) + Q]);
             e2 = wave_sum_d(e2);
@@ -879,9 +901,10 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
         // ---- T = 2^-S RX + a U - L into XB (row stride q) ----
         {
             const float ifx = ldexpf(1.f, -S);
-            float tv[ADM_CVT_MAX];
+            constexpr int CVT = ADM_CVT_ELEMS / THREADS;   // per thread
+            float tv[CVT];
 #pragma unroll
-            for (int u = 0; u < ADM_CVT_MAX; ++u) {
+            for (int u = 0; u < CVT; ++u) {
                 const int e = t + u * THREADS;
                 tv[u] = 0.f;
                 if (e < m * Q) {
@@ -891,9 +914,9 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
             }
             __syncthreads();
 #pragma unroll
-            for (int u = 0; u < ADM_CVT_MAX; ++u) {
+            for (int u = 0; u < CVT; ++u) {
                 const int e = t + u * THREADS;
-                if (e < m * Q) XB[e] = tv[u];
+                if (e < m * Q) XB[xpos<Q>(e / Q, e % Q)] = tv[u];
             }
         }
         // ---- X system: Inv = (GY + a I)^-1, F = GY Inv ----
@@ -907,33 +930,33 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
         __syncthreads();
         // ---- X+ = X F + T Inv (FP64 MFMA), U, L, Grams X+^T X+ and X+^T X ----
         {
-            double b1[QV], b2[QV];
+            float b1[QV], b2[QV];
             load_rhs(b1, b2);
             f4 gx = {0.f, 0.f, 0.f, 0.f}, cx = {0.f, 0.f, 0.f, 0.f};
             for (int r0 = 16 * wave; r0 < m; r0 += 16 * NW) {
                 const int ra = r0 + lane % 16;
-                d4 D = {0.0, 0.0, 0.0, 0.0};
+                f4 D = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int v = 0; v < QV; ++v) {
                     const int kk = 4 * v + lane / 16;
-                    const double a1 = ra < m ? (double)XA[ra * Q + kk] : 0.0;
-                    const double a2 = ra < m ? (double)XB[ra * Q + kk] : 0.0;
-                    D = mfma16d(a1, b1[v], D);
-                    D = mfma16d(a2, b2[v], D);
+                    const float a1 = ra < m ? XA[xpos<Q>(ra, kk)] : 0.f;
+                    const float a2 = ra < m ? XB[xpos<Q>(ra, kk)] : 0.f;
+                    D = mfma16(a1, b1[v], D);
+                    D = mfma16(a2, b2[v], D);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int r = r0 + lane / 16 + 4 * v, c = lane % 16;   // FP64 result layout
+                    const int r = r0 + 4 * (lane / 16) + v, c = lane % 16;   // FP32 result layout
                     const bool ok = r < m && c < Q;
-                    const float xn = ok ? (float)D[v] : 0.f;
-                    const float xk = ok ? XA[r * Q + c] : 0.f;
+                    const float xn = ok ? D[v] : 0.f;
+                    const float xk = ok ? XA[xpos<Q>(r, c)] : 0.f;
                     if (ok) {
                         const int e = r * Q + c;
                         const float lam = Lam[e];
                         const float u = fmaxf(0.f, xn + lam * inv_alpha);
                         Xp[e] = u;
                         Lam[e] = lam + ga * (xn - u);
-                        XB[e] = xn;
+                        XB[xpos<Q>(r, c)] = xn;
                     }
                     gx = mfma16(xn, xn, gx);
                     cx = mfma16(xn, xk, cx);
@@ -950,94 +973,117 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
             sh.F[b * Q + a] = v;
         }
         __syncthreads();
-        // ---- phase B: T_j = X+^T R_j + b V_j - P_j ----
+        // ---- phase B: T_j = X+^T R_j + b V_j - P_j (columns of several parts: partial sums) ----
         for (int g = wave; g < G; g += NW) {
-            int j, cnt;
-            column(g, j, cnt);
+            int j, cnt, pc, np;
+            part_of(g, j, cnt, pc, np);
             const int base = grp[g];
             const int len = (grp[g + 1] - base) >> 6;
             float acc[3 * Q];
 #pragma unroll
             for (int kk = 0; kk < 3 * Q; ++kk) acc[kk] = 0.f;
-            int i = 0;
-            float r0 = 0.f, r1 = 0.f, r2 = 0.f;
-            if (cnt > 0) {
-                const int e = base + lane;
-                i = erow[e];
-                r0 = eres[3 * e];
-                r1 = eres[3 * e + 1];
-                r2 = eres[3 * e + 2];
-            }
-            for (int k = 0; k < len; ++k) {
-                const bool act = k < cnt;
-                int in = 0;
-                float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-                if (k + 1 < cnt) {
-                    const int e = base + 64 * (k + 1) + lane;
-                    in = erow[e];
-                    n0 = eres[3 * e];
-                    n1 = eres[3 * e + 1];
-                    n2 = eres[3 * e + 2];
+            // the part's entries are loaded ADM_DB at a time, all in flight together
+            for (int k0 = 0; k0 < len; k0 += ADM_DB) {
+                int ib[ADM_DB];
+                float rb0[ADM_DB], rb1[ADM_DB], rb2[ADM_DB];
+#pragma unroll
+                for (int u = 0; u < ADM_DB; ++u) {
+                    const bool act = k0 + u < cnt;
+                    const int e = base + 64 * (k0 + u) + lane;
+                    ib[u] = act ? erow[e] : -1;
+                    rb0[u] = act ? eres[3 * e] : 0.f;
+                    rb1[u] = act ? eres[3 * e + 1] : 0.f;
+                    rb2[u] = act ? eres[3 * e + 2] : 0.f;
                 }
-                if (act) {
-                    const float4 *x4 = reinterpret_cast<const float4 *>(XB + i * Q);
 #pragma unroll
-                    for (int v = 0; v < QV; ++v) {
-                        const float4 a = x4[v];
-                        const float xs[4] = {a.x, a.y, a.z, a.w};
+                for (int u = 0; u < ADM_DB; ++u) {
+                    if (ib[u] >= 0) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            acc[4 * v + u] = fmaf(r0, xs[u], acc[4 * v + u]);
-                            acc[Q + 4 * v + u] = fmaf(r1, xs[u], acc[Q + 4 * v + u]);
-                            acc[2 * Q + 4 * v + u] = fmaf(r2, xs[u], acc[2 * Q + 4 * v + u]);
+                        for (int v = 0; v < QV; ++v) {
+                            const float4 a = *xchunk<Q>(XB, ib[u], v);
+                            const float xs[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+                            for (int w = 0; w < 4; ++w) {
+                                acc[4 * v + w] = fmaf(rb0[u], xs[w], acc[4 * v + w]);
+                                acc[Q + 4 * v + w] = fmaf(rb1[u], xs[w], acc[Q + 4 * v + w]);
+                                acc[2 * Q + 4 * v + w] = fmaf(rb2[u], xs[w], acc[2 * Q + 4 * v + w]);
+                            }
                         }
                     }
                 }
-                i = in;
-                r0 = n0;
-                r1 = n1;
-                r2 = n2;
             }
-            if (64 * g + lane < n) {
-                const size_t o = (size_t)j * 3 * Q;
+            if (64 * g + lane < P) {
+                if (np == 1) {
+                    const size_t o = (size_t)j * 3 * Q;
 #pragma unroll
-                for (int v = 0; v < 3 * Q / 4; ++v) {
-                    const float4 yp = reinterpret_cast<const float4 *>(Yp + o)[v];
-                    const float4 pi = reinterpret_cast<const float4 *>(Pi + o)[v];
-                    float4 tt;
-                    tt.x = acc[4 * v] + (beta_f * yp.x - pi.x);
-                    tt.y = acc[4 * v + 1] + (beta_f * yp.y - pi.y);
-                    tt.z = acc[4 * v + 2] + (beta_f * yp.z - pi.z);
-                    tt.w = acc[4 * v + 3] + (beta_f * yp.w - pi.w);
-                    reinterpret_cast<float4 *>(Yt + o)[v] = tt;
+                    for (int v = 0; v < 3 * Q / 4; ++v) {
+                        const float4 yp = reinterpret_cast<const float4 *>(Yp + o)[v];
+                        const float4 pi = reinterpret_cast<const float4 *>(Pi + o)[v];
+                        float4 tt;
+                        tt.x = acc[4 * v] + (beta_f * yp.x - pi.x);
+                        tt.y = acc[4 * v + 1] + (beta_f * yp.y - pi.y);
+                        tt.z = acc[4 * v + 2] + (beta_f * yp.z - pi.z);
+                        tt.w = acc[4 * v + 3] + (beta_f * yp.w - pi.w);
+                        reinterpret_cast<float4 *>(Yt + o)[v] = tt;
+                    }
+                } else {
+                    float4 *pp = reinterpret_cast<float4 *>(partial + (size_t)pc * 3 * Q);
+#pragma unroll
+                    for (int v = 0; v < 3 * Q / 4; ++v)
+                        pp[v] = make_float4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
                 }
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+        // columns of several parts: sum their partials in part order
+        const int nsplit = ell.nsplit[s];
+        for (int e = t; e < nsplit * (3 * Q / 4); e += THREADS) {
+            const int j = ell.split[d.off_col + e / (3 * Q / 4)], v = e % (3 * Q / 4);
+            const int p0 = pbase[j], p1 = pbase[j + 1];
+            {
+                float4 a = reinterpret_cast<const float4 *>(partial + (size_t)p0 * 3 * Q)[v];
+                for (int u = p0 + 1; u < p1; ++u) {
+                    const float4 b = reinterpret_cast<const float4 *>(partial + (size_t)u * 3 * Q)[v];
+                    a.x += b.x;
+                    a.y += b.y;
+                    a.z += b.z;
+                    a.w += b.w;
+                }
+                const size_t o = (size_t)j * 3 * Q;
+                const float4 yp = reinterpret_cast<const float4 *>(Yp + o)[v];
+                const float4 pi = reinterpret_cast<const float4 *>(Pi + o)[v];
+                float4 tt;
+                tt.x = a.x + (beta_f * yp.x - pi.x);
+                tt.y = a.y + (beta_f * yp.y - pi.y);
+                tt.z = a.z + (beta_f * yp.z - pi.z);
+                tt.w = a.w + (beta_f * yp.w - pi.w);
+                reinterpret_cast<float4 *>(Yt + o)[v] = tt;
             }
         }
         __threadfence_block();
         __syncthreads();
         // ---- Y+ = Y F + T Inv (FP64 MFMA) over the 3n rows, V, P, Gram Y+^T Y+ ----
         {
-            double b1[QV], b2[QV];
+            float b1[QV], b2[QV];
             load_rhs(b1, b2);
             f4 gy = {0.f, 0.f, 0.f, 0.f};
             const f4 zero = {0.f, 0.f, 0.f, 0.f};
             float ymx = 0.f;
             for (int r0 = 16 * wave; r0 < R3; r0 += 16 * NW) {
                 const int ra = r0 + lane % 16;
-                d4 D = {0.0, 0.0, 0.0, 0.0};
+                f4 D = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int v = 0; v < QV; ++v) {
                     const int kk = 4 * v + lane / 16;
-                    const double a1 = ra < R3 ? (double)Y[(size_t)ra * Q + kk] : 0.0;
-                    const double a2 = ra < R3 ? (double)Yt[(size_t)ra * Q + kk] : 0.0;
-                    D = mfma16d(a1, b1[v], D);
-                    D = mfma16d(a2, b2[v], D);
+                    D = mfma16(ra < R3 ? Y[(size_t)ra * Q + kk] : 0.f, b1[v], D);
+                    D = mfma16(ra < R3 ? Yt[(size_t)ra * Q + kk] : 0.f, b2[v], D);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int r = r0 + lane / 16 + 4 * v, c = lane % 16;   // FP64 result layout
+                    const int r = r0 + 4 * (lane / 16) + v, c = lane % 16;   // FP32 result layout
                     const bool ok = r < R3 && c < Q;
-                    const float yn = ok ? (float)D[v] : 0.f;
+                    const float yn = ok ? D[v] : 0.f;
                     if (ok) {
                         const size_t e = (size_t)r * Q + c;
                         const float pi = Pi[e];
@@ -1058,7 +1104,7 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
         XA = XB;
         XB = tmp;
     }
-    for (int e = t; e < m * Q; e += THREADS) Xg[e] = XA[e];
+    for (int e = t; e < m * Q; e += THREADS) Xg[e] = XA[xpos<Q>(e / Q, e % Q)];
     if (t == 0) {
         st[0] = iters;
         if (!fixed_iters && iters >= max_iter) st[1] |= VPLMC_SLICE_NOT_CONVERGED;
@@ -1130,7 +1176,7 @@ template <int Q>
 int launch_adm_ell(hipStream_t st, size_t count, int max_m, const int32_t *ids_dev, const SliceDesc *desc,
                    const vplmc_params &prm, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
                    const EllView &ell, float *X, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt,
-                   float *red, double *e2col, float *scale, int32_t *stats) {
+                   float *red, double *e2part, float *scale, int32_t *stats) {
     if (count == 0) return VPLMC_OK;
     constexpr int T = adm_lds_threads(Q);
     const size_t dyn = adm_lds_dynamic_bytes(Q, max_m);
@@ -1139,7 +1185,7 @@ int launch_adm_ell(hipStream_t st, size_t count, int max_m, const int32_t *ids_d
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     hipLaunchKernelGGL(kern, dim3((unsigned)count), dim3(T), dyn, st, desc, ids_dev, prm.seed, prm.max_iter,
                        (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0, prm.gamma, col_ptr,
-                       csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2col, scale, stats);
+                       csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale, stats);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
@@ -1149,7 +1195,7 @@ int launch_adm_ell(hipStream_t st, size_t count, int max_m, const int32_t *ids_d
 int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
                const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
                const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, const EllView &ell, float *X,
-               float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt, float *red, double *e2col,
+               float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt, float *red, double *e2part,
                float *scale, int32_t *stats) {
     // ids_dev holds the slice ids of groups 0..7 in order (2 * rank bucket + variant)
     size_t base[9] = {0};
@@ -1159,7 +1205,7 @@ int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, co
     int rc;
 #define VPLMC_ADM_PAIR(B, Q, TG)                                                                                   \
     if ((rc = launch_adm_ell<Q>(st, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], desc, prm,       \
-                                col_ptr, csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2col, scale,       \
+                                col_ptr, csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale,      \
                                 stats)))                                                                           \
         return rc;                                                                                                 \
     if ((rc = launch_adm_global<Q, TG>(st, plan.groups[2 * B + 1].size(), id[2 * B + 1], desc, prm, row_ptr,      \

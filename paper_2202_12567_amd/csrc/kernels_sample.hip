@@ -466,6 +466,13 @@ __global__ __launch_bounds__(256) void k_ptrscan(const SliceDesc *__restrict__ d
 }
 
 // Scatter one pass's samples to their CSR and CSC positions.
+// parts of a column with c samples: p = max(1, ceil(c / ELL_LMAX)) of
+// l = ceil(c / p) samples, the last one c - (p - 1) l
+__device__ __forceinline__ void part_shape(int c, int &p, int &l) {
+    p = c > ELL_LMAX ? (c + ELL_LMAX - 1) / ELL_LMAX : 1;
+    l = (c + p - 1) / p;
+}
+
 __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t total, int which,
                           const int32_t *__restrict__ stats, const uint32_t *__restrict__ keys,
                           const float *__restrict__ vals, const uint32_t *__restrict__ bm,
@@ -498,9 +505,13 @@ __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t tot
     csc_val[3 * (o + pc) + 1] = v1;
     csc_val[3 * (o + pc) + 2] = v2;
     if (ell.row && d.ell) {
-        const int64_t k2 = pc - col_ptr[d.off_colptr + j];
-        const int32_t sp = ell.pos[d.off_col + j];
-        const int64_t e = d.off_ell + ell.grp[d.off_grp + (sp >> 6)] + 64 * k2 + (sp & 63);
+        const int32_t *cp = col_ptr + d.off_colptr;
+        const int k2 = (int)(pc - cp[j]);
+        int p, l;
+        part_shape(cp[j + 1] - cp[j], p, l);
+        const int u = k2 / l, kl = k2 - u * l;
+        const int32_t sp = ell.ppos[d.off_part + ell.pbase[d.off_colptr + j] + u];
+        const int64_t e = d.off_ell + ell.grp[d.off_grp + (sp >> 6)] + 64 * (int64_t)kl + (sp & 63);
         ell.row[e] = (int32_t)i;
         ell.val[3 * e] = v0;
         ell.val[3 * e + 1] = v1;
@@ -508,56 +519,85 @@ __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t tot
     }
 }
 
-// Columns of an ELL slice sorted by sample count, descending (counting sort
-// over the counts; the order among equal counts is immaterial), and the
-// offsets of the 64-column groups: a group takes 64 x the count of its first
-// (largest) column.
-__global__ __launch_bounds__(1024) void k_colsort(const SliceDesc *__restrict__ desc,
-                                                  const int32_t *__restrict__ col_ptr, EllView ell) {
-    __shared__ uint32_t hist[ELL_MAX_M + 1];
+// ELL parts of a slice: per column the first part (pbase), the parts sorted by
+// length, descending (counting sort over the lengths; the order among equal
+// lengths is immaterial to every result), and the offsets of the 64-part
+// groups, a group taking 64 x the length of its first part.
+__global__ __launch_bounds__(1024) void k_partsort(const SliceDesc *__restrict__ desc,
+                                                   const int32_t *__restrict__ col_ptr, EllView ell) {
+    __shared__ uint32_t hist[ELL_LMAX + 1];
     __shared__ uint32_t sm[1024 / WAVE];
+    __shared__ uint32_t nsplit;
     const SliceDesc d = desc[blockIdx.x];
     if (!d.ell) return;
-    const int m = d.m, n = d.n, t = threadIdx.x;
+    const int n = d.n, t = threadIdx.x;
     const int32_t *cp = col_ptr + d.off_colptr;
-    for (int c = t; c <= m; c += 1024) hist[c] = 0;
-    __syncthreads();
-    for (int j = t; j < n; j += 1024) atomicAdd(&hist[cp[j + 1] - cp[j]], 1u);
-    __syncthreads();
-    // bins in the order m, m - 1, ..., 0; thread t owns C consecutive ones
-    const int B = m + 1, C = (B + 1023) / 1024;
-    uint32_t loc = 0;
-    for (int u = 0; u < C; ++u) {
-        const int r = t * C + u;
-        if (r < B) loc += hist[m - r];
+    int32_t *pb = ell.pbase + d.off_colptr;
+    int32_t *part = ell.part + d.off_part;
+    int32_t *ppos = ell.ppos + d.off_part;
+    int32_t *grp = ell.grp + d.off_grp;
+    if (t <= ELL_LMAX) hist[t] = 0;
+    if (t == 0) nsplit = 0;
+    uint32_t carry = 0, tot;
+    for (int j0 = 0; j0 < n; j0 += 1024) {
+        const int j = j0 + t;
+        int p = 0, l;
+        if (j < n) part_shape(cp[j + 1] - cp[j], p, l);
+        const uint32_t ex = block_excl_scan((uint32_t)p, &tot, sm);
+        if (j < n) pb[j] = (int32_t)(carry + ex);
+        carry += tot;
     }
-    uint32_t tot;
-    uint32_t run = block_excl_scan(loc, &tot, sm);
-    for (int u = 0; u < C; ++u) {
-        const int r = t * C + u;
-        if (r < B) {
-            const uint32_t h = hist[m - r];
-            hist[m - r] = run;
+    const int P = (int)carry;
+    if (t == 0) pb[n] = P;
+    __syncthreads();
+    for (int j = t; j < n; j += 1024) {
+        const int c = cp[j + 1] - cp[j];
+        int p, l;
+        part_shape(c, p, l);
+        for (int u = 0; u < p; ++u) atomicAdd(&hist[min(l, c - u * l)], 1u);
+        if (p > 1) ell.split[d.off_col + atomicAdd(&nsplit, 1u)] = j;
+    }
+    __syncthreads();
+    if (t == 0) ell.nsplit[blockIdx.x] = (int32_t)nsplit;
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int b = ELL_LMAX; b >= 0; --b) {
+            const uint32_t h = hist[b];
+            hist[b] = run;
             run += h;
         }
     }
     __syncthreads();
     for (int j = t; j < n; j += 1024) {
-        const uint32_t p = atomicAdd(&hist[cp[j + 1] - cp[j]], 1u);
-        ell.perm[d.off_col + p] = j;
-        ell.pos[d.off_col + j] = (int32_t)p;
+        const int c = cp[j + 1] - cp[j];
+        int p, l;
+        part_shape(c, p, l);
+        for (int u = 0; u < p; ++u) {
+            const uint32_t pos = atomicAdd(&hist[min(l, c - u * l)], 1u);
+            part[pos] = j | (u << 16);
+            ppos[pb[j] + u] = (int32_t)pos;
+        }
     }
     __threadfence_block();
     __syncthreads();
-    const int G = (n + 63) / 64;   // <= 1024
-    uint32_t len = 0;
-    if (t < G) {
-        const int j = ell.perm[d.off_col + 64 * t];
-        len = 64u * (uint32_t)(cp[j + 1] - cp[j]);
+    const int G = (P + 63) / 64;
+    carry = 0;
+    for (int g0 = 0; g0 < G; g0 += 1024) {
+        const int g = g0 + t;
+        uint32_t len = 0;
+        if (g < G) {
+            const int v = part[64 * g];
+            const int j = v & 0xFFFF, u = v >> 16;
+            const int c = cp[j + 1] - cp[j];
+            int p, l;
+            part_shape(c, p, l);
+            len = 64u * (uint32_t)min(l, c - u * l);
+        }
+        const uint32_t ex = block_excl_scan(len, &tot, sm);
+        if (g < G) grp[g] = (int32_t)(carry + ex);
+        carry += tot;
     }
-    const uint32_t off = block_excl_scan(len, &tot, sm);
-    if (t < G) ell.grp[d.off_grp + t] = (int32_t)off;
-    if (t == 0) ell.grp[d.off_grp + G] = (int32_t)tot;
+    if (t == 0) grp[G] = (int32_t)carry;
 }
 
 unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
@@ -661,7 +701,7 @@ int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, c
     hipLaunchKernelGGL(k_ptrscan, dim3(S), dim3(256), 0, st, desc, 1, col_ptr);
     VPLMC_HIP(hipGetLastError());
     if (plan.n_ell > 0) {
-        hipLaunchKernelGGL(k_colsort, dim3(S), dim3(1024), 0, st, desc, col_ptr, ell);
+        hipLaunchKernelGGL(k_partsort, dim3(S), dim3(1024), 0, st, desc, col_ptr, ell);
         VPLMC_HIP(hipGetLastError());
     }
     if (plan.tot1 > 0) {

@@ -96,23 +96,33 @@ struct SliceDesc {
     int64_t off_row, off_colptr, off_x, off_y;
     int64_t off_bm, off_bmt;                   // bitmap word offsets (row- and column-major)
     int64_t off_ell, off_red;                  // ELL entry offset; cross-wave reduction scratch (floats)
+    int64_t off_part, pad1;                    // first part slot of the slice
 };
 
-// Column-major ELL copy of a slice's samples for the LDS-resident completion:
-// the columns sorted by sample count (descending) are cut into groups of 64;
-// sample k (CSC order) of the column at sorted position 64 g + l is entry
+// Column-major ELL copy of a slice's samples for the LDS-resident completion.
+// Column j with c_j samples is cut into p_j = max(1, ceil(c_j / ELL_LMAX))
+// parts of ceil(c_j / p_j) consecutive samples (CSC order; the last part may
+// be shorter).  The parts, sorted by length (descending), are cut into groups
+// of 64; sample k of the part at sorted position 64 g + l is entry
 // grp[g] + 64 k + l, so that one load instruction of a wavefront whose lane l
-// walks that column reads 64 consecutive entries.  Entries past a column's
-// count are padding and never read.
+// walks that part reads 64 consecutive entries and every lane of a group has
+// nearly the same number of samples.  Entries past a part's length are
+// padding and never read.  Parts are numbered in column order by
+// pbase[j] + t.
 struct EllView {
-    int32_t *perm;   // per (slice, sorted position): column
-    int32_t *pos;    // per (slice, column): sorted position
-    int32_t *grp;    // per slice: ceil(n / 64) + 1 group offsets, relative to off_ell
-    int32_t *row;    // per entry: row of the sample
-    float *val;      // 3 per entry: sampled values
-    float *res;      // 3 per entry: residual of the current iterate
+    int32_t *part;     // per (slice, sorted position): column j | part t << 16
+    int32_t *ppos;     // per (slice, part in column order): sorted position
+    int32_t *pbase;    // per (slice, column + 1): first part of the column (like col_ptr)
+    int32_t *grp;      // per slice: groups + 1 offsets, relative to off_ell
+    int32_t *row;      // per entry: row of the sample
+    float *val;        // 3 per entry: sampled values
+    float *res;        // 3 per entry: residual of the current iterate
+    float *partial;    // 48 per part slot: X+^T R of the part (columns cut into several parts)
+    int32_t *split;    // per (slice, column): the columns of more than one part, first nsplit entries
+    int32_t *nsplit;   // per slice
 };
-constexpr int ELL_MAX_M = 8192;   // rows of a slice that may use the ELL copy (histogram bins)
+constexpr int ELL_LMAX = 64;      // longest part
+constexpr int ELL_MAX_M = 8192;   // rows of a slice that may use the ELL copy
 constexpr int ADM_RED_FLOATS = 16 * 2 * 256;   // per slice: 16 wavefronts x two 16 x 16 partial Grams
 
 // extra (internal) regions, after the public ones
@@ -133,15 +143,19 @@ enum {
     R_COLSUMSQ,      // double per (slice, column): sum of t^2
     R_COLZERO,       // int32 per (slice, column): observations with t = 0
     R_SLICE_GEO,     // float[8] per slice: centroid xyz, bbox diagonal, mean normal xyz, -
-    R_ELL_PERM,      // int32 per (slice, column)
-    R_ELL_POS,       // int32 per (slice, column)
-    R_ELL_GRP,       // int32 per slice: ceil(n / 64) + 1
+    R_ELL_PART,      // int32 per part slot
+    R_ELL_PPOS,      // int32 per part slot
+    R_ELL_PBASE,     // int32 per (slice, column + 1)
+    R_ELL_PARTIAL,   // float[48] per part slot
+    R_ELL_GRP,       // int32 per group slot
+    R_ELL_SPLIT,     // int32 per (slice, column)
+    R_ELL_NSPLIT,    // int32 per slice
     R_ELL_ROW,       // int32 per ELL entry
     R_ELL_VAL,       // float[3] per ELL entry
     R_ELL_RES,       // float[3] per ELL entry
     R_YT,            // float[n][3][q]: staging of the right-hand sides of the Y update
     R_ADM_RED,       // float per slice: ADM_RED_FLOATS
-    R_E2COL,         // double per (slice, column): squared residual over the column's samples
+    R_E2PART,        // double per part slot: squared residual over the part's samples
     R_INTERNAL_END
 };
 
@@ -182,6 +196,7 @@ struct vplmc_plan {
     int64_t tot1 = 0, tot2 = 0, tot_omega = 0, tot_col = 0, tot_row = 0, tot_x = 0, tot_y = 0;
     int64_t tot_bm = 0, tot_bmt = 0;
     int64_t tot_grp = 0, tot_ell = 0, n_ell = 0;   // ELL group table entries, ELL entries, ELL slices
+    int64_t tot_part = 0;                           // part slots
     std::vector<int32_t> ids;                  // slice ids grouped by rank bucket
     std::vector<char> upload;                  // descriptor table + ids, as copied to the workspace
 };
@@ -245,7 +260,7 @@ int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, c
 int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
                const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
                const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, const EllView &ell, float *X,
-               float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt, float *red, double *e2col,
+               float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt, float *red, double *e2part,
                float *scale, int32_t *stats);
 int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,
                   const float *X, const float *Y, const float *scale, float *radiance);
