@@ -34,7 +34,36 @@ def parse():
     ap.add_argument("--seed", type=int, default=11)
     ap.add_argument("--rmse-pixels", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", default="1,2.5,5,10",
+                    help="total sampling rates (percent) of the plain vs learned fixed-RMSE comparison; empty: none")
+    ap.add_argument("--sweep-steps", type=int, default=2)
     return ap.parse_args()
+
+
+def frame_times(api, torch, ctx, plan, ds, prm, ws, rad, steps, warmup):
+    """Mean frame ms over `steps` frames after `warmup` (device-resident inputs)."""
+    for _ in range(warmup):
+        api.render(ctx, plan, ds, prm, ws, rad)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        api.render(ctx, plan, ds, prm, ws, rad)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def interp_ms_at(points, target):
+    """Frame ms at pixel RMSE `target` by log-log interpolation over (rmse, ms)
+    points of one proposal; None outside their range."""
+    pts = sorted(points)
+    for (r0, m0), (r1, m1) in zip(pts, pts[1:]):
+        if min(r0, r1) <= target <= max(r0, r1) and r0 != r1:
+            w = (np.log(target) - np.log(r0)) / (np.log(r1) - np.log(r0))
+            return float(np.exp(np.log(m0) + w * (np.log(m1) - np.log(m0))))
+    return None
 
 
 def cpu_baseline(sc, ppm, seed, slices=(0,)):
@@ -78,6 +107,14 @@ def main():
     plan = api.Plan(sc, prm)
     ws = api.workspace(plan, dev)
     rad = torch.empty((sc.m, 3), dtype=torch.float32, device=dev)
+    # the proposal network trained on scenes of this workload's shape, else the default one
+    weights_path = os.path.join(ROOT, "paper_2202_12567_amd", f"proposal_mlp_{args.workload}.npy")
+    if not os.path.exists(weights_path):
+        weights_path = os.path.join(ROOT, "paper_2202_12567_amd", "proposal_mlp.npy")
+    proposal = None
+    if os.path.exists(weights_path):
+        proposal = torch.as_tensor(np.load(weights_path)).to(dev)
+        api.set_proposal(ctx, proposal)
 
     for _ in range(args.warmup):
         api.render(ctx, plan, ds, prm, ws, rad)
@@ -132,6 +169,45 @@ def main():
             "fp32_frac": round(adm_flops / t_adm / 1e12 / FP32_PEAK_TFLOPS, 4)}
     dominant = max(phase_ms, key=phase_ms.get)
 
+    # learned proposal at the same rate, and the plain vs learned sweep
+    learned = None
+    fixed = None
+    if proposal is not None:
+        prm_l = api.default_params(seed=args.seed, pass1_ppm=ppm, pass2_ppm=ppm, learned=True)
+        rad_l = torch.empty_like(rad)
+        ms_l = frame_times(api, torch, ctx, plan, ds, prm_l, ws, rad_l, args.steps, 1)
+        st_l = api.read_stats(ctx, plan, ws)
+        rmse_l = rel(rad_l[pid_t.long()].double(), ref)
+        learned = {"weights": os.path.basename(weights_path), "frame_ms": round(ms_l, 3),
+                   "pixel_rmse_vs_full_sum": round(rmse_l, 5),
+                   "fallback_slices": int(((st_l["flags"] & 8) != 0).sum()),
+                   "sampled_entries_per_frame": int(N1.sum() + st_l["n2"].astype(np.int64).sum())}
+        rates = [float(x) for x in args.sweep.split(",") if x.strip()]
+        if rates:
+            pts = {"plain": [], "learned": []}
+            rows = []
+            for r in rates:
+                pr = int(round(r * 1e4 / 2))
+                pl = api.Plan(sc, api.default_params(seed=args.seed, pass1_ppm=pr, pass2_ppm=pr))
+                wsr = api.workspace(pl, dev)
+                row = {"rate_pct": r}
+                for name, flag in (("plain", False), ("learned", True)):
+                    pp = api.default_params(seed=args.seed, pass1_ppm=pr, pass2_ppm=pr, learned=flag)
+                    msr = frame_times(api, torch, ctx, pl, ds, pp, wsr, rad_l, args.sweep_steps, 1)
+                    er = rel(rad_l[pid_t.long()].double(), ref)
+                    pts[name].append((er, msr))
+                    row[name] = {"frame_ms": round(msr, 3), "pixel_rmse": round(er, 5)}
+                rows.append(row)
+                del wsr
+                pl.close()
+            target = rmse_full
+            ms_plain_t = interp_ms_at(pts["plain"] + [(rmse_full, ms)], target)
+            ms_learned_t = interp_ms_at(pts["learned"], target)
+            fixed = {"target_pixel_rmse": round(target, 5), "plain_ms": None if ms_plain_t is None else round(ms_plain_t, 3),
+                     "learned_ms": None if ms_learned_t is None else round(ms_learned_t, 3),
+                     "learned_speedup": None if not (ms_plain_t and ms_learned_t) else round(ms_plain_t / ms_learned_t, 3),
+                     "sweep": rows}
+
     out = {
         "metric": "frame ms at fixed pixel RMSE vs full sum; sampled entries/s; plain vs learned",
         "value": round(entries / (ms * 1e-3), 1),
@@ -154,7 +230,8 @@ def main():
         "phase_ms": {k: round(v, 3) for k, v in phase_ms.items()},
         "dominant_phase": dominant,
         "roofline": roof,
-        "learned": None,
+        "learned": learned,
+        "fixed_rmse": fixed,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, ppm, args.seed)

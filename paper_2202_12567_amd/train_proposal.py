@@ -50,6 +50,7 @@ def build_dataset(ctx, seeds, cfg="learned", ppm=50000, device="cuda"):
         sc = make_scene(cfg, seed)
         prm.seed = seed
         f, p, o = frame_data(ctx, sc, prm, device)
+        print(f"scene {seed}: {f.shape[0]} rows", flush=True)
         F.append(f)
         Pst.append(p)
         offs.extend((o[1:] + offs[-1]).tolist())
@@ -109,16 +110,21 @@ def train(ctx, F, P, offs, steps=300, batch_groups=128, lr=1e-3, seed=0, log=pri
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="proposal_mlp.npy")
+    ap.add_argument("--config", default="learned", help="scene configuration of the training scenes")
+    ap.add_argument("--ppm", type=int, default=50000, help="first- and second-pass rate (parts per million)")
     ap.add_argument("--steps", type=int, default=600)
     ap.add_argument("--train-scenes", type=int, default=200)
+    ap.add_argument("--valid-scenes", type=int, default=20)
+    ap.add_argument("--batch-groups", type=int, default=128)
+    ap.add_argument("--lr", type=float, default=1e-3)
     args = ap.parse_args()
     dev = torch.device("cuda", 0)
     ctx = api.Context(0)
     t0 = time.time()
-    F, P, offs = build_dataset(ctx, list(TRAIN_SEEDS)[: args.train_scenes])
-    Fv, Pv, offv = build_dataset(ctx, VALID_SEEDS)
+    F, P, offs = build_dataset(ctx, list(TRAIN_SEEDS)[: args.train_scenes], cfg=args.config, ppm=args.ppm)
+    Fv, Pv, offv = build_dataset(ctx, list(VALID_SEEDS)[: args.valid_scenes], cfg=args.config, ppm=args.ppm)
     print(f"dataset: {F.shape[0]} rows ({offs.shape[0] - 1} slices), {time.time() - t0:.1f} s", flush=True)
-    params, hist = train(ctx, F, P, offs, steps=args.steps)
+    params, hist = train(ctx, F, P, offs, steps=args.steps, batch_groups=args.batch_groups, lr=args.lr)
     yv = api.mlp_forward(ctx, params, Fv)
     print(f"validation KL per slice: {kl_per_group(yv, Pv, offv):.4f}", flush=True)
     np.save(args.out, params.cpu().numpy())
