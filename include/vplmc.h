@@ -227,6 +227,47 @@ enum {
 int vplmc_profile_begin(vplmc_ctx *ctx, int32_t max_frames);
 int vplmc_profile_end(vplmc_ctx *ctx, double *ms /* HOST */, int32_t *frames /* HOST */);
 
+/* ---- batching: launch shapes, autotuning, captured frames ----------------
+ * All slices of a frame, whatever their m', n' and q, run in one launch per
+ * phase (per rank bucket for the completion).  The plan carries the launch
+ * shapes; integer results never depend on them, floating-point results only
+ * through summation order within the completion's tolerance. */
+typedef struct {
+    int32_t adm_queue;     /* 0: one workgroup per slice; 1: as many workgroups as fit on the
+                              device take slices (largest first) from a device work queue   */
+    int32_t adm_threads;   /* threads of the LDS-resident completion workgroup: 512 or 1024 */
+    int32_t eval_threads;  /* threads per block of the entry kernel: 64, 128 or 256         */
+    int32_t reserved;      /* 0 */
+} vplmc_tune;
+/* Defaults: queue 0, 1024 completion threads, 256 entry threads. */
+int vplmc_plan_get_tune(const vplmc_plan *plan, vplmc_tune *out /* HOST */);
+int vplmc_plan_set_tune(vplmc_plan *plan, const vplmc_tune *tune /* HOST */);
+/* Times `reps` frames (after one warm-up frame) of vplmc_render for each
+ * candidate launch shape on these inputs, by coordinate descent over the
+ * fields above, and leaves the fastest in the plan (also returned in *best,
+ * which may be NULL).  Same arguments as vplmc_render; synchronises; the
+ * radiance and workspace hold the last frame rendered.  reps in [1, 100]. */
+int vplmc_autotune(vplmc_ctx *ctx, vplmc_plan *plan, const vplmc_points *points, const vplmc_lights *vpls,
+                   const vplmc_cut *cut, const int32_t *pt_ids, const int32_t *cl_ids,
+                   const vplmc_params *params, void *workspace, size_t workspace_bytes, float *radiance,
+                   int32_t reps, vplmc_tune *best /* HOST, may be NULL */);
+
+/* A whole vplmc_render recorded once as a HIP graph, replayed by one call.
+ * create renders one frame eagerly (which validates the arguments and
+ * uploads the slice table), then captures the frame on a private stream.
+ * The inputs, workspace and radiance must stay at the same addresses; their
+ * contents may change between launches.  The plan (and its launch shapes)
+ * must outlive the graph; changing the plan's tune needs a new graph.
+ * Profiling must be off during create.  launch enqueues on the context's
+ * stream and does not synchronise. */
+typedef struct vplmc_graph vplmc_graph;
+int vplmc_graph_create(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points,
+                       const vplmc_lights *vpls, const vplmc_cut *cut, const int32_t *pt_ids,
+                       const int32_t *cl_ids, const vplmc_params *params, void *workspace,
+                       size_t workspace_bytes, float *radiance, vplmc_graph **out /* HOST */);
+int vplmc_graph_launch(vplmc_ctx *ctx, vplmc_graph *graph);
+int vplmc_graph_destroy(vplmc_graph *graph);
+
 /* ---- building blocks used by the frame, exposed for tests and tools ---- */
 /* Cluster table (Sec. 4): rep[c], lights float[9][n_clusters] (x y z nx ny nz
  * ir ig ib), bbox float[6][n_clusters].  All DEVICE outputs. */

@@ -31,6 +31,11 @@ class Params(ctypes.Structure):
                 ("r_min", ctypes.c_float), ("ray_eps", ctypes.c_float)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("adm_queue", ctypes.c_int32), ("adm_threads", ctypes.c_int32), ("eval_threads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class SliceInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("q", ctypes.c_int32), ("N1", ctypes.c_int32),
                 ("N2", ctypes.c_int32), ("adm_in_lds", ctypes.c_int32), ("off1", ctypes.c_int64), ("off2", ctypes.c_int64),
@@ -83,6 +88,12 @@ SIG = {
                                      ctypes.c_size_t, P]),
     "vplmc_profile_begin": (I32, [P, I32]),
     "vplmc_profile_end": (I32, [P, P, P]),
+    "vplmc_plan_get_tune": (I32, [P, P]),
+    "vplmc_plan_set_tune": (I32, [P, P]),
+    "vplmc_autotune": (I32, [P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P, I32, P]),
+    "vplmc_graph_create": (I32, [P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P, P]),
+    "vplmc_graph_launch": (I32, [P, P]),
+    "vplmc_graph_destroy": (I32, [P]),
 }
 N_PHASES = 10
 PHASES = ["setup", "cluster", "pass1", "eval1", "weights", "pass2", "eval2", "sort", "adm", "reduce"]

@@ -223,6 +223,60 @@ def profile_end(ctx):
     return dict(zip(N.PHASES, ms.tolist())), int(fr[0])
 
 
+# ---- batching: launch shapes, autotuning, captured frames --------------------
+
+def get_tune(plan):
+    t = N.Tune()
+    check(N.load().vplmc_plan_get_tune(plan.h, ctypes.byref(t)))
+    return {"adm_queue": t.adm_queue, "adm_threads": t.adm_threads, "eval_threads": t.eval_threads}
+
+
+def set_tune(plan, adm_queue=None, adm_threads=None, eval_threads=None):
+    cur = get_tune(plan)
+    t = N.Tune(cur["adm_queue"] if adm_queue is None else adm_queue,
+               cur["adm_threads"] if adm_threads is None else adm_threads,
+               cur["eval_threads"] if eval_threads is None else eval_threads, 0)
+    check(N.load().vplmc_plan_set_tune(plan.h, ctypes.byref(t)))
+
+
+def autotune(ctx, plan, ds, params, ws, radiance, reps=2):
+    """vplmc_autotune; returns the chosen launch shapes (also left in the plan)."""
+    t = N.Tune()
+    check(N.load().vplmc_autotune(ctx.h, plan.h, ctypes.byref(ds.points_c), ctypes.byref(ds.vpls_c),
+                                  ctypes.byref(ds.cut_c), _ptr(ds.pt_ids), _ptr(ds.cl_ids), ctypes.byref(params),
+                                  _ptr(ws), ws.numel(), _ptr(radiance), int(reps), ctypes.byref(t)))
+    return {"adm_queue": t.adm_queue, "adm_threads": t.adm_threads, "eval_threads": t.eval_threads}
+
+
+class Graph:
+    """A whole frame captured once (vplmc_graph_create) and replayed by launch().
+    The inputs, workspace and radiance tensors must stay alive and in place."""
+
+    def __init__(self, ctx, plan, ds, params, ws, radiance):
+        h = ctypes.c_void_p()
+        check(N.load().vplmc_graph_create(ctx.h, plan.h, ctypes.byref(ds.points_c), ctypes.byref(ds.vpls_c),
+                                          ctypes.byref(ds.cut_c), _ptr(ds.pt_ids), _ptr(ds.cl_ids),
+                                          ctypes.byref(params), _ptr(ws), ws.numel(), _ptr(radiance),
+                                          ctypes.byref(h)))
+        self.h = h
+        self.ctx = ctx
+        self._keep = (plan, ds, params, ws, radiance)
+
+    def launch(self):
+        check(N.load().vplmc_graph_launch(self.ctx.h, self.h))
+
+    def close(self):
+        if self.h:
+            N.load().vplmc_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ---- learned proposal -------------------------------------------------------
 
 def mlp_param_count():

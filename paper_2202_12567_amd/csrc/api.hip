@@ -76,7 +76,7 @@ struct PhaseMarks {
     vplmc_ctx *ctx;
     hipEvent_t *ev = nullptr;
     explicit PhaseMarks(vplmc_ctx *c) : ctx(c) {
-        if (c->prof_on && c->prof_frames < c->prof_max_frames)
+        if (c->prof_on && !c->capturing && c->prof_frames < c->prof_max_frames)
             ev = &c->prof_events[(size_t)c->prof_frames * (VPLMC_N_PHASES + 1)];
     }
     int mark(int b) {
@@ -285,6 +285,17 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         plan->group_max_m[grp] = std::max<int32_t>(plan->group_max_m[grp], (int32_t)m);
         plan->max_m = std::max<int64_t>(plan->max_m, m);
     }
+    // largest slices first in every launch group (longest-processing-time order for
+    // the hardware dispatcher and for the work queue); cost as in the multi-GPU split
+    for (int g = 0; g < 8; ++g) {
+        auto cost = [&](int32_t s) {
+            const SliceDesc &d = plan->desc[s];
+            const double q = d.q;
+            return (double)(d.N1 + d.N2) * (18.0 * q + 40.0) + 2.0 * q * q * (4.0 * d.m + 9.0 * d.n);
+        };
+        std::stable_sort(plan->groups[g].begin(), plan->groups[g].end(),
+                         [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+    }
     plan->tot1 = o1;
     plan->tot2 = o2;
     plan->tot_omega = oo;
@@ -359,6 +370,7 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     bytes[R_YT] = oy * 4;
     bytes[R_ADM_RED] = S * ADM_RED_FLOATS * 4;
     bytes[R_E2PART] = plan->tot_part * 8;
+    bytes[R_QUEUE] = 8 * 4;
     bytes[VPLMC_R_FEATURES] = oc * MLP_IN * 4;
     bytes[VPLMC_R_LOGITS] = oc * 4;
     size_t off = 0;
@@ -447,7 +459,8 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
 
     SliceDesc *desc = region<SliceDesc>(ws, plan, R_DESC);
     const int32_t *ids = reinterpret_cast<const int32_t *>(desc + S);
-    if (S > 0)
+    // (a captured frame reuses the table uploaded by the eager frame before the capture)
+    if (S > 0 && !ctx->capturing)
         VPLMC_HIP(hipMemcpyAsync(desc, plan->upload.data(), plan->upload.size(), hipMemcpyHostToDevice, st));
 
     uint32_t *bm = region<uint32_t>(ws, plan, R_BITMAP);
@@ -474,7 +487,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if ((rc = launch_pass1(st, *plan, desc, params->seed, omega1, bm, bmt))) return rc;
     if ((rc = ph.mark(VPLMC_PH_EVAL1))) return rc;
     if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_clusters, desc, S, pt_ids, cl_ids, omega1,
-                                plan->tot1, 0, stats, *params, val1)))
+                                plan->tot1, 0, stats, *params, val1, plan->tune.eval_threads)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_WEIGHTS))) return rc;
     int32_t *col_ptr = region<int32_t>(ws, plan, VPLMC_R_COL_PTR);
@@ -512,7 +525,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if ((rc = launch_pass2(st, *plan, desc, params->seed, prefix, bm, bmt, omega2, stats))) return rc;
     if ((rc = ph.mark(VPLMC_PH_EVAL2))) return rc;
     if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_clusters, desc, S, pt_ids, cl_ids, omega2,
-                                plan->tot2, 1, stats, *params, val2)))
+                                plan->tot2, 1, stats, *params, val2, plan->tune.eval_threads)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_SORT))) return rc;
     int32_t *row_ptr = region<int32_t>(ws, plan, VPLMC_R_ROW_PTR);
@@ -537,7 +550,8 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     float *Y = region<float>(ws, plan, VPLMC_R_Y);
     float *scale = region<float>(ws, plan, VPLMC_R_SLICE_SCALE);
     if ((rc = ph.mark(VPLMC_PH_ADM))) return rc;
-    if ((rc = launch_adm(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X,
+    if ((rc = launch_adm(st, *plan, ctx->n_cu, desc, ids, region<int32_t>(ws, plan, R_QUEUE), *params, row_ptr,
+                         csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X,
                          region<float>(ws, plan, R_XNEXT), region<float>(ws, plan, R_XP),
                          region<float>(ws, plan, R_LAMBDA), Y, region<float>(ws, plan, R_YP),
                          region<float>(ws, plan, R_PI), region<float>(ws, plan, R_YT),
@@ -547,6 +561,162 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if ((rc = launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, radiance))) return rc;
     if ((rc = ph.mark(VPLMC_N_PHASES))) return rc;
     ph.done();
+    return VPLMC_OK;
+}
+
+static int check_tune(const vplmc_tune *t) {
+    if (!t) return set_error(VPLMC_EINVAL, "tune is NULL");
+    if (t->adm_queue != 0 && t->adm_queue != 1) return set_error(VPLMC_EINVAL, "adm_queue must be 0 or 1");
+    if (t->adm_threads != 512 && t->adm_threads != 1024) return set_error(VPLMC_EINVAL, "adm_threads must be 512 or 1024");
+    if (t->eval_threads != 64 && t->eval_threads != 128 && t->eval_threads != 256)
+        return set_error(VPLMC_EINVAL, "eval_threads must be 64, 128 or 256");
+    if (t->reserved != 0) return set_error(VPLMC_EINVAL, "reserved must be 0");
+    return VPLMC_OK;
+}
+
+int vplmc_plan_get_tune(const vplmc_plan *plan, vplmc_tune *out) {
+    if (!plan || !out) return set_error(VPLMC_EINVAL, "plan and out must be non-NULL");
+    *out = plan->tune;
+    return VPLMC_OK;
+}
+
+int vplmc_plan_set_tune(vplmc_plan *plan, const vplmc_tune *tune) {
+    if (!plan) return set_error(VPLMC_EINVAL, "plan is NULL");
+    int rc = check_tune(tune);
+    if (rc) return rc;
+    plan->tune = *tune;
+    return VPLMC_OK;
+}
+
+int vplmc_autotune(vplmc_ctx *ctx, vplmc_plan *plan, const vplmc_points *points, const vplmc_lights *vpls,
+                   const vplmc_cut *cut, const int32_t *pt_ids, const int32_t *cl_ids, const vplmc_params *params,
+                   void *workspace, size_t workspace_bytes, float *radiance, int32_t reps, vplmc_tune *best) {
+    if (!ctx || !plan) return set_error(VPLMC_EINVAL, "ctx and plan must be non-NULL");
+    if (reps < 1 || reps > 100) return set_error(VPLMC_EINVAL, "reps must be in [1, 100]");
+    if (ctx->prof_on) return set_error(VPLMC_EINVAL, "profiling is on");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    hipEvent_t e0, e1;
+    VPLMC_HIP(hipEventCreate(&e0));
+    VPLMC_HIP(hipEventCreate(&e1));
+    auto time_of = [&](const vplmc_tune &t, float &ms) -> int {
+        plan->tune = t;
+        int rc = vplmc_render(ctx, plan, points, vpls, cut, pt_ids, cl_ids, params, workspace, workspace_bytes,
+                              radiance);
+        if (rc) return rc;
+        VPLMC_HIP(hipEventRecord(e0, ctx->stream));
+        for (int k = 0; k < reps && !rc; ++k)
+            rc = vplmc_render(ctx, plan, points, vpls, cut, pt_ids, cl_ids, params, workspace, workspace_bytes,
+                              radiance);
+        if (rc) return rc;
+        VPLMC_HIP(hipEventRecord(e1, ctx->stream));
+        VPLMC_HIP(hipEventSynchronize(e1));
+        VPLMC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        return VPLMC_OK;
+    };
+    const vplmc_tune start = plan->tune;
+    vplmc_tune cur = start;
+    float cur_ms = 0.f;
+    int rc = time_of(cur, cur_ms);
+    // coordinate descent: completion launch (queue x threads), then entry block size
+    const vplmc_tune adm_cands[4] = {{0, 1024, 0, 0}, {1, 1024, 0, 0}, {0, 512, 0, 0}, {1, 512, 0, 0}};
+    for (int k = 0; k < 4 && !rc; ++k) {
+        vplmc_tune t = cur;
+        t.adm_queue = adm_cands[k].adm_queue;
+        t.adm_threads = adm_cands[k].adm_threads;
+        if (t.adm_queue == cur.adm_queue && t.adm_threads == cur.adm_threads) continue;
+        float ms;
+        if ((rc = time_of(t, ms))) break;
+        if (ms < cur_ms) {
+            cur = t;
+            cur_ms = ms;
+        }
+    }
+    const int eval_cands[3] = {64, 128, 256};
+    for (int k = 0; k < 3 && !rc; ++k) {
+        if (eval_cands[k] == cur.eval_threads) continue;
+        vplmc_tune t = cur;
+        t.eval_threads = eval_cands[k];
+        float ms;
+        if ((rc = time_of(t, ms))) break;
+        if (ms < cur_ms) {
+            cur = t;
+            cur_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan->tune = rc ? start : cur;
+    if (rc) return rc;
+    if (best) *best = cur;
+    return VPLMC_OK;
+}
+
+struct vplmc_graph {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int vplmc_graph_create(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points, const vplmc_lights *vpls,
+                       const vplmc_cut *cut, const int32_t *pt_ids, const int32_t *cl_ids, const vplmc_params *params,
+                       void *workspace, size_t workspace_bytes, float *radiance, vplmc_graph **out) {
+    if (!out) return set_error(VPLMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return set_error(VPLMC_EINVAL, "ctx is NULL");
+    if (ctx->prof_on) return set_error(VPLMC_EINVAL, "profiling is on");
+    // one eager frame: validates everything and uploads the slice table
+    int rc = vplmc_render(ctx, plan, points, vpls, cut, pt_ids, cl_ids, params, workspace, workspace_bytes, radiance);
+    if (rc) return rc;
+    VPLMC_HIP(hipStreamSynchronize(ctx->stream));
+    hipStream_t cs;
+    VPLMC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipStream_t saved = ctx->stream;
+    ctx->stream = cs;
+    ctx->capturing = true;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        rc = vplmc_render(ctx, plan, points, vpls, cut, pt_ids, cl_ids, params, workspace, workspace_bytes, radiance);
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e2 != hipSuccess && !rc) e = e2;
+    }
+    ctx->stream = saved;
+    ctx->capturing = false;
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess || rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : hip_error(e, "stream capture");
+    }
+    vplmc_graph *gr = new (std::nothrow) vplmc_graph();
+    if (!gr) {
+        (void)hipGraphDestroy(g);
+        return set_error(VPLMC_ENOMEM, "graph allocation failed");
+    }
+    gr->device = ctx->device;
+    gr->graph = g;
+    e = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete gr;
+        return hip_error(e, "graph instantiate");
+    }
+    *out = gr;
+    return VPLMC_OK;
+}
+
+int vplmc_graph_launch(vplmc_ctx *ctx, vplmc_graph *graph) {
+    if (!ctx || !graph) return set_error(VPLMC_EINVAL, "ctx and graph must be non-NULL");
+    if (graph->device != ctx->device) return set_error(VPLMC_EINVAL, "graph was captured on another device");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    VPLMC_HIP(hipGraphLaunch(graph->exec, ctx->stream));
+    return VPLMC_OK;
+}
+
+int vplmc_graph_destroy(vplmc_graph *graph) {
+    if (!graph) return VPLMC_OK;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
     return VPLMC_OK;
 }
 

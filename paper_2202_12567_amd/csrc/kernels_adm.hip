@@ -24,6 +24,7 @@
 // iteration; rows and columns are then multiplied by the FP64 inverse.
 // Every reduction has a fixed order: results are bitwise reproducible.
 
+#include <algorithm>
 #include <type_traits>
 
 #include "vplmc_internal.h"
@@ -132,8 +133,8 @@ __device__ void gram_rows(AdmShared<Q> &sh, const float *__restrict__ M, int row
 }
 
 template <int Q, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_adm(
-    const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, uint64_t seed,
+__device__ void adm_global_slice(
+    int s, const SliceDesc *__restrict__ desc, uint64_t seed,
     int32_t max_iter, int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma,
     const int32_t *__restrict__ row_ptr_all, const int32_t *__restrict__ csr_col_all,
     const float *__restrict__ csr_val_all, const int32_t *__restrict__ col_ptr_all,
@@ -144,7 +145,6 @@ __global__ __launch_bounds__(THREADS) void k_adm(
     __shared__ AdmShared<Q> sh;
     __shared__ float part[(NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024];
 
-    const int s = slice_list[blockIdx.x];
     const SliceDesc d = desc[s];
     const int m = d.m, n = d.n;
     const int t = threadIdx.x, lane = t % WAVE;
@@ -572,8 +572,8 @@ constexpr int ADM_DA = 4;
 constexpr int ADM_DB = 8;
 
 template <int Q, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_adm_ell(
-    const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, uint64_t seed, int32_t max_iter,
+__device__ void adm_ell_slice(
+    int s, const SliceDesc *__restrict__ desc, uint64_t seed, int32_t max_iter,
     int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma, const int32_t *__restrict__ col_ptr_all,
     const int32_t *__restrict__ csc_row_all, const float *__restrict__ csc_val_all, EllView ell, float *X_all,
     float *Xp_all, float *Lam_all, float *Y_all, float *Yp_all, float *Pi_all, float *Yt_all, float *red_all,
@@ -585,7 +585,6 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
     __shared__ AdmShared<Q> sh;
     __shared__ float redf[NW];
 
-    const int s = slice_list[blockIdx.x];
     const SliceDesc d = desc[s];
     const int m = d.m, n = d.n;
     const int t = threadIdx.x, lane = t % WAVE;
@@ -1112,6 +1111,59 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
     }
 }
 
+
+// The slices of slice_list[0 .. count): one workgroup per slice, or, with a
+// queue counter (zero at launch), a fixed number of workgroups that take the
+// next slice from the counter until the list is exhausted (the list is
+// ordered by decreasing cost, so the queue runs longest-first).
+__device__ __forceinline__ bool next_slice(int32_t *queue, int32_t count, int &k, int &state) {
+    __shared__ int32_t taken;
+    if (!queue) {
+        k = blockIdx.x;
+        return state++ == 0 && k < count;
+    }
+    if (threadIdx.x == 0) taken = atomicAdd(queue, 1);
+    __syncthreads();
+    k = taken;
+    __syncthreads();
+    return k < count;
+}
+
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_adm(
+    const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, int32_t count, int32_t *queue,
+    uint64_t seed, int32_t max_iter, int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma,
+    const int32_t *__restrict__ row_ptr_all, const int32_t *__restrict__ csr_col_all,
+    const float *__restrict__ csr_val_all, const int32_t *__restrict__ col_ptr_all,
+    const int32_t *__restrict__ csc_row_all, const float *__restrict__ csc_val_all, float *X_all,
+    float *Xn_all, float *Xp_all, float *Lam_all, float *Y_all, float *Yp_all, float *Pi_all,
+    float *scale_all, int32_t *stats_all) {
+    int k, state = 0;
+    while (next_slice(queue, count, k, state)) {
+        adm_global_slice<Q, THREADS>(slice_list[k], desc, seed, max_iter, fixed_iters, tol, alpha0, beta0, gamma,
+                                     row_ptr_all, csr_col_all, csr_val_all, col_ptr_all, csc_row_all, csc_val_all,
+                                     X_all, Xn_all, Xp_all, Lam_all, Y_all, Yp_all, Pi_all, scale_all, stats_all);
+        __syncthreads();
+    }
+}
+
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_adm_ell(
+    const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, int32_t count, int32_t *queue,
+    uint64_t seed, int32_t max_iter, int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma,
+    const int32_t *__restrict__ col_ptr_all, const int32_t *__restrict__ csc_row_all,
+    const float *__restrict__ csc_val_all, EllView ell, float *X_all, float *Xp_all, float *Lam_all, float *Y_all,
+    float *Yp_all, float *Pi_all, float *Yt_all, float *red_all, double *e2part_all, float *scale_all,
+    int32_t *stats_all) {
+    int k, state = 0;
+    while (next_slice(queue, count, k, state)) {
+        adm_ell_slice<Q, THREADS>(slice_list[k], desc, seed, max_iter, fixed_iters, tol, alpha0, beta0, gamma,
+                                  col_ptr_all, csc_row_all, csc_val_all, ell, X_all, Xp_all, Lam_all, Y_all, Yp_all,
+                                  Pi_all, Yt_all, red_all, e2part_all, scale_all, stats_all);
+        __syncthreads();
+    }
+}
+
 // I^c_i = s0 sum_k X_ik (sum_j Y[j][c][k]), FP64 accumulation; one workgroup per slice.
 __global__ __launch_bounds__(256) void k_reduce(const SliceDesc *__restrict__ desc,
                                                  const int32_t *__restrict__ pt_ids,
@@ -1158,13 +1210,32 @@ __global__ __launch_bounds__(256) void k_reduce(const SliceDesc *__restrict__ de
     }
 }
 
+// grid of a launch over `count` slices: one workgroup per slice, or with a
+// queue as many workgroups as fit on the device at once (at most count)
+template <typename K>
+int adm_grid(K kern, int threads, size_t dyn, int n_cu, bool queue, size_t count, unsigned &grid) {
+    grid = (unsigned)count;
+    if (!queue) return VPLMC_OK;
+    int per_cu = 0;
+    VPLMC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, dyn));
+    const size_t g = (size_t)std::max(per_cu, 1) * (size_t)std::max(n_cu, 1);
+    grid = (unsigned)std::min(count, g);
+    return VPLMC_OK;
+}
+
 template <int Q, int THREADS>
-int launch_adm_global(hipStream_t st, size_t count, const int32_t *ids_dev, const SliceDesc *desc,
-                      const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
-                      const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, float *X, float *Xn,
-                      float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale, int32_t *stats) {
+int launch_adm_global(hipStream_t st, size_t count, const int32_t *ids_dev, int32_t *queue, int n_cu,
+                      const SliceDesc *desc, const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col,
+                      const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
+                      float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale,
+                      int32_t *stats) {
     if (count == 0) return VPLMC_OK;
-    hipLaunchKernelGGL((k_adm<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, desc, ids_dev, prm.seed,
+    auto kern = k_adm<Q, THREADS>;
+    unsigned grid;
+    int rc;
+    if ((rc = adm_grid(kern, THREADS, 0, n_cu, queue != nullptr, count, grid))) return rc;
+    if (queue && (rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(queue), 1, 0u))) return rc;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(THREADS), 0, st, desc, ids_dev, (int32_t)count, queue, prm.seed,
                        prm.max_iter, (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0,
                        prm.gamma, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi,
                        scale, stats);
@@ -1172,52 +1243,72 @@ int launch_adm_global(hipStream_t st, size_t count, const int32_t *ids_dev, cons
     return VPLMC_OK;
 }
 
-template <int Q>
-int launch_adm_ell(hipStream_t st, size_t count, int max_m, const int32_t *ids_dev, const SliceDesc *desc,
-                   const vplmc_params &prm, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
-                   const EllView &ell, float *X, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt,
-                   float *red, double *e2part, float *scale, int32_t *stats) {
-    if (count == 0) return VPLMC_OK;
-    constexpr int T = adm_lds_threads(Q);
+template <int Q, int T>
+int launch_adm_ell_t(hipStream_t st, size_t count, int max_m, const int32_t *ids_dev, int32_t *queue, int n_cu,
+                     const SliceDesc *desc, const vplmc_params &prm, const int32_t *col_ptr, const int32_t *csc_row,
+                     const float *csc_val, const EllView &ell, float *X, float *Xp, float *Lam, float *Y, float *Yp,
+                     float *Pi, float *Yt, float *red, double *e2part, float *scale, int32_t *stats) {
     const size_t dyn = adm_lds_dynamic_bytes(Q, max_m);
     auto kern = k_adm_ell<Q, T>;
     VPLMC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-    hipLaunchKernelGGL(kern, dim3((unsigned)count), dim3(T), dyn, st, desc, ids_dev, prm.seed, prm.max_iter,
-                       (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0, prm.gamma, col_ptr,
-                       csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale, stats);
+    unsigned grid;
+    int rc;
+    if ((rc = adm_grid(kern, T, dyn, n_cu, queue != nullptr, count, grid))) return rc;
+    if (queue && (rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(queue), 1, 0u))) return rc;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(T), dyn, st, desc, ids_dev, (int32_t)count, queue, prm.seed,
+                       prm.max_iter, (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0,
+                       prm.gamma, col_ptr, csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale,
+                       stats);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
 
+template <int Q>
+int launch_adm_ell(hipStream_t st, int threads, size_t count, int max_m, const int32_t *ids_dev, int32_t *queue,
+                   int n_cu, const SliceDesc *desc, const vplmc_params &prm, const int32_t *col_ptr,
+                   const int32_t *csc_row, const float *csc_val, const EllView &ell, float *X, float *Xp, float *Lam,
+                   float *Y, float *Yp, float *Pi, float *Yt, float *red, double *e2part, float *scale,
+                   int32_t *stats) {
+    if (count == 0) return VPLMC_OK;
+    if (threads == 512)
+        return launch_adm_ell_t<Q, 512>(st, count, max_m, ids_dev, queue, n_cu, desc, prm, col_ptr, csc_row, csc_val,
+                                        ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale, stats);
+    return launch_adm_ell_t<Q, 1024>(st, count, max_m, ids_dev, queue, n_cu, desc, prm, col_ptr, csc_row, csc_val,
+                                     ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale, stats);
+}
+
 }  // namespace
 
-int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
-               const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
-               const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, const EllView &ell, float *X,
-               float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt, float *red, double *e2part,
-               float *scale, int32_t *stats) {
+int launch_adm(hipStream_t st, const vplmc_plan &plan, int n_cu, const SliceDesc *desc, const int32_t *ids_dev,
+               int32_t *queues, const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col,
+               const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
+               const EllView &ell, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
+               float *Yt, float *red, double *e2part, float *scale, int32_t *stats) {
     // ids_dev holds the slice ids of groups 0..7 in order (2 * rank bucket + variant)
     size_t base[9] = {0};
     for (int g = 0; g < 8; ++g) base[g + 1] = base[g] + plan.groups[g].size();
     const int32_t *id[8];
     for (int g = 0; g < 8; ++g) id[g] = ids_dev + base[g];
+    const bool qm = plan.tune.adm_queue != 0;
+    auto qp = [&](int g) { return qm ? queues + g : nullptr; };
+    const int thr = plan.tune.adm_threads;
     int rc;
 #define VPLMC_ADM_PAIR(B, Q, TG)                                                                                   \
-    if ((rc = launch_adm_ell<Q>(st, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], desc, prm,       \
-                                col_ptr, csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale,      \
-                                stats)))                                                                           \
+    if ((rc = launch_adm_ell<Q>(st, thr, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], qp(2 * B), \
+                                n_cu, desc, prm, col_ptr, csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red,    \
+                                e2part, scale, stats)))                                                            \
         return rc;                                                                                                 \
-    if ((rc = launch_adm_global<Q, TG>(st, plan.groups[2 * B + 1].size(), id[2 * B + 1], desc, prm, row_ptr,      \
-                                       csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi,      \
-                                       scale, stats)))                                                             \
+    if ((rc = launch_adm_global<Q, TG>(st, plan.groups[2 * B + 1].size(), id[2 * B + 1], qp(2 * B + 1), n_cu, desc, \
+                                       prm, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam,   \
+                                       Y, Yp, Pi, scale, stats)))                                                  \
         return rc;
     VPLMC_ADM_PAIR(0, 4, 1024)
     VPLMC_ADM_PAIR(1, 8, 512)
     VPLMC_ADM_PAIR(2, 16, 512)
-    if ((rc = launch_adm_global<32, 256>(st, plan.groups[6].size() + plan.groups[7].size(), id[6], desc, prm, row_ptr,
-                                         csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi,
-                                         scale, stats)))
+    if ((rc = launch_adm_global<32, 256>(st, plan.groups[6].size() + plan.groups[7].size(), id[6], qp(6), n_cu, desc,
+                                         prm, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y,
+                                         Yp, Pi, scale, stats)))
         return rc;
 #undef VPLMC_ADM_PAIR
     return VPLMC_OK;

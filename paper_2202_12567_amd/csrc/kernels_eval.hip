@@ -304,9 +304,10 @@ int launch_targets(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc
 int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
                       int32_t n_lights, const SliceDesc *desc, int32_t n_slices, const int32_t *pt_ids,
                       const int32_t *cl_ids, const uint32_t *keys, int64_t n_keys, int which,
-                      const int32_t *stats, const vplmc_params &prm, float *vals) {
+                      const int32_t *stats, const vplmc_params &prm, float *vals, int threads) {
     if (n_keys <= 0) return VPLMC_OK;
-    hipLaunchKernelGGL(k_eval_omega, dim3(blocks_for(n_keys, 256)), dim3(256), 0, st, bvh, pts, lights, n_lights,
+    if (threads != 64 && threads != 128 && threads != 256) threads = 256;   // __launch_bounds__(256)
+    hipLaunchKernelGGL(k_eval_omega, dim3(blocks_for(n_keys, threads)), dim3(threads), 0, st, bvh, pts, lights, n_lights,
                        desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats, prm.r_min * prm.r_min,
                        prm.ray_eps, vals);
     VPLMC_HIP(hipGetLastError());

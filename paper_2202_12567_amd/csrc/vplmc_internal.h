@@ -156,6 +156,7 @@ enum {
     R_YT,            // float[n][3][q]: staging of the right-hand sides of the Y update
     R_ADM_RED,       // float per slice: ADM_RED_FLOATS
     R_E2PART,        // double per part slot: squared residual over the part's samples
+    R_QUEUE,         // int32[8]: work-queue counters of the completion launches
     R_INTERNAL_END
 };
 
@@ -180,6 +181,7 @@ struct vplmc_ctx {
     int prof_max_frames = 0;
     int prof_frames = 0;
     bool prof_on = false;
+    bool capturing = false;                     // a frame is being recorded into a graph
 };
 
 struct vplmc_plan {
@@ -197,6 +199,7 @@ struct vplmc_plan {
     int64_t tot_bm = 0, tot_bmt = 0;
     int64_t tot_grp = 0, tot_ell = 0, n_ell = 0;   // ELL group table entries, ELL entries, ELL slices
     int64_t tot_part = 0;                           // part slots
+    vplmc_tune tune = {0, 1024, 256, 0};             // launch shapes
     std::vector<int32_t> ids;                  // slice ids grouped by rank bucket
     std::vector<char> upload;                  // descriptor table + ids, as copied to the workspace
 };
@@ -226,7 +229,7 @@ int launch_pass1(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, 
 int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
                       int32_t n_lights, const SliceDesc *desc, int32_t n_slices, const int32_t *pt_ids,
                       const int32_t *cl_ids, const uint32_t *keys, int64_t n_keys, int which_pass,
-                      const int32_t *stats, const vplmc_params &prm, float *vals);
+                      const int32_t *stats, const vplmc_params &prm, float *vals, int threads = 256);
 int launch_colstats(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *omega1,
                     const float *val1, const uint32_t *bmt, uint16_t *wpret, int32_t *col_ptr, int32_t *csc_row,
                     float *csc_val, int32_t *cnt, float *mn, float *mx, double *sum, double *sumsq, int32_t *zeros);
@@ -257,11 +260,11 @@ int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, c
                 const uint32_t *omega1, const float *val1, const uint32_t *omega2, const float *val2,
                 const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, float *csc_val,
                 const EllView &ell);
-int launch_adm(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
-               const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
-               const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, const EllView &ell, float *X,
-               float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *Yt, float *red, double *e2part,
-               float *scale, int32_t *stats);
+int launch_adm(hipStream_t st, const vplmc_plan &plan, int n_cu, const SliceDesc *desc, const int32_t *ids_dev,
+               int32_t *queues, const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col,
+               const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
+               const EllView &ell, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
+               float *Yt, float *red, double *e2part, float *scale, int32_t *stats);
 int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,
                   const float *X, const float *Y, const float *scale, float *radiance);
 int launch_eval_pairs(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,

@@ -136,3 +136,23 @@ def test_calls_without_a_context_fail_cleanly():
     assert lib.vplmc_set_stream(None, None) == N.EINVAL
     assert lib.vplmc_philox4x64(None, 0, 0, None, 0, None) == N.EINVAL
     assert lib.vplmc_render(None, None, None, None, None, None, None, None, None, 0, None) == N.EINVAL
+
+
+def test_launch_shapes_default_and_validation():
+    lib = N.load()
+    rc, h = plan([0, 256], [0, 1024], [16], nc=1024)
+    assert rc == 0
+    t = N.Tune()
+    assert lib.vplmc_plan_get_tune(h, ctypes.byref(t)) == 0
+    assert (t.adm_queue, t.adm_threads, t.eval_threads, t.reserved) == (0, 1024, 256, 0)
+    for bad in [(2, 1024, 256, 0), (0, 768, 256, 0), (0, 1024, 512, 0), (0, 1024, 256, 1)]:
+        assert lib.vplmc_plan_set_tune(h, ctypes.byref(N.Tune(*bad))) == N.EINVAL
+    assert lib.vplmc_plan_set_tune(h, ctypes.byref(N.Tune(1, 512, 64, 0))) == 0
+    assert lib.vplmc_plan_get_tune(h, ctypes.byref(t)) == 0
+    assert (t.adm_queue, t.adm_threads, t.eval_threads) == (1, 512, 64)
+    assert lib.vplmc_graph_destroy(None) == 0
+    out = ctypes.c_void_p()
+    assert lib.vplmc_graph_create(None, h, None, None, None, None, None, None, None, 0, None,
+                                  ctypes.byref(out)) == N.EINVAL
+    assert lib.vplmc_autotune(None, h, None, None, None, None, None, None, None, 0, None, 2, None) == N.EINVAL
+    lib.vplmc_plan_destroy(h)

@@ -1,0 +1,94 @@
+"""Batching on the GPU: every slice of an uneven frame in one launch per phase,
+the completion launched directly or from a device work queue and at either
+workgroup size, a frame captured as a HIP graph and replayed, and the
+autotuner.  Integer outputs never depend on the launch shape; the queue
+changes only which workgroup completes a slice (bit-identical radiance); a
+different completion workgroup size changes only FP summation order."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from _gpu_common import check_scene_indices, log  # noqa: E402
+from paper_2202_12567_amd import api  # noqa: E402
+from scenegen import CONFIGS, make_scene  # noqa: E402
+
+BATCH = dataclasses.replace(CONFIGS["batch"], width=320, height=200, n_spheres=256, n_vpls=8000,
+                            batch_slices=24, batch_m=(64, 2048), batch_n=(256, 1024))
+INT_REGIONS = {"OMEGA1": torch.int32, "OMEGA2": torch.int32, "WEIGHTS": torch.int32, "CSC_ROW": torch.int32,
+               "ROW_PTR": torch.int32, "COL_PTR": torch.int32}
+
+
+@pytest.fixture(scope="module")
+def setup():
+    sc = make_scene(BATCH, 21)
+    check_scene_indices(sc)
+    dev = torch.device("cuda", 0)
+    prm = api.default_params(seed=21, pass1_ppm=25000, pass2_ppm=25000, max_iter=20, fixed_iters=True)
+    ctx = api.Context(0)
+    ctx.set_occluders(sc.spheres)
+    ds = api.DeviceScene(sc, dev)
+    return sc, prm, ctx, ds, dev
+
+
+def render_with(setup, **tune):
+    sc, prm, ctx, ds, dev = setup
+    plan = api.Plan(sc, prm)
+    if tune:
+        api.set_tune(plan, **tune)
+    ws = api.workspace(plan, dev)
+    log(f"render uneven batch with {api.get_tune(plan)}")
+    rad = api.render(ctx, plan, ds, prm, ws).clone()
+    torch.cuda.synchronize()
+    ints = {k: api.region_view(plan, ws, k, dt).cpu().numpy().copy() for k, dt in INT_REGIONS.items()}
+    return rad.cpu().numpy().astype(np.float64), ints, plan, ws
+
+
+def test_queue_and_workgroup_size(setup):
+    rad0, ints0, *_ = render_with(setup)
+    rad_q, ints_q, *_ = render_with(setup, adm_queue=1)
+    rad_t, ints_t, *_ = render_with(setup, adm_queue=1, adm_threads=512, eval_threads=64)
+    for k in INT_REGIONS:
+        assert np.array_equal(ints0[k], ints_q[k]) and np.array_equal(ints0[k], ints_t[k]), k
+    assert np.array_equal(rad0, rad_q)
+    rel = np.linalg.norm(rad_t - rad0) / np.linalg.norm(rad0)
+    log(f"512- vs 1024-thread completion: relative difference {rel:.2e}")
+    assert rel <= 1e-4
+
+
+def test_graph_replays_equal_the_eager_frame(setup):
+    sc, prm, ctx, ds, dev = setup
+    plan = api.Plan(sc, prm)
+    ws = api.workspace(plan, dev)
+    rad = torch.empty((sc.m, 3), dtype=torch.float32, device=dev)
+    api.render(ctx, plan, ds, prm, ws, rad)
+    torch.cuda.synchronize()
+    eager = rad.clone()
+    g = api.Graph(ctx, plan, ds, prm, ws, rad)
+    for rep in range(3):
+        rad.fill_(-1.0)                      # eager work between replays
+        _ = (eager * 2.0).sum().item()
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(rad, eager), f"replay {rep}"
+        log(f"graph replay {rep}: equal to the eager frame")
+    g.close()
+
+
+def test_autotune_picks_a_valid_shape(setup):
+    sc, prm, ctx, ds, dev = setup
+    plan = api.Plan(sc, prm)
+    ws = api.workspace(plan, dev)
+    rad = torch.empty((sc.m, 3), dtype=torch.float32, device=dev)
+    best = api.autotune(ctx, plan, ds, prm, ws, rad, reps=1)
+    log(f"autotune: {best}")
+    assert best == api.get_tune(plan)
+    assert best["adm_queue"] in (0, 1) and best["adm_threads"] in (512, 1024) and best["eval_threads"] in (64, 128, 256)
+    rad0, *_ = render_with(setup)
+    got = api.render(ctx, plan, ds, prm, ws, rad).cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - rad0) / np.linalg.norm(rad0) <= 1e-4
