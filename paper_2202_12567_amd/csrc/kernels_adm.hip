@@ -61,10 +61,19 @@ struct AdmShared {
     double red[32];
 };
 
+// threadIdx.x behind an empty asm statement: what is derived from it is
+// recomputed where it is used, not hoisted out of the iteration loop or
+// shared between phases, where it would hold registers through every phase
+__device__ __forceinline__ int fresh_tid() {
+    int x = threadIdx.x;
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // (G + shift I)^-1 in FP64 by Cholesky; result in sh.Inv.  All threads call.
 template <int Q>
 __device__ void spd_inverse(AdmShared<Q> &sh, double shift) {
-    const int t = threadIdx.x;
+    const int t = fresh_tid();
     for (int e = t; e < Q * Q; e += blockDim.x) {
         const int a = e / Q, b = e % Q;
         sh.A[e] = (double)sh.G[e] + (a == b ? shift : 0.0);
@@ -516,8 +525,19 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // block-wide maximum of per-thread values; every thread calls it and gets the result
+// a value every lane holds alike, moved to scalar registers
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uni(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xFFFFFFFFll)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ float block_max(float v, float *red) {
-    const int nw = blockDim.x / WAVE, lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    const int t = fresh_tid(), nw = blockDim.x / WAVE, lane = t % WAVE, w = t / WAVE;
     v = wave_max(v);
     __syncthreads();
     if (lane == 0) red[w] = v;
@@ -525,7 +545,7 @@ __device__ __forceinline__ float block_max(float v, float *red) {
     float r = red[0];
     for (int k = 1; k < nw; ++k) r = fmaxf(r, red[k]);
     __syncthreads();
-    return r;
+    return uni(r);
 }
 
 // Sum over the wavefronts of two per-wavefront 16 x 16 partials (result
@@ -533,7 +553,7 @@ __device__ __forceinline__ float block_max(float v, float *red) {
 // q x q corners land in out0 and out1 (out1 may be null).  All threads call.
 template <int Q, int NW>
 __device__ void sum_partials(const f4 &p0, const f4 &p1, float *red, float *out0, float *out1) {
-    const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+    const int t = fresh_tid(), lane = t % WAVE, w = t / WAVE;
     const int rr = 4 * (lane / 16), cc = lane % 16;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -570,6 +590,8 @@ constexpr int ADM_CVT_ELEMS = 18 * 1024;
 // ELL entries a lane loads at once in phase A and in phase B
 constexpr int ADM_DA = 4;
 constexpr int ADM_DB = 8;
+// split-column sums a thread gathers before it stores them
+constexpr int ADM_CMB = 4;
 
 template <int Q, int THREADS>
 __device__ void adm_ell_slice(
@@ -606,7 +628,7 @@ __device__ void adm_ell_slice(
     float *Xp = Xp_all + d.off_x;
     float *Lam = Lam_all + d.off_x;
     float *Y = Y_all + d.off_y;
-    float *Yp = Yp_all + d.off_y;
+    float *W = Yp_all + d.off_y;          // W = b V - P: all that phase B needs of V and P
     float *Pi = Pi_all + d.off_y;
     float *Yt = Yt_all + d.off_y;
     float *red = red_all + d.off_red;
@@ -636,6 +658,8 @@ __device__ void adm_ell_slice(
         tot += sh.red[w];
         totsq += sh.red[16 + w];
     }
+    tot = uni(tot);
+    totsq = uni(totsq);
     __syncthreads();
     if (!(nnz > 0 && tot > 0.0)) {
         for (int e = t; e < m * Q; e += THREADS) Xg[e] = 0.f;
@@ -664,13 +688,14 @@ __device__ void adm_ell_slice(
         Lam[e] = 0.f;
     }
     float ym0 = 0.f;
+    const float beta0_f = (float)((double)beta0 * (double)m / Q);
     for (int e = t; e < 3 * n * Q; e += THREADS) {
         const int j = e / (3 * Q), c = (e / Q) % 3, k = e % Q;
         const uint64_t col = (uint64_t)c * (uint64_t)n + (uint64_t)j;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)k, col, TAG_INITY, 0);
         const float v = __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq);
         Y[e] = v;
-        Yp[e] = v;
+        W[e] = __fmul_rn(beta0_f, v);                 // b V_0 - P_0 with V_0 = Y_0, P_0 = 0
         Pi[e] = 0.f;
         ym0 = fmaxf(ym0, v);
     }
@@ -737,40 +762,41 @@ __device__ void adm_ell_slice(
     const float alpha_f = (float)alpha, beta_f = (float)beta;
     const float ga = (float)((double)gamma * alpha), gb = (float)((double)gamma * beta);
     const float inv_alpha = (float)(1.0 / alpha), inv_beta = (float)(1.0 / beta);
-    // lane's part in group g (sorted position 64 g + lane): column j, part u,
-    // its length cnt, its number pc in column order and the column's part count np
-    auto part_of = [&](int g, int &j, int &cnt, int &pc, int &np) {
-        const int sp = 64 * g + lane;
-        j = 0;
-        cnt = 0;
-        pc = 0;
-        np = 1;
-        if (sp < P) {
-            const int v = part[sp];
-            j = v & 0xFFFF;
-            const int u = v >> 16;
-            const int c = col_ptr[j + 1] - col_ptr[j];
-            np = c > ELL_LMAX ? (c + ELL_LMAX - 1) / ELL_LMAX : 1;
-            const int l = (c + np - 1) / np;
-            cnt = min(l, c - u * l);
-            pc = pbase[j] + u;
-        }
-    };
-    // right-hand operands of the dense updates: F[l][k] and Inv[l][k] (FP64),
-    // zero outside q x q; lane holds row 4 v + lane / 16, column lane % 16
-    auto load_rhs = [&](float *b1, float *b2) {
-        const int c = lane % 16;
-#pragma unroll
-        for (int v = 0; v < QV; ++v) {
-            const int l = 4 * v + lane / 16;
-            b1[v] = c < Q ? (float)sh.F[l * Q + c] : 0.f;
-            b2[v] = c < Q ? (float)sh.Inv[l * Q + c] : 0.f;
-        }
-    };
-
     int iters = max_iter;
     double err = 0.0;
     for (int it = 0; it < max_iter; ++it) {
+        // a fresh thread index in every phase (fresh_tid)
+        int t = fresh_tid(), lane = t % WAVE;
+        // lane's part in group g (sorted position 64 g + lane): column j, part u,
+        // its length cnt, its number pc in column order and the column's part count np
+        auto part_of = [&](int g, int &j, int &cnt, int &pc, int &np) {
+            const int sp = 64 * g + lane;
+            j = 0;
+            cnt = 0;
+            pc = 0;
+            np = 1;
+            if (sp < P) {
+                const int v = part[sp];
+                j = v & 0xFFFF;
+                const int u = v >> 16;
+                const int c = col_ptr[j + 1] - col_ptr[j];
+                np = c > ELL_LMAX ? (c + ELL_LMAX - 1) / ELL_LMAX : 1;
+                const int l = (c + np - 1) / np;
+                cnt = min(l, c - u * l);
+                pc = pbase[j] + u;
+            }
+        };
+        // right-hand operands of the dense updates: F[l][k] and Inv[l][k] (FP64),
+        // zero outside q x q; lane holds row 4 v + lane / 16, column lane % 16
+        auto load_rhs = [&](float *b1, float *b2) {
+            const int c = lane % 16;
+#pragma unroll
+            for (int v = 0; v < QV; ++v) {
+                const int l = 4 * v + lane / 16;
+                b1[v] = c < Q ? (float)sh.F[l * Q + c] : 0.f;
+                b2[v] = c < Q ? (float)sh.Inv[l * Q + c] : 0.f;
+            }
+        };
         // ---- phase A: residuals, 2^S R Y^T into XB ----
         int32_t *RXI = reinterpret_cast<int32_t *>(XB);
         int Sr = pow2_below(2147483648.0, Krow * rs_est);
@@ -874,6 +900,9 @@ __device__ void adm_ell_slice(
                 rsc = fmaxf(rsc, redf[w]);
                 rsw_max = fmax(rsw_max, sh.red[16 + w]);
             }
+            e2t = uni(e2t);
+            rsc = uni(rsc);
+            rsw_max = uni(rsw_max);
             __syncthreads();
             // every integer sum provably fits, or the residuals are not finite
             const double rsb = (double)rsc * (1.0 + 1e-5);
@@ -898,6 +927,8 @@ __device__ void adm_ell_slice(
         }
 
         // ---- T = 2^-S RX + a U - L into XB (row stride q) ----
+        t = fresh_tid();
+        lane = t % WAVE;
         {
             const float ifx = ldexpf(1.f, -S);
             constexpr int CVT = ADM_CVT_ELEMS / THREADS;   // per thread
@@ -919,6 +950,8 @@ __device__ void adm_ell_slice(
             }
         }
         // ---- X system: Inv = (GY + a I)^-1, F = GY Inv ----
+        t = fresh_tid();
+        lane = t % WAVE;
         spd_inverse<Q>(sh, alpha);           // begins and ends with a barrier
         for (int e = t; e < Q * Q; e += THREADS) {
             const int a = e / Q, b = e % Q;
@@ -928,6 +961,8 @@ __device__ void adm_ell_slice(
         }
         __syncthreads();
         // ---- X+ = X F + T Inv (FP64 MFMA), U, L, Grams X+^T X+ and X+^T X ----
+        t = fresh_tid();
+        lane = t % WAVE;
         {
             float b1[QV], b2[QV];
             load_rhs(b1, b2);
@@ -964,6 +999,8 @@ __device__ void adm_ell_slice(
             sum_partials<Q, NW>(gx, cx, red, sh.G, sh.C);
         }
         // ---- Y system: Inv = (GX + b I)^-1, F[l][k] = (Inv C)[k][l] ----
+        t = fresh_tid();
+        lane = t % WAVE;
         spd_inverse<Q>(sh, beta);
         for (int e = t; e < Q * Q; e += THREADS) {
             const int a = e / Q, b = e % Q;
@@ -973,6 +1010,8 @@ __device__ void adm_ell_slice(
         }
         __syncthreads();
         // ---- phase B: T_j = X+^T R_j + b V_j - P_j (columns of several parts: partial sums) ----
+        t = fresh_tid();
+        lane = t % WAVE;
         for (int g = wave; g < G; g += NW) {
             int j, cnt, pc, np;
             part_of(g, j, cnt, pc, np);
@@ -1013,18 +1052,17 @@ __device__ void adm_ell_slice(
             }
             if (64 * g + lane < P) {
                 if (np == 1) {
+                    // every load before the first store: loads and stores share
+                    // one in-order counter, so a load after a store waits for it
                     const size_t o = (size_t)j * 3 * Q;
+                    float4 wv[3 * Q / 4];
 #pragma unroll
-                    for (int v = 0; v < 3 * Q / 4; ++v) {
-                        const float4 yp = reinterpret_cast<const float4 *>(Yp + o)[v];
-                        const float4 pi = reinterpret_cast<const float4 *>(Pi + o)[v];
-                        float4 tt;
-                        tt.x = acc[4 * v] + (beta_f * yp.x - pi.x);
-                        tt.y = acc[4 * v + 1] + (beta_f * yp.y - pi.y);
-                        tt.z = acc[4 * v + 2] + (beta_f * yp.z - pi.z);
-                        tt.w = acc[4 * v + 3] + (beta_f * yp.w - pi.w);
-                        reinterpret_cast<float4 *>(Yt + o)[v] = tt;
-                    }
+                    for (int v = 0; v < 3 * Q / 4; ++v) wv[v] = reinterpret_cast<const float4 *>(W + o)[v];
+#pragma unroll
+                    for (int v = 0; v < 3 * Q / 4; ++v)
+                        reinterpret_cast<float4 *>(Yt + o)[v] =
+                            make_float4(acc[4 * v] + wv[v].x, acc[4 * v + 1] + wv[v].y, acc[4 * v + 2] + wv[v].z,
+                                        acc[4 * v + 3] + wv[v].w);
                 } else {
                     float4 *pp = reinterpret_cast<float4 *>(partial + (size_t)pc * 3 * Q);
 #pragma unroll
@@ -1036,47 +1074,80 @@ __device__ void adm_ell_slice(
         __threadfence_block();
         __syncthreads();
         // columns of several parts: sum their partials in part order
+        t = fresh_tid();
+        lane = t % WAVE;
         const int nsplit = ell.nsplit[s];
-        for (int e = t; e < nsplit * (3 * Q / 4); e += THREADS) {
-            const int j = ell.split[d.off_col + e / (3 * Q / 4)], v = e % (3 * Q / 4);
-            const int p0 = pbase[j], p1 = pbase[j + 1];
-            {
-                float4 a = reinterpret_cast<const float4 *>(partial + (size_t)p0 * 3 * Q)[v];
-                for (int u = p0 + 1; u < p1; ++u) {
-                    const float4 b = reinterpret_cast<const float4 *>(partial + (size_t)u * 3 * Q)[v];
-                    a.x += b.x;
-                    a.y += b.y;
-                    a.z += b.z;
-                    a.w += b.w;
+        const int ncmb = nsplit * (3 * Q / 4);
+        for (int e0 = t; e0 < ncmb; e0 += ADM_CMB * THREADS) {
+            float4 a[ADM_CMB];
+            size_t o[ADM_CMB];
+#pragma unroll
+            for (int b = 0; b < ADM_CMB; ++b) {
+                const int e = e0 + b * THREADS;
+                a[b] = make_float4(0.f, 0.f, 0.f, 0.f);
+                o[b] = 0;
+                if (e < ncmb) {
+                    const int j = ell.split[d.off_col + e / (3 * Q / 4)], v = e % (3 * Q / 4);
+                    const int p0 = pbase[j], p1 = pbase[j + 1];
+                    a[b] = reinterpret_cast<const float4 *>(partial + (size_t)p0 * 3 * Q)[v];
+                    for (int u = p0 + 1; u < p1; ++u) {
+                        const float4 c = reinterpret_cast<const float4 *>(partial + (size_t)u * 3 * Q)[v];
+                        a[b].x += c.x;
+                        a[b].y += c.y;
+                        a[b].z += c.z;
+                        a[b].w += c.w;
+                    }
+                    o[b] = (size_t)j * 3 * Q + 4 * v;
+                    const float4 w = *reinterpret_cast<const float4 *>(W + o[b]);
+                    a[b].x += w.x;
+                    a[b].y += w.y;
+                    a[b].z += w.z;
+                    a[b].w += w.w;
                 }
-                const size_t o = (size_t)j * 3 * Q;
-                const float4 yp = reinterpret_cast<const float4 *>(Yp + o)[v];
-                const float4 pi = reinterpret_cast<const float4 *>(Pi + o)[v];
-                float4 tt;
-                tt.x = a.x + (beta_f * yp.x - pi.x);
-                tt.y = a.y + (beta_f * yp.y - pi.y);
-                tt.z = a.z + (beta_f * yp.z - pi.z);
-                tt.w = a.w + (beta_f * yp.w - pi.w);
-                reinterpret_cast<float4 *>(Yt + o)[v] = tt;
             }
+#pragma unroll
+            for (int b = 0; b < ADM_CMB; ++b)
+                if (e0 + b * THREADS < ncmb) *reinterpret_cast<float4 *>(Yt + o[b]) = a[b];
         }
         __threadfence_block();
         __syncthreads();
         // ---- Y+ = Y F + T Inv (FP64 MFMA) over the 3n rows, V, P, Gram Y+^T Y+ ----
+        t = fresh_tid();
+        lane = t % WAVE;
         {
             float b1[QV], b2[QV];
             load_rhs(b1, b2);
             f4 gy = {0.f, 0.f, 0.f, 0.f};
             const f4 zero = {0.f, 0.f, 0.f, 0.f};
             float ymx = 0.f;
+            // tile r0: Y and T in the MFMA operand layout (row lane % 16,
+            // column 4 v + lane / 16), P in the result layout; indices clamped
+            // into the slice, values outside it masked at use
+            auto load_tile = [&](int r0, float *ya, float *ta, float *pa) {
+                const int ra = min(r0 + lane % 16, R3 - 1);
+#pragma unroll
+                for (int v = 0; v < QV; ++v) {
+                    const size_t e = (size_t)ra * Q + 4 * v + lane / 16;
+                    ya[v] = Y[e];
+                    ta[v] = Yt[e];
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = min(r0 + 4 * (lane / 16) + v, R3 - 1), c = min(lane % 16, Q - 1);
+                    pa[v] = Pi[(size_t)r * Q + c];
+                }
+            };
+            float ya[QV], ta[QV], pa[4];
+            if (16 * wave < R3) load_tile(16 * wave, ya, ta, pa);
             for (int r0 = 16 * wave; r0 < R3; r0 += 16 * NW) {
-                const int ra = r0 + lane % 16;
+                float yb[QV], tb[QV], pb[4];
+                if (r0 + 16 * NW < R3) load_tile(r0 + 16 * NW, yb, tb, pb);
+                const bool rok = r0 + lane % 16 < R3;
                 f4 D = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int v = 0; v < QV; ++v) {
-                    const int kk = 4 * v + lane / 16;
-                    D = mfma16(ra < R3 ? Y[(size_t)ra * Q + kk] : 0.f, b1[v], D);
-                    D = mfma16(ra < R3 ? Yt[(size_t)ra * Q + kk] : 0.f, b2[v], D);
+                    D = mfma16(rok ? ya[v] : 0.f, b1[v], D);
+                    D = mfma16(rok ? ta[v] : 0.f, b2[v], D);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -1085,15 +1156,23 @@ __device__ void adm_ell_slice(
                     const float yn = ok ? D[v] : 0.f;
                     if (ok) {
                         const size_t e = (size_t)r * Q + c;
-                        const float pi = Pi[e];
+                        const float pi = pa[v];
                         const float u = fmaxf(0.f, yn + pi * inv_beta);
-                        Yp[e] = u;
-                        Pi[e] = pi + gb * (yn - u);
+                        const float pn = pi + gb * (yn - u);
+                        W[e] = fmaf(beta_f, u, -pn);
+                        Pi[e] = pn;
                         Y[e] = yn;
                         ymx = fmaxf(ymx, fabsf(yn));
                     }
                     gy = mfma16(yn, yn, gy);
                 }
+#pragma unroll
+                for (int v = 0; v < QV; ++v) {
+                    ya[v] = yb[v];
+                    ta[v] = tb[v];
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pa[v] = pb[v];
             }
             __threadfence_block();
             sum_partials<Q, NW>(gy, zero, red, sh.G, nullptr);
@@ -1124,7 +1203,7 @@ __device__ __forceinline__ bool next_slice(int32_t *queue, int32_t count, int &k
     }
     if (threadIdx.x == 0) taken = atomicAdd(queue, 1);
     __syncthreads();
-    k = taken;
+    k = __builtin_amdgcn_readfirstlane(taken);     // uniform: descriptors and pointers stay scalar
     __syncthreads();
     return k < count;
 }
@@ -1140,7 +1219,7 @@ __global__ __launch_bounds__(THREADS) void k_adm(
     float *scale_all, int32_t *stats_all) {
     int k, state = 0;
     while (next_slice(queue, count, k, state)) {
-        adm_global_slice<Q, THREADS>(slice_list[k], desc, seed, max_iter, fixed_iters, tol, alpha0, beta0, gamma,
+        adm_global_slice<Q, THREADS>(__builtin_amdgcn_readfirstlane(slice_list[k]), desc, seed, max_iter, fixed_iters, tol, alpha0, beta0, gamma,
                                      row_ptr_all, csr_col_all, csr_val_all, col_ptr_all, csc_row_all, csc_val_all,
                                      X_all, Xn_all, Xp_all, Lam_all, Y_all, Yp_all, Pi_all, scale_all, stats_all);
         __syncthreads();
@@ -1157,7 +1236,7 @@ __global__ __launch_bounds__(THREADS) void k_adm_ell(
     int32_t *stats_all) {
     int k, state = 0;
     while (next_slice(queue, count, k, state)) {
-        adm_ell_slice<Q, THREADS>(slice_list[k], desc, seed, max_iter, fixed_iters, tol, alpha0, beta0, gamma,
+        adm_ell_slice<Q, THREADS>(__builtin_amdgcn_readfirstlane(slice_list[k]), desc, seed, max_iter, fixed_iters, tol, alpha0, beta0, gamma,
                                   col_ptr_all, csc_row_all, csc_val_all, ell, X_all, Xp_all, Lam_all, Y_all, Yp_all,
                                   Pi_all, Yt_all, red_all, e2part_all, scale_all, stats_all);
         __syncthreads();
