@@ -357,14 +357,14 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     bytes[R_COLSUMSQ] = oc * 8;
     bytes[R_COLZERO] = oc * 4;
     bytes[R_SLICE_GEO] = S * 8 * 4;
-    bytes[R_ELL_PART] = plan->tot_part * 4;
+    bytes[R_ELL_PART] = plan->tot_part * 8;
     bytes[R_ELL_PPOS] = plan->tot_part * 4;
     bytes[R_ELL_PBASE] = ocp * 4;
     bytes[R_ELL_PARTIAL] = plan->tot_part * 48 * 4;
     bytes[R_ELL_GRP] = plan->tot_grp * 4;
     bytes[R_ELL_SPLIT] = oc * 4;
     bytes[R_ELL_NSPLIT] = S * 4;
-    bytes[R_ELL_ROW] = plan->tot_ell * 4;
+    bytes[R_ELL_ROW] = plan->tot_ell * 2;
     bytes[R_ELL_VAL] = 3 * plan->tot_ell * 4;
     bytes[R_ELL_RES] = 3 * plan->tot_ell * 4;
     bytes[R_YT] = oy * 4;
@@ -532,14 +532,14 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     int32_t *csr_col = region<int32_t>(ws, plan, VPLMC_R_CSR_COL);
     float *csr_val = region<float>(ws, plan, VPLMC_R_CSR_VAL);
     EllView ell;
-    ell.part = region<int32_t>(ws, plan, R_ELL_PART);
+    ell.part = region<int2>(ws, plan, R_ELL_PART);
     ell.ppos = region<int32_t>(ws, plan, R_ELL_PPOS);
     ell.pbase = region<int32_t>(ws, plan, R_ELL_PBASE);
     ell.partial = region<float>(ws, plan, R_ELL_PARTIAL);
     ell.grp = region<int32_t>(ws, plan, R_ELL_GRP);
     ell.split = region<int32_t>(ws, plan, R_ELL_SPLIT);
     ell.nsplit = region<int32_t>(ws, plan, R_ELL_NSPLIT);
-    ell.row = plan->tot_ell > 0 ? region<int32_t>(ws, plan, R_ELL_ROW) : nullptr;
+    ell.row = plan->tot_ell > 0 ? region<uint16_t>(ws, plan, R_ELL_ROW) : nullptr;
     ell.val = region<float>(ws, plan, R_ELL_VAL);
     ell.res = region<float>(ws, plan, R_ELL_RES);
     if ((rc = launch_sort(st, *plan, desc, bm, bmt, region<uint16_t>(ws, plan, R_WPRE), region<uint16_t>(ws, plan, R_WPRET),

@@ -617,11 +617,11 @@ __device__ void adm_ell_slice(
     const int32_t *col_ptr = col_ptr_all + d.off_colptr;
     const int32_t *csc_row = csc_row_all + d.off_omega;
     const float *csc_val = csc_val_all + 3 * d.off_omega;
-    const int32_t *part = ell.part + d.off_part;
+    const int2 *part = ell.part + d.off_part;
     const int32_t *pbase = ell.pbase + d.off_colptr;
     const int32_t *grp = ell.grp + d.off_grp;
     float *partial = ell.partial + 48 * d.off_part;
-    const int32_t *erow = ell.row + d.off_ell;
+    const uint16_t *erow = ell.row + d.off_ell;
     const float *eval = ell.val + 3 * d.off_ell;
     float *eres = ell.res + 3 * d.off_ell;
     float *Xg = X_all + d.off_x;
@@ -767,23 +767,21 @@ __device__ void adm_ell_slice(
     for (int it = 0; it < max_iter; ++it) {
         // a fresh thread index in every phase (fresh_tid)
         int t = fresh_tid(), lane = t % WAVE;
-        // lane's part in group g (sorted position 64 g + lane): column j, part u,
-        // its length cnt, its number pc in column order and the column's part count np
+        // lane's part in group g (sorted position 64 g + lane): column j, its
+        // length cnt, its number pc in column order, np = 1 for a column of one
+        // part and 2 for a column of several
         auto part_of = [&](int g, int &j, int &cnt, int &pc, int &np) {
             const int sp = 64 * g + lane;
             j = 0;
             cnt = 0;
             pc = 0;
             np = 1;
-            if (sp < P) {
-                const int v = part[sp];
-                j = v & 0xFFFF;
-                const int u = v >> 16;
-                const int c = col_ptr[j + 1] - col_ptr[j];
-                np = c > ELL_LMAX ? (c + ELL_LMAX - 1) / ELL_LMAX : 1;
-                const int l = (c + np - 1) / np;
-                cnt = min(l, c - u * l);
-                pc = pbase[j] + u;
+            if (sp < P) {                    // one load: everything was packed by the part sort
+                const int2 v = part[sp];
+                j = v.x & 0xFFFF;
+                cnt = (v.x >> 16) & 0x7F;
+                np = (v.x >> 23) & 1 ? 2 : 1;
+                pc = v.y;
             }
         };
         // right-hand operands of the dense updates: F[l][k] and Inv[l][k] (FP64),
@@ -831,7 +829,7 @@ __device__ void adm_ell_slice(
                     for (int u = 0; u < ADM_DA; ++u) {
                         const bool act = k0 + u < cnt;
                         const int e = base + 64 * (k0 + u) + lane;
-                        ib[u] = act ? erow[e] : -1;
+                        ib[u] = act ? (int)erow[e] : -1;
                         mb0[u] = act ? eval[3 * e] * inv_s0 : 0.f;
                         mb1[u] = act ? eval[3 * e + 1] * inv_s0 : 0.f;
                         mb2[u] = act ? eval[3 * e + 2] * inv_s0 : 0.f;
@@ -1028,7 +1026,7 @@ __device__ void adm_ell_slice(
                 for (int u = 0; u < ADM_DB; ++u) {
                     const bool act = k0 + u < cnt;
                     const int e = base + 64 * (k0 + u) + lane;
-                    ib[u] = act ? erow[e] : -1;
+                    ib[u] = act ? (int)erow[e] : -1;
                     rb0[u] = act ? eres[3 * e] : 0.f;
                     rb1[u] = act ? eres[3 * e + 1] : 0.f;
                     rb2[u] = act ? eres[3 * e + 2] : 0.f;

@@ -512,7 +512,7 @@ __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t tot
         const int u = k2 / l, kl = k2 - u * l;
         const int32_t sp = ell.ppos[d.off_part + ell.pbase[d.off_colptr + j] + u];
         const int64_t e = d.off_ell + ell.grp[d.off_grp + (sp >> 6)] + 64 * (int64_t)kl + (sp & 63);
-        ell.row[e] = (int32_t)i;
+        ell.row[e] = (uint16_t)i;
         ell.val[3 * e] = v0;
         ell.val[3 * e + 1] = v1;
         ell.val[3 * e + 2] = v2;
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(1024) void k_partsort(const SliceDesc *__restrict__
     const int n = d.n, t = threadIdx.x;
     const int32_t *cp = col_ptr + d.off_colptr;
     int32_t *pb = ell.pbase + d.off_colptr;
-    int32_t *part = ell.part + d.off_part;
+    int2 *part = ell.part + d.off_part;
     int32_t *ppos = ell.ppos + d.off_part;
     int32_t *grp = ell.grp + d.off_grp;
     if (t <= ELL_LMAX) hist[t] = 0;
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(1024) void k_partsort(const SliceDesc *__restrict__
         part_shape(c, p, l);
         for (int u = 0; u < p; ++u) {
             const uint32_t pos = atomicAdd(&hist[min(l, c - u * l)], 1u);
-            part[pos] = j | (u << 16);
+            part[pos] = make_int2(j | (min(l, c - u * l) << 16) | ((p > 1 ? 1 : 0) << 23), pb[j] + u);
             ppos[pb[j] + u] = (int32_t)pos;
         }
     }
@@ -586,12 +586,7 @@ __global__ __launch_bounds__(1024) void k_partsort(const SliceDesc *__restrict__
         const int g = g0 + t;
         uint32_t len = 0;
         if (g < G) {
-            const int v = part[64 * g];
-            const int j = v & 0xFFFF, u = v >> 16;
-            const int c = cp[j + 1] - cp[j];
-            int p, l;
-            part_shape(c, p, l);
-            len = 64u * (uint32_t)min(l, c - u * l);
+            len = 64u * (uint32_t)((part[64 * g].x >> 16) & 0x7F);
         }
         const uint32_t ex = block_excl_scan(len, &tot, sm);
         if (g < G) grp[g] = (int32_t)(carry + ex);

@@ -110,11 +110,12 @@ struct SliceDesc {
 // padding and never read.  Parts are numbered in column order by
 // pbase[j] + t.
 struct EllView {
-    int32_t *part;     // per (slice, sorted position): column j | part t << 16
+    int2 *part;        // per (slice, sorted position): {j | len << 16 | (column of several parts) << 23,
+                       //  part number in column order}
     int32_t *ppos;     // per (slice, part in column order): sorted position
     int32_t *pbase;    // per (slice, column + 1): first part of the column (like col_ptr)
     int32_t *grp;      // per slice: groups + 1 offsets, relative to off_ell
-    int32_t *row;      // per entry: row of the sample
+    uint16_t *row;     // per entry: row of the sample (rows < ELL_MAX_M)
     float *val;        // 3 per entry: sampled values
     float *res;        // 3 per entry: residual of the current iterate
     float *partial;    // 48 per part slot: X+^T R of the part (columns cut into several parts)
@@ -143,14 +144,14 @@ enum {
     R_COLSUMSQ,      // double per (slice, column): sum of t^2
     R_COLZERO,       // int32 per (slice, column): observations with t = 0
     R_SLICE_GEO,     // float[8] per slice: centroid xyz, bbox diagonal, mean normal xyz, -
-    R_ELL_PART,      // int32 per part slot
+    R_ELL_PART,      // int2 per part slot
     R_ELL_PPOS,      // int32 per part slot
     R_ELL_PBASE,     // int32 per (slice, column + 1)
     R_ELL_PARTIAL,   // float[48] per part slot
     R_ELL_GRP,       // int32 per group slot
     R_ELL_SPLIT,     // int32 per (slice, column)
     R_ELL_NSPLIT,    // int32 per slice
-    R_ELL_ROW,       // int32 per ELL entry
+    R_ELL_ROW,       // uint16 per ELL entry
     R_ELL_VAL,       // float[3] per ELL entry
     R_ELL_RES,       // float[3] per ELL entry
     R_YT,            // float[n][3][q]: staging of the right-hand sides of the Y update
