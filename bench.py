@@ -27,8 +27,8 @@ FP32_PEAK_TFLOPS = 157.3
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mid")
     ap.add_argument("--rate", type=float, default=5.0, help="total sampling rate in percent, split evenly")
     ap.add_argument("--seed", type=int, default=11)
@@ -37,24 +37,44 @@ def parse():
     ap.add_argument("--sweep", default="0.5,1,2,3,4,5,7.5,10",
                     help="total sampling rates (percent) of the plain vs learned fixed-RMSE comparison; empty: none")
     ap.add_argument("--sweep-steps", type=int, default=2)
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager frames instead of the captured graph (for counter collection)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized buffer 3 times (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
 
 
-def frame_times(api, torch, ctx, plan, ds, prm, ws, rad, steps, warmup):
-    """Mean frame ms of the captured frame graph over `steps` launches after
-    `warmup` (device-resident inputs); `rad` holds the frame afterwards."""
-    g = api.Graph(ctx, plan, ds, prm, ws, rad)
+def copy_probe(mib):
+    """A plain device copy of known size: what FETCH_SIZE / WRITE_SIZE read for
+    it converts the counters of the other kernels to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "copies": 3}), flush=True)
+
+
+def frame_times(api, torch, ctx, plan, ds, prm, ws, rad, steps, warmup, eager=False):
+    """Mean frame ms of the captured frame graph (or of eager frames) over
+    `steps` launches after `warmup` (device-resident inputs); `rad` holds the
+    frame afterwards."""
+    g = None if eager else api.Graph(ctx, plan, ds, prm, ws, rad)
+    launch = g.launch if g else (lambda: api.render(ctx, plan, ds, prm, ws, rad))
     for _ in range(warmup):
-        g.launch()
+        launch()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
     for _ in range(steps):
-        g.launch()
+        launch()
     e1.record()
     torch.cuda.synchronize()
-    g.close()
+    if g:
+        g.close()
     return e0.elapsed_time(e1) / steps
 
 
@@ -67,6 +87,32 @@ def interp_ms_at(points, target):
             w = (np.log(target) - np.log(r0)) / (np.log(r1) - np.log(r0))
             return float(np.exp(np.log(m0) + w * (np.log(m1) - np.log(m0))))
     return None
+
+
+def source_digest():
+    """SHA-256 over the completion kernel's sources: counters taken on other
+    sources no longer describe the kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels_adm.hip", "vplmc_internal.h"):
+        with open(os.path.join(ROOT, "paper_2202_12567_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, ppm):
+    """HBM bytes per completion launch from FETCH_SIZE + WRITE_SIZE (rocprofv3
+    --pmc, one pass each, scaled by the same counters on a plain copy of known
+    size), recorded under profiles/ for this workload, rate and kernel source;
+    None when absent or stale."""
+    path = os.path.join(ROOT, "profiles", f"k_adm_ell_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("ppm") != ppm or rec.get("source_sha256") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def _oracle_slice(job):
@@ -105,6 +151,9 @@ def cpu_baseline(sc, ppm, seed):
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (slices would shard across GPUs "
               "with one radiance gather; not implemented here).", file=sys.stderr)
@@ -134,22 +183,25 @@ def main():
         proposal = torch.as_tensor(np.load(weights_path)).to(dev)
         api.set_proposal(ctx, proposal)
 
-    # the frame as a captured graph: W untimed launches, then exactly K timed ones
-    graph = api.Graph(ctx, plan, ds, prm, ws, rad)
+    # the frame as a captured graph (or eager calls on the library's stream):
+    # W untimed launches, then exactly K timed ones, an event after each
+    graph = None if args.eager else api.Graph(ctx, plan, ds, prm, ws, rad)
+    frame = graph.launch if graph else (lambda: api.render(ctx, plan, ds, prm, ws, rad))
     for _ in range(args.warmup):
-        graph.launch()
+        frame()
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     ev[0].record()
     for k in range(args.steps):
-        graph.launch()
+        frame()
         ev[k + 1].record()
     torch.cuda.synchronize()
     per_frame = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
     ms = ev[0].elapsed_time(ev[-1]) / args.steps
     ms_median = float(np.median(per_frame))
-    graph.close()
+    if graph:
+        graph.close()
 
     # phase times from HIP events around each phase (eager frames of the same plan)
     api.profile_begin(ctx, args.steps)
@@ -183,16 +235,27 @@ def main():
     rmse_cut = rel(got, cut_ref)
     cut_vs_full = rel(cut_ref, ref)
 
-    # roofline of the dominant kernel (ADM): algorithmic HBM bytes per launch =
-    # 16 B (packed index + RGB) per sampled entry per iteration; FP32 work =
-    # 18 q flop per sampled entry per iteration
+    # roofline of the dominant kernel (the completion, one launch per frame):
+    # algorithmic HBM bytes = 16 B (row index + RGB) per sampled entry per
+    # iteration + 4 q (6 m' + 18 n') B of factor state (X, U, L and Y, V, P
+    # read and written) per slice per iteration; FP32 work = 18 q flop per
+    # sampled entry per iteration
     t_adm = phase_ms["adm"] * 1e-3
-    adm_bytes = 16.0 * sample_iters
+    m_s = np.array([i["m"] for i in infos], np.int64)
+    n_s = np.array([i["n"] for i in infos], np.int64)
+    sample_bytes = 16.0 * sample_iters
+    state_bytes = float((4 * q * (6 * m_s + 18 * n_s) * iters).sum())
+    adm_bytes = sample_bytes + state_bytes
     adm_flops = float((18 * q * omega * iters).sum())
     achieved = adm_bytes / t_adm / 1e9
+    all_ell = all(i["adm_in_lds"] for i in infos)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_adm",
-            "kernel_ms": round(phase_ms["adm"], 3), "fp32_tflops": round(adm_flops / t_adm / 1e12, 2),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(args.workload, ppm) if all_ell else None,
+            "kernel": "k_adm_ell" if all_ell else "k_adm_ell + k_adm",
+            "kernel_ms": round(phase_ms["adm"], 3),
+            "algorithmic_bytes": {"samples": sample_bytes, "factor_state": state_bytes},
+            "fp32_tflops": round(adm_flops / t_adm / 1e12, 2),
             "fp32_frac": round(adm_flops / t_adm / 1e12 / FP32_PEAK_TFLOPS, 4)}
     dominant = max(phase_ms, key=phase_ms.get)
 
@@ -202,7 +265,7 @@ def main():
     if proposal is not None:
         prm_l = api.default_params(seed=args.seed, pass1_ppm=ppm, pass2_ppm=ppm, learned=True)
         rad_l = torch.empty_like(rad)
-        ms_l = frame_times(api, torch, ctx, plan, ds, prm_l, ws, rad_l, args.steps, 1)
+        ms_l = frame_times(api, torch, ctx, plan, ds, prm_l, ws, rad_l, args.steps, 1, args.eager)
         st_l = api.read_stats(ctx, plan, ws)
         rmse_l = rel(rad_l[pid_t.long()].double(), ref)
         learned = {"weights": os.path.basename(weights_path), "frame_ms": round(ms_l, 3),
@@ -220,7 +283,7 @@ def main():
                 row = {"rate_pct": r}
                 for name, flag in (("plain", False), ("learned", True)):
                     pp = api.default_params(seed=args.seed, pass1_ppm=pr, pass2_ppm=pr, learned=flag)
-                    msr = frame_times(api, torch, ctx, pl, ds, pp, wsr, rad_l, args.sweep_steps, 1)
+                    msr = frame_times(api, torch, ctx, pl, ds, pp, wsr, rad_l, args.sweep_steps, 1, args.eager)
                     er = rel(rad_l[pid_t.long()].double(), ref)
                     pts[name].append((er, msr))
                     row[name] = {"frame_ms": round(msr, 3), "pixel_rmse": round(er, 5)}
@@ -258,7 +321,8 @@ def main():
                    "seed": args.seed, "proposal": "plain"},
         "frame_ms": round(ms, 3),
         "frame_ms_median": round(ms_median, 3),
-        "timing": "captured frame graph (vplmc_graph_create), HIP events per launch; phase_ms from eager frames",
+        "timing": ("eager frames" if args.eager else "captured frame graph (vplmc_graph_create)")
+                  + ", HIP events per launch; phase_ms from eager frames",
         "eager_frame_ms_sum_of_phases": round(eager_ms, 3),
         "sampled_entries_per_frame": entries,
         "pixel_rmse_vs_full_sum": round(rmse_full, 5),
