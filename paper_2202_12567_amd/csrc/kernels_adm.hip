@@ -587,8 +587,9 @@ __device__ __forceinline__ const float4 *xchunk(const float *X, int i, int c) {
 
 // elements of the fixed-point to float pass (m q <= ADM_CVT_ELEMS)
 constexpr int ADM_CVT_ELEMS = 18 * 1024;
-// ELL entries a lane loads at once in phase A and in phase B
-constexpr int ADM_DA = 4;
+// ELL entries a lane loads at once in phase A (one more block of them in
+// flight while a block is processed) and in phase B
+constexpr int ADM_DA = 2;
 constexpr int ADM_DB = 8;
 // split-column sums a thread gathers before it stores them
 constexpr int ADM_CMB = 4;
@@ -822,17 +823,31 @@ __device__ void adm_ell_slice(
                     y[4 * v + 2] = a.z;
                     y[4 * v + 3] = a.w;
                 }
-                for (int k0 = 0; k0 < len; k0 += ADM_DA) {
-                    int ib[ADM_DA];
-                    float mb0[ADM_DA], mb1[ADM_DA], mb2[ADM_DA];
+                // entries k0 .. k0 + ADM_DA - 1 of the lane's part; the next block
+                // is loaded before this block's residuals are stored
+                auto load_block = [&](int k0, int *ib, float *mb0, float *mb1, float *mb2) {
 #pragma unroll
                     for (int u = 0; u < ADM_DA; ++u) {
                         const bool act = k0 + u < cnt;
                         const int e = base + 64 * (k0 + u) + lane;
                         ib[u] = act ? (int)erow[e] : -1;
-                        mb0[u] = act ? eval[3 * e] * inv_s0 : 0.f;
-                        mb1[u] = act ? eval[3 * e + 1] * inv_s0 : 0.f;
-                        mb2[u] = act ? eval[3 * e + 2] * inv_s0 : 0.f;
+                        mb0[u] = act ? eval[3 * e] : 0.f;
+                        mb1[u] = act ? eval[3 * e + 1] : 0.f;
+                        mb2[u] = act ? eval[3 * e + 2] : 0.f;
+                    }
+                };
+                int ib[ADM_DA];
+                float mb0[ADM_DA], mb1[ADM_DA], mb2[ADM_DA];
+                if (len > 0) load_block(0, ib, mb0, mb1, mb2);
+                for (int k0 = 0; k0 < len; k0 += ADM_DA) {
+                    int ibn[ADM_DA];
+                    float mn0[ADM_DA], mn1[ADM_DA], mn2[ADM_DA];
+                    if (k0 + ADM_DA < len) load_block(k0 + ADM_DA, ibn, mn0, mn1, mn2);
+#pragma unroll
+                    for (int u = 0; u < ADM_DA; ++u) {
+                        mb0[u] *= inv_s0;
+                        mb1[u] *= inv_s0;
+                        mb2[u] *= inv_s0;
                     }
 #pragma unroll
                     for (int u = 0; u < ADM_DA; ++u) {
@@ -870,6 +885,13 @@ __device__ void adm_ell_slice(
                                           __float2int_rn(fmaf(s0r, y[kk], fmaf(s1r, y[Q + kk], s2r * y[2 * Q + kk]))));
                             atomicAdd(reinterpret_cast<uint32_t *>(row + Q), __float2uint_ru(rsa * fxr));
                         }
+                    }
+#pragma unroll
+                    for (int u = 0; u < ADM_DA; ++u) {
+                        ib[u] = ibn[u];
+                        mb0[u] = mn0[u];
+                        mb1[u] = mn1[u];
+                        mb2[u] = mn2[u];
                     }
                 }
                 if (64 * g + lane < P) e2part[pc] = e2;
@@ -1135,11 +1157,8 @@ __device__ void adm_ell_slice(
                     pa[v] = Pi[(size_t)r * Q + c];
                 }
             };
-            float ya[QV], ta[QV], pa[4];
-            if (16 * wave < R3) load_tile(16 * wave, ya, ta, pa);
-            for (int r0 = 16 * wave; r0 < R3; r0 += 16 * NW) {
-                float yb[QV], tb[QV], pb[4];
-                if (r0 + 16 * NW < R3) load_tile(r0 + 16 * NW, yb, tb, pb);
+            // tiles in pairs: both tiles' operands are loaded before either's stores
+            auto do_tile = [&](int r0, const float *ya, const float *ta, const float *pa) {
                 const bool rok = r0 + lane % 16 < R3;
                 f4 D = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -1164,13 +1183,14 @@ __device__ void adm_ell_slice(
                     }
                     gy = mfma16(yn, yn, gy);
                 }
-#pragma unroll
-                for (int v = 0; v < QV; ++v) {
-                    ya[v] = yb[v];
-                    ta[v] = tb[v];
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) pa[v] = pb[v];
+            };
+            for (int r0 = 16 * wave; r0 < R3; r0 += 32 * NW) {
+                const int r1 = r0 + 16 * NW;
+                float ya[QV], ta[QV], pa[4], yb[QV], tb[QV], pb[4];
+                load_tile(r0, ya, ta, pa);
+                if (r1 < R3) load_tile(r1, yb, tb, pb);
+                do_tile(r0, ya, ta, pa);
+                if (r1 < R3) do_tile(r1, yb, tb, pb);
             }
             __threadfence_block();
             sum_partials<Q, NW>(gy, zero, red, sh.G, nullptr);
