@@ -159,7 +159,7 @@ int vplmc_set_stream(vplmc_ctx *ctx, void *stream) {
 int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float *cy, const float *cz,
                         const float *r) {
     if (!ctx) return set_error(VPLMC_EINVAL, "ctx is NULL");
-    if (n < 0) return set_error(VPLMC_EINVAL, "n must be >= 0");
+    if (n < 0 || n > BVH_MAX_SPHERES) return set_error(VPLMC_EINVAL, "n must be in [0, 2^27]");
     if (n > 0 && (!cx || !cy || !cz || !r)) return set_error(VPLMC_EINVAL, "sphere arrays must be non-NULL");
     for (int k = 0; k < n; ++k)
         if (!(r[k] > 0.f) || !std::isfinite(cx[k]) || !std::isfinite(cy[k]) || !std::isfinite(cz[k]))

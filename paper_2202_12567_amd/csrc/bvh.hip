@@ -7,7 +7,9 @@
 // so that an FP32 slab test never rejects a segment that meets a sphere;
 // inner nodes split their spheres at the median of the centroids along
 // the longest centroid extent; leaves hold at most two spheres.  Nodes are
-// stored in depth-first order.
+// stored in depth-first order, each with the index of the node after its
+// subtree, so a traversal needs no stack: on a hit go to the next node
+// (the left child), on a miss or after a leaf go to the skip index.
 
 #include <algorithm>
 #include <cmath>
@@ -48,8 +50,8 @@ struct Builder {
             nodes[id].hi[a] = bhi[a] + pad_hi;
         }
         if (hi - lo <= 2) {
-            nodes[id].left_or_first = lo;
-            nodes[id].right_or_count = hi - lo;
+            nodes[id].leaf = (lo << 4) | (hi - lo);
+            nodes[id].skip = (int)nodes.size();
             return id;
         }
         int axis = 0;
@@ -60,10 +62,10 @@ struct Builder {
         std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi, [ca](int32_t a, int32_t b) {
             return ca[a] < ca[b] || (ca[a] == ca[b] && a < b);
         });
-        const int left = build(lo, mid, depth + 1);
-        const int right = build(mid, hi, depth + 1);
-        nodes[id].left_or_first = left;
-        nodes[id].right_or_count = -right - 1;
+        build(lo, mid, depth + 1);           // left child: id + 1
+        build(mid, hi, depth + 1);
+        nodes[id].leaf = 0;
+        nodes[id].skip = (int)nodes.size();
         return id;
     }
 };

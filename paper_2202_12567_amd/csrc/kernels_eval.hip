@@ -8,7 +8,8 @@
 //   A = f * I * G * V
 // V = 0 iff the segment from x + eps n_x to y passes within the radius of a
 // sphere (closest point of the segment to the centre), found by an any-hit
-// traversal of a bounding-volume hierarchy with a short register stack.
+// traversal of a bounding-volume hierarchy in depth-first order with skip
+// indices (no stack).
 
 #include "vplmc_internal.h"
 
@@ -23,6 +24,21 @@ struct P3 {
 __device__ __forceinline__ P3 sub(P3 a, P3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ float dot(P3 a, P3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
 
+// does a sphere of a leaf (first << 4 | count) come closer to the segment
+// o + t D, t in [0, 1], than its radius
+__device__ __forceinline__ bool leaf_occludes(const Bvh &bvh, int leaf, P3 o, P3 D, float inv_dd) {
+    const int first = leaf >> 4, cnt = leaf & 15;
+    bool any = false;
+    for (int k = 0; k < cnt; ++k) {
+        const float4 sp4 = bvh.spheres[first + k];
+        const P3 oc = {sp4.x - o.x, sp4.y - o.y, sp4.z - o.z};
+        const float t = fminf(fmaxf(dot(oc, D) * inv_dd, 0.0f), 1.0f);
+        const P3 p = {oc.x - t * D.x, oc.y - t * D.y, oc.z - t * D.z};
+        any = any || dot(p, p) < sp4.w * sp4.w;
+    }
+    return any;
+}
+
 // any hit on the open segment o + t D, t in (0, 1)
 __device__ __forceinline__ bool occluded(const Bvh &bvh, P3 o, P3 D) {
     if (bvh.n_nodes == 0) return false;
@@ -31,35 +47,21 @@ __device__ __forceinline__ bool occluded(const Bvh &bvh, P3 o, P3 D) {
     const float ix = 1.0f / (fabsf(D.x) > 1e-20f ? D.x : copysignf(1e-20f, D.x));
     const float iy = 1.0f / (fabsf(D.y) > 1e-20f ? D.y : copysignf(1e-20f, D.y));
     const float iz = 1.0f / (fabsf(D.z) > 1e-20f ? D.z : copysignf(1e-20f, D.z));
-    int stack[40];
-    int sp = 0;
     int node = 0;
-    while (true) {
+    while (node < bvh.n_nodes) {
         const BvhNode nd = bvh.nodes[node];
         const float tx0 = (nd.lo[0] - o.x) * ix, tx1 = (nd.hi[0] - o.x) * ix;
         const float ty0 = (nd.lo[1] - o.y) * iy, ty1 = (nd.hi[1] - o.y) * iy;
         const float tz0 = (nd.lo[2] - o.z) * iz, tz1 = (nd.hi[2] - o.z) * iz;
         const float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
         const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), 1.0f));
-        if (tmin <= tmax) {
-            if (nd.right_or_count > 0) {
-                const int first = nd.left_or_first, cnt = nd.right_or_count;
-                for (int k = 0; k < cnt; ++k) {
-                    const float4 sp4 = bvh.spheres[first + k];
-                    const P3 oc = {sp4.x - o.x, sp4.y - o.y, sp4.z - o.z};
-                    const float t = fminf(fmaxf(dot(oc, D) * inv_dd, 0.0f), 1.0f);
-                    const P3 p = {oc.x - t * D.x, oc.y - t * D.y, oc.z - t * D.z};
-                    if (dot(p, p) < sp4.w * sp4.w) return true;
-                }
-            } else {
-                stack[sp++] = -nd.right_or_count - 1;
-                node = nd.left_or_first;
-                continue;
-            }
-        }
-        if (sp == 0) return false;
-        node = stack[--sp];
+        const bool hit = tmin <= tmax;
+        if (hit && nd.leaf != 0 && leaf_occludes(bvh, nd.leaf, o, D, inv_dd)) return true;
+        // an inner node that is hit descends to its left child; anything else
+        // continues after its subtree
+        node = hit && nd.leaf == 0 ? node + 1 : nd.skip;
     }
+    return false;
 }
 
 struct PointData {

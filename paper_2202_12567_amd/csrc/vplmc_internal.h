@@ -68,12 +68,13 @@ __device__ __forceinline__ U64x4 philox(uint64_t k0, uint64_t k1, uint64_t c0, u
 __device__ __forceinline__ uint64_t mulhi64(uint64_t r, uint64_t n) { return __umul64hi(r, n); }
 
 // ------------------------------------------------------------ geometry
-struct BvhNode {            // 32 bytes; leaves: count > 0 spheres from first
+struct BvhNode {            // 32 bytes, depth-first order: an inner node's left child follows it
     float lo[3];
-    int32_t left_or_first;  // inner: index of the left child (right = left + 1 is NOT assumed)
+    int32_t leaf;           // leaf: first sphere << 4 | sphere count (1..15); inner: 0
     float hi[3];
-    int32_t right_or_count; // inner: -(right child) - 1 ; leaf: sphere count
+    int32_t skip;           // the node after this node's subtree (n_nodes past the last)
 };
+constexpr int32_t BVH_MAX_SPHERES = 1 << 27;
 
 struct Bvh {
     const BvhNode *nodes = nullptr;
