@@ -296,18 +296,23 @@ __device__ __forceinline__ uint32_t load_word(const uint32_t *p) {
 
 // Second pass (Sec. 5): attempt t draws column j by the integer CDF of w and
 // row i uniformly, and is accepted iff (i, j) is not sampled yet.  A block
-// tests 256 consecutive attempts at once; an attempt is accepted iff its
-// entry is not in the bitmap and no earlier attempt of the same batch drew
-// it, which is exactly the sequential rule.  Stops after N2 acceptances or
+// tests P2_THREADS consecutive attempts at once; an attempt is accepted iff
+// its entry is not in the bitmap and no earlier attempt of the same batch
+// drew it (the smallest attempt per entry, found through an LDS hash table),
+// which is exactly the sequential rule.  Stops after N2 acceptances or
 // 64 N2 + 65536 attempts.
-constexpr int P2_LDS = 6144;   // prefix entries staged in LDS (48 KiB)
+constexpr int P2_LDS = 6144;       // prefix entries staged in LDS (48 KiB)
+constexpr int P2_THREADS = 1024;   // attempts per batch
+constexpr int P2_HASH = 4096;      // hash slots (load <= 1/4)
+constexpr uint32_t P2_EMPTY = 0xFFFFFFFFu;
 
-__global__ __launch_bounds__(256) void k_pass2(const SliceDesc *__restrict__ desc, uint64_t seed,
-                                               const uint64_t *__restrict__ prefix_all, uint32_t *bm,
-                                               uint32_t *bmt, uint32_t *omega2, int32_t *stats) {
+__global__ __launch_bounds__(P2_THREADS) void k_pass2(const SliceDesc *__restrict__ desc, uint64_t seed,
+                                                      const uint64_t *__restrict__ prefix_all, uint32_t *bm,
+                                                      uint32_t *bmt, uint32_t *omega2, int32_t *stats) {
     __shared__ uint64_t P[P2_LDS];
-    __shared__ uint32_t keys[256];
-    __shared__ uint32_t sm[8];
+    __shared__ uint32_t hkey[P2_HASH];
+    __shared__ uint32_t hmin[P2_HASH];
+    __shared__ uint32_t sm[P2_THREADS / WAVE];
     __shared__ int accepted_s;
     const int s = blockIdx.x;
     const SliceDesc d = desc[s];
@@ -323,7 +328,7 @@ __global__ __launch_bounds__(256) void k_pass2(const SliceDesc *__restrict__ des
     if (N2 > 0 && (int64_t)d.N1 + N2 == D) {
         // every remaining entry, row-major: scan the row-major bitmap in word order
         const int64_t words = (int64_t)m * d.words_row;
-        for (int64_t w0 = 0; w0 < words; w0 += 256) {
+        for (int64_t w0 = 0; w0 < words; w0 += P2_THREADS) {
             const int64_t w = w0 + t;
             uint32_t freeb = 0;
             int i = 0, jb = 0;
@@ -354,11 +359,15 @@ __global__ __launch_bounds__(256) void k_pass2(const SliceDesc *__restrict__ des
         const uint64_t *pre = prefix_all + d.off_col;
         const bool in_lds = n <= P2_LDS;
         if (in_lds)
-            for (int j = t; j < n; j += 256) P[j] = pre[j];
+            for (int j = t; j < n; j += P2_THREADS) P[j] = pre[j];
+        for (int h = t; h < P2_HASH; h += P2_THREADS) {
+            hkey[h] = P2_EMPTY;
+            hmin[h] = P2_EMPTY;
+        }
         __syncthreads();
         const uint64_t totalw = pre[n - 1];
         const int64_t cap = 64 * (int64_t)N2 + 65536;
-        for (int64_t tb = 0; tb < cap; tb += 256) {
+        for (int64_t tb = 0; tb < cap; tb += P2_THREADS) {
             const int acc0 = accepted_s;
             if (acc0 >= N2) break;
             const int64_t at = tb + t;
@@ -379,14 +388,25 @@ __global__ __launch_bounds__(256) void k_pass2(const SliceDesc *__restrict__ des
                 cand = ((word >> (j & 31)) & 1u) == 0u;
                 key = (i << 16) | j;
             }
-            keys[t] = cand ? key : 0xFFFFFFFFu;
+            // smallest attempt of the batch per entry: open addressing, linear probing
+            int slot = 0;
+            if (cand) {
+                slot = (int)((key * 2654435761u) >> 20) & (P2_HASH - 1);
+                for (;;) {
+                    const uint32_t old = atomicCAS(&hkey[slot], P2_EMPTY, key);
+                    if (old == P2_EMPTY || old == key) break;
+                    slot = (slot + 1) & (P2_HASH - 1);
+                }
+                atomicMin(&hmin[slot], (uint32_t)t);
+            }
             __syncthreads();
-            bool dup = false;
-            if (cand)
-                for (int l = 0; l < t; ++l) dup |= keys[l] == key;
-            const bool acc = cand && !dup;
+            const bool acc = cand && hmin[slot] == (uint32_t)t;
             uint32_t tot;
             const uint32_t rank = block_excl_scan(acc ? 1u : 0u, &tot, sm);
+            if (cand) {                       // every used slot is cleared by its entries
+                hkey[slot] = P2_EMPTY;
+                hmin[slot] = P2_EMPTY;
+            }
             if (acc && acc0 + (int)rank < N2) {
                 out[acc0 + rank] = key;
                 atomicOr(bmr + (int64_t)i * d.words_row + (j >> 5), 1u << (j & 31));
@@ -670,7 +690,7 @@ int launch_weights(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc
 int launch_pass2(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, uint64_t seed,
                  const uint64_t *prefix, uint32_t *bm, uint32_t *bmt, uint32_t *omega2, int32_t *stats) {
     if (plan.n_slices <= 0) return VPLMC_OK;
-    hipLaunchKernelGGL(k_pass2, dim3(plan.n_slices), dim3(256), 0, st, desc, seed, prefix, bm, bmt, omega2,
+    hipLaunchKernelGGL(k_pass2, dim3(plan.n_slices), dim3(P2_THREADS), 0, st, desc, seed, prefix, bm, bmt, omega2,
                        stats);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
