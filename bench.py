@@ -1,7 +1,7 @@
 """Frame benchmark of the sparse-sampling + completion hot path on one MI355X.
 
 One step = one whole frame of the method (cluster table, both sampling
-passes, entries with shadow rays, CSR/CSC ordering, ADM completion of every
+passes, entries with shadow rays, ordering of the samples, ADM completion of every
 slice, factorised column sum) on device-resident inputs.  Prints ONE JSON
 line.  ``value`` is sampled entries per second of frame time; the frame
 time, the pixel RMSE against the brute-force sum over every VPL (sampled

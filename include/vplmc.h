@@ -134,10 +134,14 @@ enum {
     VPLMC_R_COLMIN,       /* float per (slice, column): min of R+G+B over the first pass   */
     VPLMC_R_COLMAX,       /* float per (slice, column): max                                */
     VPLMC_R_COLCNT,       /* int32 per (slice, column): first-pass observations            */
+    /* ROW_PTR, CSR_* and CSC_* describe Omega only for slices completed in
+     * global memory (vplmc_slice_info.adm_in_lds = 0); a slice completed in
+     * LDS is completed from an internal ELL copy, and its CSC_* regions keep
+     * the first pass alone (the column statistics' ordering). */
     VPLMC_R_ROW_PTR,      /* int32[m + 1] per slice: CSR row pointers                      */
     VPLMC_R_CSR_COL,      /* int32 per entry: column, CSR order (row-major)                */
     VPLMC_R_CSR_VAL,      /* float[3] per entry, CSR order                                 */
-    VPLMC_R_COL_PTR,      /* int32[n + 1] per slice: CSC column pointers                   */
+    VPLMC_R_COL_PTR,      /* int32[n + 1] per slice: CSC column pointers (every slice)     */
     VPLMC_R_CSC_ROW,      /* int32 per entry: row, CSC order (column-major)                */
     VPLMC_R_CSC_VAL,      /* float[3] per entry, CSC order                                 */
     VPLMC_R_X,            /* float[m][q] per slice: final X (initial X when max_iter = 0)  */
@@ -220,7 +224,7 @@ enum {
     VPLMC_PH_WEIGHTS,     /* column statistics and importance        */
     VPLMC_PH_PASS2,       /* second-pass sampling                    */
     VPLMC_PH_EVAL2,       /* entries of the second pass              */
-    VPLMC_PH_SORT,        /* CSR / CSC ordering                      */
+    VPLMC_PH_SORT,        /* ordering of Omega (ELL copy, CSR / CSC) */
     VPLMC_PH_ADM,         /* ADM completion                          */
     VPLMC_PH_REDUCE       /* factorised column sum                   */
 };

@@ -598,7 +598,7 @@ template <int Q, int THREADS>
 __device__ void adm_ell_slice(
     int s, const SliceDesc *__restrict__ desc, uint64_t seed, int32_t max_iter,
     int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma, const int32_t *__restrict__ col_ptr_all,
-    const int32_t *__restrict__ csc_row_all, const float *__restrict__ csc_val_all, EllView ell, float *X_all,
+    EllView ell, float *X_all,
     float *Xp_all, float *Lam_all, float *Y_all, float *Yp_all, float *Pi_all, float *Yt_all, float *red_all,
     double *e2part_all, float *scale_all, int32_t *stats_all) {
     static_assert(Q % 4 == 0 && Q <= 16, "ranks 4, 8, 16");
@@ -616,8 +616,6 @@ __device__ void adm_ell_slice(
     float *XB = dyn + (size_t)m * (Q + 1);            // fixed-point R Y^T (stride q + 1), then T and X+ (stride q)
 
     const int32_t *col_ptr = col_ptr_all + d.off_colptr;
-    const int32_t *csc_row = csc_row_all + d.off_omega;
-    const float *csc_val = csc_val_all + 3 * d.off_omega;
     const int2 *part = ell.part + d.off_part;
     const int32_t *pbase = ell.pbase + d.off_colptr;
     const int32_t *grp = ell.grp + d.off_grp;
@@ -640,13 +638,27 @@ __device__ void adm_ell_slice(
     const int G = (P + 63) / 64;          // groups of 64 parts
     const int R3 = 3 * n;
 
+    // the slice's samples in the ELL copy: entries k < length of the part at
+    // sorted position 64 g + lane lie at grp[g] + 64 k + lane
+    auto for_each_entry = [&](auto &&f) {
+        for (int g = wave; g < G; g += NW) {
+            const int sp = 64 * g + lane;
+            const int cl = sp < P ? (part[sp].x >> 16) & 0x7F : 0;
+            const int base = grp[g];
+            for (int k = 0; k < cl; ++k) f(base + 64 * k + lane);
+        }
+    };
+
     // ---- scale s0 = mean sampled value; ||P_Omega M|| ----
     double sum = 0.0, sumsq = 0.0;
-    for (int p = t; p < 3 * nnz; p += THREADS) {
-        const double v = (double)csc_val[p];
-        sum += v;
-        sumsq += v * v;
-    }
+    for_each_entry([&](int e) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double v = (double)eval[3 * e + c];
+            sum += v;
+            sumsq += v * v;
+        }
+    });
     sum = wave_sum_d(sum);
     sumsq = wave_sum_d(sumsq);
     if (lane == 0) {
@@ -721,10 +733,10 @@ __device__ void adm_ell_slice(
     for (int e = t; e < m; e += THREADS) cntr[e] = 0;
     __syncthreads();
     float msum = 0.f;
-    for (int p = t; p < nnz; p += THREADS) {
-        atomicAdd(cntr + csc_row[p], 1);
-        msum = fmaxf(msum, fabsf(csc_val[3 * p]) + fabsf(csc_val[3 * p + 1]) + fabsf(csc_val[3 * p + 2]));
-    }
+    for_each_entry([&](int e) {
+        atomicAdd(cntr + erow[e], 1);
+        msum = fmaxf(msum, fabsf(eval[3 * e]) + fabsf(eval[3 * e + 1]) + fabsf(eval[3 * e + 2]));
+    });
     __syncthreads();
     float kmx = 0.f, x1 = 0.f;
     for (int i = t; i < m; i += THREADS) {
@@ -1248,14 +1260,13 @@ template <int Q, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_adm_ell(
     const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, int32_t count, int32_t *queue,
     uint64_t seed, int32_t max_iter, int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma,
-    const int32_t *__restrict__ col_ptr_all, const int32_t *__restrict__ csc_row_all,
-    const float *__restrict__ csc_val_all, EllView ell, float *X_all, float *Xp_all, float *Lam_all, float *Y_all,
+    const int32_t *__restrict__ col_ptr_all, EllView ell, float *X_all, float *Xp_all, float *Lam_all, float *Y_all,
     float *Yp_all, float *Pi_all, float *Yt_all, float *red_all, double *e2part_all, float *scale_all,
     int32_t *stats_all) {
     int k, state = 0;
     while (next_slice(queue, count, k, state)) {
         adm_ell_slice<Q, THREADS>(__builtin_amdgcn_readfirstlane(slice_list[k]), desc, seed, max_iter, fixed_iters, tol, alpha0, beta0, gamma,
-                                  col_ptr_all, csc_row_all, csc_val_all, ell, X_all, Xp_all, Lam_all, Y_all, Yp_all,
+                                  col_ptr_all, ell, X_all, Xp_all, Lam_all, Y_all, Yp_all,
                                   Pi_all, Yt_all, red_all, e2part_all, scale_all, stats_all);
         __syncthreads();
     }
@@ -1342,8 +1353,8 @@ int launch_adm_global(hipStream_t st, size_t count, const int32_t *ids_dev, int3
 
 template <int Q, int T>
 int launch_adm_ell_t(hipStream_t st, size_t count, int max_m, const int32_t *ids_dev, int32_t *queue, int n_cu,
-                     const SliceDesc *desc, const vplmc_params &prm, const int32_t *col_ptr, const int32_t *csc_row,
-                     const float *csc_val, const EllView &ell, float *X, float *Xp, float *Lam, float *Y, float *Yp,
+                     const SliceDesc *desc, const vplmc_params &prm, const int32_t *col_ptr, const EllView &ell,
+                     float *X, float *Xp, float *Lam, float *Y, float *Yp,
                      float *Pi, float *Yt, float *red, double *e2part, float *scale, int32_t *stats) {
     const size_t dyn = adm_lds_dynamic_bytes(Q, max_m);
     auto kern = k_adm_ell<Q, T>;
@@ -1355,7 +1366,7 @@ int launch_adm_ell_t(hipStream_t st, size_t count, int max_m, const int32_t *ids
     if (queue && (rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(queue), 1, 0u))) return rc;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(T), dyn, st, desc, ids_dev, (int32_t)count, queue, prm.seed,
                        prm.max_iter, (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0,
-                       prm.gamma, col_ptr, csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale,
+                       prm.gamma, col_ptr, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale,
                        stats);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
@@ -1364,15 +1375,15 @@ int launch_adm_ell_t(hipStream_t st, size_t count, int max_m, const int32_t *ids
 template <int Q>
 int launch_adm_ell(hipStream_t st, int threads, size_t count, int max_m, const int32_t *ids_dev, int32_t *queue,
                    int n_cu, const SliceDesc *desc, const vplmc_params &prm, const int32_t *col_ptr,
-                   const int32_t *csc_row, const float *csc_val, const EllView &ell, float *X, float *Xp, float *Lam,
+                   const EllView &ell, float *X, float *Xp, float *Lam,
                    float *Y, float *Yp, float *Pi, float *Yt, float *red, double *e2part, float *scale,
                    int32_t *stats) {
     if (count == 0) return VPLMC_OK;
     if (threads == 512)
-        return launch_adm_ell_t<Q, 512>(st, count, max_m, ids_dev, queue, n_cu, desc, prm, col_ptr, csc_row, csc_val,
-                                        ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale, stats);
-    return launch_adm_ell_t<Q, 1024>(st, count, max_m, ids_dev, queue, n_cu, desc, prm, col_ptr, csc_row, csc_val,
-                                     ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale, stats);
+        return launch_adm_ell_t<Q, 512>(st, count, max_m, ids_dev, queue, n_cu, desc, prm, col_ptr, ell, X, Xp, Lam,
+                                        Y, Yp, Pi, Yt, red, e2part, scale, stats);
+    return launch_adm_ell_t<Q, 1024>(st, count, max_m, ids_dev, queue, n_cu, desc, prm, col_ptr, ell, X, Xp, Lam, Y,
+                                     Yp, Pi, Yt, red, e2part, scale, stats);
 }
 
 }  // namespace
@@ -1393,7 +1404,7 @@ int launch_adm(hipStream_t st, const vplmc_plan &plan, int n_cu, const SliceDesc
     int rc;
 #define VPLMC_ADM_PAIR(B, Q, TG)                                                                                   \
     if ((rc = launch_adm_ell<Q>(st, thr, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], qp(2 * B), \
-                                n_cu, desc, prm, col_ptr, csc_row, csc_val, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red,    \
+                                n_cu, desc, prm, col_ptr, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red,                      \
                                 e2part, scale, stats)))                                                            \
         return rc;                                                                                                 \
     if ((rc = launch_adm_global<Q, TG>(st, plan.groups[2 * B + 1].size(), id[2 * B + 1], qp(2 * B + 1), n_cu, desc, \

@@ -485,7 +485,6 @@ __global__ __launch_bounds__(256) void k_ptrscan(const SliceDesc *__restrict__ d
     }
 }
 
-// Scatter one pass's samples to their CSR and CSC positions.
 // parts of a column with c samples: p = max(1, ceil(c / ELL_LMAX)) of
 // l = ceil(c / p) samples, the last one c - (p - 1) l
 __device__ __forceinline__ void part_shape(int c, int &p, int &l) {
@@ -493,6 +492,10 @@ __device__ __forceinline__ void part_shape(int c, int &p, int &l) {
     l = (c + p - 1) / p;
 }
 
+// Scatter one pass's samples: a slice completed in global memory gets its CSC
+// copy (and its CSR copy when csr_col is given); a slice completed from the
+// ELL copy (when ell.row is given) gets only its ELL slot, whose position
+// follows from the CSC rank.
 __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t total, int which,
                           const int32_t *__restrict__ stats, const uint32_t *__restrict__ keys,
                           const float *__restrict__ vals, const uint32_t *__restrict__ bm,
@@ -508,23 +511,27 @@ __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t tot
     if (which && k >= stats[4 * s + 3]) return;
     const uint32_t key = keys[g];
     const uint32_t i = key >> 16, j = key & 0xFFFFu;
-    const int64_t wr = d.off_bm + (int64_t)i * d.words_row + (j >> 5);
-    const int64_t pr = csr_col ? row_ptr[d.off_row + i] + wpre[wr] + __popc(bm[wr] & ((1u << (j & 31)) - 1u)) : 0;
+    // a slice completed from its ELL copy gets only that copy
+    const bool to_ell = ell.row && d.ell;
     const int64_t wc = d.off_bmt + (int64_t)j * d.words_col + (i >> 5);
     const int64_t pc = col_ptr[d.off_colptr + j] + wpret[wc] + __popc(bmt[wc] & ((1u << (i & 31)) - 1u));
     const float v0 = vals[3 * g], v1 = vals[3 * g + 1], v2 = vals[3 * g + 2];
     const int64_t o = d.off_omega;
-    if (csr_col) {
+    if (csr_col && !to_ell) {
+        const int64_t wr = d.off_bm + (int64_t)i * d.words_row + (j >> 5);
+        const int64_t pr = row_ptr[d.off_row + i] + wpre[wr] + __popc(bm[wr] & ((1u << (j & 31)) - 1u));
         csr_col[o + pr] = (int32_t)j;
         csr_val[3 * (o + pr)] = v0;
         csr_val[3 * (o + pr) + 1] = v1;
         csr_val[3 * (o + pr) + 2] = v2;
     }
-    csc_row[o + pc] = (int32_t)i;
-    csc_val[3 * (o + pc)] = v0;
-    csc_val[3 * (o + pc) + 1] = v1;
-    csc_val[3 * (o + pc) + 2] = v2;
-    if (ell.row && d.ell) {
+    if (!to_ell) {
+        csc_row[o + pc] = (int32_t)i;
+        csc_val[3 * (o + pc)] = v0;
+        csc_val[3 * (o + pc) + 1] = v1;
+        csc_val[3 * (o + pc) + 2] = v2;
+    }
+    if (to_ell) {
         const int32_t *cp = col_ptr + d.off_colptr;
         const int k2 = (int)(pc - cp[j]);
         int p, l;
@@ -705,14 +712,20 @@ int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, c
     const int S = plan.n_slices;
     const int64_t rows = plan.tot_row - S;     // sum of m
     const int64_t cols = plan.tot_col;         // sum of n
-    hipLaunchKernelGGL(k_rowscan, dim3(blocks_for(rows * WAVE, 256)), dim3(256), 0, st, desc, S, rows, 0, bm,
-                       wpre, row_ptr);
-    VPLMC_HIP(hipGetLastError());
+    // row order (CSR) only for slices completed in global memory
+    const bool csr = plan.n_ell < S;
+    if (csr) {
+        hipLaunchKernelGGL(k_rowscan, dim3(blocks_for(rows * WAVE, 256)), dim3(256), 0, st, desc, S, rows, 0, bm,
+                           wpre, row_ptr);
+        VPLMC_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_rowscan, dim3(blocks_for(cols * WAVE, 256)), dim3(256), 0, st, desc, S, cols, 1, bmt,
                        wpret, col_ptr);
     VPLMC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_ptrscan, dim3(S), dim3(256), 0, st, desc, 0, row_ptr);
-    VPLMC_HIP(hipGetLastError());
+    if (csr) {
+        hipLaunchKernelGGL(k_ptrscan, dim3(S), dim3(256), 0, st, desc, 0, row_ptr);
+        VPLMC_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_ptrscan, dim3(S), dim3(256), 0, st, desc, 1, col_ptr);
     VPLMC_HIP(hipGetLastError());
     if (plan.n_ell > 0) {

@@ -58,6 +58,39 @@ def keys_to_ij(keys):
     return keys >> 16, keys & 0xFFFF
 
 
+def omega_of(run, s):
+    """Rows, columns and FP32 RGB values of slice s's samples (both passes, draw
+    and acceptance order), from the passes' own output regions."""
+    info = run["info"][s]
+    n2 = int(run["stats"]["n2"][s])
+    k1 = run["r"]["OMEGA1"][info["off1"]: info["off1"] + info["N1"]]
+    k2 = run["r"]["OMEGA2"][info["off2"]: info["off2"] + n2]
+    v1 = run["r"]["VAL1"][3 * info["off1"]: 3 * (info["off1"] + info["N1"])]
+    v2 = run["r"]["VAL2"][3 * info["off2"]: 3 * (info["off2"] + n2)]
+    i, j = keys_to_ij(np.concatenate([k1, k2]))
+    return i, j, np.concatenate([v1, v2]).reshape(-1, 3)
+
+
+def check_csr_csc(run, s):
+    """CSR and CSC copies of a slice completed in global memory: row-major and
+    column-major orders of exactly the passes' samples."""
+    info = run["info"][s]
+    m, n = info["m"], info["n"]
+    i, j, v = omega_of(run, s)
+    nnz = i.shape[0]
+    o = info["off_omega"]
+    order = np.lexsort((j, i))
+    rp = np.concatenate([[0], np.cumsum(np.bincount(i, minlength=m))])
+    assert np.array_equal(run["r"]["ROW_PTR"][info["off_row"]: info["off_row"] + m + 1], rp)
+    assert np.array_equal(run["r"]["CSR_COL"][o: o + nnz], j[order])
+    assert np.array_equal(run["r"]["CSR_VAL"][3 * o: 3 * (o + nnz)].reshape(-1, 3), v[order])
+    order = np.lexsort((i, j))
+    cp = np.concatenate([[0], np.cumsum(np.bincount(j, minlength=n))])
+    assert np.array_equal(run["r"]["COL_PTR"][info["off_colptr"]: info["off_colptr"] + n + 1], cp)
+    assert np.array_equal(run["r"]["CSC_ROW"][o: o + nnz], i[order])
+    assert np.array_equal(run["r"]["CSC_VAL"][3 * o: 3 * (o + nnz)].reshape(-1, 3), v[order])
+
+
 def within_entry_tol(g, o, amb=None):
     """|g - o| <= 1e-4 |o| + 1e-7 max|o| per entry and channel (unflagged entries)."""
     g = np.asarray(g, np.float64)

@@ -19,8 +19,8 @@ from scenegen import CONFIGS, make_scene  # noqa: E402
 
 BATCH = dataclasses.replace(CONFIGS["batch"], width=320, height=200, n_spheres=256, n_vpls=8000,
                             batch_slices=24, batch_m=(64, 2048), batch_n=(256, 1024))
-INT_REGIONS = {"OMEGA1": torch.int32, "OMEGA2": torch.int32, "WEIGHTS": torch.int32, "CSC_ROW": torch.int32,
-               "ROW_PTR": torch.int32, "COL_PTR": torch.int32}
+INT_REGIONS = {"OMEGA1": torch.int32, "OMEGA2": torch.int32, "WEIGHTS": torch.int32, "COL_PTR": torch.int32}
+DENSE_REGIONS = {"ROW_PTR": torch.int32, "CSR_COL": torch.int32, "CSC_ROW": torch.int32}
 
 
 @pytest.fixture(scope="module")
@@ -45,6 +45,16 @@ def render_with(setup, **tune):
     rad = api.render(ctx, plan, ds, prm, ws).clone()
     torch.cuda.synchronize()
     ints = {k: api.region_view(plan, ws, k, dt).cpu().numpy().copy() for k, dt in INT_REGIONS.items()}
+    # CSR / CSC orders exist for the slices completed in global memory
+    dense = {k: api.region_view(plan, ws, k, dt).cpu().numpy() for k, dt in DENSE_REGIONS.items()}
+    for s in range(sc.n_slices):
+        info = plan.slice_info(s)
+        if info["adm_in_lds"]:
+            continue
+        nnz = int(dense["ROW_PTR"][info["off_row"] + info["m"]])
+        ints[f"ROW_PTR {s}"] = dense["ROW_PTR"][info["off_row"]: info["off_row"] + info["m"] + 1].copy()
+        ints[f"CSR_COL {s}"] = dense["CSR_COL"][info["off_omega"]: info["off_omega"] + nnz].copy()
+        ints[f"CSC_ROW {s}"] = dense["CSC_ROW"][info["off_omega"]: info["off_omega"] + nnz].copy()
     return rad.cpu().numpy().astype(np.float64), ints, plan, ws
 
 
@@ -52,7 +62,8 @@ def test_queue_and_workgroup_size(setup):
     rad0, ints0, *_ = render_with(setup)
     rad_q, ints_q, *_ = render_with(setup, adm_queue=1)
     rad_t, ints_t, *_ = render_with(setup, adm_queue=1, adm_threads=512, eval_threads=64)
-    for k in INT_REGIONS:
+    assert any(k.startswith("CSR_COL") for k in ints0)
+    for k in ints0:
         assert np.array_equal(ints0[k], ints_q[k]) and np.array_equal(ints0[k], ints_t[k]), k
     assert np.array_equal(rad0, rad_q)
     rel = np.linalg.norm(rad_t - rad0) / np.linalg.norm(rad0)

@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-from _gpu_common import keys_to_ij, log, run_frame, within_entry_tol  # noqa: E402
+from _gpu_common import check_csr_csc, keys_to_ij, log, omega_of, run_frame, within_entry_tol  # noqa: E402
 from oracle import render as orender  # noqa: E402
 from oracle.sampling import pass1, pass2, weights_from_g  # noqa: E402
 from paper_2202_12567_amd import api  # noqa: E402
@@ -60,7 +60,7 @@ def test_every_slice_properties(mid):
         assert np.unique(e1).shape[0] == info["N1"]
         assert np.unique(e2).shape[0] == e2.shape[0] == info["N2"]
         assert not np.isin(e2, e1).any()
-        assert int(view(run, "ROW_PTR", s)[-1]) == info["N1"] + info["N2"]
+        assert int(view(run, "COL_PTR", s)[-1]) == info["N1"] + info["N2"]
     assert (st["iters"] == 100).all()
     assert not (st["flags"] & 4).any()
 
@@ -100,10 +100,8 @@ def test_sampled_slices_adm_parity(mid):
         info = run["info"][s]
         m, n, q = info["m"], info["n"], info["q"]
         log(f"mid slice {s}: oracle ADM on the GPU's samples")
-        rp = view(run, "ROW_PTR", s)
-        ii = np.repeat(np.arange(m), np.diff(rp))
-        jj = view(run, "CSR_COL", s).astype(np.int64)
-        A = view(run, "CSR_VAL", s, 3).reshape(-1, 3).astype(np.float64)
+        ii, jj, A = omega_of(run, s)
+        A = A.astype(np.float64)
         I, iters, err, flags, fac = orender.complete_and_render(m, n, q, ii, jj, A, SEED, s, p)
         rel = orender.relative_rmse(run["radiance"][sc.slice_rows(s)], I)
         log(f"mid slice {s}: pixel RMSE vs oracle {rel:.2e}")
@@ -142,10 +140,10 @@ def test_uneven_batch_against_oracle(batch):
     for s in range(sc.n_slices):
         info = run["info"][s]
         m, n, q = info["m"], info["n"], info["q"]
-        rp = view(run, "ROW_PTR", s)
-        ii = np.repeat(np.arange(m), np.diff(rp))
-        jj = view(run, "CSR_COL", s).astype(np.int64)
-        A = view(run, "CSR_VAL", s, 3).reshape(-1, 3).astype(np.float64)
+        if not info["adm_in_lds"]:
+            check_csr_csc(run, s)       # the global-memory kernel's input orders
+        ii, jj, A = omega_of(run, s)
+        A = A.astype(np.float64)
         I, *_ = orender.complete_and_render(m, n, q, ii, jj, A, 21, s, p)
         rel = orender.relative_rmse(run["radiance"][sc.slice_rows(s)], I)
         log(f"batch slice {s} (m={m}, n={n}, q={q}, {'lds' if info['adm_in_lds'] else 'global'}): "

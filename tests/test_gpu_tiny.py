@@ -8,7 +8,7 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-from _gpu_common import keys_to_ij, log, run_frame, within_entry_tol  # noqa: E402
+from _gpu_common import keys_to_ij, log, omega_of, run_frame, within_entry_tol  # noqa: E402
 from oracle import adm as oadm  # noqa: E402
 from oracle import render as orender  # noqa: E402
 from oracle.cluster import cluster_table  # noqa: E402
@@ -181,23 +181,18 @@ def test_pass2_bit_exact_given_weights(run, scene):
         assert bool(run["stats"]["flags"][s] & 4) == short
 
 
-def test_csr_and_csc_order(run, scene):
+def test_column_pointers_and_distinct_samples(run, scene):
+    """Every slice here is completed from its ELL copy (checked through the
+    completion itself); the column pointers cover Omega = Omega1 u Omega2, whose
+    entries are distinct."""
     for s in range(scene.n_slices):
         info = run["info"][s]
         m, n = info["m"], info["n"]
-        i = np.concatenate([keys_to_ij(slice_view(run, "OMEGA1", s))[0], keys_to_ij(slice_view(run, "OMEGA2", s))[0]])
-        j = np.concatenate([keys_to_ij(slice_view(run, "OMEGA1", s))[1], keys_to_ij(slice_view(run, "OMEGA2", s))[1]])
-        v = np.concatenate([slice_view(run, "VAL1", s, 3), slice_view(run, "VAL2", s, 3)]).reshape(-1, 3)
-        order = np.lexsort((j, i))
-        rp = np.concatenate([[0], np.cumsum(np.bincount(i, minlength=m))])
-        assert np.array_equal(slice_view(run, "ROW_PTR", s), rp)
-        assert np.array_equal(slice_view(run, "CSR_COL", s), j[order])
-        assert np.array_equal(slice_view(run, "CSR_VAL", s, 3).reshape(-1, 3), v[order])
-        order = np.lexsort((i, j))
+        assert info["adm_in_lds"] == 1
+        i, j, _ = omega_of(run, s)
+        assert np.unique(i * n + j).shape[0] == i.shape[0]
         cp = np.concatenate([[0], np.cumsum(np.bincount(j, minlength=n))])
         assert np.array_equal(slice_view(run, "COL_PTR", s), cp)
-        assert np.array_equal(slice_view(run, "CSC_ROW", s), i[order])
-        assert np.array_equal(slice_view(run, "CSC_VAL", s, 3).reshape(-1, 3), v[order])
 
 
 def test_initial_factors_bit_exact(scene):
@@ -216,10 +211,8 @@ def test_initial_factors_bit_exact(scene):
 def adm_on_gpu_samples(run, s, iters=ITERS):
     info = run["info"][s]
     m, n, q = info["m"], info["n"], info["q"]
-    rp = slice_view(run, "ROW_PTR", s)
-    ii = np.repeat(np.arange(m), np.diff(rp))
-    jj = slice_view(run, "CSR_COL", s).astype(np.int64)
-    A = slice_view(run, "CSR_VAL", s, 3).reshape(-1, 3).astype(np.float64)
+    ii, jj, A = omega_of(run, s)
+    A = A.astype(np.float64)
     p = oracle_params(max_iter=iters)
     return orender.complete_and_render(m, n, q, ii, jj, A, SEED, s, p)
 
