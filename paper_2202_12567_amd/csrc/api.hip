@@ -487,7 +487,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if ((rc = launch_pass1(st, *plan, desc, params->seed, omega1, bm, bmt))) return rc;
     if ((rc = ph.mark(VPLMC_PH_EVAL1))) return rc;
     if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_clusters, desc, S, pt_ids, cl_ids, omega1,
-                                plan->tot1, 0, stats, *params, val1, plan->tune.eval_threads)))
+                                plan->tot1, 0, stats, *params, val1, plan->tune.eval_threads, ctx->n_cu)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_WEIGHTS))) return rc;
     int32_t *col_ptr = region<int32_t>(ws, plan, VPLMC_R_COL_PTR);
@@ -525,7 +525,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if ((rc = launch_pass2(st, *plan, desc, params->seed, prefix, bm, bmt, omega2, stats))) return rc;
     if ((rc = ph.mark(VPLMC_PH_EVAL2))) return rc;
     if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_clusters, desc, S, pt_ids, cl_ids, omega2,
-                                plan->tot2, 1, stats, *params, val2, plan->tune.eval_threads)))
+                                plan->tot2, 1, stats, *params, val2, plan->tune.eval_threads, ctx->n_cu)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_SORT))) return rc;
     int32_t *row_ptr = region<int32_t>(ws, plan, VPLMC_R_ROW_PTR);

@@ -11,6 +11,8 @@
 // traversal of a bounding-volume hierarchy in depth-first order with skip
 // indices (no stack).
 
+#include <algorithm>
+
 #include "vplmc_internal.h"
 
 namespace vplmc {
@@ -24,13 +26,40 @@ struct P3 {
 __device__ __forceinline__ P3 sub(P3 a, P3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ float dot(P3 a, P3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
 
+// The BVH as read by a traversal: from global memory, or from a copy staged
+// in LDS (nodes as pairs of float4, then the spheres).
+struct BvhGlobal {
+    const Bvh &b;
+    __device__ BvhNode node(int k) const { return b.nodes[k]; }
+    __device__ float4 sphere(int k) const { return b.spheres[k]; }
+};
+struct BvhStaged {
+    const float4 *lds;   // LDS: 2 n_nodes float4 of nodes, then the spheres
+    int n_nodes;
+    __device__ BvhNode node(int k) const {
+        const float4 a = lds[2 * k], c = lds[2 * k + 1];
+        BvhNode nd;
+        nd.lo[0] = a.x;
+        nd.lo[1] = a.y;
+        nd.lo[2] = a.z;
+        nd.leaf = __float_as_int(a.w);
+        nd.hi[0] = c.x;
+        nd.hi[1] = c.y;
+        nd.hi[2] = c.z;
+        nd.skip = __float_as_int(c.w);
+        return nd;
+    }
+    __device__ float4 sphere(int k) const { return lds[2 * n_nodes + k]; }
+};
+
 // does a sphere of a leaf (first << 4 | count) come closer to the segment
 // o + t D, t in [0, 1], than its radius
-__device__ __forceinline__ bool leaf_occludes(const Bvh &bvh, int leaf, P3 o, P3 D, float inv_dd) {
+template <typename B>
+__device__ __forceinline__ bool leaf_occludes(const B &bvh, int leaf, P3 o, P3 D, float inv_dd) {
     const int first = leaf >> 4, cnt = leaf & 15;
     bool any = false;
     for (int k = 0; k < cnt; ++k) {
-        const float4 sp4 = bvh.spheres[first + k];
+        const float4 sp4 = bvh.sphere(first + k);
         const P3 oc = {sp4.x - o.x, sp4.y - o.y, sp4.z - o.z};
         const float t = fminf(fmaxf(dot(oc, D) * inv_dd, 0.0f), 1.0f);
         const P3 p = {oc.x - t * D.x, oc.y - t * D.y, oc.z - t * D.z};
@@ -40,16 +69,17 @@ __device__ __forceinline__ bool leaf_occludes(const Bvh &bvh, int leaf, P3 o, P3
 }
 
 // any hit on the open segment o + t D, t in (0, 1)
-__device__ __forceinline__ bool occluded(const Bvh &bvh, P3 o, P3 D) {
-    if (bvh.n_nodes == 0) return false;
+template <typename B>
+__device__ __forceinline__ bool occluded_in(const B &bvh, int n_nodes, P3 o, P3 D) {
+    if (n_nodes == 0) return false;
     const float dd = dot(D, D);
     const float inv_dd = 1.0f / dd;
     const float ix = 1.0f / (fabsf(D.x) > 1e-20f ? D.x : copysignf(1e-20f, D.x));
     const float iy = 1.0f / (fabsf(D.y) > 1e-20f ? D.y : copysignf(1e-20f, D.y));
     const float iz = 1.0f / (fabsf(D.z) > 1e-20f ? D.z : copysignf(1e-20f, D.z));
     int node = 0;
-    while (node < bvh.n_nodes) {
-        const BvhNode nd = bvh.nodes[node];
+    while (node < n_nodes) {
+        const BvhNode nd = bvh.node(node);
         const float tx0 = (nd.lo[0] - o.x) * ix, tx1 = (nd.hi[0] - o.x) * ix;
         const float ty0 = (nd.lo[1] - o.y) * iy, ty1 = (nd.hi[1] - o.y) * iy;
         const float tz0 = (nd.lo[2] - o.z) * iz, tz1 = (nd.hi[2] - o.z) * iz;
@@ -62,6 +92,10 @@ __device__ __forceinline__ bool occluded(const Bvh &bvh, P3 o, P3 D) {
         node = hit && nd.leaf == 0 ? node + 1 : nd.skip;
     }
     return false;
+}
+
+__device__ __forceinline__ bool occluded(const Bvh &bvh, P3 o, P3 D) {
+    return occluded_in(BvhGlobal{bvh}, bvh.n_nodes, o, D);
 }
 
 struct PointData {
@@ -87,9 +121,11 @@ struct Light {
     float i0, i1, i2;
 };
 
-// entry of one (point, light) pair; returns false (and zeros) when no ray is needed
-__device__ __forceinline__ void shade(const Bvh &bvh, const PointData &q, const Light &L, float r_min2,
-                                      float eps, float &o0, float &o1, float &o2) {
+// entry of one (point, light) pair (zero when the pair faces away or is
+// occluded); bvh is a BVH view (BvhGlobal or BvhStaged) of n_nodes nodes
+template <typename B>
+__device__ __forceinline__ void shade_in(const B &bvh, int n_nodes, const PointData &q, const Light &L,
+                                         float r_min2, float eps, float &o0, float &o1, float &o2) {
     o0 = o1 = o2 = 0.0f;
     const P3 d = sub(L.y, q.x);
     const float r2 = dot(d, d);
@@ -106,10 +142,15 @@ __device__ __forceinline__ void shade(const Bvh &bvh, const PointData &q, const 
         spec = q.ks * (q.e + 2.0f) * (0.5f * INV_PI) * powf(cr, q.e);
     }
     const P3 o = {fmaf(eps, q.n.x, q.x.x), fmaf(eps, q.n.y, q.x.y), fmaf(eps, q.n.z, q.x.z)};
-    if (occluded(bvh, o, sub(L.y, o))) return;
+    if (occluded_in(bvh, n_nodes, o, sub(L.y, o))) return;
     o0 = fmaf(q.kd0, INV_PI, spec) * L.i0 * G;
     o1 = fmaf(q.kd1, INV_PI, spec) * L.i1 * G;
     o2 = fmaf(q.kd2, INV_PI, spec) * L.i2 * G;
+}
+
+__device__ __forceinline__ void shade(const Bvh &bvh, const PointData &q, const Light &L, float r_min2,
+                                      float eps, float &o0, float &o1, float &o2) {
+    shade_in(BvhGlobal{bvh}, bvh.n_nodes, q, L, r_min2, eps, o0, o1, o2);
 }
 
 __device__ __forceinline__ int slice_of_off(const SliceDesc *__restrict__ desc, int S, int64_t g, int which) {
@@ -122,16 +163,14 @@ __device__ __forceinline__ int slice_of_off(const SliceDesc *__restrict__ desc, 
     return lo;
 }
 
-// entries of one pass's samples (draw order), lights = cluster table planes
-__global__ __launch_bounds__(256) void k_eval_omega(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
-                                                    int32_t n_lights, const SliceDesc *__restrict__ desc, int S,
-                                                    const int32_t *__restrict__ pt_ids,
-                                                    const int32_t *__restrict__ cl_ids,
-                                                    const uint32_t *__restrict__ keys, int64_t n_keys,
-                                                    int which, const int32_t *__restrict__ stats, float r_min2,
-                                                    float eps, float *__restrict__ vals) {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= n_keys) return;
+// entry of sample g of one pass (nothing for second-pass slots past the accepted count)
+template <bool STAGED>
+__device__ __forceinline__ void eval_one(const Bvh &bvh, const BvhStaged &staged, const vplmc_points &pts,
+                                         const float *__restrict__ lights, int32_t n_lights,
+                                         const SliceDesc *__restrict__ desc, int S, const int32_t *__restrict__ pt_ids,
+                                         const int32_t *__restrict__ cl_ids, const uint32_t *__restrict__ keys,
+                                         int64_t g, int which, const int32_t *__restrict__ stats, float r_min2,
+                                         float eps, float *__restrict__ vals) {
     const int s = slice_of_off(desc, S, g, which);
     const SliceDesc d = desc[s];
     if (which && g - d.off2 >= stats[4 * s + 3]) return;
@@ -145,10 +184,45 @@ __global__ __launch_bounds__(256) void k_eval_omega(Bvh bvh, vplmc_points pts, c
                      lights[6 * N + c], lights[7 * N + c], lights[8 * N + c]};
     const PointData q = load_point(pts, pid);
     float o0, o1, o2;
-    shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+    if (STAGED)
+        shade_in(staged, bvh.n_nodes, q, L, r_min2, eps, o0, o1, o2);
+    else
+        shade(bvh, q, L, r_min2, eps, o0, o1, o2);
     vals[3 * g] = o0;
     vals[3 * g + 1] = o1;
     vals[3 * g + 2] = o2;
+}
+
+// BVH bytes (nodes and spheres) an entry kernel stages in LDS; larger ones are
+// read from global memory
+constexpr int EVAL_LDS_BYTES = 48 * 1024;
+// workgroups per compute unit of an entry launch
+constexpr int EVAL_GRID_PER_CU = 16;
+
+// entries of one pass's samples (draw order), lights = cluster table planes;
+// a fixed grid walks the samples, each workgroup first copying the BVH to LDS
+// when STAGED
+template <bool STAGED>
+__global__ __launch_bounds__(256) void k_eval_omega(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
+                                                    int32_t n_lights, const SliceDesc *__restrict__ desc, int S,
+                                                    const int32_t *__restrict__ pt_ids,
+                                                    const int32_t *__restrict__ cl_ids,
+                                                    const uint32_t *__restrict__ keys, int64_t n_keys,
+                                                    int which, const int32_t *__restrict__ stats, float r_min2,
+                                                    float eps, float *__restrict__ vals) {
+    extern __shared__ float4 stage[];
+    if (STAGED) {
+        const int nn = 2 * bvh.n_nodes, ns = bvh.n_spheres;
+        const float4 *nodes4 = reinterpret_cast<const float4 *>(bvh.nodes);
+        for (int k = threadIdx.x; k < nn + ns; k += blockDim.x) stage[k] = k < nn ? nodes4[k] : bvh.spheres[k - nn];
+        __syncthreads();
+    }
+    const BvhStaged staged{stage, bvh.n_nodes};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_keys; g += stride) {
+        eval_one<STAGED>(bvh, staged, pts, lights, n_lights, desc, S, pt_ids, cl_ids, keys, g, which, stats, r_min2,
+                         eps, vals);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_eval_pairs(Bvh bvh, vplmc_points pts, vplmc_lights l, int64_t n,
@@ -306,12 +380,21 @@ int launch_targets(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc
 int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
                       int32_t n_lights, const SliceDesc *desc, int32_t n_slices, const int32_t *pt_ids,
                       const int32_t *cl_ids, const uint32_t *keys, int64_t n_keys, int which,
-                      const int32_t *stats, const vplmc_params &prm, float *vals, int threads) {
+                      const int32_t *stats, const vplmc_params &prm, float *vals, int threads, int n_cu) {
     if (n_keys <= 0) return VPLMC_OK;
     if (threads != 64 && threads != 128 && threads != 256) threads = 256;   // __launch_bounds__(256)
-    hipLaunchKernelGGL(k_eval_omega, dim3(blocks_for(n_keys, threads)), dim3(threads), 0, st, bvh, pts, lights, n_lights,
-                       desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats, prm.r_min * prm.r_min,
-                       prm.ray_eps, vals);
+    // enough workgroups to fill the chip several times over; each walks the
+    // samples with a grid stride
+    const int64_t blocks = std::min<int64_t>(blocks_for(n_keys, threads), (int64_t)EVAL_GRID_PER_CU * n_cu);
+    const size_t staged = ((size_t)2 * bvh.n_nodes + bvh.n_spheres) * sizeof(float4);
+    if (bvh.n_nodes > 0 && staged <= (size_t)EVAL_LDS_BYTES)
+        hipLaunchKernelGGL(k_eval_omega<true>, dim3((unsigned)blocks), dim3(threads), staged, st, bvh, pts, lights,
+                           n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
+                           prm.r_min * prm.r_min, prm.ray_eps, vals);
+    else
+        hipLaunchKernelGGL(k_eval_omega<false>, dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
+                           n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
+                           prm.r_min * prm.r_min, prm.ray_eps, vals);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }

@@ -231,7 +231,7 @@ int launch_pass1(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, 
 int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
                       int32_t n_lights, const SliceDesc *desc, int32_t n_slices, const int32_t *pt_ids,
                       const int32_t *cl_ids, const uint32_t *keys, int64_t n_keys, int which_pass,
-                      const int32_t *stats, const vplmc_params &prm, float *vals, int threads = 256);
+                      const int32_t *stats, const vplmc_params &prm, float *vals, int threads, int n_cu);
 int launch_colstats(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *omega1,
                     const float *val1, const uint32_t *bmt, uint16_t *wpret, int32_t *col_ptr, int32_t *csc_row,
                     float *csc_val, int32_t *cnt, float *mn, float *mx, double *sum, double *sumsq, int32_t *zeros);
