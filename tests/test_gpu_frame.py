@@ -1,0 +1,151 @@
+"""The 1080p frame configuration at full size on the GPU: 1920x1080 points,
+2,048 spheres, 300,000 VPLs cut to 16,384 clusters, ~3,000 uneven slices (rank
+32 from 512 rows, completed in global memory; 16 below, from the ELL copy),
+0.25% + 0.25% sampling (a 100 GB workspace), the completion cut to 10 fixed
+iterations so that the test stays short.  Checked through properties of every
+slice and, on sampled slices, stage by stage and through the oracle's
+completion of the GPU's own samples."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from _gpu_common import check_scene_indices, keys_to_ij, log, within_entry_tol  # noqa: E402
+from oracle import render as orender  # noqa: E402
+from oracle.sampling import pass1, pass2, weights_from_g  # noqa: E402
+from paper_2202_12567_amd import api  # noqa: E402
+from scenegen import make_scene  # noqa: E402
+
+SEED = 41
+PPM = 2500
+ITERS = 10
+
+
+@pytest.fixture(scope="module")
+def frame():
+    log("frame config: building the scene (1920x1080, 300,000 VPLs)")
+    sc = make_scene("frame", SEED)
+    check_scene_indices(sc)
+    dev = torch.device("cuda", 0)
+    prm = api.default_params(seed=SEED, pass1_ppm=PPM, pass2_ppm=PPM, max_iter=ITERS, fixed_iters=True)
+    ctx = api.Context(0)
+    ctx.set_occluders(sc.spheres)
+    ds = api.DeviceScene(sc, dev)
+    plan = api.Plan(sc, prm)
+    log(f"frame config: {sc.n_slices} slices, workspace {plan.workspace_bytes / 1e9:.1f} GB")
+    ws = api.workspace(plan, dev)
+    rad = api.render(ctx, plan, ds, prm, ws)
+    torch.cuda.synchronize()
+    log("frame config: rendered")
+    info = [plan.slice_info(s) for s in range(sc.n_slices)]
+    out = dict(sc=sc, plan=plan, ws=ws, ctx=ctx, info=info, stats=api.read_stats(ctx, plan, ws),
+               radiance=rad.double().cpu().numpy())
+    yield out
+    del ws
+    torch.cuda.empty_cache()
+
+
+def region(fr, name, dtype, a, n, width=1):
+    v = api.region_view(fr["plan"], fr["ws"], name, dtype)
+    return v[width * a: width * (a + n)].cpu().numpy()
+
+
+def samples(fr, s):
+    info = fr["info"][s]
+    n2 = int(fr["stats"]["n2"][s])
+    k1 = region(fr, "OMEGA1", torch.int32, info["off1"], info["N1"])
+    k2 = region(fr, "OMEGA2", torch.int32, info["off2"], n2)
+    v1 = region(fr, "VAL1", torch.float32, info["off1"], info["N1"], 3).reshape(-1, 3)
+    v2 = region(fr, "VAL2", torch.float32, info["off2"], n2, 3).reshape(-1, 3)
+    return k1, k2, v1, v2
+
+
+def chosen_slices(fr):
+    """The smallest slice completed from the ELL copy, the smallest and the
+    largest completed in global memory."""
+    info = fr["info"]
+    ell = [s for s in range(len(info)) if info[s]["adm_in_lds"]]
+    glob = [s for s in range(len(info)) if not info[s]["adm_in_lds"]]
+    assert ell and glob
+    by_m = lambda ss: sorted(ss, key=lambda s: (info[s]["m"], s))
+    return by_m(ell)[0], by_m(glob)[0], by_m(glob)[-1]
+
+
+def test_frame_every_slice(frame):
+    sc, info, st = frame["sc"], frame["info"], frame["stats"]
+    assert np.isfinite(frame["radiance"]).all()
+    assert (st["iters"] == ITERS).all()
+    # at 0.25% of 16,384 columns most columns have at most one first-pass
+    # observation, so g = 0 there, and the second pass may exhaust its attempts
+    # on the few columns left: those slices carry the shortfall flag
+    n2 = st["n2"].astype(np.int64)
+    N2 = np.array([i["N2"] for i in info])
+    short = (st["flags"] & 4) != 0
+    assert np.array_equal(n2[~short], N2[~short])
+    assert (n2[short] < N2[short]).all()
+    log(f"frame config: {int(short.sum())} of {sc.n_slices} slices short in the second pass")
+    q = np.array([i["q"] for i in info])
+    m = np.array([i["m"] for i in info])
+    assert np.array_equal(q, np.where(m >= 512, 32, 16))
+    # distinct samples of both passes, inside the slice, on every 16th slice
+    for s in range(0, sc.n_slices, 16):
+        k1, k2, _, _ = samples(frame, s)
+        i1, j1 = keys_to_ij(k1)
+        i2, j2 = keys_to_ij(k2)
+        mm, nn = info[s]["m"], info[s]["n"]
+        e = np.concatenate([i1 * nn + j1, i2 * nn + j2])
+        assert i1.max() < mm and j1.max() < nn and (i2.size == 0 or (i2.max() < mm and j2.max() < nn))
+        assert np.unique(e).shape[0] == e.shape[0]
+    log(f"frame config: {sc.n_slices} slices, {int(n2.sum() + sum(i['N1'] for i in info))} samples")
+
+
+def test_frame_sampled_slices_stage_parity(frame):
+    sc, info = frame["sc"], frame["info"]
+    lights = orender.cluster_lights(sc, SEED)
+    p = orender.Params(seed=SEED, pass1_ppm=PPM, pass2_ppm=PPM)
+    for s in chosen_slices(frame):
+        m, n = info[s]["m"], info[s]["n"]
+        log(f"frame slice {s} (m={m}, n={n}, q={info[s]['q']}): pass 1")
+        k1, k2, v1, _ = samples(frame, s)
+        gi, gj = keys_to_ij(k1)
+        i1, j1 = pass1(SEED, s, m, n, PPM)
+        assert np.array_equal(gi, i1) and np.array_equal(gj, j1)
+        log(f"frame slice {s}: entries")
+        sel = np.random.default_rng(s).choice(i1.shape[0], min(2000, i1.shape[0]), replace=False)
+        o, amb, _ = orender.eval_entries(sc, lights, sc.slice_rows(s)[gi[sel]], sc.slice_cols(s)[gj[sel]], p)
+        assert not within_entry_tol(v1[sel], o, amb).any()
+        log(f"frame slice {s}: weights and pass 2")
+        a = info[s]["off_col"]
+        gmin = region(frame, "COLMIN", torch.float32, a, n)
+        gmax = region(frame, "COLMAX", torch.float32, a, n)
+        cnt = region(frame, "COLCNT", torch.int32, a, n)
+        g32 = np.where(cnt > 0, (gmax - gmin).astype(np.float32), np.float32(0))
+        w = region(frame, "WEIGHTS", torch.int32, a, n).astype(np.uint64)
+        assert np.array_equal(w, weights_from_g(g32.astype(np.float64)))
+        taken = np.zeros(m * n, bool)
+        taken[gi * n + gj] = True
+        i2, j2, short = pass2(SEED, s, m, n, info[s]["N1"], PPM, w, taken)
+        gi2, gj2 = keys_to_ij(k2)
+        assert np.array_equal(gi2, i2) and np.array_equal(gj2, j2)
+        assert bool(short) == bool(frame["stats"]["flags"][s] & 4)
+
+
+def test_frame_completion_on_the_gpu_samples(frame):
+    """The oracle's completion (same 10 iterations, same initial factors) of
+    the GPU's samples against the GPU's radiance, for the smallest slice of
+    each completion kernel."""
+    sc, info = frame["sc"], frame["info"]
+    p = orender.Params(seed=SEED, pass1_ppm=PPM, pass2_ppm=PPM, max_iter=ITERS, fixed_iters=True)
+    ell, small_global, _ = chosen_slices(frame)
+    for s in (ell, small_global):
+        m, n, q = info[s]["m"], info[s]["n"], info[s]["q"]
+        k1, k2, v1, v2 = samples(frame, s)
+        ii, jj = keys_to_ij(np.concatenate([k1, k2]))
+        A = np.concatenate([v1, v2]).astype(np.float64)
+        log(f"frame slice {s} (m={m}, n={n}, q={q}, {'ELL' if info[s]['adm_in_lds'] else 'global'}): oracle ADM")
+        I, *_ = orender.complete_and_render(m, n, q, ii, jj, A, SEED, s, p)
+        rel = orender.relative_rmse(frame["radiance"][sc.slice_rows(s)], I)
+        log(f"frame slice {s}: pixel RMSE vs oracle {rel:.2e}")
+        assert rel <= 1e-3
