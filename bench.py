@@ -57,6 +57,11 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "copies": 3}), flush=True)
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def frame_times(api, torch, ctx, plan, ds, prm, ws, rad, steps, warmup, eager=False):
     """Mean frame ms of the captured frame graph (or of eager frames) over
     `steps` launches after `warmup` (device-resident inputs); `rad` holds the
@@ -187,9 +192,11 @@ def main():
     # W untimed launches, then exactly K timed ones, an event after each
     graph = None if args.eager else api.Graph(ctx, plan, ds, prm, ws, rad)
     frame = graph.launch if graph else (lambda: api.render(ctx, plan, ds, prm, ws, rad))
+    progress(f"{args.workload}: {sc.n_slices} slices, workspace {plan.workspace_bytes / 1e9:.1f} GB")
     for _ in range(args.warmup):
         frame()
     torch.cuda.synchronize()
+    progress("warm-up done")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     ev[0].record()
@@ -202,6 +209,7 @@ def main():
     ms_median = float(np.median(per_frame))
     if graph:
         graph.close()
+    progress(f"timed {args.steps} frames: {ms:.3f} ms per frame")
 
     # phase times from HIP events around each phase (eager frames of the same plan)
     api.profile_begin(ctx, args.steps)
@@ -209,6 +217,7 @@ def main():
         api.render(ctx, plan, ds, prm, ws, rad)
     torch.cuda.synchronize()
     phase_ms, frames = api.profile_end(ctx)
+    progress("phase times done")
     phase_ms = {k: v / max(frames, 1) for k, v in phase_ms.items()}
     eager_ms = sum(phase_ms.values())
 
@@ -234,6 +243,7 @@ def main():
     rmse_full = rel(got, ref)
     rmse_cut = rel(got, cut_ref)
     cut_vs_full = rel(cut_ref, ref)
+    progress("reference sums done")
 
     # roofline of the dominant kernel (the completion, one launch per frame):
     # algorithmic HBM bytes = 16 B (row index + RGB) per sampled entry per
@@ -288,6 +298,7 @@ def main():
                     pts[name].append((er, msr))
                     row[name] = {"frame_ms": round(msr, 3), "pixel_rmse": round(er, 5)}
                 rows.append(row)
+                progress(f"sweep {r}%: plain {row['plain']['frame_ms']} ms, learned {row['learned']['frame_ms']} ms")
                 del wsr
                 pl.close()
             target = rmse_full
