@@ -39,11 +39,6 @@ __device__ __forceinline__ float wave_sum(float v) {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
     return v;
 }
-// a wavefront-uniform value kept in a scalar register
-__device__ __forceinline__ float uniform(float v) {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
@@ -480,30 +475,35 @@ __device__ void adm_global_slice(
 }
 
 // ---------------------------------------------------------------------------
-// LDS-resident variant for ranks 4, 8, 16 (m (q + 1) words of X_k and one
-// more buffer in LDS).  The samples are read from the slice's ELL copy, in
-// which one lane walks one part of a column (at most ELL_LMAX samples; the
-// parts of a 64-lane group have nearly equal lengths) and every load of a
-// wavefront covers 64 consecutive entries.
+// LDS-resident variant for ranks 4, 8, 16 (two LDS buffers of m (q + 1)
+// words: X_k, and the R Y^T accumulator that then holds T and X+).  The
+// samples are read from the slice's ELL copy, in which one lane walks one
+// part of a column (at most ELL_LMAX samples; the parts of a 64-lane group
+// have nearly equal lengths) and every load of a wavefront covers 64
+// consecutive entries.
 //   phase A, lane = part of column j: Y_j (3q floats) in registers, X_i from LDS;
 //     the residual r is stored in the ELL copy and the q components of
 //     sum_c r_c Y_j^c, times 2^S and rounded, are added into row i of a
 //     fixed-point R Y^T accumulator with integer LDS atomics (LDS float
 //     atomics serialise per lane on this chip).  Integer sums do not depend
-//     on the order of the additions.  2^S is the largest power of two with
-//     K (rs |Y|max 2^S + 1/2) < 2^31, K = most samples of a row, rs = the
-//     largest sum_c |r_c| (a bound of the first iterate, then twice the
-//     previous iterate's); if the iterate's own rs breaks the bound the
-//     phase is run again with the smaller scale, so no sum overflows.
-//   X update: T = R Y^T + a U - L, then X+ = X (GY Inv) + T Inv as FP32
-//     16 x 16 x 4 MFMA products per 16 rows (the FP64 factors of the q x q
-//     solve rounded to FP32), with U, L and the Grams X+^T X+ and X+^T X
-//     fused on the product's output registers.
+//     on the order of the additions.  Word q of each row sums a ceil-rounded
+//     bound of the row's L1 residual sum; the scale 2^S keeps every row sum
+//     below 2^31 given that bound and |Y|max, and the phase runs again with
+//     a smaller scale whenever an estimate taken from the previous iterate
+//     fails, so no sum overflows.
+//   X system, X update: Inv = (GY + a I)^-1 by FP64 Cholesky, T = R Y^T + a U - L,
+//     then X+ = X (GY Inv) + T Inv as FP32 16 x 16 x 4 MFMA products per 16
+//     rows (the FP64 factors rounded to FP32), with U, L and the Grams X+^T X+
+//     and X+^T X fused on the product's output registers.
 //   phase B, lane = part of column j: X+^T R over the part from the stored
-//     residuals and X+ (LDS); T_j = X+^T R_j + b V_j - P_j (global staging),
-//     the partial sums of a column of several parts added in part order.
-//   Y update: Y+ = Y (Inv C)^T + T Inv as FP32 MFMA products per 16 rows of
-//     the 3n x q matrix, with V, P and the Gram Y+^T Y+.
+//     residuals and X+ (LDS); T_j = X+^T R_j + W_j staged in global memory
+//     (W = b V - P is what the Y update stores of V and P), the partial sums
+//     of a column of several parts added in part order.
+//   Y system, Y update: Inv = (GX + b I)^-1, Y+ = Y (Inv C)^T + T Inv as FP32
+//     MFMA products per 16 rows of the 3n x q matrix, with P, W and the Gram
+//     Y+^T Y+.
+// Every phase issues a unit's loads before its stores: loads and stores retire
+// through one in-order counter, so a load behind a store waits for the store.
 // Rows of X in LDS keep their 4-float chunks rotated (xpos), which spreads the
 // 128-bit reads of a wavefront over the banks.
 // Per-wavefront partial Grams are summed in a fixed order through the
@@ -524,9 +524,7 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-// block-wide maximum of per-thread values; every thread calls it and gets the result
 // a value every lane holds alike, moved to scalar registers
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ float uni(float x) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
@@ -536,6 +534,7 @@ __device__ __forceinline__ double uni(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// block-wide maximum of per-thread values; every thread calls it and gets the result
 __device__ __forceinline__ float block_max(float v, float *red) {
     const int t = fresh_tid(), nw = blockDim.x / WAVE, lane = t % WAVE, w = t / WAVE;
     v = wave_max(v);

@@ -94,9 +94,6 @@ __device__ __forceinline__ bool occluded_in(const B &bvh, int n_nodes, P3 o, P3 
     return false;
 }
 
-__device__ __forceinline__ bool occluded(const Bvh &bvh, P3 o, P3 D) {
-    return occluded_in(BvhGlobal{bvh}, bvh.n_nodes, o, D);
-}
 
 struct PointData {
     P3 x, n, wo;
