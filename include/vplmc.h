@@ -323,7 +323,7 @@ int vplmc_mlp_train_step(vplmc_ctx *ctx, float *params, float *m, float *v, int3
                          const float *features, const float *pstar, int32_t n_groups, const int32_t *group_offsets,
                          void *scratch, size_t scratch_bytes, float *loss);
 /* Training targets from fully evaluated slices: pstar per (slice, column) in
- * the plan's column layout, p*_j ~ sigma_j + 0.01 mean(sigma), sigma_j the
+ * the plan's column layout, p*_j ~ sigma_j + 3 mean(sigma), sigma_j the
  * standard deviation of R+G+B over the column.  lights: DEVICE float[9][n_clusters]
  * (vplmc_cluster_table); the workspace is used as scratch. */
 int vplmc_proposal_targets(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points, const float *lights,

@@ -12,10 +12,14 @@ Readings (the paper has no network):
 * network y = W3 h2 + b3, h2 = bf16(gelu(W2 h1 + b2)), h1 = bf16(gelu(W1 f + b1)),
   128 hidden units, GELU in its tanh form (Hendrycks & Gimpel), weights used
   rounded to bfloat16 (round to nearest even), FP32/FP64 accumulation;
-* training target p*_j ~ sigma_j + 0.01 mean(sigma) per slice, sigma_j the
+* training target p*_j ~ sigma_j + 3 mean(sigma) per slice, sigma_j the
   standard deviation of t over the full column (the variance the paper uses
-  as importance); loss KL(p* || softmax(y)) summed over the slice; Adam
-  (Kingma & Ba) on FP32 master weights;
+  as importance), mixed with three times its mean in uniform mass: sampling
+  by sigma + 0.01 mean(sigma) concentrates the second pass as much as g does
+  and completed no better than g, while the mix of 3 gave the smallest pixel
+  error of the mixes 0.01 to 30 and the uniform density on mid slices at 5%;
+  loss KL(p* || softmax(y)) summed over the slice; Adam (Kingma & Ba) on FP32
+  master weights;
 * deployment: column weights w_j = max(1, floor(2^24 exp(y_j - max y)));
   any non-finite y falls back to the plain g weights.
 
@@ -28,6 +32,7 @@ import numpy as np
 N_IN = 12
 N_HID = 128
 TWO24 = float(1 << 24)
+TARGET_MIX = 3.0       # uniform mass of the target density, in units of mean(sigma)
 SQRT_2_OVER_PI = np.sqrt(2.0 / np.pi)
 
 
@@ -145,9 +150,9 @@ def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def targets(tfull, n):
-    """p*_j ~ sigma_j + 0.01 mean(sigma) from a full slice matrix tfull (m', n')."""
+    """p*_j ~ sigma_j + TARGET_MIX mean(sigma) from a full slice matrix tfull (m', n')."""
     sig = np.asarray(tfull, np.float64).std(axis=0)
-    w = sig + 0.01 * (sig.mean() if sig.mean() > 0 else 1.0)
+    w = sig + TARGET_MIX * (sig.mean() if sig.mean() > 0 else 1.0)
     return w / w.sum()
 
 

@@ -348,7 +348,7 @@ __global__ __launch_bounds__(256) void k_target_norm(const SliceDesc *__restrict
         __syncthreads();
     }
     const double mean = red[0] / d.n;
-    const double add = 0.01 * (mean > 0.0 ? mean : 1.0);
+    const double add = PROPOSAL_TARGET_MIX * (mean > 0.0 ? mean : 1.0);
     const double total = red[0] + add * d.n;
     for (int j = t; j < d.n; j += 256) {
         const int64_t o = d.off_col + j;

@@ -124,6 +124,9 @@ struct EllView {
     int32_t *nsplit;   // per slice
 };
 constexpr int ELL_LMAX = 64;      // longest part
+// uniform mass of the proposal's training target, in units of the slice's mean
+// column standard deviation: p*_j ~ sigma_j + PROPOSAL_TARGET_MIX mean(sigma)
+constexpr double PROPOSAL_TARGET_MIX = 3.0;
 constexpr int ELL_MAX_M = 8192;   // rows of a slice that may use the ELL copy
 constexpr int ADM_RED_FLOATS = 16 * 2 * 256;   // per slice: 16 wavefronts x two 16 x 16 partial Grams
 

@@ -7,7 +7,7 @@ For every training scene (seeded, "learned" workload shape: 64x64 points,
 1,024 VPL clusters, 16 slices of 256) one frame is run with the plain
 proposal and VPLMC_FEATURES to obtain the first-pass features, and
 vplmc_proposal_targets evaluates every entry of every slice to form the
-target density p*_j ~ sigma_j + 0.01 mean(sigma).  Training minimises the
+target density p*_j ~ sigma_j + 3 mean(sigma).  Training minimises the
 summed per-slice KL(p* || softmax(y)) with vplmc_mlp_train_step (forward,
 softmax-KL, backward, Adam).  Held-out evaluation compares, at the same
 sample budget, the frame's pixel RMSE against the brute-force sum with the

@@ -187,7 +187,7 @@ def test_trained_network_gain_on_held_out_scenes():
     lg = np.zeros_like(g)
     for k in range(o.shape[0] - 1):
         gs = g[o[k]:o[k + 1]]
-        lg[o[k]:o[k + 1]] = np.log(gs + 0.01 * max(gs.mean(), 1e-30))
+        lg[o[k]:o[k + 1]] = np.log(gs + omlp.TARGET_MIX * max(gs.mean(), 1e-30))
     kl_plain = train_proposal.kl_per_group(torch.as_tensor(lg), P, offs)
     gains = train_proposal.rmse_gain(ctx, params, seeds[:4])
     log(f"held-out KL(p*||q): learned {kl_learned:.4f}, plain g {kl_plain:.4f}; pixel RMSE vs full sum "

@@ -87,6 +87,6 @@ def test_weights_from_logits():
 def test_targets_follow_column_std():
     t = np.array([[0.0, 1.0, 5.0], [0.0, 3.0, 5.0]])
     p = mlp.targets(t, 3)
-    # sigma = (0, 1, 0), mean sigma = 1/3: weights (1/300, 1 + 1/300, 1/300)
-    expect = np.array([1 / 300, 1 + 1 / 300, 1 / 300])
+    # sigma = (0, 1, 0), mean sigma = 1/3, mix 3 mean sigma = 1: weights (1, 2, 1)
+    expect = np.array([1.0, 2.0, 1.0])
     np.testing.assert_allclose(p, expect / expect.sum(), rtol=1e-14)
