@@ -33,6 +33,9 @@ namespace vplmc {
 namespace {
 
 constexpr int WAVE = 64;
+// columns with at most this many samples take the lane-per-column path of
+// the global-memory completion kernel; longer ones a wavefront each
+constexpr int ADM_LIGHT = 16;
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -106,32 +109,72 @@ __device__ void spd_inverse(AdmShared<Q> &sh, double shift) {
     __syncthreads();
 }
 
-// Gram G = M^T M of a (rows x Q) FP32 matrix into sh.G, fixed summation order.
-template <int Q>
-__device__ void gram_rows(AdmShared<Q> &sh, const float *__restrict__ M, int rows, float *part) {
-    const int t = threadIdx.x;
-    const int T = blockDim.x;
-    constexpr int P = Q * Q;
-    if (T >= P) {
-        const int groups = T / P, g = t / P, p = t % P;
-        if (g < groups) {
-            float acc = 0.f;
-            for (int r = g; r < rows; r += groups)
-                acc = fmaf(M[(size_t)r * Q + p / Q], M[(size_t)r * Q + p % Q], acc);
-            part[g * P + p] = acc;
+// Gram G = M^T M of a (rows x Q) FP32 matrix into sh.G.  The rows stream
+// through LDS in tiles of GRAM_STAGE floats (coalesced float4 loads, the next
+// tile in flight while the current one is used); a thread owns a 4 x 4 block
+// of G and every groups-th row of a tile.  The groups' partial blocks are then
+// summed in group order, so the result does not depend on timing.  part holds
+// PCAP floats.
+constexpr int GRAM_STAGE = 16384;
+
+template <int Q, int PCAP, int THREADS>
+__device__ void gram_rows(AdmShared<Q> &sh, const float *__restrict__ M, int rows, float *part, float *stage) {
+    constexpr int P = Q * Q, QB = Q / 4, NB = QB * QB;
+    constexpr int TR = GRAM_STAGE / Q;                  // rows per tile
+    constexpr int NL = GRAM_STAGE / 4 / THREADS;        // float4 per thread per tile
+    static_assert(NL >= 1 && NL * 4 * THREADS == GRAM_STAGE, "tile split");
+    const int t = fresh_tid();
+    const int groups = min(THREADS / NB, PCAP / P);
+    const int g = t / NB, blk = t % NB;
+    const int a0 = 4 * (blk / QB), b0 = 4 * (blk % QB);
+    const float4 *M4 = reinterpret_cast<const float4 *>(M);
+    const int64_t tot4 = (int64_t)rows * (Q / 4);
+    const int ntiles = (rows + TR - 1) / TR;
+    float4 buf[NL];
+    auto load = [&](int tile) {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int64_t idx = (int64_t)tile * (GRAM_STAGE / 4) + u * THREADS + t;
+            buf[u] = idx < tot4 ? M4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
+    };
+    float acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
+    if (ntiles > 0) load(0);
+    float4 *stage4 = reinterpret_cast<float4 *>(stage);
+    for (int tile = 0; tile < ntiles; ++tile) {
         __syncthreads();
-        for (int e = t; e < P; e += T) {
-            float v = 0.f;
-            for (int gg = 0; gg < groups; ++gg) v += part[gg * P + e];
-            sh.G[e] = v;
+#pragma unroll
+        for (int u = 0; u < NL; ++u) stage4[u * THREADS + t] = buf[u];
+        __syncthreads();
+        if (tile + 1 < ntiles) load(tile + 1);
+        const int rt = min(TR, rows - tile * TR);
+        if (g < groups) {
+            for (int r = g; r < rt; r += groups) {
+                const float4 u = stage4[(r * Q + a0) / 4];
+                const float4 v = stage4[(r * Q + b0) / 4];
+                const float ua[4] = {u.x, u.y, u.z, u.w}, vb[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(ua[x], vb[y], acc[x][y]);
+            }
         }
-    } else {
-        for (int e = t; e < P; e += T) {
-            float acc = 0.f;
-            for (int r = 0; r < rows; ++r) acc = fmaf(M[(size_t)r * Q + e / Q], M[(size_t)r * Q + e % Q], acc);
-            sh.G[e] = acc;
-        }
+    }
+    if (g < groups) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) part[g * P + (a0 + x) * Q + b0 + y] = acc[x][y];
+    }
+    __syncthreads();
+    for (int e = t; e < P; e += THREADS) {
+        float v = 0.f;
+        for (int gg = 0; gg < groups; ++gg) v += part[gg * P + e];
+        sh.G[e] = v;
     }
     __syncthreads();
 }
@@ -147,7 +190,11 @@ __device__ void adm_global_slice(
     float *scale_all, int32_t *stats_all) {
     constexpr int NW = THREADS / WAVE;
     __shared__ AdmShared<Q> sh;
-    __shared__ float part[(NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024];
+    constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
+    __shared__ float part[PCAP];
+    __shared__ __align__(16) float Ff[Q * Q];   // Y system, FP32: Ff[k][l] = F[k][l], If[k][l] = Inv[k][l]
+    __shared__ __align__(16) float If[Q * Q];
+    __shared__ __align__(16) float stage[GRAM_STAGE];
 
     const SliceDesc d = desc[s];
     const int m = d.m, n = d.n;
@@ -234,7 +281,7 @@ __device__ void adm_global_slice(
     const float ga = (float)((double)gamma * alpha), gb = (float)((double)gamma * beta);
     const float inv_alpha = (float)(1.0 / alpha), inv_beta = (float)(1.0 / beta);
 
-    gram_rows<Q>(sh, Y, 3 * n, part);
+    gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * n, part, stage);
 
     float *X = Xa, *Xn = Xb;
     int iters = max_iter;
@@ -362,103 +409,230 @@ __device__ void adm_global_slice(
             double v = 0.0;
             for (int l = 0; l < Q; ++l) v += sh.Inv[a * Q + l] * (double)sh.C[l * Q + b];
             sh.F[b * Q + a] = v;
+            Ff[e] = (float)v;
+            If[e] = (float)sh.Inv[e];
         }
         __syncthreads();
 
-        // ---- phase B: columns ----
-        for (int j = wave; j < n; j += NW) {
-            float y0[Q], y1[Q], y2[Q];
-            const float *yj = Y + (size_t)j * 3 * Q;
-#pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                y0[k] = yj[k];
-                y1[k] = yj[Q + k];
-                y2[k] = yj[2 * Q + k];
+        // ---- phase B, light columns (at most ADM_LIGHT samples): lane per column ----
+        // X+^T R_j over the column's samples, then per channel Y+_j = F Y_j + Inv T_j
+        // with the FP32 copies of the system
+        for (int jb = 0; jb < n; jb += THREADS) {
+            const int j = jb + fresh_tid();
+            int beg = 0, end = 0;
+            if (j < n) {
+                beg = col_ptr[j];
+                end = col_ptr[j + 1];
             }
-            float a0[Q], a1[Q], a2[Q];
+            if (j < n && end - beg <= ADM_LIGHT) {
+                // an opaque zero offset keeps the system's LDS reads inside the loop
+                // (hoisted, 2 Q^2 values would stay in registers)
+                int z = 0;
+                asm volatile("" : "+v"(z));
+                float y[3][Q], acc[3][Q];
+                const float4 *yj = reinterpret_cast<const float4 *>(Y + (size_t)j * 3 * Q);
 #pragma unroll
-            for (int k = 0; k < Q; ++k) a0[k] = a1[k] = a2[k] = 0.f;
-            const int beg = col_ptr[j], end = col_ptr[j + 1];
-            for (int p = beg + lane; p < end; p += WAVE) {
-                const int i = csc_row[p];
-                const float m0 = csc_val[3 * p] * inv_s0;
-                const float m1 = csc_val[3 * p + 1] * inv_s0;
-                const float m2 = csc_val[3 * p + 2] * inv_s0;
-                const float *xo = X + (size_t)i * Q;
-                const float *xp = Xn + (size_t)i * Q;
-                float xa[Q], xb[Q];
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int k = 0; k < Q; k += 4) {
-                    const float4 u = *(const float4 *)(xo + k);
-                    const float4 v = *(const float4 *)(xp + k);
-                    xa[k] = u.x; xa[k + 1] = u.y; xa[k + 2] = u.z; xa[k + 3] = u.w;
-                    xb[k] = v.x; xb[k + 1] = v.y; xb[k + 2] = v.z; xb[k + 3] = v.w;
-                }
-                float d0 = 0.f, d1 = 0.f, d2 = 0.f;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    d0 = fmaf(xa[k], y0[k], d0);
-                    d1 = fmaf(xa[k], y1[k], d1);
-                    d2 = fmaf(xa[k], y2[k], d2);
-                }
-                const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    a0[k] = fmaf(xb[k], r0, a0[k]);
-                    a1[k] = fmaf(xb[k], r1, a1[k]);
-                    a2[k] = fmaf(xb[k], r2, a2[k]);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                a0[k] = wave_sum(a0[k]);
-                a1[k] = wave_sum(a1[k]);
-                a2[k] = wave_sum(a2[k]);
-            }
-            // Y+ for output o = (c, k): lanes o < 3Q (two rounds when 3Q > 64)
-            float *ypj = Yp + (size_t)j * 3 * Q;
-            float *pij = Pi + (size_t)j * 3 * Q;
-            float outv[2];
-            int outo[2];
-#pragma unroll
-            for (int rnd = 0; rnd < 2; ++rnd) {
-                const int o = lane + rnd * WAVE;
-                outo[rnd] = o;
-                outv[rnd] = 0.f;
-                if (o < 3 * Q) {
-                    const int c = o / Q, k = o % Q;
-                    double v = 0.0;
-#pragma unroll
-                    for (int l = 0; l < Q; ++l) {
-                        const float yl = c == 0 ? y0[l] : (c == 1 ? y1[l] : y2[l]);
-                        const float rl = c == 0 ? a0[l] : (c == 1 ? a1[l] : a2[l]);
-                        const float tl = rl + beta_f * ypj[c * Q + l] - pij[c * Q + l];
-                        v += sh.F[l * Q + k] * (double)yl + sh.Inv[l * Q + k] * (double)tl;
+                    for (int k = 0; k < Q; k += 4) {
+                        const float4 u = yj[(c * Q + k) / 4];
+                        y[c][k] = u.x;
+                        y[c][k + 1] = u.y;
+                        y[c][k + 2] = u.z;
+                        y[c][k + 3] = u.w;
+                        acc[c][k] = acc[c][k + 1] = acc[c][k + 2] = acc[c][k + 3] = 0.f;
                     }
-                    outv[rnd] = (float)v;
+                for (int p = beg; p < end; ++p) {
+                    const int i = csc_row[p];
+                    const float m0 = csc_val[3 * p] * inv_s0;
+                    const float m1 = csc_val[3 * p + 1] * inv_s0;
+                    const float m2 = csc_val[3 * p + 2] * inv_s0;
+                    const float4 *xo = reinterpret_cast<const float4 *>(X + (size_t)i * Q);
+                    const float4 *xp = reinterpret_cast<const float4 *>(Xn + (size_t)i * Q);
+                    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+#pragma unroll
+                    for (int k = 0; k < Q; k += 4) {
+                        const float4 u = xo[k / 4];
+                        const float xa[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            d0 = fmaf(xa[e], y[0][k + e], d0);
+                            d1 = fmaf(xa[e], y[1][k + e], d1);
+                            d2 = fmaf(xa[e], y[2][k + e], d2);
+                        }
+                    }
+                    const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
+#pragma unroll
+                    for (int k = 0; k < Q; k += 4) {
+                        const float4 v = xp[k / 4];
+                        const float xb[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            acc[0][k + e] = fmaf(xb[e], r0, acc[0][k + e]);
+                            acc[1][k + e] = fmaf(xb[e], r1, acc[1][k + e]);
+                            acc[2][k + e] = fmaf(xb[e], r2, acc[2][k + e]);
+                        }
+                    }
+                }
+                float4 *ypj = reinterpret_cast<float4 *>(Yp + (size_t)j * 3 * Q);
+                float4 *pij = reinterpret_cast<float4 *>(Pi + (size_t)j * 3 * Q);
+                float4 *yw = reinterpret_cast<float4 *>(Y + (size_t)j * 3 * Q);
+                // T_j = X+^T R_j + b V_j - P_j in place of the sums
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int l = 0; l < Q; l += 4) {
+                        const float4 v = ypj[(c * Q + l) / 4], pp = pij[(c * Q + l) / 4];
+                        acc[c][l] = acc[c][l] + beta_f * v.x - pp.x;
+                        acc[c][l + 1] = acc[c][l + 1] + beta_f * v.y - pp.y;
+                        acc[c][l + 2] = acc[c][l + 2] + beta_f * v.z - pp.z;
+                        acc[c][l + 3] = acc[c][l + 3] + beta_f * v.w - pp.w;
+                    }
+                // outputs k..k+3 of the three channels; every read of Yp and P is
+                // above, so they are stored at once
+#pragma unroll 1
+                for (int k = 0; k < Q; k += 4) {
+                    float o[3][4];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const float4 *fk = reinterpret_cast<const float4 *>(Ff + z + (k + kk) * Q);
+                        const float4 *ik = reinterpret_cast<const float4 *>(If + z + (k + kk) * Q);
+                        float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+#pragma unroll
+                        for (int l = 0; l < Q; l += 4) {
+                            const float4 f = fk[l / 4], g = ik[l / 4];
+                            const float fa[4] = {f.x, f.y, f.z, f.w}, ga[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                v0 = fmaf(fa[e], y[0][l + e], fmaf(ga[e], acc[0][l + e], v0));
+                                v1 = fmaf(fa[e], y[1][l + e], fmaf(ga[e], acc[1][l + e], v1));
+                                v2 = fmaf(fa[e], y[2][l + e], fmaf(ga[e], acc[2][l + e], v2));
+                            }
+                        }
+                        o[0][kk] = v0;
+                        o[1][kk] = v1;
+                        o[2][kk] = v2;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int w = (c * Q + k) / 4;
+                        const float4 pv = pij[w];
+                        const float pa[4] = {pv.x, pv.y, pv.z, pv.w};
+                        float un[4], pn[4];
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            un[kk] = fmaxf(0.f, o[c][kk] + pa[kk] * inv_beta);
+                            pn[kk] = pa[kk] + gb * (o[c][kk] - un[kk]);
+                        }
+                        ypj[w] = make_float4(un[0], un[1], un[2], un[3]);
+                        pij[w] = make_float4(pn[0], pn[1], pn[2], pn[3]);
+                        yw[w] = make_float4(o[c][0], o[c][1], o[c][2], o[c][3]);
+                    }
                 }
             }
-            // all reads of Yp/Pi/Y for this column are done by every lane
-            __builtin_amdgcn_wave_barrier();
+        }
+
+        // ---- phase B, heavy columns: wavefront per column ----
+        for (int jb = wave * WAVE; jb < n; jb += NW * WAVE) {
+            const int jl = jb + lane;
+            const int cnt = jl < n ? col_ptr[jl + 1] - col_ptr[jl] : 0;
+            uint64_t heavy = __ballot(cnt > ADM_LIGHT);
+            while (heavy) {
+                const int j = jb + __builtin_ctzll(heavy);
+                heavy &= heavy - 1;
+                float y0[Q], y1[Q], y2[Q];
+                const float *yj = Y + (size_t)j * 3 * Q;
 #pragma unroll
-            for (int rnd = 0; rnd < 2; ++rnd) {
-                const int o = outo[rnd];
-                if (o < 3 * Q) {
-                    const float yn = outv[rnd];
-                    const float pv = pij[o];
-                    const float v = fmaxf(0.f, yn + pv * inv_beta);
-                    ypj[o] = v;
-                    pij[o] = pv + gb * (yn - v);
+                for (int k = 0; k < Q; ++k) {
+                    y0[k] = yj[k];
+                    y1[k] = yj[Q + k];
+                    y2[k] = yj[2 * Q + k];
                 }
-            }
-            __builtin_amdgcn_wave_barrier();
+                float a0[Q], a1[Q], a2[Q];
 #pragma unroll
-            for (int rnd = 0; rnd < 2; ++rnd)
-                if (outo[rnd] < 3 * Q) Y[(size_t)j * 3 * Q + outo[rnd]] = outv[rnd];
+                for (int k = 0; k < Q; ++k) a0[k] = a1[k] = a2[k] = 0.f;
+                const int beg = col_ptr[j], end = col_ptr[j + 1];
+                for (int p = beg + lane; p < end; p += WAVE) {
+                    const int i = csc_row[p];
+                    const float m0 = csc_val[3 * p] * inv_s0;
+                    const float m1 = csc_val[3 * p + 1] * inv_s0;
+                    const float m2 = csc_val[3 * p + 2] * inv_s0;
+                    const float *xo = X + (size_t)i * Q;
+                    const float *xp = Xn + (size_t)i * Q;
+                    float xa[Q], xb[Q];
+#pragma unroll
+                    for (int k = 0; k < Q; k += 4) {
+                        const float4 u = *(const float4 *)(xo + k);
+                        const float4 v = *(const float4 *)(xp + k);
+                        xa[k] = u.x; xa[k + 1] = u.y; xa[k + 2] = u.z; xa[k + 3] = u.w;
+                        xb[k] = v.x; xb[k + 1] = v.y; xb[k + 2] = v.z; xb[k + 3] = v.w;
+                    }
+                    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) {
+                        d0 = fmaf(xa[k], y0[k], d0);
+                        d1 = fmaf(xa[k], y1[k], d1);
+                        d2 = fmaf(xa[k], y2[k], d2);
+                    }
+                    const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) {
+                        a0[k] = fmaf(xb[k], r0, a0[k]);
+                        a1[k] = fmaf(xb[k], r1, a1[k]);
+                        a2[k] = fmaf(xb[k], r2, a2[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    a0[k] = wave_sum(a0[k]);
+                    a1[k] = wave_sum(a1[k]);
+                    a2[k] = wave_sum(a2[k]);
+                }
+                // Y+ for output o = (c, k): lanes o < 3Q (two rounds when 3Q > 64)
+                float *ypj = Yp + (size_t)j * 3 * Q;
+                float *pij = Pi + (size_t)j * 3 * Q;
+                float outv[2];
+                int outo[2];
+#pragma unroll
+                for (int rnd = 0; rnd < 2; ++rnd) {
+                    const int o = lane + rnd * WAVE;
+                    outo[rnd] = o;
+                    outv[rnd] = 0.f;
+                    if (o < 3 * Q) {
+                        const int c = o / Q, k = o % Q;
+                        double v = 0.0;
+#pragma unroll
+                        for (int l = 0; l < Q; ++l) {
+                            const float yl = c == 0 ? y0[l] : (c == 1 ? y1[l] : y2[l]);
+                            const float rl = c == 0 ? a0[l] : (c == 1 ? a1[l] : a2[l]);
+                            const float tl = rl + beta_f * ypj[c * Q + l] - pij[c * Q + l];
+                            v += sh.F[l * Q + k] * (double)yl + sh.Inv[l * Q + k] * (double)tl;
+                        }
+                        outv[rnd] = (float)v;
+                    }
+                }
+                // all reads of Yp/Pi/Y for this column are done by every lane
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int rnd = 0; rnd < 2; ++rnd) {
+                    const int o = outo[rnd];
+                    if (o < 3 * Q) {
+                        const float yn = outv[rnd];
+                        const float pv = pij[o];
+                        const float v = fmaxf(0.f, yn + pv * inv_beta);
+                        ypj[o] = v;
+                        pij[o] = pv + gb * (yn - v);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int rnd = 0; rnd < 2; ++rnd)
+                    if (outo[rnd] < 3 * Q) Y[(size_t)j * 3 * Q + outo[rnd]] = outv[rnd];
+            }
         }
         __threadfence_block();
         __syncthreads();
-        gram_rows<Q>(sh, Y, 3 * n, part);
+        gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * n, part, stage);
         float *tmp = X;
         X = Xn;
         Xn = tmp;
