@@ -16,12 +16,14 @@
 //     U_i = max(0, X+_i + L_i / a), L_i += g a (X+_i - U_i),
 //     and the Grams X+^T X+ and X+^T X are accumulated;
 //   stop test on ||R|| / ||P_Omega M|| (before any state is kept);
-//   phase B, one wavefront per column j (CSC): the residual again from
-//     (X_k, Y_k), RY_j = sum r X+_i, Y+_j = (GX + bI)^-1 ((X+^T X) Y_j + RY_j + b V_j - P_j),
-//     V_j = max(0, Y+_j + P_j / b), P_j += g b (Y+_j - V_j);
-//   GY = Y+ Y+^T for the next iteration.
+//   phase B, per column j (CSC): the residual again from (X_k, Y_k),
+//     RY_j = sum r X+_i, Y+_j = (GX + bI)^-1 ((X+^T X) Y_j + RY_j + b V_j - P_j),
+//     V_j = max(0, Y+_j + P_j / b), P_j += g b (Y+_j - V_j); a column of at
+//     most ADM_LIGHT samples by one lane, a longer one by a wavefront;
+//   GY = Y+ Y+^T for the next iteration, Y streamed through LDS tiles.
 // The q x q systems are factored by Cholesky in FP64 and inverted once per
-// iteration; rows and columns are then multiplied by the FP64 inverse.
+// iteration; phase A and the wavefront columns multiply by the FP64 inverse,
+// the lane columns by its FP32 rounding.
 // Every reduction has a fixed order: results are bitwise reproducible.
 
 #include <algorithm>
