@@ -172,3 +172,30 @@ def test_uneven_batch_against_oracle(batch):
         assert rel <= bound, f"slice {s} (m={rows.shape[0]}, q={sc.rank[s]}): {rel:.2e} > {bound:.2e}"
     outside = np.setdiff1d(np.arange(sc.m), sc.pt_ids)
     assert (run["radiance"][outside] == 0).all()
+
+
+LOWQ = dataclasses.replace(CONFIGS["batch"], width=160, height=140, n_spheres=256, n_vpls=8000,
+                           batch_slices=4, batch_m=(4700, 5200), batch_n=(256, 320), batch_q=(4, 8))
+
+
+def test_low_rank_tall_slices_in_global_memory():
+    """Ranks 4 and 8 on slices too tall for the LDS-resident kernel (m' q >
+    18,432) complete in the global-memory kernel: the oracle's ADM on the
+    GPU's samples against the GPU's radiance, 1e-3 pixel RMSE per slice."""
+    sc = make_scene(LOWQ, 23)
+    prm = api.default_params(seed=23, pass1_ppm=PPM, pass2_ppm=PPM, max_iter=40, fixed_iters=True)
+    run = run_frame(sc, prm, label="tall low-rank slices")
+    p = orender.Params(seed=23, pass1_ppm=PPM, pass2_ppm=PPM, max_iter=40, fixed_iters=True)
+    ranks = set()
+    for s in range(sc.n_slices):
+        info = run["info"][s]
+        m, n, q = info["m"], info["n"], info["q"]
+        assert not info["adm_in_lds"], f"slice {s} (m={m}, q={q}) is not a global-memory slice"
+        ranks.add(q)
+        check_csr_csc(run, s)
+        ii, jj, A = omega_of(run, s)
+        I, *_ = orender.complete_and_render(m, n, q, ii, jj, A.astype(np.float64), 23, s, p)
+        rel = orender.relative_rmse(run["radiance"][sc.slice_rows(s)], I)
+        log(f"tall slice {s} (m={m}, n={n}, q={q}, global): ADM on the GPU's samples {rel:.2e}")
+        assert rel <= 1e-3, f"slice {s}: {rel:.2e}"
+    assert ranks == {4, 8}, ranks
