@@ -61,6 +61,14 @@ struct AdmShared {
     double red[32];
 };
 
+// LDS written by some lanes of a wavefront and then read by others: the
+// wavefront's LDS operations complete, and the compiler keeps them in order
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // threadIdx.x behind an empty asm statement: what is derived from it is
 // recomputed where it is used, not hoisted out of the iteration loop or
 // shared between phases, where it would hold registers through every phase
@@ -197,6 +205,7 @@ __device__ void adm_global_slice(
     __shared__ __align__(16) float Ff[Q * Q];   // Y system, FP32: Ff[k][l] = F[k][l], If[k][l] = Inv[k][l]
     __shared__ __align__(16) float If[Q * Q];
     __shared__ __align__(16) float stage[GRAM_STAGE];
+    static_assert(NW * 33 * 3 * Q <= GRAM_STAGE, "heavy-column areas exceed the stage buffer");
 
     const SliceDesc d = desc[s];
     const int m = d.m, n = d.n;
@@ -535,6 +544,7 @@ __device__ void adm_global_slice(
         }
 
         // ---- phase B, heavy columns: wavefront per column ----
+        float *wst = stage + wave * (33 * 3 * Q);   // [32][3q] partial rows, then T_j (3q)
         for (int jb = wave * WAVE; jb < n; jb += NW * WAVE) {
             const int jl = jb + lane;
             const int cnt = jl < n ? col_ptr[jl + 1] - col_ptr[jl] : 0;
@@ -543,12 +553,13 @@ __device__ void adm_global_slice(
                 const int j = jb + __builtin_ctzll(heavy);
                 heavy &= heavy - 1;
                 float y0[Q], y1[Q], y2[Q];
-                const float *yj = Y + (size_t)j * 3 * Q;
+                const float4 *yj = reinterpret_cast<const float4 *>(Y + (size_t)j * 3 * Q);
 #pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    y0[k] = yj[k];
-                    y1[k] = yj[Q + k];
-                    y2[k] = yj[2 * Q + k];
+                for (int k = 0; k < Q; k += 4) {
+                    const float4 u = yj[k / 4], v = yj[(Q + k) / 4], w = yj[(2 * Q + k) / 4];
+                    y0[k] = u.x; y0[k + 1] = u.y; y0[k + 2] = u.z; y0[k + 3] = u.w;
+                    y1[k] = v.x; y1[k + 1] = v.y; y1[k + 2] = v.z; y1[k + 3] = v.w;
+                    y2[k] = w.x; y2[k + 1] = w.y; y2[k + 2] = w.z; y2[k + 3] = w.w;
                 }
                 float a0[Q], a1[Q], a2[Q];
 #pragma unroll
@@ -584,52 +595,62 @@ __device__ void adm_global_slice(
                         a2[k] = fmaf(xb[k], r2, a2[k]);
                     }
                 }
+                // X+^T R_j: lanes 32..63 folded onto 0..31, the 32 partial rows
+                // transposed through the wavefront's LDS area, lane o summing element o
 #pragma unroll
                 for (int k = 0; k < Q; ++k) {
-                    a0[k] = wave_sum(a0[k]);
-                    a1[k] = wave_sum(a1[k]);
-                    a2[k] = wave_sum(a2[k]);
+                    a0[k] += __shfl_xor(a0[k], 32, WAVE);
+                    a1[k] += __shfl_xor(a1[k], 32, WAVE);
+                    a2[k] += __shfl_xor(a2[k], 32, WAVE);
                 }
-                // Y+ for output o = (c, k): lanes o < 3Q (two rounds when 3Q > 64)
+                if (lane < 32) {
+                    float4 *row = reinterpret_cast<float4 *>(wst + lane * 3 * Q);
+#pragma unroll
+                    for (int k = 0; k < Q; k += 4) {
+                        row[k / 4] = make_float4(a0[k], a0[k + 1], a0[k + 2], a0[k + 3]);
+                        row[(Q + k) / 4] = make_float4(a1[k], a1[k + 1], a1[k + 2], a1[k + 3]);
+                        row[(2 * Q + k) / 4] = make_float4(a2[k], a2[k + 1], a2[k + 2], a2[k + 3]);
+                    }
+                }
+                wave_lds_sync();
+                // output o = (c, k), lanes o < 3q (two rounds when 3q > 64):
+                // T_o = (X+^T R_j)_o + b V_o - P_o, staged for the whole wavefront
                 float *ypj = Yp + (size_t)j * 3 * Q;
                 float *pij = Pi + (size_t)j * 3 * Q;
-                float outv[2];
-                int outo[2];
+                float pv[2];
 #pragma unroll
                 for (int rnd = 0; rnd < 2; ++rnd) {
                     const int o = lane + rnd * WAVE;
-                    outo[rnd] = o;
-                    outv[rnd] = 0.f;
+                    pv[rnd] = 0.f;
+                    if (o < 3 * Q) {
+                        float sum = 0.f;
+                        for (int r = 0; r < 32; ++r) sum += wst[r * 3 * Q + o];
+                        pv[rnd] = pij[o];
+                        wst[32 * 3 * Q + o] = sum + beta_f * ypj[o] - pv[rnd];
+                    }
+                }
+                wave_lds_sync();
+                const float *tj = wst + 32 * 3 * Q;
+#pragma unroll
+                for (int rnd = 0; rnd < 2; ++rnd) {
+                    const int o = lane + rnd * WAVE;
                     if (o < 3 * Q) {
                         const int c = o / Q, k = o % Q;
                         double v = 0.0;
 #pragma unroll
                         for (int l = 0; l < Q; ++l) {
                             const float yl = c == 0 ? y0[l] : (c == 1 ? y1[l] : y2[l]);
-                            const float rl = c == 0 ? a0[l] : (c == 1 ? a1[l] : a2[l]);
-                            const float tl = rl + beta_f * ypj[c * Q + l] - pij[c * Q + l];
-                            v += sh.F[l * Q + k] * (double)yl + sh.Inv[l * Q + k] * (double)tl;
+                            v += sh.F[l * Q + k] * (double)yl + sh.Inv[l * Q + k] * (double)tj[c * Q + l];
                         }
-                        outv[rnd] = (float)v;
+                        const float yn = (float)v;
+                        const float u = fmaxf(0.f, yn + pv[rnd] * inv_beta);
+                        ypj[o] = u;
+                        pij[o] = pv[rnd] + gb * (yn - u);
+                        Y[(size_t)j * 3 * Q + o] = yn;
                     }
                 }
-                // all reads of Yp/Pi/Y for this column are done by every lane
-                __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                for (int rnd = 0; rnd < 2; ++rnd) {
-                    const int o = outo[rnd];
-                    if (o < 3 * Q) {
-                        const float yn = outv[rnd];
-                        const float pv = pij[o];
-                        const float v = fmaxf(0.f, yn + pv * inv_beta);
-                        ypj[o] = v;
-                        pij[o] = pv + gb * (yn - v);
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                for (int rnd = 0; rnd < 2; ++rnd)
-                    if (outo[rnd] < 3 * Q) Y[(size_t)j * 3 * Q + outo[rnd]] = outv[rnd];
+                // the next column's partial rows overwrite this area
+                wave_lds_sync();
             }
         }
         __threadfence_block();
