@@ -309,14 +309,19 @@ __device__ void adm_global_slice(
         __syncthreads();
 
         // ---- phase A: rows ----
+        float *wsa = stage + wave * (33 * Q);   // [32][q] partial rows, then T_i (q)
         double e2 = 0.0;
         float gx[Q], cx[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) gx[k] = cx[k] = 0.f;
         for (int i = wave; i < m; i += NW) {
             float xi[Q];
+            const float4 *xr = reinterpret_cast<const float4 *>(X + (size_t)i * Q);
 #pragma unroll
-            for (int k = 0; k < Q; ++k) xi[k] = X[(size_t)i * Q + k];
+            for (int k = 0; k < Q; k += 4) {
+                const float4 u = xr[k / 4];
+                xi[k] = u.x; xi[k + 1] = u.y; xi[k + 2] = u.z; xi[k + 3] = u.w;
+            }
             float acc[Q];
 #pragma unroll
             for (int k = 0; k < Q; ++k) acc[k] = 0.f;
@@ -349,25 +354,41 @@ __device__ void adm_global_slice(
 #pragma unroll
                 for (int k = 0; k < Q; ++k) acc[k] = fmaf(r0, y0[k], fmaf(r1, y1[k], fmaf(r2, y2[k], acc[k])));
             }
+            // R_i Y^T: lanes 32..63 folded onto 0..31, the 32 partial rows
+            // transposed through the wavefront's LDS area, lane k summing element k
 #pragma unroll
-            for (int k = 0; k < Q; ++k) acc[k] = wave_sum(acc[k]);
-            // X+_i (lane k < Q owns column k), U and Lambda updates
+            for (int k = 0; k < Q; ++k) acc[k] += __shfl_xor(acc[k], 32, WAVE);
+            if (lane < 32) {
+                float4 *row = reinterpret_cast<float4 *>(wsa + lane * Q);
+#pragma unroll
+                for (int k = 0; k < Q; k += 4) row[k / 4] = make_float4(acc[k], acc[k + 1], acc[k + 2], acc[k + 3]);
+            }
+            wave_lds_sync();
+            // X+_i (lane k < Q owns column k): T_k = (R_i Y^T)_k + a U_ik - L_ik staged
+            // for the wavefront, then U and Lambda updates
+            float lam = 0.f;
+            if (lane < Q) {
+                float sum = 0.f;
+                for (int r = 0; r < 32; ++r) sum += wsa[r * Q + lane];
+                lam = Lam[(size_t)i * Q + lane];
+                wsa[32 * Q + lane] = sum + alpha_f * Xp[(size_t)i * Q + lane] - lam;
+            }
+            wave_lds_sync();
             float xn = 0.f;
             if (lane < Q) {
                 const int k = lane;
                 double v = 0.0;
 #pragma unroll
-                for (int l = 0; l < Q; ++l) {
-                    const float tl = acc[l] + alpha_f * Xp[(size_t)i * Q + l] - Lam[(size_t)i * Q + l];
-                    v += (double)xi[l] * sh.F[l * Q + k] + (double)tl * sh.Inv[l * Q + k];
-                }
+                for (int l = 0; l < Q; ++l)
+                    v += (double)xi[l] * sh.F[l * Q + k] + (double)wsa[32 * Q + l] * sh.Inv[l * Q + k];
                 xn = (float)v;
-                const float lam = Lam[(size_t)i * Q + k];
                 const float u = fmaxf(0.f, xn + lam * inv_alpha);
                 Xn[(size_t)i * Q + k] = xn;
                 Xp[(size_t)i * Q + k] = u;
                 Lam[(size_t)i * Q + k] = lam + ga * (xn - u);
             }
+            // the next row's partial rows overwrite this area
+            wave_lds_sync();
             // Grams: lane k accumulates GX[l][k] = sum x+_l x+_k and C[l][k] = sum x+_l x_k
             float xk = 0.f;
 #pragma unroll
