@@ -136,6 +136,15 @@ int vplmc_create(int device, void *stream, vplmc_ctx **out) {
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(stream);
     ctx->n_cu = prop.multiProcessorCount;
+    hipError_t he = hipEventCreateWithFlags(&ctx->adm.fork, hipEventDisableTiming);
+    for (int k = 0; k < 3 && he == hipSuccess; ++k) {
+        he = hipStreamCreateWithFlags(&ctx->adm.side[k], hipStreamNonBlocking);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&ctx->adm.join[k], hipEventDisableTiming);
+    }
+    if (he != hipSuccess) {
+        vplmc_destroy(ctx);
+        return hip_error(he, "completion streams");
+    }
     *out = ctx;
     return VPLMC_OK;
 }
@@ -146,6 +155,14 @@ int vplmc_destroy(vplmc_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->bvh_mem) (void)hipFree(ctx->bvh_mem);
     for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
+    for (int k = 0; k < 3; ++k) {
+        if (ctx->adm.side[k]) {
+            (void)hipStreamSynchronize(ctx->adm.side[k]);
+            (void)hipStreamDestroy(ctx->adm.side[k]);
+        }
+        if (ctx->adm.join[k]) (void)hipEventDestroy(ctx->adm.join[k]);
+    }
+    if (ctx->adm.fork) (void)hipEventDestroy(ctx->adm.fork);
     delete ctx;
     return VPLMC_OK;
 }
@@ -550,7 +567,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     float *Y = region<float>(ws, plan, VPLMC_R_Y);
     float *scale = region<float>(ws, plan, VPLMC_R_SLICE_SCALE);
     if ((rc = ph.mark(VPLMC_PH_ADM))) return rc;
-    if ((rc = launch_adm(st, *plan, ctx->n_cu, desc, ids, region<int32_t>(ws, plan, R_QUEUE), *params, row_ptr,
+    if ((rc = launch_adm(st, &ctx->adm, *plan, ctx->n_cu, desc, ids, region<int32_t>(ws, plan, R_QUEUE), *params, row_ptr,
                          csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X,
                          region<float>(ws, plan, R_XNEXT), region<float>(ws, plan, R_XP),
                          region<float>(ws, plan, R_LAMBDA), Y, region<float>(ws, plan, R_YP),

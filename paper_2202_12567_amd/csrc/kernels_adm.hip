@@ -1605,7 +1605,8 @@ int launch_adm_ell(hipStream_t st, int threads, size_t count, int max_m, const i
 
 }  // namespace
 
-int launch_adm(hipStream_t st, const vplmc_plan &plan, int n_cu, const SliceDesc *desc, const int32_t *ids_dev,
+int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int n_cu, const SliceDesc *desc,
+               const int32_t *ids_dev,
                int32_t *queues, const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col,
                const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
                const EllView &ell, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
@@ -1618,25 +1619,45 @@ int launch_adm(hipStream_t st, const vplmc_plan &plan, int n_cu, const SliceDesc
     const bool qm = plan.tune.adm_queue != 0;
     auto qp = [&](int g) { return qm ? queues + g : nullptr; };
     const int thr = plan.tune.adm_threads;
-    int rc;
-#define VPLMC_ADM_PAIR(B, Q, TG)                                                                                   \
-    if ((rc = launch_adm_ell<Q>(st, thr, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], qp(2 * B), \
-                                n_cu, desc, prm, col_ptr, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red,                      \
-                                e2part, scale, stats)))                                                            \
-        return rc;                                                                                                 \
-    if ((rc = launch_adm_global<Q, TG>(st, plan.groups[2 * B + 1].size(), id[2 * B + 1], qp(2 * B + 1), n_cu, desc, \
-                                       prm, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam,   \
-                                       Y, Yp, Pi, scale, stats)))                                                  \
-        return rc;
-    VPLMC_ADM_PAIR(0, 4, 1024)
-    VPLMC_ADM_PAIR(1, 8, 512)
+    // The rank buckets touch disjoint slices: with more than one bucket present,
+    // ranks 4, 8 and 16 run on streams forked from st while rank 32 (the
+    // longest slices) runs on st, so that one bucket's tail of large slices
+    // overlaps the others.  Every stream is joined back into st.
+    int buckets = 0;
+    for (int b = 0; b < 4; ++b) buckets += (plan.groups[2 * b].size() + plan.groups[2 * b + 1].size()) > 0;
+    const bool fork = ss != nullptr && buckets > 1;
+    hipStream_t sb[4] = {st, st, st, st};
+    if (fork) {
+        VPLMC_HIP(hipEventRecord(ss->fork, st));
+        for (int k = 0; k < 3; ++k) {
+            VPLMC_HIP(hipStreamWaitEvent(ss->side[k], ss->fork, 0));
+            sb[k] = ss->side[k];
+        }
+    }
+    int rc = launch_adm_global<32, 256>(sb[3], plan.groups[6].size() + plan.groups[7].size(), id[6], qp(6), n_cu,
+                                        desc, prm, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp,
+                                        Lam, Y, Yp, Pi, scale, stats);
+#define VPLMC_ADM_PAIR(B, Q, TG)                                                                                      \
+    if (!rc)                                                                                                          \
+        rc = launch_adm_ell<Q>(sb[B], thr, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], qp(2 * B), \
+                               n_cu, desc, prm, col_ptr, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale, stats); \
+    if (!rc)                                                                                                          \
+        rc = launch_adm_global<Q, TG>(sb[B], plan.groups[2 * B + 1].size(), id[2 * B + 1], qp(2 * B + 1), n_cu, desc, \
+                                      prm, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y,  \
+                                      Yp, Pi, scale, stats);
     VPLMC_ADM_PAIR(2, 16, 512)
-    if ((rc = launch_adm_global<32, 256>(st, plan.groups[6].size() + plan.groups[7].size(), id[6], qp(6), n_cu, desc,
-                                         prm, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y,
-                                         Yp, Pi, scale, stats)))
-        return rc;
+    VPLMC_ADM_PAIR(1, 8, 512)
+    VPLMC_ADM_PAIR(0, 4, 1024)
 #undef VPLMC_ADM_PAIR
-    return VPLMC_OK;
+    if (fork) {
+        // joined even after a failed launch, so that no stream is left forked
+        for (int k = 0; k < 3; ++k) {
+            hipError_t e = hipEventRecord(ss->join[k], ss->side[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, ss->join[k], 0);
+            if (e != hipSuccess && !rc) rc = hip_error(e, "joining the completion streams");
+        }
+    }
+    return rc;
 }
 
 int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,

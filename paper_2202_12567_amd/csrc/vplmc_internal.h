@@ -174,9 +174,19 @@ struct Layout {
 
 }  // namespace vplmc
 
+// Streams forked from the caller's stream for the completion's rank groups,
+// which touch disjoint slices and so may run side by side (default priority;
+// joined back by events, which stream capture records as graph edges).
+struct AdmStreams {
+    hipStream_t side[3] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[3] = {};
+};
+
 struct vplmc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    AdmStreams adm;
     vplmc::Bvh bvh;
     void *bvh_mem = nullptr;   // owned device allocation holding nodes + spheres
     int n_cu = 256;
@@ -265,7 +275,8 @@ int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, c
                 const uint32_t *omega1, const float *val1, const uint32_t *omega2, const float *val2,
                 const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, float *csc_val,
                 const EllView &ell);
-int launch_adm(hipStream_t st, const vplmc_plan &plan, int n_cu, const SliceDesc *desc, const int32_t *ids_dev,
+int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int n_cu, const SliceDesc *desc,
+               const int32_t *ids_dev,
                int32_t *queues, const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col,
                const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
                const EllView &ell, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
