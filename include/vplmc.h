@@ -22,8 +22,11 @@
  *  - The caller owns every buffer it passes (inputs, outputs, workspace).
  *    The library owns only what its create calls return (context, plan)
  *    and the occluder BVH it uploads in vplmc_set_occluders.
- *  - All device work is enqueued on the context's stream.  Only calls that
- *    fill HOST outputs synchronise that stream.
+ *  - All device work is ordered on the context's stream: the completion's
+ *    rank groups run on three streams of the context forked from it and
+ *    joined back into it by events, so work enqueued on the stream after a
+ *    call sees all of that call's results.  Only calls that fill HOST
+ *    outputs synchronise that stream.
  *  - Arguments are validated on the host before anything is launched.
  */
 #ifndef VPLMC_H
@@ -161,7 +164,9 @@ int vplmc_default_params(vplmc_params *out /* HOST */);
 
 /* ---- context: device + stream ---------------------------------------- */
 /* stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream), or
- * NULL for the null stream. */
+ * NULL for the null stream.  The context also creates three non-blocking
+ * streams of default priority and four events for the completion's rank
+ * groups; vplmc_destroy releases them. */
 int vplmc_create(int device, void *stream, vplmc_ctx **out /* HOST */);
 int vplmc_destroy(vplmc_ctx *ctx);
 int vplmc_set_stream(vplmc_ctx *ctx, void *stream);
