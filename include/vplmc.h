@@ -203,7 +203,12 @@ int vplmc_plan_region(const vplmc_plan *plan, int32_t region, size_t *offset /* 
  * pt_ids / cl_ids: DEVICE int32 arrays of the layout given to the plan.
  * workspace: DEVICE, at least vplmc_workspace_size bytes, 256-byte aligned.
  * radiance: DEVICE float[m][3]; points outside every slice are set to 0.
- * params must equal, in its rates, the params given to the plan. */
+ * params must equal, in its rates, the params given to the plan.
+ * Index arrays are not range-checked on the host (they live on the device):
+ * an out-of-range point, cluster or member id is clamped into range by the
+ * kernels, so it never reads or writes outside the caller's arrays, and the
+ * frame's result is then meaningless; vplmc_check_inputs finds such ids.
+ * The cut's offsets must be non-decreasing from 0 (also checked there). */
 int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points,
                  const vplmc_lights *vpls, const vplmc_cut *cut, const int32_t *pt_ids,
                  const int32_t *cl_ids, const vplmc_params *params, void *workspace,
@@ -213,6 +218,14 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
  * HOST arrays of n_slices each; any may be NULL. */
 int vplmc_read_stats(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace,
                      int32_t *iters, int32_t *flags, float *resid, int32_t *n2_accepted);
+
+/* Counts, on the device, the ids that break the contract of vplmc_render:
+ * pt_ids outside [0, n_points), cl_ids outside [0, n_clusters), cut offsets
+ * not non-decreasing from 0, and (when the offsets are ordered) members
+ * outside [0, n_vpls).  *n_bad (HOST) = 0 means every id is valid.
+ * Synchronises the context's stream; allocates a 16-byte counter. */
+int vplmc_check_inputs(vplmc_ctx *ctx, const vplmc_plan *plan, int32_t n_points, int32_t n_vpls,
+                       const vplmc_cut *cut, const int32_t *pt_ids, const int32_t *cl_ids, int64_t *n_bad);
 
 /* ---- phase timing ---------------------------------------------------------
  * Between begin and end, every vplmc_render on this context records HIP

@@ -170,6 +170,14 @@ def read_stats(ctx, plan, ws):
     return dict(iters=iters, flags=flags, resid=resid, n2=n2)
 
 
+def check_inputs(ctx, plan, ds):
+    """vplmc_check_inputs: number of out-of-range point, cluster and member ids."""
+    bad = ctypes.c_int64()
+    check(N.load().vplmc_check_inputs(ctx.h, plan.h, ds.m, ds.n_vpls, ctypes.byref(ds.cut_c), _ptr(ds.pt_ids),
+                                      _ptr(ds.cl_ids), ctypes.byref(bad)))
+    return int(bad.value)
+
+
 def cluster_table(ctx, ds, seed):
     nc = ds.n_clusters
     dev = ds.pt_ids.device

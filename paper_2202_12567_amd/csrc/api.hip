@@ -250,6 +250,10 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         const int64_t N1 = count_from_ppm(params->pass1_ppm, D);
         int64_t N2 = count_from_ppm(params->pass2_ppm, D);
         if (N2 > D - N1) N2 = D - N1;
+        if (N1 + N2 > INT32_MAX) {
+            delete plan;
+            return set_error(VPLMC_EINVAL, "slice %d: %lld samples exceed 2^31 - 1", s, (long long)(N1 + N2));
+        }
         SliceDesc &d = plan->desc[s];
         memset(&d, 0, sizeof(d));
         d.m = (int32_t)m;
@@ -575,7 +579,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
                          region<float>(ws, plan, R_ADM_RED), region<double>(ws, plan, R_E2PART), scale, stats)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_REDUCE))) return rc;
-    if ((rc = launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, radiance))) return rc;
+    if ((rc = launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, points->m, radiance))) return rc;
     if ((rc = ph.mark(VPLMC_N_PHASES))) return rc;
     ph.done();
     return VPLMC_OK;
@@ -807,6 +811,7 @@ int vplmc_eval_pairs(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lig
     if (!ctx || !points || !lights || !params) return set_error(VPLMC_EINVAL, "NULL argument");
     if (n_pairs < 0) return set_error(VPLMC_EINVAL, "n_pairs must be >= 0");
     if (n_pairs > 0 && (!point_ids || !light_ids || !out)) return set_error(VPLMC_EINVAL, "NULL pair arrays");
+    if (n_pairs > 0 && (points->m < 1 || lights->n < 1)) return set_error(VPLMC_EINVAL, "no points or no lights");
     if (bad_ptrs_points(points) || bad_ptrs_lights(lights)) return set_error(VPLMC_EINVAL, "incomplete arrays");
     int rc = check_params(params);
     if (rc) return rc;
@@ -819,6 +824,7 @@ int vplmc_brute_force(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_li
     if (!ctx || !points || !lights || !params) return set_error(VPLMC_EINVAL, "NULL argument");
     if (n_out < 0 || (n_out > 0 && !out)) return set_error(VPLMC_EINVAL, "invalid output");
     if (!point_ids && n_out > points->m) return set_error(VPLMC_EINVAL, "n_out exceeds the number of points");
+    if (n_out > 0 && (points->m < 1 || lights->n < 1)) return set_error(VPLMC_EINVAL, "no points or no lights");
     if (bad_ptrs_points(points) || bad_ptrs_lights(lights)) return set_error(VPLMC_EINVAL, "incomplete arrays");
     int rc = check_params(params);
     if (rc) return rc;
@@ -912,6 +918,48 @@ int vplmc_proposal_targets(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_p
     double *moments = region<double>(workspace, plan, R_COLSUM);
     return launch_targets(ctx->stream, *plan, desc, ctx->bvh, *points, lights, plan->n_clusters, pt_ids, cl_ids,
                           *params, moments, pstar);
+}
+
+int vplmc_check_inputs(vplmc_ctx *ctx, const vplmc_plan *plan, int32_t n_points, int32_t n_vpls,
+                       const vplmc_cut *cut, const int32_t *pt_ids, const int32_t *cl_ids, int64_t *n_bad) {
+    if (!ctx || !plan || !cut || !n_bad) return set_error(VPLMC_EINVAL, "ctx, plan, cut and n_bad must be non-NULL");
+    *n_bad = 0;
+    if (n_points < 0 || n_vpls < 0) return set_error(VPLMC_EINVAL, "n_points and n_vpls must be >= 0");
+    if (cut->n_clusters != plan->n_clusters) return set_error(VPLMC_EINVAL, "cut does not match the plan");
+    if (cut->n_clusters > 0 && (!cut->offsets || !cut->members)) return set_error(VPLMC_EINVAL, "invalid cut");
+    if (plan->n_slices > 0 && (!pt_ids || !cl_ids)) return set_error(VPLMC_EINVAL, "pt_ids and cl_ids must be non-NULL");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    unsigned long long *bad = nullptr;
+    if (hipMalloc(&bad, 2 * sizeof(unsigned long long)) != hipSuccess)
+        return set_error(VPLMC_ENOMEM, "counter allocation failed");
+    unsigned long long h[2] = {0, 0};
+    int32_t n_members = 0;
+    int rc = VPLMC_OK;
+    auto run = [&]() -> int {
+        VPLMC_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(unsigned long long), st));
+        int r;
+        if ((r = launch_count_out_of_range(st, pt_ids, plan->sum_m, n_points, bad))) return r;
+        if ((r = launch_count_out_of_range(st, cl_ids, plan->tot_col, plan->n_clusters, bad))) return r;
+        if (cut->n_clusters > 0) {
+            if ((r = launch_count_unordered(st, cut->offsets, cut->n_clusters, bad + 1))) return r;
+            VPLMC_HIP(hipMemcpyAsync(&n_members, cut->offsets + cut->n_clusters, 4, hipMemcpyDeviceToHost, st));
+        }
+        VPLMC_HIP(hipMemcpyAsync(h, bad, sizeof(h), hipMemcpyDeviceToHost, st));
+        VPLMC_HIP(hipStreamSynchronize(st));
+        // members are read only when the offsets are ordered (their count is then offsets[n_clusters])
+        if (h[1] == 0 && n_members > 0) {
+            if ((r = launch_count_out_of_range(st, cut->members, n_members, n_vpls, bad))) return r;
+            VPLMC_HIP(hipMemcpyAsync(h, bad, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+            VPLMC_HIP(hipStreamSynchronize(st));
+        }
+        return VPLMC_OK;
+    };
+    rc = run();
+    (void)hipFree(bad);
+    if (rc) return rc;
+    *n_bad = (int64_t)(h[0] + h[1]);
+    return VPLMC_OK;
 }
 
 int vplmc_philox4x64(vplmc_ctx *ctx, uint64_t key0, uint64_t key1, const uint64_t *ctr, int64_t n, uint64_t *out) {

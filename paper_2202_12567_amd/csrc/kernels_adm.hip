@@ -1209,7 +1209,7 @@ __device__ void adm_ell_slice(
             sh.F[e] = v;
         }
         __syncthreads();
-        // ---- X+ = X F + T Inv (FP64 MFMA), U, L, Grams X+^T X+ and X+^T X ----
+        // ---- X+ = X F + T Inv (FP32 MFMA on FP32 copies of the FP64 q x q factors), U, L, Grams X+^T X+ and X+^T X ----
         t = fresh_tid();
         lane = t % WAVE;
         {
@@ -1360,7 +1360,7 @@ __device__ void adm_ell_slice(
         }
         __threadfence_block();
         __syncthreads();
-        // ---- Y+ = Y F + T Inv (FP64 MFMA) over the 3n rows, V, P, Gram Y+^T Y+ ----
+        // ---- Y+ = Y F + T Inv (FP32 MFMA on FP32 copies of the FP64 q x q factors) over the 3n rows, V, P, Gram Y+^T Y+ ----
         t = fresh_tid();
         lane = t % WAVE;
         {
@@ -1494,7 +1494,7 @@ __global__ __launch_bounds__(256) void k_reduce(const SliceDesc *__restrict__ de
                                                  const int32_t *__restrict__ pt_ids,
                                                  const float *__restrict__ X_all,
                                                  const float *__restrict__ Y_all,
-                                                 const float *__restrict__ scale,
+                                                 const float *__restrict__ scale, int32_t n_points,
                                                  float *__restrict__ radiance) {
     __shared__ double w[3 * VPLMC_MAX_RANK];
     __shared__ double part[256 / 32 * 3 * VPLMC_MAX_RANK];
@@ -1528,7 +1528,7 @@ __global__ __launch_bounds__(256) void k_reduce(const SliceDesc *__restrict__ de
             gg += x * w[q + k];
             b += x * w[2 * q + k];
         }
-        const int pid = pt_ids[d.pt_off + i];
+        const int pid = clamp_index(pt_ids[d.pt_off + i], n_points);
         radiance[3 * (size_t)pid] = (float)(s0 * r);
         radiance[3 * (size_t)pid + 1] = (float)(s0 * gg);
         radiance[3 * (size_t)pid + 2] = (float)(s0 * b);
@@ -1661,9 +1661,10 @@ int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int
 }
 
 int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,
-                  const float *X, const float *Y, const float *scale, float *radiance) {
-    if (plan.n_slices == 0) return VPLMC_OK;
-    hipLaunchKernelGGL(k_reduce, dim3(plan.n_slices), dim3(256), 0, st, desc, pt_ids, X, Y, scale, radiance);
+                  const float *X, const float *Y, const float *scale, int32_t n_points, float *radiance) {
+    if (plan.n_slices == 0 || n_points < 1) return VPLMC_OK;
+    hipLaunchKernelGGL(k_reduce, dim3(plan.n_slices), dim3(256), 0, st, desc, pt_ids, X, Y, scale, n_points,
+                       radiance);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }

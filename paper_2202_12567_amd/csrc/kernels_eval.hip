@@ -101,6 +101,7 @@ struct PointData {
 };
 
 __device__ __forceinline__ PointData load_point(const vplmc_points &p, int i) {
+    i = clamp_index(i, p.m);
     PointData q;
     q.x = {p.px[i], p.py[i], p.pz[i]};
     q.n = {p.nx[i], p.ny[i], p.nz[i]};
@@ -174,7 +175,7 @@ __device__ __forceinline__ void eval_one(const Bvh &bvh, const BvhStaged &staged
     const uint32_t key = keys[g];
     const int i = (int)(key >> 16), j = (int)(key & 0xFFFFu);
     const int pid = pt_ids[d.pt_off + i];
-    const int c = cl_ids[d.cl_off + j];
+    const int c = clamp_index(cl_ids[d.cl_off + j], n_lights);
     const size_t N = (size_t)n_lights;
     const Light L = {{lights[c], lights[N + c], lights[2 * N + c]},
                      {lights[3 * N + c], lights[4 * N + c], lights[5 * N + c]},
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(256) void k_eval_pairs(Bvh bvh, vplmc_points pts, v
                                                     float *__restrict__ out) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= n) return;
-    const int c = lid[g];
+    const int c = clamp_index(lid[g], l.n);
     const Light L = {{l.x[c], l.y[c], l.z[c]}, {l.nx[c], l.ny[c], l.nz[c]}, l.ir[c], l.ig[c], l.ib[c]};
     const PointData q = load_point(pts, pid[g]);
     float o0, o1, o2;
@@ -297,7 +298,7 @@ __global__ void k_zero_f64(double *p, size_t n) {
 // Training targets of the learned proposal from fully evaluated slices: per
 // (slice, column) the mean and mean square of t = R + G + B over every row
 // (one thread per column, FP64 sums in row order), then per slice
-// p*_j ~ sigma_j + 0.01 mean(sigma).
+// p*_j ~ sigma_j + PROPOSAL_TARGET_MIX mean(sigma) (mix 3).
 __global__ __launch_bounds__(256) void k_target_moments(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
                                                         int32_t n_lights, const SliceDesc *__restrict__ desc, int S,
                                                         int64_t total_cols, const int32_t *__restrict__ pt_ids,
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(256) void k_target_moments(Bvh bvh, vplmc_points pt
     const int s = lo;
     const SliceDesc d = desc[s];
     const int64_t j = g - (d.off_colptr - s);
-    const int c = cl_ids[d.cl_off + j];
+    const int c = clamp_index(cl_ids[d.cl_off + j], n_lights);
     const size_t N = (size_t)n_lights;
     const Light L = {{lights[c], lights[N + c], lights[2 * N + c]},
                      {lights[3 * N + c], lights[4 * N + c], lights[5 * N + c]},

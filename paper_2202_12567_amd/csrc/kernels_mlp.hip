@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_features(const SliceDesc *__restrict__ 
     double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int i = t; i < d.m; i += 256) {
-        const int p = pt_ids[d.pt_off + i];
+        const int p = clamp_index(pt_ids[d.pt_off + i], pts.m);
         const float x = pts.px[p], y = pts.py[p], z = pts.pz[p];
         a[0] += x; a[1] += y; a[2] += z;
         a[3] += pts.nx[p]; a[4] += pts.ny[p]; a[5] += pts.nz[p];
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_features(const SliceDesc *__restrict__ 
     }
     for (int j = t; j < d.n; j += 256) {
         a[6] += sum[d.off_col + j];
-        const int c = cl_ids[d.cl_off + j];
+        const int c = clamp_index(cl_ids[d.cl_off + j], nc);
         a[7] += (double)((lights[6 * N + c] + lights[7 * N + c]) + lights[8 * N + c]);
     }
     for (int k = 0; k < 8; ++k) red[k][t] = a[k];
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_features(const SliceDesc *__restrict__ 
     const float per = (float)d.N1 / (float)d.n;
     for (int j = t; j < d.n; j += 256) {
         const int64_t o = d.off_col + j;
-        const int c = cl_ids[d.cl_off + j];
+        const int c = clamp_index(cl_ids[d.cl_off + j], nc);
         const float k = (float)cnt[o];
         const float safe = k > 0.f ? k : 1.f;
         const double mean = sum[o] / (double)safe;

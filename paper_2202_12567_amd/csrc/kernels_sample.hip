@@ -78,6 +78,23 @@ __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
         p[i] = v;
 }
 
+// number of ids outside [0, hi)
+__global__ void k_count_out_of_range(const int32_t *__restrict__ ids, int64_t n, int32_t hi,
+                                     unsigned long long *bad) {
+    unsigned long long c = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += (ids[i] < 0 || ids[i] >= hi) ? 1ull : 0ull;
+    if (c) atomicAdd(bad, c);
+}
+
+// number of offsets that break 0 = offsets[0] <= offsets[1] <= ... <= offsets[n]
+__global__ void k_count_unordered(const int32_t *__restrict__ offsets, int64_t n, unsigned long long *bad) {
+    unsigned long long c = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x)
+        c += (i == 0 ? offsets[0] != 0 : offsets[i] < offsets[i - 1]) ? 1ull : 0ull;
+    if (c) atomicAdd(bad, c);
+}
+
 __global__ void k_philox(uint64_t k0, uint64_t k1, const uint64_t *ctr, int64_t n, uint64_t *out) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -98,13 +115,13 @@ __global__ void k_cluster_table(vplmc_lights v, vplmc_cut cut, uint64_t seed, in
     const int b = cut.offsets[c], e = cut.offsets[c + 1];
     double smax = 0.0;
     for (int k = b; k < e; ++k) {
-        const int id = cut.members[k];
+        const int id = clamp_index(cut.members[k], v.n);
         const double sk = ((double)v.ir[id] + (double)v.ig[id]) + (double)v.ib[id];
         smax = sk > smax ? sk : smax;
     }
     uint64_t total = 0;
     for (int k = b; k < e; ++k) {
-        const int id = cut.members[k];
+        const int id = clamp_index(cut.members[k], v.n);
         const double sk = ((double)v.ir[id] + (double)v.ig[id]) + (double)v.ib[id];
         uint64_t w = 1;
         if (smax > 0.0) {
@@ -113,12 +130,12 @@ __global__ void k_cluster_table(vplmc_lights v, vplmc_cut cut, uint64_t seed, in
         }
         total += w;
     }
-    int rep = e > b ? cut.members[b] : -1;
+    int rep = e > b ? clamp_index(cut.members[b], v.n) : -1;
     if (e > b) {
         const uint64_t u = mulhi64(philox(seed, 0, (uint64_t)c, 0, TAG_REP, 0).a, total);
         uint64_t acc = 0;
         for (int k = b; k < e; ++k) {
-            const int id = cut.members[k];
+            const int id = clamp_index(cut.members[k], v.n);
             const double sk = ((double)v.ir[id] + (double)v.ig[id]) + (double)v.ib[id];
             uint64_t w = 1;
             if (smax > 0.0) {
@@ -135,7 +152,7 @@ __global__ void k_cluster_table(vplmc_lights v, vplmc_cut cut, uint64_t seed, in
     double sr = 0.0, sg = 0.0, sb = 0.0;
     float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
     for (int k = b; k < e; ++k) {
-        const int id = cut.members[k];
+        const int id = clamp_index(cut.members[k], v.n);
         sr += (double)v.ir[id];
         sg += (double)v.ig[id];
         sb += (double)v.ib[id];
@@ -279,13 +296,17 @@ __global__ __launch_bounds__(256) void k_weights(const SliceDesc *__restrict__ d
             }
             w[d.off_col + j] = wj;
         }
-        // inclusive uint64 prefix: weights are <= 2^24, a 256-chunk sum fits in 32 bits
+        // inclusive uint64 prefix.  Weights are <= 2^24, so an exclusive sum of
+        // at most 255 of them fits in 32 bits, but a whole chunk of 256 may
+        // reach 2^32 exactly: the chunk total is carried in 64 bits as the last
+        // lane's inclusive prefix, not as the 32-bit block total.
         uint32_t tot;
         const uint32_t ex = block_excl_scan(wj, &tot, sm);
         const uint64_t carry = carry_s;
-        if (j < d.n) prefix[d.off_col + j] = carry + (uint64_t)ex + wj;
+        const uint64_t incl = carry + (uint64_t)ex + wj;
+        if (j < d.n) prefix[d.off_col + j] = incl;
         __syncthreads();
-        if (t == 0) carry_s = carry + tot;
+        if (t == 255) carry_s = incl;
         __syncthreads();
     }
 }
@@ -631,6 +652,21 @@ int launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v) {
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_count_out_of_range(hipStream_t st, const int32_t *ids, int64_t n, int32_t hi, unsigned long long *bad) {
+    if (n <= 0) return VPLMC_OK;
+    const unsigned blocks = (unsigned)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_count_out_of_range, dim3(blocks), dim3(256), 0, st, ids, n, hi, bad);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_count_unordered(hipStream_t st, const int32_t *offsets, int64_t n, unsigned long long *bad) {
+    const unsigned blocks = (unsigned)std::min<int64_t>(4096, (n + 256) / 256);
+    hipLaunchKernelGGL(k_count_unordered, dim3(blocks), dim3(256), 0, st, offsets, n, bad);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }

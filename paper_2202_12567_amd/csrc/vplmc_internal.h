@@ -64,6 +64,10 @@ __device__ __forceinline__ U64x4 philox(uint64_t k0, uint64_t k1, uint64_t c0, u
     return U64x4{c0, c1, c2, c3};
 }
 
+// An index read from a caller's array, clamped into [0, n): out-of-range ids
+// never reach memory (vplmc_check_inputs reports them).
+__device__ __forceinline__ int clamp_index(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
 // floor(r * n / 2^64): a uniform 64-bit word mapped onto [0, n).
 __device__ __forceinline__ uint64_t mulhi64(uint64_t r, uint64_t n) { return __umul64hi(r, n); }
 
@@ -237,6 +241,8 @@ inline bool adm_fits_lds(int q, int m) {
 int launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v);
 int launch_cluster_table(hipStream_t st, const vplmc_lights &v, const vplmc_cut &cut, uint64_t seed,
                          int32_t *rep, float *lights, float *bbox);
+int launch_count_out_of_range(hipStream_t st, const int32_t *ids, int64_t n, int32_t hi, unsigned long long *bad);
+int launch_count_unordered(hipStream_t st, const int32_t *offsets, int64_t n, unsigned long long *bad);
 int launch_philox(hipStream_t st, uint64_t k0, uint64_t k1, const uint64_t *ctr, int64_t n,
                   uint64_t *out);
 int launch_pass1(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, uint64_t seed,
@@ -282,7 +288,7 @@ int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int
                const EllView &ell, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
                float *Yt, float *red, double *e2part, float *scale, int32_t *stats);
 int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,
-                  const float *X, const float *Y, const float *scale, float *radiance);
+                  const float *X, const float *Y, const float *scale, int32_t n_points, float *radiance);
 int launch_eval_pairs(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,
                       int64_t n, const int32_t *pid, const int32_t *lid, const vplmc_params &prm, float *out);
 int launch_brute_force(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,

@@ -91,7 +91,7 @@ def check_csr_csc(run, s):
     assert np.array_equal(run["r"]["CSC_VAL"][3 * o: 3 * (o + nnz)].reshape(-1, 3), v[order])
 
 
-def within_entry_tol(g, o, amb=None):
+def entries_out_of_tol(g, o, amb=None):
     """|g - o| <= 1e-4 |o| + 1e-7 max|o| per entry and channel (unflagged entries)."""
     g = np.asarray(g, np.float64)
     o = np.asarray(o, np.float64)

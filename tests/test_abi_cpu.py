@@ -116,9 +116,11 @@ def test_public_region_sizes_follow_their_definitions():
     (([0, 64], [0, 64], [33]), N.EINVAL, "rank"),
     (([0, 64], [0, 64], [12]), N.EUNSUPPORTED, "rank"),
     (([1, 64], [0, 64], [4]), N.EINVAL, "must be 0"),
+    (([0, 65535], [0, 65535], [4], 8, dict(pass1_ppm=500000, pass2_ppm=500000)), N.EINVAL, "2^31"),
 ])
 def test_plan_rejects_bad_shapes(args, code, needle):
-    rc, _ = plan(*args)
+    kw = args[4] if len(args) > 4 else {}
+    rc, _ = plan(*args[:4], **kw)
     assert rc == code
     assert needle in N.load().vplmc_last_error().decode()
 

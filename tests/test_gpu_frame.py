@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-from _gpu_common import check_scene_indices, keys_to_ij, log, within_entry_tol  # noqa: E402
+from _gpu_common import check_scene_indices, keys_to_ij, log, entries_out_of_tol  # noqa: E402
 from oracle import render as orender  # noqa: E402
 from oracle.sampling import pass1, pass2, weights_from_g  # noqa: E402
 from paper_2202_12567_amd import api  # noqa: E402
@@ -115,7 +115,7 @@ def test_frame_sampled_slices_stage_parity(frame):
         log(f"frame slice {s}: entries")
         sel = np.random.default_rng(s).choice(i1.shape[0], min(2000, i1.shape[0]), replace=False)
         o, amb, _ = orender.eval_entries(sc, lights, sc.slice_rows(s)[gi[sel]], sc.slice_cols(s)[gj[sel]], p)
-        assert not within_entry_tol(v1[sel], o, amb).any()
+        assert not entries_out_of_tol(v1[sel], o, amb).any()
         log(f"frame slice {s}: weights and pass 2")
         a = info[s]["off_col"]
         gmin = region(frame, "COLMIN", torch.float32, a, n)

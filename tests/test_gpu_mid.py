@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-from _gpu_common import check_csr_csc, keys_to_ij, log, omega_of, run_frame, within_entry_tol  # noqa: E402
+from _gpu_common import check_csr_csc, keys_to_ij, log, omega_of, run_frame, entries_out_of_tol  # noqa: E402
 from oracle import render as orender  # noqa: E402
 from oracle.sampling import pass1, pass2, weights_from_g  # noqa: E402
 from paper_2202_12567_amd import api  # noqa: E402
@@ -80,7 +80,7 @@ def test_sampled_slices_stage_parity(mid):
         sel = np.random.default_rng(s).choice(i1.shape[0], 20000, replace=False)
         o, amb, _ = orender.eval_entries(sc, lights, sc.slice_rows(s)[gi[sel]], sc.slice_cols(s)[gj[sel]], p)
         g = view(run, "VAL1", s, 3).reshape(-1, 3)[sel]
-        assert not within_entry_tol(g, o, amb).any()
+        assert not entries_out_of_tol(g, o, amb).any()
         log(f"mid slice {s}: weights and pass 2")
         gmin, gmax, cnt = view(run, "COLMIN", s), view(run, "COLMAX", s), view(run, "COLCNT", s)
         g32 = np.where(cnt > 0, (gmax - gmin).astype(np.float32), np.float32(0))

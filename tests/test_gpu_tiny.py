@@ -8,7 +8,7 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-from _gpu_common import keys_to_ij, log, omega_of, run_frame, within_entry_tol  # noqa: E402
+from _gpu_common import keys_to_ij, log, omega_of, run_frame, entries_out_of_tol  # noqa: E402
 from oracle import adm as oadm  # noqa: E402
 from oracle import render as orender  # noqa: E402
 from oracle.cluster import cluster_table  # noqa: E402
@@ -127,7 +127,7 @@ def test_first_pass_entries(run, scene, lights):
         gi, gj = keys_to_ij(slice_view(run, "OMEGA1", s))
         o, amb, _ = orender.eval_entries(scene, lights, scene.slice_rows(s)[gi], scene.slice_cols(s)[gj], p)
         g = slice_view(run, "VAL1", s, 3).reshape(-1, 3)
-        bad = within_entry_tol(g, o, amb)
+        bad = entries_out_of_tol(g, o, amb)
         total_amb += int(amb.sum())
         assert not bad.any(), f"slice {s}: {int(bad.any(axis=1).sum())} entries out of tolerance"
     log(f"first-pass ambiguous-visibility entries excluded: {total_amb}")
@@ -264,7 +264,7 @@ def test_eval_pairs_random(run, scene, lights):
     nrm = np.stack([V["nx"], V["ny"], V["nz"]], 1)[lid]
     inten = np.stack([V["ir"], V["ig"], V["ib"]], 1)[lid]
     o, amb, lit = entries(x, nn, kd, ks, pe, wo, pos, nrm, inten, scene.spheres)
-    assert not within_entry_tol(out, o, amb).any()
+    assert not entries_out_of_tol(out, o, amb).any()
     assert lit.sum() > 1000 and (o[lit].sum(1) == 0).sum() > 100      # shadows present
 
 
