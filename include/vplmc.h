@@ -336,7 +336,9 @@ int vplmc_mlp_grad(vplmc_ctx *ctx, const float *params, int64_t rows, const floa
 int vplmc_mlp_adam(vplmc_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t step, float lr);
 /* Forward, loss sum over groups of KL(pstar || softmax(y)) (groups = rows
  * [group_offsets[g], group_offsets[g+1]), DEVICE int32), backward and Adam.
- * loss: DEVICE float, overwritten. */
+ * loss: DEVICE float, overwritten.  After the call the scratch begins with
+ * this step's gradient (float[param_count]), then its logits y (float[rows])
+ * and dloss/dy = softmax(y) - pstar (float[rows]), for inspection. */
 int vplmc_mlp_train_step(vplmc_ctx *ctx, float *params, float *m, float *v, int32_t step, float lr, int64_t rows,
                          const float *features, const float *pstar, int32_t n_groups, const int32_t *group_offsets,
                          void *scratch, size_t scratch_bytes, float *loss);

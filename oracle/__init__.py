@@ -15,6 +15,9 @@ in its own order and notation and cites the passage it implements:
 * ``shading``   -- lighting-matrix entries A(i, j) (Sec. 3) with shadow-ray
                    visibility, brute force over every sphere.
 * ``cluster``   -- cluster representative and intensity (Sec. 4, I_f = I_a + I_b).
+* ``coarsen``   -- per-slice light coarsening over the tree above the global
+                   cut (Sec. 4: eps, the recursive cost, merge order) and the
+                   first pass its pixel draws give (Sec. 5).
 * ``sampling``  -- first uniform pass, importance g(j) = max C_j - min C_j and
                    the second pass (Sec. 5, Eq. pdf).
 * ``adm``       -- non-negative completion by ADM (Appendix A).

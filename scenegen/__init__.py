@@ -107,6 +107,10 @@ class Scene:
     cl_offsets: np.ndarray
     cl_ids: np.ndarray
     rank: np.ndarray
+    # the light tree above the cut (left/right children of the n_c - 1 split
+    # nodes, ids as in tree_above_cut); None where the slices have their own cuts
+    tree_left: np.ndarray = None
+    tree_right: np.ndarray = None
 
     @property
     def m(self):
@@ -228,6 +232,7 @@ def light_tree_cut_sequence(pos, rgb, max_clusters):
     heap = [(-w_of(nodes[0]), 0)]
     cut = {0}
     history = []
+    children = {}
     while len(cut) < max_clusters and heap:
         negw, nid = heapq.heappop(heap)
         members = nodes[nid]
@@ -240,14 +245,33 @@ def light_tree_cut_sequence(pos, rgb, max_clusters):
         left = np.sort(members[order[:half]])
         right = np.sort(members[order[half:]])
         cut.discard(nid)
+        kids = []
         for ch in (left, right):
             nodes.append(ch)
             cid = len(nodes) - 1
             cut.add(cid)
+            kids.append(cid)
             heapq.heappush(heap, (-w_of(ch), cid))
+        children[nid] = tuple(kids)
         history.append(sorted(cut))
     del weight
+    light_tree_cut_sequence.children = children
     return nodes, history, sorted(cut)
+
+
+def tree_above_cut(children, cut_node_order):
+    """The light tree's nodes above a cut as a binary tree over the cut's
+    clusters: cluster k (cut-table order) is node k; the n_c - 1 split nodes
+    are nodes n_c .. 2 n_c - 2, children before parents (the root last).
+    Returns (left, right) int32 arrays of the split nodes' children."""
+    nc = len(cut_node_order)
+    ids = {nid: k for k, nid in enumerate(cut_node_order)}
+    split = sorted(children, reverse=True)        # created later -> deeper -> first
+    for k, nid in enumerate(split):
+        ids[nid] = nc + k
+    left = np.array([ids[children[nid][0]] for nid in split], dtype=np.int32)
+    right = np.array([ids[children[nid][1]] for nid in split], dtype=np.int32)
+    return left, right
 
 
 def _cut_table(nodes, node_ids):
@@ -350,13 +374,13 @@ def make_scene(cfg, seed, n_vpls=None, n_clusters=None):
     diag = float(np.linalg.norm(pts_pos.max(axis=0) - pts_pos.min(axis=0)))
     feat = np.concatenate([pts_pos / diag, 0.5 * pts_nrm], axis=1)
 
+    tree_left = tree_right = None
     if cfg.slice_mode in ("equal", "uneven"):
-        if n_clusters >= n_vpls:
-            cut_offsets = np.arange(n_vpls + 1, dtype=np.int32)
-            cut_members = np.arange(n_vpls, dtype=np.int32)
-        else:
-            nodes, _, final = light_tree_cut_sequence(vpos, vrgb64, n_clusters)
-            cut_offsets, cut_members, _ = _cut_table(nodes, final)
+        # a cut of every VPL is the tree grown down to single lights
+        nodes, _, final = light_tree_cut_sequence(vpos, vrgb64, min(n_clusters, n_vpls))
+        children = light_tree_cut_sequence.children
+        cut_offsets, cut_members, order = _cut_table(nodes, final)
+        tree_left, tree_right = tree_above_cut(children, order)
         ids = np.arange(m, dtype=np.int64)
         if cfg.slice_mode == "equal":
             leaves = _bisect_slices(feat, ids, "equal", n_leaves=cfg.n_slices)
@@ -414,7 +438,7 @@ def make_scene(cfg, seed, n_vpls=None, n_clusters=None):
                  cut_members=np.asarray(cut_members, dtype=np.int32),
                  pt_offsets=pt_offsets.astype(np.int32), pt_ids=pt_ids.astype(np.int32),
                  cl_offsets=cl_offsets.astype(np.int32), cl_ids=cl_ids.astype(np.int32),
-                 rank=np.asarray(rank, dtype=np.int32))
+                 rank=np.asarray(rank, dtype=np.int32), tree_left=tree_left, tree_right=tree_right)
 
 
 def scene_sample(scene: Scene, slices):

@@ -194,3 +194,119 @@ def test_trained_network_gain_on_held_out_scenes():
     assert kl_learned < kl_plain
     # same seeds, same sample budget; the whole frame is deterministic
     assert gains["learned"] < gains["plain"]
+
+
+def _full_slice_matrix(scene, s, seed):
+    """Every entry of slice s by the oracle (FP64) and its visibility flags."""
+    L = orender.cluster_lights(scene, seed)
+    rows, cols = scene.slice_rows(s), scene.slice_cols(s)
+    rr = np.repeat(rows, cols.shape[0])
+    cc = np.tile(cols, rows.shape[0])
+    A, amb, _ = orender.eval_entries(scene, L, rr, cc, orender.Params(seed=seed))
+    return A.sum(axis=1).reshape(rows.shape[0], cols.shape[0]), amb.reshape(rows.shape[0], cols.shape[0])
+
+
+def test_proposal_targets_match_oracle(scene):
+    """vplmc_proposal_targets (GPU entries of every (point, cluster) pair of a
+    slice, FP64 column moments, p* ~ sigma + 3 mean sigma) against
+    oracle.mlp.targets on the oracle's FP64 full slice matrices: 1e-4 relative
+    per column, columns holding a visibility-ambiguous entry left out."""
+    prm = api.default_params(seed=SEED)
+    ctx = api.Context(0)
+    ctx.set_occluders(scene.spheres)
+    dev = torch.device("cuda", 0)
+    ds = api.DeviceScene(scene, dev)
+    plan = api.Plan(scene, prm)
+    ws = api.workspace(plan, dev)
+    _, lights, _ = api.cluster_table(ctx, ds, SEED)
+    log("proposal targets on the learned scene")
+    pstar = api.proposal_targets(ctx, plan, ds, lights, prm, ws).cpu().numpy().astype(np.float64)
+    for s in (0, 7):
+        info = plan.slice_info(s)
+        a, b = info["off_col"], info["off_col"] + info["n"]
+        tfull, amb = _full_slice_matrix(scene, s, SEED)
+        po = omlp.targets(tfull, info["n"])
+        ok = ~amb.any(axis=0)
+        rel = np.abs(pstar[a:b] - po) / po
+        log(f"slice {s}: targets max relative error {rel[ok].max():.2e} over {ok.sum()} columns "
+            f"({(~ok).sum()} with ambiguous entries left out)")
+        assert ok.sum() > 0.9 * info["n"]
+        assert rel[ok].max() <= 1e-4
+        assert abs(pstar[a:b].sum() - 1.0) < 1e-4
+
+
+def test_train_step_loss_and_dy_match_oracle(feat_run):
+    """vplmc_mlp_train_step: the loss sum over slices of KL(p* || softmax y) and
+    dloss/dy against oracle.mlp.softmax_kl evaluated on the step's own logits
+    (1e-5), and the step's logits against the oracle's forward (1e-2)."""
+    ctx = feat_run["ctx"]
+    Fn = feat_run["r"]["FEATURES"].reshape(-1, 12)[:4096].astype(np.float32)
+    rng = np.random.default_rng(5)
+    groups = [np.arange(a, a + 1024) for a in range(0, 4096, 1024)]
+    ps = rng.uniform(0.0, 1.0, 4096)
+    ps[rng.uniform(0, 1, 4096) < 0.1] = 0.0          # zero targets are skipped in the loss
+    for g in groups:
+        ps[g] /= ps[g].sum()
+    pv = random_params(13)
+    dev = torch.device("cuda", 0)
+    tp = torch.as_tensor(pv).to(dev)
+    tm = torch.zeros_like(tp)
+    tv = torch.zeros_like(tp)
+    offs = torch.as_tensor(np.array([0, 1024, 2048, 3072, 4096], np.int32)).to(dev)
+    scratch = api.mlp_scratch(4096, dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    api.mlp_train_step(ctx, tp, tm, tv, 1, 1e-3, torch.as_tensor(Fn).to(dev),
+                       torch.as_tensor(ps.astype(np.float32)).to(dev), offs, scratch, loss)
+    torch.cuda.synchronize()
+    sc = scratch.view(torch.float32).cpu().numpy()
+    P = api.mlp_param_count()
+    y = sc[P:P + 4096].astype(np.float64)
+    dy = sc[P + 4096:P + 8192].astype(np.float64)
+    lo, dyo = omlp.softmax_kl(y, ps.astype(np.float32).astype(np.float64), groups)
+    log(f"train step: loss {loss.item():.6f} (oracle {lo:.6f}), dy max error {np.abs(dy - dyo).max():.2e}")
+    assert abs(loss.item() - lo) <= 1e-5 * max(1.0, abs(lo))
+    assert np.abs(dy - dyo).max() <= 1e-5
+    yo, _ = omlp.forward(omlp.unflatten(pv), Fn, rounding=True)
+    assert np.abs(y - yo).max() <= 1e-2 * np.abs(yo).max()
+
+
+def test_forward_rounding_points_exact_on_gpu(feat_run):
+    """The one-unit networks of tests/golden/mlp_bf16_rounding_cases.txt through
+    the BF16 MFMA forward: every output is the hand-worked rounded value
+    exactly (each rounding point dropped alone would move it by > 5%)."""
+    import test_oracle_mlp as tom
+    for r in tom._golden_rows("mlp_bf16_rounding_cases.txt"):
+        vals = [float(v) for v in r[1:]]
+        p, F = tom._one_unit_net(*vals[:7])
+        y = api.mlp_forward(feat_run["ctx"], torch.as_tensor(omlp.flatten(p)).cuda(),
+                            torch.as_tensor(np.repeat(F, 64, axis=0)).cuda()).cpu().numpy()
+        assert np.all(y == np.float32(vals[7])), (r[0], y[:4])
+
+
+def test_non_finite_logit_falls_back_with_plain_samples(scene):
+    """A model with a NaN weight gives NaN logits on every column: every slice
+    is flagged VPLMC_SLICE_FALLBACK and its weights and second pass are the
+    plain method's, bit for bit."""
+    pv = random_params(5)
+    pv[3] = np.nan                                     # a weight of the first layer
+    prm_l = api.default_params(seed=SEED, max_iter=3, fixed_iters=True, learned=True)
+    prm_p = api.default_params(seed=SEED, max_iter=3, fixed_iters=True)
+    dev = torch.device("cuda", 0)
+    ctx = api.Context(0)
+    api.set_proposal(ctx, torch.as_tensor(pv).to(dev))
+    ctx.set_occluders(scene.spheres)
+    ds = api.DeviceScene(scene, dev)
+    plan = api.Plan(scene, prm_l)
+    ws = api.workspace(plan, dev)
+    log("learned frame with a NaN weight")
+    rad = api.render(ctx, plan, ds, prm_l, ws).cpu().numpy()
+    st = api.read_stats(ctx, plan, ws)
+    lg = api.region_view(plan, ws, "LOGITS", torch.float32).cpu().numpy()
+    w = api.region_view(plan, ws, "WEIGHTS", torch.int32).cpu().numpy()
+    om2 = api.region_view(plan, ws, "OMEGA2", torch.int32).cpu().numpy()
+    rp = run_frame(scene, prm_p, label="plain")
+    assert (st["flags"] & 8).all()
+    assert not np.isfinite(lg).any()
+    assert np.array_equal(w, rp["r"]["WEIGHTS"])
+    assert np.array_equal(om2, rp["r"]["OMEGA2"])
+    assert np.array_equal(rad.astype(np.float64), rp["radiance"])

@@ -274,5 +274,63 @@ def test_brute_force_matches_oracle(run, scene):
     ds = run["ds"]
     g = api.brute_force(run["ctx"], ds, ds.vpl, gpu_params(), point_ids=torch.as_tensor(pid).cuda()).cpu().numpy()
     o = orender.brute_force(scene, oracle_params(), point_ids=pid)
+    # pixels one of whose 1,024 entries has a visibility within 1e-5 of flipping
+    # may differ by a whole entry; every other pixel holds to 1e-4
+    from oracle.shading import entries, point_arrays
+    V = scene.vpls
+    pr = np.repeat(pid, scene.n)
+    lj = np.tile(np.arange(scene.n), pid.shape[0])
+    x, nn, kd, ks, pe, wo = point_arrays(scene.points, pr)
+    pos = np.stack([V["x"], V["y"], V["z"]], 1)[lj]
+    nrm = np.stack([V["nx"], V["ny"], V["nz"]], 1)[lj]
+    inten = np.stack([V["ir"], V["ig"], V["ib"]], 1)[lj]
+    _, amb, _ = entries(x, nn, kd, ks, pe, wo, pos, nrm, inten, scene.spheres)
+    clear = ~amb.reshape(pid.shape[0], scene.n).any(axis=1)
     rel = np.abs(g - o) / np.maximum(np.abs(o), 1e-12)
-    assert np.median(rel) < 1e-5 and np.mean(rel > 1e-4) < 0.02
+    log(f"brute force: {clear.sum()} of {pid.shape[0]} pixels without an ambiguous entry, "
+        f"max relative error there {rel[clear].max():.2e}")
+    assert clear.sum() >= 80
+    assert rel[clear].max() <= 1e-4
+
+
+def test_full_sampling_takes_the_rest_in_row_major_order(scene):
+    """100% sampling (5% uniform + 95%): the second pass is every entry the
+    first pass left, in row-major order, bit for bit; the completion of the
+    fully observed slices matches the oracle's (30 fixed iterations)."""
+    prm = gpu_params(pass1_ppm=50000, pass2_ppm=950000, max_iter=30)
+    r = run_frame(scene, prm, label="tiny at 100%")
+    for s in range(scene.n_slices):
+        info = r["info"][s]
+        m, n = info["m"], info["n"]
+        assert info["N1"] + info["N2"] == m * n
+        assert int(r["stats"]["n2"][s]) == info["N2"] and not (r["stats"]["flags"][s] & 4)
+        i1, j1 = pass1(SEED, s, m, n, 50000)
+        taken = np.zeros(m * n, bool)
+        taken[i1 * n + j1] = True
+        i2, j2, short = pass2(SEED, s, m, n, i1.shape[0], 950000, np.ones(n, np.uint64), taken)
+        gi, gj = keys_to_ij(slice_view(r, "OMEGA2", s))
+        assert not short and np.array_equal(gi, i2) and np.array_equal(gj, j2), f"slice {s}"
+    slices = [0, 9]
+    I, _ = orender.render(scene, oracle_params(pass1_ppm=50000, pass2_ppm=950000, max_iter=30), slices=slices)
+    for s in slices:
+        pid = scene.slice_rows(s)
+        rel = orender.relative_rmse(r["radiance"][pid], I[pid])
+        log(f"100% sampling, slice {s}: pixel RMSE vs oracle {rel:.2e}")
+        assert rel <= 1e-3
+
+
+def test_all_zero_slice_is_flagged_and_black(scene):
+    """Every VPL turned to face up (away from every surface point below it):
+    every entry is 0, so every slice is flagged VPLMC_SLICE_ALL_ZERO and its
+    radiance is exactly 0 (the completion is skipped, Appendix A has nothing
+    to fit)."""
+    import dataclasses
+    v = dict(scene.vpls)
+    v["nx"] = np.zeros_like(v["nx"])
+    v["ny"] = np.zeros_like(v["ny"])
+    v["nz"] = np.ones_like(v["nz"])
+    sc = dataclasses.replace(scene, vpls=v)
+    r = run_frame(sc, gpu_params(max_iter=10), label="all-zero")
+    assert (r["stats"]["flags"] & 1).all()
+    assert not np.any(r["radiance"])
+    assert not np.any(r["r"]["VAL1"]) and not np.any(r["r"]["VAL2"])

@@ -90,3 +90,53 @@ def test_targets_follow_column_std():
     # sigma = (0, 1, 0), mean sigma = 1/3, mix 3 mean sigma = 1: weights (1, 2, 1)
     expect = np.array([1.0, 2.0, 1.0])
     np.testing.assert_allclose(p, expect / expect.sum(), rtol=1e-14)
+
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def _golden_rows(name):
+    rows = []
+    for ln in open(__import__("os").path.join(GOLDEN, name)):
+        ln = ln.strip()
+        if ln and not ln.startswith("#"):
+            rows.append(ln.split())
+    return rows
+
+
+def test_features_of_a_hand_worked_slice():
+    """tests/golden/features_toy.txt: every feature of two columns, derived by
+    hand from the definitions (count normalisation, cosine signs, logs)."""
+    stats = dict(count=np.array([2, 1]), sum=np.array([6.0, 0.0]), sumsq=np.array([20.0, 0.0]),
+                 min=np.array([2.0, 0.0]), max=np.array([4.0, 0.0]), zeros=np.array([0.0, 1.0]))
+    geo = dict(centroid=np.array([1.0, 0.0, 0.0]), diag=2.0, mean_normal=np.array([0.0, 0.0, 1.0]))
+    clusters = dict(pos=np.array([[1.0, 0.0, 3.0], [1.0, 4.0, 0.0]]),
+                    nrm=np.array([[0.0, 0.0, -1.0], [0.0, -1.0, 0.0]]),
+                    intensity=np.array([6.0, 2.0]), bbox_diag=np.array([0.5, 0.0]), members=np.array([4, 1]))
+    F = mlp.features(stats, geo, clusters, np.array([0, 1]), 3)
+    want = np.array([[float(v) for v in r[1:]] for r in _golden_rows("features_toy.txt")])
+    assert want.shape == (2, 12)
+    # the +1e-6 / +1e-12 guards of the definitions move the values by < 1e-6
+    np.testing.assert_allclose(F, want, rtol=0, atol=2e-6)
+
+
+def _one_unit_net(F0, W1, b1, W2, b2, W3, b3):
+    p = {k: np.zeros(v.shape, np.float32) for k, v in mlp.init_params(0).items()}
+    p["W1"][0, 0], p["b1"][0], p["W2"][0, 0], p["b2"][0], p["W3"][0, 0], p["b3"][0] = W1, b1, W2, b2, W3, b3
+    F = np.zeros((1, mlp.N_IN), np.float32)
+    F[0, 0] = F0
+    return p, F
+
+
+def test_every_bf16_rounding_point_of_the_forward_pass():
+    """tests/golden/mlp_bf16_rounding_cases.txt: for each rounding point (W1,
+    W2, W3, h1, h2) a network whose output moves by more than 5% of |y| if that point
+    alone were dropped; the oracle must give the hand-worked rounded value."""
+    rows = _golden_rows("mlp_bf16_rounding_cases.txt")
+    assert {r[0] for r in rows} == {"W1", "W2", "W3", "h1", "h2"}
+    for r in rows:
+        vals = [float(v) for v in r[1:]]
+        p, F = _one_unit_net(*vals[:7])
+        y, _ = mlp.forward(p, F, rounding=True)
+        assert y[0] == vals[7], (r[0], y[0])
+        assert abs(vals[7] - vals[8]) > 0.05 * abs(vals[7]), r[0]
