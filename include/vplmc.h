@@ -214,6 +214,23 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
                  const int32_t *cl_ids, const vplmc_params *params, void *workspace,
                  size_t workspace_bytes, float *radiance);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * frame as vplmc_render, with the workspace replaced by a static device array
+ * of VPLMC_STATIC_WORKSPACE_BYTES that the library holds on every GPU it runs
+ * on until the process ends.  Calls no allocating routine.  Returns
+ * VPLMC_EINVAL if the plan's workspace (vplmc_workspace_size) exceeds that
+ * size; small frames only (the tiny 64 x 64 configuration needs 46 MiB).
+ * All calls on one GPU share the array, which keeps the last frame's
+ * contents (every buffer a frame reads is cleared or written by that frame
+ * first): calls that overlap on one GPU, from any context or stream, race
+ * and must be ordered by the caller.  The per-slice stats of such a frame
+ * are not readable (vplmc_read_stats needs the workspace pointer). */
+#define VPLMC_STATIC_WORKSPACE_BYTES (64u << 20)
+int vplmc_render_static(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points,
+                        const vplmc_lights *vpls, const vplmc_cut *cut, const int32_t *pt_ids,
+                        const int32_t *cl_ids, const vplmc_params *params, float *radiance);
+
 /* Per-slice outcome of the last vplmc_render on this workspace (synchronises).
  * HOST arrays of n_slices each; any may be NULL. */
 int vplmc_read_stats(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace,

@@ -70,6 +70,8 @@ SIG = {
     "vplmc_plan_region": (I32, [P, I32, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "vplmc_render": (I32, [P, P, ctypes.POINTER(Points), ctypes.POINTER(Lights), ctypes.POINTER(Cut), P, P,
                            ctypes.POINTER(Params), P, ctypes.c_size_t, P]),
+    "vplmc_render_static": (I32, [P, P, ctypes.POINTER(Points), ctypes.POINTER(Lights), ctypes.POINTER(Cut), P, P,
+                                  ctypes.POINTER(Params), P]),
     "vplmc_read_stats": (I32, [P, P, P, P, P, P, P]),
     "vplmc_check_inputs": (I32, [P, P, I32, I32, ctypes.POINTER(Cut), P, P, ctypes.POINTER(I64)]),
     "vplmc_cluster_table": (I32, [P, ctypes.POINTER(Lights), ctypes.POINTER(Cut), U64, P, P, P]),

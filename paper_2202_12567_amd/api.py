@@ -159,6 +159,17 @@ def render(ctx, plan, ds, params, ws, radiance=None):
     return radiance
 
 
+def render_static(ctx, plan, ds, params, radiance=None):
+    """One frame on the library's static device workspace (vplmc_render_static):
+    no allocation inside the call; returns radiance float32 [m, 3]."""
+    if radiance is None:
+        radiance = torch.empty((ds.m, 3), dtype=torch.float32, device=ds.pt_ids.device)
+    check(N.load().vplmc_render_static(ctx.h, plan.h, ctypes.byref(ds.points_c), ctypes.byref(ds.vpls_c),
+                                       ctypes.byref(ds.cut_c), _ptr(ds.pt_ids), _ptr(ds.cl_ids),
+                                       ctypes.byref(params), _ptr(radiance)))
+    return radiance
+
+
 def read_stats(ctx, plan, ws):
     S = plan.n_slices
     iters = np.zeros(S, np.int32)

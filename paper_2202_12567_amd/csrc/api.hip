@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "vplmc_internal.h"
@@ -27,6 +28,32 @@ int hip_error(hipError_t e, const char *what) {
 }
 
 namespace {
+
+// Workspace of vplmc_render_static: a file-scope device array, so the call
+// needs no allocation.  Every GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the array's name as an
+// address (on the host it is only a stand-in for the device symbol): the
+// device address comes from hipGetSymbolAddress, once per device, below.
+__device__ __align__(256) unsigned char scratch[VPLMC_STATIC_WORKSPACE_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device` (the current device): looked up on
+// the first call for that device and kept.
+int scratch_address(int device, void **out) {
+    if (device < 0 || device >= MAX_DEVICES) return set_error(VPLMC_EUNSUPPORTED, "device %d >= %d", device, MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_error(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return VPLMC_OK;
+}
 
 int64_t count_from_ppm(int64_t ppm, int64_t D) { return (ppm * D + 500000) / 1000000; }
 
@@ -136,6 +163,10 @@ int vplmc_create(int device, void *stream, vplmc_ctx **out) {
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(stream);
     ctx->n_cu = prop.multiProcessorCount;
+    if (int rc = scratch_address(device, &ctx->scratch)) {
+        delete ctx;
+        return rc;
+    }
     hipError_t he = hipEventCreateWithFlags(&ctx->adm.fork, hipEventDisableTiming);
     for (int k = 0; k < 3 && he == hipSuccess; ++k) {
         he = hipStreamCreateWithFlags(&ctx->adm.side[k], hipStreamNonBlocking);
@@ -583,6 +614,22 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if ((rc = ph.mark(VPLMC_N_PHASES))) return rc;
     ph.done();
     return VPLMC_OK;
+}
+
+int vplmc_render_static(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points,
+                        const vplmc_lights *vpls, const vplmc_cut *cut, const int32_t *pt_ids, const int32_t *cl_ids,
+                        const vplmc_params *params, float *radiance) {
+    if (!ctx || !plan) return set_error(VPLMC_EINVAL, "ctx and plan must be non-NULL");
+    if (plan->layout.total > VPLMC_STATIC_WORKSPACE_BYTES)
+        return set_error(VPLMC_EINVAL, "frame needs a %zu-byte workspace, above the %zu-byte static workspace "
+                         "(use vplmc_render with a caller workspace)", plan->layout.total,
+                         (size_t)VPLMC_STATIC_WORKSPACE_BYTES);
+    if (!ctx->scratch) return set_error(VPLMC_EHIP, "static workspace address unknown");
+    // the same frame as vplmc_render, on the device array: every buffer the
+    // frame reads before writing is cleared by its fill kernels, so the
+    // previous call's contents do not matter
+    return vplmc_render(ctx, plan, points, vpls, cut, pt_ids, cl_ids, params, ctx->scratch,
+                        (size_t)VPLMC_STATIC_WORKSPACE_BYTES, radiance);
 }
 
 static int check_tune(const vplmc_tune *t) {

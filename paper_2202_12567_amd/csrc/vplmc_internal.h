@@ -201,6 +201,7 @@ struct vplmc_ctx {
     int prof_frames = 0;
     bool prof_on = false;
     bool capturing = false;                     // a frame is being recorded into a graph
+    void *scratch = nullptr;                    // device address of the static workspace on this device
 };
 
 struct vplmc_plan {
