@@ -51,6 +51,7 @@ extern "C" {
 #define VPLMC_MAX_ROWS 65535
 #define VPLMC_MAX_COLS 65535
 #define VPLMC_MAX_RANK 32
+#define VPLMC_MAX_LEAVES 32768  /* leaves of a coarsening tree (node ids and heights fit in 16 bits) */
 
 /* vplmc_params.flags */
 #define VPLMC_FIXED_ITERS 1     /* ignore tol: run exactly max_iter ADM iterations */
@@ -152,6 +153,12 @@ enum {
     VPLMC_R_SLICE_SCALE,  /* float per slice: s0, the mean sampled value M is divided by   */
     VPLMC_R_FEATURES,     /* float[12] per (slice, column): proposal features (learned mode) */
     VPLMC_R_LOGITS,       /* float per (slice, column): proposal log-density (learned mode) */
+    /* plans with light coarsening only (0 bytes otherwise); LIGHTS, REP and
+     * BBOX then hold the 2 n_leaves - 1 nodes of the tree (leaves first) */
+    VPLMC_R_COLUMNS,      /* int32 per (slice, column): tree node of the column             */
+    VPLMC_R_NODE_EPS,     /* float per (slice, split node): merge error eps (Sec. 4)        */
+    VPLMC_R_LEAF_DRAWS,   /* int32 per leaf: row draws per slice before the cap at m'       */
+    VPLMC_R_NODE_MEMBERS, /* int32 per node: VPLs below it                                  */
     VPLMC_R_COUNT
 };
 
@@ -187,6 +194,45 @@ int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float 
 int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t *cl_offsets,
                       const int32_t *rank, int32_t n_clusters, const vplmc_params *params,
                       vplmc_plan **out /* HOST */);
+
+/* Per-slice light coarsening (Sec. 4).  The global cut's clusters are the
+ * leaves of a binary tree, the light tree above the cut: split node
+ * n_leaves + k has children left[k] and right[k], each a leaf or an earlier
+ * split node, and every node but the root (node 2 n_leaves - 2) is the child
+ * of exactly one split node.  A split node keeps the position and normal of
+ * one child a, drawn with probability proportional to the children's
+ * quantised intensities (Philox, seed), and the summed intensity.  For each
+ * slice, `pixels` row draws are shared out over the leaves in proportion to
+ * their intensity (each leaf's rows distinct, from its own keyed
+ * permutation of the slice's rows, at most m' per leaf); the error of
+ * merging split node f is eps(f) = max over the rows drawn below f and the
+ * channels of |V_b - V_a I_b / I_a|, its cost eps(f) + cost(dropped child)
+ * (leaves cost 0).  Sibling pairs are merged from the least cost on until
+ * the slice has n_max[s] columns, and further while the cost stays below
+ * `bound`, never below the slice's rank q; the remaining nodes, ordered by
+ * their smallest leaf, are the slice's columns.  The first pass of the
+ * coarsened slice is the set of (row, column) entries the draws hit (Sec. 5);
+ * the second pass, completion and sum follow as in vplmc_render. */
+typedef struct {
+    int32_t n_leaves;        /* clusters of the global cut, [1, VPLMC_MAX_LEAVES]                */
+    int32_t pixels;          /* row draws per slice, [0, 2^30]                                    */
+    const int32_t *left;     /* HOST, n_leaves - 1                                                */
+    const int32_t *right;    /* HOST, n_leaves - 1                                                */
+    const int32_t *n_max;    /* HOST, n_slices: column cap of each slice (>= 1)                   */
+    double bound;            /* merge further while the least cost is below it (>= 0; 0: caps only) */
+    int32_t reserved;        /* 0 */
+} vplmc_coarsen;
+/* A frame plan whose slices coarsen the cut (HOST arrays as in
+ * vplmc_plan_create; no column layout: slice s gets at most
+ * n'_s = min(n_leaves, max(rank[s], n_max[s])) columns, exactly that many
+ * when bound = 0).  vplmc_plan_slice then reports n', N1 (at most pixels)
+ * and N2 as capacities; a frame's own counts are read with
+ * vplmc_read_counts.  params.pass1_ppm is not used by such a plan.  Its
+ * frames take the global cut (n_leaves clusters) as `cut` and ignore
+ * `cl_ids` (which may be NULL). */
+int vplmc_plan_create_coarse(int32_t n_slices, const int32_t *pt_offsets, const int32_t *rank,
+                             const vplmc_coarsen *coarsen, const vplmc_params *params,
+                             vplmc_plan **out /* HOST */);
 int vplmc_plan_destroy(vplmc_plan *plan);
 int vplmc_workspace_size(const vplmc_plan *plan, size_t *bytes /* HOST */);
 int vplmc_plan_slice(const vplmc_plan *plan, int32_t s, vplmc_slice_info *out /* HOST */);
@@ -236,6 +282,13 @@ int vplmc_render_static(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_poin
 int vplmc_read_stats(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace,
                      int32_t *iters, int32_t *flags, float *resid, int32_t *n2_accepted);
 
+/* Per-slice column count n', first-pass count N1 and second-pass target N2
+ * of the last frame rendered on this workspace (synchronises).  HOST arrays
+ * of n_slices each; any may be NULL.  Without coarsening these equal the
+ * plan's values. */
+int vplmc_read_counts(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace, int32_t *n,
+                      int32_t *N1, int32_t *N2);
+
 /* Counts, on the device, the ids that break the contract of vplmc_render:
  * pt_ids outside [0, n_points), cl_ids outside [0, n_clusters), cut offsets
  * not non-decreasing from 0, and (when the offsets are ordered) members
@@ -250,10 +303,11 @@ int vplmc_check_inputs(vplmc_ctx *ctx, const vplmc_plan *plan, int32_t n_points,
  * frames are not recorded).  end synchronises the stream and returns the
  * summed milliseconds per phase (HOST double[VPLMC_N_PHASES]) and the
  * number of frames recorded. */
-#define VPLMC_N_PHASES 10
+#define VPLMC_N_PHASES 11
 enum {
     VPLMC_PH_SETUP = 0,   /* descriptor upload and buffer clears     */
-    VPLMC_PH_CLUSTER,     /* cluster table                           */
+    VPLMC_PH_CLUSTER,     /* cluster table (and tree node table)     */
+    VPLMC_PH_COARSEN,     /* light coarsening: merge errors, columns */
     VPLMC_PH_PASS1,       /* first-pass sampling                     */
     VPLMC_PH_EVAL1,       /* entries of the first pass               */
     VPLMC_PH_WEIGHTS,     /* column statistics and importance        */

@@ -31,6 +31,12 @@ class Params(ctypes.Structure):
                 ("r_min", ctypes.c_float), ("ray_eps", ctypes.c_float)]
 
 
+class Coarsen(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_int32), ("pixels", ctypes.c_int32), ("left", ctypes.c_void_p),
+                ("right", ctypes.c_void_p), ("n_max", ctypes.c_void_p), ("bound", ctypes.c_double),
+                ("reserved", ctypes.c_int32)]
+
+
 class Tune(ctypes.Structure):
     _fields_ = [("adm_queue", ctypes.c_int32), ("adm_threads", ctypes.c_int32), ("eval_threads", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -48,7 +54,7 @@ FIXED_ITERS, LEARNED, FEATURES = 1, 2, 4
 SLICE_ALL_ZERO, SLICE_NOT_CONVERGED, SLICE_SHORTFALL, SLICE_FALLBACK = 1, 2, 4, 8
 REGIONS = ["LIGHTS", "REP", "BBOX", "OMEGA1", "VAL1", "OMEGA2", "VAL2", "WEIGHTS", "COLMIN", "COLMAX",
            "COLCNT", "ROW_PTR", "CSR_COL", "CSR_VAL", "COL_PTR", "CSC_ROW", "CSC_VAL", "X", "Y", "SLICE_SCALE",
-           "FEATURES", "LOGITS"]
+           "FEATURES", "LOGITS", "COLUMNS", "NODE_EPS", "LEAF_DRAWS", "NODE_MEMBERS"]
 R = {name: k for k, name in enumerate(REGIONS)}
 
 P = ctypes.c_void_p
@@ -64,6 +70,8 @@ SIG = {
     "vplmc_set_stream": (I32, [P, P]),
     "vplmc_set_occluders": (I32, [P, I32, P, P, P, P]),
     "vplmc_plan_create": (I32, [I32, P, P, P, I32, ctypes.POINTER(Params), ctypes.POINTER(P)]),
+    "vplmc_plan_create_coarse": (I32, [I32, P, P, ctypes.POINTER(Coarsen), ctypes.POINTER(Params),
+                                       ctypes.POINTER(P)]),
     "vplmc_plan_destroy": (I32, [P]),
     "vplmc_workspace_size": (I32, [P, ctypes.POINTER(ctypes.c_size_t)]),
     "vplmc_plan_slice": (I32, [P, I32, ctypes.POINTER(SliceInfo)]),
@@ -73,6 +81,7 @@ SIG = {
     "vplmc_render_static": (I32, [P, P, ctypes.POINTER(Points), ctypes.POINTER(Lights), ctypes.POINTER(Cut), P, P,
                                   ctypes.POINTER(Params), P]),
     "vplmc_read_stats": (I32, [P, P, P, P, P, P, P]),
+    "vplmc_read_counts": (I32, [P, P, P, P, P, P]),
     "vplmc_check_inputs": (I32, [P, P, I32, I32, ctypes.POINTER(Cut), P, P, ctypes.POINTER(I64)]),
     "vplmc_cluster_table": (I32, [P, ctypes.POINTER(Lights), ctypes.POINTER(Cut), U64, P, P, P]),
     "vplmc_eval_pairs": (I32, [P, ctypes.POINTER(Points), ctypes.POINTER(Lights), I64, P, P,
@@ -98,8 +107,8 @@ SIG = {
     "vplmc_graph_launch": (I32, [P, P]),
     "vplmc_graph_destroy": (I32, [P]),
 }
-N_PHASES = 10
-PHASES = ["setup", "cluster", "pass1", "eval1", "weights", "pass2", "eval2", "sort", "adm", "reduce"]
+N_PHASES = 11
+PHASES = ["setup", "cluster", "coarsen", "pass1", "eval1", "weights", "pass2", "eval2", "sort", "adm", "reduce"]
 
 _lib = None
 

@@ -99,20 +99,40 @@ def lights_struct(d):
     return N.Lights(n, *[_ptr(d[k]) for k in DeviceScene.LIGHT_KEYS])
 
 
-class Plan:
-    """Frame plan (vplmc_plan_create): host-only layout of every slice."""
+class Coarsening:
+    """Light coarsening of every slice (Sec. 4): `pixels` row draws per slice,
+    column cap n_max (int or one per slice), merge bound."""
 
-    def __init__(self, scene, params):
+    def __init__(self, pixels, n_max, bound=0.0):
+        self.pixels = int(pixels)
+        self.n_max = n_max
+        self.bound = float(bound)
+
+
+class Plan:
+    """Frame plan (vplmc_plan_create, or vplmc_plan_create_coarse with a
+    Coarsening and the scene's tree above the cut): host-only layout of every slice."""
+
+    def __init__(self, scene, params, coarsen=None):
         lib = N.load()
         self.n_slices = scene.n_slices
         self.n_clusters = scene.n_clusters
+        self.coarse = coarsen is not None
         pt = np.ascontiguousarray(scene.pt_offsets, dtype=np.int32)
-        cl = np.ascontiguousarray(scene.cl_offsets, dtype=np.int32)
         rk = np.ascontiguousarray(scene.rank, dtype=np.int32)
         h = ctypes.c_void_p()
         f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-        check(lib.vplmc_plan_create(self.n_slices, f(pt), f(cl), f(rk), self.n_clusters, ctypes.byref(params),
-                                    ctypes.byref(h)))
+        if coarsen is None:
+            cl = np.ascontiguousarray(scene.cl_offsets, dtype=np.int32)
+            check(lib.vplmc_plan_create(self.n_slices, f(pt), f(cl), f(rk), self.n_clusters, ctypes.byref(params),
+                                        ctypes.byref(h)))
+        else:
+            left = np.ascontiguousarray(scene.tree_left, dtype=np.int32)
+            right = np.ascontiguousarray(scene.tree_right, dtype=np.int32)
+            nmax = np.ascontiguousarray(np.broadcast_to(np.asarray(coarsen.n_max), (self.n_slices,)), dtype=np.int32)
+            c = N.Coarsen(self.n_clusters, coarsen.pixels, f(left), f(right), f(nmax), coarsen.bound, 0)
+            check(lib.vplmc_plan_create_coarse(self.n_slices, f(pt), f(rk), ctypes.byref(c), ctypes.byref(params),
+                                               ctypes.byref(h)))
         self.h = h
         sz = ctypes.c_size_t()
         check(lib.vplmc_workspace_size(h, ctypes.byref(sz)))
@@ -179,6 +199,15 @@ def read_stats(ctx, plan, ws):
     f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     check(N.load().vplmc_read_stats(ctx.h, plan.h, _ptr(ws), f(iters), f(flags), f(resid), f(n2)))
     return dict(iters=iters, flags=flags, resid=resid, n2=n2)
+
+
+def read_counts(ctx, plan, ws):
+    """Per-slice n', N1, N2 of the last frame on this workspace (vplmc_read_counts)."""
+    S = plan.n_slices
+    n, n1, n2 = (np.zeros(S, np.int32) for _ in range(3))
+    f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    check(N.load().vplmc_read_counts(ctx.h, plan.h, _ptr(ws), f(n), f(n1), f(n2)))
+    return dict(n=n, N1=n1, N2=n2)
 
 
 def check_inputs(ctx, plan, ds):

@@ -237,31 +237,104 @@ int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float 
     return VPLMC_OK;
 }
 
-int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t *cl_offsets, const int32_t *rank,
-                      int32_t n_clusters, const vplmc_params *params, vplmc_plan **out) {
+// Topology of the tree above the cut (integer bookkeeping, no method
+// arithmetic): validates that every node but the root is the child of
+// exactly one later split node, and lays out left, right, parent, height,
+// smallest leaf, the split nodes ordered by (height, id) and the level offsets.
+static int build_tree(const vplmc_coarsen *co, std::vector<int32_t> &tree, int32_t &height_max) {
+    const int ng = co->n_leaves, ns = ng - 1, NC = 2 * ng - 1;
+    if (ns > 0 && (!co->left || !co->right)) return set_error(VPLMC_EINVAL, "tree arrays must be non-NULL");
+    std::vector<int32_t> parent(NC, -1), height(NC, 0), min_leaf(NC);
+    for (int x = 0; x < NC; ++x) min_leaf[x] = x;
+    for (int k = 0; k < ns; ++k) {
+        const int f = ng + k, l = co->left[k], r = co->right[k];
+        if (l < 0 || r < 0 || l >= f || r >= f || l == r)
+            return set_error(VPLMC_EINVAL, "tree: split node %d has children %d, %d (must be distinct and earlier)", f, l, r);
+        if (parent[l] >= 0 || parent[r] >= 0)
+            return set_error(VPLMC_EINVAL, "tree: node %d or %d already has a parent", l, r);
+        parent[l] = parent[r] = f;
+        height[f] = 1 + std::max(height[l], height[r]);
+        min_leaf[f] = std::min(min_leaf[l], min_leaf[r]);
+    }
+    for (int x = 0; x < NC - 1; ++x)
+        if (parent[x] < 0) return set_error(VPLMC_EINVAL, "tree: node %d has no parent (one root expected)", x);
+    height_max = ns > 0 ? height[NC - 1] : 0;
+    std::vector<int32_t> level_off(height_max + 1, 0), order(ns);
+    for (int k = 0; k < ns; ++k) level_off[height[ng + k]]++;
+    for (int h = 1; h <= height_max; ++h) level_off[h] += level_off[h - 1];
+    std::vector<int32_t> fill(level_off.begin(), level_off.end());
+    for (int k = 0; k < ns; ++k) order[fill[height[ng + k] - 1]++] = ng + k;
+    tree.clear();
+    tree.insert(tree.end(), co->left, co->left + ns);
+    tree.insert(tree.end(), co->right, co->right + ns);
+    tree.insert(tree.end(), parent.begin(), parent.end());
+    tree.insert(tree.end(), height.begin(), height.end());
+    tree.insert(tree.end(), min_leaf.begin(), min_leaf.end());
+    tree.insert(tree.end(), order.begin(), order.end());
+    tree.insert(tree.end(), level_off.begin(), level_off.end());
+    return VPLMC_OK;
+}
+
+static CoarsenTree tree_view(const vplmc_plan *plan, const int32_t *dev) {
+    CoarsenTree t;
+    const int ng = plan->n_leaves, ns = ng - 1, NC = 2 * ng - 1;
+    t.n_leaves = ng;
+    t.height_max = plan->height_max;
+    t.left = dev;
+    t.right = dev + ns;
+    t.parent = dev + 2 * ns;
+    t.height = dev + 2 * ns + NC;
+    t.min_leaf = dev + 2 * ns + 2 * NC;
+    t.order = dev + 2 * ns + 3 * NC;
+    t.level_off = dev + 3 * ns + 3 * NC;
+    return t;
+}
+
+// The plan of a frame: the columns of slice s are the cut clusters
+// cl_offsets[s] .. cl_offsets[s+1], or (co given) the slice's own coarsening
+// of the tree above the cut, at most min(n_leaves, max(q, n_max[s])) nodes.
+static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t *cl_offsets, const int32_t *rank,
+                      int32_t n_clusters, const vplmc_params *params, const vplmc_coarsen *co, vplmc_plan **out) {
     if (!out) return set_error(VPLMC_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_slices < 0) return set_error(VPLMC_EINVAL, "n_slices must be >= 0");
-    if (n_slices > 0 && (!pt_offsets || !cl_offsets || !rank))
+    if (n_slices > 0 && (!pt_offsets || (!co && !cl_offsets) || !rank || (co && !co->n_max)))
         return set_error(VPLMC_EINVAL, "slice layout arrays must be non-NULL");
     if (n_clusters < 0) return set_error(VPLMC_EINVAL, "n_clusters must be >= 0");
     int rc = check_params(params);
     if (rc) return rc;
-    if (n_slices > 0 && (pt_offsets[0] != 0 || cl_offsets[0] != 0))
+    if (n_slices > 0 && (pt_offsets[0] != 0 || (!co && cl_offsets[0] != 0)))
         return set_error(VPLMC_EINVAL, "pt_offsets[0] and cl_offsets[0] must be 0");
     vplmc_plan *plan = new (std::nothrow) vplmc_plan();
     if (!plan) return set_error(VPLMC_ENOMEM, "plan allocation failed");
     plan->n_slices = n_slices;
     plan->n_clusters = n_clusters;
+    plan->n_lights = n_clusters;
     plan->pass1_ppm = params->pass1_ppm;
     plan->pass2_ppm = params->pass2_ppm;
+    if (co) {
+        plan->coarse = true;
+        plan->n_leaves = co->n_leaves;
+        plan->n_lights = 2 * co->n_leaves - 1;
+        plan->pixels = co->pixels;
+        plan->bound = co->bound;
+        if ((rc = build_tree(co, plan->tree, plan->height_max))) {
+            delete plan;
+            return rc;
+        }
+    }
     plan->desc.resize(n_slices);
     int64_t o1 = 0, o2 = 0, oo = 0, oc = 0, orow = 0, ocp = 0, ox = 0, oy = 0, obm = 0, obmt = 0, summ = 0;
     int64_t ogrp = 0, oell = 0, nell = 0, opart = 0;
     for (int s = 0; s < n_slices; ++s) {
         const int64_t m = (int64_t)pt_offsets[s + 1] - pt_offsets[s];
-        const int64_t n = (int64_t)cl_offsets[s + 1] - cl_offsets[s];
         const int q = rank[s];
+        if (co && co->n_max[s] < 1) {
+            delete plan;
+            return set_error(VPLMC_EINVAL, "slice %d: n_max must be >= 1", s);
+        }
+        const int64_t n = co ? std::min<int64_t>(co->n_leaves, std::max<int64_t>(q, co->n_max[s]))
+                             : (int64_t)cl_offsets[s + 1] - cl_offsets[s];
         if (m < 1 || m > VPLMC_MAX_ROWS || n < 1 || n > VPLMC_MAX_COLS) {
             delete plan;
             return set_error(VPLMC_EINVAL, "slice %d: %lld rows x %lld columns outside [1, 65535]", s, (long long)m,
@@ -278,9 +351,11 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
             return set_error(VPLMC_EUNSUPPORTED, "slice %d: rank %d (this build completes at ranks 4, 8, 16, 32)", s, q);
         }
         const int64_t D = m * n;
-        const int64_t N1 = count_from_ppm(params->pass1_ppm, D);
+        // coarsened slices: capacities (the first pass is the coarsening's
+        // row draws, at most `pixels` distinct entries)
+        const int64_t N1 = co ? std::min<int64_t>(co->pixels, D) : count_from_ppm(params->pass1_ppm, D);
         int64_t N2 = count_from_ppm(params->pass2_ppm, D);
-        if (N2 > D - N1) N2 = D - N1;
+        if (N2 > D - (co ? 0 : N1)) N2 = D - (co ? 0 : N1);
         if (N1 + N2 > INT32_MAX) {
             delete plan;
             return set_error(VPLMC_EINVAL, "slice %d: %lld samples exceed 2^31 - 1", s, (long long)(N1 + N2));
@@ -293,7 +368,8 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         d.N1 = (int32_t)N1;
         d.N2 = (int32_t)N2;
         d.pt_off = pt_offsets[s];
-        d.cl_off = cl_offsets[s];
+        d.cl_off = co ? (int32_t)oc : cl_offsets[s];
+        d.nmax = co ? co->n_max[s] : 0;
         d.words_row = (int32_t)((n + 31) / 32);
         d.words_col = (int32_t)((m + 31) / 32);
         d.off1 = o1;
@@ -361,6 +437,10 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     plan->tot_part = opart;
     plan->tot_ell = oell;
     plan->n_ell = nell;
+    if (co && oc > INT32_MAX) {
+        delete plan;
+        return set_error(VPLMC_EINVAL, "too many columns (%lld)", (long long)oc);
+    }
     if (ogrp > INT32_MAX) {
         delete plan;
         return set_error(VPLMC_EINVAL, "too many column groups (%lld)", (long long)ogrp);
@@ -371,8 +451,24 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
 
     Layout &L = plan->layout;
     memset(&L, 0, sizeof(L));
-    const int64_t S = n_slices, NC = n_clusters;
+    const int64_t S = n_slices, NC = plan->n_lights;
     size_t bytes[R_INTERNAL_END] = {};
+    if (co) {
+        const int64_t ng = co->n_leaves, ns = ng - 1;
+        bytes[VPLMC_R_COLUMNS] = oc * 4;
+        bytes[VPLMC_R_NODE_EPS] = S * ns * 4;
+        bytes[VPLMC_R_LEAF_DRAWS] = ng * 4;
+        bytes[VPLMC_R_NODE_MEMBERS] = NC * 4;
+        bytes[R_TREE] = plan->tree.size() * 4;
+        bytes[R_NODE_KD] = 2 * ns * 4;
+        bytes[R_LEAF_KPRE] = (ng + 1) * 8;
+        bytes[R_NODE_COST] = S * ns * 4;
+        bytes[R_NODE_EFF] = S * ns * 4;
+        bytes[R_NODE_MERGED] = S * ns;
+        bytes[R_NODE_TOP] = S * NC * 4;
+        bytes[R_LEAF_COL] = S * ng * 4;
+        bytes[R_ZETA] = S * (int64_t)co->pixels * 2;
+    }
     bytes[VPLMC_R_LIGHTS] = 9 * NC * 4;
     bytes[VPLMC_R_REP] = NC * 4;
     bytes[VPLMC_R_BBOX] = 6 * NC * 4;
@@ -442,6 +538,24 @@ int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     return VPLMC_OK;
 }
 
+int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t *cl_offsets, const int32_t *rank,
+                      int32_t n_clusters, const vplmc_params *params, vplmc_plan **out) {
+    return plan_build(n_slices, pt_offsets, cl_offsets, rank, n_clusters, params, nullptr, out);
+}
+
+int vplmc_plan_create_coarse(int32_t n_slices, const int32_t *pt_offsets, const int32_t *rank,
+                             const vplmc_coarsen *coarsen, const vplmc_params *params, vplmc_plan **out) {
+    if (out) *out = nullptr;
+    if (!coarsen) return set_error(VPLMC_EINVAL, "coarsen is NULL");
+    if (coarsen->n_leaves < 1 || coarsen->n_leaves > VPLMC_MAX_LEAVES)
+        return set_error(VPLMC_EINVAL, "n_leaves must be in [1, %d] (got %d)", VPLMC_MAX_LEAVES, coarsen->n_leaves);
+    if (coarsen->pixels < 0 || coarsen->pixels > (1 << 30))
+        return set_error(VPLMC_EINVAL, "pixels must be in [0, 2^30] (got %d)", coarsen->pixels);
+    if (!(coarsen->bound >= 0.0)) return set_error(VPLMC_EINVAL, "bound must be >= 0");
+    if (coarsen->reserved != 0) return set_error(VPLMC_EINVAL, "reserved must be 0");
+    return plan_build(n_slices, pt_offsets, nullptr, rank, coarsen->n_leaves, params, coarsen, out);
+}
+
 int vplmc_plan_destroy(vplmc_plan *plan) {
     delete plan;
     return VPLMC_OK;
@@ -495,7 +609,8 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if (vpls->n < 1 || bad_ptrs_lights(vpls)) return set_error(VPLMC_EINVAL, "incomplete VPL arrays");
     if (cut->n_clusters != plan->n_clusters || !cut->offsets || !cut->members)
         return set_error(VPLMC_EINVAL, "cut does not match the plan (%d clusters planned)", plan->n_clusters);
-    if (plan->n_slices > 0 && (!pt_ids || !cl_ids)) return set_error(VPLMC_EINVAL, "pt_ids and cl_ids must be non-NULL");
+    if (plan->n_slices > 0 && (!pt_ids || (!cl_ids && !plan->coarse)))
+        return set_error(VPLMC_EINVAL, "pt_ids and cl_ids must be non-NULL");
     if (!radiance) return set_error(VPLMC_EINVAL, "radiance is NULL");
     if (!workspace || workspace_bytes < plan->layout.total)
         return set_error(VPLMC_EINVAL, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes,
@@ -511,9 +626,12 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
 
     SliceDesc *desc = region<SliceDesc>(ws, plan, R_DESC);
     const int32_t *ids = reinterpret_cast<const int32_t *>(desc + S);
-    // (a captured frame reuses the table uploaded by the eager frame before the capture)
+    // (a captured frame reuses the tables uploaded by the eager frame before the capture)
     if (S > 0 && !ctx->capturing)
         VPLMC_HIP(hipMemcpyAsync(desc, plan->upload.data(), plan->upload.size(), hipMemcpyHostToDevice, st));
+    if (plan->coarse && !plan->tree.empty() && !ctx->capturing)
+        VPLMC_HIP(hipMemcpyAsync(region<int32_t>(ws, plan, R_TREE), plan->tree.data(), plan->tree.size() * 4,
+                                 hipMemcpyHostToDevice, st));
 
     uint32_t *bm = region<uint32_t>(ws, plan, R_BITMAP);
     uint32_t *bmt = region<uint32_t>(ws, plan, R_BITMAPT);
@@ -528,17 +646,57 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
 
     if ((rc = ph.mark(VPLMC_PH_CLUSTER))) return rc;
     float *lights = region<float>(ws, plan, VPLMC_R_LIGHTS);
-    if ((rc = launch_cluster_table(st, *vpls, *cut, params->seed, region<int32_t>(ws, plan, VPLMC_R_REP), lights,
-                                   region<float>(ws, plan, VPLMC_R_BBOX))))
-        return rc;
+    int32_t *rep = region<int32_t>(ws, plan, VPLMC_R_REP);
+    float *bbox = region<float>(ws, plan, VPLMC_R_BBOX);
+    if ((rc = launch_cluster_table(st, *vpls, *cut, params->seed, rep, lights, bbox, plan->n_lights))) return rc;
     uint32_t *omega1 = region<uint32_t>(ws, plan, VPLMC_R_OMEGA1);
     float *val1 = region<float>(ws, plan, VPLMC_R_VAL1);
     uint32_t *omega2 = region<uint32_t>(ws, plan, VPLMC_R_OMEGA2);
     float *val2 = region<float>(ws, plan, VPLMC_R_VAL2);
-    if ((rc = ph.mark(VPLMC_PH_PASS1))) return rc;
-    if ((rc = launch_pass1(st, *plan, desc, params->seed, omega1, bm, bmt))) return rc;
+    const int32_t *node_members = nullptr;
+    if (plan->coarse) {
+        // light coarsening (Sec. 4): node table, row draws and merge errors,
+        // merge decisions and columns, then the first pass from the draws
+        const CoarsenTree tr = tree_view(plan, region<int32_t>(ws, plan, R_TREE));
+        const int ng = plan->n_leaves, ns = ng - 1;
+        int32_t *kd = region<int32_t>(ws, plan, R_NODE_KD);
+        int32_t *members = region<int32_t>(ws, plan, VPLMC_R_NODE_MEMBERS);
+        node_members = members;
+        if ((rc = launch_node_table(st, tr, cut->offsets, params->seed, rep, lights, bbox, members, kd, kd + ns)))
+            return rc;
+        CoarsenSlices cs;
+        cs.eps = region<float>(ws, plan, VPLMC_R_NODE_EPS);
+        cs.cost = region<float>(ws, plan, R_NODE_COST);
+        cs.eff = region<float>(ws, plan, R_NODE_EFF);
+        cs.merged = region<uint8_t>(ws, plan, R_NODE_MERGED);
+        cs.top = region<int32_t>(ws, plan, R_NODE_TOP);
+        cs.leaf_col = region<int32_t>(ws, plan, R_LEAF_COL);
+        cs.kept = kd;
+        cs.dropped = kd + ns;
+        int64_t *kpre = region<int64_t>(ws, plan, R_LEAF_KPRE);
+        cs.kpre = kpre;
+        cs.zeta = region<uint16_t>(ws, plan, R_ZETA);
+        if ((rc = launch_leaf_draws(st, ng, lights, plan->pixels, region<int32_t>(ws, plan, VPLMC_R_LEAF_DRAWS),
+                                    kpre)))
+            return rc;
+        if ((rc = ph.mark(VPLMC_PH_COARSEN))) return rc;
+        if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(cs.eps), (size_t)S * ns, 0u))) return rc;
+        if ((rc = launch_coarsen_eps(st, *plan, ctx->bvh, *points, lights, desc, pt_ids, tr, cs, *params, ctx->n_cu)))
+            return rc;
+        int32_t *columns = region<int32_t>(ws, plan, VPLMC_R_COLUMNS);
+        if ((rc = launch_coarsen_merge(st, *plan, desc, tr, cs, columns))) return rc;
+        cl_ids = columns;
+        if ((rc = ph.mark(VPLMC_PH_PASS1))) return rc;
+        if ((rc = launch_coarsen_pass1(st, *plan, desc, cs, bm, bmt, region<int32_t>(ws, plan, VPLMC_R_ROW_PTR),
+                                       omega1)))
+            return rc;
+    } else {
+        if ((rc = ph.mark(VPLMC_PH_COARSEN))) return rc;
+        if ((rc = ph.mark(VPLMC_PH_PASS1))) return rc;
+        if ((rc = launch_pass1(st, *plan, desc, params->seed, omega1, bm, bmt))) return rc;
+    }
     if ((rc = ph.mark(VPLMC_PH_EVAL1))) return rc;
-    if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_clusters, desc, S, pt_ids, cl_ids, omega1,
+    if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_lights, desc, S, pt_ids, cl_ids, omega1,
                                 plan->tot1, 0, stats, *params, val1, plan->tune.eval_threads, ctx->n_cu)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_WEIGHTS))) return rc;
@@ -555,8 +713,8 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     const float *logits = nullptr;
     if (learned || (params->flags & VPLMC_FEATURES)) {
         float *feat = region<float>(ws, plan, VPLMC_R_FEATURES);
-        if ((rc = launch_features(st, *plan, desc, *points, pt_ids, cl_ids, lights, region<float>(ws, plan, VPLMC_R_BBOX),
-                                  *cut, cnt, mn, mx, csum, csumsq, czero, region<float>(ws, plan, R_SLICE_GEO), feat)))
+        if ((rc = launch_features(st, *plan, desc, *points, pt_ids, cl_ids, lights, bbox, *cut, node_members, cnt, mn,
+                                  mx, csum, csumsq, czero, region<float>(ws, plan, R_SLICE_GEO), feat)))
             return rc;
         if (learned) {
             float *lg = region<float>(ws, plan, VPLMC_R_LOGITS);
@@ -576,7 +734,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if ((rc = ph.mark(VPLMC_PH_PASS2))) return rc;
     if ((rc = launch_pass2(st, *plan, desc, params->seed, prefix, bm, bmt, omega2, stats))) return rc;
     if ((rc = ph.mark(VPLMC_PH_EVAL2))) return rc;
-    if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_clusters, desc, S, pt_ids, cl_ids, omega2,
+    if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_lights, desc, S, pt_ids, cl_ids, omega2,
                                 plan->tot2, 1, stats, *params, val2, plan->tune.eval_threads, ctx->n_cu)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_SORT))) return rc;
@@ -843,6 +1001,24 @@ int vplmc_read_stats(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspa
     return VPLMC_OK;
 }
 
+int vplmc_read_counts(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace, int32_t *n, int32_t *N1,
+                      int32_t *N2) {
+    if (!ctx || !plan || !workspace) return set_error(VPLMC_EINVAL, "ctx, plan and workspace must be non-NULL");
+    const int S = plan->n_slices;
+    std::vector<SliceDesc> h(S);
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    if (S > 0)
+        VPLMC_HIP(hipMemcpyAsync(h.data(), static_cast<const char *>(workspace) + plan->layout.off[R_DESC],
+                                 S * sizeof(SliceDesc), hipMemcpyDeviceToHost, ctx->stream));
+    VPLMC_HIP(hipStreamSynchronize(ctx->stream));
+    for (int s = 0; s < S; ++s) {
+        if (n) n[s] = h[s].n;
+        if (N1) N1[s] = h[s].N1;
+        if (N2) N2[s] = h[s].N2;
+    }
+    return VPLMC_OK;
+}
+
 int vplmc_cluster_table(vplmc_ctx *ctx, const vplmc_lights *vpls, const vplmc_cut *cut, uint64_t seed, int32_t *rep,
                         float *lights, float *bbox) {
     if (!ctx || !vpls || !cut || !rep || !lights || !bbox) return set_error(VPLMC_EINVAL, "NULL argument");
@@ -850,7 +1026,7 @@ int vplmc_cluster_table(vplmc_ctx *ctx, const vplmc_lights *vpls, const vplmc_cu
     if (cut->n_clusters < 0 || (cut->n_clusters > 0 && (!cut->offsets || !cut->members)))
         return set_error(VPLMC_EINVAL, "invalid cut");
     VPLMC_HIP(hipSetDevice(ctx->device));
-    return launch_cluster_table(ctx->stream, *vpls, *cut, seed, rep, lights, bbox);
+    return launch_cluster_table(ctx->stream, *vpls, *cut, seed, rep, lights, bbox, cut->n_clusters);
 }
 
 int vplmc_eval_pairs(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lights *lights, int64_t n_pairs,
@@ -951,6 +1127,7 @@ int vplmc_proposal_targets(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_p
                            const int32_t *pt_ids, const int32_t *cl_ids, const vplmc_params *params, void *workspace,
                            size_t workspace_bytes, float *pstar) {
     if (!ctx || !plan || !points || !lights || !params || !pstar) return set_error(VPLMC_EINVAL, "NULL argument");
+    if (plan->coarse) return set_error(VPLMC_EUNSUPPORTED, "training targets need a plan with fixed cluster columns");
     if (bad_ptrs_points(points)) return set_error(VPLMC_EINVAL, "incomplete points arrays");
     if (plan->n_slices > 0 && (!pt_ids || !cl_ids)) return set_error(VPLMC_EINVAL, "pt_ids and cl_ids must be non-NULL");
     if (!workspace || workspace_bytes < plan->layout.total)
@@ -974,7 +1151,8 @@ int vplmc_check_inputs(vplmc_ctx *ctx, const vplmc_plan *plan, int32_t n_points,
     if (n_points < 0 || n_vpls < 0) return set_error(VPLMC_EINVAL, "n_points and n_vpls must be >= 0");
     if (cut->n_clusters != plan->n_clusters) return set_error(VPLMC_EINVAL, "cut does not match the plan");
     if (cut->n_clusters > 0 && (!cut->offsets || !cut->members)) return set_error(VPLMC_EINVAL, "invalid cut");
-    if (plan->n_slices > 0 && (!pt_ids || !cl_ids)) return set_error(VPLMC_EINVAL, "pt_ids and cl_ids must be non-NULL");
+    if (plan->n_slices > 0 && (!pt_ids || (!cl_ids && !plan->coarse)))
+        return set_error(VPLMC_EINVAL, "pt_ids and cl_ids must be non-NULL");
     VPLMC_HIP(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     unsigned long long *bad = nullptr;
@@ -987,7 +1165,8 @@ int vplmc_check_inputs(vplmc_ctx *ctx, const vplmc_plan *plan, int32_t n_points,
         VPLMC_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(unsigned long long), st));
         int r;
         if ((r = launch_count_out_of_range(st, pt_ids, plan->sum_m, n_points, bad))) return r;
-        if ((r = launch_count_out_of_range(st, cl_ids, plan->tot_col, plan->n_clusters, bad))) return r;
+        if (!plan->coarse && (r = launch_count_out_of_range(st, cl_ids, plan->tot_col, plan->n_clusters, bad)))
+            return r;
         if (cut->n_clusters > 0) {
             if ((r = launch_count_unordered(st, cut->offsets, cut->n_clusters, bad + 1))) return r;
             VPLMC_HIP(hipMemcpyAsync(&n_members, cut->offsets + cut->n_clusters, 4, hipMemcpyDeviceToHost, st));

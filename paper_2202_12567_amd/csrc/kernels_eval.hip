@@ -161,7 +161,8 @@ __device__ __forceinline__ int slice_of_off(const SliceDesc *__restrict__ desc, 
     return lo;
 }
 
-// entry of sample g of one pass (nothing for second-pass slots past the accepted count)
+// entry of sample g of one pass (nothing for slots past the slice's first-pass
+// count or its accepted second-pass count)
 template <bool STAGED>
 __device__ __forceinline__ void eval_one(const Bvh &bvh, const BvhStaged &staged, const vplmc_points &pts,
                                          const float *__restrict__ lights, int32_t n_lights,
@@ -171,7 +172,7 @@ __device__ __forceinline__ void eval_one(const Bvh &bvh, const BvhStaged &staged
                                          float eps, float *__restrict__ vals) {
     const int s = slice_of_off(desc, S, g, which);
     const SliceDesc d = desc[s];
-    if (which && g - d.off2 >= stats[4 * s + 3]) return;
+    if (which ? g - d.off2 >= stats[4 * s + 3] : g - d.off1 >= d.N1) return;
     const uint32_t key = keys[g];
     const int i = (int)(key >> 16), j = (int)(key & 0xFFFFu);
     const int pid = pt_ids[d.pt_off + i];
@@ -220,6 +221,111 @@ __global__ __launch_bounds__(256) void k_eval_omega(Bvh bvh, vplmc_points pts, c
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_keys; g += stride) {
         eval_one<STAGED>(bvh, staged, pts, lights, n_lights, desc, S, pt_ids, cl_ids, keys, g, which, stats, r_min2,
                          eps, vals);
+    }
+}
+
+// Merge errors of the per-slice light coarsening (Sec. 4).  One thread per
+// row draw (slice s, draw r; r < kpre[n_g]): the draw belongs to leaf x
+// (kpre[x] <= r < kpre[x + 1]) and is its k-th, k = r - kpre[x] < m'; its row
+// is the k-th image of leaf x's keyed permutation of [0, m') (4-round
+// Feistel, round function Philox(key = (seed, s), ctr = (R, round, TAG_ZETA,
+// x)) & mask, cycle-walked).  Walking from x to the root, the thread carries
+// S(i, rep of the current node) at unit intensity; at each split node f
+// (kept child a, dropped b) one new entry gives the other child's, and
+// I_b |S(i, rep_b) - S(i, rep_a)| (max over channels) goes into eps(f) by an
+// integer max (non-negative floats order as their bits).  A node's light is
+// its kept child's, so the carried value becomes S(i, rep_a).  Every node's
+// eps is thus the max over the union of its leaves' draws, each pixel
+// evaluated once per level (the reuse Sec. 4 describes).
+__device__ __forceinline__ uint64_t feistel_zeta(uint64_t v, uint64_t seed, uint64_t s, uint64_t x, int h) {
+    const uint64_t mask = (1ull << h) - 1ull;
+    uint64_t L = v >> h, R = v & mask;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t F = philox(seed, s, R, (uint64_t)r, TAG_ZETA, x).a & mask;
+        const uint64_t nL = R;
+        R = L ^ F;
+        L = nL;
+    }
+    return (L << h) | R;
+}
+
+__device__ __forceinline__ Light node_light(const float *__restrict__ lights, size_t N, int c, bool unit) {
+    return Light{{lights[c], lights[N + c], lights[2 * N + c]},
+                 {lights[3 * N + c], lights[4 * N + c], lights[5 * N + c]},
+                 unit ? 1.0f : lights[6 * N + c], unit ? 1.0f : lights[7 * N + c], unit ? 1.0f : lights[8 * N + c]};
+}
+
+template <bool STAGED>
+__global__ __launch_bounds__(256) void k_coarsen_eps(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
+                                                     const SliceDesc *__restrict__ desc, int64_t total, int64_t K,
+                                                     const int32_t *__restrict__ pt_ids, CoarsenTree tr,
+                                                     CoarsenSlices cs, uint64_t seed, float r_min2, float eps) {
+    extern __shared__ float4 stage[];
+    if (STAGED) {
+        const int nn = 2 * bvh.n_nodes, ns = bvh.n_spheres;
+        const float4 *nodes4 = reinterpret_cast<const float4 *>(bvh.nodes);
+        for (int k = threadIdx.x; k < nn + ns; k += blockDim.x) stage[k] = k < nn ? nodes4[k] : bvh.spheres[k - nn];
+        __syncthreads();
+    }
+    const BvhStaged staged{stage, bvh.n_nodes};
+    const int ng = tr.n_leaves;
+    const size_t N = (size_t)(2 * ng - 1);
+    const int64_t kt = cs.kpre[ng];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += stride) {
+        const int s = (int)(g / K);
+        const int64_t r = g - (int64_t)s * K;
+        if (r >= kt) continue;
+        const SliceDesc d = desc[s];
+        int lo = 0, hi = ng;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cs.kpre[mid] <= r) lo = mid; else hi = mid;
+        }
+        const int x = lo;
+        const int64_t k = r - cs.kpre[x];
+        if (k >= d.m) continue;
+        // row of the draw
+        const uint64_t m = (uint64_t)d.m;
+        int b = m > 1 ? 64 - __clzll((long long)(m - 1)) : 0;
+        b = b < 2 ? 2 : b;
+        const int h = (b + 1) / 2;
+        uint64_t e = feistel_zeta((uint64_t)k, seed, (uint64_t)s, (uint64_t)x, h);
+        while (e >= m) e = feistel_zeta(e, seed, (uint64_t)s, (uint64_t)x, h);
+        const int i = (int)e;
+        cs.zeta[g] = (uint16_t)i;
+        const PointData q = load_point(pts, pt_ids[d.pt_off + i]);
+        float c0, c1, c2;
+        if (STAGED)
+            shade_in(staged, bvh.n_nodes, q, node_light(lights, N, x, true), r_min2, eps, c0, c1, c2);
+        else
+            shade(bvh, q, node_light(lights, N, x, true), r_min2, eps, c0, c1, c2);
+        float *node_eps = cs.eps + (size_t)s * (ng - 1);
+        int c = x;
+        for (int f = tr.parent[x]; f >= 0; c = f, f = tr.parent[f]) {
+            const int kk = f - ng;
+            const int a = cs.kept[kk], bb = cs.dropped[kk];
+            const int other = c == a ? bb : a;
+            float o0, o1, o2;
+            if (STAGED)
+                shade_in(staged, bvh.n_nodes, q, node_light(lights, N, other, true), r_min2, eps, o0, o1, o2);
+            else
+                shade(bvh, q, node_light(lights, N, other, true), r_min2, eps, o0, o1, o2);
+            const bool kept_path = c == a;
+            const float a0 = kept_path ? c0 : o0, a1 = kept_path ? c1 : o1, a2 = kept_path ? c2 : o2;
+            const float b0 = kept_path ? o0 : c0, b1 = kept_path ? o1 : c1, b2 = kept_path ? o2 : c2;
+            const float err = fmaxf(fmaxf(lights[6 * N + bb] * fabsf(b0 - a0), lights[7 * N + bb] * fabsf(b1 - a1)),
+                                    lights[8 * N + bb] * fabsf(b2 - a2));
+            if (err > 0.0f) {
+                unsigned int *slot = reinterpret_cast<unsigned int *>(node_eps + kk);
+                const unsigned int bits = __float_as_uint(err);
+                if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < bits) atomicMax(slot, bits);
+            }
+            c0 = a0;
+            c1 = a1;
+            c2 = a2;
+        }
     }
 }
 
@@ -393,6 +499,26 @@ int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, c
         hipLaunchKernelGGL(k_eval_omega<false>, dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
                            n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
                            prm.r_min * prm.r_min, prm.ray_eps, vals);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_coarsen_eps(hipStream_t st, const vplmc_plan &plan, const Bvh &bvh, const vplmc_points &pts,
+                       const float *lights, const SliceDesc *desc, const int32_t *pt_ids, const CoarsenTree &tr,
+                       const CoarsenSlices &cs, const vplmc_params &prm, int n_cu) {
+    const int64_t total = (int64_t)plan.n_slices * plan.pixels;
+    if (total <= 0) return VPLMC_OK;
+    const int threads = 256;
+    const int64_t blocks = std::min<int64_t>(blocks_for(total, threads), (int64_t)EVAL_GRID_PER_CU * n_cu);
+    const size_t staged = ((size_t)2 * bvh.n_nodes + bvh.n_spheres) * sizeof(float4);
+    if (bvh.n_nodes > 0 && staged <= (size_t)EVAL_LDS_BYTES)
+        hipLaunchKernelGGL(k_coarsen_eps<true>, dim3((unsigned)blocks), dim3(threads), staged, st, bvh, pts, lights,
+                           desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
+                           prm.ray_eps);
+    else
+        hipLaunchKernelGGL(k_coarsen_eps<false>, dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
+                           desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
+                           prm.ray_eps);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }

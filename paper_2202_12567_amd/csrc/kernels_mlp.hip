@@ -55,10 +55,13 @@ __device__ __forceinline__ float gelu_grad(float x) {
 //   4 zero fraction 5 log1p(cluster bbox diag / dist) 6 log1p(dist / slice diag)
 //   7 cos(slice mean normal, slice->cluster) 8 cos(cluster normal, cluster->slice)
 //   9 log1p(I_c / mean I over the cut) 10 log(members) 11 1 - |slice mean normal|
+// Member counts come from the cut's offsets, or (light coarsening: columns
+// are tree nodes) from node_members.
 __global__ __launch_bounds__(256) void k_features(const SliceDesc *__restrict__ desc, vplmc_points pts,
                                                   const int32_t *__restrict__ pt_ids,
                                                   const int32_t *__restrict__ cl_ids, const float *__restrict__ lights,
                                                   int32_t nc, const float *__restrict__ bbox, vplmc_cut cut,
+                                                  const int32_t *__restrict__ node_members,
                                                   const int32_t *__restrict__ cnt, const float *__restrict__ mn,
                                                   const float *__restrict__ mx, const double *__restrict__ sum,
                                                   const double *__restrict__ sumsq, const int32_t *__restrict__ zeros,
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(256) void k_features(const SliceDesc *__restrict__ 
         f[8] = -(lights[3 * N + c] * ux + lights[4 * N + c] * uy + lights[5 * N + c] * uz);
         const double is = (double)((lights[6 * N + c] + lights[7 * N + c]) + lights[8 * N + c]);
         f[9] = (float)log1p(is / (imean_s + 1e-30));
-        f[10] = logf((float)(cut.offsets[c + 1] - cut.offsets[c]));
+        f[10] = logf((float)(node_members ? node_members[c] : cut.offsets[c + 1] - cut.offsets[c]));
         f[11] = 1.0f - nn;
     }
 }
@@ -429,11 +432,12 @@ unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1
 
 int launch_features(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const vplmc_points &pts,
                     const int32_t *pt_ids, const int32_t *cl_ids, const float *lights, const float *bbox,
-                    const vplmc_cut &cut, const int32_t *cnt, const float *mn, const float *mx, const double *sum,
-                    const double *sumsq, const int32_t *zeros, float *slice_geo, float *features) {
+                    const vplmc_cut &cut, const int32_t *node_members, const int32_t *cnt, const float *mn,
+                    const float *mx, const double *sum, const double *sumsq, const int32_t *zeros, float *slice_geo,
+                    float *features) {
     if (plan.n_slices <= 0) return VPLMC_OK;
     hipLaunchKernelGGL(k_features, dim3(plan.n_slices), dim3(256), 0, st, desc, pts, pt_ids, cl_ids, lights,
-                       plan.n_clusters, bbox, cut, cnt, mn, mx, sum, sumsq, zeros, slice_geo, features);
+                       plan.n_lights, bbox, cut, node_members, cnt, mn, mx, sum, sumsq, zeros, slice_geo, features);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }

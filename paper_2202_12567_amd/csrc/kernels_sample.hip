@@ -107,8 +107,9 @@ __global__ void k_philox(uint64_t k0, uint64_t k1, const uint64_t *ctr, int64_t 
 
 // One thread per cluster: representative drawn with probability ~ quantised
 // member intensity, intensity = FP64 member sum, bbox of member positions.
+// Planes of `stride` floats (the tree's node count when coarsening follows).
 __global__ void k_cluster_table(vplmc_lights v, vplmc_cut cut, uint64_t seed, int32_t *rep_out,
-                                float *lights, float *bbox) {
+                                float *lights, float *bbox, int32_t stride) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int nc = cut.n_clusters;
     if (c >= nc) return;
@@ -162,7 +163,7 @@ __global__ void k_cluster_table(vplmc_lights v, vplmc_cut cut, uint64_t seed, in
     }
     rep_out[c] = rep;
     const int r = rep < 0 ? 0 : rep;
-    const size_t N = (size_t)nc;
+    const size_t N = (size_t)stride;
     lights[0 * N + c] = v.x[r];
     lights[1 * N + c] = v.y[r];
     lights[2 * N + c] = v.z[r];
@@ -211,6 +212,7 @@ __global__ void k_colstats(const SliceDesc *__restrict__ desc, int S, int64_t to
     const int s = slice_of(desc, S, g, 3);
     const SliceDesc d = desc[s];
     const int64_t j = g - (d.off_colptr - s);
+    if (j >= d.n) return;   // past a coarsened slice's columns
     const int b = col_ptr[d.off_colptr + j], e = col_ptr[d.off_colptr + j + 1];
     float lo = INFINITY, hi = 0.f;
     double s1 = 0.0, s2 = 0.0;
@@ -356,7 +358,8 @@ __global__ __launch_bounds__(P2_THREADS) void k_pass2(const SliceDesc *__restric
             if (w < words) {
                 i = (int)(w / d.words_row);
                 jb = (int)(w % d.words_row) * 32;
-                const int valid = n - jb >= 32 ? 32 : n - jb;
+                // (words past a coarsened slice's columns hold no entry)
+                const int valid = n - jb >= 32 ? 32 : (n - jb > 0 ? n - jb : 0);
                 const uint32_t vmask = valid == 32 ? 0xFFFFFFFFu : ((1u << valid) - 1u);
                 freeb = ~load_word(bmr + w) & vmask;
             }
@@ -462,6 +465,7 @@ __global__ void k_rowscan(const SliceDesc *__restrict__ desc, int S, int64_t tot
         ptr_base = d.off_row;
     } else {
         r = g - (d.off_colptr - s);
+        if (r >= d.n) return;   // past a coarsened slice's columns
         words = d.words_col;
         base_word = d.off_bmt;
         ptr_base = d.off_colptr;
@@ -529,7 +533,7 @@ __global__ void k_scatter(const SliceDesc *__restrict__ desc, int S, int64_t tot
     const int s = slice_of(desc, S, g, which);
     const SliceDesc d = desc[s];
     const int64_t k = g - (which ? d.off2 : d.off1);
-    if (which && k >= stats[4 * s + 3]) return;
+    if (which ? k >= stats[4 * s + 3] : k >= d.N1) return;
     const uint32_t key = keys[g];
     const uint32_t i = key >> 16, j = key & 0xFFFFu;
     // a slice completed from its ELL copy gets only that copy
@@ -679,10 +683,10 @@ int launch_philox(hipStream_t st, uint64_t k0, uint64_t k1, const uint64_t *ctr,
 }
 
 int launch_cluster_table(hipStream_t st, const vplmc_lights &v, const vplmc_cut &cut, uint64_t seed,
-                         int32_t *rep, float *lights, float *bbox) {
+                         int32_t *rep, float *lights, float *bbox, int32_t stride) {
     if (cut.n_clusters <= 0) return VPLMC_OK;
     hipLaunchKernelGGL(k_cluster_table, dim3(blocks_for(cut.n_clusters, 64)), dim3(64), 0, st, v, cut, seed,
-                       rep, lights, bbox);
+                       rep, lights, bbox, stride);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }

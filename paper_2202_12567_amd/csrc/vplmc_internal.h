@@ -39,6 +39,8 @@ constexpr uint64_t TAG_PASS2 = 2;
 constexpr uint64_t TAG_INITX = 3;
 constexpr uint64_t TAG_INITY = 4;
 constexpr uint64_t TAG_REP = 5;
+constexpr uint64_t TAG_TREE = 6;   // kept child of a split node (light coarsening)
+constexpr uint64_t TAG_ZETA = 7;   // row draws of the light coarsening
 
 struct U64x4 {
     uint64_t a, b, c, d;
@@ -92,11 +94,15 @@ void build_bvh(int32_t n, const float *cx, const float *cy, const float *cz, con
                std::vector<BvhNode> &nodes, std::vector<float> &sph4);
 
 // --------------------------------------------------------- frame layout
-// Device copy of one slice's layout (offsets in elements).
+// Device copy of one slice's layout (offsets in elements).  With light
+// coarsening the host plan holds capacities (n, N1, N2 at most these) and
+// the frame's coarsening kernels write the slice's own n, N1 and N2 here
+// before anything reads them; every region is laid out for the capacities.
 struct SliceDesc {
     int32_t m, n, q, N1;
-    int32_t N2, pt_off, cl_off, words_row;     // words_row = ceil(n / 32)
-    int32_t words_col, off_grp, ell, pad0;     // words_col = ceil(m / 32); ell: completed from the ELL copy
+    int32_t N2, pt_off, cl_off, words_row;     // words_row = ceil(n / 32) (of the capacity)
+    int32_t words_col, off_grp, ell, nmax;     // words_col = ceil(m / 32); ell: completed from the ELL copy;
+                                               // nmax: column cap of the coarsening
     int64_t off1, off2, off_omega, off_col;
     int64_t off_row, off_colptr, off_x, off_y;
     int64_t off_bm, off_bmt;                   // bitmap word offsets (row- and column-major)
@@ -166,7 +172,39 @@ enum {
     R_ADM_RED,       // float per slice: ADM_RED_FLOATS
     R_E2PART,        // double per part slot: squared residual over the part's samples
     R_QUEUE,         // int32[8]: work-queue counters of the completion launches
+    R_TREE,          // int32: the coarsening tree (uploaded with the plan)
+    R_NODE_KD,       // int32 per split node: kept child, then dropped child
+    R_LEAF_KPRE,     // int64 per leaf + 1: prefix of the draw counts
+    R_NODE_COST,     // float per (slice, split node)
+    R_NODE_EFF,      // float per (slice, split node)
+    R_NODE_MERGED,   // uint8 per (slice, split node)
+    R_NODE_TOP,      // int32 per (slice, node)
+    R_LEAF_COL,      // int32 per (slice, leaf)
+    R_ZETA,          // uint16 per (slice, draw slot)
     R_INTERNAL_END
+};
+
+// Light tree above the global cut, as uploaded by the plan: leaves 0 .. n_g - 1,
+// split node n_g + k with children left[k], right[k] (children first); the
+// root is node 2 n_g - 2.
+struct CoarsenTree {
+    int32_t n_leaves = 0, height_max = 0;
+    const int32_t *left = nullptr, *right = nullptr;      // per split node
+    const int32_t *parent = nullptr;                      // per node (-1 at the root)
+    const int32_t *height = nullptr, *min_leaf = nullptr; // per node (leaves: 0, itself)
+    const int32_t *order = nullptr;                       // split nodes by (height, id)
+    const int32_t *level_off = nullptr;                   // height_max + 1: order[level_off[h-1] .. level_off[h]) have height h
+};
+
+// Per-frame and per-slice state of the coarsening.
+struct CoarsenSlices {
+    float *eps = nullptr, *cost = nullptr, *eff = nullptr;   // per (slice, split node)
+    uint8_t *merged = nullptr;                               // per (slice, split node)
+    int32_t *top = nullptr;                                  // per (slice, node): column node above it
+    int32_t *leaf_col = nullptr;                             // per (slice, leaf): its column
+    const int32_t *kept = nullptr, *dropped = nullptr;       // per split node
+    const int64_t *kpre = nullptr;                           // n_leaves + 1: prefix of the draw counts
+    uint16_t *zeta = nullptr;                                // per (slice, draw slot): row of the draw
 };
 
 // Regions of the workspace: byte offsets.
@@ -207,6 +245,12 @@ struct vplmc_ctx {
 struct vplmc_plan {
     int32_t n_slices = 0;
     int32_t n_clusters = 0;
+    int32_t n_lights = 0;          // lights of the table: n_clusters, or 2 n_leaves - 1 tree nodes
+    // light coarsening (Sec. 4): on when the plan was made with a tree
+    bool coarse = false;
+    int32_t n_leaves = 0, height_max = 0, pixels = 0;
+    double bound = 0.0;
+    std::vector<int32_t> tree;     // left, right, parent, height, min_leaf, order, level_off
     int32_t pass1_ppm = 0, pass2_ppm = 0;
     int64_t sum_m = 0, max_m = 0;
     std::vector<vplmc::SliceDesc> desc;
@@ -241,7 +285,18 @@ inline bool adm_fits_lds(int q, int m) {
 // kernel launchers (kernels_*.hip)
 int launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v);
 int launch_cluster_table(hipStream_t st, const vplmc_lights &v, const vplmc_cut &cut, uint64_t seed,
-                         int32_t *rep, float *lights, float *bbox);
+                         int32_t *rep, float *lights, float *bbox, int32_t stride);
+// light coarsening (kernels_coarsen.hip, kernels_eval.hip)
+int launch_node_table(hipStream_t st, const CoarsenTree &tr, const int32_t *cut_offsets, uint64_t seed, int32_t *rep,
+                      float *lights, float *bbox, int32_t *members, int32_t *kept, int32_t *dropped);
+int launch_leaf_draws(hipStream_t st, int32_t ng, const float *lights, int64_t K, int32_t *quota, int64_t *kpre);
+int launch_coarsen_eps(hipStream_t st, const vplmc_plan &plan, const Bvh &bvh, const vplmc_points &pts,
+                       const float *lights, const SliceDesc *desc, const int32_t *pt_ids, const CoarsenTree &tr,
+                       const CoarsenSlices &cs, const vplmc_params &prm, int n_cu);
+int launch_coarsen_merge(hipStream_t st, const vplmc_plan &plan, SliceDesc *desc, const CoarsenTree &tr,
+                         const CoarsenSlices &cs, int32_t *columns);
+int launch_coarsen_pass1(hipStream_t st, const vplmc_plan &plan, SliceDesc *desc, const CoarsenSlices &cs,
+                         uint32_t *bm, uint32_t *bmt, int32_t *row_ptr, uint32_t *omega1);
 int launch_count_out_of_range(hipStream_t st, const int32_t *ids, int64_t n, int32_t hi, unsigned long long *bad);
 int launch_count_unordered(hipStream_t st, const int32_t *offsets, int64_t n, unsigned long long *bad);
 int launch_philox(hipStream_t st, uint64_t k0, uint64_t k1, const uint64_t *ctr, int64_t n,
@@ -263,8 +318,9 @@ constexpr int MLP_IN = 12, MLP_HID = 128;
 constexpr int MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_HID + 1;
 int launch_features(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const vplmc_points &pts,
                     const int32_t *pt_ids, const int32_t *cl_ids, const float *lights, const float *bbox,
-                    const vplmc_cut &cut, const int32_t *cnt, const float *mn, const float *mx, const double *sum,
-                    const double *sumsq, const int32_t *zeros, float *slice_geo, float *features);
+                    const vplmc_cut &cut, const int32_t *node_members, const int32_t *cnt, const float *mn,
+                    const float *mx, const double *sum, const double *sumsq, const int32_t *zeros, float *slice_geo,
+                    float *features);
 int launch_mlp_forward(hipStream_t st, const float *params, int64_t rows, const float *features, float *y);
 int launch_mlp_train_step(hipStream_t st, float *params, float *m, float *v, int32_t step, float lr, int64_t rows,
                           const float *features, const float *pstar, int32_t n_groups, const int32_t *group_off,

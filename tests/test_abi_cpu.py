@@ -96,7 +96,9 @@ def test_public_region_sizes_follow_their_definitions():
             "COLMAX": n.sum() * 4, "COLCNT": n.sum() * 4, "ROW_PTR": (m + 1).sum() * 4,
             "CSR_COL": (N1 + N2) * 4, "CSR_VAL": 3 * (N1 + N2) * 4, "COL_PTR": (n + 1).sum() * 4,
             "CSC_ROW": (N1 + N2) * 4, "CSC_VAL": 3 * (N1 + N2) * 4, "X": (m * q).sum() * 4,
-            "Y": (3 * n * q).sum() * 4, "SLICE_SCALE": 3 * 4, "FEATURES": n.sum() * 12 * 4, "LOGITS": n.sum() * 4}
+            "Y": (3 * n * q).sum() * 4, "SLICE_SCALE": 3 * 4, "FEATURES": n.sum() * 12 * 4, "LOGITS": n.sum() * 4,
+            # light coarsening only
+            "COLUMNS": 0, "NODE_EPS": 0, "LEAF_DRAWS": 0, "NODE_MEMBERS": 0}
     assert set(want) == set(N.REGIONS)
     spans = []
     off, nb = ctypes.c_size_t(), ctypes.c_size_t()
@@ -158,3 +160,64 @@ def test_launch_shapes_default_and_validation():
                                   ctypes.byref(out)) == N.EINVAL
     assert lib.vplmc_autotune(None, h, None, None, None, None, None, None, None, 0, None, 2, None) == N.EINVAL
     lib.vplmc_plan_destroy(h)
+
+
+def coarse_plan(pt, rank, left, right, n_max, n_leaves, pixels=64, bound=0.0, **kw):
+    lib = N.load()
+    p = N.Params()
+    lib.vplmc_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    arrs = [np.asarray(a, np.int32) for a in (pt, rank, left, right, n_max)]
+    f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    c = N.Coarsen(n_leaves, pixels, f(arrs[2]), f(arrs[3]), f(arrs[4]), bound, 0)
+    h = ctypes.c_void_p()
+    rc = lib.vplmc_plan_create_coarse(len(arrs[1]), f(arrs[0]), f(arrs[1]), ctypes.byref(c), ctypes.byref(p),
+                                      ctypes.byref(h))
+    return rc, h
+
+
+def test_coarse_plan_capacities_and_regions():
+    """A plan with light coarsening: column capacity min(n_leaves, max(q, n_max)),
+    first-pass capacity min(pixels, m' n'), node-sized light regions."""
+    lib = N.load()
+    # leaves 0..3, split nodes 4 = (0, 1), 5 = (2, 3), 6 = (4, 5)
+    rc, h = coarse_plan([0, 100, 300], [4, 4], [0, 2, 4], [1, 3, 5], [3, 9], 4, pixels=250, pass2_ppm=100000)
+    assert rc == 0, N.load().vplmc_last_error()
+    info = N.SliceInfo()
+    assert lib.vplmc_plan_slice(h, 0, ctypes.byref(info)) == 0
+    assert (info.m, info.n, info.q, info.N1) == (100, 4, 4, 250)
+    assert info.N2 == (100000 * 400 + 500000) // 1000000
+    assert lib.vplmc_plan_slice(h, 1, ctypes.byref(info)) == 0
+    assert (info.m, info.n, info.N1, info.off_col) == (200, 4, 250, 4)
+    off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+    for name, size in (("LIGHTS", 9 * 7 * 4), ("REP", 7 * 4), ("BBOX", 6 * 7 * 4), ("COLUMNS", 8 * 4),
+                       ("NODE_EPS", 2 * 3 * 4), ("LEAF_DRAWS", 4 * 4), ("NODE_MEMBERS", 7 * 4)):
+        assert lib.vplmc_plan_region(h, N.R[name], ctypes.byref(off), ctypes.byref(nb)) == 0
+        assert nb.value == size, name
+    lib.vplmc_plan_destroy(h)
+    # the plain plan has no coarsening regions
+    rc, h = plan([0, 256], [0, 64], [8], nc=64)
+    assert lib.vplmc_plan_region(h, N.R["NODE_EPS"], ctypes.byref(off), ctypes.byref(nb)) == 0 and nb.value == 0
+    lib.vplmc_plan_destroy(h)
+
+
+@pytest.mark.parametrize("left,right,why", [
+    ([0, 2, 4], [1, 3, 4], "a node as both children"),
+    ([0, 2, 4], [1, 3, 6], "a child that is not earlier"),
+    ([0, 0, 4], [1, 3, 5], "a node with two parents"),
+    ([0, 2, 1], [1, 3, 5], "a node with two parents"),
+    ([0, 2, 4], [1, -1, 5], "a negative child"),
+])
+def test_coarse_plan_rejects_bad_trees(left, right, why):
+    rc, _ = coarse_plan([0, 100], [4], left, right, [3], 4)
+    assert rc == N.EINVAL, why
+
+
+def test_coarse_plan_rejects_bad_arguments():
+    assert coarse_plan([0, 100], [4], [0, 2, 4], [1, 3, 5], [0], 4)[0] == N.EINVAL          # n_max < 1
+    assert coarse_plan([0, 100], [4], [0, 2, 4], [1, 3, 5], [3], 4, pixels=-1)[0] == N.EINVAL
+    assert coarse_plan([0, 100], [4], [0, 2, 4], [1, 3, 5], [3], 4, bound=-1.0)[0] == N.EINVAL
+    assert coarse_plan([0, 100], [8], [0, 2, 4], [1, 3, 5], [3], 4)[0] == N.EINVAL          # q > n_leaves
+    assert coarse_plan([0, 100], [4], [], [], [3], 0)[0] == N.EINVAL                        # no leaves
+    assert coarse_plan([0, 100], [4], [0, 2, 4], [1, 3, 5], [3], 40000)[0] == N.EINVAL      # too many leaves
