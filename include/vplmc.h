@@ -116,6 +116,9 @@ typedef struct {
     int32_t m, n, q;         /* rows, cut columns, rank                           */
     int32_t N1, N2;          /* first-pass count and second-pass target           */
     int32_t adm_in_lds;      /* 1: the ADM kernel keeps X in LDS; 0: in global memory */
+    int32_t q_pad;           /* row length of X and Y: the next of 4, 8, 16, 32 >= q;
+                                components q .. q_pad-1 stay 0                     */
+    int32_t reserved;
     int64_t off1, off2;      /* element offsets into OMEGA1/VAL1, OMEGA2/VAL2     */
     int64_t off_omega;       /* element offset into CSR_* / CSC_* (N1 + N2 each)  */
     int64_t off_col;         /* element offset into per-column regions            */
@@ -148,8 +151,8 @@ enum {
     VPLMC_R_COL_PTR,      /* int32[n + 1] per slice: CSC column pointers (every slice)     */
     VPLMC_R_CSC_ROW,      /* int32 per entry: row, CSC order (column-major)                */
     VPLMC_R_CSC_VAL,      /* float[3] per entry, CSC order                                 */
-    VPLMC_R_X,            /* float[m][q] per slice: final X (initial X when max_iter = 0)  */
-    VPLMC_R_Y,            /* float[n][3][q] per slice: final Y (row c n + j of the paper's Y^T) */
+    VPLMC_R_X,            /* float[m][q_pad] per slice: final X (initial X when max_iter = 0) */
+    VPLMC_R_Y,            /* float[n][3][q_pad] per slice: final Y (row c n + j of the paper's Y^T) */
     VPLMC_R_SLICE_SCALE,  /* float per slice: s0, the mean sampled value M is divided by   */
     VPLMC_R_FEATURES,     /* float[12] per (slice, column): proposal features (learned mode) */
     VPLMC_R_LOGITS,       /* float per (slice, column): proposal log-density (learned mode) */
@@ -190,7 +193,10 @@ int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float 
  * clusters cl_ids[cl_offsets[s] .. cl_offsets[s+1]) and completes at rank
  * rank[s].  All three arrays are HOST (n_slices + 1, n_slices + 1, n_slices).
  * Rejects m' > VPLMC_MAX_ROWS, n' > VPLMC_MAX_COLS, q < 1,
- * q > min(VPLMC_MAX_RANK, m', n'), rates outside [0, 10^6] or summing above it. */
+ * q > min(VPLMC_MAX_RANK, m', n'), rates outside [0, 10^6] or summing above it.
+ * Any rank 1..32 is served: the completion runs at the next of 4, 8, 16, 32
+ * with the extra components of X and Y held at exactly 0, which leaves the
+ * rank-q iteration unchanged. */
 int vplmc_plan_create(int32_t n_slices, const int32_t *pt_offsets, const int32_t *cl_offsets,
                       const int32_t *rank, int32_t n_clusters, const vplmc_params *params,
                       vplmc_plan **out /* HOST */);
@@ -288,6 +294,13 @@ int vplmc_read_stats(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspa
  * plan's values. */
 int vplmc_read_counts(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace, int32_t *n,
                       int32_t *N1, int32_t *N2);
+
+/* Totals of the last frame rendered on this workspace (synchronises), HOST
+ * int64[4]: sampled entries (both passes), shadow rays cast for them (entries
+ * whose point and light face each other), entries the light coarsening
+ * evaluated (unit-intensity lighting of a drawn row by a node's light), and
+ * the shadow rays among those. */
+int vplmc_read_totals(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace, int64_t *out);
 
 /* Counts, on the device, the ids that break the contract of vplmc_render:
  * pt_ids outside [0, n_points), cl_ids outside [0, n_clusters), cut offsets

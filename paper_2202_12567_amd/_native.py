@@ -44,7 +44,8 @@ class Tune(ctypes.Structure):
 
 class SliceInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("q", ctypes.c_int32), ("N1", ctypes.c_int32),
-                ("N2", ctypes.c_int32), ("adm_in_lds", ctypes.c_int32), ("off1", ctypes.c_int64), ("off2", ctypes.c_int64),
+                ("N2", ctypes.c_int32), ("adm_in_lds", ctypes.c_int32), ("q_pad", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("off1", ctypes.c_int64), ("off2", ctypes.c_int64),
                 ("off_omega", ctypes.c_int64), ("off_col", ctypes.c_int64), ("off_row", ctypes.c_int64),
                 ("off_colptr", ctypes.c_int64), ("off_x", ctypes.c_int64), ("off_y", ctypes.c_int64)]
 
@@ -82,6 +83,7 @@ SIG = {
                                   ctypes.POINTER(Params), P]),
     "vplmc_read_stats": (I32, [P, P, P, P, P, P, P]),
     "vplmc_read_counts": (I32, [P, P, P, P, P, P]),
+    "vplmc_read_totals": (I32, [P, P, P, P]),
     "vplmc_check_inputs": (I32, [P, P, I32, I32, ctypes.POINTER(Cut), P, P, ctypes.POINTER(I64)]),
     "vplmc_cluster_table": (I32, [P, ctypes.POINTER(Lights), ctypes.POINTER(Cut), U64, P, P, P]),
     "vplmc_eval_pairs": (I32, [P, ctypes.POINTER(Points), ctypes.POINTER(Lights), I64, P, P,

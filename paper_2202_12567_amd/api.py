@@ -210,6 +210,14 @@ def read_counts(ctx, plan, ws):
     return dict(n=n, N1=n1, N2=n2)
 
 
+def read_totals(ctx, plan, ws):
+    """Frame totals (vplmc_read_totals): sampled entries, their shadow rays, the
+    coarsening's entry evaluations and its shadow rays."""
+    out = np.zeros(4, np.int64)
+    check(N.load().vplmc_read_totals(ctx.h, plan.h, _ptr(ws), out.ctypes.data_as(ctypes.c_void_p)))
+    return dict(entries=int(out[0]), rays=int(out[1]), coarsen_evals=int(out[2]), coarsen_rays=int(out[3]))
+
+
 def check_inputs(ctx, plan, ds):
     """vplmc_check_inputs: number of out-of-range point, cluster and member ids."""
     bad = ctypes.c_int64()

@@ -88,15 +88,10 @@ int check_params(const vplmc_params *p) {
     return VPLMC_OK;
 }
 
-int rank_bucket(int q) {
-    switch (q) {
-        case 4: return 0;
-        case 8: return 1;
-        case 16: return 2;
-        case 32: return 3;
-        default: return -1;
-    }
-}
+// rank group of a slice completed at rank q: the kernels run at the next of
+// 4, 8, 16, 32 (extra components of the factors stay 0)
+int rank_bucket(int q) { return q <= 4 ? 0 : (q <= 8 ? 1 : (q <= 16 ? 2 : 3)); }
+int padded_rank(int q) { return 4 << rank_bucket(q); }
 
 // records the boundary event `b` (0 .. VPLMC_N_PHASES) of the current frame
 struct PhaseMarks {
@@ -346,10 +341,7 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
                              (long long)m, (long long)n);
         }
         const int bucket = rank_bucket(q);
-        if (bucket < 0) {
-            delete plan;
-            return set_error(VPLMC_EUNSUPPORTED, "slice %d: rank %d (this build completes at ranks 4, 8, 16, 32)", s, q);
-        }
+        const int qp = padded_rank(q);
         const int64_t D = m * n;
         // coarsened slices: capacities (the first pass is the coarsening's
         // row draws, at most `pixels` distinct entries)
@@ -364,7 +356,8 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         memset(&d, 0, sizeof(d));
         d.m = (int32_t)m;
         d.n = (int32_t)n;
-        d.q = q;
+        d.q = qp;
+        d.qr = q;
         d.N1 = (int32_t)N1;
         d.N2 = (int32_t)N2;
         d.pt_off = pt_offsets[s];
@@ -382,7 +375,7 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         d.off_y = oy;
         d.off_bm = obm;
         d.off_bmt = obmt;
-        const bool in_lds = adm_fits_lds(q, (int)m);
+        const bool in_lds = adm_fits_lds(qp, (int)m);
         d.ell = in_lds ? 1 : 0;
         d.off_grp = (int32_t)ogrp;
         d.off_ell = oell;
@@ -403,8 +396,8 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         oc += n;
         orow += m + 1;
         ocp += n + 1;
-        ox += m * q;
-        oy += 3 * n * q;
+        ox += m * qp;
+        oy += 3 * n * qp;
         obm += m * d.words_row;
         obmt += n * d.words_col;
         summ += m;
@@ -519,6 +512,7 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     bytes[R_ADM_RED] = S * ADM_RED_FLOATS * 4;
     bytes[R_E2PART] = plan->tot_part * 8;
     bytes[R_QUEUE] = 8 * 4;
+    bytes[R_COUNTS] = 4 * 8;
     bytes[VPLMC_R_FEATURES] = oc * MLP_IN * 4;
     bytes[VPLMC_R_LOGITS] = oc * 4;
     size_t off = 0;
@@ -573,7 +567,8 @@ int vplmc_plan_slice(const vplmc_plan *plan, int32_t s, vplmc_slice_info *out) {
     const SliceDesc &d = plan->desc[s];
     out->m = d.m;
     out->n = d.n;
-    out->q = d.q;
+    out->q = d.qr;
+    out->q_pad = d.q;
     out->N1 = d.N1;
     out->N2 = d.N2;
     out->adm_in_lds = adm_fits_lds(d.q, d.m) ? 1 : 0;
@@ -643,6 +638,8 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if ((rc = launch_fill_u32(st, bmt, plan->tot_bmt, 0u))) return rc;
     if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(stats), 4 * (size_t)S, 0u))) return rc;
     if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(radiance), 3 * (size_t)points->m, 0u))) return rc;
+    unsigned long long *counts = region<unsigned long long>(ws, plan, R_COUNTS);
+    if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(counts), 8, 0u))) return rc;
 
     if ((rc = ph.mark(VPLMC_PH_CLUSTER))) return rc;
     float *lights = region<float>(ws, plan, VPLMC_R_LIGHTS);
@@ -681,7 +678,8 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
             return rc;
         if ((rc = ph.mark(VPLMC_PH_COARSEN))) return rc;
         if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(cs.eps), (size_t)S * ns, 0u))) return rc;
-        if ((rc = launch_coarsen_eps(st, *plan, ctx->bvh, *points, lights, desc, pt_ids, tr, cs, *params, ctx->n_cu)))
+        if ((rc = launch_coarsen_eps(st, *plan, ctx->bvh, *points, lights, desc, pt_ids, tr, cs, *params, ctx->n_cu,
+                                     counts + 1)))
             return rc;
         int32_t *columns = region<int32_t>(ws, plan, VPLMC_R_COLUMNS);
         if ((rc = launch_coarsen_merge(st, *plan, desc, tr, cs, columns))) return rc;
@@ -697,7 +695,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     }
     if ((rc = ph.mark(VPLMC_PH_EVAL1))) return rc;
     if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_lights, desc, S, pt_ids, cl_ids, omega1,
-                                plan->tot1, 0, stats, *params, val1, plan->tune.eval_threads, ctx->n_cu)))
+                                plan->tot1, 0, stats, *params, val1, plan->tune.eval_threads, ctx->n_cu, counts)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_WEIGHTS))) return rc;
     int32_t *col_ptr = region<int32_t>(ws, plan, VPLMC_R_COL_PTR);
@@ -735,7 +733,7 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if ((rc = launch_pass2(st, *plan, desc, params->seed, prefix, bm, bmt, omega2, stats))) return rc;
     if ((rc = ph.mark(VPLMC_PH_EVAL2))) return rc;
     if ((rc = launch_eval_omega(st, ctx->bvh, *points, lights, plan->n_lights, desc, S, pt_ids, cl_ids, omega2,
-                                plan->tot2, 1, stats, *params, val2, plan->tune.eval_threads, ctx->n_cu)))
+                                plan->tot2, 1, stats, *params, val2, plan->tune.eval_threads, ctx->n_cu, counts)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_SORT))) return rc;
     int32_t *row_ptr = region<int32_t>(ws, plan, VPLMC_R_ROW_PTR);
@@ -1016,6 +1014,31 @@ int vplmc_read_counts(vplmc_ctx *ctx, const vplmc_plan *plan, const void *worksp
         if (N1) N1[s] = h[s].N1;
         if (N2) N2[s] = h[s].N2;
     }
+    return VPLMC_OK;
+}
+
+int vplmc_read_totals(vplmc_ctx *ctx, const vplmc_plan *plan, const void *workspace, int64_t *out) {
+    if (!ctx || !plan || !workspace || !out) return set_error(VPLMC_EINVAL, "ctx, plan, workspace and out must be non-NULL");
+    const int S = plan->n_slices;
+    std::vector<SliceDesc> d(S);
+    std::vector<int32_t> st(4 * (size_t)S);
+    unsigned long long c[4] = {0, 0, 0, 0};
+    const char *ws = static_cast<const char *>(workspace);
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    if (S > 0) {
+        VPLMC_HIP(hipMemcpyAsync(d.data(), ws + plan->layout.off[R_DESC], S * sizeof(SliceDesc), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+        VPLMC_HIP(hipMemcpyAsync(st.data(), ws + plan->layout.off[R_SLICE_STATS], st.size() * 4, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    }
+    VPLMC_HIP(hipMemcpyAsync(c, ws + plan->layout.off[R_COUNTS], sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
+    VPLMC_HIP(hipStreamSynchronize(ctx->stream));
+    int64_t entries = 0;
+    for (int s = 0; s < S; ++s) entries += (int64_t)d[s].N1 + st[4 * s + 3];
+    out[0] = entries;
+    out[1] = (int64_t)c[0];
+    out[2] = (int64_t)c[1];
+    out[3] = (int64_t)c[2];
     return VPLMC_OK;
 }
 

@@ -209,6 +209,11 @@ __device__ void adm_global_slice(
 
     const SliceDesc d = desc[s];
     const int m = d.m, n = d.n;
+    // the slice's own rank qr <= Q: components qr .. Q-1 of X, Y and their
+    // multipliers start at 0 and stay exactly 0 (their Gram block is alpha I
+    // or beta I and every cross term is 0), so a rank-qr completion runs in
+    // the rank-Q kernel
+    const int qr = d.qr;
     const int t = threadIdx.x, lane = t % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
 
@@ -265,11 +270,11 @@ __device__ void adm_global_slice(
     if (t == 0) scale_all[s] = (float)s0;
 
     // ---- initial factors: fp32(u24(Philox) * fp32(2 / sqrt q)) ----
-    const float cq = (float)(2.0 / sqrt((double)Q));
+    const float cq = (float)(2.0 / sqrt((double)qr));
     for (int e = t; e < m * Q; e += THREADS) {
         const int i = e / Q, k = e % Q;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
-        const float v = __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq);
+        const float v = k < qr ? __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq) : 0.f;
         Xa[e] = v;
         Xp[e] = v;
         Lam[e] = 0.f;
@@ -278,7 +283,7 @@ __device__ void adm_global_slice(
         const int j = e / (3 * Q), c = (e / Q) % 3, k = e % Q;
         const uint64_t col = (uint64_t)c * (uint64_t)n + (uint64_t)j;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)k, col, TAG_INITY, 0);
-        const float v = __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq);
+        const float v = k < qr ? __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq) : 0.f;
         Y[e] = v;
         Yp[e] = v;
         Pi[e] = 0.f;
@@ -286,8 +291,8 @@ __device__ void adm_global_slice(
     __threadfence_block();
     __syncthreads();
 
-    const double alpha = (double)alpha0 * (3.0 * n) / Q;
-    const double beta = (double)beta0 * (double)m / Q;
+    const double alpha = (double)alpha0 * (3.0 * n) / qr;
+    const double beta = (double)beta0 * (double)m / qr;
     const float alpha_f = (float)alpha, beta_f = (float)beta;
     const float ga = (float)((double)gamma * alpha), gb = (float)((double)gamma * beta);
     const float inv_alpha = (float)(1.0 / alpha), inv_beta = (float)(1.0 / beta);
@@ -827,6 +832,11 @@ __device__ void adm_ell_slice(
 
     const SliceDesc d = desc[s];
     const int m = d.m, n = d.n;
+    // the slice's own rank qr <= Q: components qr .. Q-1 of X, Y and their
+    // multipliers start at 0 and stay exactly 0 (their Gram block is alpha I
+    // or beta I and every cross term is 0), so a rank-qr completion runs in
+    // the rank-Q kernel
+    const int qr = d.qr;
     const int t = threadIdx.x, lane = t % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
     float *XA = dyn;                                  // X_k, row stride q
@@ -908,22 +918,22 @@ __device__ void adm_ell_slice(
     if (t == 0) scale_all[s] = (float)s0;
 
     // ---- initial factors: fp32(u24(Philox) * fp32(2 / sqrt q)) ----
-    const float cq = (float)(2.0 / sqrt((double)Q));
+    const float cq = (float)(2.0 / sqrt((double)qr));
     for (int e = t; e < m * Q; e += THREADS) {
         const int i = e / Q, k = e % Q;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
-        const float v = __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq);
+        const float v = k < qr ? __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq) : 0.f;
         XA[xpos<Q>(i, k)] = v;
         Xp[e] = v;
         Lam[e] = 0.f;
     }
     float ym0 = 0.f;
-    const float beta0_f = (float)((double)beta0 * (double)m / Q);
+    const float beta0_f = (float)((double)beta0 * (double)m / qr);
     for (int e = t; e < 3 * n * Q; e += THREADS) {
         const int j = e / (3 * Q), c = (e / Q) % 3, k = e % Q;
         const uint64_t col = (uint64_t)c * (uint64_t)n + (uint64_t)j;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)k, col, TAG_INITY, 0);
-        const float v = __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq);
+        const float v = k < qr ? __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq) : 0.f;
         Y[e] = v;
         W[e] = __fmul_rn(beta0_f, v);                 // b V_0 - P_0 with V_0 = Y_0, P_0 = 0
         Pi[e] = 0.f;
@@ -987,8 +997,8 @@ __device__ void adm_ell_slice(
         return RS * ymax * ldexp(1.0, S) * (1.0 + 1e-5) + 0.5 * Krow < 2147483647.0;
     };
 
-    const double alpha = (double)alpha0 * (3.0 * n) / Q;
-    const double beta = (double)beta0 * (double)m / Q;
+    const double alpha = (double)alpha0 * (3.0 * n) / qr;
+    const double beta = (double)beta0 * (double)m / qr;
     const float alpha_f = (float)alpha, beta_f = (float)beta;
     const float ga = (float)((double)gamma * alpha), gb = (float)((double)gamma * beta);
     const float inv_alpha = (float)(1.0 / alpha), inv_beta = (float)(1.0 / beta);

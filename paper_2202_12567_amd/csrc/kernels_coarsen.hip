@@ -213,7 +213,7 @@ __global__ __launch_bounds__(CT) void k_coarsen_merge(SliceDesc *desc, CoarsenTr
     for (int k = 0; k < CT / WAVE; ++k) B += cnt_s[k];
     int64_t L = (int64_t)ng - d.nmax;
     if (L < B) L = B;
-    if (L > (int64_t)ng - d.q) L = (int64_t)ng - d.q;
+    if (L > (int64_t)ng - d.qr) L = (int64_t)ng - d.qr;
     if (L < 0) L = 0;
     // the L-th smallest key (rank L - 1), 8 bits at a time from the top
     if (t == 0) {

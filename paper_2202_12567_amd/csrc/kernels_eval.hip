@@ -120,9 +120,10 @@ struct Light {
 };
 
 // entry of one (point, light) pair (zero when the pair faces away or is
-// occluded); bvh is a BVH view (BvhGlobal or BvhStaged) of n_nodes nodes
+// occluded); bvh is a BVH view (BvhGlobal or BvhStaged) of n_nodes nodes.
+// Returns whether a shadow ray was cast (both cosines positive).
 template <typename B>
-__device__ __forceinline__ void shade_in(const B &bvh, int n_nodes, const PointData &q, const Light &L,
+__device__ __forceinline__ bool shade_in(const B &bvh, int n_nodes, const PointData &q, const Light &L,
                                          float r_min2, float eps, float &o0, float &o1, float &o2) {
     o0 = o1 = o2 = 0.0f;
     const P3 d = sub(L.y, q.x);
@@ -131,7 +132,7 @@ __device__ __forceinline__ void shade_in(const B &bvh, int n_nodes, const PointD
     const P3 w = {d.x * inv_r, d.y * inv_r, d.z * inv_r};
     const float cx = dot(q.n, w);
     const float cy = -dot(L.n, w);
-    if (!(cx > 0.0f && cy > 0.0f)) return;
+    if (!(cx > 0.0f && cy > 0.0f)) return false;
     const float G = cx * cy / fmaxf(r2, r_min2);
     float spec = 0.0f;
     if (q.ks > 0.0f) {
@@ -140,15 +141,23 @@ __device__ __forceinline__ void shade_in(const B &bvh, int n_nodes, const PointD
         spec = q.ks * (q.e + 2.0f) * (0.5f * INV_PI) * powf(cr, q.e);
     }
     const P3 o = {fmaf(eps, q.n.x, q.x.x), fmaf(eps, q.n.y, q.x.y), fmaf(eps, q.n.z, q.x.z)};
-    if (occluded_in(bvh, n_nodes, o, sub(L.y, o))) return;
+    if (occluded_in(bvh, n_nodes, o, sub(L.y, o))) return true;
     o0 = fmaf(q.kd0, INV_PI, spec) * L.i0 * G;
     o1 = fmaf(q.kd1, INV_PI, spec) * L.i1 * G;
     o2 = fmaf(q.kd2, INV_PI, spec) * L.i2 * G;
+    return true;
 }
 
-__device__ __forceinline__ void shade(const Bvh &bvh, const PointData &q, const Light &L, float r_min2,
+__device__ __forceinline__ bool shade(const Bvh &bvh, const PointData &q, const Light &L, float r_min2,
                                       float eps, float &o0, float &o1, float &o2) {
-    shade_in(BvhGlobal{bvh}, bvh.n_nodes, q, L, r_min2, eps, o0, o1, o2);
+    return shade_in(BvhGlobal{bvh}, bvh.n_nodes, q, L, r_min2, eps, o0, o1, o2);
+}
+
+// adds a per-thread count into a device total: one atomic per wavefront
+__device__ __forceinline__ void add_count(unsigned long long *total, uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(total, (unsigned long long)v);
 }
 
 __device__ __forceinline__ int slice_of_off(const SliceDesc *__restrict__ desc, int S, int64_t g, int which) {
@@ -164,7 +173,7 @@ __device__ __forceinline__ int slice_of_off(const SliceDesc *__restrict__ desc, 
 // entry of sample g of one pass (nothing for slots past the slice's first-pass
 // count or its accepted second-pass count)
 template <bool STAGED>
-__device__ __forceinline__ void eval_one(const Bvh &bvh, const BvhStaged &staged, const vplmc_points &pts,
+__device__ __forceinline__ uint32_t eval_one(const Bvh &bvh, const BvhStaged &staged, const vplmc_points &pts,
                                          const float *__restrict__ lights, int32_t n_lights,
                                          const SliceDesc *__restrict__ desc, int S, const int32_t *__restrict__ pt_ids,
                                          const int32_t *__restrict__ cl_ids, const uint32_t *__restrict__ keys,
@@ -172,7 +181,7 @@ __device__ __forceinline__ void eval_one(const Bvh &bvh, const BvhStaged &staged
                                          float eps, float *__restrict__ vals) {
     const int s = slice_of_off(desc, S, g, which);
     const SliceDesc d = desc[s];
-    if (which ? g - d.off2 >= stats[4 * s + 3] : g - d.off1 >= d.N1) return;
+    if (which ? g - d.off2 >= stats[4 * s + 3] : g - d.off1 >= d.N1) return 0;
     const uint32_t key = keys[g];
     const int i = (int)(key >> 16), j = (int)(key & 0xFFFFu);
     const int pid = pt_ids[d.pt_off + i];
@@ -183,13 +192,15 @@ __device__ __forceinline__ void eval_one(const Bvh &bvh, const BvhStaged &staged
                      lights[6 * N + c], lights[7 * N + c], lights[8 * N + c]};
     const PointData q = load_point(pts, pid);
     float o0, o1, o2;
+    bool ray;
     if (STAGED)
-        shade_in(staged, bvh.n_nodes, q, L, r_min2, eps, o0, o1, o2);
+        ray = shade_in(staged, bvh.n_nodes, q, L, r_min2, eps, o0, o1, o2);
     else
-        shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+        ray = shade(bvh, q, L, r_min2, eps, o0, o1, o2);
     vals[3 * g] = o0;
     vals[3 * g + 1] = o1;
     vals[3 * g + 2] = o2;
+    return ray ? 1u : 0u;
 }
 
 // BVH bytes (nodes and spheres) an entry kernel stages in LDS; larger ones are
@@ -208,7 +219,8 @@ __global__ __launch_bounds__(256) void k_eval_omega(Bvh bvh, vplmc_points pts, c
                                                     const int32_t *__restrict__ cl_ids,
                                                     const uint32_t *__restrict__ keys, int64_t n_keys,
                                                     int which, const int32_t *__restrict__ stats, float r_min2,
-                                                    float eps, float *__restrict__ vals) {
+                                                    float eps, float *__restrict__ vals,
+                                                    unsigned long long *__restrict__ rays) {
     extern __shared__ float4 stage[];
     if (STAGED) {
         const int nn = 2 * bvh.n_nodes, ns = bvh.n_spheres;
@@ -218,10 +230,12 @@ __global__ __launch_bounds__(256) void k_eval_omega(Bvh bvh, vplmc_points pts, c
     }
     const BvhStaged staged{stage, bvh.n_nodes};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t traced = 0;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_keys; g += stride) {
-        eval_one<STAGED>(bvh, staged, pts, lights, n_lights, desc, S, pt_ids, cl_ids, keys, g, which, stats, r_min2,
-                         eps, vals);
+        traced += eval_one<STAGED>(bvh, staged, pts, lights, n_lights, desc, S, pt_ids, cl_ids, keys, g, which, stats,
+                                   r_min2, eps, vals);
     }
+    if (rays) add_count(rays, traced);
 }
 
 // Merge errors of the per-slice light coarsening (Sec. 4).  One thread per
@@ -260,7 +274,8 @@ template <bool STAGED>
 __global__ __launch_bounds__(256) void k_coarsen_eps(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
                                                      const SliceDesc *__restrict__ desc, int64_t total, int64_t K,
                                                      const int32_t *__restrict__ pt_ids, CoarsenTree tr,
-                                                     CoarsenSlices cs, uint64_t seed, float r_min2, float eps) {
+                                                     CoarsenSlices cs, uint64_t seed, float r_min2, float eps,
+                                                     unsigned long long *__restrict__ counts) {
     extern __shared__ float4 stage[];
     if (STAGED) {
         const int nn = 2 * bvh.n_nodes, ns = bvh.n_spheres;
@@ -273,6 +288,7 @@ __global__ __launch_bounds__(256) void k_coarsen_eps(Bvh bvh, vplmc_points pts, 
     const size_t N = (size_t)(2 * ng - 1);
     const int64_t kt = cs.kpre[ng];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t n_eval = 0, n_ray = 0;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += stride) {
         const int s = (int)(g / K);
         const int64_t r = g - (int64_t)s * K;
@@ -297,10 +313,13 @@ __global__ __launch_bounds__(256) void k_coarsen_eps(Bvh bvh, vplmc_points pts, 
         cs.zeta[g] = (uint16_t)i;
         const PointData q = load_point(pts, pt_ids[d.pt_off + i]);
         float c0, c1, c2;
+        bool ray;
         if (STAGED)
-            shade_in(staged, bvh.n_nodes, q, node_light(lights, N, x, true), r_min2, eps, c0, c1, c2);
+            ray = shade_in(staged, bvh.n_nodes, q, node_light(lights, N, x, true), r_min2, eps, c0, c1, c2);
         else
-            shade(bvh, q, node_light(lights, N, x, true), r_min2, eps, c0, c1, c2);
+            ray = shade(bvh, q, node_light(lights, N, x, true), r_min2, eps, c0, c1, c2);
+        n_eval += 1;
+        n_ray += ray ? 1u : 0u;
         float *node_eps = cs.eps + (size_t)s * (ng - 1);
         int c = x;
         for (int f = tr.parent[x]; f >= 0; c = f, f = tr.parent[f]) {
@@ -309,9 +328,11 @@ __global__ __launch_bounds__(256) void k_coarsen_eps(Bvh bvh, vplmc_points pts, 
             const int other = c == a ? bb : a;
             float o0, o1, o2;
             if (STAGED)
-                shade_in(staged, bvh.n_nodes, q, node_light(lights, N, other, true), r_min2, eps, o0, o1, o2);
+                ray = shade_in(staged, bvh.n_nodes, q, node_light(lights, N, other, true), r_min2, eps, o0, o1, o2);
             else
-                shade(bvh, q, node_light(lights, N, other, true), r_min2, eps, o0, o1, o2);
+                ray = shade(bvh, q, node_light(lights, N, other, true), r_min2, eps, o0, o1, o2);
+            n_eval += 1;
+            n_ray += ray ? 1u : 0u;
             const bool kept_path = c == a;
             const float a0 = kept_path ? c0 : o0, a1 = kept_path ? c1 : o1, a2 = kept_path ? c2 : o2;
             const float b0 = kept_path ? o0 : c0, b1 = kept_path ? o1 : c1, b2 = kept_path ? o2 : c2;
@@ -326,6 +347,10 @@ __global__ __launch_bounds__(256) void k_coarsen_eps(Bvh bvh, vplmc_points pts, 
             c1 = a1;
             c2 = a2;
         }
+    }
+    if (counts) {
+        add_count(counts, n_eval);
+        add_count(counts + 1, n_ray);
     }
 }
 
@@ -484,7 +509,8 @@ int launch_targets(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc
 int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
                       int32_t n_lights, const SliceDesc *desc, int32_t n_slices, const int32_t *pt_ids,
                       const int32_t *cl_ids, const uint32_t *keys, int64_t n_keys, int which,
-                      const int32_t *stats, const vplmc_params &prm, float *vals, int threads, int n_cu) {
+                      const int32_t *stats, const vplmc_params &prm, float *vals, int threads, int n_cu,
+                      unsigned long long *rays) {
     if (n_keys <= 0) return VPLMC_OK;
     if (threads != 64 && threads != 128 && threads != 256) threads = 256;   // __launch_bounds__(256)
     // enough workgroups to fill the chip several times over; each walks the
@@ -494,18 +520,18 @@ int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, c
     if (bvh.n_nodes > 0 && staged <= (size_t)EVAL_LDS_BYTES)
         hipLaunchKernelGGL(k_eval_omega<true>, dim3((unsigned)blocks), dim3(threads), staged, st, bvh, pts, lights,
                            n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
-                           prm.r_min * prm.r_min, prm.ray_eps, vals);
+                           prm.r_min * prm.r_min, prm.ray_eps, vals, rays);
     else
         hipLaunchKernelGGL(k_eval_omega<false>, dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
                            n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
-                           prm.r_min * prm.r_min, prm.ray_eps, vals);
+                           prm.r_min * prm.r_min, prm.ray_eps, vals, rays);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
 
 int launch_coarsen_eps(hipStream_t st, const vplmc_plan &plan, const Bvh &bvh, const vplmc_points &pts,
                        const float *lights, const SliceDesc *desc, const int32_t *pt_ids, const CoarsenTree &tr,
-                       const CoarsenSlices &cs, const vplmc_params &prm, int n_cu) {
+                       const CoarsenSlices &cs, const vplmc_params &prm, int n_cu, unsigned long long *counts) {
     const int64_t total = (int64_t)plan.n_slices * plan.pixels;
     if (total <= 0) return VPLMC_OK;
     const int threads = 256;
@@ -514,11 +540,11 @@ int launch_coarsen_eps(hipStream_t st, const vplmc_plan &plan, const Bvh &bvh, c
     if (bvh.n_nodes > 0 && staged <= (size_t)EVAL_LDS_BYTES)
         hipLaunchKernelGGL(k_coarsen_eps<true>, dim3((unsigned)blocks), dim3(threads), staged, st, bvh, pts, lights,
                            desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
-                           prm.ray_eps);
+                           prm.ray_eps, counts);
     else
         hipLaunchKernelGGL(k_coarsen_eps<false>, dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
                            desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
-                           prm.ray_eps);
+                           prm.ray_eps, counts);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }

@@ -107,7 +107,9 @@ struct SliceDesc {
     int64_t off_row, off_colptr, off_x, off_y;
     int64_t off_bm, off_bmt;                   // bitmap word offsets (row- and column-major)
     int64_t off_ell, off_red;                  // ELL entry offset; cross-wave reduction scratch (floats)
-    int64_t off_part, pad1;                    // first part slot of the slice
+    int64_t off_part;                          // first part slot of the slice
+    int32_t qr, pad1;                          // qr: the slice's rank; q: the kernels' rank (4, 8, 16 or 32
+                                               // >= qr), the row length of X and Y (components past qr are 0)
 };
 
 // Column-major ELL copy of a slice's samples for the LDS-resident completion.
@@ -181,6 +183,7 @@ enum {
     R_NODE_TOP,      // int32 per (slice, node)
     R_LEAF_COL,      // int32 per (slice, leaf)
     R_ZETA,          // uint16 per (slice, draw slot)
+    R_COUNTS,        // uint64[4]: shadow rays of the entries, coarsening evaluations and rays, -
     R_INTERNAL_END
 };
 
@@ -292,7 +295,7 @@ int launch_node_table(hipStream_t st, const CoarsenTree &tr, const int32_t *cut_
 int launch_leaf_draws(hipStream_t st, int32_t ng, const float *lights, int64_t K, int32_t *quota, int64_t *kpre);
 int launch_coarsen_eps(hipStream_t st, const vplmc_plan &plan, const Bvh &bvh, const vplmc_points &pts,
                        const float *lights, const SliceDesc *desc, const int32_t *pt_ids, const CoarsenTree &tr,
-                       const CoarsenSlices &cs, const vplmc_params &prm, int n_cu);
+                       const CoarsenSlices &cs, const vplmc_params &prm, int n_cu, unsigned long long *counts);
 int launch_coarsen_merge(hipStream_t st, const vplmc_plan &plan, SliceDesc *desc, const CoarsenTree &tr,
                          const CoarsenSlices &cs, int32_t *columns);
 int launch_coarsen_pass1(hipStream_t st, const vplmc_plan &plan, SliceDesc *desc, const CoarsenSlices &cs,
@@ -306,7 +309,8 @@ int launch_pass1(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, 
 int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
                       int32_t n_lights, const SliceDesc *desc, int32_t n_slices, const int32_t *pt_ids,
                       const int32_t *cl_ids, const uint32_t *keys, int64_t n_keys, int which_pass,
-                      const int32_t *stats, const vplmc_params &prm, float *vals, int threads, int n_cu);
+                      const int32_t *stats, const vplmc_params &prm, float *vals, int threads, int n_cu,
+                      unsigned long long *rays);
 int launch_colstats(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *omega1,
                     const float *val1, const uint32_t *bmt, uint16_t *wpret, int32_t *col_ptr, int32_t *csc_row,
                     float *csc_val, int32_t *cnt, float *mn, float *mx, double *sum, double *sumsq, int32_t *zeros);

@@ -2,6 +2,13 @@
 kernels, on lighting matrices the method itself evaluates.
 
     python -m paper_2202_12567_amd.train_proposal --out proposal_mlp.npy
+    python -m paper_2202_12567_amd.train_proposal --config frame --coarsen 32768:512 --rank 16 \
+        --train-scenes 12 --valid-scenes 2 --out proposal_mlp_frame.npy
+
+With --coarsen the training frames coarsen every slice (Sec. 4) and the
+features and targets are those of the coarsened columns: the frame's node
+lights and column ids feed vplmc_proposal_targets through a plan whose
+clusters are the tree's nodes.
 
 For every training scene (seeded, "learned" workload shape: 64x64 points,
 1,024 VPL clusters, 16 slices of 256) one frame is run with the plain
@@ -14,6 +21,7 @@ sample budget, the frame's pixel RMSE against the brute-force sum with the
 plain and the learned proposal.
 """
 import argparse
+import ctypes
 import time
 
 import numpy as np
@@ -42,14 +50,51 @@ def frame_data(ctx, scene, params_plain, device):
     return feats, pstar.clone(), np.asarray(offs, np.int32)
 
 
-def build_dataset(ctx, seeds, cfg="learned", ppm=50000, device="cuda"):
-    from scenegen import make_scene
-    prm = api.default_params(pass1_ppm=ppm, pass2_ppm=ppm, max_iter=0, fixed_iters=True, features=True)
+def frame_data_coarse(ctx, scene, params_plain, coarsen, device):
+    """(features, p*, group offsets) of the coarsened columns of one scene."""
+    import types
+
+    from . import _native as N
+    ds = api.DeviceScene(scene, device)
+    ctx.set_occluders(scene.spheres)
+    plan = api.Plan(scene, params_plain, coarsen)
+    ws = api.workspace(plan, device)
+    api.render(ctx, plan, ds, params_plain, ws)
+    n = api.read_counts(ctx, plan, ws)["n"].astype(np.int64)
+    base = np.array([plan.slice_info(s)["off_col"] for s in range(scene.n_slices)], np.int64)
+    take = torch.as_tensor(np.concatenate([np.arange(b, b + k) for b, k in zip(base, n)]), device=device)
+    feats = api.region_view(plan, ws, "FEATURES", torch.float32).view(-1, 12)[take].clone()
+    cols = api.region_view(plan, ws, "COLUMNS", torch.int32)[take].clone()
+    lights = api.region_view(plan, ws, "LIGHTS", torch.float32).view(9, -1).clone()
+    offs = np.concatenate([[0], np.cumsum(n)]).astype(np.int32)
+    del ws
+    # a plan whose clusters are the tree's nodes and whose columns are the frame's
+    ns = types.SimpleNamespace(n_slices=scene.n_slices, n_clusters=int(lights.shape[1]),
+                               pt_offsets=scene.pt_offsets, cl_offsets=offs, rank=scene.rank)
+    plan_t = api.Plan(ns, params_plain)
+    ws_t = api.workspace(plan_t, device)
+    pstar = torch.empty(int(offs[-1]), dtype=torch.float32, device=device)
+    api.check(N.load().vplmc_proposal_targets(ctx.h, plan_t.h, ctypes.byref(ds.points_c), api._ptr(lights),
+                                              api._ptr(ds.pt_ids), api._ptr(cols), ctypes.byref(params_plain),
+                                              api._ptr(ws_t), ws_t.numel(), api._ptr(pstar)))
+    torch.cuda.synchronize()
+    return feats, pstar, offs
+
+
+def build_dataset(ctx, seeds, cfg="learned", ppm=50000, device="cuda", coarsen=None, rank=None):
+    from scenegen import make_scene, supported_rank
+    prm = api.default_params(pass1_ppm=0 if coarsen else ppm, pass2_ppm=ppm, max_iter=0, fixed_iters=True,
+                             features=True)
     F, Pst, offs = [], [], [0]
     for seed in seeds:
         sc = make_scene(cfg, seed)
+        if rank:
+            sc.rank = supported_rank(rank, np.diff(sc.pt_offsets))
         prm.seed = seed
-        f, p, o = frame_data(ctx, sc, prm, device)
+        if coarsen:
+            f, p, o = frame_data_coarse(ctx, sc, prm, coarsen, device)
+        else:
+            f, p, o = frame_data(ctx, sc, prm, device)
         print(f"scene {seed}: {f.shape[0]} rows", flush=True)
         F.append(f)
         Pst.append(p)
@@ -117,12 +162,19 @@ def main():
     ap.add_argument("--valid-scenes", type=int, default=20)
     ap.add_argument("--batch-groups", type=int, default=128)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--coarsen", default="", help="K:n_max: coarsen every slice with K row draws to n_max columns")
+    ap.add_argument("--rank", type=int, default=0, help="rank of every slice (0: the configuration's)")
     args = ap.parse_args()
     dev = torch.device("cuda", 0)
     ctx = api.Context(0)
     t0 = time.time()
-    F, P, offs = build_dataset(ctx, list(TRAIN_SEEDS)[: args.train_scenes], cfg=args.config, ppm=args.ppm)
-    Fv, Pv, offv = build_dataset(ctx, list(VALID_SEEDS)[: args.valid_scenes], cfg=args.config, ppm=args.ppm)
+    co = None
+    if args.coarsen:
+        k, nmax = (int(v) for v in args.coarsen.split(":"))
+        co = api.Coarsening(k, nmax)
+    kw = dict(cfg=args.config, ppm=args.ppm, coarsen=co, rank=args.rank or None)
+    F, P, offs = build_dataset(ctx, list(TRAIN_SEEDS)[: args.train_scenes], **kw)
+    Fv, Pv, offv = build_dataset(ctx, list(VALID_SEEDS)[: args.valid_scenes], **kw)
     print(f"dataset: {F.shape[0]} rows ({offs.shape[0] - 1} slices), {time.time() - t0:.1f} s", flush=True)
     params, hist = train(ctx, F, P, offs, steps=args.steps, batch_groups=args.batch_groups, lr=args.lr)
     yv = api.mlp_forward(ctx, params, Fv)

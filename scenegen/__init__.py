@@ -345,6 +345,14 @@ def _morton(width, height):
 # entry point
 # ----------------------------------------------------------------------------
 
+def supported_rank(q, limit):
+    """The largest completion rank in {4, 8, 16, 32} that is at most both q and
+    limit (a slice's rows or columns), elementwise; limit below 4 keeps limit."""
+    q = np.minimum(np.asarray(q, np.int64), np.asarray(limit, np.int64))
+    out = np.where(q >= 32, 32, np.where(q >= 16, 16, np.where(q >= 8, 8, np.where(q >= 4, 4, q))))
+    return out.astype(np.int32)
+
+
 def make_scene(cfg, seed, n_vpls=None, n_clusters=None):
     if isinstance(cfg, str):
         cfg = CONFIGS[cfg]
@@ -399,7 +407,7 @@ def make_scene(cfg, seed, n_vpls=None, n_clusters=None):
         else:
             sizes = np.diff(pt_offsets)
             rank = np.where(sizes >= 512, cfg.rank, min(cfg.rank, 16)).astype(np.int32)
-            rank = np.minimum(rank, np.minimum(sizes, nc)).astype(np.int32)
+            rank = supported_rank(rank, np.minimum(sizes, nc))
     else:  # batch: per-slice cuts from one greedy growth sequence
         S = cfg.batch_slices
         lo_m, hi_m = cfg.batch_m

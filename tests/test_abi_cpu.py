@@ -116,7 +116,7 @@ def test_public_region_sizes_follow_their_definitions():
     (([0, 70000], [0, 8], [4]), N.EINVAL, "rows"),
     (([0, 64], [0, 8], [16]), N.EINVAL, "rank"),
     (([0, 64], [0, 64], [33]), N.EINVAL, "rank"),
-    (([0, 64], [0, 64], [12]), N.EUNSUPPORTED, "rank"),
+    (([0, 64], [0, 64], [0]), N.EINVAL, "rank"),
     (([1, 64], [0, 64], [4]), N.EINVAL, "must be 0"),
     (([0, 65535], [0, 65535], [4], 8, dict(pass1_ppm=500000, pass2_ppm=500000)), N.EINVAL, "2^31"),
 ])
@@ -221,3 +221,17 @@ def test_coarse_plan_rejects_bad_arguments():
     assert coarse_plan([0, 100], [8], [0, 2, 4], [1, 3, 5], [3], 4)[0] == N.EINVAL          # q > n_leaves
     assert coarse_plan([0, 100], [4], [], [], [3], 0)[0] == N.EINVAL                        # no leaves
     assert coarse_plan([0, 100], [4], [0, 2, 4], [1, 3, 5], [3], 40000)[0] == N.EINVAL      # too many leaves
+
+
+@pytest.mark.parametrize("q,qp", [(1, 4), (2, 4), (4, 4), (5, 8), (12, 16), (16, 16), (17, 32), (32, 32)])
+def test_any_rank_is_padded_to_a_kernel_rank(q, qp):
+    """Ranks 1..32: X and Y rows are q_pad long (the next of 4, 8, 16, 32)."""
+    lib = N.load()
+    rc, h = plan([0, 64, 128], [0, 64, 128], [q, 4], nc=64)
+    assert rc == 0
+    info = N.SliceInfo()
+    assert lib.vplmc_plan_slice(h, 0, ctypes.byref(info)) == 0
+    assert (info.q, info.q_pad) == (q, qp)
+    assert lib.vplmc_plan_slice(h, 1, ctypes.byref(info)) == 0
+    assert info.off_x == 64 * qp and info.off_y == 3 * 64 * qp
+    lib.vplmc_plan_destroy(h)

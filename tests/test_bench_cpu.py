@@ -50,22 +50,31 @@ def test_digest_follows_code(tree):
 
 
 def test_traffic_record_is_keyed_by_rate_and_source(tree):
-    rec = {"ppm": 25000, "source_sha256": bench.source_digest(), "bytes_per_launch": 123456789}
+    rec = {"ppm": 25000, "source_sha256": bench.source_digest(), "bytes_per_launch": 123456789,
+           "coarsen": "32768:512", "rank": 16}
     path = tree / "profiles" / "k_adm_ell_mid_traffic.json"
-    assert bench.measured_traffic("mid", 25000) is None          # no record
+    for p in (tree / "profiles").glob("k_adm_ell_*_traffic.json"):
+        p.unlink()
+    assert bench.measured_traffic("mid", 25000, "32768:512", 16) is None          # no record
     path.write_text(json.dumps(rec))
-    assert bench.measured_traffic("mid", 25000) == 123456789
-    assert bench.measured_traffic("mid", 2500) is None           # other rate
-    assert bench.measured_traffic("frame", 25000) is None        # other workload
+    assert bench.measured_traffic("mid", 25000, "32768:512", 16) == 123456789
+    assert bench.measured_traffic("mid", 2500, "32768:512", 16) is None           # other rate
+    assert bench.measured_traffic("frame", 25000, "32768:512", 16) is None        # other workload
+    assert bench.measured_traffic("mid", 25000, "none", 0) is None                # other coarsening
+    assert bench.measured_traffic("mid", 25000, "32768:512", 8) is None           # other rank
     edit(tree, "kernels_adm.hip", lambda s: s + "\nconstexpr int UNUSED_FOR_THE_TEST = 1;\n")
-    assert bench.measured_traffic("mid", 25000) is None          # other code
+    assert bench.measured_traffic("mid", 25000, "32768:512", 16) is None          # other code
 
 
-def test_committed_traffic_record_matches_the_committed_kernel():
-    with open(os.path.join(ROOT, "profiles", "k_adm_ell_mid_traffic.json")) as fh:
-        rec = json.load(fh)
-    assert rec["source_sha256"] == bench.source_digest()
-    assert rec["bytes_per_launch"] == rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+def test_committed_traffic_records_match_the_committed_kernel():
+    import glob
+    paths = glob.glob(os.path.join(ROOT, "profiles", "k_adm_ell_*_traffic.json"))
+    assert paths, "the benchmark's traffic record is committed"
+    for path in paths:
+        with open(path) as fh:
+            rec = json.load(fh)
+        assert rec["source_sha256"] == bench.source_digest(), path
+        assert rec["bytes_per_launch"] == rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def test_more_than_one_gpu_exits_with_a_message():

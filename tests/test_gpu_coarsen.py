@@ -221,3 +221,23 @@ def test_mid_frame_coarsened(tmp_path):
     assert np.array_equal(i1, co["i1"]) and np.array_equal(j1, co["j1"])
     log(f"mid: {sc.n_slices} slices coarsened to {int(n.min())}..{int(n.max())} columns, "
         f"first pass {int(run['counts']['N1'].sum())} entries")
+
+
+def test_frame_totals_count_every_evaluation(scene, table, run):
+    """vplmc_read_totals: the sampled entries of both passes, and exactly one
+    coarsening evaluation per drawn row and level, from its leaf to the root
+    (min(m', k_x) draws of leaf x, each walking depth(x) + 1 nodes)."""
+    ng = scene.n_clusters
+    tot = api.read_totals(run["ctx"], run["plan"], run["ws"])
+    assert tot["entries"] == int(run["counts"]["N1"].sum() + run["stats"]["n2"].sum())
+    depth = np.zeros(ng, np.int64)
+    for x in range(ng):
+        y = x
+        while table["parent"][y] >= 0:
+            y = table["parent"][y]
+            depth[x] += 1
+    k = run["r"]["LEAF_DRAWS"].astype(np.int64)
+    want = sum(int((np.minimum(k, info["m"]) * (depth + 1)).sum()) for info in run["info"])
+    assert tot["coarsen_evals"] == want
+    assert 0 < tot["coarsen_rays"] <= tot["coarsen_evals"] and 0 < tot["rays"] <= tot["entries"]
+    log(f"totals: {tot}")

@@ -64,9 +64,9 @@ def slice_view(run, name, s, width=1):
     elif name in ("CSR_COL", "CSC_ROW", "CSR_VAL", "CSC_VAL"):
         a, n = info["off_omega"], info["N1"] + int(run["stats"]["n2"][s])
     elif name == "X":
-        a, n = info["off_x"], info["m"] * info["q"]
+        a, n = info["off_x"], info["m"] * info["q_pad"]
     elif name == "Y":
-        a, n = info["off_y"], 3 * info["n"] * info["q"]
+        a, n = info["off_y"], 3 * info["n"] * info["q_pad"]
     else:
         raise KeyError(name)
     return r[width * a: width * (a + n)]
@@ -334,3 +334,29 @@ def test_all_zero_slice_is_flagged_and_black(scene):
     assert (r["stats"]["flags"] & 1).all()
     assert not np.any(r["radiance"])
     assert not np.any(r["r"]["VAL1"]) and not np.any(r["r"]["VAL2"])
+
+
+def test_ranks_between_the_kernel_ranks(scene):
+    """Ranks 1, 2, 3, 5, 7, 12 and 20 (padded to the kernels' 4, 8, 16, 32 with
+    zero components): the oracle's rank-q ADM on the GPU's samples, 1e-3;
+    rank 20 on a 256-row slice runs the global-memory kernel (rank 32), the
+    others the LDS-resident one."""
+    from scenegen import scene_sample
+    ranks = [1, 2, 3, 5, 7, 12, 20]
+    sub = scene_sample(scene, list(range(len(ranks))))
+    sub.rank = np.asarray(ranks, np.int32)
+    r = run_frame(sub, gpu_params(max_iter=40), label="ranks 1-20")
+    worst = 0.0
+    for s, q in enumerate(ranks):
+        info = r["info"][s]
+        assert info["q"] == q and info["q_pad"] == (4 if q <= 4 else 8 if q <= 8 else 16 if q <= 16 else 32)
+        ii, jj, A = omega_of(r, s)
+        I, *_ = orender.complete_and_render(info["m"], info["n"], q, ii, jj, A.astype(np.float64), SEED, s,
+                                            oracle_params(max_iter=40))
+        rel = orender.relative_rmse(r["radiance"][sub.slice_rows(s)], I)
+        worst = max(worst, rel)
+        assert rel <= 1e-3, f"rank {q}: pixel RMSE {rel:.2e}"
+        # the padded components of X stay exactly zero
+        X = r["r"]["X"][info["off_x"]: info["off_x"] + info["m"] * info["q_pad"]].reshape(info["m"], -1)
+        assert not X[:, q:].any()
+    log(f"ranks {ranks}: worst pixel RMSE vs oracle {worst:.2e}")
