@@ -57,6 +57,8 @@ extern "C" {
 #define VPLMC_FIXED_ITERS 1     /* ignore tol: run exactly max_iter ADM iterations */
 #define VPLMC_LEARNED 2         /* second pass by the learned proposal (vplmc_set_proposal) */
 #define VPLMC_FEATURES 4        /* compute the proposal features even with the plain proposal */
+#define VPLMC_GIVEN_INIT 8      /* ADM starts from the X and Y regions' contents (components past q
+                                   are taken as 0) instead of the seeded draw X0, Y0 (Appendix A) */
 
 /* per-slice result flags (vplmc_read_stats) -- outcomes, not errors */
 #define VPLMC_SLICE_ALL_ZERO 1      /* every sampled entry is 0: radiance 0      */
@@ -433,6 +435,43 @@ int vplmc_mlp_train_step(vplmc_ctx *ctx, float *params, float *m, float *v, int3
 int vplmc_proposal_targets(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points, const float *lights,
                            const int32_t *pt_ids, const int32_t *cl_ids, const vplmc_params *params, void *workspace,
                            size_t workspace_bytes, float *pstar);
+
+/* ---- stage calls: the frame's kernels on inputs the caller places in the
+ * workspace's public regions (parity tests, tools).  Plans without
+ * coarsening only; each validates on the host, synchronises, and returns
+ * VPLMC_EINVAL when a first-pass entry in OMEGA1 lies outside its slice or
+ * repeats within it (nothing further is launched then). -------------------- */
+
+/* Second pass (Sec. 5) of every slice given its first pass (OMEGA1: N1
+ * entries per slice, packed i << 16 | j, any order) and its column weights
+ * (WEIGHTS: uint32 per (slice, column), not all 0): OMEGA2 receives the
+ * accepted entries in acceptance order and vplmc_read_stats their count and
+ * the shortfall flag.  The inclusive prefix of the weights is kept in 64
+ * bits, so any uint32 weights are exact. */
+int vplmc_stage_pass2(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_params *params,
+                      void *workspace, size_t workspace_bytes);
+
+/* Completion (Appendix A) and factorised sum (Sec. 3, step 5) of every slice
+ * from the samples in OMEGA1 / VAL1 (N1 distinct entries per slice with RGB
+ * values; no second pass), with params.max_iter, tol, alpha0, beta0, gamma,
+ * VPLMC_FIXED_ITERS and VPLMC_GIVEN_INIT (then X and Y hold the initial
+ * factors, layouts as the X and Y regions).  Fills X, Y, SLICE_SCALE, the
+ * per-slice stats and radiance float[n_points][3] (0 outside the slices). */
+int vplmc_stage_adm(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_params *params,
+                    const int32_t *pt_ids, int32_t n_points, void *workspace, size_t workspace_bytes,
+                    float *radiance);
+
+/* Factorised column sum I(s) = s0 X (Y e) (Sec. 3, step 5) of every slice
+ * from the X, Y and SLICE_SCALE regions: radiance float[n_points][3]. */
+int vplmc_stage_reduce(vplmc_ctx *ctx, const vplmc_plan *plan, const int32_t *pt_ids, int32_t n_points,
+                       void *workspace, size_t workspace_bytes, float *radiance);
+
+/* Every entry A(i, j) (Sec. 3) of slices [slice_begin, slice_end) of a plan
+ * without coarsening: lights float[9][n_lights] as the LIGHTS region, cl_ids
+ * indexing them; out float[sum m' n'][3], slice after slice, row-major (i, j). */
+int vplmc_full_matrix(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points,
+                      const float *lights, int32_t n_lights, const int32_t *pt_ids, const int32_t *cl_ids,
+                      const vplmc_params *params, int32_t slice_begin, int32_t slice_end, float *out);
 
 /* Philox4x64-10 (Salmon et al., SC'11): out[4k .. 4k+3] =
  * Philox(key, ctr[4k .. 4k+3]); ctr/out DEVICE uint64[4 n]. */

@@ -51,7 +51,7 @@ class SliceInfo(ctypes.Structure):
 
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
-FIXED_ITERS, LEARNED, FEATURES = 1, 2, 4
+FIXED_ITERS, LEARNED, FEATURES, GIVEN_INIT = 1, 2, 4, 8
 SLICE_ALL_ZERO, SLICE_NOT_CONVERGED, SLICE_SHORTFALL, SLICE_FALLBACK = 1, 2, 4, 8
 REGIONS = ["LIGHTS", "REP", "BBOX", "OMEGA1", "VAL1", "OMEGA2", "VAL2", "WEIGHTS", "COLMIN", "COLMAX",
            "COLCNT", "ROW_PTR", "CSR_COL", "CSR_VAL", "COL_PTR", "CSC_ROW", "CSC_VAL", "X", "Y", "SLICE_SCALE",
@@ -91,6 +91,10 @@ SIG = {
     "vplmc_brute_force": (I32, [P, ctypes.POINTER(Points), ctypes.POINTER(Lights), I32, P,
                                 ctypes.POINTER(Params), P]),
     "vplmc_philox4x64": (I32, [P, U64, U64, P, I64, P]),
+    "vplmc_stage_pass2": (I32, [P, P, ctypes.POINTER(Params), P, ctypes.c_size_t]),
+    "vplmc_stage_adm": (I32, [P, P, ctypes.POINTER(Params), P, I32, P, ctypes.c_size_t, P]),
+    "vplmc_stage_reduce": (I32, [P, P, P, I32, P, ctypes.c_size_t, P]),
+    "vplmc_full_matrix": (I32, [P, P, ctypes.POINTER(Points), P, I32, P, P, ctypes.POINTER(Params), I32, I32, P]),
     "vplmc_mlp_param_count": (I32, []),
     "vplmc_set_proposal": (I32, [P, P]),
     "vplmc_mlp_forward": (I32, [P, P, I64, P, P]),

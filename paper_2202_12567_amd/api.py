@@ -23,7 +23,7 @@ def version():
     return N.load().vplmc_version()
 
 
-def default_params(fixed_iters=None, learned=None, features=None, **kw):
+def default_params(fixed_iters=None, learned=None, features=None, given_init=None, **kw):
     """vplmc_default_params with overrides; booleans toggle the flag bits."""
     p = N.Params()
     check(N.load().vplmc_default_params(ctypes.byref(p)))
@@ -31,7 +31,8 @@ def default_params(fixed_iters=None, learned=None, features=None, **kw):
         if not hasattr(p, k):
             raise AttributeError(k)
         setattr(p, k, v)
-    for bit, on in ((N.FIXED_ITERS, fixed_iters), (N.LEARNED, learned), (N.FEATURES, features)):
+    for bit, on in ((N.FIXED_ITERS, fixed_iters), (N.LEARNED, learned), (N.FEATURES, features),
+                    (N.GIVEN_INIT, given_init)):
         if on is not None:
             p.flags = (p.flags | bit) if on else (p.flags & ~bit)
     return p
@@ -256,6 +257,42 @@ def brute_force(ctx, ds, lights, params, point_ids=None, n_out=None):
     L = lights_struct(lights)
     check(N.load().vplmc_brute_force(ctx.h, ctypes.byref(ds.points_c), ctypes.byref(L), n_out,
                                      _ptr(point_ids), ctypes.byref(params), _ptr(out)))
+    return out
+
+
+# ---- stage calls -----------------------------------------------------------
+
+def stage_pass2(ctx, plan, params, ws):
+    """vplmc_stage_pass2: second pass from OMEGA1 and WEIGHTS (already in ws)."""
+    check(N.load().vplmc_stage_pass2(ctx.h, plan.h, ctypes.byref(params), _ptr(ws), ws.numel()))
+
+
+def stage_adm(ctx, plan, params, ds_or_pt_ids, ws, n_points=None, radiance=None):
+    """vplmc_stage_adm: completion + sum from OMEGA1/VAL1 (already in ws)."""
+    pt_ids = ds_or_pt_ids.pt_ids if hasattr(ds_or_pt_ids, "pt_ids") else ds_or_pt_ids
+    n_points = ds_or_pt_ids.m if n_points is None else n_points
+    if radiance is None:
+        radiance = torch.empty((n_points, 3), dtype=torch.float32, device=ws.device)
+    check(N.load().vplmc_stage_adm(ctx.h, plan.h, ctypes.byref(params), _ptr(pt_ids), int(n_points), _ptr(ws),
+                                   ws.numel(), _ptr(radiance)))
+    return radiance
+
+
+def stage_reduce(ctx, plan, pt_ids, n_points, ws):
+    radiance = torch.empty((n_points, 3), dtype=torch.float32, device=ws.device)
+    check(N.load().vplmc_stage_reduce(ctx.h, plan.h, _ptr(pt_ids), int(n_points), _ptr(ws), ws.numel(),
+                                      _ptr(radiance)))
+    return radiance
+
+
+def full_matrix(ctx, plan, ds, lights, params, slice_begin, slice_end, cl_ids=None):
+    """Every entry of slices [slice_begin, slice_end): float32 [sum m'n', 3]."""
+    cl = ds.cl_ids if cl_ids is None else cl_ids
+    total = sum(plan.slice_info(s)["m"] * plan.slice_info(s)["n"] for s in range(slice_begin, slice_end))
+    out = torch.empty((total, 3), dtype=torch.float32, device=ds.pt_ids.device)
+    check(N.load().vplmc_full_matrix(ctx.h, plan.h, ctypes.byref(ds.points_c), _ptr(lights), int(lights.shape[-1]),
+                                     _ptr(ds.pt_ids), _ptr(cl), ctypes.byref(params), int(slice_begin),
+                                     int(slice_end), _ptr(out)))
     return out
 
 

@@ -83,7 +83,7 @@ int check_params(const vplmc_params *p) {
         return set_error(VPLMC_EINVAL, "gamma must be in (0, 1.618) (got %g)", (double)p->gamma);
     if (!(p->tol >= 0.f)) return set_error(VPLMC_EINVAL, "tol must be >= 0");
     if (!(p->r_min > 0.f) || !(p->ray_eps >= 0.f)) return set_error(VPLMC_EINVAL, "r_min must be > 0, ray_eps >= 0");
-    if (p->flags & ~(VPLMC_FIXED_ITERS | VPLMC_LEARNED | VPLMC_FEATURES))
+    if (p->flags & ~(VPLMC_FIXED_ITERS | VPLMC_LEARNED | VPLMC_FEATURES | VPLMC_GIVEN_INIT))
         return set_error(VPLMC_EINVAL, "unknown flags 0x%x", p->flags);
     return VPLMC_OK;
 }
@@ -1013,6 +1013,160 @@ int vplmc_read_counts(vplmc_ctx *ctx, const vplmc_plan *plan, const void *worksp
         if (n) n[s] = h[s].n;
         if (N1) N1[s] = h[s].N1;
         if (N2) N2[s] = h[s].N2;
+    }
+    return VPLMC_OK;
+}
+
+// ---- stage calls: the frame's kernels on inputs placed in the workspace ----
+
+namespace {
+
+// validates a stage call's common arguments and uploads the slice table
+int stage_setup(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_params *params, void *ws, size_t bytes) {
+    if (!ctx || !plan || !params || !ws) return set_error(VPLMC_EINVAL, "ctx, plan, params and workspace must be non-NULL");
+    if (plan->coarse) return set_error(VPLMC_EUNSUPPORTED, "stage calls take plans without coarsening");
+    int rc = check_params(params);
+    if (rc) return rc;
+    if (bytes < plan->layout.total) return set_error(VPLMC_EINVAL, "workspace smaller than vplmc_workspace_size");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return set_error(VPLMC_EINVAL, "workspace must be 256-byte aligned");
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    if (plan->n_slices > 0)
+        VPLMC_HIP(hipMemcpyAsync(region<char>(ws, plan, R_DESC), plan->upload.data(), plan->upload.size(),
+                                 hipMemcpyHostToDevice, ctx->stream));
+    return VPLMC_OK;
+}
+
+// occupancy bitmaps from the first-pass keys in OMEGA1; EINVAL if a key lies
+// outside its slice or repeats (synchronises)
+int stage_bitmaps(vplmc_ctx *ctx, const vplmc_plan *plan, void *ws) {
+    hipStream_t st = ctx->stream;
+    uint32_t *bm = region<uint32_t>(ws, plan, R_BITMAP);
+    uint32_t *bmt = region<uint32_t>(ws, plan, R_BITMAPT);
+    unsigned long long *bad = region<unsigned long long>(ws, plan, R_COUNTS);
+    int rc;
+    if ((rc = launch_fill_u32(st, bm, plan->tot_bm, 0u))) return rc;
+    if ((rc = launch_fill_u32(st, bmt, plan->tot_bmt, 0u))) return rc;
+    if ((rc = launch_fill_u32(st, region<uint32_t>(ws, plan, R_SLICE_STATS), 4 * (size_t)plan->n_slices, 0u))) return rc;
+    if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(bad), 8, 0u))) return rc;
+    if ((rc = launch_keys_bitmap(st, *plan, region<SliceDesc>(ws, plan, R_DESC),
+                                 region<uint32_t>(ws, plan, VPLMC_R_OMEGA1), bm, bmt, bad)))
+        return rc;
+    unsigned long long h = 0;
+    VPLMC_HIP(hipMemcpyAsync(&h, bad, sizeof(h), hipMemcpyDeviceToHost, st));
+    VPLMC_HIP(hipStreamSynchronize(st));
+    if (h) return set_error(VPLMC_EINVAL, "%llu first-pass entries lie outside their slice or repeat", h);
+    return VPLMC_OK;
+}
+
+}  // namespace
+
+int vplmc_stage_pass2(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_params *params, void *workspace,
+                      size_t workspace_bytes) {
+    int rc = stage_setup(ctx, plan, params, workspace, workspace_bytes);
+    if (rc) return rc;
+    if (params->pass2_ppm != plan->pass2_ppm) return set_error(VPLMC_EINVAL, "params rates differ from the plan's");
+    if ((rc = stage_bitmaps(ctx, plan, workspace))) return rc;
+    hipStream_t st = ctx->stream;
+    SliceDesc *desc = region<SliceDesc>(workspace, plan, R_DESC);
+    uint64_t *prefix = region<uint64_t>(workspace, plan, R_COLW_PREFIX);
+    if ((rc = launch_prefix_given(st, *plan, desc, region<uint32_t>(workspace, plan, VPLMC_R_WEIGHTS), prefix)))
+        return rc;
+    if ((rc = launch_pass2(st, *plan, desc, params->seed, prefix, region<uint32_t>(workspace, plan, R_BITMAP),
+                           region<uint32_t>(workspace, plan, R_BITMAPT), region<uint32_t>(workspace, plan, VPLMC_R_OMEGA2),
+                           region<int32_t>(workspace, plan, R_SLICE_STATS))))
+        return rc;
+    VPLMC_HIP(hipStreamSynchronize(st));
+    return VPLMC_OK;
+}
+
+int vplmc_stage_adm(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_params *params, const int32_t *pt_ids,
+                    int32_t n_points, void *workspace, size_t workspace_bytes, float *radiance) {
+    int rc = stage_setup(ctx, plan, params, workspace, workspace_bytes);
+    if (rc) return rc;
+    if (!radiance || (plan->n_slices > 0 && !pt_ids)) return set_error(VPLMC_EINVAL, "radiance and pt_ids must be non-NULL");
+    if (n_points < plan->sum_m) return set_error(VPLMC_EINVAL, "slices hold more rows than there are points");
+    if ((rc = stage_bitmaps(ctx, plan, workspace))) return rc;
+    hipStream_t st = ctx->stream;
+    void *ws = workspace;
+    SliceDesc *desc = region<SliceDesc>(ws, plan, R_DESC);
+    const int32_t *ids = reinterpret_cast<const int32_t *>(desc + plan->n_slices);
+    EllView ell;
+    ell.part = region<int2>(ws, plan, R_ELL_PART);
+    ell.ppos = region<int32_t>(ws, plan, R_ELL_PPOS);
+    ell.pbase = region<int32_t>(ws, plan, R_ELL_PBASE);
+    ell.partial = region<float>(ws, plan, R_ELL_PARTIAL);
+    ell.grp = region<int32_t>(ws, plan, R_ELL_GRP);
+    ell.split = region<int32_t>(ws, plan, R_ELL_SPLIT);
+    ell.nsplit = region<int32_t>(ws, plan, R_ELL_NSPLIT);
+    ell.row = plan->tot_ell > 0 ? region<uint16_t>(ws, plan, R_ELL_ROW) : nullptr;
+    ell.val = region<float>(ws, plan, R_ELL_VAL);
+    ell.res = region<float>(ws, plan, R_ELL_RES);
+    int32_t *stats = region<int32_t>(ws, plan, R_SLICE_STATS);
+    int32_t *row_ptr = region<int32_t>(ws, plan, VPLMC_R_ROW_PTR);
+    int32_t *col_ptr = region<int32_t>(ws, plan, VPLMC_R_COL_PTR);
+    int32_t *csr_col = region<int32_t>(ws, plan, VPLMC_R_CSR_COL);
+    float *csr_val = region<float>(ws, plan, VPLMC_R_CSR_VAL);
+    int32_t *csc_row = region<int32_t>(ws, plan, VPLMC_R_CSC_ROW);
+    float *csc_val = region<float>(ws, plan, VPLMC_R_CSC_VAL);
+    // the second pass is empty (accepted count 0 from the cleared stats)
+    if ((rc = launch_sort(st, *plan, desc, region<uint32_t>(ws, plan, R_BITMAP), region<uint32_t>(ws, plan, R_BITMAPT),
+                          region<uint16_t>(ws, plan, R_WPRE), region<uint16_t>(ws, plan, R_WPRET), row_ptr, col_ptr,
+                          region<uint32_t>(ws, plan, VPLMC_R_OMEGA1), region<float>(ws, plan, VPLMC_R_VAL1),
+                          region<uint32_t>(ws, plan, VPLMC_R_OMEGA2), region<float>(ws, plan, VPLMC_R_VAL2), stats,
+                          csr_col, csr_val, csc_row, csc_val, ell)))
+        return rc;
+    float *X = region<float>(ws, plan, VPLMC_R_X);
+    float *Y = region<float>(ws, plan, VPLMC_R_Y);
+    float *scale = region<float>(ws, plan, VPLMC_R_SLICE_SCALE);
+    if ((rc = launch_adm(st, &ctx->adm, *plan, ctx->n_cu, desc, ids, region<int32_t>(ws, plan, R_QUEUE), *params, row_ptr,
+                         csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X, region<float>(ws, plan, R_XNEXT),
+                         region<float>(ws, plan, R_XP), region<float>(ws, plan, R_LAMBDA), Y, region<float>(ws, plan, R_YP),
+                         region<float>(ws, plan, R_PI), region<float>(ws, plan, R_YT),
+                         region<float>(ws, plan, R_ADM_RED), region<double>(ws, plan, R_E2PART), scale, stats)))
+        return rc;
+    if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(radiance), 3 * (size_t)n_points, 0u))) return rc;
+    if ((rc = launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, n_points, radiance))) return rc;
+    VPLMC_HIP(hipStreamSynchronize(st));
+    return VPLMC_OK;
+}
+
+int vplmc_stage_reduce(vplmc_ctx *ctx, const vplmc_plan *plan, const int32_t *pt_ids, int32_t n_points,
+                       void *workspace, size_t workspace_bytes, float *radiance) {
+    vplmc_params p;
+    vplmc_default_params(&p);
+    p.pass1_ppm = plan ? plan->pass1_ppm : 0;
+    p.pass2_ppm = plan ? plan->pass2_ppm : 0;
+    int rc = stage_setup(ctx, plan, &p, workspace, workspace_bytes);
+    if (rc) return rc;
+    if (!radiance || (plan->n_slices > 0 && !pt_ids)) return set_error(VPLMC_EINVAL, "radiance and pt_ids must be non-NULL");
+    if (n_points < plan->sum_m) return set_error(VPLMC_EINVAL, "slices hold more rows than there are points");
+    hipStream_t st = ctx->stream;
+    if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(radiance), 3 * (size_t)n_points, 0u))) return rc;
+    return launch_reduce(st, *plan, region<SliceDesc>(workspace, plan, R_DESC), pt_ids,
+                         region<float>(workspace, plan, VPLMC_R_X), region<float>(workspace, plan, VPLMC_R_Y),
+                         region<float>(workspace, plan, VPLMC_R_SLICE_SCALE), n_points, radiance);
+}
+
+int vplmc_full_matrix(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *points, const float *lights,
+                      int32_t n_lights, const int32_t *pt_ids, const int32_t *cl_ids, const vplmc_params *params,
+                      int32_t slice_begin, int32_t slice_end, float *out) {
+    if (!ctx || !plan || !points || !lights || !params || !out) return set_error(VPLMC_EINVAL, "NULL argument");
+    if (plan->coarse) return set_error(VPLMC_EUNSUPPORTED, "full matrices need a plan with fixed cluster columns");
+    if (bad_ptrs_points(points)) return set_error(VPLMC_EINVAL, "incomplete points arrays");
+    if (n_lights < 1) return set_error(VPLMC_EINVAL, "n_lights must be >= 1");
+    if (slice_begin < 0 || slice_end > plan->n_slices || slice_begin > slice_end)
+        return set_error(VPLMC_EINVAL, "slice range [%d, %d) outside [0, %d]", slice_begin, slice_end, plan->n_slices);
+    if (slice_end > slice_begin && (!pt_ids || !cl_ids)) return set_error(VPLMC_EINVAL, "pt_ids and cl_ids must be non-NULL");
+    int rc = check_params(params);
+    if (rc) return rc;
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    int64_t o = 0;
+    for (int s = slice_begin; s < slice_end; ++s) {
+        const SliceDesc &d = plan->desc[s];
+        if ((rc = launch_full_matrix(ctx->stream, ctx->bvh, *points, lights, n_lights, d.m, d.n, pt_ids + d.pt_off,
+                                     cl_ids + d.cl_off, *params, out + 3 * o)))
+            return rc;
+        o += (int64_t)d.m * d.n;
     }
     return VPLMC_OK;
 }

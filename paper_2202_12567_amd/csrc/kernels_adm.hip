@@ -269,12 +269,14 @@ __device__ void adm_global_slice(
     const double normM = sqrt(totsq) / s0;
     if (t == 0) scale_all[s] = (float)s0;
 
-    // ---- initial factors: fp32(u24(Philox) * fp32(2 / sqrt q)) ----
+    // ---- initial factors: fp32(u24(Philox) * fp32(2 / sqrt q)), or (mode bit 1)
+    // the contents of the X and Y regions ----
     const float cq = (float)(2.0 / sqrt((double)qr));
+    const bool given = (fixed_iters & 2) != 0;
     for (int e = t; e < m * Q; e += THREADS) {
         const int i = e / Q, k = e % Q;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
-        const float v = k < qr ? __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq) : 0.f;
+        const float v = k < qr ? (given ? Xa[e] : __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq)) : 0.f;
         Xa[e] = v;
         Xp[e] = v;
         Lam[e] = 0.f;
@@ -283,7 +285,7 @@ __device__ void adm_global_slice(
         const int j = e / (3 * Q), c = (e / Q) % 3, k = e % Q;
         const uint64_t col = (uint64_t)c * (uint64_t)n + (uint64_t)j;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)k, col, TAG_INITY, 0);
-        const float v = k < qr ? __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq) : 0.f;
+        const float v = k < qr ? (given ? Y[e] : __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq)) : 0.f;
         Y[e] = v;
         Yp[e] = v;
         Pi[e] = 0.f;
@@ -434,7 +436,7 @@ __device__ void adm_global_slice(
             sh.C[e] = v;
         }
         __syncthreads();
-        if (!fixed_iters && err < (double)tol) {
+        if (!(fixed_iters & 1) && err < (double)tol) {
             iters = it;
             break;
         }
@@ -692,7 +694,7 @@ __device__ void adm_global_slice(
     }
     if (t == 0) {
         st[0] = iters;
-        if (!fixed_iters && iters >= max_iter) st[1] |= VPLMC_SLICE_NOT_CONVERGED;
+        if (!(fixed_iters & 1) && iters >= max_iter) st[1] |= VPLMC_SLICE_NOT_CONVERGED;
         st[2] = __float_as_int((float)err);
     }
 }
@@ -917,12 +919,14 @@ __device__ void adm_ell_slice(
     const double normM = sqrt(totsq) / s0;
     if (t == 0) scale_all[s] = (float)s0;
 
-    // ---- initial factors: fp32(u24(Philox) * fp32(2 / sqrt q)) ----
+    // ---- initial factors: fp32(u24(Philox) * fp32(2 / sqrt q)), or (mode bit 1)
+    // the contents of the X and Y regions ----
     const float cq = (float)(2.0 / sqrt((double)qr));
+    const bool given = (fixed_iters & 2) != 0;
     for (int e = t; e < m * Q; e += THREADS) {
         const int i = e / Q, k = e % Q;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
-        const float v = k < qr ? __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq) : 0.f;
+        const float v = k < qr ? (given ? Xg[e] : __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq)) : 0.f;
         XA[xpos<Q>(i, k)] = v;
         Xp[e] = v;
         Lam[e] = 0.f;
@@ -933,7 +937,7 @@ __device__ void adm_ell_slice(
         const int j = e / (3 * Q), c = (e / Q) % 3, k = e % Q;
         const uint64_t col = (uint64_t)c * (uint64_t)n + (uint64_t)j;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)k, col, TAG_INITY, 0);
-        const float v = k < qr ? __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq) : 0.f;
+        const float v = k < qr ? (given ? Y[e] : __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq)) : 0.f;
         Y[e] = v;
         W[e] = __fmul_rn(beta0_f, v);                 // b V_0 - P_0 with V_0 = Y_0, P_0 = 0
         Pi[e] = 0.f;
@@ -1180,7 +1184,7 @@ __device__ void adm_ell_slice(
         rs_est = 2.0 * (double)rsc;
         RS_est = 2.0 * RSc;
         err = sqrt(e2t) / normM;
-        if (!fixed_iters && err < (double)tol) {
+        if (!(fixed_iters & 1) && err < (double)tol) {
             iters = it;
             break;
         }
@@ -1442,7 +1446,7 @@ __device__ void adm_ell_slice(
     for (int e = t; e < m * Q; e += THREADS) Xg[e] = XA[xpos<Q>(e / Q, e % Q)];
     if (t == 0) {
         st[0] = iters;
-        if (!fixed_iters && iters >= max_iter) st[1] |= VPLMC_SLICE_NOT_CONVERGED;
+        if (!(fixed_iters & 1) && iters >= max_iter) st[1] |= VPLMC_SLICE_NOT_CONVERGED;
         st[2] = __float_as_int((float)err);
     }
 }
@@ -1545,6 +1549,12 @@ __global__ __launch_bounds__(256) void k_reduce(const SliceDesc *__restrict__ de
     }
 }
 
+// mode word of the completion kernels: bit 0 a fixed iteration count, bit 1
+// initial factors given in the X and Y regions
+inline int32_t adm_mode(const vplmc_params &prm) {
+    return ((prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0) | ((prm.flags & VPLMC_GIVEN_INIT) ? 2 : 0);
+}
+
 // grid of a launch over `count` slices: one workgroup per slice, or with a
 // queue as many workgroups as fit on the device at once (at most count)
 template <typename K>
@@ -1571,7 +1581,7 @@ int launch_adm_global(hipStream_t st, size_t count, const int32_t *ids_dev, int3
     if ((rc = adm_grid(kern, THREADS, 0, n_cu, queue != nullptr, count, grid))) return rc;
     if (queue && (rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(queue), 1, 0u))) return rc;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(THREADS), 0, st, desc, ids_dev, (int32_t)count, queue, prm.seed,
-                       prm.max_iter, (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0,
+                       prm.max_iter, adm_mode(prm), prm.tol, prm.alpha0, prm.beta0,
                        prm.gamma, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi,
                        scale, stats);
     VPLMC_HIP(hipGetLastError());
@@ -1592,7 +1602,7 @@ int launch_adm_ell_t(hipStream_t st, size_t count, int max_m, const int32_t *ids
     if ((rc = adm_grid(kern, T, dyn, n_cu, queue != nullptr, count, grid))) return rc;
     if (queue && (rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(queue), 1, 0u))) return rc;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(T), dyn, st, desc, ids_dev, (int32_t)count, queue, prm.seed,
-                       prm.max_iter, (prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0, prm.tol, prm.alpha0, prm.beta0,
+                       prm.max_iter, adm_mode(prm), prm.tol, prm.alpha0, prm.beta0,
                        prm.gamma, col_ptr, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale,
                        stats);
     VPLMC_HIP(hipGetLastError());

@@ -354,6 +354,28 @@ __global__ __launch_bounds__(256) void k_coarsen_eps(Bvh bvh, vplmc_points pts, 
     }
 }
 
+// every entry of one slice, row-major: out[(i n + j) 3 + c]
+__global__ __launch_bounds__(256) void k_full_matrix(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
+                                                     int32_t n_lights, int32_t m, int32_t n,
+                                                     const int32_t *__restrict__ pt_ids,
+                                                     const int32_t *__restrict__ cl_ids, float r_min2, float eps,
+                                                     float *__restrict__ out) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= (int64_t)m * n) return;
+    const int i = (int)(g / n), j = (int)(g % n);
+    const int c = clamp_index(cl_ids[j], n_lights);
+    const size_t N = (size_t)n_lights;
+    const Light L = {{lights[c], lights[N + c], lights[2 * N + c]},
+                     {lights[3 * N + c], lights[4 * N + c], lights[5 * N + c]},
+                     lights[6 * N + c], lights[7 * N + c], lights[8 * N + c]};
+    const PointData q = load_point(pts, pt_ids[i]);
+    float o0, o1, o2;
+    shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+    out[3 * g] = o0;
+    out[3 * g + 1] = o1;
+    out[3 * g + 2] = o2;
+}
+
 __global__ __launch_bounds__(256) void k_eval_pairs(Bvh bvh, vplmc_points pts, vplmc_lights l, int64_t n,
                                                     const int32_t *__restrict__ pid,
                                                     const int32_t *__restrict__ lid, float r_min2, float eps,
@@ -545,6 +567,17 @@ int launch_coarsen_eps(hipStream_t st, const vplmc_plan &plan, const Bvh &bvh, c
         hipLaunchKernelGGL(k_coarsen_eps<false>, dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
                            desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
                            prm.ray_eps, counts);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_full_matrix(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
+                       int32_t n_lights, int32_t m, int32_t n, const int32_t *pt_ids, const int32_t *cl_ids,
+                       const vplmc_params &prm, float *out) {
+    const int64_t total = (int64_t)m * n;
+    if (total <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_full_matrix, dim3(blocks_for(total, 256)), dim3(256), 0, st, bvh, pts, lights, n_lights, m, n,
+                       pt_ids, cl_ids, prm.r_min * prm.r_min, prm.ray_eps, out);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }

@@ -647,9 +647,81 @@ __global__ __launch_bounds__(1024) void k_partsort(const SliceDesc *__restrict__
     if (t == 0) grp[G] = (int32_t)carry;
 }
 
+// First-pass entries given by a caller (stage calls): each key of slice s
+// (k < N1) sets its bit in both occupancy bitmaps; a key outside the slice, or
+// one already set, is counted in *bad and sets nothing.
+__global__ void k_keys_bitmap(const SliceDesc *__restrict__ desc, int S, int64_t total,
+                              const uint32_t *__restrict__ keys, uint32_t *bm, uint32_t *bmt,
+                              unsigned long long *bad) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int s = slice_of(desc, S, g, 0);
+    const SliceDesc d = desc[s];
+    if (g - d.off1 >= d.N1) return;
+    const uint32_t key = keys[g];
+    const uint32_t i = key >> 16, j = key & 0xFFFFu;
+    if ((int)i >= d.m || (int)j >= d.n) {
+        atomicAdd(bad, 1ull);
+        return;
+    }
+    const uint32_t old = atomicOr(bm + d.off_bm + (int64_t)i * d.words_row + (j >> 5), 1u << (j & 31));
+    if (old & (1u << (j & 31))) {
+        atomicAdd(bad, 1ull);
+        return;
+    }
+    atomicOr(bmt + d.off_bmt + (int64_t)j * d.words_col + (i >> 5), 1u << (i & 31));
+}
+
+// inclusive uint64 prefix of given column weights, one block per slice
+__global__ __launch_bounds__(256) void k_prefix_given(const SliceDesc *__restrict__ desc, const uint32_t *w,
+                                                      uint64_t *prefix) {
+    __shared__ uint64_t carry_s;
+    __shared__ uint64_t wsum[4];
+    const int s = blockIdx.x, t = threadIdx.x;
+    const SliceDesc d = desc[s];
+    if (t == 0) carry_s = 0;
+    __syncthreads();
+    for (int j0 = 0; j0 < d.n; j0 += 256) {
+        const int j = j0 + t;
+        // weights may be anything up to 2^32 - 1 here: the block sum is kept in 64 bits
+        const uint64_t wj = j < d.n ? (uint64_t)w[d.off_col + j] : 0ull;
+        uint64_t incl = wj;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint64_t u = __shfl_up(incl, o, WAVE);
+            if ((t % WAVE) >= o) incl += u;
+        }
+        if (t % WAVE == WAVE - 1) wsum[t / WAVE] = incl;
+        __syncthreads();
+        uint64_t base = carry_s;
+        for (int k = 0; k < t / WAVE; ++k) base += wsum[k];
+        if (j < d.n) prefix[d.off_col + j] = base + incl;
+        __syncthreads();
+        if (t == 255) carry_s = base + incl;
+        __syncthreads();
+    }
+}
+
 unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 }  // namespace
+
+int launch_keys_bitmap(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *keys,
+                       uint32_t *bm, uint32_t *bmt, unsigned long long *bad) {
+    if (plan.tot1 <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_keys_bitmap, dim3(blocks_for(plan.tot1, 256)), dim3(256), 0, st, desc, plan.n_slices,
+                       plan.tot1, keys, bm, bmt, bad);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+int launch_prefix_given(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *w,
+                        uint64_t *prefix) {
+    if (plan.n_slices <= 0) return VPLMC_OK;
+    hipLaunchKernelGGL(k_prefix_given, dim3(plan.n_slices), dim3(256), 0, st, desc, w, prefix);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
 
 int launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v) {
     if (n == 0) return VPLMC_OK;

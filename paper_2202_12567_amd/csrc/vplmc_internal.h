@@ -350,6 +350,13 @@ int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int
                float *Yt, float *red, double *e2part, float *scale, int32_t *stats);
 int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,
                   const float *X, const float *Y, const float *scale, int32_t n_points, float *radiance);
+int launch_keys_bitmap(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *keys,
+                       uint32_t *bm, uint32_t *bmt, unsigned long long *bad);
+int launch_prefix_given(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *w,
+                        uint64_t *prefix);
+int launch_full_matrix(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const float *lights,
+                       int32_t n_lights, int32_t m, int32_t n, const int32_t *pt_ids, const int32_t *cl_ids,
+                       const vplmc_params &prm, float *out);
 int launch_eval_pairs(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,
                       int64_t n, const int32_t *pid, const int32_t *lid, const vplmc_params &prm, float *out);
 int launch_brute_force(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,

@@ -128,7 +128,7 @@ def test_plan_rejects_bad_shapes(args, code, needle):
 
 
 @pytest.mark.parametrize("kw", [dict(pass1_ppm=-1), dict(pass1_ppm=600000, pass2_ppm=500000),
-                                dict(gamma=1.7), dict(alpha0=0.0), dict(max_iter=-1), dict(flags=8)])
+                                dict(gamma=1.7), dict(alpha0=0.0), dict(max_iter=-1), dict(flags=16)])
 def test_plan_rejects_bad_params(kw):
     rc, _ = plan([0, 64], [0, 64], [4], **kw)
     assert rc == N.EINVAL
