@@ -20,7 +20,10 @@ in its own order and notation and cites the passage it implements:
                    first pass its pixel draws give (Sec. 5).
 * ``sampling``  -- first uniform pass, importance g(j) = max C_j - min C_j and
                    the second pass (Sec. 5, Eq. pdf).
-* ``adm``       -- non-negative completion by ADM (Appendix A).
+* ``adm``       -- non-negative completion by ADM (Appendix A), and the same
+                   iteration with the non-negativity switched off.
+* ``als``       -- per-row masked ALS with weighted regularisation, a
+                   completion variant compared with the ADM on equal terms.
 * ``render``    -- I(s) = X (Y e) (Sec. 3, step 5), the whole frame, and the
                    brute-force column sum the method approximates.
 * ``mlp``       -- the learned second-pass proposal (motivated by the

@@ -30,9 +30,19 @@ beta = beta0 m / q, gamma = 1.6; the initial factors are Philox draws
 (``init_factors``) with E[(X0 Y0)_ij] = 1, M scaled to unit mean on Omega; U0 = X0,
 V0 = Y0, Lambda0 = Pi0 = 0; Z0 = X0 Y0 + P_Omega(M - X0 Y0).
 
+Non-negativity switch (a completion variant; the paper uses the
+non-negative form): with nonneg off, U+ = X+ + Lambda / alpha and
+V+ = Y+ + Pi / beta (no projection), so Lambda and Pi stay 0 and U = X+,
+V = Y+: each half-step is then the proximal least-squares update
+X+ = argmin ||Z - X Y||^2 + alpha ||X - X_k||^2.
+
 Pinned by: the sparse form against the dense transcription, recovery of
 planted non-negative rank-r matrices, exact data reproduction at 100%
-sampling, and the KKT conditions at convergence (tests/test_oracle_adm.py).
+sampling, and the KKT conditions at convergence; with nonneg off, one step
+against the proximal least-squares problem solved by QR (numpy lstsq on the
+stacked system [Y^T; sqrt(alpha) I]) and recovery of a planted matrix with
+negative entries that the non-negative form cannot fit
+(tests/test_oracle_adm.py, tests/test_oracle_als.py).
 """
 import numpy as np
 import scipy.linalg
@@ -66,7 +76,7 @@ def residual(rows, cols, mvals, X, Y):
     return mvals - np.einsum("ek,ke->e", X[rows], Y[:, cols])
 
 
-def adm_step(rows, cols, mvals, m, N, X, Y, U, V, Lam, Pi, alpha, beta, gamma, Rv=None):
+def adm_step(rows, cols, mvals, m, N, X, Y, U, V, Lam, Pi, alpha, beta, gamma, Rv=None, nonneg=True):
     """One iteration in sparse-residual form; returns (X+, Y+, U+, V+, Lambda+, Pi+)."""
     q = X.shape[1]
     Iq = np.eye(q)
@@ -81,14 +91,17 @@ def adm_step(rows, cols, mvals, m, N, X, Y, U, V, Lam, Pi, alpha, beta, gamma, R
     cX = scipy.linalg.cho_factor(GX + beta * Iq, lower=True)
     rhsY = (Xn.T @ X) @ Y + np.asarray((R.T @ Xn).T) + beta * V - Pi   # = X+^T Z + beta V - Pi
     Yn = scipy.linalg.cho_solve(cX, rhsY)
-    Un = np.maximum(0.0, Xn + Lam / alpha)
-    Vn = np.maximum(0.0, Yn + Pi / beta)
+    Un = Xn + Lam / alpha
+    Vn = Yn + Pi / beta
+    if nonneg:
+        Un = np.maximum(0.0, Un)
+        Vn = np.maximum(0.0, Vn)
     Lamn = Lam + gamma * alpha * (Xn - Un)
     Pin = Pi + gamma * beta * (Yn - Vn)
     return Xn, Yn, Un, Vn, Lamn, Pin
 
 
-def adm(rows, cols, mvals, m, N, X0, Y0, alpha, beta, gamma, tol, max_iter, fixed_iters=False):
+def adm(rows, cols, mvals, m, N, X0, Y0, alpha, beta, gamma, tol, max_iter, fixed_iters=False, nonneg=True):
     """Sparse-residual ADM.  rows/cols index the known entries of the
     m x N matrix, mvals their values.  Returns X, Y, iterations done, last
     relative residual, and the final (U, V, Lambda, Pi)."""
@@ -106,7 +119,7 @@ def adm(rows, cols, mvals, m, N, X0, Y0, alpha, beta, gamma, tol, max_iter, fixe
             iters = k
             break
         X, Y, U, V, Lam, Pi = adm_step(rows, cols, mvals, m, N, X, Y, U, V, Lam, Pi,
-                                       alpha, beta, gamma, Rv=Rv)
+                                       alpha, beta, gamma, Rv=Rv, nonneg=nonneg)
     return X, Y, iters, err, (U, V, Lam, Pi)
 
 

@@ -53,6 +53,11 @@ class Params:
     beta0: float = 0.1
     gamma: float = 1.6
     r_min: float = 0.05
+    # completion: "adm" (Appendix A) or "als" (per-row masked ALS, oracle.als);
+    # nonneg False switches the ADM's projection off; lam the ALS regulariser
+    method: str = "adm"
+    nonneg: bool = True
+    lam: float = 0.01
     ray_eps: float = 1e-4
     fixed_iters: bool = False
 
@@ -107,9 +112,14 @@ def complete_and_render(m, n, q, ii, jj, A, seed, s, params, X0Y0=None):
         X0, Y0 = adm_mod.init_factors(params.seed, s, m, N, q)
     else:
         X0, Y0 = X0Y0
-    alpha, beta = adm_mod.penalties(m, N, q, params.alpha0, params.beta0)
-    X, Y, iters, err, _ = adm_mod.adm(rows, cols, mvals, m, N, X0, Y0, alpha, beta, params.gamma,
-                                      params.tol, params.max_iter, params.fixed_iters)
+    if params.method == "als":
+        from . import als as als_mod
+        X, Y, iters, err = als_mod.als(rows, cols, mvals, m, N, X0, Y0, params.lam, params.tol, params.max_iter,
+                                       params.fixed_iters)
+    else:
+        alpha, beta = adm_mod.penalties(m, N, q, params.alpha0, params.beta0)
+        X, Y, iters, err, _ = adm_mod.adm(rows, cols, mvals, m, N, X0, Y0, alpha, beta, params.gamma,
+                                          params.tol, params.max_iter, params.fixed_iters, nonneg=params.nonneg)
     if iters >= params.max_iter and not params.fixed_iters:
         flags |= FLAG_NOT_CONVERGED
     I = reduce_factors(X, Y, n, s0)
