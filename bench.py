@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--sweep", default="0.5,1,2,3,5,7.5,10",
                     help="total sampling rates (percent) of the plain vs learned fixed-RMSE comparison; empty: none")
     ap.add_argument("--sweep-steps", type=int, default=1)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the completion variants and the rank sweep at the headline rate")
     ap.add_argument("--eager", action="store_true",
                     help="time eager frames instead of the captured graph (for counter collection)")
     ap.add_argument("--write-traffic", nargs=4, metavar="CSV", default=None,
@@ -414,7 +416,7 @@ def main():
                    "sampled_entries_per_frame": int(N1.sum() + st_l["n2"].astype(np.int64).sum())}
         rates = [float(x) for x in args.sweep.split(",") if x.strip()]
         if rates:
-            del ws
+            ws = None                     # the headline workspace is not needed past this point
             torch.cuda.empty_cache()
             pts = {"plain": [], "learned": []}
             rows = []
@@ -453,6 +455,41 @@ def main():
                      "learned_speedup_interpolated": None if not (ms_plain_t and ms_learned_t)
                      else round(ms_plain_t / ms_learned_t, 3),
                      "sweep": rows}
+
+    # completion variants (ADM, ADM without non-negativity, masked ALS) and
+    # ranks 8 / 16 / 32 at the headline rate: one graph frame each
+    variants = None
+    if not args.no_variants:
+        ws = None
+        torch.cuda.empty_cache()
+        rad_v = torch.empty_like(rad)
+        variants = {"completion": [], "rank": []}
+        for name, kw in (("adm", {}), ("adm_without_nonnegativity", dict(no_nonneg=True)),
+                         ("masked_als", dict(als=True))):
+            pv = api.default_params(seed=seed, pass1_ppm=ppm1, pass2_ppm=ppm2, **kw)
+            pl = make_plan(pv)
+            wsv = api.workspace(pl, dev)
+            msv = frame_times(api, torch, ctx, pl, ds, pv, wsv, rad_v, 1, 1, args.eager)
+            variants["completion"].append({"method": name, "frame_ms": round(msv, 3),
+                                           "pixel_rmse": round(rel(rad_v[pid_t.long()].double(), ref), 5)})
+            progress(f"variant {name}: {msv:.1f} ms")
+            del wsv
+            pl.close()
+            torch.cuda.empty_cache()
+        rank0 = sc.rank.copy()
+        for qv in (8, 16, 32):
+            sc.rank = supported_rank(qv, np.diff(sc.pt_offsets))
+            pv = api.default_params(seed=seed, pass1_ppm=ppm1, pass2_ppm=ppm2)
+            pl = make_plan(pv)
+            wsv = api.workspace(pl, dev)
+            msv = frame_times(api, torch, ctx, pl, ds, pv, wsv, rad_v, 1, 1, args.eager)
+            variants["rank"].append({"rank": qv, "frame_ms": round(msv, 3),
+                                     "pixel_rmse": round(rel(rad_v[pid_t.long()].double(), ref), 5)})
+            progress(f"rank {qv}: {msv:.1f} ms")
+            del wsv
+            pl.close()
+            torch.cuda.empty_cache()
+        sc.rank = rank0
 
     if coarsen:
         rate_txt = (f"every slice coarsened from {coarsen[0]} row draws to at most {coarsen[1]} of the "
@@ -496,6 +533,7 @@ def main():
         "roofline": roof,
         "learned": learned,
         "fixed_rmse": fixed,
+        "variants": variants,
     }
     if not args.no_cpu_baseline:
         progress("oracle on the host ...")

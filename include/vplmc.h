@@ -59,6 +59,10 @@ extern "C" {
 #define VPLMC_FEATURES 4        /* compute the proposal features even with the plain proposal */
 #define VPLMC_GIVEN_INIT 8      /* ADM starts from the X and Y regions' contents (components past q
                                    are taken as 0) instead of the seeded draw X0, Y0 (Appendix A) */
+#define VPLMC_NO_NONNEG 16      /* ADM without its non-negativity: U = X+ + L / alpha, V = Y+ + P / beta
+                                   (no projection; the multipliers then stay 0) */
+#define VPLMC_ALS 32            /* complete by per-row masked ALS instead of ADM (a plan property:
+                                   the plan must be made with the same flag) */
 
 /* per-slice result flags (vplmc_read_stats) -- outcomes, not errors */
 #define VPLMC_SLICE_ALL_ZERO 1      /* every sampled entry is 0: radiance 0      */
@@ -107,6 +111,8 @@ typedef struct {
     float gamma;          /* multiplier step, in (0, 1.618)                    */
     float r_min;          /* distance clamp of the geometry term               */
     float ray_eps;        /* shadow-ray origin offset along the normal         */
+    float lam;            /* masked-ALS regulariser: lam max(1, n) I per row / column (> 0) */
+    int32_t reserved;     /* 0                                                 */
 } vplmc_params;
 
 typedef struct vplmc_ctx vplmc_ctx;
@@ -171,7 +177,7 @@ enum {
 int vplmc_version(void);
 const char *vplmc_last_error(void);
 /* Paper defaults: 5% + 5%, max_iter 100, tol 1e-3, alpha0 = beta0 = 0.1,
- * gamma 1.6, r_min 0.05, ray_eps 1e-4, seed 1. */
+ * gamma 1.6, r_min 0.05, ray_eps 1e-4, seed 1; lam 0.01 (masked ALS). */
 int vplmc_default_params(vplmc_params *out /* HOST */);
 
 /* ---- context: device + stream ---------------------------------------- */

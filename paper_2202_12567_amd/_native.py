@@ -28,7 +28,8 @@ class Params(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("pass1_ppm", ctypes.c_int32), ("pass2_ppm", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32), ("tol", ctypes.c_float),
                 ("alpha0", ctypes.c_float), ("beta0", ctypes.c_float), ("gamma", ctypes.c_float),
-                ("r_min", ctypes.c_float), ("ray_eps", ctypes.c_float)]
+                ("r_min", ctypes.c_float), ("ray_eps", ctypes.c_float), ("lam", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
 
 
 class Coarsen(ctypes.Structure):
@@ -51,7 +52,7 @@ class SliceInfo(ctypes.Structure):
 
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
-FIXED_ITERS, LEARNED, FEATURES, GIVEN_INIT = 1, 2, 4, 8
+FIXED_ITERS, LEARNED, FEATURES, GIVEN_INIT, NO_NONNEG, ALS = 1, 2, 4, 8, 16, 32
 SLICE_ALL_ZERO, SLICE_NOT_CONVERGED, SLICE_SHORTFALL, SLICE_FALLBACK = 1, 2, 4, 8
 REGIONS = ["LIGHTS", "REP", "BBOX", "OMEGA1", "VAL1", "OMEGA2", "VAL2", "WEIGHTS", "COLMIN", "COLMAX",
            "COLCNT", "ROW_PTR", "CSR_COL", "CSR_VAL", "COL_PTR", "CSC_ROW", "CSC_VAL", "X", "Y", "SLICE_SCALE",

@@ -23,7 +23,7 @@ def version():
     return N.load().vplmc_version()
 
 
-def default_params(fixed_iters=None, learned=None, features=None, given_init=None, **kw):
+def default_params(fixed_iters=None, learned=None, features=None, given_init=None, no_nonneg=None, als=None, **kw):
     """vplmc_default_params with overrides; booleans toggle the flag bits."""
     p = N.Params()
     check(N.load().vplmc_default_params(ctypes.byref(p)))
@@ -32,7 +32,7 @@ def default_params(fixed_iters=None, learned=None, features=None, given_init=Non
             raise AttributeError(k)
         setattr(p, k, v)
     for bit, on in ((N.FIXED_ITERS, fixed_iters), (N.LEARNED, learned), (N.FEATURES, features),
-                    (N.GIVEN_INIT, given_init)):
+                    (N.GIVEN_INIT, given_init), (N.NO_NONNEG, no_nonneg), (N.ALS, als)):
         if on is not None:
             p.flags = (p.flags | bit) if on else (p.flags & ~bit)
     return p

@@ -83,7 +83,9 @@ int check_params(const vplmc_params *p) {
         return set_error(VPLMC_EINVAL, "gamma must be in (0, 1.618) (got %g)", (double)p->gamma);
     if (!(p->tol >= 0.f)) return set_error(VPLMC_EINVAL, "tol must be >= 0");
     if (!(p->r_min > 0.f) || !(p->ray_eps >= 0.f)) return set_error(VPLMC_EINVAL, "r_min must be > 0, ray_eps >= 0");
-    if (p->flags & ~(VPLMC_FIXED_ITERS | VPLMC_LEARNED | VPLMC_FEATURES | VPLMC_GIVEN_INIT))
+    if (!(p->lam > 0.f)) return set_error(VPLMC_EINVAL, "lam must be > 0");
+    if (p->reserved != 0) return set_error(VPLMC_EINVAL, "reserved must be 0");
+    if (p->flags & ~(VPLMC_FIXED_ITERS | VPLMC_LEARNED | VPLMC_FEATURES | VPLMC_GIVEN_INIT | VPLMC_NO_NONNEG | VPLMC_ALS))
         return set_error(VPLMC_EINVAL, "unknown flags 0x%x", p->flags);
     return VPLMC_OK;
 }
@@ -140,6 +142,7 @@ int vplmc_default_params(vplmc_params *out) {
     out->gamma = 1.6f;
     out->r_min = 0.05f;
     out->ray_eps = 1e-4f;
+    out->lam = 0.01f;
     return VPLMC_OK;
 }
 
@@ -307,6 +310,7 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     plan->n_lights = n_clusters;
     plan->pass1_ppm = params->pass1_ppm;
     plan->pass2_ppm = params->pass2_ppm;
+    plan->als = (params->flags & VPLMC_ALS) != 0;
     if (co) {
         plan->coarse = true;
         plan->n_leaves = co->n_leaves;
@@ -375,7 +379,9 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         d.off_y = oy;
         d.off_bm = obm;
         d.off_bmt = obmt;
-        const bool in_lds = adm_fits_lds(qp, (int)m);
+        // the LDS-resident ADM kernel takes the slices that fit; masked ALS
+        // reads every slice's CSR and CSC copies
+        const bool in_lds = !plan->als && adm_fits_lds(qp, (int)m);
         d.ell = in_lds ? 1 : 0;
         d.off_grp = (int32_t)ogrp;
         d.off_ell = oell;
@@ -571,7 +577,7 @@ int vplmc_plan_slice(const vplmc_plan *plan, int32_t s, vplmc_slice_info *out) {
     out->q_pad = d.q;
     out->N1 = d.N1;
     out->N2 = d.N2;
-    out->adm_in_lds = adm_fits_lds(d.q, d.m) ? 1 : 0;
+    out->adm_in_lds = d.ell;
     out->off1 = d.off1;
     out->off2 = d.off2;
     out->off_omega = d.off_omega;
@@ -600,6 +606,8 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     if (rc) return rc;
     if (params->pass1_ppm != plan->pass1_ppm || params->pass2_ppm != plan->pass2_ppm)
         return set_error(VPLMC_EINVAL, "params rates differ from the plan's");
+    if (((params->flags & VPLMC_ALS) != 0) != plan->als)
+        return set_error(VPLMC_EINVAL, "the completion method (VPLMC_ALS) differs from the plan's");
     if (points->m < 0 || bad_ptrs_points(points)) return set_error(VPLMC_EINVAL, "incomplete points arrays");
     if (vpls->n < 1 || bad_ptrs_lights(vpls)) return set_error(VPLMC_EINVAL, "incomplete VPL arrays");
     if (cut->n_clusters != plan->n_clusters || !cut->offsets || !cut->members)
@@ -758,13 +766,16 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
     float *Y = region<float>(ws, plan, VPLMC_R_Y);
     float *scale = region<float>(ws, plan, VPLMC_R_SLICE_SCALE);
     if ((rc = ph.mark(VPLMC_PH_ADM))) return rc;
-    if ((rc = launch_adm(st, &ctx->adm, *plan, ctx->n_cu, desc, ids, region<int32_t>(ws, plan, R_QUEUE), *params, row_ptr,
-                         csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X,
-                         region<float>(ws, plan, R_XNEXT), region<float>(ws, plan, R_XP),
-                         region<float>(ws, plan, R_LAMBDA), Y, region<float>(ws, plan, R_YP),
-                         region<float>(ws, plan, R_PI), region<float>(ws, plan, R_YT),
-                         region<float>(ws, plan, R_ADM_RED), region<double>(ws, plan, R_E2PART), scale, stats)))
-        return rc;
+    if (plan->als)
+        rc = launch_als(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Y,
+                        scale, stats);
+    else
+        rc = launch_adm(st, &ctx->adm, *plan, ctx->n_cu, desc, ids, region<int32_t>(ws, plan, R_QUEUE), *params,
+                        row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X, region<float>(ws, plan, R_XNEXT),
+                        region<float>(ws, plan, R_XP), region<float>(ws, plan, R_LAMBDA), Y,
+                        region<float>(ws, plan, R_YP), region<float>(ws, plan, R_PI), region<float>(ws, plan, R_YT),
+                        region<float>(ws, plan, R_ADM_RED), region<double>(ws, plan, R_E2PART), scale, stats);
+    if (rc) return rc;
     if ((rc = ph.mark(VPLMC_PH_REDUCE))) return rc;
     if ((rc = launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, points->m, radiance))) return rc;
     if ((rc = ph.mark(VPLMC_N_PHASES))) return rc;
@@ -1118,12 +1129,16 @@ int vplmc_stage_adm(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_params *
     float *X = region<float>(ws, plan, VPLMC_R_X);
     float *Y = region<float>(ws, plan, VPLMC_R_Y);
     float *scale = region<float>(ws, plan, VPLMC_R_SLICE_SCALE);
-    if ((rc = launch_adm(st, &ctx->adm, *plan, ctx->n_cu, desc, ids, region<int32_t>(ws, plan, R_QUEUE), *params, row_ptr,
-                         csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X, region<float>(ws, plan, R_XNEXT),
-                         region<float>(ws, plan, R_XP), region<float>(ws, plan, R_LAMBDA), Y, region<float>(ws, plan, R_YP),
-                         region<float>(ws, plan, R_PI), region<float>(ws, plan, R_YT),
-                         region<float>(ws, plan, R_ADM_RED), region<double>(ws, plan, R_E2PART), scale, stats)))
-        return rc;
+    if (plan->als)
+        rc = launch_als(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Y,
+                        scale, stats);
+    else
+        rc = launch_adm(st, &ctx->adm, *plan, ctx->n_cu, desc, ids, region<int32_t>(ws, plan, R_QUEUE), *params,
+                        row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X, region<float>(ws, plan, R_XNEXT),
+                        region<float>(ws, plan, R_XP), region<float>(ws, plan, R_LAMBDA), Y,
+                        region<float>(ws, plan, R_YP), region<float>(ws, plan, R_PI), region<float>(ws, plan, R_YT),
+                        region<float>(ws, plan, R_ADM_RED), region<double>(ws, plan, R_E2PART), scale, stats);
+    if (rc) return rc;
     if ((rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(radiance), 3 * (size_t)n_points, 0u))) return rc;
     if ((rc = launch_reduce(st, *plan, desc, pt_ids, X, Y, scale, n_points, radiance))) return rc;
     VPLMC_HIP(hipStreamSynchronize(st));

@@ -273,6 +273,7 @@ __device__ void adm_global_slice(
     // the contents of the X and Y regions ----
     const float cq = (float)(2.0 / sqrt((double)qr));
     const bool given = (fixed_iters & 2) != 0;
+    const bool nonneg = (fixed_iters & 4) == 0;    // mode bit 2: projections off
     for (int e = t; e < m * Q; e += THREADS) {
         const int i = e / Q, k = e % Q;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
@@ -389,7 +390,7 @@ __device__ void adm_global_slice(
                 for (int l = 0; l < Q; ++l)
                     v += (double)xi[l] * sh.F[l * Q + k] + (double)wsa[32 * Q + l] * sh.Inv[l * Q + k];
                 xn = (float)v;
-                const float u = fmaxf(0.f, xn + lam * inv_alpha);
+                const float u = nonneg ? fmaxf(0.f, xn + lam * inv_alpha) : xn + lam * inv_alpha;
                 Xn[(size_t)i * Q + k] = xn;
                 Xp[(size_t)i * Q + k] = u;
                 Lam[(size_t)i * Q + k] = lam + ga * (xn - u);
@@ -560,7 +561,7 @@ __device__ void adm_global_slice(
                         float un[4], pn[4];
 #pragma unroll
                         for (int kk = 0; kk < 4; ++kk) {
-                            un[kk] = fmaxf(0.f, o[c][kk] + pa[kk] * inv_beta);
+                            un[kk] = nonneg ? fmaxf(0.f, o[c][kk] + pa[kk] * inv_beta) : o[c][kk] + pa[kk] * inv_beta;
                             pn[kk] = pa[kk] + gb * (o[c][kk] - un[kk]);
                         }
                         ypj[w] = make_float4(un[0], un[1], un[2], un[3]);
@@ -671,7 +672,7 @@ __device__ void adm_global_slice(
                             v += sh.F[l * Q + k] * (double)yl + sh.Inv[l * Q + k] * (double)tj[c * Q + l];
                         }
                         const float yn = (float)v;
-                        const float u = fmaxf(0.f, yn + pv[rnd] * inv_beta);
+                        const float u = nonneg ? fmaxf(0.f, yn + pv[rnd] * inv_beta) : yn + pv[rnd] * inv_beta;
                         ypj[o] = u;
                         pij[o] = pv[rnd] + gb * (yn - u);
                         Y[(size_t)j * 3 * Q + o] = yn;
@@ -923,6 +924,7 @@ __device__ void adm_ell_slice(
     // the contents of the X and Y regions ----
     const float cq = (float)(2.0 / sqrt((double)qr));
     const bool given = (fixed_iters & 2) != 0;
+    const bool nonneg = (fixed_iters & 4) == 0;    // mode bit 2: projections off
     for (int e = t; e < m * Q; e += THREADS) {
         const int i = e / Q, k = e % Q;
         const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
@@ -1250,7 +1252,7 @@ __device__ void adm_ell_slice(
                     if (ok) {
                         const int e = r * Q + c;
                         const float lam = Lam[e];
-                        const float u = fmaxf(0.f, xn + lam * inv_alpha);
+                        const float u = nonneg ? fmaxf(0.f, xn + lam * inv_alpha) : xn + lam * inv_alpha;
                         Xp[e] = u;
                         Lam[e] = lam + ga * (xn - u);
                         XB[xpos<Q>(r, c)] = xn;
@@ -1417,7 +1419,7 @@ __device__ void adm_ell_slice(
                     if (ok) {
                         const size_t e = (size_t)r * Q + c;
                         const float pi = pa[v];
-                        const float u = fmaxf(0.f, yn + pi * inv_beta);
+                        const float u = nonneg ? fmaxf(0.f, yn + pi * inv_beta) : yn + pi * inv_beta;
                         const float pn = pi + gb * (yn - u);
                         W[e] = fmaf(beta_f, u, -pn);
                         Pi[e] = pn;
@@ -1550,9 +1552,11 @@ __global__ __launch_bounds__(256) void k_reduce(const SliceDesc *__restrict__ de
 }
 
 // mode word of the completion kernels: bit 0 a fixed iteration count, bit 1
-// initial factors given in the X and Y regions
+// initial factors given in the X and Y regions, bit 2 no non-negativity
+// (U = X+ + Lambda / alpha, V = Y+ + Pi / beta without the projection)
 inline int32_t adm_mode(const vplmc_params &prm) {
-    return ((prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0) | ((prm.flags & VPLMC_GIVEN_INIT) ? 2 : 0);
+    return ((prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0) | ((prm.flags & VPLMC_GIVEN_INIT) ? 2 : 0) |
+           ((prm.flags & VPLMC_NO_NONNEG) ? 4 : 0);
 }
 
 // grid of a launch over `count` slices: one workgroup per slice, or with a

@@ -270,8 +270,10 @@ __device__ __forceinline__ Light node_light(const float *__restrict__ lights, si
                  unit ? 1.0f : lights[6 * N + c], unit ? 1.0f : lights[7 * N + c], unit ? 1.0f : lights[8 * N + c]};
 }
 
+// six wavefronts per SIMD (80 VGPRs): the walk's latency needs the occupancy;
+// at 83 VGPRs (five) the kernel ran 14% slower on the 1080p frame
 template <bool STAGED>
-__global__ __launch_bounds__(256) void k_coarsen_eps(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_coarsen_eps(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
                                                      const SliceDesc *__restrict__ desc, int64_t total, int64_t K,
                                                      const int32_t *__restrict__ pt_ids, CoarsenTree tr,
                                                      CoarsenSlices cs, uint64_t seed, float r_min2, float eps,

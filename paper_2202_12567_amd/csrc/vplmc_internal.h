@@ -251,6 +251,7 @@ struct vplmc_plan {
     int32_t n_lights = 0;          // lights of the table: n_clusters, or 2 n_leaves - 1 tree nodes
     // light coarsening (Sec. 4): on when the plan was made with a tree
     bool coarse = false;
+    bool als = false;              // completion by per-row masked ALS (VPLMC_ALS)
     int32_t n_leaves = 0, height_max = 0, pixels = 0;
     double bound = 0.0;
     std::vector<int32_t> tree;     // left, right, parent, height, min_leaf, order, level_off
@@ -348,6 +349,10 @@ int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int
                const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
                const EllView &ell, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
                float *Yt, float *red, double *e2part, float *scale, int32_t *stats);
+int launch_als(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
+               const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
+               const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, float *X, float *Y, float *scale,
+               int32_t *stats);
 int launch_reduce(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *pt_ids,
                   const float *X, const float *Y, const float *scale, int32_t n_points, float *radiance);
 int launch_keys_bitmap(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const uint32_t *keys,
