@@ -15,6 +15,8 @@ in its own order and notation and cites the passage it implements:
 * ``shading``   -- lighting-matrix entries A(i, j) (Sec. 3) with shadow-ray
                    visibility, brute force over every sphere.
 * ``cluster``   -- cluster representative and intensity (Sec. 4, I_f = I_a + I_b).
+* ``lightcut``  -- the global light cut (Sec. 3 step 1, Sec. 6): conservative
+                   error bound, level-by-level split test, the cap.
 * ``coarsen``   -- per-slice light coarsening over the tree above the global
                    cut (Sec. 4: eps, the recursive cost, merge order) and the
                    first pass its pixel draws give (Sec. 5).

@@ -100,10 +100,11 @@ def quantize(t):
     return [int(max(1.0, np.floor(TWO24 * v / tmax))) for v in t]
 
 
-def node_table(leaf_rep, leaf_int, leaf_lo, leaf_hi, leaf_members, left, right, seed):
+def node_table(leaf_rep, leaf_int, leaf_lo, leaf_hi, leaf_members, left, right, seed, tag=TAG_TREE):
     """Every node of the tree above the cut: leaves 0 .. n_g - 1 (the cut's
     clusters), split nodes n_g .. 2 n_g - 2 (children first).  Returns a dict
-    of arrays over the 2 n_g - 1 nodes."""
+    of arrays over the 2 n_g - 1 nodes.  ``tag`` keys the kept-child draws
+    (the full light tree of the global cut uses its own)."""
     ng = int(np.asarray(leaf_rep).shape[0])
     N = 2 * ng - 1
     rep = np.zeros(N, np.int64)
@@ -128,7 +129,7 @@ def node_table(leaf_rep, leaf_int, leaf_lo, leaf_hi, leaf_members, left, right, 
         parent[l] = parent[r] = f
         inten[f] = (inten[l].astype(np.float64) + inten[r].astype(np.float64)).astype(np.float32)
         ql, qr = quantize(total_intensity(inten[[l, r]]))
-        u = mulhi64(philox4x64((seed, 0), (f, 0, TAG_TREE, 0))[0], ql + qr)
+        u = mulhi64(philox4x64((seed, 0), (f, 0, tag, 0))[0], ql + qr)
         a, b = (l, r) if u < ql else (r, l)
         kept[f], dropped[f] = a, b
         rep[f] = rep[a]

@@ -274,6 +274,55 @@ def tree_above_cut(children, cut_node_order):
     return left, right
 
 
+def full_light_tree(pos):
+    """The light tree over every VPL, grown to single lights by the same split
+    as light_tree_cut_sequence (median along the longest axis of the members'
+    box, members taken by ascending id before a stable sort), so any cut that
+    sequence makes is a cut of this tree.
+
+    Layout: leaves 0 .. n-1 are the VPLs perm[0 .. n) in an order where every
+    node's leaves are contiguous (left child's before right child's); split
+    node n + k has children left[k], right[k], children before parents, the
+    root 2 n - 2.  Returns (perm, left, right) as int32 arrays."""
+    pos = np.asarray(pos, np.float64)
+    n = pos.shape[0]
+    perm = np.arange(n, dtype=np.int64)
+    if n < 2:
+        return perm.astype(np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32)
+    # internal nodes are numbered breadth-first (root 0) while growing; BFS id
+    # b is node n + (n - 2 - b), so children precede parents and the root is last
+    L = np.zeros(n - 1, np.int64)
+    R = np.zeros(n - 1, np.int64)
+    starts = np.array([0], np.int64)
+    sizes = np.array([n], np.int64)
+    ids = np.array([0], np.int64)     # BFS id of each segment of this level
+    next_id = 1
+    while starts.size:
+        first = np.cumsum(sizes) - sizes
+        seg = np.repeat(np.arange(starts.size), sizes)
+        idx = np.arange(int(sizes.sum())) + np.repeat(starts - first, sizes)
+        p = pos[perm[idx]]
+        lo = np.minimum.reduceat(p, first, axis=0)
+        hi = np.maximum.reduceat(p, first, axis=0)
+        axis = np.argmax(hi - lo, axis=1)
+        coord = p[np.arange(idx.size), axis[seg]]
+        order = np.lexsort((perm[idx], coord, seg))
+        perm[idx] = perm[idx][order]
+        half = sizes // 2
+        c_st = np.stack([starts, starts + half], axis=1).ravel()
+        c_sz = np.stack([half, sizes - half], axis=1).ravel()
+        inner = c_sz > 1
+        c_bfs = next_id + np.cumsum(inner) - 1
+        next_id += int(inner.sum())
+        c_node = np.where(inner, n + (n - 2 - c_bfs), c_st)
+        k = (n - 2) - ids
+        L[k] = c_node[0::2]
+        R[k] = c_node[1::2]
+        starts, sizes, ids = c_st[inner], c_sz[inner], c_bfs[inner]
+    assert next_id == n - 1
+    return perm.astype(np.int32), L.astype(np.int32), R.astype(np.int32)
+
+
 def _cut_table(nodes, node_ids):
     """Cut as CSR: clusters ordered by their smallest member id."""
     node_ids = sorted(node_ids, key=lambda i: int(nodes[i][0]))

@@ -1,6 +1,9 @@
 """The seeded input generator produces well-formed inputs of the stated shapes."""
 import numpy as np
 
+import pytest
+
+import scenegen
 from scenegen import make_scene
 
 
@@ -34,3 +37,28 @@ def test_cut_is_a_partition_for_clustered_config():
     assert sc.n_clusters == 256
     assert np.array_equal(np.sort(sc.cut_members), np.arange(2048))
     assert np.all(np.diff(sc.cut_offsets) >= 1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 301])
+def test_full_light_tree_layout_and_node_sets(n):
+    """Leaves contiguous under every node, children before parents, root last,
+    and the same node sets the greedy cut sequence creates when grown to
+    single VPLs."""
+    rng = np.random.default_rng(n)
+    pos = rng.uniform(size=(n, 3))
+    perm, left, right = scenegen.full_light_tree(pos)
+    assert sorted(perm.tolist()) == list(range(n))
+    N = 2 * n - 1
+    parent = -np.ones(N, np.int64)
+    first = np.arange(N)
+    last = np.arange(N)
+    for k in range(n - 1):
+        f, l, r = n + k, int(left[k]), int(right[k])
+        assert l < f and r < f and parent[l] < 0 and parent[r] < 0
+        parent[l] = parent[r] = f
+        assert last[l] + 1 == first[r]
+        first[f], last[f] = first[l], last[r]
+    assert (parent[:N - 1] >= 0).all() and first[N - 1] == 0 and last[N - 1] == n - 1
+    if n > 1:
+        nodes, _, _ = scenegen.light_tree_cut_sequence(pos, rng.uniform(size=(n, 3)), n)
+        assert {tuple(sorted(perm[first[f]:last[f] + 1])) for f in range(N)} == {tuple(x) for x in nodes}
