@@ -52,6 +52,7 @@ extern "C" {
 #define VPLMC_MAX_COLS 65535
 #define VPLMC_MAX_RANK 32
 #define VPLMC_MAX_LEAVES 32768  /* leaves of a coarsening tree (node ids and heights fit in 16 bits) */
+#define VPLMC_MAX_TREE_LEAVES (1 << 27) /* VPLs under the light tree of vplmc_lightcut */
 
 /* vplmc_params.flags */
 #define VPLMC_FIXED_ITERS 1     /* ignore tol: run exactly max_iter ADM iterations */
@@ -402,6 +403,66 @@ int vplmc_eval_pairs(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lig
 int vplmc_brute_force(vplmc_ctx *ctx, const vplmc_points *points, const vplmc_lights *lights,
                       int32_t n_out, const int32_t *point_ids, const vplmc_params *params,
                       double *out);
+
+/* ---- global light cut (Sec. 3, step 1; Sec. 6) -------------------------------
+ * Step 1 of the method: the cut of a light tree over every VPL that the
+ * lightcut method (Walter et al. 2005) picks for the whole image, with the
+ * visibility bounded by 1 (conservative) and the split test run for all
+ * nodes of one tree level at a time.
+ *
+ * Tree (HOST arrays, read by vplmc_lightcut_plan_create only): leaves
+ * 0 .. n_leaves-1 are the VPLs perm[0 .. n_leaves) (a permutation); split
+ * node n_leaves + k has children left[k], right[k], both below
+ * n_leaves + k, every node but the root 2 n_leaves - 2 the child of one split
+ * node, and the leaves under every node contiguous, the left child's first.
+ *
+ * Node lights: a leaf is its VPL; split node f keeps the position and normal
+ * of child a drawn with probability Q_a / (Q_l + Q_r),
+ * Q = max(1, floor(2^24 t / max(t_l, t_r))), t = (R + G) + B in FP64, by
+ * Philox4x64-10 with key (seed, 0) and counter (f, 0, 8, 0) (a = left iff
+ * mulhi64(word 0, Q_l + Q_r) < Q_l); I_f = fp32(fp64(I_l) + fp64(I_r)); the
+ * box is the union of the children's boxes.
+ *
+ * Split test at sample pixel x (position p, normal n, kd, ks, e):
+ *   est(x)    = the current cut's entries with V = 1, summed over nodes and channels
+ *   bound(x,f) = c / max(d^2, r_min^2) * sum_c (kd_c / pi + ks (e + 2) / (2 pi)) I_f,c
+ *   d = distance from p to f's box, h = max over the box of n . (y - p),
+ *   c = 0 if h <= 0, else min(1, h / d) (1 if d = 0)
+ *   rho(f) = max over the samples of bound / est (b / 0 = inf, 0 / 0 = 0; no samples: 0)
+ * The root is level 0; the nodes of a level that are not single VPLs are
+ * tested against the estimate of the current cut and all with rho > eps
+ * split at once, their children forming the next level.  When the failing
+ * nodes would take the cut past max_cut, only the max_cut - |cut| with the
+ * largest rho split (ties: lower node id) and the cut is final.
+ *
+ * Outputs, DEVICE: n_cut[1]; cut_nodes[max_cut] and cut_offsets[max_cut + 1]:
+ * the cut by smallest leaf, cluster k holding the VPLs
+ * perm[cut_offsets[k] .. cut_offsets[k+1]) (so {n_cut, cut_offsets, perm} is
+ * a vplmc_cut); above_left / above_right [max_cut - 1] (each may be NULL): the
+ * tree above the cut in the layout of vplmc_coarsen (the cut's nodes are
+ * leaves 0 .. n_cut-1 in cut order, the split nodes follow by increasing tree
+ * id); rho[2 n_leaves - 1] (may be NULL): rho of every tested node, -1
+ * elsewhere.  Only the first n_cut (+1) entries of the cut arrays are
+ * written.  sample_ids: DEVICE [n_samples] point ids in [0, points->m)
+ * (others read a clamped point).  The bound is FP32, est FP64 over FP32
+ * entries.  Errors: VPLMC_EINVAL for a malformed tree, eps < 0 or NaN,
+ * r_min <= 0, vpls->n != n_leaves, a short or misaligned workspace. */
+typedef struct {
+    int32_t n_leaves;
+    const int32_t *perm;  /* n_leaves     */
+    const int32_t *left;  /* n_leaves - 1 */
+    const int32_t *right; /* n_leaves - 1 */
+} vplmc_light_tree;
+
+typedef struct vplmc_lightcut_plan vplmc_lightcut_plan;
+int vplmc_lightcut_plan_create(const vplmc_light_tree *tree /* HOST */, int32_t n_samples, int32_t max_cut,
+                               vplmc_lightcut_plan **out /* HOST */);
+int vplmc_lightcut_plan_destroy(vplmc_lightcut_plan *plan);
+int vplmc_lightcut_workspace_size(const vplmc_lightcut_plan *plan, size_t *bytes /* HOST */);
+int vplmc_lightcut(vplmc_ctx *ctx, const vplmc_lightcut_plan *plan, const vplmc_points *points,
+                   const vplmc_lights *vpls, const int32_t *sample_ids, double eps, float r_min, uint64_t seed,
+                   void *workspace, size_t workspace_bytes, int32_t *n_cut, int32_t *cut_nodes,
+                   int32_t *cut_offsets, int32_t *above_left, int32_t *above_right, float *rho);
 
 /* ---- learned second-pass proposal ------------------------------------------
  * A 12 -> 128 -> 128 -> 1 GELU network predicting the log sampling density

@@ -38,6 +38,11 @@ class Coarsen(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class LightTree(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_int32), ("perm", ctypes.c_void_p), ("left", ctypes.c_void_p),
+                ("right", ctypes.c_void_p)]
+
+
 class Tune(ctypes.Structure):
     _fields_ = [("adm_queue", ctypes.c_int32), ("adm_threads", ctypes.c_int32), ("eval_threads", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -92,6 +97,11 @@ SIG = {
     "vplmc_brute_force": (I32, [P, ctypes.POINTER(Points), ctypes.POINTER(Lights), I32, P,
                                 ctypes.POINTER(Params), P]),
     "vplmc_philox4x64": (I32, [P, U64, U64, P, I64, P]),
+    "vplmc_lightcut_plan_create": (I32, [ctypes.POINTER(LightTree), I32, I32, ctypes.POINTER(P)]),
+    "vplmc_lightcut_plan_destroy": (I32, [P]),
+    "vplmc_lightcut_workspace_size": (I32, [P, ctypes.POINTER(ctypes.c_size_t)]),
+    "vplmc_lightcut": (I32, [P, P, ctypes.POINTER(Points), ctypes.POINTER(Lights), P, ctypes.c_double,
+                             ctypes.c_float, U64, P, ctypes.c_size_t, P, P, P, P, P, P]),
     "vplmc_stage_pass2": (I32, [P, P, ctypes.POINTER(Params), P, ctypes.c_size_t]),
     "vplmc_stage_adm": (I32, [P, P, ctypes.POINTER(Params), P, I32, P, ctypes.c_size_t, P]),
     "vplmc_stage_reduce": (I32, [P, P, P, I32, P, ctypes.c_size_t, P]),

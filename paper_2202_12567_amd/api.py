@@ -316,6 +316,63 @@ def profile_end(ctx):
     return dict(zip(N.PHASES, ms.tolist())), int(fr[0])
 
 
+# ---- global light cut (Sec. 3 step 1, Sec. 6) ---------------------------------
+
+class LightcutPlan:
+    """Plan of the global light cut over a full light tree (perm, left, right
+    as scenegen.full_light_tree lays it out) for n_samples sample pixels and
+    a cut of at most max_cut nodes; validates the tree on the host."""
+
+    def __init__(self, perm, left, right, n_samples, max_cut):
+        lib = N.load()
+        self.perm = np.ascontiguousarray(perm, dtype=np.int32)
+        self._left = np.ascontiguousarray(left, dtype=np.int32)
+        self._right = np.ascontiguousarray(right, dtype=np.int32)
+        self.n = int(self.perm.shape[0])
+        self.n_samples = int(n_samples)
+        self.max_cut = int(max_cut)
+        f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        tree = N.LightTree(self.n, f(self.perm), f(self._left), f(self._right))
+        h = ctypes.c_void_p()
+        check(lib.vplmc_lightcut_plan_create(ctypes.byref(tree), self.n_samples, self.max_cut, ctypes.byref(h)))
+        self.h = h
+        sz = ctypes.c_size_t()
+        check(lib.vplmc_lightcut_workspace_size(self.h, ctypes.byref(sz)))
+        self.workspace_bytes = int(sz.value)
+
+    def workspace(self, device):
+        return torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            N.load().vplmc_lightcut_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lightcut(ctx, lplan, ds, sample_ids, eps, r_min, seed, ws, want_rho=False):
+    """The global cut (vplmc_lightcut).  Returns device tensors: n_cut (1,),
+    cut_nodes (max_cut,), cut_offsets (max_cut + 1,), above_left/right
+    (max_cut - 1,) and rho (2 n - 1,) or None; only the first n_cut entries
+    of the cut arrays are meaningful."""
+    dev = ws.device
+    i32 = lambda k: torch.full((max(k, 1),), -1, dtype=torch.int32, device=dev)
+    n_cut = i32(1)
+    nodes, offs = i32(lplan.max_cut), i32(lplan.max_cut + 1)
+    al, ar = i32(lplan.max_cut - 1), i32(lplan.max_cut - 1)
+    rho = torch.empty(2 * lplan.n - 1, dtype=torch.float32, device=dev) if want_rho else None
+    check(N.load().vplmc_lightcut(ctx.h, lplan.h, ctypes.byref(ds.points_c), ctypes.byref(ds.vpls_c),
+                                  _ptr(sample_ids), float(eps), float(r_min), int(seed), _ptr(ws),
+                                  int(ws.numel()), _ptr(n_cut), _ptr(nodes), _ptr(offs), _ptr(al), _ptr(ar),
+                                  _ptr(rho) if rho is not None else None))
+    return dict(n_cut=n_cut, cut_nodes=nodes, cut_offsets=offs, above_left=al, above_right=ar, rho=rho)
+
+
 # ---- batching: launch shapes, autotuning, captured frames --------------------
 
 def get_tune(plan):

@@ -6,6 +6,9 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <vector>
+#include <cmath>
+#include <algorithm>
 
 #include "vplmc_internal.h"
 
@@ -1385,6 +1388,168 @@ int vplmc_philox4x64(vplmc_ctx *ctx, uint64_t key0, uint64_t key1, const uint64_
     if (n < 0 || (n > 0 && (!ctr || !out))) return set_error(VPLMC_EINVAL, "invalid counter/output arrays");
     VPLMC_HIP(hipSetDevice(ctx->device));
     return launch_philox(ctx->stream, key0, key1, ctr, n, out);
+}
+
+// ---- global light cut ------------------------------------------------------
+
+}  // extern "C"
+
+struct vplmc_lightcut_plan {
+    int32_t n = 0, S = 0, cap = 0, F = 0, height_max = 0, depth = 0;
+    std::vector<int32_t> upload;      // perm | left | right | order | min_leaf
+    std::vector<int32_t> level_off;   // height_max + 1
+    enum { L_TREE, L_REP, L_LIGHTS, L_BBOX, L_SAMP, L_EST, L_INV, L_PART, L_STATE, L_FRONT, L_RHO, L_SPLIT, L_CTL,
+           L_LEAF, L_REN, L_END };
+    size_t off[L_END + 1] = {};
+};
+
+namespace {
+
+LightcutView lightcut_view(const vplmc_lightcut_plan *p, void *ws, const int32_t *sample_ids) {
+    char *b = static_cast<char *>(ws);
+    const size_t n = p->n;
+    LightcutView v;
+    v.n = p->n;
+    v.S = p->S;
+    v.cap = p->cap;
+    v.F = p->F;
+    const int32_t *t = reinterpret_cast<const int32_t *>(b + p->off[vplmc_lightcut_plan::L_TREE]);
+    v.perm = t;
+    v.left = t + n;
+    v.right = t + n + (n - 1);
+    v.order = t + n + 2 * (n - 1);
+    v.min_leaf = t + n + 3 * (n - 1);
+    v.sample_ids = sample_ids;
+    v.rep = reinterpret_cast<int32_t *>(b + p->off[vplmc_lightcut_plan::L_REP]);
+    v.lights = reinterpret_cast<float *>(b + p->off[vplmc_lightcut_plan::L_LIGHTS]);
+    v.bbox = reinterpret_cast<float *>(b + p->off[vplmc_lightcut_plan::L_BBOX]);
+    v.samp = reinterpret_cast<float *>(b + p->off[vplmc_lightcut_plan::L_SAMP]);
+    v.est = reinterpret_cast<double *>(b + p->off[vplmc_lightcut_plan::L_EST]);
+    v.inv_est = reinterpret_cast<float *>(b + p->off[vplmc_lightcut_plan::L_INV]);
+    v.part = reinterpret_cast<double *>(b + p->off[vplmc_lightcut_plan::L_PART]);
+    v.state = reinterpret_cast<uint32_t *>(b + p->off[vplmc_lightcut_plan::L_STATE]);
+    v.front = reinterpret_cast<int32_t *>(b + p->off[vplmc_lightcut_plan::L_FRONT]);
+    v.rho_f = reinterpret_cast<uint32_t *>(b + p->off[vplmc_lightcut_plan::L_RHO]);
+    v.split = reinterpret_cast<int32_t *>(b + p->off[vplmc_lightcut_plan::L_SPLIT]);
+    v.ctl = reinterpret_cast<int32_t *>(b + p->off[vplmc_lightcut_plan::L_CTL]);
+    v.leafmark = reinterpret_cast<int32_t *>(b + p->off[vplmc_lightcut_plan::L_LEAF]);
+    v.ren = reinterpret_cast<int32_t *>(b + p->off[vplmc_lightcut_plan::L_REN]);
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vplmc_lightcut_plan_create(const vplmc_light_tree *tree, int32_t n_samples, int32_t max_cut,
+                               vplmc_lightcut_plan **out) {
+    if (!out) return set_error(VPLMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!tree) return set_error(VPLMC_EINVAL, "tree is NULL");
+    const int64_t n = tree->n_leaves;
+    if (n < 1 || n > VPLMC_MAX_TREE_LEAVES)
+        return set_error(VPLMC_EINVAL, "n_leaves %lld outside [1, %d]", (long long)n, VPLMC_MAX_TREE_LEAVES);
+    if (!tree->perm || (n > 1 && (!tree->left || !tree->right))) return set_error(VPLMC_EINVAL, "tree arrays must be non-NULL");
+    if (n_samples < 0) return set_error(VPLMC_EINVAL, "n_samples must be >= 0");
+    if (max_cut < 1) return set_error(VPLMC_EINVAL, "max_cut must be >= 1");
+    const int64_t N = 2 * n - 1;
+    std::vector<int32_t> seen(n, 0);
+    for (int64_t x = 0; x < n; ++x) {
+        const int32_t j = tree->perm[x];
+        if (j < 0 || j >= n || seen[j]) return set_error(VPLMC_EINVAL, "perm is not a permutation of 0 .. %lld", (long long)(n - 1));
+        seen[j] = 1;
+    }
+    std::vector<int32_t> parent(N, -1), height(N, 0), min_leaf(N), max_leaf(N), depth(N, 0);
+    for (int64_t x = 0; x < N; ++x) min_leaf[x] = max_leaf[x] = (int32_t)x;
+    for (int64_t k = 0; k + 1 < n; ++k) {
+        const int64_t f = n + k;
+        const int32_t l = tree->left[k], r = tree->right[k];
+        if (l < 0 || r < 0 || l >= f || r >= f || l == r)
+            return set_error(VPLMC_EINVAL, "tree: split node %lld has children %d, %d (must be distinct and earlier)", (long long)f, l, r);
+        if (parent[l] >= 0 || parent[r] >= 0) return set_error(VPLMC_EINVAL, "tree: node %d or %d already has a parent", l, r);
+        if (max_leaf[l] + 1 != min_leaf[r])
+            return set_error(VPLMC_EINVAL, "tree: the leaves of node %lld are not contiguous (left before right)", (long long)f);
+        parent[l] = parent[r] = (int32_t)f;
+        height[f] = 1 + std::max(height[l], height[r]);
+        min_leaf[f] = min_leaf[l];
+        max_leaf[f] = max_leaf[r];
+    }
+    auto plan = new (std::nothrow) vplmc_lightcut_plan;
+    if (!plan) return set_error(VPLMC_ENOMEM, "host allocation failed");
+    plan->n = (int32_t)n;
+    plan->S = n_samples;
+    plan->cap = max_cut;
+    plan->F = (int32_t)(2 * std::min<int64_t>(max_cut, n));
+    plan->height_max = n > 1 ? height[N - 1] : 0;
+    int32_t dmax = 0;
+    for (int64_t f = N - 1; f >= n; --f) {
+        const int64_t k = f - n;
+        depth[tree->left[k]] = depth[tree->right[k]] = depth[f] + 1;
+        dmax = std::max(dmax, depth[f] + 1);
+    }
+    plan->depth = dmax;
+    const int H = plan->height_max;
+    plan->level_off.assign(H + 1, 0);
+    for (int64_t k = 0; k + 1 < n; ++k) plan->level_off[height[n + k]]++;
+    for (int h = 1; h <= H; ++h) plan->level_off[h] += plan->level_off[h - 1];
+    std::vector<int32_t> order(n - 1), fill(plan->level_off.begin(), plan->level_off.end());
+    for (int64_t k = 0; k + 1 < n; ++k) order[fill[height[n + k] - 1]++] = (int32_t)(n + k);
+    plan->upload.reserve(n + 3 * (n - 1) + N);
+    plan->upload.insert(plan->upload.end(), tree->perm, tree->perm + n);
+    if (n > 1) {
+        plan->upload.insert(plan->upload.end(), tree->left, tree->left + (n - 1));
+        plan->upload.insert(plan->upload.end(), tree->right, tree->right + (n - 1));
+    }
+    plan->upload.insert(plan->upload.end(), order.begin(), order.end());
+    plan->upload.insert(plan->upload.end(), min_leaf.begin(), min_leaf.end());
+    const size_t S = n_samples, F = plan->F, cap = max_cut;
+    const size_t chunks = (std::min<size_t>(cap, n) + LC_UPDATE_CHUNK - 1) / LC_UPDATE_CHUNK;
+    const size_t bytes[vplmc_lightcut_plan::L_END] = {
+        plan->upload.size() * 4, (size_t)N * 4, (size_t)N * 36, (size_t)N * 24, S * 36, S * 8, S * 4,
+        chunks * S * 8, (size_t)N * 4, 2 * F * 4, 2 * F * 4, cap * 4, 8 * 4, (size_t)n * 4, (size_t)N * 4};
+    size_t o = 0;
+    for (int r = 0; r < vplmc_lightcut_plan::L_END; ++r) {
+        plan->off[r] = o;
+        o += align256(bytes[r]);
+    }
+    plan->off[vplmc_lightcut_plan::L_END] = o;
+    *out = plan;
+    return VPLMC_OK;
+}
+
+int vplmc_lightcut_plan_destroy(vplmc_lightcut_plan *plan) {
+    delete plan;
+    return VPLMC_OK;
+}
+
+int vplmc_lightcut_workspace_size(const vplmc_lightcut_plan *plan, size_t *bytes) {
+    if (!plan || !bytes) return set_error(VPLMC_EINVAL, "plan and bytes must be non-NULL");
+    *bytes = plan->off[vplmc_lightcut_plan::L_END];
+    return VPLMC_OK;
+}
+
+int vplmc_lightcut(vplmc_ctx *ctx, const vplmc_lightcut_plan *plan, const vplmc_points *points,
+                   const vplmc_lights *vpls, const int32_t *sample_ids, double eps, float r_min, uint64_t seed,
+                   void *workspace, size_t workspace_bytes, int32_t *n_cut, int32_t *cut_nodes, int32_t *cut_offsets,
+                   int32_t *above_left, int32_t *above_right, float *rho) {
+    if (!ctx || !plan || !points || !vpls) return set_error(VPLMC_EINVAL, "NULL argument");
+    if (vpls->n != plan->n) return set_error(VPLMC_EINVAL, "vpls->n = %d, the tree has %d leaves", vpls->n, plan->n);
+    if (bad_ptrs_lights(vpls)) return set_error(VPLMC_EINVAL, "incomplete VPL arrays");
+    if (plan->S > 0 && (points->m < 1 || bad_ptrs_points(points) || !sample_ids))
+        return set_error(VPLMC_EINVAL, "samples need points and sample_ids");
+    if (!(eps >= 0.0)) return set_error(VPLMC_EINVAL, "eps must be >= 0");
+    if (!(r_min > 0.0f) || !std::isfinite(r_min)) return set_error(VPLMC_EINVAL, "r_min must be finite and > 0");
+    if (!n_cut || !cut_nodes || !cut_offsets) return set_error(VPLMC_EINVAL, "n_cut, cut_nodes and cut_offsets must be non-NULL");
+    const size_t need = plan->off[vplmc_lightcut_plan::L_END];
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return set_error(VPLMC_EINVAL, "workspace must be 256-byte aligned and hold %zu bytes", need);
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    VPLMC_HIP(hipMemcpyAsync(static_cast<char *>(workspace) + plan->off[vplmc_lightcut_plan::L_TREE],
+                             plan->upload.data(), plan->upload.size() * 4, hipMemcpyHostToDevice, st));
+    const LightcutView v = lightcut_view(plan, workspace, sample_ids);
+    return launch_lightcut(st, v, plan->level_off.data(), plan->height_max, plan->depth, *points, *vpls, eps, r_min,
+                           seed, n_cut, cut_nodes, cut_offsets, above_left, above_right, rho);
 }
 
 }  // extern "C"

@@ -59,17 +59,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total,
     return base + incl - v;
 }
 
-__device__ __forceinline__ double total_t(float r, float g, float b) {
-    return ((double)r + (double)g) + (double)b;
-}
-
-// max(1, floor(2^24 t / tmax)), or 1 when tmax is not positive
-__device__ __forceinline__ uint64_t quantise(double t, double tmax) {
-    if (!(tmax > 0.0)) return 1;
-    const double f = floor((16777216.0 * t) / tmax);
-    return f > 1.0 ? (uint64_t)f : 1ull;
-}
-
 // Split nodes level by level (children first): kept / dropped child,
 // representative, light, intensity, bbox, member count.  Leaves were written
 // by the cluster table (planes of stride NC); member counts of leaves come
@@ -85,26 +74,9 @@ __global__ __launch_bounds__(CT) void k_node_table(CoarsenTree tr, const int32_t
         for (int idx = tr.level_off[h - 1] + t; idx < tr.level_off[h]; idx += CT) {
             const int f = tr.order[idx], k = f - ng;
             const int l = tr.left[k], r = tr.right[k];
-            const float ir = (float)((double)lights[6 * N + l] + (double)lights[6 * N + r]);
-            const float ig = (float)((double)lights[7 * N + l] + (double)lights[7 * N + r]);
-            const float ib = (float)((double)lights[8 * N + l] + (double)lights[8 * N + r]);
-            const double tl = total_t(lights[6 * N + l], lights[7 * N + l], lights[8 * N + l]);
-            const double trr = total_t(lights[6 * N + r], lights[7 * N + r], lights[8 * N + r]);
-            const double tmax = tl > trr ? tl : trr;
-            const uint64_t ql = quantise(tl, tmax), qr = quantise(trr, tmax);
-            const uint64_t u = mulhi64(philox(seed, 0, (uint64_t)f, 0, TAG_TREE, 0).a, ql + qr);
-            const int a = u < ql ? l : r, b = u < ql ? r : l;
+            const int a = combine_node(rep, lights, bbox, N, f, l, r, seed, TAG_TREE);
             kept[k] = a;
-            dropped[k] = b;
-            rep[f] = rep[a];
-            for (int p = 0; p < 6; ++p) lights[p * N + f] = lights[p * N + a];
-            lights[6 * N + f] = ir;
-            lights[7 * N + f] = ig;
-            lights[8 * N + f] = ib;
-            for (int p = 0; p < 3; ++p) {
-                bbox[p * N + f] = fminf(bbox[p * N + l], bbox[p * N + r]);
-                bbox[(3 + p) * N + f] = fmaxf(bbox[(3 + p) * N + l], bbox[(3 + p) * N + r]);
-            }
+            dropped[k] = a == l ? r : l;
             members[f] = members[l] + members[r];
         }
         __syncthreads();

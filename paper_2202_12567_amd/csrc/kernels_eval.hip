@@ -14,17 +14,10 @@
 #include <algorithm>
 
 #include "vplmc_internal.h"
+#include "shading.h"
 
 namespace vplmc {
 namespace {
-
-constexpr float INV_PI = 0.318309886183790671538f;
-
-struct P3 {
-    float x, y, z;
-};
-__device__ __forceinline__ P3 sub(P3 a, P3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ float dot(P3 a, P3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
 
 // The BVH as read by a traversal: from global memory, or from a copy staged
 // in LDS (nodes as pairs of float4, then the spheres).
@@ -94,30 +87,6 @@ __device__ __forceinline__ bool occluded_in(const B &bvh, int n_nodes, P3 o, P3 
     return false;
 }
 
-
-struct PointData {
-    P3 x, n, wo;
-    float kd0, kd1, kd2, ks, e;
-};
-
-__device__ __forceinline__ PointData load_point(const vplmc_points &p, int i) {
-    i = clamp_index(i, p.m);
-    PointData q;
-    q.x = {p.px[i], p.py[i], p.pz[i]};
-    q.n = {p.nx[i], p.ny[i], p.nz[i]};
-    q.kd0 = p.kd_r[i];
-    q.kd1 = p.kd_g[i];
-    q.kd2 = p.kd_b[i];
-    q.ks = p.ks ? p.ks[i] : 0.0f;
-    q.e = p.phong_e ? p.phong_e[i] : 1.0f;
-    q.wo = p.vx ? P3{p.vx[i], p.vy[i], p.vz[i]} : P3{0.0f, 0.0f, 1.0f};
-    return q;
-}
-
-struct Light {
-    P3 y, n;
-    float i0, i1, i2;
-};
 
 // entry of one (point, light) pair (zero when the pair faces away or is
 // occluded); bvh is a BVH view (BvhGlobal or BvhStaged) of n_nodes nodes.
@@ -264,11 +233,6 @@ __device__ __forceinline__ uint64_t feistel_zeta(uint64_t v, uint64_t seed, uint
     return (L << h) | R;
 }
 
-__device__ __forceinline__ Light node_light(const float *__restrict__ lights, size_t N, int c, bool unit) {
-    return Light{{lights[c], lights[N + c], lights[2 * N + c]},
-                 {lights[3 * N + c], lights[4 * N + c], lights[5 * N + c]},
-                 unit ? 1.0f : lights[6 * N + c], unit ? 1.0f : lights[7 * N + c], unit ? 1.0f : lights[8 * N + c]};
-}
 
 // six wavefronts per SIMD (80 VGPRs): the walk's latency needs the occupancy;
 // at 83 VGPRs (five) the kernel ran 14% slower on the 1080p frame

@@ -235,3 +235,68 @@ def test_any_rank_is_padded_to_a_kernel_rank(q, qp):
     assert lib.vplmc_plan_slice(h, 1, ctypes.byref(info)) == 0
     assert info.off_x == 64 * qp and info.off_y == 3 * 64 * qp
     lib.vplmc_plan_destroy(h)
+
+
+# ---------------------------------------------------------------- global light cut plan
+def lightcut_plan(perm, left, right, n_samples=16, max_cut=8):
+    lib = N.load()
+    perm = np.ascontiguousarray(perm, np.int32)
+    left = np.ascontiguousarray(left, np.int32)
+    right = np.ascontiguousarray(right, np.int32)
+    f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    tree = N.LightTree(perm.shape[0], f(perm), f(left), f(right))
+    h = ctypes.c_void_p()
+    rc = lib.vplmc_lightcut_plan_create(ctypes.byref(tree), n_samples, max_cut, ctypes.byref(h))
+    return rc, h
+
+
+def test_lightcut_plan_accepts_the_scene_trees_and_sizes_its_workspace():
+    import scenegen
+    lib = N.load()
+    rng = np.random.default_rng(0)
+    for n in (1, 2, 5, 300):
+        perm, left, right = scenegen.full_light_tree(rng.uniform(size=(n, 3)))
+        rc, h = lightcut_plan(perm, left, right, n_samples=100, max_cut=64)
+        assert rc == 0, N.load().vplmc_last_error()
+        sz = ctypes.c_size_t()
+        assert lib.vplmc_lightcut_workspace_size(h, ctypes.byref(sz)) == 0
+        # at least the node table (rep, 9 light planes, 6 box planes) and the samples' state
+        assert sz.value >= (2 * n - 1) * 64 + 100 * (36 + 8 + 4)
+        assert lib.vplmc_lightcut_plan_destroy(h) == 0
+
+
+@pytest.mark.parametrize("perm,left,right,why", [
+    ([0, 0, 1], [0, 3], [1, 2], "permutation"),          # perm repeats a VPL
+    ([0, 1, 2], [0, 3], [2, 1], "contiguous"),           # node 3 = (0, 2) skips leaf 1
+    ([0, 1, 2], [1, 3], [0, 2], "contiguous"),           # right child's leaves before the left's
+    ([0, 1, 2], [0, 4], [1, 2], "earlier"),              # a child after its parent
+    ([0, 1, 2], [0, 0], [1, 2], "earlier"),              # root's children must be distinct / not reused
+])
+def test_lightcut_plan_rejects_bad_trees(perm, left, right, why):
+    rc, h = lightcut_plan(perm, left, right)
+    assert rc == N.EINVAL and h.value is None
+    msg = N.load().vplmc_last_error().decode()
+    assert why in msg or "parent" in msg or "distinct" in msg, msg
+
+
+def test_lightcut_plan_rejects_bad_sizes():
+    rc, _ = lightcut_plan([0, 1], [0], [1], n_samples=-1)
+    assert rc == N.EINVAL
+    rc, _ = lightcut_plan([0, 1], [0], [1], max_cut=0)
+    assert rc == N.EINVAL
+    lib = N.load()
+    h = ctypes.c_void_p()
+    assert lib.vplmc_lightcut_plan_create(None, 4, 4, ctypes.byref(h)) == N.EINVAL
+    tree = N.LightTree(0, None, None, None)
+    assert lib.vplmc_lightcut_plan_create(ctypes.byref(tree), 4, 4, ctypes.byref(h)) == N.EINVAL
+
+
+def test_lightcut_call_validates_before_touching_the_gpu():
+    lib = N.load()
+    rc, h = lightcut_plan([0, 1], [0], [1])
+    assert rc == 0
+    pts, vpl = N.Points(), N.Lights()
+    # no context: rejected on the host
+    assert lib.vplmc_lightcut(None, h, ctypes.byref(pts), ctypes.byref(vpl), None, 0.02, 0.05, 0, None, 0,
+                              None, None, None, None, None, None) == N.EINVAL
+    lib.vplmc_lightcut_plan_destroy(h)
