@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--sweep", default="0.5,1,2,3,5,7.5,10",
                     help="total sampling rates (percent) of the plain vs learned fixed-RMSE comparison; empty: none")
     ap.add_argument("--sweep-steps", type=int, default=1)
+    ap.add_argument("--lightcut", default="0.02:16384:8192",
+                    help="EPS:MAX_CUT:SAMPLES of the global light cut timed over every VPL (Sec. 3 step 1); "
+                         "'none' to skip")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the completion variants and the rank sweep at the headline rate")
     ap.add_argument("--eager", action="store_true",
@@ -491,6 +494,46 @@ def main():
             torch.cuda.empty_cache()
         sc.rank = rank0
 
+    # the global light cut over the full light tree of every VPL (Sec. 3 step
+    # 1, Sec. 6): the tree is an input (built on the host, outside the timing);
+    # the call uploads it, builds the node table and runs the level-by-level
+    # split test on the GPU
+    lightcut = None
+    if args.lightcut != "none":
+        from scenegen import full_light_tree
+        lc_eps, lc_cap, lc_S = args.lightcut.split(":")
+        lc_eps, lc_cap, lc_S = float(lc_eps), int(lc_cap), min(int(lc_S), sc.m)
+        ws = None
+        torch.cuda.empty_cache()
+        perm, left, right = full_light_tree(np.stack([sc.vpls["x"], sc.vpls["y"], sc.vpls["z"]], 1))
+        lp = api.LightcutPlan(perm, left, right, lc_S, lc_cap)
+        wsl = lp.workspace(dev)
+        sid = torch.as_tensor(np.sort(np.random.default_rng(seed).choice(sc.m, lc_S, replace=False)).astype(np.int32),
+                              device=dev)
+        run = lambda: api.lightcut(ctx, lp, ds, sid, lc_eps, prm.r_min, seed, wsl, want_rho=True)
+        out_lc = run()
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 10))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record()
+        for k in range(reps):
+            out_lc = run()
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        lc_ms = ev[0].elapsed_time(ev[-1]) / reps
+        ng = int(out_lc["n_cut"].item())
+        rho_lc = out_lc["rho"].cpu().numpy()
+        n_tested = int((rho_lc >= 0).sum())
+        lightcut = {"vpls": sc.n, "samples": lc_S, "eps": lc_eps, "max_cut": lc_cap, "cut_nodes": ng,
+                    "tested_nodes": n_tested, "ms": round(lc_ms, 3),
+                    "bound_evaluations": n_tested * lc_S,
+                    "estimate_entries": 2 * (ng - 1) * lc_S,
+                    "timing": f"HIP events around {reps} calls (tree upload, node table, levels, output)"}
+        progress(f"global light cut: {ng} nodes in {lc_ms:.2f} ms")
+        del wsl
+        lp.close()
+        torch.cuda.empty_cache()
+
     if coarsen:
         rate_txt = (f"every slice coarsened from {coarsen[0]} row draws to at most {coarsen[1]} of the "
                     f"{sc.n_clusters}-cluster cut's nodes, second pass {rate:g}% ({ppm2} ppm) of the coarsened "
@@ -534,6 +577,7 @@ def main():
         "learned": learned,
         "fixed_rmse": fixed,
         "variants": variants,
+        "global_lightcut": lightcut,
     }
     if not args.no_cpu_baseline:
         progress("oracle on the host ...")

@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "vplmc_internal.h"
+#include "lightcut.h"
 
 namespace vplmc {
 
@@ -1399,7 +1400,7 @@ struct vplmc_lightcut_plan {
     std::vector<int32_t> upload;      // perm | left | right | order | min_leaf
     std::vector<int32_t> level_off;   // height_max + 1
     enum { L_TREE, L_REP, L_LIGHTS, L_BBOX, L_SAMP, L_EST, L_INV, L_PART, L_STATE, L_FRONT, L_RHO, L_SPLIT, L_CTL,
-           L_LEAF, L_REN, L_END };
+           L_LEAF, L_REN, L_BLK, L_END };
     size_t off[L_END + 1] = {};
 };
 
@@ -1434,6 +1435,7 @@ LightcutView lightcut_view(const vplmc_lightcut_plan *p, void *ws, const int32_t
     v.ctl = reinterpret_cast<int32_t *>(b + p->off[vplmc_lightcut_plan::L_CTL]);
     v.leafmark = reinterpret_cast<int32_t *>(b + p->off[vplmc_lightcut_plan::L_LEAF]);
     v.ren = reinterpret_cast<int32_t *>(b + p->off[vplmc_lightcut_plan::L_REN]);
+    v.blk = reinterpret_cast<uint32_t *>(b + p->off[vplmc_lightcut_plan::L_BLK]);
     return v;
 }
 
@@ -1506,7 +1508,8 @@ int vplmc_lightcut_plan_create(const vplmc_light_tree *tree, int32_t n_samples, 
     const size_t chunks = (std::min<size_t>(cap, n) + LC_UPDATE_CHUNK - 1) / LC_UPDATE_CHUNK;
     const size_t bytes[vplmc_lightcut_plan::L_END] = {
         plan->upload.size() * 4, (size_t)N * 4, (size_t)N * 36, (size_t)N * 24, S * 36, S * 8, S * 4,
-        chunks * S * 8, (size_t)N * 4, 2 * F * 4, 2 * F * 4, cap * 4, 8 * 4, (size_t)n * 4, (size_t)N * 4};
+        chunks * S * 8, (size_t)N * 4, 2 * F * 4, 2 * F * 4, cap * 4, 8 * 4, (size_t)n * 4, (size_t)N * 4,
+        2 * (size_t)((n + LC_ORDER_BLOCK - 1) / LC_ORDER_BLOCK) * 4};
     size_t o = 0;
     for (int r = 0; r < vplmc_lightcut_plan::L_END; ++r) {
         plan->off[r] = o;

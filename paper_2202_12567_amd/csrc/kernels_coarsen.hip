@@ -27,6 +27,7 @@
 // available.  The L-th key is found by an MSB-first radix select.
 
 #include "vplmc_internal.h"
+#include "tree_nodes.h"
 
 namespace vplmc {
 namespace {

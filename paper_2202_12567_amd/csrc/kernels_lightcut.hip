@@ -8,9 +8,9 @@
 //
 // Per sample pixel x (k_lc_samples): M_c = kd_c / pi + ks (e + 2) / (2 pi)
 // (the material bound) and est(x), the unoccluded sum of the current cut's
-// entries, kept in FP64 and updated by every split: est += A(l) + A(r) - A(f)
-// (k_lc_update over chunks of splits, then k_lc_est in chunk order, so the
-// sums do not depend on scheduling).
+// entries, kept in FP64 and updated by every split f -> (a kept, b):
+// est += I_b (S(rep_b) - S(rep_a)) (k_lc_update over chunks of splits, then
+// k_lc_est in chunk order, so the sums do not depend on scheduling).
 //
 // Per level (k_lc_test, k_lc_select, k_lc_update, k_lc_est):
 //   bound(x, f) = c_ub / max(d_min^2, r_min^2) * sum_c M_c I_f,c
@@ -24,14 +24,16 @@
 // which case the cap - |cut| largest rho split (ties to the lower id, found
 // by an MSB-first radix select on (~bits(rho), id)) and the cut is final.
 //
-// Output (k_lc_mark, k_lc_order, k_lc_above): the cut by smallest leaf and
+// Output (k_lc_mark, k_lc_count, k_lc_scan_blocks, k_lc_emit, k_lc_above): the cut by smallest leaf and
 // the tree above it with the cut's nodes as leaves 0 .. n_g - 1 and the
 // split nodes after them by increasing tree id.
 
 #include <algorithm>
 
 #include "vplmc_internal.h"
+#include "lightcut.h"
 #include "shading.h"
+#include "tree_nodes.h"
 
 namespace vplmc {
 namespace {
@@ -41,6 +43,8 @@ constexpr int LT = 256;          // threads of the grid kernels
 constexpr int CHUNK = 4 * LT;    // samples per tile of the split test
 constexpr int ST = 1024;         // threads of the single-workgroup kernels
 constexpr int UPD = LC_UPDATE_CHUNK;
+constexpr int OT = 256;               // threads of the ordering kernels
+constexpr int OE = LC_ORDER_BLOCK;    // leaves per ordering block
 
 __global__ void k_lc_fill_u32(uint32_t *p, size_t n, uint32_t v) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -169,6 +173,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
     return x;
 }
 
+template <int T>
 __device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t *sm) {
     const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
 #pragma unroll
@@ -176,19 +181,20 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t *sm) {
     if (lane == 0) sm[w] = x;
     __syncthreads();
     uint32_t tot = 0;
-    for (int k = 0; k < ST / WAVE; ++k) tot += sm[k];
+    for (int k = 0; k < T / WAVE; ++k) tot += sm[k];
     __syncthreads();
     return tot;
 }
 
-// exclusive scan over the ST threads; the block total in *total
+// exclusive scan over the T threads of the block; the block total in *total
+template <int T>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *total, uint32_t *sm) {
     const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
     const uint32_t incl = wave_incl_scan(x, lane);
     if (lane == WAVE - 1) sm[w] = incl;
     __syncthreads();
     uint32_t base = 0, tot = 0;
-    for (int k = 0; k < ST / WAVE; ++k) {
+    for (int k = 0; k < T / WAVE; ++k) {
         if (k < w) base += sm[k];
         tot += sm[k];
     }
@@ -232,7 +238,7 @@ __global__ __launch_bounds__(ST) void k_lc_select(LightcutView v, int p, double 
             if (rho_out) rho_out[f] = r;
         }
     }
-    const uint32_t F = block_sum(fails, sm);
+    const uint32_t F = block_sum<ST>(fails, sm);
     const int n_cut = v.ctl[2];
     int64_t room = (int64_t)v.cap - n_cut;
     if (room < 0) room = 0;
@@ -283,7 +289,7 @@ __global__ __launch_bounds__(ST) void k_lc_select(LightcutView v, int p, double 
                 ch = !capped ? 1u : (room > 0 && cap_key(rho[i], f) <= T ? 1u : 0u);
         }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan(ch, &tot, sm);
+        const uint32_t ex = block_excl_scan<ST>(ch, &tot, sm);
         const uint32_t j = carry_s + ex;
         if (ch) {
             const int l = v.left[f - n], r = v.right[f - n];
@@ -309,22 +315,29 @@ __global__ __launch_bounds__(ST) void k_lc_select(LightcutView v, int p, double 
     }
 }
 
-// est(x) changes of the level's splits, one chunk of UPD splits per blockIdx.y
+// est(x) changes of the level's splits, one chunk of UPD splits per blockIdx.y.
+// Split node f holds the light of its kept child a, so replacing f by a and
+// b changes est by A(a) + A(b) - A(f) = I_b (S(rep_b) - S(rep_a)) channel by
+// channel, S the lighting at unit intensity: two entries per split.
 __global__ __launch_bounds__(LT) void k_lc_update(LightcutView v, vplmc_points pts, float r_min2) {
-    __shared__ float lt[3 * 9][UPD];
+    __shared__ float lt[15][UPD];    // rep_a position, normal; rep_b position, normal; I_b
     const int ns = v.ctl[3];
     const int c = blockIdx.y;
-    const int b = c * UPD;
-    if (b >= ns) return;
-    const int cnt = ns - b < UPD ? ns - b : UPD;
+    const int b0 = c * UPD;
+    if (b0 >= ns) return;
+    const int cnt = ns - b0 < UPD ? ns - b0 : UPD;
     const size_t N = 2 * (size_t)v.n - 1;
     for (int k = threadIdx.x; k < cnt; k += LT) {
-        const int f = v.split[b + k];
-        const int nodes[3] = {f, v.left[f - v.n], v.right[f - v.n]};
+        const int f = v.split[b0 + k];
+        const int l = v.left[f - v.n], r = v.right[f - v.n];
+        const int a = v.rep[f] == v.rep[l] ? l : r, b = a == l ? r : l;
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int pl = 0; pl < 6; ++pl) {
+            lt[pl][k] = v.lights[pl * N + a];
+            lt[6 + pl][k] = v.lights[pl * N + b];
+        }
 #pragma unroll
-            for (int pl = 0; pl < 9; ++pl) lt[a * 9 + pl][k] = v.lights[pl * N + nodes[a]];
+        for (int ch = 0; ch < 3; ++ch) lt[12 + ch][k] = v.lights[(6 + ch) * N + b];
     }
     __syncthreads();
     const int s = blockIdx.x * LT + threadIdx.x;
@@ -332,16 +345,10 @@ __global__ __launch_bounds__(LT) void k_lc_update(LightcutView v, vplmc_points p
     const PointData q = load_point(pts, v.sample_ids[s]);
     double acc = 0.0;
     for (int k = 0; k < cnt; ++k) {
-        double d = 0.0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const Light L{{lt[a * 9][k], lt[a * 9 + 1][k], lt[a * 9 + 2][k]},
-                          {lt[a * 9 + 3][k], lt[a * 9 + 4][k], lt[a * 9 + 5][k]},
-                          lt[a * 9 + 6][k], lt[a * 9 + 7][k], lt[a * 9 + 8][k]};
-            const double e = entry_sum(q, L, r_min2);
-            d += a == 0 ? -e : e;
-        }
-        acc += d;
+        const float i0 = lt[12][k], i1 = lt[13][k], i2 = lt[14][k];
+        const Light La{{lt[0][k], lt[1][k], lt[2][k]}, {lt[3][k], lt[4][k], lt[5][k]}, i0, i1, i2};
+        const Light Lb{{lt[6][k], lt[7][k], lt[8][k]}, {lt[9][k], lt[10][k], lt[11][k]}, i0, i1, i2};
+        acc += entry_sum(q, Lb, r_min2) - entry_sum(q, La, r_min2);
     }
     v.part[(size_t)c * v.S + s] = acc;
 }
@@ -363,46 +370,77 @@ __global__ void k_lc_mark(LightcutView v) {
     if (f < N && v.state[f] == 1) v.leafmark[v.min_leaf[f]] = (int32_t)f;
 }
 
-// cut nodes by smallest leaf, then the split nodes by tree id
-__global__ __launch_bounds__(ST) void k_lc_order(LightcutView v, int32_t *n_cut, int32_t *cut_nodes,
-                                                 int32_t *cut_offsets) {
+// Output order in three passes over blocks of OE leaves (and split nodes
+// n + x for the same x): counts per block, their exclusive scan, then each
+// block's own scan.  Cut nodes are numbered by smallest leaf, split nodes
+// n_cut + their rank by tree id.
+__global__ __launch_bounds__(OT) void k_lc_count(LightcutView v) {
+    __shared__ uint32_t sm[OT / WAVE];
+    const int b = blockIdx.x, t = threadIdx.x, n = v.n;
+    uint32_t cl = 0, cs = 0;
+    for (int k = 0; k < OE / OT; ++k) {
+        const int x = b * OE + k * OT + t;
+        if (x < n && v.leafmark[x] >= 0) ++cl;
+        if (x < n - 1 && v.state[n + x] == 2) ++cs;
+    }
+    const uint32_t tl = block_sum<OT>(cl, sm);
+    const uint32_t ts = block_sum<OT>(cs, sm);
+    if (t == 0) {
+        v.blk[b] = tl;
+        v.blk[gridDim.x + b] = ts;
+    }
+}
+
+__global__ __launch_bounds__(ST) void k_lc_scan_blocks(LightcutView v, int nb, int32_t *n_cut, int32_t *cut_offsets) {
     __shared__ uint32_t sm[ST / WAVE];
     __shared__ uint32_t carry_s;
-    const int t = threadIdx.x, n = v.n;
-    if (t == 0) carry_s = 0;
-    __syncthreads();
-    for (int x0 = 0; x0 < n; x0 += ST) {
-        const int x = x0 + t;
-        const int f = x < n ? v.leafmark[x] : -1;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(f >= 0 ? 1u : 0u, &tot, sm);
-        const uint32_t k = carry_s + ex;
-        if (f >= 0) {
-            cut_nodes[k] = f;
-            cut_offsets[k] = x;
-            v.ren[f] = (int32_t)k;
+    const int t = threadIdx.x;
+    uint32_t totals[2];
+    for (int a = 0; a < 2; ++a) {
+        uint32_t *c = v.blk + (size_t)a * nb;
+        if (t == 0) carry_s = 0;
+        __syncthreads();
+        for (int b0 = 0; b0 < nb; b0 += ST) {
+            const int b = b0 + t;
+            const uint32_t x = b < nb ? c[b] : 0;
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan<ST>(x, &tot, sm);
+            if (b < nb) c[b] = carry_s + ex;
+            __syncthreads();
+            if (t == 0) carry_s += tot;
+            __syncthreads();
         }
-        __syncthreads();
-        if (t == 0) carry_s += tot;
+        totals[a] = carry_s;
         __syncthreads();
     }
-    const uint32_t ng = carry_s;
     if (t == 0) {
-        cut_offsets[ng] = n;
-        *n_cut = (int32_t)ng;
+        *n_cut = (int32_t)totals[0];
+        cut_offsets[totals[0]] = v.n;
+        v.ctl[5] = (int32_t)totals[0];
     }
-    __syncthreads();
-    if (t == 0) carry_s = 0;
-    __syncthreads();
-    for (int k0 = 0; k0 < n - 1; k0 += ST) {
-        const int k = k0 + t;
-        const bool sp = k < n - 1 && v.state[n + k] == 2;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(sp ? 1u : 0u, &tot, sm);
-        if (sp) v.ren[n + k] = (int32_t)(ng + carry_s + ex);
-        __syncthreads();
-        if (t == 0) carry_s += tot;
-        __syncthreads();
+}
+
+__global__ __launch_bounds__(OT) void k_lc_emit(LightcutView v, int nb, int32_t *cut_nodes, int32_t *cut_offsets) {
+    __shared__ uint32_t sm[OT / WAVE];
+    const int b = blockIdx.x, t = threadIdx.x, n = v.n;
+    const uint32_t ng = (uint32_t)v.ctl[5];
+    uint32_t cl = v.blk[b], cs = v.blk[nb + b];
+    for (int k = 0; k < OE / OT; ++k) {
+        const int x = b * OE + k * OT + t;
+        const int f = x < n ? v.leafmark[x] : -1;
+        const bool sp = x < n - 1 && v.state[n + x] == 2;
+        uint32_t tl, ts;
+        const uint32_t el = block_excl_scan<OT>(f >= 0 ? 1u : 0u, &tl, sm);
+        const uint32_t es = block_excl_scan<OT>(sp ? 1u : 0u, &ts, sm);
+        if (f >= 0) {
+            const uint32_t j = cl + el;
+            cut_nodes[j] = f;
+            cut_offsets[j] = x;
+            v.ren[f] = (int32_t)j;
+        }
+        if (sp) v.ren[n + x] = (int32_t)(ng + cs + es);
+        cl += tl;
+        cs += ts;
     }
 }
 
@@ -468,7 +506,12 @@ int launch_lightcut(hipStream_t st, const LightcutView &v, const int32_t *level_
     }
     hipLaunchKernelGGL(k_lc_mark, dim3(grid_for(N, LT)), dim3(LT), 0, st, v);
     VPLMC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_lc_order, dim3(1), dim3(ST), 0, st, v, n_cut, cut_nodes, cut_offsets);
+    const int nb = (v.n + OE - 1) / OE;
+    hipLaunchKernelGGL(k_lc_count, dim3(nb), dim3(OT), 0, st, v);
+    VPLMC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_lc_scan_blocks, dim3(1), dim3(ST), 0, st, v, nb, n_cut, cut_offsets);
+    VPLMC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_lc_emit, dim3(nb), dim3(OT), 0, st, v, nb, cut_nodes, cut_offsets);
     VPLMC_HIP(hipGetLastError());
     if (v.n > 1 && (above_left || above_right)) {
         hipLaunchKernelGGL(k_lc_above, dim3(grid_for(v.n - 1, LT)), dim3(LT), 0, st, v, above_left, above_right,

@@ -41,7 +41,6 @@ constexpr uint64_t TAG_INITY = 4;
 constexpr uint64_t TAG_REP = 5;
 constexpr uint64_t TAG_TREE = 6;   // kept child of a split node (light coarsening)
 constexpr uint64_t TAG_ZETA = 7;   // row draws of the light coarsening
-constexpr uint64_t TAG_LTREE = 8;  // kept child of a split node of the full light tree (global cut)
 
 struct U64x4 {
     uint64_t a, b, c, d;
@@ -73,48 +72,6 @@ __device__ __forceinline__ int clamp_index(int v, int n) { return v < 0 ? 0 : (v
 
 // floor(r * n / 2^64): a uniform 64-bit word mapped onto [0, n).
 __device__ __forceinline__ uint64_t mulhi64(uint64_t r, uint64_t n) { return __umul64hi(r, n); }
-
-// total intensity t = (R + G) + B in FP64 of FP32 channels
-__device__ __forceinline__ double total_t(float r, float g, float b) {
-    return ((double)r + (double)g) + (double)b;
-}
-
-// max(1, floor(2^24 t / tmax)), or 1 when tmax is not positive
-__device__ __forceinline__ uint64_t quantise(double t, double tmax) {
-    if (!(tmax > 0.0)) return 1;
-    const double f = floor((16777216.0 * t) / tmax);
-    return f > 1.0 ? (uint64_t)f : 1ull;
-}
-
-// A split node f of a light tree from its children l, r (Sec. 4: L_f is the
-// same light as one child L_a, I_f = I_a + I_b): the kept child a is drawn
-// with probability Q_a / (Q_l + Q_r) by Philox(key = (seed, 0),
-// ctr = (f, 0, tag, 0)); f takes a's representative and light, the FP32 sum
-// (in FP64) of both intensities and the union of both boxes.  Planes of
-// stride N: lights x y z nx ny nz ir ig ib, bbox lo xyz then hi xyz.
-// Returns a.
-__device__ __forceinline__ int combine_node(int32_t *rep, float *lights, float *bbox, size_t N, int f, int l, int r,
-                                            uint64_t seed, uint64_t tag) {
-    const float ir = (float)((double)lights[6 * N + l] + (double)lights[6 * N + r]);
-    const float ig = (float)((double)lights[7 * N + l] + (double)lights[7 * N + r]);
-    const float ib = (float)((double)lights[8 * N + l] + (double)lights[8 * N + r]);
-    const double tl = total_t(lights[6 * N + l], lights[7 * N + l], lights[8 * N + l]);
-    const double trr = total_t(lights[6 * N + r], lights[7 * N + r], lights[8 * N + r]);
-    const double tmax = tl > trr ? tl : trr;
-    const uint64_t ql = quantise(tl, tmax), qr = quantise(trr, tmax);
-    const uint64_t u = mulhi64(philox(seed, 0, (uint64_t)f, 0, tag, 0).a, ql + qr);
-    const int a = u < ql ? l : r;
-    rep[f] = rep[a];
-    for (int p = 0; p < 6; ++p) lights[p * N + f] = lights[p * N + a];
-    lights[6 * N + f] = ir;
-    lights[7 * N + f] = ig;
-    lights[8 * N + f] = ib;
-    for (int p = 0; p < 3; ++p) {
-        bbox[p * N + f] = fminf(bbox[p * N + l], bbox[p * N + r]);
-        bbox[(3 + p) * N + f] = fmaxf(bbox[(3 + p) * N + l], bbox[(3 + p) * N + r]);
-    }
-    return a;
-}
 
 // ------------------------------------------------------------ geometry
 struct BvhNode {            // 32 bytes, depth-first order: an inner node's left child follows it
@@ -251,31 +208,6 @@ struct CoarsenSlices {
     const int32_t *kept = nullptr, *dropped = nullptr;       // per split node
     const int64_t *kpre = nullptr;                           // n_leaves + 1: prefix of the draw counts
     uint16_t *zeta = nullptr;                                // per (slice, draw slot): row of the draw
-};
-
-// Global light cut over the full light tree (n leaves, N = 2 n - 1 nodes):
-// the tree as uploaded by its plan, the node table and the level-by-level
-// state, all inside the caller's workspace.
-constexpr int LC_UPDATE_CHUNK = 128;   // splits per chunk of the estimate update
-
-struct LightcutView {
-    int32_t n = 0, S = 0, cap = 0, F = 0;                  // leaves, samples, cut cap, frontier capacity
-    const int32_t *perm = nullptr, *left = nullptr, *right = nullptr;
-    const int32_t *order = nullptr, *min_leaf = nullptr;   // split nodes by height; per node
-    const int32_t *sample_ids = nullptr;
-    int32_t *rep = nullptr;                                // per node
-    float *lights = nullptr, *bbox = nullptr;              // 9 and 6 planes of N
-    float *samp = nullptr;                                 // 9 planes of S: x y z nx ny nz M_r M_g M_b
-    double *est = nullptr;                                 // S
-    float *inv_est = nullptr;                              // S: 1 / est (inf where est = 0)
-    double *part = nullptr;                                // per (split chunk, sample): estimate updates
-    uint32_t *state = nullptr;                             // per node: 0 not reached, 1 in the cut, 2 split
-    int32_t *front = nullptr;                              // [2][F] frontier of the level, by parity
-    uint32_t *rho_f = nullptr;                             // [2][F] float bits of the frontier's ratios
-    int32_t *split = nullptr;                              // cap: nodes split at the level
-    int32_t *ctl = nullptr;                                // n_front[2], n_cut, n_split, done
-    int32_t *leafmark = nullptr;                           // n: cut node starting at each leaf, or -1
-    int32_t *ren = nullptr;                                // per node: index in the output layout
 };
 
 // Regions of the workspace: byte offsets.
@@ -434,8 +366,4 @@ int launch_eval_pairs(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, c
                       int64_t n, const int32_t *pid, const int32_t *lid, const vplmc_params &prm, float *out);
 int launch_brute_force(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l,
                        int32_t n_out, const int32_t *pid, const vplmc_params &prm, double *out);
-int launch_lightcut(hipStream_t st, const LightcutView &v, const int32_t *level_off, int32_t height_max,
-                    int32_t depth, const vplmc_points &pts, const vplmc_lights &vpls, double eps, float r_min,
-                    uint64_t seed, int32_t *n_cut, int32_t *cut_nodes, int32_t *cut_offsets, int32_t *above_left,
-                    int32_t *above_right, float *rho);
 }  // namespace vplmc
