@@ -183,7 +183,8 @@ def write_traffic_record(args, csvs):
            "fetch_factor": round(ff, 4), "write_factor": round(wf, 4), "bytes_per_launch": rd + wr,
            "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
            "commands": [f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} -d <out> -o <name> --output-format csv "
-                        f"-- python3 /root/repo/bench.py --eager --steps 1 --warmup 0 --sweep \"\" --no-cpu-baseline"
+                        f"-- python3 /root/repo/bench.py --eager --steps 1 --warmup 0 --sweep \"\" --no-cpu-baseline "
+                        f"--no-variants --lightcut none"
                         for c in ("FETCH_SIZE", "WRITE_SIZE")]
            + [f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} -d <out> -o <name> --output-format csv "
               f"-- python3 /root/repo/bench.py --copy-probe 1024" for c in ("FETCH_SIZE", "WRITE_SIZE")]}

@@ -119,6 +119,62 @@ __device__ void spd_inverse(AdmShared<Q> &sh, double shift) {
     __syncthreads();
 }
 
+// The same q x q system and F from it on one wavefront, with no workgroup
+// barrier: the caller runs it on a wavefront of its own while the others
+// work on what does not need Inv or F, and orders it with the workgroup's
+// next barrier.  Cholesky with the reciprocal of each pivot, L^-1 by forward
+// substitution, Inv = L^-T L^-1; XSIDE: F = G Inv, else F[b][a] = (Inv C)[a][b].
+template <int Q, bool XSIDE>
+__device__ void spd_solve_wave(AdmShared<Q> &sh, double shift, int lane) {
+    for (int e = lane; e < Q * Q; e += WAVE) {
+        const int a = e / Q, b = e % Q;
+        sh.A[e] = (double)sh.G[e] + (a == b ? shift : 0.0);
+    }
+    wave_lds_sync();
+    for (int j = 0; j < Q; ++j) {
+        const double djj = sqrt(sh.A[j * Q + j]);
+        const double rj = 1.0 / djj;
+        for (int e = lane; e < Q * Q; e += WAVE) {
+            const int i = e / Q, k = e % Q;
+            if (k > j && i >= k) sh.A[e] -= (sh.A[i * Q + j] * rj) * (sh.A[k * Q + j] * rj);
+        }
+        wave_lds_sync();
+        for (int i = j + 1 + lane; i < Q; i += WAVE) sh.A[i * Q + j] *= rj;
+        if (lane == 0) sh.A[j * Q + j] = djj;
+        wave_lds_sync();
+    }
+    for (int i = lane; i < Q; i += WAVE) sh.Z[i * Q + i] = 1.0 / sh.A[i * Q + i];   // reciprocal pivots
+    wave_lds_sync();
+    if (lane < Q) {                             // column lane of L^-1
+        const int j = lane;
+        for (int i = j + 1; i < Q; ++i) {
+            double s = 0.0;
+            for (int l = j; l < i; ++l) s -= sh.A[i * Q + l] * sh.Z[l * Q + j];
+            sh.Z[i * Q + j] = s * sh.Z[i * Q + i];
+        }
+    }
+    wave_lds_sync();
+    for (int e = lane; e < Q * Q; e += WAVE) {  // Inv = Z^T Z
+        const int a = e / Q, b = e % Q;
+        const int lo = a > b ? a : b;
+        double s = 0.0;
+        for (int i = lo; i < Q; ++i) s += sh.Z[i * Q + a] * sh.Z[i * Q + b];
+        sh.Inv[e] = s;
+    }
+    wave_lds_sync();
+    for (int e = lane; e < Q * Q; e += WAVE) {
+        const int a = e / Q, b = e % Q;
+        double v = 0.0;
+        if (XSIDE) {
+            for (int l = 0; l < Q; ++l) v += (double)sh.G[a * Q + l] * sh.Inv[l * Q + b];
+            sh.F[e] = v;
+        } else {
+            for (int l = 0; l < Q; ++l) v += sh.Inv[a * Q + l] * (double)sh.C[l * Q + b];
+            sh.F[b * Q + a] = v;
+        }
+    }
+}
+
 // Gram G = M^T M of a (rows x Q) FP32 matrix into sh.G.  The rows stream
 // through LDS in tiles of GRAM_STAGE floats (coalesced float4 loads, the next
 // tile in flight while the current one is used); a thread owns a 4 x 4 block
@@ -993,7 +1049,10 @@ __device__ void adm_ell_slice(
     double rs_est = (msum_max + 3.0 * x1max * ymax) * (1.0 + 1e-5);   // a-priori bound for the first iterate
     double RS_est = Krow * rs_est;
     auto pow2_below = [](double lim, double b) {       // largest S in [-60, 60] with b 2^S <= lim
-        int S = b > 0.0 ? (int)floor(log2(lim / b)) : 60;
+        // start one above floor(log2(lim / b)), read off the exponent bits
+        // (no log2 call: its temporaries cost registers this kernel lacks)
+        const double qt = lim / b;
+        int S = b > 0.0 && qt < 1e300 ? (int)((__double_as_longlong(qt) >> 52) & 0x7FF) - 1023 + 1 : 60;
         S = S > 60 ? 60 : (S < -60 ? -60 : S);
         while (S > -60 && b * ldexp(1.0, S) > lim) --S;
         return S;
@@ -1003,11 +1062,12 @@ __device__ void adm_ell_slice(
         return RS * ymax * ldexp(1.0, S) * (1.0 + 1e-5) + 0.5 * Krow < 2147483647.0;
     };
 
-    const double alpha = (double)alpha0 * (3.0 * n) / qr;
-    const double beta = (double)beta0 * (double)m / qr;
-    const float alpha_f = (float)alpha, beta_f = (float)beta;
-    const float ga = (float)((double)gamma * alpha), gb = (float)((double)gamma * beta);
-    const float inv_alpha = (float)(1.0 / alpha), inv_beta = (float)(1.0 / beta);
+    // uniform constants, kept in scalar registers
+    const double alpha = uni((double)alpha0 * (3.0 * n) / qr);
+    const double beta = uni((double)beta0 * (double)m / qr);
+    const float alpha_f = uni((float)alpha), beta_f = uni((float)beta);
+    const float ga = uni((float)((double)gamma * alpha)), gb = uni((float)((double)gamma * beta));
+    const float inv_alpha = uni((float)(1.0 / alpha)), inv_beta = uni((float)(1.0 / beta));
     int iters = max_iter;
     double err = 0.0;
     for (int it = 0; it < max_iter; ++it) {
@@ -1047,12 +1107,21 @@ __device__ void adm_ell_slice(
         int S = pow2_below(1073741824.0, RS_est * ymax);
         double e2t = 0.0, RSc = 0.0;
         float rsc = 0.f;
+        bool xsys = false;
         for (;;) {
             const float fxs = ldexpf(1.f, S), fxr = ldexpf(1.f, Sr);
             for (int e = t; e < m * (Q + 1); e += THREADS) RXI[e] = 0;
             __syncthreads();
             float rsm = 0.f;
-            for (int g = wave; g < G; g += NW) {
+            // the last wavefront solves the X system (Inv, F for the X update),
+            // which needs only GY, while the others take the parts
+            if (wave == NW - 1) {
+                if (!xsys) {
+                    spd_solve_wave<Q, true>(sh, alpha, lane);
+                    xsys = true;
+                }
+            } else
+            for (int g = wave; g < G; g += NW - 1) {
                 int j, cnt, pc, np;
                 part_of(g, j, cnt, pc, np);
                 const int base = grp[g];
@@ -1214,16 +1283,7 @@ __device__ void adm_ell_slice(
                 if (e < m * Q) XB[xpos<Q>(e / Q, e % Q)] = tv[u];
             }
         }
-        // ---- X system: Inv = (GY + a I)^-1, F = GY Inv ----
-        t = fresh_tid();
-        lane = t % WAVE;
-        spd_inverse<Q>(sh, alpha);           // begins and ends with a barrier
-        for (int e = t; e < Q * Q; e += THREADS) {
-            const int a = e / Q, b = e % Q;
-            double v = 0.0;
-            for (int l = 0; l < Q; ++l) v += (double)sh.G[a * Q + l] * sh.Inv[l * Q + b];
-            sh.F[e] = v;
-        }
+        // the X system was solved during phase A; T complete before the X update reads it
         __syncthreads();
         // ---- X+ = X F + T Inv (FP32 MFMA on FP32 copies of the FP64 q x q factors), U, L, Grams X+^T X+ and X+^T X ----
         t = fresh_tid();
@@ -1263,21 +1323,15 @@ __device__ void adm_ell_slice(
             }
             sum_partials<Q, NW>(gx, cx, red, sh.G, sh.C);
         }
-        // ---- Y system: Inv = (GX + b I)^-1, F[l][k] = (Inv C)[k][l] ----
-        t = fresh_tid();
-        lane = t % WAVE;
-        spd_inverse<Q>(sh, beta);
-        for (int e = t; e < Q * Q; e += THREADS) {
-            const int a = e / Q, b = e % Q;
-            double v = 0.0;
-            for (int l = 0; l < Q; ++l) v += sh.Inv[a * Q + l] * (double)sh.C[l * Q + b];
-            sh.F[b * Q + a] = v;
-        }
-        __syncthreads();
         // ---- phase B: T_j = X+^T R_j + b V_j - P_j (columns of several parts: partial sums) ----
+        // the last wavefront meanwhile solves the Y system (Inv = (GX + b I)^-1,
+        // F[l][k] = (Inv C)[k][l]), which the Y update needs and phase B does not
         t = fresh_tid();
         lane = t % WAVE;
-        for (int g = wave; g < G; g += NW) {
+        if (wave == NW - 1)
+            spd_solve_wave<Q, false>(sh, beta, lane);
+        else
+        for (int g = wave; g < G; g += NW - 1) {
             int j, cnt, pc, np;
             part_of(g, j, cnt, pc, np);
             const int base = grp[g];
@@ -1318,16 +1372,28 @@ __device__ void adm_ell_slice(
             if (64 * g + lane < P) {
                 if (np == 1) {
                     // every load before the first store: loads and stores share
-                    // one in-order counter, so a load after a store waits for it
+                    // one in-order counter, so a load after a store waits for it.
+                    // W is added into acc one channel (q values) at a time, so
+                    // that at most q loaded values are held at once.
                     const size_t o = (size_t)j * 3 * Q;
-                    float4 wv[3 * Q / 4];
 #pragma unroll
-                    for (int v = 0; v < 3 * Q / 4; ++v) wv[v] = reinterpret_cast<const float4 *>(W + o)[v];
+                    for (int c = 0; c < 3; ++c) {
+                        float4 wv[QV];
+#pragma unroll
+                        for (int v = 0; v < QV; ++v) wv[v] = reinterpret_cast<const float4 *>(W + o)[c * QV + v];
+#pragma unroll
+                        for (int v = 0; v < QV; ++v) {
+                            const int k = 4 * (c * QV + v);
+                            acc[k] += wv[v].x;
+                            acc[k + 1] += wv[v].y;
+                            acc[k + 2] += wv[v].z;
+                            acc[k + 3] += wv[v].w;
+                        }
+                    }
 #pragma unroll
                     for (int v = 0; v < 3 * Q / 4; ++v)
                         reinterpret_cast<float4 *>(Yt + o)[v] =
-                            make_float4(acc[4 * v] + wv[v].x, acc[4 * v + 1] + wv[v].y, acc[4 * v + 2] + wv[v].z,
-                                        acc[4 * v + 3] + wv[v].w);
+                            make_float4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
                 } else {
                     float4 *pp = reinterpret_cast<float4 *>(partial + (size_t)pc * 3 * Q);
 #pragma unroll
@@ -1429,13 +1495,10 @@ __device__ void adm_ell_slice(
                     gy = mfma16(yn, yn, gy);
                 }
             };
-            for (int r0 = 16 * wave; r0 < R3; r0 += 32 * NW) {
-                const int r1 = r0 + 16 * NW;
-                float ya[QV], ta[QV], pa[4], yb[QV], tb[QV], pb[4];
+            for (int r0 = 16 * wave; r0 < R3; r0 += 16 * NW) {
+                float ya[QV], ta[QV], pa[4];
                 load_tile(r0, ya, ta, pa);
-                if (r1 < R3) load_tile(r1, yb, tb, pb);
                 do_tile(r0, ya, ta, pa);
-                if (r1 < R3) do_tile(r1, yb, tb, pb);
             }
             __threadfence_block();
             sum_partials<Q, NW>(gy, zero, red, sh.G, nullptr);
