@@ -520,7 +520,7 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     bytes[R_ELL_RES] = 3 * plan->tot_ell * 4;
     bytes[R_YT] = oy * 4;
     bytes[R_ADM_RED] = S * ADM_RED_FLOATS * 4;
-    bytes[R_E2PART] = plan->tot_part * 8;
+    bytes[R_E2PART] = plan->tot_part * 16;   // two halves per part
     bytes[R_QUEUE] = 8 * 4;
     bytes[R_COUNTS] = 4 * 8;
     bytes[VPLMC_R_FEATURES] = oc * MLP_IN * 4;

@@ -27,8 +27,6 @@
 // Every reduction has a fixed order: results are bitwise reproducible.
 
 #include <algorithm>
-#include <type_traits>
-
 #include "vplmc_internal.h"
 
 namespace vplmc {
@@ -865,6 +863,10 @@ template <int Q>
 __device__ __forceinline__ const float4 *xchunk(const float *X, int i, int c) {
     return reinterpret_cast<const float4 *>(X + i * Q + (((c + ((i * Q) >> 6)) % (Q / 4)) << 2));
 }
+template <int Q>
+__device__ __forceinline__ float4 *xchunk_w(float *X, int i, int c) {
+    return reinterpret_cast<float4 *>(X + i * Q + (((c + ((i * Q) >> 6)) % (Q / 4)) << 2));
+}
 
 // elements of the fixed-point to float pass (m q <= ADM_CVT_ELEMS)
 constexpr int ADM_CVT_ELEMS = 18 * 1024;
@@ -899,7 +901,7 @@ __device__ void adm_ell_slice(
     const int t = threadIdx.x, lane = t % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
     float *XA = dyn;                                  // X_k, row stride q
-    float *XB = dyn + (size_t)m * (Q + 1);            // fixed-point R Y^T (stride q + 1), then T and X+ (stride q)
+    float *XB = dyn + (size_t)m * (Q + 1);            // fixed-point R Y^T (stride q + 1); X+ replaces X in XA
 
     const int32_t *col_ptr = col_ptr_all + d.off_colptr;
     const int2 *part = ell.part + d.off_part;
@@ -917,11 +919,12 @@ __device__ void adm_ell_slice(
     float *Pi = Pi_all + d.off_y;
     float *Yt = Yt_all + d.off_y;
     float *red = red_all + d.off_red;
-    double *e2part = e2part_all + d.off_part;
+    double *e2part = e2part_all + 2 * d.off_part;   // per part: the two halves' sums
     int32_t *st = stats_all + 4 * s;
     const int nnz = col_ptr[n];
     const int P = pbase[n];               // parts
     const int G = (P + 63) / 64;          // groups of 64 parts
+    const bool halves = G < NW - 1;       // phase A: two wavefronts per group
     const int R3 = 3 * n;
 
     // the slice's samples in the ELL copy: entries k < length of the part at
@@ -1101,6 +1104,18 @@ __device__ void adm_ell_slice(
                 b2[v] = c < Q ? (float)sh.Inv[l * Q + c] : 0.f;
             }
         };
+        // the same with the contraction index of MFMA step v at lane row
+        // lane / 16 taken as QV (lane / 16) + v, so that a lane's operand
+        // values of one row are contiguous
+        auto load_rhs_c = [&](float *b1, float *b2) {
+            const int c = lane % 16;
+#pragma unroll
+            for (int v = 0; v < QV; ++v) {
+                const int l = QV * (lane / 16) + v;
+                b1[v] = c < Q ? (float)sh.F[l * Q + c] : 0.f;
+                b2[v] = c < Q ? (float)sh.Inv[l * Q + c] : 0.f;
+            }
+        };
         // ---- phase A: residuals, 2^S R Y^T into XB ----
         int32_t *RXI = reinterpret_cast<int32_t *>(XB);
         int Sr = pow2_below(2147483648.0, Krow * rs_est);
@@ -1120,18 +1135,26 @@ __device__ void adm_ell_slice(
                     spd_solve_wave<Q, true>(sh, alpha, lane);
                     xsys = true;
                 }
-            } else
-            for (int g = wave; g < G; g += NW - 1) {
+            } else {
+            // with fewer part groups than working wavefronts, two wavefronts
+            // share a group, the first taking entries [0, kh) of every part,
+            // the second [kh, length)
+            const int items = halves ? 2 * G : G;
+            for (int item = wave; item < items; item += NW - 1) {
+                const int g = halves ? item >> 1 : item, h = halves ? item & 1 : 0;
                 int j, cnt, pc, np;
                 part_of(g, j, cnt, pc, np);
                 const int base = grp[g];
                 const int len = (grp[g + 1] - base) >> 6;
+                const int kh = halves ? (len + 2 * ADM_DA - 1) / (2 * ADM_DA) * ADM_DA : len;
+                const int kb = h ? kh : 0, ke = h ? len : kh;
+                const int ce = cnt < ke ? cnt : ke;          // the lane's entries: [kb, ce)
                 double e2 = 0.0;
                 float y[3 * Q];
                 const float4 *y4 = reinterpret_cast<const float4 *>(Y + (size_t)j * 3 * Q);
 #pragma unroll
                 for (int v = 0; v < 3 * Q / 4; ++v) {
-                    const float4 a = cnt > 0 ? y4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    const float4 a = ce > kb ? y4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
                     y[4 * v] = a.x;
                     y[4 * v + 1] = a.y;
                     y[4 * v + 2] = a.z;
@@ -1142,7 +1165,7 @@ __device__ void adm_ell_slice(
                 auto load_block = [&](int k0, int *ib, float *mb0, float *mb1, float *mb2) {
 #pragma unroll
                     for (int u = 0; u < ADM_DA; ++u) {
-                        const bool act = k0 + u < cnt;
+                        const bool act = k0 + u < ce;
                         const int e = base + 64 * (k0 + u) + lane;
                         ib[u] = act ? (int)erow[e] : -1;
                         mb0[u] = act ? eval[3 * e] : 0.f;
@@ -1152,11 +1175,11 @@ __device__ void adm_ell_slice(
                 };
                 int ib[ADM_DA];
                 float mb0[ADM_DA], mb1[ADM_DA], mb2[ADM_DA];
-                if (len > 0) load_block(0, ib, mb0, mb1, mb2);
-                for (int k0 = 0; k0 < len; k0 += ADM_DA) {
+                if (kb < ke) load_block(kb, ib, mb0, mb1, mb2);
+                for (int k0 = kb; k0 < ke; k0 += ADM_DA) {
                     int ibn[ADM_DA];
                     float mn0[ADM_DA], mn1[ADM_DA], mn2[ADM_DA];
-                    if (k0 + ADM_DA < len) load_block(k0 + ADM_DA, ibn, mn0, mn1, mn2);
+                    if (k0 + ADM_DA < ke) load_block(k0 + ADM_DA, ibn, mn0, mn1, mn2);
 #pragma unroll
                     for (int u = 0; u < ADM_DA; ++u) {
                         mb0[u] *= inv_s0;
@@ -1208,13 +1231,14 @@ __device__ void adm_ell_slice(
                         mb2[u] = mn2[u];
                     }
                 }
-                if (64 * g + lane < P) e2part[pc] = e2;
+                if (64 * g + lane < P) e2part[2 * pc + h] = e2;
             }
-            // sum of the parts' squared residuals in column order
+            }
+            // sum of the parts' squared residuals in column order (and half order)
             __threadfence_block();
             __syncthreads();
             double e2 = 0.0;
-            for (int u = t; u < P; u += THREADS) e2 += e2part[u];
+            for (int u = t; u < P; u += THREADS) e2 += halves ? e2part[2 * u] + e2part[2 * u + 1] : e2part[2 * u];
             uint32_t rsw = 0;
             for (int i = t; i < m; i += THREADS) rsw = max(rsw, reinterpret_cast<const uint32_t *>(RXI)[i * (Q + 1) + Q]);
             e2 = wave_sum_d(e2);
@@ -1260,48 +1284,55 @@ __device__ void adm_ell_slice(
             break;
         }
 
-        // ---- T = 2^-S RX + a U - L into XB (row stride q) ----
-        t = fresh_tid();
-        lane = t % WAVE;
-        {
-            const float ifx = ldexpf(1.f, -S);
-            constexpr int CVT = ADM_CVT_ELEMS / THREADS;   // per thread
-            float tv[CVT];
-#pragma unroll
-            for (int u = 0; u < CVT; ++u) {
-                const int e = t + u * THREADS;
-                tv[u] = 0.f;
-                if (e < m * Q) {
-                    const int i = e / Q, k = e % Q;
-                    tv[u] = (float)RXI[i * (Q + 1) + k] * ifx + (alpha_f * Xp[e] - Lam[e]);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < CVT; ++u) {
-                const int e = t + u * THREADS;
-                if (e < m * Q) XB[xpos<Q>(e / Q, e % Q)] = tv[u];
-            }
-        }
-        // the X system was solved during phase A; T complete before the X update reads it
-        __syncthreads();
+        // (the X system was solved during phase A; the integer sums are complete)
         // ---- X+ = X F + T Inv (FP32 MFMA on FP32 copies of the FP64 q x q factors), U, L, Grams X+^T X+ and X+^T X ----
         t = fresh_tid();
         lane = t % WAVE;
         {
+            // as in the Y update: operands of row lane % 16 with contiguous
+            // components, the product plain (Grams) and transposed (a lane
+            // writes components 4 (lane / 16) .. + 3 of one row of X+, U, L)
+            const float ifx = ldexpf(1.f, -S);
             float b1[QV], b2[QV];
-            load_rhs(b1, b2);
+            load_rhs_c(b1, b2);
             f4 gx = {0.f, 0.f, 0.f, 0.f}, cx = {0.f, 0.f, 0.f, 0.f};
             for (int r0 = 16 * wave; r0 < m; r0 += 16 * NW) {
                 const int ra = r0 + lane % 16;
-                f4 D = {0.f, 0.f, 0.f, 0.f};
+                const bool rok = ra < m;
+                const int rc = rok ? ra : m - 1;
+                // operands: X (row rc) and T = 2^-S R Y^T + a U - L, formed
+                // here from the integer sums (read-only in XB now)
+                float a1[QV], a2[QV];
+                const int kb = QV * (lane / 16);
+                const int32_t *rxi = RXI + rc * (Q + 1) + kb;
+                const size_t eo = (size_t)rc * Q + kb;
+                const int cb = 4 * (lane / 16);
+                float4 lam4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                if constexpr (QV == 4) {
+                    const float4 x4 = *xchunk<Q>(XA, rc, lane / 16);
+                    const float4 u4 = *reinterpret_cast<const float4 *>(Xp + eo);
+                    lam4 = *reinterpret_cast<const float4 *>(Lam + eo);   // kb == cb: also the update's
+                    a1[0] = x4.x; a1[1] = x4.y; a1[2] = x4.z; a1[3] = x4.w;
+                    a2[0] = (float)rxi[0] * ifx + (alpha_f * u4.x - lam4.x);
+                    a2[1] = (float)rxi[1] * ifx + (alpha_f * u4.y - lam4.y);
+                    a2[2] = (float)rxi[2] * ifx + (alpha_f * u4.z - lam4.z);
+                    a2[3] = (float)rxi[3] * ifx + (alpha_f * u4.w - lam4.w);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < QV; ++v) {
+                        a1[v] = XA[xpos<Q>(rc, kb + v)];
+                        a2[v] = (float)rxi[v] * ifx + (alpha_f * Xp[eo + v] - Lam[eo + v]);
+                    }
+                    if (rok && cb < Q) lam4 = *reinterpret_cast<const float4 *>(Lam + (size_t)ra * Q + cb);
+                }
+                f4 D = {0.f, 0.f, 0.f, 0.f}, Dt = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int v = 0; v < QV; ++v) {
-                    const int kk = 4 * v + lane / 16;
-                    const float a1 = ra < m ? XA[xpos<Q>(ra, kk)] : 0.f;
-                    const float a2 = ra < m ? XB[xpos<Q>(ra, kk)] : 0.f;
-                    D = mfma16(a1, b1[v], D);
-                    D = mfma16(a2, b2[v], D);
+                    const float x = rok ? a1[v] : 0.f, tt = rok ? a2[v] : 0.f;
+                    D = mfma16(x, b1[v], D);
+                    D = mfma16(tt, b2[v], D);
+                    Dt = mfma16(b1[v], x, Dt);
+                    Dt = mfma16(b2[v], tt, Dt);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -1309,16 +1340,24 @@ __device__ void adm_ell_slice(
                     const bool ok = r < m && c < Q;
                     const float xn = ok ? D[v] : 0.f;
                     const float xk = ok ? XA[xpos<Q>(r, c)] : 0.f;
-                    if (ok) {
-                        const int e = r * Q + c;
-                        const float lam = Lam[e];
-                        const float u = nonneg ? fmaxf(0.f, xn + lam * inv_alpha) : xn + lam * inv_alpha;
-                        Xp[e] = u;
-                        Lam[e] = lam + ga * (xn - u);
-                        XB[xpos<Q>(r, c)] = xn;
-                    }
                     gx = mfma16(xn, xn, gx);
                     cx = mfma16(xn, xk, cx);
+                }
+                if (rok && cb < Q) {
+                    const float li[4] = {lam4.x, lam4.y, lam4.z, lam4.w};
+                    float uo[4], lo[4], xo[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float xn = Dt[v];
+                        const float u = nonneg ? fmaxf(0.f, xn + li[v] * inv_alpha) : xn + li[v] * inv_alpha;
+                        uo[v] = u;
+                        lo[v] = li[v] + ga * (xn - u);
+                        xo[v] = xn;
+                    }
+                    const size_t e = (size_t)ra * Q + cb;
+                    *reinterpret_cast<float4 *>(Xp + e) = make_float4(uo[0], uo[1], uo[2], uo[3]);
+                    *reinterpret_cast<float4 *>(Lam + e) = make_float4(lo[0], lo[1], lo[2], lo[3]);
+                    *xchunk_w<Q>(XA, ra, lane / 16) = make_float4(xo[0], xo[1], xo[2], xo[3]);   // X+ in place
                 }
             }
             sum_partials<Q, NW>(gx, cx, red, sh.G, sh.C);
@@ -1357,7 +1396,7 @@ __device__ void adm_ell_slice(
                     if (ib[u] >= 0) {
 #pragma unroll
                         for (int v = 0; v < QV; ++v) {
-                            const float4 a = *xchunk<Q>(XB, ib[u], v);
+                            const float4 a = *xchunk<Q>(XA, ib[u], v);
                             const float xs[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
                             for (int w = 0; w < 4; ++w) {
@@ -1447,56 +1486,77 @@ __device__ void adm_ell_slice(
         lane = t % WAVE;
         {
             float b1[QV], b2[QV];
-            load_rhs(b1, b2);
+            load_rhs_c(b1, b2);
             f4 gy = {0.f, 0.f, 0.f, 0.f};
             const f4 zero = {0.f, 0.f, 0.f, 0.f};
             float ymx = 0.f;
-            // tile r0: Y and T in the MFMA operand layout (row lane % 16,
-            // column 4 v + lane / 16), P in the result layout; indices clamped
-            // into the slice, values outside it masked at use
-            auto load_tile = [&](int r0, float *ya, float *ta, float *pa) {
+            // tile r0 of the 3n rows.  Y and T enter as MFMA operands of row
+            // lane % 16, components QV (lane / 16) .. + QV - 1 (one vector
+            // load each).  The product is formed twice: transposed, so that a
+            // lane holds components 4 (lane / 16) .. + 3 of row r0 + lane % 16
+            // (P read, Y, W and P written as float4), and plain (result layout)
+            // for the Gram Y+^T Y+.  Indices are clamped into the slice and
+            // values outside it masked at use.
+            auto load_tile = [&](int r0, float *ya, float *ta, float4 &pa) {
                 const int ra = min(r0 + lane % 16, R3 - 1);
-#pragma unroll
-                for (int v = 0; v < QV; ++v) {
-                    const size_t e = (size_t)ra * Q + 4 * v + lane / 16;
-                    ya[v] = Y[e];
-                    ta[v] = Yt[e];
+                const size_t e = (size_t)ra * Q + QV * (lane / 16);
+                if constexpr (QV == 4) {
+                    const float4 y4 = *reinterpret_cast<const float4 *>(Y + e);
+                    const float4 t4 = *reinterpret_cast<const float4 *>(Yt + e);
+                    ya[0] = y4.x; ya[1] = y4.y; ya[2] = y4.z; ya[3] = y4.w;
+                    ta[0] = t4.x; ta[1] = t4.y; ta[2] = t4.z; ta[3] = t4.w;
+                } else if constexpr (QV == 2) {
+                    const float2 y2 = *reinterpret_cast<const float2 *>(Y + e);
+                    const float2 t2 = *reinterpret_cast<const float2 *>(Yt + e);
+                    ya[0] = y2.x; ya[1] = y2.y;
+                    ta[0] = t2.x; ta[1] = t2.y;
+                } else {
+                    ya[0] = Y[e];
+                    ta[0] = Yt[e];
                 }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = min(r0 + 4 * (lane / 16) + v, R3 - 1), c = min(lane % 16, Q - 1);
-                    pa[v] = Pi[(size_t)r * Q + c];
-                }
+                const int cb = min(4 * (lane / 16), Q - 4);
+                pa = *reinterpret_cast<const float4 *>(Pi + (size_t)ra * Q + cb);
             };
-            // tiles in pairs: both tiles' operands are loaded before either's stores
-            auto do_tile = [&](int r0, const float *ya, const float *ta, const float *pa) {
+            auto do_tile = [&](int r0, const float *ya, const float *ta, const float4 &pa) {
                 const bool rok = r0 + lane % 16 < R3;
-                f4 D = {0.f, 0.f, 0.f, 0.f};
+                f4 D = {0.f, 0.f, 0.f, 0.f}, Dt = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int v = 0; v < QV; ++v) {
-                    D = mfma16(rok ? ya[v] : 0.f, b1[v], D);
-                    D = mfma16(rok ? ta[v] : 0.f, b2[v], D);
+                    const float y = rok ? ya[v] : 0.f, tt = rok ? ta[v] : 0.f;
+                    D = mfma16(y, b1[v], D);
+                    D = mfma16(tt, b2[v], D);
+                    Dt = mfma16(b1[v], y, Dt);
+                    Dt = mfma16(b2[v], tt, Dt);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = r0 + 4 * (lane / 16) + v, c = lane % 16;   // FP32 result layout
-                    const bool ok = r < R3 && c < Q;
-                    const float yn = ok ? D[v] : 0.f;
-                    if (ok) {
-                        const size_t e = (size_t)r * Q + c;
-                        const float pi = pa[v];
+                    const float yn = r < R3 && c < Q ? D[v] : 0.f;
+                    gy = mfma16(yn, yn, gy);
+                }
+                const int cb = 4 * (lane / 16);
+                if (rok && cb < Q) {
+                    const float pin[4] = {pa.x, pa.y, pa.z, pa.w};
+                    float wo[4], po[4], yo[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float yn = Dt[v], pi = pin[v];
                         const float u = nonneg ? fmaxf(0.f, yn + pi * inv_beta) : yn + pi * inv_beta;
                         const float pn = pi + gb * (yn - u);
-                        W[e] = fmaf(beta_f, u, -pn);
-                        Pi[e] = pn;
-                        Y[e] = yn;
+                        wo[v] = fmaf(beta_f, u, -pn);
+                        po[v] = pn;
+                        yo[v] = yn;
                         ymx = fmaxf(ymx, fabsf(yn));
                     }
-                    gy = mfma16(yn, yn, gy);
+                    const size_t e = (size_t)(r0 + lane % 16) * Q + cb;
+                    *reinterpret_cast<float4 *>(W + e) = make_float4(wo[0], wo[1], wo[2], wo[3]);
+                    *reinterpret_cast<float4 *>(Pi + e) = make_float4(po[0], po[1], po[2], po[3]);
+                    *reinterpret_cast<float4 *>(Y + e) = make_float4(yo[0], yo[1], yo[2], yo[3]);
                 }
             };
             for (int r0 = 16 * wave; r0 < R3; r0 += 16 * NW) {
-                float ya[QV], ta[QV], pa[4];
+                float ya[QV], ta[QV];
+                float4 pa;
                 load_tile(r0, ya, ta, pa);
                 do_tile(r0, ya, ta, pa);
             }
@@ -1504,9 +1564,6 @@ __device__ void adm_ell_slice(
             sum_partials<Q, NW>(gy, zero, red, sh.G, nullptr);
             ymax = (double)block_max(ymx, redf);
         }
-        float *tmp = XA;
-        XA = XB;
-        XB = tmp;
     }
     for (int e = t; e < m * Q; e += THREADS) Xg[e] = XA[xpos<Q>(e / Q, e % Q)];
     if (t == 0) {
