@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--lightcut", default="0.02:16384:8192",
                     help="EPS:MAX_CUT:SAMPLES of the global light cut timed over every VPL (Sec. 3 step 1); "
                          "'none' to skip")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of running vplmc_autotune before the timing")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the completion variants and the rank sweep at the headline rate")
     ap.add_argument("--eager", action="store_true",
@@ -320,6 +322,17 @@ def main():
         proposal = torch.as_tensor(np.load(weights_path)).to(dev)
         api.set_proposal(ctx, proposal)
 
+    # launch shapes (completion queue and workgroup size, entry workgroup size)
+    # chosen by the library's autotuner on these inputs, before any timing
+    tune = api.autotune(ctx, plan, ds, prm, ws, rad, reps=2) if not args.no_autotune else api.get_tune(plan)
+    progress(f"launch shapes: {tune}")
+    plain_plan = make_plan
+
+    def make_plan(p):          # the other plans of this run take the same shapes
+        pl = plain_plan(p)
+        api.set_tune(pl, **tune)
+        return pl
+
     # the frame as a captured graph (or eager calls on the library's stream):
     # W untimed launches, then exactly K timed ones, an event after each
     graph = None if args.eager else api.Graph(ctx, plan, ds, prm, ws, rad)
@@ -554,6 +567,7 @@ def main():
                    "seed": seed, "proposal": "plain"},
         "frame_ms": round(ms, 3),
         "frame_ms_median": round(ms_median, 3),
+        "launch_shapes": dict(tune, autotuned=not args.no_autotune),
         "timing": ("eager frames" if args.eager else "captured frame graph (vplmc_graph_create)")
                   + ", HIP events per launch; phase_ms from eager frames",
         "eager_frame_ms_sum_of_phases": round(eager_ms, 3),
