@@ -427,6 +427,28 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
         std::stable_sort(plan->groups[g].begin(), plan->groups[g].end(),
                          [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
     }
+    // global-memory completion: row and column blocks of every slice, as prefixes
+    // per group (the launch grids), and the squared-residual slot of each row block
+    plan->gblk.clear();
+    int64_t e2b = 0;
+    for (int g = 1; g < 8; g += 2) {
+        plan->gblk_off[g] = (int64_t)plan->gblk.size();
+        int64_t r = 0, c = 0;
+        plan->gblk.push_back(0);
+        for (int32_t sl : plan->groups[g]) {
+            r += ((int64_t)plan->desc[sl].m + GADM_RB - 1) / GADM_RB;
+            plan->gblk.push_back((int32_t)r);
+        }
+        plan->gblk.push_back(0);
+        for (int32_t sl : plan->groups[g]) {
+            c += ((int64_t)plan->desc[sl].n + GADM_CB - 1) / GADM_CB;
+            plan->gblk.push_back((int32_t)c);
+        }
+        plan->g_rows[g] = r;
+        plan->g_cols[g] = c;
+        plan->ge2_base[g] = e2b;
+        e2b += r;
+    }
     plan->tot1 = o1;
     plan->tot2 = o2;
     plan->tot_omega = oo;
@@ -492,7 +514,11 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     bytes[VPLMC_R_X] = ox * 4;
     bytes[VPLMC_R_Y] = oy * 4;
     bytes[VPLMC_R_SLICE_SCALE] = S * 4;
-    bytes[R_DESC] = S * sizeof(SliceDesc) + S * 4;
+    bytes[R_DESC] = S * sizeof(SliceDesc) + S * 4 + plan->gblk.size() * 4;
+    bool any_global = false;
+    for (int g = 1; g < 8; g += 2) any_global = any_global || !plan->groups[g].empty();
+    bytes[R_GSYS] = any_global ? (size_t)S * GADM_SYS_BYTES : 0;
+    bytes[R_GE2] = (size_t)e2b * 8;
     bytes[R_COLW_PREFIX] = oc * 8;
     bytes[R_BITMAP] = obm * 4;
     bytes[R_BITMAPT] = obmt * 4;
@@ -537,6 +563,8 @@ static int plan_build(int32_t n_slices, const int32_t *pt_offsets, const int32_t
     if (n_slices > 0) {
         memcpy(plan->upload.data(), plan->desc.data(), S * sizeof(SliceDesc));
         memcpy(plan->upload.data() + S * sizeof(SliceDesc), plan->ids.data(), S * 4);
+        if (!plan->gblk.empty())
+            memcpy(plan->upload.data() + S * sizeof(SliceDesc) + S * 4, plan->gblk.data(), plan->gblk.size() * 4);
     }
     *out = plan;
     return VPLMC_OK;
@@ -774,7 +802,8 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
         rc = launch_als(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Y,
                         scale, stats);
     else
-        rc = launch_adm(st, &ctx->adm, *plan, ctx->n_cu, desc, ids, region<int32_t>(ws, plan, R_QUEUE), *params,
+        rc = launch_adm(st, &ctx->adm, *plan, ctx->n_cu, desc, ids, ids + S, region<char>(ws, plan, R_GSYS),
+                        region<double>(ws, plan, R_GE2), region<int32_t>(ws, plan, R_QUEUE), *params,
                         row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X, region<float>(ws, plan, R_XNEXT),
                         region<float>(ws, plan, R_XP), region<float>(ws, plan, R_LAMBDA), Y,
                         region<float>(ws, plan, R_YP), region<float>(ws, plan, R_PI), region<float>(ws, plan, R_YT),
@@ -1137,7 +1166,8 @@ int vplmc_stage_adm(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_params *
         rc = launch_als(st, *plan, desc, ids, *params, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Y,
                         scale, stats);
     else
-        rc = launch_adm(st, &ctx->adm, *plan, ctx->n_cu, desc, ids, region<int32_t>(ws, plan, R_QUEUE), *params,
+        rc = launch_adm(st, &ctx->adm, *plan, ctx->n_cu, desc, ids, ids + plan->n_slices, region<char>(ws, plan, R_GSYS),
+                        region<double>(ws, plan, R_GE2), region<int32_t>(ws, plan, R_QUEUE), *params,
                         row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, ell, X, region<float>(ws, plan, R_XNEXT),
                         region<float>(ws, plan, R_XP), region<float>(ws, plan, R_LAMBDA), Y,
                         region<float>(ws, plan, R_YP), region<float>(ws, plan, R_PI), region<float>(ws, plan, R_YT),

@@ -2,8 +2,10 @@
 // method (Appendix A), and the factorised column sum I(s) = X (Y e)
 // (Sec. 3, step 5).
 //
-// One workgroup owns one slice for the whole iteration, so an iteration
-// needs only workgroup barriers.  The slice matrix is the stacked
+// A slice whose X fits in LDS is completed by one workgroup for all its
+// iterations (k_adm_ell), so an iteration needs only workgroup barriers; the
+// others (rank 32, tall slices) by a sequence of launches per iteration over
+// all such slices (k_gadm_*, below).  The slice matrix is the stacked
 // m' x 3n' matrix [M_R | M_G | M_B] known on the sampled entries; Y is
 // stored cluster-major, Y[j][c][k] = the paper's Y(k, c n' + j).
 //
@@ -19,7 +21,7 @@
 //   phase B, per column j (CSC): the residual again from (X_k, Y_k),
 //     RY_j = sum r X+_i, Y+_j = (GX + bI)^-1 ((X+^T X) Y_j + RY_j + b V_j - P_j),
 //     V_j = max(0, Y+_j + P_j / b), P_j += g b (Y+_j - V_j); a column of at
-//     most ADM_LIGHT samples by one lane, a longer one by a wavefront;
+//     most GADM_LIGHT samples by one lane, a longer one by a wavefront;
 //   GY = Y+ Y+^T for the next iteration, Y streamed through LDS tiles.
 // The q x q systems are factored by Cholesky in FP64 and inverted once per
 // iteration; phase A and the wavefront columns multiply by the FP64 inverse,
@@ -34,8 +36,9 @@ namespace {
 
 constexpr int WAVE = 64;
 // columns with at most this many samples take the lane-per-column path of
-// the global-memory completion kernel; longer ones a wavefront each
-constexpr int ADM_LIGHT = 16;
+// the global-memory completion, longer ones a wavefront each (measured on the
+// rank-32 1080p frame: 2.00 s of completion at 64 against 2.13 s at 16)
+constexpr int GADM_LIGHT = 64;
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -243,49 +246,190 @@ __device__ void gram_rows(AdmShared<Q> &sh, const float *__restrict__ M, int row
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Completion of the slices whose X does not fit in LDS (rank 32, or tall
+// slices), with X and Y in global memory, as a sequence of launches per
+// iteration over all such slices of a rank bucket, so that every phase has
+// the whole GPU and the launch boundaries order the phases (no workgroup
+// waits for another):
+//   init    (workgroup per slice)  scale, initial factors, GY, X system
+//   rows    (per 64-row block)     residuals of the row's samples, R_i Y^T,
+//                                  X+_i = X_i F + T_i Inv, U, Lambda (a wavefront per row)
+//   ysys    (workgroup per slice)  residual norm and the stop test, GX = X+^T X+,
+//                                  C = X+^T X, Y system
+//   cols    (per 256-column block) residuals again from X and Y, X+^T R_j,
+//                                  Y+_j = F Y_j + Inv T_j, V, Pi (a lane per light
+//                                  column, a wavefront per heavy one)
+//   xsys    (workgroup per slice)  GY = Y+^T Y+, X system for the next iteration
+//   final   (workgroup per slice)  the final X into the X region, statistics
+// The two X buffers alternate by iteration parity.  The q x q systems (FP64,
+// with FP32 copies for the light columns) and the slice's stop state live in
+// GADM_SYS_BYTES per slice.  The arithmetic per row and per column is that of
+// a single-workgroup completion; the Grams are sums in a fixed order.
+
+struct GadmArgs {
+    const SliceDesc *desc;
+    const int32_t *ids;                  // the group's slices
+    const int32_t *rowp, *colp;          // count + 1: prefixes of the slices' row and column blocks
+    int32_t count;
+    uint64_t seed;
+    int32_t max_iter, mode;
+    float tol, alpha0, beta0, gamma;
+    const int32_t *row_ptr_all, *csr_col_all;
+    const float *csr_val_all;
+    const int32_t *col_ptr_all, *csc_row_all;
+    const float *csc_val_all;
+    float *X_all, *Xn_all, *Xp_all, *Lam_all, *Y_all, *Yp_all, *Pi_all, *scale_all;
+    int32_t *stats_all;
+    char *gsys;
+    double *ge2;                         // the group's first row block slot
+};
+
+struct GSys {
+    double *F, *Inv;                     // Q x Q (X side: F = G Inv; Y side: F stored transposed)
+    float *Ff, *If;                      // Y side, FP32: Ff[a][b] = (Inv C)[a][b], If = Inv
+    int32_t *state;                      // done, iterations, FP32 bits of the residual, all-zero
+    double *dstate;                      // ||P_Omega M|| / s0, s0
+};
+
+__device__ __forceinline__ GSys gsys_of(char *base, int s) {
+    char *p = base + (size_t)s * GADM_SYS_BYTES;
+    GSys g;
+    g.F = reinterpret_cast<double *>(p);
+    g.Inv = g.F + 32 * 32;
+    g.Ff = reinterpret_cast<float *>(p + 2 * 32 * 32 * 8);
+    g.If = g.Ff + 32 * 32;
+    g.state = reinterpret_cast<int32_t *>(p + 2 * 32 * 32 * 8 + 2 * 32 * 32 * 4);
+    g.dstate = reinterpret_cast<double *>(p + 2 * 32 * 32 * 8 + 2 * 32 * 32 * 4 + 16);
+    return g;
+}
+
+// item b of a launch over the group's blocks: the slice position k with
+// pre[k] <= b < pre[k + 1]
+__device__ __forceinline__ int block_slice(const int32_t *__restrict__ pre, int count, int b) {
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Cross Gram C = A^T B of two (rows x Q) FP32 matrices into sh.C, streamed
+// through LDS like gram_rows (half a stage each).
+template <int Q, int PCAP, int THREADS>
+__device__ void gram_cross(AdmShared<Q> &sh, const float *__restrict__ A, const float *__restrict__ B, int rows,
+                           float *part, float *stage) {
+    constexpr int P = Q * Q, QB = Q / 4, NB = QB * QB;
+    constexpr int HALF = GRAM_STAGE / 2;
+    constexpr int TR = HALF / Q;
+    constexpr int NL = HALF / 4 / THREADS;
+    static_assert(NL >= 1 && NL * 4 * THREADS == HALF, "tile split");
+    const int t = fresh_tid();
+    const int groups = min(THREADS / NB, PCAP / P);
+    const int g = t / NB, blk = t % NB;
+    const int a0 = 4 * (blk / QB), b0 = 4 * (blk % QB);
+    const float4 *A4 = reinterpret_cast<const float4 *>(A);
+    const float4 *B4 = reinterpret_cast<const float4 *>(B);
+    const int64_t tot4 = (int64_t)rows * (Q / 4);
+    const int ntiles = (rows + TR - 1) / TR;
+    float acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
+    float4 *sa = reinterpret_cast<float4 *>(stage);
+    float4 *sb = reinterpret_cast<float4 *>(stage + HALF);
+    for (int tile = 0; tile < ntiles; ++tile) {
+        float4 ba[NL], bb[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int64_t idx = (int64_t)tile * (HALF / 4) + u * THREADS + t;
+            ba[u] = idx < tot4 ? A4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+            bb[u] = idx < tot4 ? B4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            sa[u * THREADS + t] = ba[u];
+            sb[u * THREADS + t] = bb[u];
+        }
+        __syncthreads();
+        const int rt = min(TR, rows - tile * TR);
+        if (g < groups) {
+            for (int r = g; r < rt; r += groups) {
+                const float4 u = sa[(r * Q + a0) / 4];
+                const float4 v = sb[(r * Q + b0) / 4];
+                const float ua[4] = {u.x, u.y, u.z, u.w}, vb[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(ua[x], vb[y], acc[x][y]);
+            }
+        }
+    }
+    if (g < groups) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) part[g * P + (a0 + x) * Q + b0 + y] = acc[x][y];
+    }
+    __syncthreads();
+    for (int e = t; e < P; e += THREADS) {
+        float v = 0.f;
+        for (int gg = 0; gg < groups; ++gg) v += part[gg * P + e];
+        sh.C[e] = v;
+    }
+    __syncthreads();
+}
+
+// sh.F, sh.Inv of the X system (F = G Inv, Inv = (G + a I)^-1) from sh.G, stored into the slice's state
 template <int Q, int THREADS>
-__device__ void adm_global_slice(
-    int s, const SliceDesc *__restrict__ desc, uint64_t seed,
-    int32_t max_iter, int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma,
-    const int32_t *__restrict__ row_ptr_all, const int32_t *__restrict__ csr_col_all,
-    const float *__restrict__ csr_val_all, const int32_t *__restrict__ col_ptr_all,
-    const int32_t *__restrict__ csc_row_all, const float *__restrict__ csc_val_all, float *X_all,
-    float *Xn_all, float *Xp_all, float *Lam_all, float *Y_all, float *Yp_all, float *Pi_all,
-    float *scale_all, int32_t *stats_all) {
+__device__ void gadm_x_system(AdmShared<Q> &sh, const GSys &g, double alpha) {
+    const int t = fresh_tid();
+    spd_inverse<Q>(sh, alpha);
+    for (int e = t; e < Q * Q; e += THREADS) {
+        const int a = e / Q, b = e % Q;
+        double v = 0.0;
+        for (int l = 0; l < Q; ++l) v += (double)sh.G[a * Q + l] * sh.Inv[l * Q + b];
+        g.F[e] = v;
+        g.Inv[e] = sh.Inv[e];
+    }
+}
+
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_init(GadmArgs a) {
     constexpr int NW = THREADS / WAVE;
     __shared__ AdmShared<Q> sh;
     constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
     __shared__ float part[PCAP];
-    __shared__ __align__(16) float Ff[Q * Q];   // Y system, FP32: Ff[k][l] = F[k][l], If[k][l] = Inv[k][l]
-    __shared__ __align__(16) float If[Q * Q];
     __shared__ __align__(16) float stage[GRAM_STAGE];
-    static_assert(NW * 33 * 3 * Q <= GRAM_STAGE, "heavy-column areas exceed the stage buffer");
-
-    const SliceDesc d = desc[s];
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
+    const SliceDesc d = a.desc[s];
     const int m = d.m, n = d.n;
-    // the slice's own rank qr <= Q: components qr .. Q-1 of X, Y and their
-    // multipliers start at 0 and stay exactly 0 (their Gram block is alpha I
-    // or beta I and every cross term is 0), so a rank-qr completion runs in
-    // the rank-Q kernel
     const int qr = d.qr;
     const int t = threadIdx.x, lane = t % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
-
-    const int32_t *row_ptr = row_ptr_all + d.off_row;
-    const int32_t *col_ptr = col_ptr_all + d.off_colptr;
-    const int32_t *csr_col = csr_col_all + d.off_omega;
-    const float *csr_val = csr_val_all + 3 * d.off_omega;
-    const int32_t *csc_row = csc_row_all + d.off_omega;
-    const float *csc_val = csc_val_all + 3 * d.off_omega;
-    float *Xa = X_all + d.off_x;
-    float *Xb = Xn_all + d.off_x;
-    float *Xp = Xp_all + d.off_x;
-    float *Lam = Lam_all + d.off_x;
-    float *Y = Y_all + d.off_y;
-    float *Yp = Yp_all + d.off_y;
-    float *Pi = Pi_all + d.off_y;
-    int32_t *st = stats_all + 4 * s;
+    const GSys g = gsys_of(a.gsys, s);
+    const uint64_t seed = a.seed;
+    const int32_t fixed_iters = a.mode;
+    const int32_t *row_ptr = a.row_ptr_all + d.off_row;
+    const float *csr_val = a.csr_val_all + 3 * d.off_omega;
+    float *Xa = a.X_all + d.off_x;
+    float *Xp = a.Xp_all + d.off_x;
+    float *Lam = a.Lam_all + d.off_x;
+    float *Y = a.Y_all + d.off_y;
+    float *Yp = a.Yp_all + d.off_y;
+    float *Pi = a.Pi_all + d.off_y;
+    float *scale_all = a.scale_all;
+    int32_t *st = a.stats_all + 4 * s;
     const int nnz = row_ptr[m];
+    if (t == 0) {
+        g.state[0] = 0;
+        g.state[1] = a.max_iter;
+        g.state[2] = __float_as_int(0.f);
+        g.state[3] = 0;
+    }
 
     // ---- scale s0 = mean sampled value; ||P_Omega M|| ----
     double sum = 0.0, sumsq = 0.0;
@@ -315,13 +459,20 @@ __device__ void adm_global_slice(
             st[0] = 0;
             st[1] |= VPLMC_SLICE_ALL_ZERO;
             st[2] = __float_as_int(0.f);
+            g.state[0] = 1;     // done
+            g.state[1] = 0;     // iterations
+            g.state[3] = 1;     // all zero: the stats stand
         }
         return;
     }
     const double s0 = tot / (3.0 * (double)nnz);
     const float inv_s0 = (float)(1.0 / s0);
     const double normM = sqrt(totsq) / s0;
-    if (t == 0) scale_all[s] = (float)s0;
+    if (t == 0) {
+        scale_all[s] = (float)s0;
+        g.dstate[0] = normM;
+        g.dstate[1] = s0;
+    }
 
     // ---- initial factors: fp32(u24(Philox) * fp32(2 / sqrt q)), or (mode bit 1)
     // the contents of the X and Y regions ----
@@ -348,35 +499,55 @@ __device__ void adm_global_slice(
     __threadfence_block();
     __syncthreads();
 
-    const double alpha = (double)alpha0 * (3.0 * n) / qr;
-    const double beta = (double)beta0 * (double)m / qr;
-    const float alpha_f = (float)alpha, beta_f = (float)beta;
-    const float ga = (float)((double)gamma * alpha), gb = (float)((double)gamma * beta);
-    const float inv_alpha = (float)(1.0 / alpha), inv_beta = (float)(1.0 / beta);
 
     gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * n, part, stage);
+    gadm_x_system<Q, THREADS>(sh, g, (double)a.alpha0 * (3.0 * n) / qr);
+    (void)wave;
+    (void)lane;
+    (void)inv_s0;
+}
 
-    float *X = Xa, *Xn = Xb;
-    int iters = max_iter;
-    double err = 0.0;
-    for (int it = 0; it < max_iter; ++it) {
-        // ---- X system: Inv = (GY + a I)^-1, F = GY Inv ----
-        spd_inverse<Q>(sh, alpha);
-        for (int e = t; e < Q * Q; e += THREADS) {
-            const int a = e / Q, b = e % Q;
-            double v = 0.0;
-            for (int l = 0; l < Q; ++l) v += (double)sh.G[a * Q + l] * sh.Inv[l * Q + b];
-            sh.F[e] = v;
-        }
-        __syncthreads();
-
-        // ---- phase A: rows ----
-        float *wsa = stage + wave * (33 * Q);   // [32][q] partial rows, then T_i (q)
-        double e2 = 0.0;
-        float gx[Q], cx[Q];
-#pragma unroll
-        for (int k = 0; k < Q; ++k) gx[k] = cx[k] = 0.f;
-        for (int i = wave; i < m; i += NW) {
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_rows(GadmArgs a, int it) {
+    constexpr int NW = THREADS / WAVE;
+    __shared__ double shF[Q * Q], shInv[Q * Q];
+    __shared__ __align__(16) float stage[NW * 33 * Q];
+    const int b = blockIdx.x;
+    const int k = block_slice(a.rowp, a.count, b);
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
+    const GSys g = gsys_of(a.gsys, s);
+    if (g.state[0]) return;
+    const SliceDesc d = a.desc[s];
+    const int m = d.m, n = d.n, qr = d.qr;
+    const int t = threadIdx.x, lane = t % WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
+    const int r_beg = (b - a.rowp[k]) * GADM_RB, r_end = min(m, r_beg + GADM_RB);
+    for (int e = t; e < Q * Q; e += THREADS) {
+        shF[e] = g.F[e];
+        shInv[e] = g.Inv[e];
+    }
+    struct {
+        double *F, *Inv;
+    } sh = {shF, shInv};
+    const bool nonneg = (a.mode & 4) == 0;
+    const double s0 = g.dstate[1];
+    const float inv_s0 = (float)(1.0 / s0);
+    const double alpha = (double)a.alpha0 * (3.0 * n) / qr;
+    const float alpha_f = (float)alpha;
+    const float ga = (float)((double)a.gamma * alpha);
+    const float inv_alpha = (float)(1.0 / alpha);
+    const int32_t *row_ptr = a.row_ptr_all + d.off_row;
+    const int32_t *csr_col = a.csr_col_all + d.off_omega;
+    const float *csr_val = a.csr_val_all + 3 * d.off_omega;
+    const float *X = ((it & 1) ? a.Xn_all : a.X_all) + d.off_x;
+    float *Xn = ((it & 1) ? a.X_all : a.Xn_all) + d.off_x;
+    float *Xp = a.Xp_all + d.off_x;
+    float *Lam = a.Lam_all + d.off_x;
+    const float *Y = a.Y_all + d.off_y;
+    __syncthreads();
+    float *wsa = stage + wave * (33 * Q);   // [32][q] partial rows, then T_i (q)
+    double e2 = 0.0;
+        for (int i = r_beg + wave; i < r_end; i += NW) {
             float xi[Q];
             const float4 *xr = reinterpret_cast<const float4 *>(X + (size_t)i * Q);
 #pragma unroll
@@ -451,74 +622,118 @@ __device__ void adm_global_slice(
             }
             // the next row's partial rows overwrite this area
             wave_lds_sync();
-            // Grams: lane k accumulates GX[l][k] = sum x+_l x+_k and C[l][k] = sum x+_l x_k
-            float xk = 0.f;
-#pragma unroll
-            for (int k = 0; k < Q; ++k) xk = (lane == k) ? xi[k] : xk;
-#pragma unroll
-            for (int l = 0; l < Q; ++l) {
-                const float xl = __shfl(xn, l, WAVE);
-                gx[l] = fmaf(xl, xn, gx[l]);
-                cx[l] = fmaf(xl, xk, cx[l]);
-            }
         }
-        e2 = wave_sum_d(e2);
-        if (lane == 0) sh.red[wave] = e2;
-        if (lane < Q) {
-#pragma unroll
-            for (int l = 0; l < Q; ++l) {
-                part[(wave * Q + l) * Q + lane] = gx[l];
-            }
-        }
-        __syncthreads();
-        double e2t = 0.0;
-        for (int w = 0; w < NW; ++w) e2t += sh.red[w];
-        err = sqrt(e2t) / normM;
-        for (int e = t; e < Q * Q; e += THREADS) {
-            float v = 0.f;
-            for (int w = 0; w < NW; ++w) v += part[w * Q * Q + e];
-            sh.G[e] = v;
-        }
-        __syncthreads();
-        if (lane < Q) {
-#pragma unroll
-            for (int l = 0; l < Q; ++l) part[(wave * Q + l) * Q + lane] = cx[l];
-        }
-        __syncthreads();
-        for (int e = t; e < Q * Q; e += THREADS) {
-            float v = 0.f;
-            for (int w = 0; w < NW; ++w) v += part[w * Q * Q + e];
-            sh.C[e] = v;
-        }
-        __syncthreads();
-        if (!(fixed_iters & 1) && err < (double)tol) {
-            iters = it;
-            break;
-        }
+    e2 = wave_sum_d(e2);
+    __shared__ double red[NW];
+    if (lane == 0) red[wave] = e2;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < NW; ++w) tot += red[w];
+        a.ge2[b] = tot;
+    }
+}
 
-        // ---- Y system: Inv = (GX + b I)^-1, F^T = (Inv C)^T ----
-        spd_inverse<Q>(sh, beta);
-        for (int e = t; e < Q * Q; e += THREADS) {
-            const int a = e / Q, b = e % Q;   // F[a][b] = sum_l Inv[a][l] C[l][b]; store F^T at [b][a]
-            double v = 0.0;
-            for (int l = 0; l < Q; ++l) v += sh.Inv[a * Q + l] * (double)sh.C[l * Q + b];
-            sh.F[b * Q + a] = v;
-            Ff[e] = (float)v;
-            If[e] = (float)sh.Inv[e];
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_ysys(GadmArgs a, int it) {
+    constexpr int NW = THREADS / WAVE;
+    __shared__ AdmShared<Q> sh;
+    constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
+    __shared__ float part[PCAP];
+    __shared__ __align__(16) float stage[GRAM_STAGE];
+    __shared__ int stop_s;
+    const int k = blockIdx.x;
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
+    const GSys g = gsys_of(a.gsys, s);
+    if (g.state[0]) return;
+    const SliceDesc d = a.desc[s];
+    const int m = d.m, qr = d.qr;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        // the squared residuals of the slice's row blocks, in block order
+        double e2 = 0.0;
+        for (int rb = a.rowp[k]; rb < a.rowp[k + 1]; ++rb) e2 += a.ge2[rb];
+        const double err = sqrt(e2) / g.dstate[0];
+        g.state[2] = __float_as_int((float)err);
+        const bool stop = !(a.mode & 1) && err < (double)a.tol;
+        if (stop) {
+            g.state[0] = 1;
+            g.state[1] = it;
         }
-        __syncthreads();
+        stop_s = stop ? 1 : 0;
+    }
+    __syncthreads();
+    if (stop_s) return;
+    const float *X = ((it & 1) ? a.Xn_all : a.X_all) + d.off_x;
+    const float *Xn = ((it & 1) ? a.X_all : a.Xn_all) + d.off_x;
+    gram_rows<Q, PCAP, THREADS>(sh, Xn, m, part, stage);
+    gram_cross<Q, PCAP, THREADS>(sh, Xn, X, m, part, stage);
+    const double beta = (double)a.beta0 * (double)m / qr;
+    spd_inverse<Q>(sh, beta);
+    for (int e = t; e < Q * Q; e += THREADS) {
+        const int aa = e / Q, bb = e % Q;   // F[a][b] = sum_l Inv[a][l] C[l][b]; F^T at [b][a]
+        double v = 0.0;
+        for (int l = 0; l < Q; ++l) v += sh.Inv[aa * Q + l] * (double)sh.C[l * Q + bb];
+        g.F[bb * Q + aa] = v;
+        g.Inv[e] = sh.Inv[e];
+        g.Ff[e] = (float)v;
+        g.If[e] = (float)sh.Inv[e];
+    }
+}
 
-        // ---- phase B, light columns (at most ADM_LIGHT samples): lane per column ----
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_cols(GadmArgs a, int it) {
+    constexpr int NW = THREADS / WAVE;
+    __shared__ double shF[Q * Q], shInv[Q * Q];
+    __shared__ __align__(16) float Ff[Q * Q];
+    __shared__ __align__(16) float If[Q * Q];
+    __shared__ __align__(16) float stage[NW * 33 * 3 * Q];
+    const int b = blockIdx.x;
+    const int k = block_slice(a.colp, a.count, b);
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
+    const GSys g = gsys_of(a.gsys, s);
+    if (g.state[0]) return;
+    const SliceDesc d = a.desc[s];
+    const int m = d.m, n = d.n, qr = d.qr;
+    const int t = threadIdx.x, lane = t % WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
+    const int c_beg = (b - a.colp[k]) * GADM_CB, c_end = min(n, c_beg + GADM_CB);
+    for (int e = t; e < Q * Q; e += THREADS) {
+        shF[e] = g.F[e];
+        shInv[e] = g.Inv[e];
+        Ff[e] = g.Ff[e];
+        If[e] = g.If[e];
+    }
+    struct {
+        double *F, *Inv;
+    } sh = {shF, shInv};
+    const bool nonneg = (a.mode & 4) == 0;
+    const double s0 = g.dstate[1];
+    const float inv_s0 = (float)(1.0 / s0);
+    const double beta = (double)a.beta0 * (double)m / qr;
+    const float beta_f = (float)beta;
+    const float gb = (float)((double)a.gamma * beta);
+    const float inv_beta = (float)(1.0 / beta);
+    const int32_t *col_ptr = a.col_ptr_all + d.off_colptr;
+    const int32_t *csc_row = a.csc_row_all + d.off_omega;
+    const float *csc_val = a.csc_val_all + 3 * d.off_omega;
+    const float *X = ((it & 1) ? a.Xn_all : a.X_all) + d.off_x;
+    const float *Xn = ((it & 1) ? a.X_all : a.Xn_all) + d.off_x;
+    float *Y = a.Y_all + d.off_y;
+    float *Yp = a.Yp_all + d.off_y;
+    float *Pi = a.Pi_all + d.off_y;
+    __syncthreads();
+        // ---- phase B, light columns (at most GADM_LIGHT samples): lane per column ----
         // X+^T R_j over the column's samples, then per channel Y+_j = F Y_j + Inv T_j
         // with the FP32 copies of the system
-        for (int jb = 0; jb < n; jb += THREADS) {
-            const int j = jb + fresh_tid();
+        {
+            const int j = c_beg + fresh_tid();
             int beg = 0, end = 0;
-            if (j < n) {
+            if (j < c_end) {
                 beg = col_ptr[j];
                 end = col_ptr[j + 1];
             }
-            if (j < n && end - beg <= ADM_LIGHT) {
+            if (j < c_end && end - beg <= GADM_LIGHT) {
                 // an opaque zero offset keeps the system's LDS reads inside the loop
                 // (hoisted, 2 Q^2 values would stay in registers)
                 int z = 0;
@@ -628,10 +843,10 @@ __device__ void adm_global_slice(
 
         // ---- phase B, heavy columns: wavefront per column ----
         float *wst = stage + wave * (33 * 3 * Q);   // [32][3q] partial rows, then T_j (3q)
-        for (int jb = wave * WAVE; jb < n; jb += NW * WAVE) {
+        for (int jb = c_beg + wave * WAVE; jb < c_end; jb += NW * WAVE) {
             const int jl = jb + lane;
-            const int cnt = jl < n ? col_ptr[jl + 1] - col_ptr[jl] : 0;
-            uint64_t heavy = __ballot(cnt > ADM_LIGHT);
+            const int cnt = jl < c_end ? col_ptr[jl + 1] - col_ptr[jl] : 0;
+            uint64_t heavy = __ballot(cnt > GADM_LIGHT);
             while (heavy) {
                 const int j = jb + __builtin_ctzll(heavy);
                 heavy &= heavy - 1;
@@ -736,21 +951,43 @@ __device__ void adm_global_slice(
                 wave_lds_sync();
             }
         }
-        __threadfence_block();
-        __syncthreads();
-        gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * n, part, stage);
-        float *tmp = X;
-        X = Xn;
-        Xn = tmp;
-    }
-    // final X lives in X; make it the X region
-    if (X != Xa) {
-        for (int e = t; e < m * Q; e += THREADS) Xa[e] = X[e];
+}
+
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_xsys(GadmArgs a, int it) {
+    constexpr int NW = THREADS / WAVE;
+    __shared__ AdmShared<Q> sh;
+    constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
+    __shared__ float part[PCAP];
+    __shared__ __align__(16) float stage[GRAM_STAGE];
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
+    const GSys g = gsys_of(a.gsys, s);
+    if (g.state[0]) return;
+    const SliceDesc d = a.desc[s];
+    const float *Y = a.Y_all + d.off_y;
+    gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * d.n, part, stage);
+    gadm_x_system<Q, THREADS>(sh, g, (double)a.alpha0 * (3.0 * d.n) / d.qr);
+    (void)it;
+}
+
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_final(GadmArgs a) {
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
+    const GSys g = gsys_of(a.gsys, s);
+    if (g.state[3]) return;                  // all-zero slice: set by the init launch
+    const SliceDesc d = a.desc[s];
+    const int iters = g.state[1];
+    const int t = threadIdx.x;
+    if (iters & 1) {                          // the final X is in the second buffer
+        const float *src = a.Xn_all + d.off_x;
+        float *dst = a.X_all + d.off_x;
+        for (int e = t; e < d.m * Q; e += THREADS) dst[e] = src[e];
     }
     if (t == 0) {
+        int32_t *st = a.stats_all + 4 * s;
         st[0] = iters;
-        if (!(fixed_iters & 1) && iters >= max_iter) st[1] |= VPLMC_SLICE_NOT_CONVERGED;
-        st[2] = __float_as_int((float)err);
+        if (!(a.mode & 1) && iters >= a.max_iter) st[1] |= VPLMC_SLICE_NOT_CONVERGED;
+        st[2] = g.state[2];
     }
 }
 
@@ -1592,24 +1829,6 @@ __device__ __forceinline__ bool next_slice(int32_t *queue, int32_t count, int &k
 }
 
 template <int Q, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_adm(
-    const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, int32_t count, int32_t *queue,
-    uint64_t seed, int32_t max_iter, int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma,
-    const int32_t *__restrict__ row_ptr_all, const int32_t *__restrict__ csr_col_all,
-    const float *__restrict__ csr_val_all, const int32_t *__restrict__ col_ptr_all,
-    const int32_t *__restrict__ csc_row_all, const float *__restrict__ csc_val_all, float *X_all,
-    float *Xn_all, float *Xp_all, float *Lam_all, float *Y_all, float *Yp_all, float *Pi_all,
-    float *scale_all, int32_t *stats_all) {
-    int k, state = 0;
-    while (next_slice(queue, count, k, state)) {
-        adm_global_slice<Q, THREADS>(__builtin_amdgcn_readfirstlane(slice_list[k]), desc, seed, max_iter, fixed_iters, tol, alpha0, beta0, gamma,
-                                     row_ptr_all, csr_col_all, csr_val_all, col_ptr_all, csc_row_all, csc_val_all,
-                                     X_all, Xn_all, Xp_all, Lam_all, Y_all, Yp_all, Pi_all, scale_all, stats_all);
-        __syncthreads();
-    }
-}
-
-template <int Q, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_adm_ell(
     const SliceDesc *__restrict__ desc, const int32_t *__restrict__ slice_list, int32_t count, int32_t *queue,
     uint64_t seed, int32_t max_iter, int32_t fixed_iters, float tol, float alpha0, float beta0, float gamma,
@@ -1692,22 +1911,62 @@ int adm_grid(K kern, int threads, size_t dyn, int n_cu, bool queue, size_t count
     return VPLMC_OK;
 }
 
+// the global-memory completion of group grp (odd: X in global memory): an
+// init launch, four launches per iteration, a final launch
 template <int Q, int THREADS>
-int launch_adm_global(hipStream_t st, size_t count, const int32_t *ids_dev, int32_t *queue, int n_cu,
-                      const SliceDesc *desc, const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col,
-                      const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
-                      float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale,
-                      int32_t *stats) {
+int launch_gadm(hipStream_t st, const vplmc_plan &plan, int grp, const int32_t *ids, const int32_t *gblk_dev,
+                char *gsys, double *ge2, const SliceDesc *desc, const vplmc_params &prm, const int32_t *row_ptr,
+                const int32_t *csr_col, const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row,
+                const float *csc_val, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
+                float *scale, int32_t *stats) {
+    const size_t count = plan.groups[grp].size();
     if (count == 0) return VPLMC_OK;
-    auto kern = k_adm<Q, THREADS>;
-    unsigned grid;
-    int rc;
-    if ((rc = adm_grid(kern, THREADS, 0, n_cu, queue != nullptr, count, grid))) return rc;
-    if (queue && (rc = launch_fill_u32(st, reinterpret_cast<uint32_t *>(queue), 1, 0u))) return rc;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(THREADS), 0, st, desc, ids_dev, (int32_t)count, queue, prm.seed,
-                       prm.max_iter, adm_mode(prm), prm.tol, prm.alpha0, prm.beta0,
-                       prm.gamma, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi,
-                       scale, stats);
+    GadmArgs a;
+    a.desc = desc;
+    a.ids = ids;
+    a.rowp = gblk_dev + plan.gblk_off[grp];
+    a.colp = a.rowp + count + 1;
+    a.count = (int32_t)count;
+    a.seed = prm.seed;
+    a.max_iter = prm.max_iter;
+    a.mode = adm_mode(prm);
+    a.tol = prm.tol;
+    a.alpha0 = prm.alpha0;
+    a.beta0 = prm.beta0;
+    a.gamma = prm.gamma;
+    a.row_ptr_all = row_ptr;
+    a.csr_col_all = csr_col;
+    a.csr_val_all = csr_val;
+    a.col_ptr_all = col_ptr;
+    a.csc_row_all = csc_row;
+    a.csc_val_all = csc_val;
+    a.X_all = X;
+    a.Xn_all = Xn;
+    a.Xp_all = Xp;
+    a.Lam_all = Lam;
+    a.Y_all = Y;
+    a.Yp_all = Yp;
+    a.Pi_all = Pi;
+    a.scale_all = scale;
+    a.stats_all = stats;
+    a.gsys = gsys;
+    a.ge2 = ge2 + plan.ge2_base[grp];
+    const unsigned nr = (unsigned)plan.g_rows[grp], nc = (unsigned)plan.g_cols[grp];
+    hipLaunchKernelGGL((k_gadm_init<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a);
+    VPLMC_HIP(hipGetLastError());
+    for (int it = 0; it < prm.max_iter; ++it) {
+        hipLaunchKernelGGL((k_gadm_rows<Q, THREADS>), dim3(nr), dim3(THREADS), 0, st, a, it);
+        VPLMC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_gadm_ysys<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a, it);
+        VPLMC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_gadm_cols<Q, THREADS>), dim3(nc), dim3(THREADS), 0, st, a, it);
+        VPLMC_HIP(hipGetLastError());
+        if (it + 1 < prm.max_iter) {
+            hipLaunchKernelGGL((k_gadm_xsys<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a, it);
+            VPLMC_HIP(hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL((k_gadm_final<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
@@ -1750,7 +2009,7 @@ int launch_adm_ell(hipStream_t st, int threads, size_t count, int max_m, const i
 }  // namespace
 
 int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int n_cu, const SliceDesc *desc,
-               const int32_t *ids_dev,
+               const int32_t *ids_dev, const int32_t *gblk_dev, char *gsys, double *ge2,
                int32_t *queues, const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col,
                const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
                const EllView &ell, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
@@ -1778,17 +2037,16 @@ int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int
             sb[k] = ss->side[k];
         }
     }
-    int rc = launch_adm_global<32, 256>(sb[3], plan.groups[6].size() + plan.groups[7].size(), id[6], qp(6), n_cu,
-                                        desc, prm, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp,
-                                        Lam, Y, Yp, Pi, scale, stats);
+    // rank 32 never fits in LDS (group 6 is empty)
+    int rc = launch_gadm<32, 256>(sb[3], plan, 7, id[7], gblk_dev, gsys, ge2, desc, prm, row_ptr, csr_col, csr_val,
+                                  col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
 #define VPLMC_ADM_PAIR(B, Q, TG)                                                                                      \
     if (!rc)                                                                                                          \
         rc = launch_adm_ell<Q>(sb[B], thr, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], qp(2 * B), \
                                n_cu, desc, prm, col_ptr, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale, stats); \
     if (!rc)                                                                                                          \
-        rc = launch_adm_global<Q, TG>(sb[B], plan.groups[2 * B + 1].size(), id[2 * B + 1], qp(2 * B + 1), n_cu, desc, \
-                                      prm, row_ptr, csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y,  \
-                                      Yp, Pi, scale, stats);
+        rc = launch_gadm<Q, 256>(sb[B], plan, 2 * B + 1, id[2 * B + 1], gblk_dev, gsys, ge2, desc, prm, row_ptr,    \
+                                 csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
     VPLMC_ADM_PAIR(2, 16, 512)
     VPLMC_ADM_PAIR(1, 8, 512)
     VPLMC_ADM_PAIR(0, 4, 1024)

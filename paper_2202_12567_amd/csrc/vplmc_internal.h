@@ -184,6 +184,8 @@ enum {
     R_LEAF_COL,      // int32 per (slice, leaf)
     R_ZETA,          // uint16 per (slice, draw slot)
     R_COUNTS,        // uint64[4]: shadow rays of the entries, coarsening evaluations and rays, -
+    R_GSYS,          // GADM_SYS_BYTES per slice: q x q systems and state of the global-memory completion
+    R_GE2,           // double per row block of the global-memory slices: squared residual sums
     R_INTERNAL_END
 };
 
@@ -269,10 +271,20 @@ struct vplmc_plan {
     int64_t tot_part = 0;                           // part slots
     vplmc_tune tune = {0, 1024, 256, 0};             // launch shapes
     std::vector<int32_t> ids;                  // slice ids grouped by rank bucket
-    std::vector<char> upload;                  // descriptor table + ids, as copied to the workspace
+    // global-memory completion: per group (odd g) the prefix over its slices of
+    // the row blocks and of the column blocks (count + 1 each), at gblk_off[g]
+    // ints into gblk; the first row block's squared-residual slot at ge2_base[g]
+    std::vector<int32_t> gblk;
+    int64_t gblk_off[8] = {}, ge2_base[8] = {}, g_rows[8] = {}, g_cols[8] = {};
+    std::vector<char> upload;                  // descriptor table + ids + gblk, as copied to the workspace
 };
 
 namespace vplmc {
+// global-memory completion: rows per row block, columns per column block,
+// bytes of a slice's system state (F and Inv in FP64, their FP32 copies, flags)
+constexpr int GADM_RB = 64;
+constexpr int GADM_CB = 256;
+constexpr size_t GADM_SYS_BYTES = 2 * 32 * 32 * 8 + 2 * 32 * 32 * 4 + 256;
 // LDS budget of the LDS-resident ADM kernel (gfx950: 160 KiB per workgroup)
 constexpr size_t LDS_BYTES = 160 * 1024;
 constexpr int adm_lds_threads(int q) { return q == 32 ? 0 : 1024; }
@@ -344,7 +356,7 @@ int launch_sort(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, c
                 const int32_t *stats, int32_t *csr_col, float *csr_val, int32_t *csc_row, float *csc_val,
                 const EllView &ell);
 int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int n_cu, const SliceDesc *desc,
-               const int32_t *ids_dev,
+               const int32_t *ids_dev, const int32_t *gblk_dev, char *gsys, double *ge2,
                int32_t *queues, const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col,
                const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
                const EllView &ell, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
