@@ -51,6 +51,9 @@ def parse():
                          "'none' to skip")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of running vplmc_autotune before the timing")
+    ap.add_argument("--launch-shape", default=None, metavar="QUEUE:THREADS:EVAL",
+                    help="use these launch shapes (completion work queue 0/1, completion threads, entry threads) "
+                         "instead of the autotuner's")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the completion variants and the rank sweep at the headline rate")
     ap.add_argument("--eager", action="store_true",
@@ -128,18 +131,19 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(workload, ppm, coarsen="none", rank=0):
+def measured_traffic(workload, ppm, coarsen="none", rank=0, adm_threads=1024, adm_queue=0):
     """HBM bytes per completion launch from FETCH_SIZE + WRITE_SIZE (rocprofv3
     --pmc, one pass each, scaled by the same counters on a plain copy of known
-    size), recorded under profiles/ for this workload, rate, coarsening, rank
-    and kernel source; None when absent or stale."""
+    size), recorded under profiles/ for this workload, rate, coarsening, rank,
+    launch shape and kernel source; None when absent or stale."""
     path = os.path.join(ROOT, "profiles", f"k_adm_ell_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if (rec.get("ppm") != ppm or rec.get("source_sha256") != source_digest()
-            or rec.get("coarsen", "none") != coarsen or rec.get("rank", 0) != rank):
+            or rec.get("coarsen", "none") != coarsen or rec.get("rank", 0) != rank
+            or rec.get("adm_threads", 1024) != adm_threads or rec.get("adm_queue", 0) != adm_queue):
         return None
     return rec.get("bytes_per_launch")
 
@@ -164,6 +168,7 @@ def write_traffic_record(args, csvs):
     """profiles/k_adm_ell_<workload>_traffic.json from four rocprofv3 --pmc
     CSVs: FETCH_SIZE and WRITE_SIZE of the benchmark, then of --copy-probe."""
     f_csv, w_csv, cf_csv, cw_csv = csvs
+    shape = tuple(int(v) for v in (args.launch_shape or "0:1024:256").split(":"))
     fetch, nf = _pmc_per_dispatch(f_csv, "::k_adm_ell<", "FETCH_SIZE")
     write, nw = _pmc_per_dispatch(w_csv, "::k_adm_ell<", "WRITE_SIZE")
     probe = 1 << 30
@@ -179,6 +184,7 @@ def write_traffic_record(args, csvs):
     ppm = int(round(rate * 1e4)) if cspec != "none" else int(round(rate * 1e4 / 2))
     rank = args.rank if args.rank is not None else (16 if cspec != "none" else 0)
     rec = {"kernel": "k_adm_ell", "workload": args.workload, "ppm": ppm, "coarsen": cspec, "rank": rank,
+           "adm_threads": shape[1], "adm_queue": shape[0],   # the shape the counter runs used
            "source_sha256": source_digest(), "fetch_size_kib_per_dispatch": round(fetch, 1),
            "write_size_kib_per_dispatch": round(write, 1), "dispatches": [nf, nw], "copy_probe_bytes": probe,
            "copy_fetch_size_kib": round(cfetch, 1), "copy_write_size_kib": round(cwrite, 1),
@@ -186,7 +192,7 @@ def write_traffic_record(args, csvs):
            "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
            "commands": [f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} -d <out> -o <name> --output-format csv "
                         f"-- python3 /root/repo/bench.py --eager --steps 1 --warmup 0 --sweep \"\" --no-cpu-baseline "
-                        f"--no-variants --lightcut none"
+                        f"--no-variants --lightcut none --launch-shape {':'.join(map(str, shape))}"
                         for c in ("FETCH_SIZE", "WRITE_SIZE")]
            + [f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} -d <out> -o <name> --output-format csv "
               f"-- python3 /root/repo/bench.py --copy-probe 1024" for c in ("FETCH_SIZE", "WRITE_SIZE")]}
@@ -324,7 +330,14 @@ def main():
 
     # launch shapes (completion queue and workgroup size, entry workgroup size)
     # chosen by the library's autotuner on these inputs, before any timing
-    tune = api.autotune(ctx, plan, ds, prm, ws, rad, reps=2) if not args.no_autotune else api.get_tune(plan)
+    if args.launch_shape:
+        qv, tv, ev = (int(v) for v in args.launch_shape.split(":"))
+        api.set_tune(plan, adm_queue=qv, adm_threads=tv, eval_threads=ev)
+        tune = api.get_tune(plan)
+    elif not args.no_autotune:
+        tune = api.autotune(ctx, plan, ds, prm, ws, rad, reps=2)
+    else:
+        tune = api.get_tune(plan)
     progress(f"launch shapes: {tune}")
     plain_plan = make_plan
 
@@ -410,7 +423,8 @@ def main():
     all_ell = all(i["adm_in_lds"] for i in infos)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.workload, ppm2 if coarsen else ppm1, cspec, rank) if all_ell else None,
+            "traffic": measured_traffic(args.workload, ppm2 if coarsen else ppm1, cspec, rank, tune["adm_threads"],
+                                        tune["adm_queue"]) if all_ell else None,
             "kernel": "k_adm_ell" if all_ell else "k_adm_ell + k_adm",
             "kernel_ms": round(phase_ms["adm"], 3),
             "algorithmic_bytes": {"samples": sample_bytes, "factor_state": state_bytes},
@@ -567,7 +581,7 @@ def main():
                    "seed": seed, "proposal": "plain"},
         "frame_ms": round(ms, 3),
         "frame_ms_median": round(ms_median, 3),
-        "launch_shapes": dict(tune, autotuned=not args.no_autotune),
+        "launch_shapes": dict(tune, autotuned=not (args.no_autotune or args.launch_shape)),
         "timing": ("eager frames" if args.eager else "captured frame graph (vplmc_graph_create)")
                   + ", HIP events per launch; phase_ms from eager frames",
         "eager_frame_ms_sum_of_phases": round(eager_ms, 3),

@@ -41,9 +41,9 @@ def test_digest_ignores_comments_and_blank_lines(tree):
 
 def test_digest_follows_code(tree):
     d0 = bench.source_digest()
-    edit(tree, "kernels_adm.hip", lambda s: s.replace("constexpr int ADM_LIGHT = 16;", "constexpr int ADM_LIGHT = 17;"))
+    edit(tree, "kernels_adm.hip", lambda s: s.replace("constexpr int GADM_LIGHT = 64;", "constexpr int GADM_LIGHT = 65;"))
     assert bench.source_digest() != d0
-    edit(tree, "kernels_adm.hip", lambda s: s.replace("constexpr int ADM_LIGHT = 17;", "constexpr int ADM_LIGHT = 16;"))
+    edit(tree, "kernels_adm.hip", lambda s: s.replace("constexpr int GADM_LIGHT = 65;", "constexpr int GADM_LIGHT = 64;"))
     assert bench.source_digest() == d0
     edit(tree, "vplmc_internal.h", lambda s: s + "\nconstexpr int UNUSED_FOR_THE_TEST = 1;\n")
     assert bench.source_digest() != d0
