@@ -122,7 +122,7 @@ def source_digest():
     kernel, while an edit of a comment leaves them valid."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels_adm.hip", "vplmc_internal.h"):
+    for f in ("kernels_adm.hip", "adm_common.h", "vplmc_internal.h"):
         with open(os.path.join(ROOT, "paper_2202_12567_amd", "csrc", f), encoding="utf-8") as fh:
             for line in fh:
                 code = line.split("//", 1)[0].rstrip()

@@ -5,7 +5,7 @@
 // A slice whose X fits in LDS is completed by one workgroup for all its
 // iterations (k_adm_ell), so an iteration needs only workgroup barriers; the
 // others (rank 32, tall slices) by a sequence of launches per iteration over
-// all such slices (k_gadm_*, below).  The slice matrix is the stacked
+// all such slices (k_gadm_*, kernels_gadm.hip).  The slice matrix is the stacked
 // m' x 3n' matrix [M_R | M_G | M_B] known on the sampled entries; Y is
 // stored cluster-major, Y[j][c][k] = the paper's Y(k, c n' + j).
 //
@@ -20,976 +20,18 @@
 //   stop test on ||R|| / ||P_Omega M|| (before any state is kept);
 //   phase B, per column j (CSC): the residual again from (X_k, Y_k),
 //     RY_j = sum r X+_i, Y+_j = (GX + bI)^-1 ((X+^T X) Y_j + RY_j + b V_j - P_j),
-//     V_j = max(0, Y+_j + P_j / b), P_j += g b (Y+_j - V_j); a column of at
-//     most GADM_LIGHT samples by one lane, a longer one by a wavefront;
+//     V_j = max(0, Y+_j + P_j / b), P_j += g b (Y+_j - V_j);
 //   GY = Y+ Y+^T for the next iteration, Y streamed through LDS tiles.
 // The q x q systems are factored by Cholesky in FP64 and inverted once per
-// iteration; phase A and the wavefront columns multiply by the FP64 inverse,
-// the lane columns by its FP32 rounding.
+// iteration; phase A multiplies by the FP64 inverse, phase B by its FP32
+// rounding.
 // Every reduction has a fixed order: results are bitwise reproducible.
 
 #include <algorithm>
-#include "vplmc_internal.h"
+#include "adm_common.h"
 
 namespace vplmc {
 namespace {
-
-constexpr int WAVE = 64;
-// columns with at most this many samples take the lane-per-column path of
-// the global-memory completion, longer ones a wavefront each (measured on the
-// rank-32 1080p frame: 2.00 s of completion at 64 against 2.13 s at 16)
-constexpr int GADM_LIGHT = 64;
-
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-
-template <int Q>
-struct AdmShared {
-    double A[Q * Q];      // Gram + shift, factored in place (lower)
-    double Z[Q * Q];      // L^-1
-    double Inv[Q * Q];    // (G + shift)^-1
-    double F[Q * Q];      // X side: G Inv ; Y side: transpose of Inv C
-    float G[Q * Q];       // current Gram (FP32)
-    float C[Q * Q];       // X+^T X (C[a][b] = sum x+_a x_b)
-    double red[32];
-};
-
-// LDS written by some lanes of a wavefront and then read by others: the
-// wavefront's LDS operations complete, and the compiler keeps them in order
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// threadIdx.x behind an empty asm statement: what is derived from it is
-// recomputed where it is used, not hoisted out of the iteration loop or
-// shared between phases, where it would hold registers through every phase
-__device__ __forceinline__ int fresh_tid() {
-    int x = threadIdx.x;
-    asm volatile("" : "+v"(x));
-    return x;
-}
-
-// (G + shift I)^-1 in FP64 by Cholesky; result in sh.Inv.  All threads call.
-template <int Q>
-__device__ void spd_inverse(AdmShared<Q> &sh, double shift) {
-    const int t = fresh_tid();
-    for (int e = t; e < Q * Q; e += blockDim.x) {
-        const int a = e / Q, b = e % Q;
-        sh.A[e] = (double)sh.G[e] + (a == b ? shift : 0.0);
-        sh.Z[e] = 0.0;
-    }
-    __syncthreads();
-    for (int j = 0; j < Q; ++j) {          // right-looking Cholesky, lower triangle
-        if (t == 0) sh.A[j * Q + j] = sqrt(sh.A[j * Q + j]);
-        __syncthreads();
-        const double djj = sh.A[j * Q + j];
-        for (int i = j + 1 + t; i < Q; i += blockDim.x) sh.A[i * Q + j] /= djj;
-        __syncthreads();
-        for (int e = t; e < Q * Q; e += blockDim.x) {
-            const int i = e / Q, k = e % Q;
-            if (k > j && i >= k) sh.A[i * Q + k] -= sh.A[i * Q + j] * sh.A[k * Q + j];
-        }
-        __syncthreads();
-    }
-    if (t < Q) {                            // column t of L^-1 by forward substitution
-        const int j = t;
-        for (int i = j; i < Q; ++i) {
-            double s = (i == j) ? 1.0 : 0.0;
-            for (int l = j; l < i; ++l) s -= sh.A[i * Q + l] * sh.Z[l * Q + j];
-            sh.Z[i * Q + j] = s / sh.A[i * Q + i];
-        }
-    }
-    __syncthreads();
-    for (int e = t; e < Q * Q; e += blockDim.x) {   // Inv = Z^T Z
-        const int a = e / Q, b = e % Q;
-        const int lo = a > b ? a : b;
-        double s = 0.0;
-        for (int i = lo; i < Q; ++i) s += sh.Z[i * Q + a] * sh.Z[i * Q + b];
-        sh.Inv[e] = s;
-    }
-    __syncthreads();
-}
-
-// The same q x q system and F from it on one wavefront, with no workgroup
-// barrier: the caller runs it on a wavefront of its own while the others
-// work on what does not need Inv or F, and orders it with the workgroup's
-// next barrier.  Cholesky with the reciprocal of each pivot, L^-1 by forward
-// substitution, Inv = L^-T L^-1; XSIDE: F = G Inv, else F[b][a] = (Inv C)[a][b].
-template <int Q, bool XSIDE>
-__device__ void spd_solve_wave(AdmShared<Q> &sh, double shift, int lane) {
-    for (int e = lane; e < Q * Q; e += WAVE) {
-        const int a = e / Q, b = e % Q;
-        sh.A[e] = (double)sh.G[e] + (a == b ? shift : 0.0);
-    }
-    wave_lds_sync();
-    for (int j = 0; j < Q; ++j) {
-        const double djj = sqrt(sh.A[j * Q + j]);
-        const double rj = 1.0 / djj;
-        for (int e = lane; e < Q * Q; e += WAVE) {
-            const int i = e / Q, k = e % Q;
-            if (k > j && i >= k) sh.A[e] -= (sh.A[i * Q + j] * rj) * (sh.A[k * Q + j] * rj);
-        }
-        wave_lds_sync();
-        for (int i = j + 1 + lane; i < Q; i += WAVE) sh.A[i * Q + j] *= rj;
-        if (lane == 0) sh.A[j * Q + j] = djj;
-        wave_lds_sync();
-    }
-    for (int i = lane; i < Q; i += WAVE) sh.Z[i * Q + i] = 1.0 / sh.A[i * Q + i];   // reciprocal pivots
-    wave_lds_sync();
-    if (lane < Q) {                             // column lane of L^-1
-        const int j = lane;
-        for (int i = j + 1; i < Q; ++i) {
-            double s = 0.0;
-            for (int l = j; l < i; ++l) s -= sh.A[i * Q + l] * sh.Z[l * Q + j];
-            sh.Z[i * Q + j] = s * sh.Z[i * Q + i];
-        }
-    }
-    wave_lds_sync();
-    for (int e = lane; e < Q * Q; e += WAVE) {  // Inv = Z^T Z
-        const int a = e / Q, b = e % Q;
-        const int lo = a > b ? a : b;
-        double s = 0.0;
-        for (int i = lo; i < Q; ++i) s += sh.Z[i * Q + a] * sh.Z[i * Q + b];
-        sh.Inv[e] = s;
-    }
-    wave_lds_sync();
-    for (int e = lane; e < Q * Q; e += WAVE) {
-        const int a = e / Q, b = e % Q;
-        double v = 0.0;
-        if (XSIDE) {
-            for (int l = 0; l < Q; ++l) v += (double)sh.G[a * Q + l] * sh.Inv[l * Q + b];
-            sh.F[e] = v;
-        } else {
-            for (int l = 0; l < Q; ++l) v += sh.Inv[a * Q + l] * (double)sh.C[l * Q + b];
-            sh.F[b * Q + a] = v;
-        }
-    }
-}
-
-// Gram G = M^T M of a (rows x Q) FP32 matrix into sh.G.  The rows stream
-// through LDS in tiles of GRAM_STAGE floats (coalesced float4 loads, the next
-// tile in flight while the current one is used); a thread owns a 4 x 4 block
-// of G and every groups-th row of a tile.  The groups' partial blocks are then
-// summed in group order, so the result does not depend on timing.  part holds
-// PCAP floats.
-constexpr int GRAM_STAGE = 16384;
-
-template <int Q, int PCAP, int THREADS>
-__device__ void gram_rows(AdmShared<Q> &sh, const float *__restrict__ M, int rows, float *part, float *stage) {
-    constexpr int P = Q * Q, QB = Q / 4, NB = QB * QB;
-    constexpr int TR = GRAM_STAGE / Q;                  // rows per tile
-    constexpr int NL = GRAM_STAGE / 4 / THREADS;        // float4 per thread per tile
-    static_assert(NL >= 1 && NL * 4 * THREADS == GRAM_STAGE, "tile split");
-    const int t = fresh_tid();
-    const int groups = min(THREADS / NB, PCAP / P);
-    const int g = t / NB, blk = t % NB;
-    const int a0 = 4 * (blk / QB), b0 = 4 * (blk % QB);
-    const float4 *M4 = reinterpret_cast<const float4 *>(M);
-    const int64_t tot4 = (int64_t)rows * (Q / 4);
-    const int ntiles = (rows + TR - 1) / TR;
-    float4 buf[NL];
-    auto load = [&](int tile) {
-#pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            const int64_t idx = (int64_t)tile * (GRAM_STAGE / 4) + u * THREADS + t;
-            buf[u] = idx < tot4 ? M4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-    };
-    float acc[4][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
-    if (ntiles > 0) load(0);
-    float4 *stage4 = reinterpret_cast<float4 *>(stage);
-    for (int tile = 0; tile < ntiles; ++tile) {
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < NL; ++u) stage4[u * THREADS + t] = buf[u];
-        __syncthreads();
-        if (tile + 1 < ntiles) load(tile + 1);
-        const int rt = min(TR, rows - tile * TR);
-        if (g < groups) {
-            for (int r = g; r < rt; r += groups) {
-                const float4 u = stage4[(r * Q + a0) / 4];
-                const float4 v = stage4[(r * Q + b0) / 4];
-                const float ua[4] = {u.x, u.y, u.z, u.w}, vb[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(ua[x], vb[y], acc[x][y]);
-            }
-        }
-    }
-    if (g < groups) {
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) part[g * P + (a0 + x) * Q + b0 + y] = acc[x][y];
-    }
-    __syncthreads();
-    for (int e = t; e < P; e += THREADS) {
-        float v = 0.f;
-        for (int gg = 0; gg < groups; ++gg) v += part[gg * P + e];
-        sh.G[e] = v;
-    }
-    __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// Completion of the slices whose X does not fit in LDS (rank 32, or tall
-// slices), with X and Y in global memory, as a sequence of launches per
-// iteration over all such slices of a rank bucket, so that every phase has
-// the whole GPU and the launch boundaries order the phases (no workgroup
-// waits for another):
-//   init    (workgroup per slice)  scale, initial factors, GY, X system
-//   rows    (per 64-row block)     residuals of the row's samples, R_i Y^T,
-//                                  X+_i = X_i F + T_i Inv, U, Lambda (a wavefront per row)
-//   ysys    (workgroup per slice)  residual norm and the stop test, GX = X+^T X+,
-//                                  C = X+^T X, Y system
-//   cols    (per 256-column block) residuals again from X and Y, X+^T R_j,
-//                                  Y+_j = F Y_j + Inv T_j, V, Pi (a lane per light
-//                                  column, a wavefront per heavy one)
-//   xsys    (workgroup per slice)  GY = Y+^T Y+, X system for the next iteration
-//   final   (workgroup per slice)  the final X into the X region, statistics
-// The two X buffers alternate by iteration parity.  The q x q systems (FP64,
-// with FP32 copies for the light columns) and the slice's stop state live in
-// GADM_SYS_BYTES per slice.  The arithmetic per row and per column is that of
-// a single-workgroup completion; the Grams are sums in a fixed order.
-
-struct GadmArgs {
-    const SliceDesc *desc;
-    const int32_t *ids;                  // the group's slices
-    const int32_t *rowp, *colp;          // count + 1: prefixes of the slices' row and column blocks
-    int32_t count;
-    uint64_t seed;
-    int32_t max_iter, mode;
-    float tol, alpha0, beta0, gamma;
-    const int32_t *row_ptr_all, *csr_col_all;
-    const float *csr_val_all;
-    const int32_t *col_ptr_all, *csc_row_all;
-    const float *csc_val_all;
-    float *X_all, *Xn_all, *Xp_all, *Lam_all, *Y_all, *Yp_all, *Pi_all, *scale_all;
-    int32_t *stats_all;
-    char *gsys;
-    double *ge2;                         // the group's first row block slot
-};
-
-struct GSys {
-    double *F, *Inv;                     // Q x Q (X side: F = G Inv; Y side: F stored transposed)
-    float *Ff, *If;                      // Y side, FP32: Ff[a][b] = (Inv C)[a][b], If = Inv
-    int32_t *state;                      // done, iterations, FP32 bits of the residual, all-zero
-    double *dstate;                      // ||P_Omega M|| / s0, s0
-};
-
-__device__ __forceinline__ GSys gsys_of(char *base, int s) {
-    char *p = base + (size_t)s * GADM_SYS_BYTES;
-    GSys g;
-    g.F = reinterpret_cast<double *>(p);
-    g.Inv = g.F + 32 * 32;
-    g.Ff = reinterpret_cast<float *>(p + 2 * 32 * 32 * 8);
-    g.If = g.Ff + 32 * 32;
-    g.state = reinterpret_cast<int32_t *>(p + 2 * 32 * 32 * 8 + 2 * 32 * 32 * 4);
-    g.dstate = reinterpret_cast<double *>(p + 2 * 32 * 32 * 8 + 2 * 32 * 32 * 4 + 16);
-    return g;
-}
-
-// item b of a launch over the group's blocks: the slice position k with
-// pre[k] <= b < pre[k + 1]
-__device__ __forceinline__ int block_slice(const int32_t *__restrict__ pre, int count, int b) {
-    int lo = 0, hi = count;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (pre[mid] <= b) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-// Cross Gram C = A^T B of two (rows x Q) FP32 matrices into sh.C, streamed
-// through LDS like gram_rows (half a stage each).
-template <int Q, int PCAP, int THREADS>
-__device__ void gram_cross(AdmShared<Q> &sh, const float *__restrict__ A, const float *__restrict__ B, int rows,
-                           float *part, float *stage) {
-    constexpr int P = Q * Q, QB = Q / 4, NB = QB * QB;
-    constexpr int HALF = GRAM_STAGE / 2;
-    constexpr int TR = HALF / Q;
-    constexpr int NL = HALF / 4 / THREADS;
-    static_assert(NL >= 1 && NL * 4 * THREADS == HALF, "tile split");
-    const int t = fresh_tid();
-    const int groups = min(THREADS / NB, PCAP / P);
-    const int g = t / NB, blk = t % NB;
-    const int a0 = 4 * (blk / QB), b0 = 4 * (blk % QB);
-    const float4 *A4 = reinterpret_cast<const float4 *>(A);
-    const float4 *B4 = reinterpret_cast<const float4 *>(B);
-    const int64_t tot4 = (int64_t)rows * (Q / 4);
-    const int ntiles = (rows + TR - 1) / TR;
-    float acc[4][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
-    float4 *sa = reinterpret_cast<float4 *>(stage);
-    float4 *sb = reinterpret_cast<float4 *>(stage + HALF);
-    for (int tile = 0; tile < ntiles; ++tile) {
-        float4 ba[NL], bb[NL];
-#pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            const int64_t idx = (int64_t)tile * (HALF / 4) + u * THREADS + t;
-            ba[u] = idx < tot4 ? A4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
-            bb[u] = idx < tot4 ? B4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            sa[u * THREADS + t] = ba[u];
-            sb[u * THREADS + t] = bb[u];
-        }
-        __syncthreads();
-        const int rt = min(TR, rows - tile * TR);
-        if (g < groups) {
-            for (int r = g; r < rt; r += groups) {
-                const float4 u = sa[(r * Q + a0) / 4];
-                const float4 v = sb[(r * Q + b0) / 4];
-                const float ua[4] = {u.x, u.y, u.z, u.w}, vb[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(ua[x], vb[y], acc[x][y]);
-            }
-        }
-    }
-    if (g < groups) {
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) part[g * P + (a0 + x) * Q + b0 + y] = acc[x][y];
-    }
-    __syncthreads();
-    for (int e = t; e < P; e += THREADS) {
-        float v = 0.f;
-        for (int gg = 0; gg < groups; ++gg) v += part[gg * P + e];
-        sh.C[e] = v;
-    }
-    __syncthreads();
-}
-
-// sh.F, sh.Inv of the X system (F = G Inv, Inv = (G + a I)^-1) from sh.G, stored into the slice's state
-template <int Q, int THREADS>
-__device__ void gadm_x_system(AdmShared<Q> &sh, const GSys &g, double alpha) {
-    const int t = fresh_tid();
-    spd_inverse<Q>(sh, alpha);
-    for (int e = t; e < Q * Q; e += THREADS) {
-        const int a = e / Q, b = e % Q;
-        double v = 0.0;
-        for (int l = 0; l < Q; ++l) v += (double)sh.G[a * Q + l] * sh.Inv[l * Q + b];
-        g.F[e] = v;
-        g.Inv[e] = sh.Inv[e];
-    }
-}
-
-template <int Q, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_gadm_init(GadmArgs a) {
-    constexpr int NW = THREADS / WAVE;
-    __shared__ AdmShared<Q> sh;
-    constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
-    __shared__ float part[PCAP];
-    __shared__ __align__(16) float stage[GRAM_STAGE];
-    const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
-    const SliceDesc d = a.desc[s];
-    const int m = d.m, n = d.n;
-    const int qr = d.qr;
-    const int t = threadIdx.x, lane = t % WAVE;
-    const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
-    const GSys g = gsys_of(a.gsys, s);
-    const uint64_t seed = a.seed;
-    const int32_t fixed_iters = a.mode;
-    const int32_t *row_ptr = a.row_ptr_all + d.off_row;
-    const float *csr_val = a.csr_val_all + 3 * d.off_omega;
-    float *Xa = a.X_all + d.off_x;
-    float *Xp = a.Xp_all + d.off_x;
-    float *Lam = a.Lam_all + d.off_x;
-    float *Y = a.Y_all + d.off_y;
-    float *Yp = a.Yp_all + d.off_y;
-    float *Pi = a.Pi_all + d.off_y;
-    float *scale_all = a.scale_all;
-    int32_t *st = a.stats_all + 4 * s;
-    const int nnz = row_ptr[m];
-    if (t == 0) {
-        g.state[0] = 0;
-        g.state[1] = a.max_iter;
-        g.state[2] = __float_as_int(0.f);
-        g.state[3] = 0;
-    }
-
-    // ---- scale s0 = mean sampled value; ||P_Omega M|| ----
-    double sum = 0.0, sumsq = 0.0;
-    for (int p = t; p < 3 * nnz; p += THREADS) {
-        const double v = (double)csr_val[p];
-        sum += v;
-        sumsq += v * v;
-    }
-    sum = wave_sum_d(sum);
-    sumsq = wave_sum_d(sumsq);
-    if (lane == 0) {
-        sh.red[wave] = sum;
-        sh.red[16 + wave] = sumsq;
-    }
-    __syncthreads();
-    double tot = 0.0, totsq = 0.0;
-    for (int w = 0; w < NW; ++w) {
-        tot += sh.red[w];
-        totsq += sh.red[16 + w];
-    }
-    __syncthreads();
-    if (!(nnz > 0 && tot > 0.0)) {
-        for (int e = t; e < m * Q; e += THREADS) Xa[e] = 0.f;
-        for (int e = t; e < 3 * n * Q; e += THREADS) Y[e] = 0.f;
-        if (t == 0) {
-            scale_all[s] = 0.f;
-            st[0] = 0;
-            st[1] |= VPLMC_SLICE_ALL_ZERO;
-            st[2] = __float_as_int(0.f);
-            g.state[0] = 1;     // done
-            g.state[1] = 0;     // iterations
-            g.state[3] = 1;     // all zero: the stats stand
-        }
-        return;
-    }
-    const double s0 = tot / (3.0 * (double)nnz);
-    const float inv_s0 = (float)(1.0 / s0);
-    const double normM = sqrt(totsq) / s0;
-    if (t == 0) {
-        scale_all[s] = (float)s0;
-        g.dstate[0] = normM;
-        g.dstate[1] = s0;
-    }
-
-    // ---- initial factors: fp32(u24(Philox) * fp32(2 / sqrt q)), or (mode bit 1)
-    // the contents of the X and Y regions ----
-    const float cq = (float)(2.0 / sqrt((double)qr));
-    const bool given = (fixed_iters & 2) != 0;
-    const bool nonneg = (fixed_iters & 4) == 0;    // mode bit 2: projections off
-    for (int e = t; e < m * Q; e += THREADS) {
-        const int i = e / Q, k = e % Q;
-        const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
-        const float v = k < qr ? (given ? Xa[e] : __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq)) : 0.f;
-        Xa[e] = v;
-        Xp[e] = v;
-        Lam[e] = 0.f;
-    }
-    for (int e = t; e < 3 * n * Q; e += THREADS) {
-        const int j = e / (3 * Q), c = (e / Q) % 3, k = e % Q;
-        const uint64_t col = (uint64_t)c * (uint64_t)n + (uint64_t)j;
-        const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)k, col, TAG_INITY, 0);
-        const float v = k < qr ? (given ? Y[e] : __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq)) : 0.f;
-        Y[e] = v;
-        Yp[e] = v;
-        Pi[e] = 0.f;
-    }
-    __threadfence_block();
-    __syncthreads();
-
-
-    gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * n, part, stage);
-    gadm_x_system<Q, THREADS>(sh, g, (double)a.alpha0 * (3.0 * n) / qr);
-    (void)wave;
-    (void)lane;
-    (void)inv_s0;
-}
-
-template <int Q, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_gadm_rows(GadmArgs a, int it) {
-    constexpr int NW = THREADS / WAVE;
-    __shared__ double shF[Q * Q], shInv[Q * Q];
-    __shared__ __align__(16) float stage[NW * 33 * Q];
-    const int b = blockIdx.x;
-    const int k = block_slice(a.rowp, a.count, b);
-    const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
-    const GSys g = gsys_of(a.gsys, s);
-    if (g.state[0]) return;
-    const SliceDesc d = a.desc[s];
-    const int m = d.m, n = d.n, qr = d.qr;
-    const int t = threadIdx.x, lane = t % WAVE;
-    const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
-    const int r_beg = (b - a.rowp[k]) * GADM_RB, r_end = min(m, r_beg + GADM_RB);
-    for (int e = t; e < Q * Q; e += THREADS) {
-        shF[e] = g.F[e];
-        shInv[e] = g.Inv[e];
-    }
-    struct {
-        double *F, *Inv;
-    } sh = {shF, shInv};
-    const bool nonneg = (a.mode & 4) == 0;
-    const double s0 = g.dstate[1];
-    const float inv_s0 = (float)(1.0 / s0);
-    const double alpha = (double)a.alpha0 * (3.0 * n) / qr;
-    const float alpha_f = (float)alpha;
-    const float ga = (float)((double)a.gamma * alpha);
-    const float inv_alpha = (float)(1.0 / alpha);
-    const int32_t *row_ptr = a.row_ptr_all + d.off_row;
-    const int32_t *csr_col = a.csr_col_all + d.off_omega;
-    const float *csr_val = a.csr_val_all + 3 * d.off_omega;
-    const float *X = ((it & 1) ? a.Xn_all : a.X_all) + d.off_x;
-    float *Xn = ((it & 1) ? a.X_all : a.Xn_all) + d.off_x;
-    float *Xp = a.Xp_all + d.off_x;
-    float *Lam = a.Lam_all + d.off_x;
-    const float *Y = a.Y_all + d.off_y;
-    __syncthreads();
-    float *wsa = stage + wave * (33 * Q);   // [32][q] partial rows, then T_i (q)
-    double e2 = 0.0;
-        for (int i = r_beg + wave; i < r_end; i += NW) {
-            float xi[Q];
-            const float4 *xr = reinterpret_cast<const float4 *>(X + (size_t)i * Q);
-#pragma unroll
-            for (int k = 0; k < Q; k += 4) {
-                const float4 u = xr[k / 4];
-                xi[k] = u.x; xi[k + 1] = u.y; xi[k + 2] = u.z; xi[k + 3] = u.w;
-            }
-            float acc[Q];
-#pragma unroll
-            for (int k = 0; k < Q; ++k) acc[k] = 0.f;
-            const int beg = row_ptr[i], end = row_ptr[i + 1];
-            for (int p = beg + lane; p < end; p += WAVE) {
-                const int j = csr_col[p];
-                const float m0 = csr_val[3 * p] * inv_s0;
-                const float m1 = csr_val[3 * p + 1] * inv_s0;
-                const float m2 = csr_val[3 * p + 2] * inv_s0;
-                const float *yj = Y + (size_t)j * 3 * Q;
-                float y0[Q], y1[Q], y2[Q];
-#pragma unroll
-                for (int k = 0; k < Q; k += 4) {
-                    const float4 a = *(const float4 *)(yj + k);
-                    const float4 b = *(const float4 *)(yj + Q + k);
-                    const float4 c = *(const float4 *)(yj + 2 * Q + k);
-                    y0[k] = a.x; y0[k + 1] = a.y; y0[k + 2] = a.z; y0[k + 3] = a.w;
-                    y1[k] = b.x; y1[k + 1] = b.y; y1[k + 2] = b.z; y1[k + 3] = b.w;
-                    y2[k] = c.x; y2[k + 1] = c.y; y2[k + 2] = c.z; y2[k + 3] = c.w;
-                }
-                float d0 = 0.f, d1 = 0.f, d2 = 0.f;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    d0 = fmaf(xi[k], y0[k], d0);
-                    d1 = fmaf(xi[k], y1[k], d1);
-                    d2 = fmaf(xi[k], y2[k], d2);
-                }
-                const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
-                e2 += (double)(r0 * r0) + (double)(r1 * r1) + (double)(r2 * r2);
-#pragma unroll
-                for (int k = 0; k < Q; ++k) acc[k] = fmaf(r0, y0[k], fmaf(r1, y1[k], fmaf(r2, y2[k], acc[k])));
-            }
-            // R_i Y^T: lanes 32..63 folded onto 0..31, the 32 partial rows
-            // transposed through the wavefront's LDS area, lane k summing element k
-#pragma unroll
-            for (int k = 0; k < Q; ++k) acc[k] += __shfl_xor(acc[k], 32, WAVE);
-            if (lane < 32) {
-                float4 *row = reinterpret_cast<float4 *>(wsa + lane * Q);
-#pragma unroll
-                for (int k = 0; k < Q; k += 4) row[k / 4] = make_float4(acc[k], acc[k + 1], acc[k + 2], acc[k + 3]);
-            }
-            wave_lds_sync();
-            // X+_i (lane k < Q owns column k): T_k = (R_i Y^T)_k + a U_ik - L_ik staged
-            // for the wavefront, then U and Lambda updates
-            float lam = 0.f;
-            if (lane < Q) {
-                float sum = 0.f;
-                for (int r = 0; r < 32; ++r) sum += wsa[r * Q + lane];
-                lam = Lam[(size_t)i * Q + lane];
-                wsa[32 * Q + lane] = sum + alpha_f * Xp[(size_t)i * Q + lane] - lam;
-            }
-            wave_lds_sync();
-            float xn = 0.f;
-            if (lane < Q) {
-                const int k = lane;
-                double v = 0.0;
-#pragma unroll
-                for (int l = 0; l < Q; ++l)
-                    v += (double)xi[l] * sh.F[l * Q + k] + (double)wsa[32 * Q + l] * sh.Inv[l * Q + k];
-                xn = (float)v;
-                const float u = nonneg ? fmaxf(0.f, xn + lam * inv_alpha) : xn + lam * inv_alpha;
-                Xn[(size_t)i * Q + k] = xn;
-                Xp[(size_t)i * Q + k] = u;
-                Lam[(size_t)i * Q + k] = lam + ga * (xn - u);
-            }
-            // the next row's partial rows overwrite this area
-            wave_lds_sync();
-        }
-    e2 = wave_sum_d(e2);
-    __shared__ double red[NW];
-    if (lane == 0) red[wave] = e2;
-    __syncthreads();
-    if (t == 0) {
-        double tot = 0.0;
-        for (int w = 0; w < NW; ++w) tot += red[w];
-        a.ge2[b] = tot;
-    }
-}
-
-template <int Q, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_gadm_ysys(GadmArgs a, int it) {
-    constexpr int NW = THREADS / WAVE;
-    __shared__ AdmShared<Q> sh;
-    constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
-    __shared__ float part[PCAP];
-    __shared__ __align__(16) float stage[GRAM_STAGE];
-    __shared__ int stop_s;
-    const int k = blockIdx.x;
-    const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
-    const GSys g = gsys_of(a.gsys, s);
-    if (g.state[0]) return;
-    const SliceDesc d = a.desc[s];
-    const int m = d.m, qr = d.qr;
-    const int t = threadIdx.x;
-    if (t == 0) {
-        // the squared residuals of the slice's row blocks, in block order
-        double e2 = 0.0;
-        for (int rb = a.rowp[k]; rb < a.rowp[k + 1]; ++rb) e2 += a.ge2[rb];
-        const double err = sqrt(e2) / g.dstate[0];
-        g.state[2] = __float_as_int((float)err);
-        const bool stop = !(a.mode & 1) && err < (double)a.tol;
-        if (stop) {
-            g.state[0] = 1;
-            g.state[1] = it;
-        }
-        stop_s = stop ? 1 : 0;
-    }
-    __syncthreads();
-    if (stop_s) return;
-    const float *X = ((it & 1) ? a.Xn_all : a.X_all) + d.off_x;
-    const float *Xn = ((it & 1) ? a.X_all : a.Xn_all) + d.off_x;
-    gram_rows<Q, PCAP, THREADS>(sh, Xn, m, part, stage);
-    gram_cross<Q, PCAP, THREADS>(sh, Xn, X, m, part, stage);
-    const double beta = (double)a.beta0 * (double)m / qr;
-    spd_inverse<Q>(sh, beta);
-    for (int e = t; e < Q * Q; e += THREADS) {
-        const int aa = e / Q, bb = e % Q;   // F[a][b] = sum_l Inv[a][l] C[l][b]; F^T at [b][a]
-        double v = 0.0;
-        for (int l = 0; l < Q; ++l) v += sh.Inv[aa * Q + l] * (double)sh.C[l * Q + bb];
-        g.F[bb * Q + aa] = v;
-        g.Inv[e] = sh.Inv[e];
-        g.Ff[e] = (float)v;
-        g.If[e] = (float)sh.Inv[e];
-    }
-}
-
-template <int Q, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_gadm_cols(GadmArgs a, int it) {
-    constexpr int NW = THREADS / WAVE;
-    __shared__ double shF[Q * Q], shInv[Q * Q];
-    __shared__ __align__(16) float Ff[Q * Q];
-    __shared__ __align__(16) float If[Q * Q];
-    __shared__ __align__(16) float stage[NW * 33 * 3 * Q];
-    const int b = blockIdx.x;
-    const int k = block_slice(a.colp, a.count, b);
-    const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
-    const GSys g = gsys_of(a.gsys, s);
-    if (g.state[0]) return;
-    const SliceDesc d = a.desc[s];
-    const int m = d.m, n = d.n, qr = d.qr;
-    const int t = threadIdx.x, lane = t % WAVE;
-    const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
-    const int c_beg = (b - a.colp[k]) * GADM_CB, c_end = min(n, c_beg + GADM_CB);
-    for (int e = t; e < Q * Q; e += THREADS) {
-        shF[e] = g.F[e];
-        shInv[e] = g.Inv[e];
-        Ff[e] = g.Ff[e];
-        If[e] = g.If[e];
-    }
-    struct {
-        double *F, *Inv;
-    } sh = {shF, shInv};
-    const bool nonneg = (a.mode & 4) == 0;
-    const double s0 = g.dstate[1];
-    const float inv_s0 = (float)(1.0 / s0);
-    const double beta = (double)a.beta0 * (double)m / qr;
-    const float beta_f = (float)beta;
-    const float gb = (float)((double)a.gamma * beta);
-    const float inv_beta = (float)(1.0 / beta);
-    const int32_t *col_ptr = a.col_ptr_all + d.off_colptr;
-    const int32_t *csc_row = a.csc_row_all + d.off_omega;
-    const float *csc_val = a.csc_val_all + 3 * d.off_omega;
-    const float *X = ((it & 1) ? a.Xn_all : a.X_all) + d.off_x;
-    const float *Xn = ((it & 1) ? a.X_all : a.Xn_all) + d.off_x;
-    float *Y = a.Y_all + d.off_y;
-    float *Yp = a.Yp_all + d.off_y;
-    float *Pi = a.Pi_all + d.off_y;
-    __syncthreads();
-        // ---- phase B, light columns (at most GADM_LIGHT samples): lane per column ----
-        // X+^T R_j over the column's samples, then per channel Y+_j = F Y_j + Inv T_j
-        // with the FP32 copies of the system
-        {
-            const int j = c_beg + fresh_tid();
-            int beg = 0, end = 0;
-            if (j < c_end) {
-                beg = col_ptr[j];
-                end = col_ptr[j + 1];
-            }
-            if (j < c_end && end - beg <= GADM_LIGHT) {
-                // an opaque zero offset keeps the system's LDS reads inside the loop
-                // (hoisted, 2 Q^2 values would stay in registers)
-                int z = 0;
-                asm volatile("" : "+v"(z));
-                float y[3][Q], acc[3][Q];
-                const float4 *yj = reinterpret_cast<const float4 *>(Y + (size_t)j * 3 * Q);
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-#pragma unroll
-                    for (int k = 0; k < Q; k += 4) {
-                        const float4 u = yj[(c * Q + k) / 4];
-                        y[c][k] = u.x;
-                        y[c][k + 1] = u.y;
-                        y[c][k + 2] = u.z;
-                        y[c][k + 3] = u.w;
-                        acc[c][k] = acc[c][k + 1] = acc[c][k + 2] = acc[c][k + 3] = 0.f;
-                    }
-                for (int p = beg; p < end; ++p) {
-                    const int i = csc_row[p];
-                    const float m0 = csc_val[3 * p] * inv_s0;
-                    const float m1 = csc_val[3 * p + 1] * inv_s0;
-                    const float m2 = csc_val[3 * p + 2] * inv_s0;
-                    const float4 *xo = reinterpret_cast<const float4 *>(X + (size_t)i * Q);
-                    const float4 *xp = reinterpret_cast<const float4 *>(Xn + (size_t)i * Q);
-                    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
-#pragma unroll
-                    for (int k = 0; k < Q; k += 4) {
-                        const float4 u = xo[k / 4];
-                        const float xa[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            d0 = fmaf(xa[e], y[0][k + e], d0);
-                            d1 = fmaf(xa[e], y[1][k + e], d1);
-                            d2 = fmaf(xa[e], y[2][k + e], d2);
-                        }
-                    }
-                    const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
-#pragma unroll
-                    for (int k = 0; k < Q; k += 4) {
-                        const float4 v = xp[k / 4];
-                        const float xb[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            acc[0][k + e] = fmaf(xb[e], r0, acc[0][k + e]);
-                            acc[1][k + e] = fmaf(xb[e], r1, acc[1][k + e]);
-                            acc[2][k + e] = fmaf(xb[e], r2, acc[2][k + e]);
-                        }
-                    }
-                }
-                float4 *ypj = reinterpret_cast<float4 *>(Yp + (size_t)j * 3 * Q);
-                float4 *pij = reinterpret_cast<float4 *>(Pi + (size_t)j * 3 * Q);
-                float4 *yw = reinterpret_cast<float4 *>(Y + (size_t)j * 3 * Q);
-                // T_j = X+^T R_j + b V_j - P_j in place of the sums
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-#pragma unroll
-                    for (int l = 0; l < Q; l += 4) {
-                        const float4 v = ypj[(c * Q + l) / 4], pp = pij[(c * Q + l) / 4];
-                        acc[c][l] = acc[c][l] + beta_f * v.x - pp.x;
-                        acc[c][l + 1] = acc[c][l + 1] + beta_f * v.y - pp.y;
-                        acc[c][l + 2] = acc[c][l + 2] + beta_f * v.z - pp.z;
-                        acc[c][l + 3] = acc[c][l + 3] + beta_f * v.w - pp.w;
-                    }
-                // outputs k..k+3 of the three channels; every read of Yp and P is
-                // above, so they are stored at once
-#pragma unroll 1
-                for (int k = 0; k < Q; k += 4) {
-                    float o[3][4];
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const float4 *fk = reinterpret_cast<const float4 *>(Ff + z + (k + kk) * Q);
-                        const float4 *ik = reinterpret_cast<const float4 *>(If + z + (k + kk) * Q);
-                        float v0 = 0.f, v1 = 0.f, v2 = 0.f;
-#pragma unroll
-                        for (int l = 0; l < Q; l += 4) {
-                            const float4 f = fk[l / 4], g = ik[l / 4];
-                            const float fa[4] = {f.x, f.y, f.z, f.w}, ga[4] = {g.x, g.y, g.z, g.w};
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                v0 = fmaf(fa[e], y[0][l + e], fmaf(ga[e], acc[0][l + e], v0));
-                                v1 = fmaf(fa[e], y[1][l + e], fmaf(ga[e], acc[1][l + e], v1));
-                                v2 = fmaf(fa[e], y[2][l + e], fmaf(ga[e], acc[2][l + e], v2));
-                            }
-                        }
-                        o[0][kk] = v0;
-                        o[1][kk] = v1;
-                        o[2][kk] = v2;
-                    }
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const int w = (c * Q + k) / 4;
-                        const float4 pv = pij[w];
-                        const float pa[4] = {pv.x, pv.y, pv.z, pv.w};
-                        float un[4], pn[4];
-#pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) {
-                            un[kk] = nonneg ? fmaxf(0.f, o[c][kk] + pa[kk] * inv_beta) : o[c][kk] + pa[kk] * inv_beta;
-                            pn[kk] = pa[kk] + gb * (o[c][kk] - un[kk]);
-                        }
-                        ypj[w] = make_float4(un[0], un[1], un[2], un[3]);
-                        pij[w] = make_float4(pn[0], pn[1], pn[2], pn[3]);
-                        yw[w] = make_float4(o[c][0], o[c][1], o[c][2], o[c][3]);
-                    }
-                }
-            }
-        }
-
-        // ---- phase B, heavy columns: wavefront per column ----
-        float *wst = stage + wave * (33 * 3 * Q);   // [32][3q] partial rows, then T_j (3q)
-        for (int jb = c_beg + wave * WAVE; jb < c_end; jb += NW * WAVE) {
-            const int jl = jb + lane;
-            const int cnt = jl < c_end ? col_ptr[jl + 1] - col_ptr[jl] : 0;
-            uint64_t heavy = __ballot(cnt > GADM_LIGHT);
-            while (heavy) {
-                const int j = jb + __builtin_ctzll(heavy);
-                heavy &= heavy - 1;
-                float y0[Q], y1[Q], y2[Q];
-                const float4 *yj = reinterpret_cast<const float4 *>(Y + (size_t)j * 3 * Q);
-#pragma unroll
-                for (int k = 0; k < Q; k += 4) {
-                    const float4 u = yj[k / 4], v = yj[(Q + k) / 4], w = yj[(2 * Q + k) / 4];
-                    y0[k] = u.x; y0[k + 1] = u.y; y0[k + 2] = u.z; y0[k + 3] = u.w;
-                    y1[k] = v.x; y1[k + 1] = v.y; y1[k + 2] = v.z; y1[k + 3] = v.w;
-                    y2[k] = w.x; y2[k + 1] = w.y; y2[k + 2] = w.z; y2[k + 3] = w.w;
-                }
-                float a0[Q], a1[Q], a2[Q];
-#pragma unroll
-                for (int k = 0; k < Q; ++k) a0[k] = a1[k] = a2[k] = 0.f;
-                const int beg = col_ptr[j], end = col_ptr[j + 1];
-                for (int p = beg + lane; p < end; p += WAVE) {
-                    const int i = csc_row[p];
-                    const float m0 = csc_val[3 * p] * inv_s0;
-                    const float m1 = csc_val[3 * p + 1] * inv_s0;
-                    const float m2 = csc_val[3 * p + 2] * inv_s0;
-                    const float *xo = X + (size_t)i * Q;
-                    const float *xp = Xn + (size_t)i * Q;
-                    float xa[Q], xb[Q];
-#pragma unroll
-                    for (int k = 0; k < Q; k += 4) {
-                        const float4 u = *(const float4 *)(xo + k);
-                        const float4 v = *(const float4 *)(xp + k);
-                        xa[k] = u.x; xa[k + 1] = u.y; xa[k + 2] = u.z; xa[k + 3] = u.w;
-                        xb[k] = v.x; xb[k + 1] = v.y; xb[k + 2] = v.z; xb[k + 3] = v.w;
-                    }
-                    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
-#pragma unroll
-                    for (int k = 0; k < Q; ++k) {
-                        d0 = fmaf(xa[k], y0[k], d0);
-                        d1 = fmaf(xa[k], y1[k], d1);
-                        d2 = fmaf(xa[k], y2[k], d2);
-                    }
-                    const float r0 = m0 - d0, r1 = m1 - d1, r2 = m2 - d2;
-#pragma unroll
-                    for (int k = 0; k < Q; ++k) {
-                        a0[k] = fmaf(xb[k], r0, a0[k]);
-                        a1[k] = fmaf(xb[k], r1, a1[k]);
-                        a2[k] = fmaf(xb[k], r2, a2[k]);
-                    }
-                }
-                // X+^T R_j: lanes 32..63 folded onto 0..31, the 32 partial rows
-                // transposed through the wavefront's LDS area, lane o summing element o
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    a0[k] += __shfl_xor(a0[k], 32, WAVE);
-                    a1[k] += __shfl_xor(a1[k], 32, WAVE);
-                    a2[k] += __shfl_xor(a2[k], 32, WAVE);
-                }
-                if (lane < 32) {
-                    float4 *row = reinterpret_cast<float4 *>(wst + lane * 3 * Q);
-#pragma unroll
-                    for (int k = 0; k < Q; k += 4) {
-                        row[k / 4] = make_float4(a0[k], a0[k + 1], a0[k + 2], a0[k + 3]);
-                        row[(Q + k) / 4] = make_float4(a1[k], a1[k + 1], a1[k + 2], a1[k + 3]);
-                        row[(2 * Q + k) / 4] = make_float4(a2[k], a2[k + 1], a2[k + 2], a2[k + 3]);
-                    }
-                }
-                wave_lds_sync();
-                // output o = (c, k), lanes o < 3q (two rounds when 3q > 64):
-                // T_o = (X+^T R_j)_o + b V_o - P_o, staged for the whole wavefront
-                float *ypj = Yp + (size_t)j * 3 * Q;
-                float *pij = Pi + (size_t)j * 3 * Q;
-                float pv[2];
-#pragma unroll
-                for (int rnd = 0; rnd < 2; ++rnd) {
-                    const int o = lane + rnd * WAVE;
-                    pv[rnd] = 0.f;
-                    if (o < 3 * Q) {
-                        float sum = 0.f;
-                        for (int r = 0; r < 32; ++r) sum += wst[r * 3 * Q + o];
-                        pv[rnd] = pij[o];
-                        wst[32 * 3 * Q + o] = sum + beta_f * ypj[o] - pv[rnd];
-                    }
-                }
-                wave_lds_sync();
-                const float *tj = wst + 32 * 3 * Q;
-#pragma unroll
-                for (int rnd = 0; rnd < 2; ++rnd) {
-                    const int o = lane + rnd * WAVE;
-                    if (o < 3 * Q) {
-                        const int c = o / Q, k = o % Q;
-                        double v = 0.0;
-#pragma unroll
-                        for (int l = 0; l < Q; ++l) {
-                            const float yl = c == 0 ? y0[l] : (c == 1 ? y1[l] : y2[l]);
-                            v += sh.F[l * Q + k] * (double)yl + sh.Inv[l * Q + k] * (double)tj[c * Q + l];
-                        }
-                        const float yn = (float)v;
-                        const float u = nonneg ? fmaxf(0.f, yn + pv[rnd] * inv_beta) : yn + pv[rnd] * inv_beta;
-                        ypj[o] = u;
-                        pij[o] = pv[rnd] + gb * (yn - u);
-                        Y[(size_t)j * 3 * Q + o] = yn;
-                    }
-                }
-                // the next column's partial rows overwrite this area
-                wave_lds_sync();
-            }
-        }
-}
-
-template <int Q, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_gadm_xsys(GadmArgs a, int it) {
-    constexpr int NW = THREADS / WAVE;
-    __shared__ AdmShared<Q> sh;
-    constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
-    __shared__ float part[PCAP];
-    __shared__ __align__(16) float stage[GRAM_STAGE];
-    const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
-    const GSys g = gsys_of(a.gsys, s);
-    if (g.state[0]) return;
-    const SliceDesc d = a.desc[s];
-    const float *Y = a.Y_all + d.off_y;
-    gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * d.n, part, stage);
-    gadm_x_system<Q, THREADS>(sh, g, (double)a.alpha0 * (3.0 * d.n) / d.qr);
-    (void)it;
-}
-
-template <int Q, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_gadm_final(GadmArgs a) {
-    const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
-    const GSys g = gsys_of(a.gsys, s);
-    if (g.state[3]) return;                  // all-zero slice: set by the init launch
-    const SliceDesc d = a.desc[s];
-    const int iters = g.state[1];
-    const int t = threadIdx.x;
-    if (iters & 1) {                          // the final X is in the second buffer
-        const float *src = a.Xn_all + d.off_x;
-        float *dst = a.X_all + d.off_x;
-        for (int e = t; e < d.m * Q; e += THREADS) dst[e] = src[e];
-    }
-    if (t == 0) {
-        int32_t *st = a.stats_all + 4 * s;
-        st[0] = iters;
-        if (!(a.mode & 1) && iters >= a.max_iter) st[1] |= VPLMC_SLICE_NOT_CONVERGED;
-        st[2] = g.state[2];
-    }
-}
 
 // ---------------------------------------------------------------------------
 // LDS-resident variant for ranks 4, 8, 16 (two LDS buffers of m (q + 1)
@@ -1890,14 +932,6 @@ __global__ __launch_bounds__(256) void k_reduce(const SliceDesc *__restrict__ de
     }
 }
 
-// mode word of the completion kernels: bit 0 a fixed iteration count, bit 1
-// initial factors given in the X and Y regions, bit 2 no non-negativity
-// (U = X+ + Lambda / alpha, V = Y+ + Pi / beta without the projection)
-inline int32_t adm_mode(const vplmc_params &prm) {
-    return ((prm.flags & VPLMC_FIXED_ITERS) ? 1 : 0) | ((prm.flags & VPLMC_GIVEN_INIT) ? 2 : 0) |
-           ((prm.flags & VPLMC_NO_NONNEG) ? 4 : 0);
-}
-
 // grid of a launch over `count` slices: one workgroup per slice, or with a
 // queue as many workgroups as fit on the device at once (at most count)
 template <typename K>
@@ -1908,66 +942,6 @@ int adm_grid(K kern, int threads, size_t dyn, int n_cu, bool queue, size_t count
     VPLMC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, dyn));
     const size_t g = (size_t)std::max(per_cu, 1) * (size_t)std::max(n_cu, 1);
     grid = (unsigned)std::min(count, g);
-    return VPLMC_OK;
-}
-
-// the global-memory completion of group grp (odd: X in global memory): an
-// init launch, four launches per iteration, a final launch
-template <int Q, int THREADS>
-int launch_gadm(hipStream_t st, const vplmc_plan &plan, int grp, const int32_t *ids, const int32_t *gblk_dev,
-                char *gsys, double *ge2, const SliceDesc *desc, const vplmc_params &prm, const int32_t *row_ptr,
-                const int32_t *csr_col, const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row,
-                const float *csc_val, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
-                float *scale, int32_t *stats) {
-    const size_t count = plan.groups[grp].size();
-    if (count == 0) return VPLMC_OK;
-    GadmArgs a;
-    a.desc = desc;
-    a.ids = ids;
-    a.rowp = gblk_dev + plan.gblk_off[grp];
-    a.colp = a.rowp + count + 1;
-    a.count = (int32_t)count;
-    a.seed = prm.seed;
-    a.max_iter = prm.max_iter;
-    a.mode = adm_mode(prm);
-    a.tol = prm.tol;
-    a.alpha0 = prm.alpha0;
-    a.beta0 = prm.beta0;
-    a.gamma = prm.gamma;
-    a.row_ptr_all = row_ptr;
-    a.csr_col_all = csr_col;
-    a.csr_val_all = csr_val;
-    a.col_ptr_all = col_ptr;
-    a.csc_row_all = csc_row;
-    a.csc_val_all = csc_val;
-    a.X_all = X;
-    a.Xn_all = Xn;
-    a.Xp_all = Xp;
-    a.Lam_all = Lam;
-    a.Y_all = Y;
-    a.Yp_all = Yp;
-    a.Pi_all = Pi;
-    a.scale_all = scale;
-    a.stats_all = stats;
-    a.gsys = gsys;
-    a.ge2 = ge2 + plan.ge2_base[grp];
-    const unsigned nr = (unsigned)plan.g_rows[grp], nc = (unsigned)plan.g_cols[grp];
-    hipLaunchKernelGGL((k_gadm_init<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a);
-    VPLMC_HIP(hipGetLastError());
-    for (int it = 0; it < prm.max_iter; ++it) {
-        hipLaunchKernelGGL((k_gadm_rows<Q, THREADS>), dim3(nr), dim3(THREADS), 0, st, a, it);
-        VPLMC_HIP(hipGetLastError());
-        hipLaunchKernelGGL((k_gadm_ysys<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a, it);
-        VPLMC_HIP(hipGetLastError());
-        hipLaunchKernelGGL((k_gadm_cols<Q, THREADS>), dim3(nc), dim3(THREADS), 0, st, a, it);
-        VPLMC_HIP(hipGetLastError());
-        if (it + 1 < prm.max_iter) {
-            hipLaunchKernelGGL((k_gadm_xsys<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a, it);
-            VPLMC_HIP(hipGetLastError());
-        }
-    }
-    hipLaunchKernelGGL((k_gadm_final<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a);
-    VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
 
@@ -2038,15 +1012,15 @@ int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int
         }
     }
     // rank 32 never fits in LDS (group 6 is empty)
-    int rc = launch_gadm<32, 256>(sb[3], plan, 7, id[7], gblk_dev, gsys, ge2, desc, prm, row_ptr, csr_col, csr_val,
-                                  col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
+    int rc = launch_gadm_group(sb[3], 32, plan, 7, id[7], gblk_dev, gsys, ge2, desc, prm, row_ptr, csr_col,
+                               csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
 #define VPLMC_ADM_PAIR(B, Q, TG)                                                                                      \
     if (!rc)                                                                                                          \
         rc = launch_adm_ell<Q>(sb[B], thr, plan.groups[2 * B].size(), plan.group_max_m[2 * B], id[2 * B], qp(2 * B), \
                                n_cu, desc, prm, col_ptr, ell, X, Xp, Lam, Y, Yp, Pi, Yt, red, e2part, scale, stats); \
     if (!rc)                                                                                                          \
-        rc = launch_gadm<Q, 256>(sb[B], plan, 2 * B + 1, id[2 * B + 1], gblk_dev, gsys, ge2, desc, prm, row_ptr,    \
-                                 csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
+        rc = launch_gadm_group(sb[B], Q, plan, 2 * B + 1, id[2 * B + 1], gblk_dev, gsys, ge2, desc, prm, row_ptr,  \
+                               csr_col, csr_val, col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats);
     VPLMC_ADM_PAIR(2, 16, 512)
     VPLMC_ADM_PAIR(1, 8, 512)
     VPLMC_ADM_PAIR(0, 4, 1024)

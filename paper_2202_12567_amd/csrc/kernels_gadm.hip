@@ -1,0 +1,821 @@
+// Completion of the slices whose X does not fit in LDS (rank 32, or tall
+// slices), with X and Y in global memory, as a sequence of launches per
+// iteration over all such slices of a rank bucket, so that every phase has
+// the whole GPU and the launch boundaries order the phases (no workgroup
+// waits for another):
+//   init    (workgroup per slice)  scale, initial factors, GY, X system
+//   rows    (per 64-row block)     residuals of the row's samples, R_i Y^T,
+//                                  X+_i = X_i F + T_i Inv, U, Lambda (q/4 lanes per row)
+//   ysys    (workgroup per slice)  residual norm and the stop test, GX = X+^T X+,
+//                                  C = X+^T X, Y system
+//   cols    (per 256-column block) residuals again from X and Y, X+^T R_j,
+//                                  Y+_j = F Y_j + Inv T_j, V, Pi (q/4 lanes per column)
+//   xsys    (workgroup per slice)  GY = Y+^T Y+, X system for the next iteration
+//   final   (workgroup per slice)  the final X into the X region, statistics
+// The two X buffers alternate by iteration parity.  The q x q systems (FP64,
+// with FP32 copies for the column updates) and the slice's stop state live in
+// GADM_SYS_BYTES per slice.  The iteration is the one the LDS-resident kernel
+// runs (Appendix A, in the sparse-residual form of kernels_adm.hip); the Grams
+// are sums in a fixed order, so results are bitwise reproducible.
+
+#include "adm_common.h"
+
+namespace vplmc {
+namespace {
+
+// rows and columns with at most this many samples are taken side by side by
+// lane groups of a wavefront in the global-memory completion, longer ones by
+// the whole wavefront each
+constexpr int GADM_LIGHT = 64;
+
+struct GadmArgs {
+    const SliceDesc *desc;
+    const int32_t *ids;                  // the group's slices
+    const int32_t *rowp, *colp;          // count + 1: prefixes of the slices' row and column blocks
+    int32_t count;
+    uint64_t seed;
+    int32_t max_iter, mode;
+    float tol, alpha0, beta0, gamma;
+    const int32_t *row_ptr_all, *csr_col_all;
+    const float *csr_val_all;
+    const int32_t *col_ptr_all, *csc_row_all;
+    const float *csc_val_all;
+    float *X_all, *Xn_all, *Xp_all, *Lam_all, *Y_all, *Yp_all, *Pi_all, *scale_all;
+    int32_t *stats_all;
+    char *gsys;
+    double *ge2;                         // the group's first row block slot
+};
+
+struct GSys {
+    double *F, *Inv;                     // Q x Q (X side: F = G Inv; Y side: F stored transposed)
+    float *Ff, *If;                      // Y side, FP32: Ff[a][b] = (Inv C)[a][b], If = Inv
+    int32_t *state;                      // done, iterations, FP32 bits of the residual, all-zero
+    double *dstate;                      // ||P_Omega M|| / s0, s0
+};
+
+__device__ __forceinline__ GSys gsys_of(char *base, int s) {
+    char *p = base + (size_t)s * GADM_SYS_BYTES;
+    GSys g;
+    g.F = reinterpret_cast<double *>(p);
+    g.Inv = g.F + 32 * 32;
+    g.Ff = reinterpret_cast<float *>(p + 2 * 32 * 32 * 8);
+    g.If = g.Ff + 32 * 32;
+    g.state = reinterpret_cast<int32_t *>(p + 2 * 32 * 32 * 8 + 2 * 32 * 32 * 4);
+    g.dstate = reinterpret_cast<double *>(p + 2 * 32 * 32 * 8 + 2 * 32 * 32 * 4 + 16);
+    return g;
+}
+
+// item b of a launch over the group's blocks: the slice position k with
+// pre[k] <= b < pre[k + 1]
+__device__ __forceinline__ int block_slice(const int32_t *__restrict__ pre, int count, int b) {
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Cross Gram C = A^T B of two (rows x Q) FP32 matrices into sh.C, streamed
+// through LDS like gram_rows (half a stage each).
+template <int Q, int PCAP, int THREADS>
+__device__ void gram_cross(AdmShared<Q> &sh, const float *__restrict__ A, const float *__restrict__ B, int rows,
+                           float *part, float *stage) {
+    constexpr int P = Q * Q, QB = Q / 4, NB = QB * QB;
+    constexpr int HALF = GRAM_STAGE / 2;
+    constexpr int TR = HALF / Q;
+    constexpr int NL = HALF / 4 / THREADS;
+    static_assert(NL >= 1 && NL * 4 * THREADS == HALF, "tile split");
+    const int t = fresh_tid();
+    const int groups = min(THREADS / NB, PCAP / P);
+    const int g = t / NB, blk = t % NB;
+    const int a0 = 4 * (blk / QB), b0 = 4 * (blk % QB);
+    const float4 *A4 = reinterpret_cast<const float4 *>(A);
+    const float4 *B4 = reinterpret_cast<const float4 *>(B);
+    const int64_t tot4 = (int64_t)rows * (Q / 4);
+    const int ntiles = (rows + TR - 1) / TR;
+    float acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
+    float4 *sa = reinterpret_cast<float4 *>(stage);
+    float4 *sb = reinterpret_cast<float4 *>(stage + HALF);
+    for (int tile = 0; tile < ntiles; ++tile) {
+        float4 ba[NL], bb[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int64_t idx = (int64_t)tile * (HALF / 4) + u * THREADS + t;
+            ba[u] = idx < tot4 ? A4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+            bb[u] = idx < tot4 ? B4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            sa[u * THREADS + t] = ba[u];
+            sb[u * THREADS + t] = bb[u];
+        }
+        __syncthreads();
+        const int rt = min(TR, rows - tile * TR);
+        if (g < groups) {
+            for (int r = g; r < rt; r += groups) {
+                const float4 u = sa[(r * Q + a0) / 4];
+                const float4 v = sb[(r * Q + b0) / 4];
+                const float ua[4] = {u.x, u.y, u.z, u.w}, vb[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(ua[x], vb[y], acc[x][y]);
+            }
+        }
+    }
+    if (g < groups) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) part[g * P + (a0 + x) * Q + b0 + y] = acc[x][y];
+    }
+    __syncthreads();
+    for (int e = t; e < P; e += THREADS) {
+        float v = 0.f;
+        for (int gg = 0; gg < groups; ++gg) v += part[gg * P + e];
+        sh.C[e] = v;
+    }
+    __syncthreads();
+}
+
+// sh.F, sh.Inv of the X system (F = G Inv, Inv = (G + a I)^-1) from sh.G, stored into the slice's state
+template <int Q, int THREADS>
+__device__ void gadm_x_system(AdmShared<Q> &sh, const GSys &g, double alpha) {
+    const int t = fresh_tid();
+    spd_inverse<Q>(sh, alpha);
+    for (int e = t; e < Q * Q; e += THREADS) {
+        const int a = e / Q, b = e % Q;
+        double v = 0.0;
+        for (int l = 0; l < Q; ++l) v += (double)sh.G[a * Q + l] * sh.Inv[l * Q + b];
+        g.F[e] = v;
+        g.Inv[e] = sh.Inv[e];
+    }
+}
+
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_init(GadmArgs a) {
+    constexpr int NW = THREADS / WAVE;
+    __shared__ AdmShared<Q> sh;
+    constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
+    __shared__ float part[PCAP];
+    __shared__ __align__(16) float stage[GRAM_STAGE];
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
+    const SliceDesc d = a.desc[s];
+    const int m = d.m, n = d.n;
+    const int qr = d.qr;
+    const int t = threadIdx.x, lane = t % WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
+    const GSys g = gsys_of(a.gsys, s);
+    const uint64_t seed = a.seed;
+    const int32_t fixed_iters = a.mode;
+    const int32_t *row_ptr = a.row_ptr_all + d.off_row;
+    const float *csr_val = a.csr_val_all + 3 * d.off_omega;
+    float *Xa = a.X_all + d.off_x;
+    float *Xp = a.Xp_all + d.off_x;
+    float *Lam = a.Lam_all + d.off_x;
+    float *Y = a.Y_all + d.off_y;
+    float *Yp = a.Yp_all + d.off_y;
+    float *Pi = a.Pi_all + d.off_y;
+    float *scale_all = a.scale_all;
+    int32_t *st = a.stats_all + 4 * s;
+    const int nnz = row_ptr[m];
+    if (t == 0) {
+        g.state[0] = 0;
+        g.state[1] = a.max_iter;
+        g.state[2] = __float_as_int(0.f);
+        g.state[3] = 0;
+    }
+
+    // ---- scale s0 = mean sampled value; ||P_Omega M|| ----
+    double sum = 0.0, sumsq = 0.0;
+    for (int p = t; p < 3 * nnz; p += THREADS) {
+        const double v = (double)csr_val[p];
+        sum += v;
+        sumsq += v * v;
+    }
+    sum = wave_sum_d(sum);
+    sumsq = wave_sum_d(sumsq);
+    if (lane == 0) {
+        sh.red[wave] = sum;
+        sh.red[16 + wave] = sumsq;
+    }
+    __syncthreads();
+    double tot = 0.0, totsq = 0.0;
+    for (int w = 0; w < NW; ++w) {
+        tot += sh.red[w];
+        totsq += sh.red[16 + w];
+    }
+    __syncthreads();
+    if (!(nnz > 0 && tot > 0.0)) {
+        for (int e = t; e < m * Q; e += THREADS) Xa[e] = 0.f;
+        for (int e = t; e < 3 * n * Q; e += THREADS) Y[e] = 0.f;
+        if (t == 0) {
+            scale_all[s] = 0.f;
+            st[0] = 0;
+            st[1] |= VPLMC_SLICE_ALL_ZERO;
+            st[2] = __float_as_int(0.f);
+            g.state[0] = 1;     // done
+            g.state[1] = 0;     // iterations
+            g.state[3] = 1;     // all zero: the stats stand
+        }
+        return;
+    }
+    const double s0 = tot / (3.0 * (double)nnz);
+    const float inv_s0 = (float)(1.0 / s0);
+    const double normM = sqrt(totsq) / s0;
+    if (t == 0) {
+        scale_all[s] = (float)s0;
+        g.dstate[0] = normM;
+        g.dstate[1] = s0;
+    }
+
+    // ---- initial factors: fp32(u24(Philox) * fp32(2 / sqrt q)), or (mode bit 1)
+    // the contents of the X and Y regions ----
+    const float cq = (float)(2.0 / sqrt((double)qr));
+    const bool given = (fixed_iters & 2) != 0;
+    const bool nonneg = (fixed_iters & 4) == 0;    // mode bit 2: projections off
+    for (int e = t; e < m * Q; e += THREADS) {
+        const int i = e / Q, k = e % Q;
+        const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)i, (uint64_t)k, TAG_INITX, 0);
+        const float v = k < qr ? (given ? Xa[e] : __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq)) : 0.f;
+        Xa[e] = v;
+        Xp[e] = v;
+        Lam[e] = 0.f;
+    }
+    for (int e = t; e < 3 * n * Q; e += THREADS) {
+        const int j = e / (3 * Q), c = (e / Q) % 3, k = e % Q;
+        const uint64_t col = (uint64_t)c * (uint64_t)n + (uint64_t)j;
+        const U64x4 r = philox(seed, (uint64_t)s, (uint64_t)k, col, TAG_INITY, 0);
+        const float v = k < qr ? (given ? Y[e] : __fmul_rn((float)(r.a >> 40) * 0x1p-24f, cq)) : 0.f;
+        Y[e] = v;
+        Yp[e] = v;
+        Pi[e] = 0.f;
+    }
+    __threadfence_block();
+    __syncthreads();
+
+
+    gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * n, part, stage);
+    gadm_x_system<Q, THREADS>(sh, g, (double)a.alpha0 * (3.0 * n) / qr);
+    (void)wave;
+    (void)lane;
+    (void)inv_s0;
+}
+
+// Sum over an aligned group of L lanes (L = 1, 2, 4 or 8) by DPP exchanges:
+// within quads, then between the two quads of a half row.  Every lane of the
+// group ends with the same bits (each step adds the same two operands).
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+    static_assert(L == 1 || L == 2 || L == 4 || L == 8, "group of 1, 2, 4 or 8 lanes");
+    if constexpr (L >= 2)   // quad_perm [1, 0, 3, 2]
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+    if constexpr (L >= 4)   // quad_perm [2, 3, 0, 1]
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+    if constexpr (L >= 8)   // row_half_mirror
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+    return v;
+}
+
+// Phase A of the global-memory completion, per 64-row block.  A row is held
+// by a group of Q/4 lanes, each with four of the q components of X_i and of
+// R_i Y^T, so a sampled Y_j is three coalesced loads per group.  A pass of a
+// wavefront takes 64/(Q/4) rows of at most GADM_LIGHT samples side by side; a
+// longer row is then taken by the whole wavefront, group g walking samples
+// g, g + G, ..., and the groups' partial sums added in a fixed tree.
+// X+_i = X_i F + T_i Inv with T_i = R_i Y^T + a U_i - L_i in FP64.
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_rows(GadmArgs a, int it) {
+    constexpr int NW = THREADS / WAVE;
+    constexpr int L = Q / 4;        // lanes per row
+    constexpr int G = WAVE / L;     // rows per pass of a wavefront
+    static_assert(Q % 4 == 0 && L <= 8, "four components per lane, at most eight lanes per row");
+    __shared__ __align__(16) double shF[Q * Q];
+    __shared__ __align__(16) double shInv[Q * Q];
+    __shared__ __align__(16) float stage[NW * G * 2 * Q];   // per row slot: X_i (q), T_i (q)
+    const int b = blockIdx.x;
+    const int k = block_slice(a.rowp, a.count, b);
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
+    const GSys g = gsys_of(a.gsys, s);
+    if (g.state[0]) return;
+    const SliceDesc d = a.desc[s];
+    const int m = d.m, n = d.n, qr = d.qr;
+    const int t = threadIdx.x, lane = t % WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
+    const int r_beg = (b - a.rowp[k]) * GADM_RB, r_end = min(m, r_beg + GADM_RB);
+    for (int e = t; e < Q * Q; e += THREADS) {
+        shF[e] = g.F[e];
+        shInv[e] = g.Inv[e];
+    }
+    const bool nonneg = (a.mode & 4) == 0;
+    const float inv_s0 = (float)(1.0 / g.dstate[1]);
+    const double alpha = (double)a.alpha0 * (3.0 * n) / qr;
+    const float alpha_f = (float)alpha;
+    const float ga = (float)((double)a.gamma * alpha);
+    const float inv_alpha = (float)(1.0 / alpha);
+    const int32_t *row_ptr = a.row_ptr_all + d.off_row;
+    const int32_t *csr_col = a.csr_col_all + d.off_omega;
+    const float *csr_val = a.csr_val_all + 3 * d.off_omega;
+    const float *X = ((it & 1) ? a.Xn_all : a.X_all) + d.off_x;
+    float *Xn = ((it & 1) ? a.X_all : a.Xn_all) + d.off_x;
+    float *Xp = a.Xp_all + d.off_x;
+    float *Lam = a.Lam_all + d.off_x;
+    const float *Y = a.Y_all + d.off_y;
+    const int slot = lane / L, k0 = 4 * (lane % L);
+    const bool lead = lane % L == 0;
+    __syncthreads();
+    double e2 = 0.0;
+
+    // one sample p of row i (act: group-uniform): r = M - X_i . Y_j per
+    // channel, acc += sum_c r_c Y_j(c), the squared residual on the group's
+    // first lane
+    auto sample = [&](bool act, int p, const float (&x)[4], float (&acc)[4]) {
+        float mv[3] = {0.f, 0.f, 0.f};
+        float4 ya = make_float4(0.f, 0.f, 0.f, 0.f), yb = ya, yc = ya;
+        if (act) {
+            const int j = csr_col[p];
+            mv[0] = csr_val[3 * p] * inv_s0;
+            mv[1] = csr_val[3 * p + 1] * inv_s0;
+            mv[2] = csr_val[3 * p + 2] * inv_s0;
+            const float *yj = Y + (size_t)j * 3 * Q + k0;
+            ya = *reinterpret_cast<const float4 *>(yj);
+            yb = *reinterpret_cast<const float4 *>(yj + Q);
+            yc = *reinterpret_cast<const float4 *>(yj + 2 * Q);
+        }
+        const float y[3][4] = {{ya.x, ya.y, ya.z, ya.w}, {yb.x, yb.y, yb.z, yb.w}, {yc.x, yc.y, yc.z, yc.w}};
+        float r[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float dd = 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dd = fmaf(x[e], y[c][e], dd);
+            r[c] = mv[c] - group_sum<L>(dd);
+        }
+        if (act && lead) e2 += (double)(r[0] * r[0]) + (double)(r[1] * r[1]) + (double)(r[2] * r[2]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = fmaf(r[0], y[0][e], fmaf(r[1], y[1][e], fmaf(r[2], y[2][e], acc[e])));
+    };
+    // T_i staged beside X_i in the row's LDS slot (the group's lanes)
+    auto stage_row = [&](int i, const float (&x)[4], const float (&acc)[4], float *wst, float (&lam)[4]) {
+        const float4 u = *reinterpret_cast<const float4 *>(Xp + (size_t)i * Q + k0);
+        const float4 l = *reinterpret_cast<const float4 *>(Lam + (size_t)i * Q + k0);
+        lam[0] = l.x; lam[1] = l.y; lam[2] = l.z; lam[3] = l.w;
+        *reinterpret_cast<float4 *>(wst + k0) = make_float4(x[0], x[1], x[2], x[3]);
+        *reinterpret_cast<float4 *>(wst + Q + k0) =
+            make_float4(acc[0] + alpha_f * u.x - l.x, acc[1] + alpha_f * u.y - l.y, acc[2] + alpha_f * u.z - l.z,
+                        acc[3] + alpha_f * u.w - l.w);
+    };
+    // components k0..k0+3 of X+_i, then U and Lambda
+    auto finish_row = [&](int i, const float *wst, const float (&lam)[4]) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int l = 0; l < Q; ++l) {
+            const double xl = (double)wst[l], tl = (double)wst[Q + l];
+            const double2 f01 = *reinterpret_cast<const double2 *>(shF + l * Q + k0);
+            const double2 f23 = *reinterpret_cast<const double2 *>(shF + l * Q + k0 + 2);
+            const double2 h01 = *reinterpret_cast<const double2 *>(shInv + l * Q + k0);
+            const double2 h23 = *reinterpret_cast<const double2 *>(shInv + l * Q + k0 + 2);
+            v[0] += xl * f01.x + tl * h01.x;
+            v[1] += xl * f01.y + tl * h01.y;
+            v[2] += xl * f23.x + tl * h23.x;
+            v[3] += xl * f23.y + tl * h23.y;
+        }
+        float xn[4], un[4], ln[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            xn[e] = (float)v[e];
+            un[e] = nonneg ? fmaxf(0.f, xn[e] + lam[e] * inv_alpha) : xn[e] + lam[e] * inv_alpha;
+            ln[e] = lam[e] + ga * (xn[e] - un[e]);
+        }
+        const size_t w = (size_t)i * Q + k0;
+        *reinterpret_cast<float4 *>(Xn + w) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+        *reinterpret_cast<float4 *>(Xp + w) = make_float4(un[0], un[1], un[2], un[3]);
+        *reinterpret_cast<float4 *>(Lam + w) = make_float4(ln[0], ln[1], ln[2], ln[3]);
+    };
+    auto load_x = [&](int i, float (&x)[4]) {
+        const float4 u = *reinterpret_cast<const float4 *>(X + (size_t)i * Q + k0);
+        x[0] = u.x; x[1] = u.y; x[2] = u.z; x[3] = u.w;
+    };
+
+    for (int ib = r_beg + wave * G; ib < r_end; ib += NW * G) {
+        const int i = ib + slot;
+        int beg = 0, cnt = 0;
+        if (i < r_end) {
+            beg = row_ptr[i];
+            cnt = row_ptr[i + 1] - beg;
+        }
+        const bool light = i < r_end && cnt <= GADM_LIGHT;
+        const int lc = light ? cnt : 0;
+        int mc = lc;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mc = max(mc, __shfl_xor(mc, o, WAVE));
+        mc = __builtin_amdgcn_readfirstlane(mc);
+        float *wst = stage + (wave * G + slot) * 2 * Q;
+        {
+            float x[4] = {0.f, 0.f, 0.f, 0.f}, acc[4] = {0.f, 0.f, 0.f, 0.f}, lam[4];
+            if (light) load_x(i, x);
+            for (int p = 0; p < mc; ++p) sample(p < lc, beg + p, x, acc);
+            if (light) stage_row(i, x, acc, wst, lam);
+            wave_lds_sync();
+            if (light) finish_row(i, wst, lam);
+            // the next row's stage overwrites this slot
+            wave_lds_sync();
+        }
+        // the pass's longer rows, one at a time by the whole wavefront
+        uint64_t heavy = __ballot(i < r_end && !light && lead);
+        while (heavy) {
+            const int ih = ib + __builtin_ctzll(heavy) / L;
+            heavy &= heavy - 1;
+            const int hbeg = row_ptr[ih], hcnt = row_ptr[ih + 1] - hbeg;
+            float x[4], acc[4] = {0.f, 0.f, 0.f, 0.f}, lam[4];
+            load_x(ih, x);
+            for (int p0 = 0; p0 < hcnt; p0 += G) sample(p0 + slot < hcnt, hbeg + p0 + slot, x, acc);
+            // groups differ in lane bits log2(L) and up: add them pairwise
+#pragma unroll
+            for (int o = L; o < WAVE; o <<= 1)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[e] += __shfl_xor(acc[e], o, WAVE);
+            float *hst = stage + wave * G * 2 * Q;   // slot 0 of the wavefront
+            if (slot == 0) stage_row(ih, x, acc, hst, lam);
+            wave_lds_sync();
+            if (slot == 0) finish_row(ih, hst, lam);
+            wave_lds_sync();
+        }
+    }
+    e2 = wave_sum_d(e2);
+    __shared__ double red[NW];
+    if (lane == 0) red[wave] = e2;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < NW; ++w) tot += red[w];
+        a.ge2[b] = tot;
+    }
+}
+
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_ysys(GadmArgs a, int it) {
+    constexpr int NW = THREADS / WAVE;
+    __shared__ AdmShared<Q> sh;
+    constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
+    __shared__ float part[PCAP];
+    __shared__ __align__(16) float stage[GRAM_STAGE];
+    __shared__ int stop_s;
+    const int k = blockIdx.x;
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
+    const GSys g = gsys_of(a.gsys, s);
+    if (g.state[0]) return;
+    const SliceDesc d = a.desc[s];
+    const int m = d.m, qr = d.qr;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        // the squared residuals of the slice's row blocks, in block order
+        double e2 = 0.0;
+        for (int rb = a.rowp[k]; rb < a.rowp[k + 1]; ++rb) e2 += a.ge2[rb];
+        const double err = sqrt(e2) / g.dstate[0];
+        g.state[2] = __float_as_int((float)err);
+        const bool stop = !(a.mode & 1) && err < (double)a.tol;
+        if (stop) {
+            g.state[0] = 1;
+            g.state[1] = it;
+        }
+        stop_s = stop ? 1 : 0;
+    }
+    __syncthreads();
+    if (stop_s) return;
+    const float *X = ((it & 1) ? a.Xn_all : a.X_all) + d.off_x;
+    const float *Xn = ((it & 1) ? a.X_all : a.Xn_all) + d.off_x;
+    gram_rows<Q, PCAP, THREADS>(sh, Xn, m, part, stage);
+    gram_cross<Q, PCAP, THREADS>(sh, Xn, X, m, part, stage);
+    const double beta = (double)a.beta0 * (double)m / qr;
+    spd_inverse<Q>(sh, beta);
+    for (int e = t; e < Q * Q; e += THREADS) {
+        const int aa = e / Q, bb = e % Q;   // F[a][b] = sum_l Inv[a][l] C[l][b]; F^T at [b][a]
+        double v = 0.0;
+        for (int l = 0; l < Q; ++l) v += sh.Inv[aa * Q + l] * (double)sh.C[l * Q + bb];
+        g.F[bb * Q + aa] = v;
+        g.Inv[e] = sh.Inv[e];
+        g.Ff[e] = (float)v;
+        g.If[e] = (float)sh.Inv[e];
+    }
+}
+
+// Phase B of the global-memory completion, per 256-column block.  A column is
+// held by a group of Q/4 lanes, each with four of the q components of Y_j and
+// of X+^T R_j for the three channels, so a sampled row X_i / X+_i is one
+// coalesced load per group.  A pass of a wavefront takes 64/(Q/4) columns of at
+// most GADM_LIGHT samples side by side (the loop runs to the pass's longest);
+// a longer column is then taken by the whole wavefront, group g walking
+// samples g, g + G, ..., and the groups' partial sums added in a fixed tree.
+// Y+_j = F Y_j + Inv T_j with T_j = X+^T R_j + b V_j - P_j uses the FP32
+// copies of the two q x q matrices, transposed in LDS.
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_cols(GadmArgs a, int it) {
+    constexpr int NW = THREADS / WAVE;
+    constexpr int L = Q / 4;        // lanes per column
+    constexpr int G = WAVE / L;     // columns per pass of a wavefront
+    static_assert(Q % 4 == 0 && L <= 8, "four components per lane, at most eight lanes per column");
+    __shared__ __align__(16) float Ft[Q * Q];    // Ft[l][k] = (Inv C)[k][l]
+    __shared__ __align__(16) float It[Q * Q];    // It[l][k] = Inv[k][l]
+    __shared__ __align__(16) float stage[NW * G * 6 * Q];   // per column slot: Y_j (3q), T_j (3q)
+    const int b = blockIdx.x;
+    const int k = block_slice(a.colp, a.count, b);
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
+    const GSys g = gsys_of(a.gsys, s);
+    if (g.state[0]) return;
+    const SliceDesc d = a.desc[s];
+    const int m = d.m, qr = d.qr;
+    const int t = threadIdx.x, lane = t % WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(t / WAVE);
+    const int c_beg = (b - a.colp[k]) * GADM_CB, c_end = min(d.n, c_beg + GADM_CB);
+    for (int e = t; e < Q * Q; e += THREADS) {
+        const int r = e / Q, c = e % Q;
+        Ft[c * Q + r] = g.Ff[e];
+        It[c * Q + r] = g.If[e];
+    }
+    const bool nonneg = (a.mode & 4) == 0;
+    const float inv_s0 = (float)(1.0 / g.dstate[1]);
+    const double beta = (double)a.beta0 * (double)m / qr;
+    const float beta_f = (float)beta;
+    const float gb = (float)((double)a.gamma * beta);
+    const float inv_beta = (float)(1.0 / beta);
+    const int32_t *col_ptr = a.col_ptr_all + d.off_colptr;
+    const int32_t *csc_row = a.csc_row_all + d.off_omega;
+    const float *csc_val = a.csc_val_all + 3 * d.off_omega;
+    const float *X = ((it & 1) ? a.Xn_all : a.X_all) + d.off_x;
+    const float *Xn = ((it & 1) ? a.X_all : a.Xn_all) + d.off_x;
+    float *Y = a.Y_all + d.off_y;
+    float *Yp = a.Yp_all + d.off_y;
+    float *Pi = a.Pi_all + d.off_y;
+    const int slot = lane / L, k0 = 4 * (lane % L);
+    __syncthreads();
+
+    // one sample p of column j (act: group-uniform): r = M - X_i . Y_j per
+    // channel, acc += X+_i r
+    auto sample = [&](bool act, int p, const float (&y)[3][4], float (&acc)[3][4]) {
+        float mv[3] = {0.f, 0.f, 0.f};
+        float4 xa = make_float4(0.f, 0.f, 0.f, 0.f), xb = xa;
+        if (act) {
+            const int i = csc_row[p];
+            mv[0] = csc_val[3 * p] * inv_s0;
+            mv[1] = csc_val[3 * p + 1] * inv_s0;
+            mv[2] = csc_val[3 * p + 2] * inv_s0;
+            xa = *reinterpret_cast<const float4 *>(X + (size_t)i * Q + k0);
+            xb = *reinterpret_cast<const float4 *>(Xn + (size_t)i * Q + k0);
+        }
+        const float xr[4] = {xa.x, xa.y, xa.z, xa.w}, xn[4] = {xb.x, xb.y, xb.z, xb.w};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float dd = 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dd = fmaf(xr[e], y[c][e], dd);
+            const float r = mv[c] - group_sum<L>(dd);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(xn[e], r, acc[c][e]);
+        }
+    };
+    auto load_y = [&](int j, float (&y)[3][4]) {
+        const float4 *yj = reinterpret_cast<const float4 *>(Y + (size_t)j * 3 * Q + k0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float4 u = yj[c * Q / 4];
+            y[c][0] = u.x; y[c][1] = u.y; y[c][2] = u.z; y[c][3] = u.w;
+        }
+    };
+    // T_j staged beside Y_j in the column's LDS slot (the group's lanes)
+    auto stage_column = [&](int j, const float (&y)[3][4], const float (&acc)[3][4], float *wst, float (&pv)[3][4]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float4 v = *reinterpret_cast<const float4 *>(Yp + (size_t)j * 3 * Q + c * Q + k0);
+            const float4 pp = *reinterpret_cast<const float4 *>(Pi + (size_t)j * 3 * Q + c * Q + k0);
+            pv[c][0] = pp.x; pv[c][1] = pp.y; pv[c][2] = pp.z; pv[c][3] = pp.w;
+            *reinterpret_cast<float4 *>(wst + c * Q + k0) = make_float4(y[c][0], y[c][1], y[c][2], y[c][3]);
+            *reinterpret_cast<float4 *>(wst + 3 * Q + c * Q + k0) =
+                make_float4(acc[c][0] + beta_f * v.x - pp.x, acc[c][1] + beta_f * v.y - pp.y,
+                            acc[c][2] + beta_f * v.z - pp.z, acc[c][3] + beta_f * v.w - pp.w);
+        }
+    };
+    // components k0..k0+3 of Y+_j for the three channels, then U, P and Y
+    auto finish_column = [&](int j, const float *wst, const float (&pv)[3][4]) {
+        float o[3][4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[c][e] = 0.f;
+#pragma unroll 2
+        for (int l = 0; l < Q; l += 4) {
+            float yl[3][4], tl[3][4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float4 u = *reinterpret_cast<const float4 *>(wst + c * Q + l);
+                const float4 v = *reinterpret_cast<const float4 *>(wst + 3 * Q + c * Q + l);
+                yl[c][0] = u.x; yl[c][1] = u.y; yl[c][2] = u.z; yl[c][3] = u.w;
+                tl[c][0] = v.x; tl[c][1] = v.y; tl[c][2] = v.z; tl[c][3] = v.w;
+            }
+#pragma unroll
+            for (int ll = 0; ll < 4; ++ll) {
+                const float4 f = *reinterpret_cast<const float4 *>(Ft + (l + ll) * Q + k0);
+                const float4 h = *reinterpret_cast<const float4 *>(It + (l + ll) * Q + k0);
+                const float fa[4] = {f.x, f.y, f.z, f.w}, ha[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) o[c][e] = fmaf(fa[e], yl[c][ll], fmaf(ha[e], tl[c][ll], o[c][e]));
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float un[4], pn[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                un[e] = nonneg ? fmaxf(0.f, o[c][e] + pv[c][e] * inv_beta) : o[c][e] + pv[c][e] * inv_beta;
+                pn[e] = pv[c][e] + gb * (o[c][e] - un[e]);
+            }
+            const size_t w = (size_t)j * 3 * Q + c * Q + k0;
+            *reinterpret_cast<float4 *>(Yp + w) = make_float4(un[0], un[1], un[2], un[3]);
+            *reinterpret_cast<float4 *>(Pi + w) = make_float4(pn[0], pn[1], pn[2], pn[3]);
+            *reinterpret_cast<float4 *>(Y + w) = make_float4(o[c][0], o[c][1], o[c][2], o[c][3]);
+        }
+    };
+
+    for (int jb = c_beg + wave * G; jb < c_end; jb += NW * G) {
+        const int j = jb + slot;
+        int beg = 0, cnt = 0;
+        if (j < c_end) {
+            beg = col_ptr[j];
+            cnt = col_ptr[j + 1] - beg;
+        }
+        const bool light = j < c_end && cnt <= GADM_LIGHT;
+        const int lc = light ? cnt : 0;
+        int mc = lc;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mc = max(mc, __shfl_xor(mc, o, WAVE));
+        mc = __builtin_amdgcn_readfirstlane(mc);
+        float *wst = stage + (wave * G + slot) * 6 * Q;
+        {
+            float y[3][4], acc[3][4], pv[3][4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) y[c][e] = acc[c][e] = 0.f;
+            if (light) load_y(j, y);
+            for (int p = 0; p < mc; ++p) sample(p < lc, beg + p, y, acc);
+            if (light) stage_column(j, y, acc, wst, pv);
+            wave_lds_sync();
+            if (light) finish_column(j, wst, pv);
+            // the next column's stage overwrites this slot
+            wave_lds_sync();
+        }
+        // the pass's longer columns, one at a time by the whole wavefront
+        uint64_t heavy = __ballot(j < c_end && !light && lane % L == 0);
+        while (heavy) {
+            const int jh = jb + __builtin_ctzll(heavy) / L;
+            heavy &= heavy - 1;
+            const int hbeg = col_ptr[jh], hcnt = col_ptr[jh + 1] - hbeg;
+            float y[3][4], acc[3][4], pv[3][4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[c][e] = 0.f;
+            load_y(jh, y);
+            for (int p0 = 0; p0 < hcnt; p0 += G) sample(p0 + slot < hcnt, hbeg + p0 + slot, y, acc);
+            // groups differ in lane bits log2(L) and up: add them pairwise
+#pragma unroll
+            for (int o = L; o < WAVE; o <<= 1)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[c][e] += __shfl_xor(acc[c][e], o, WAVE);
+            float *hst = stage + wave * G * 6 * Q;   // slot 0 of the wavefront
+            if (slot == 0) stage_column(jh, y, acc, hst, pv);
+            wave_lds_sync();
+            if (slot == 0) finish_column(jh, hst, pv);
+            wave_lds_sync();
+        }
+    }
+}
+
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_xsys(GadmArgs a, int it) {
+    constexpr int NW = THREADS / WAVE;
+    __shared__ AdmShared<Q> sh;
+    constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
+    __shared__ float part[PCAP];
+    __shared__ __align__(16) float stage[GRAM_STAGE];
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
+    const GSys g = gsys_of(a.gsys, s);
+    if (g.state[0]) return;
+    const SliceDesc d = a.desc[s];
+    const float *Y = a.Y_all + d.off_y;
+    gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * d.n, part, stage);
+    gadm_x_system<Q, THREADS>(sh, g, (double)a.alpha0 * (3.0 * d.n) / d.qr);
+    (void)it;
+}
+
+template <int Q, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_gadm_final(GadmArgs a) {
+    const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
+    const GSys g = gsys_of(a.gsys, s);
+    if (g.state[3]) return;                  // all-zero slice: set by the init launch
+    const SliceDesc d = a.desc[s];
+    const int iters = g.state[1];
+    const int t = threadIdx.x;
+    if (iters & 1) {                          // the final X is in the second buffer
+        const float *src = a.Xn_all + d.off_x;
+        float *dst = a.X_all + d.off_x;
+        for (int e = t; e < d.m * Q; e += THREADS) dst[e] = src[e];
+    }
+    if (t == 0) {
+        int32_t *st = a.stats_all + 4 * s;
+        st[0] = iters;
+        if (!(a.mode & 1) && iters >= a.max_iter) st[1] |= VPLMC_SLICE_NOT_CONVERGED;
+        st[2] = g.state[2];
+    }
+}
+
+// the global-memory completion of group grp (odd: X in global memory): an
+// init launch, four launches per iteration, a final launch
+template <int Q, int THREADS>
+int launch_gadm(hipStream_t st, const vplmc_plan &plan, int grp, const int32_t *ids, const int32_t *gblk_dev,
+                char *gsys, double *ge2, const SliceDesc *desc, const vplmc_params &prm, const int32_t *row_ptr,
+                const int32_t *csr_col, const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row,
+                const float *csc_val, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
+                float *scale, int32_t *stats) {
+    const size_t count = plan.groups[grp].size();
+    if (count == 0) return VPLMC_OK;
+    GadmArgs a;
+    a.desc = desc;
+    a.ids = ids;
+    a.rowp = gblk_dev + plan.gblk_off[grp];
+    a.colp = a.rowp + count + 1;
+    a.count = (int32_t)count;
+    a.seed = prm.seed;
+    a.max_iter = prm.max_iter;
+    a.mode = adm_mode(prm);
+    a.tol = prm.tol;
+    a.alpha0 = prm.alpha0;
+    a.beta0 = prm.beta0;
+    a.gamma = prm.gamma;
+    a.row_ptr_all = row_ptr;
+    a.csr_col_all = csr_col;
+    a.csr_val_all = csr_val;
+    a.col_ptr_all = col_ptr;
+    a.csc_row_all = csc_row;
+    a.csc_val_all = csc_val;
+    a.X_all = X;
+    a.Xn_all = Xn;
+    a.Xp_all = Xp;
+    a.Lam_all = Lam;
+    a.Y_all = Y;
+    a.Yp_all = Yp;
+    a.Pi_all = Pi;
+    a.scale_all = scale;
+    a.stats_all = stats;
+    a.gsys = gsys;
+    a.ge2 = ge2 + plan.ge2_base[grp];
+    const unsigned nr = (unsigned)plan.g_rows[grp], nc = (unsigned)plan.g_cols[grp];
+    hipLaunchKernelGGL((k_gadm_init<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a);
+    VPLMC_HIP(hipGetLastError());
+    for (int it = 0; it < prm.max_iter; ++it) {
+        hipLaunchKernelGGL((k_gadm_rows<Q, THREADS>), dim3(nr), dim3(THREADS), 0, st, a, it);
+        VPLMC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_gadm_ysys<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a, it);
+        VPLMC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_gadm_cols<Q, THREADS>), dim3(nc), dim3(THREADS), 0, st, a, it);
+        VPLMC_HIP(hipGetLastError());
+        if (it + 1 < prm.max_iter) {
+            hipLaunchKernelGGL((k_gadm_xsys<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a, it);
+            VPLMC_HIP(hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL((k_gadm_final<Q, THREADS>), dim3((unsigned)count), dim3(THREADS), 0, st, a);
+    VPLMC_HIP(hipGetLastError());
+    return VPLMC_OK;
+}
+
+}  // namespace
+
+int launch_gadm_group(hipStream_t st, int q, const vplmc_plan &plan, int grp, const int32_t *ids,
+                      const int32_t *gblk_dev, char *gsys, double *ge2, const SliceDesc *desc,
+                      const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
+                      const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, float *X, float *Xn,
+                      float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale, int32_t *stats) {
+#define VPLMC_GADM(QQ)                                                                                             \
+    return launch_gadm<QQ, 256>(st, plan, grp, ids, gblk_dev, gsys, ge2, desc, prm, row_ptr, csr_col, csr_val,   \
+                                col_ptr, csc_row, csc_val, X, Xn, Xp, Lam, Y, Yp, Pi, scale, stats)
+    switch (q) {
+    case 4: VPLMC_GADM(4);
+    case 8: VPLMC_GADM(8);
+    case 16: VPLMC_GADM(16);
+    case 32: VPLMC_GADM(32);
+    default: return VPLMC_EINVAL;
+    }
+#undef VPLMC_GADM
+}
+
+}  // namespace vplmc

@@ -361,6 +361,12 @@ int launch_adm(hipStream_t st, const AdmStreams *ss, const vplmc_plan &plan, int
                const float *csr_val, const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val,
                const EllView &ell, float *X, float *Xn, float *Xp, float *Lam, float *Y, float *Yp, float *Pi,
                float *Yt, float *red, double *e2part, float *scale, int32_t *stats);
+// the global-memory completion of plan group grp (rank q = 4, 8, 16 or 32; kernels_gadm.hip)
+int launch_gadm_group(hipStream_t st, int q, const vplmc_plan &plan, int grp, const int32_t *ids,
+                      const int32_t *gblk_dev, char *gsys, double *ge2, const SliceDesc *desc,
+                      const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
+                      const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, float *X, float *Xn,
+                      float *Xp, float *Lam, float *Y, float *Yp, float *Pi, float *scale, int32_t *stats);
 int launch_als(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *ids_dev,
                const vplmc_params &prm, const int32_t *row_ptr, const int32_t *csr_col, const float *csr_val,
                const int32_t *col_ptr, const int32_t *csc_row, const float *csc_val, float *X, float *Y, float *scale,

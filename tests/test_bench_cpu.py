@@ -13,7 +13,7 @@ sys.path.insert(0, ROOT)
 
 import bench  # noqa: E402
 
-SOURCES = ("kernels_adm.hip", "vplmc_internal.h")
+SOURCES = ("kernels_adm.hip", "adm_common.h", "vplmc_internal.h")
 
 
 @pytest.fixture
@@ -41,12 +41,15 @@ def test_digest_ignores_comments_and_blank_lines(tree):
 
 def test_digest_follows_code(tree):
     d0 = bench.source_digest()
-    edit(tree, "kernels_adm.hip", lambda s: s.replace("constexpr int GADM_LIGHT = 64;", "constexpr int GADM_LIGHT = 65;"))
+    edit(tree, "kernels_adm.hip", lambda s: s.replace("constexpr int ADM_CMB = 4;", "constexpr int ADM_CMB = 5;"))
     assert bench.source_digest() != d0
-    edit(tree, "kernels_adm.hip", lambda s: s.replace("constexpr int GADM_LIGHT = 65;", "constexpr int GADM_LIGHT = 64;"))
+    edit(tree, "kernels_adm.hip", lambda s: s.replace("constexpr int ADM_CMB = 5;", "constexpr int ADM_CMB = 4;"))
     assert bench.source_digest() == d0
+    edit(tree, "adm_common.h", lambda s: s.replace("constexpr int GRAM_STAGE = 16384;", "constexpr int GRAM_STAGE = 8192;"))
+    d1 = bench.source_digest()
+    assert d1 != d0
     edit(tree, "vplmc_internal.h", lambda s: s + "\nconstexpr int UNUSED_FOR_THE_TEST = 1;\n")
-    assert bench.source_digest() != d0
+    assert bench.source_digest() not in (d0, d1)
 
 
 def test_traffic_record_is_keyed_by_rate_and_source(tree):
