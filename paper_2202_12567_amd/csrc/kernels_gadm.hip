@@ -27,6 +27,8 @@ namespace {
 // lane groups of a wavefront in the global-memory completion, longer ones by
 // the whole wavefront each
 constexpr int GADM_LIGHT = 64;
+// samples of a row or column whose loads a lane group issues together
+constexpr int GADM_BATCH = 4;
 
 struct GadmArgs {
     const SliceDesc *desc;
@@ -332,34 +334,50 @@ __global__ __launch_bounds__(THREADS) void k_gadm_rows(GadmArgs a, int it) {
     __syncthreads();
     double e2 = 0.0;
 
-    // one sample p of row i (act: group-uniform): r = M - X_i . Y_j per
-    // channel, acc += sum_c r_c Y_j(c), the squared residual on the group's
-    // first lane
-    auto sample = [&](bool act, int p, const float (&x)[4], float (&acc)[4]) {
-        float mv[3] = {0.f, 0.f, 0.f};
-        float4 ya = make_float4(0.f, 0.f, 0.f, 0.f), yb = ya, yc = ya;
-        if (act) {
-            const int j = csr_col[p];
-            mv[0] = csr_val[3 * p] * inv_s0;
-            mv[1] = csr_val[3 * p + 1] * inv_s0;
-            mv[2] = csr_val[3 * p + 2] * inv_s0;
-            const float *yj = Y + (size_t)j * 3 * Q + k0;
-            ya = *reinterpret_cast<const float4 *>(yj);
-            yb = *reinterpret_cast<const float4 *>(yj + Q);
-            yc = *reinterpret_cast<const float4 *>(yj + 2 * Q);
+    // GADM_BATCH samples of row i at local positions p + u * step, active
+    // while below lim (group-uniform): r = M - X_i . Y_j per channel,
+    // acc += sum_c r_c Y_j(c), the squared residual on the group's first lane.
+    // The loads of the batch are issued together; an inactive sample reads
+    // the slice's first sample (every slice in this launch has one) and adds
+    // nothing.
+    auto samples = [&](int p, int step, int lim, int beg, const float (&x)[4], float (&acc)[4]) {
+        bool act[GADM_BATCH];
+        int pos[GADM_BATCH], jj[GADM_BATCH];
+#pragma unroll
+        for (int u = 0; u < GADM_BATCH; ++u) {
+            act[u] = p + u * step < lim;
+            pos[u] = act[u] ? beg + p + u * step : 0;
+            jj[u] = csr_col[pos[u]];
         }
-        const float y[3][4] = {{ya.x, ya.y, ya.z, ya.w}, {yb.x, yb.y, yb.z, yb.w}, {yc.x, yc.y, yc.z, yc.w}};
-        float r[3];
+        float mv[GADM_BATCH][3];
+        float4 yv[GADM_BATCH][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float dd = 0.f;
+        for (int u = 0; u < GADM_BATCH; ++u) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) dd = fmaf(x[e], y[c][e], dd);
-            r[c] = mv[c] - group_sum<L>(dd);
+            for (int c = 0; c < 3; ++c) mv[u][c] = csr_val[3 * pos[u] + c];
+            const float *yj = Y + (size_t)jj[u] * 3 * Q + k0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) yv[u][c] = *reinterpret_cast<const float4 *>(yj + c * Q);
         }
-        if (act && lead) e2 += (double)(r[0] * r[0]) + (double)(r[1] * r[1]) + (double)(r[2] * r[2]);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = fmaf(r[0], y[0][e], fmaf(r[1], y[1][e], fmaf(r[2], y[2][e], acc[e])));
+        for (int u = 0; u < GADM_BATCH; ++u) {
+            const float y[3][4] = {{yv[u][0].x, yv[u][0].y, yv[u][0].z, yv[u][0].w},
+                                   {yv[u][1].x, yv[u][1].y, yv[u][1].z, yv[u][1].w},
+                                   {yv[u][2].x, yv[u][2].y, yv[u][2].z, yv[u][2].w}};
+            float r[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float dd = 0.f;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dd = fmaf(x[e], y[c][e], dd);
+                const float rc = mv[u][c] * inv_s0 - group_sum<L>(dd);
+                r[c] = act[u] ? rc : 0.f;
+            }
+            if (act[u] && lead) e2 += (double)(r[0] * r[0]) + (double)(r[1] * r[1]) + (double)(r[2] * r[2]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                acc[e] = fmaf(r[0], y[0][e], fmaf(r[1], y[1][e], fmaf(r[2], y[2][e], acc[e])));
+        }
     };
     // T_i staged beside X_i in the row's LDS slot (the group's lanes)
     auto stage_row = [&](int i, const float (&x)[4], const float (&acc)[4], float *wst, float (&lam)[4]) {
@@ -419,7 +437,7 @@ __global__ __launch_bounds__(THREADS) void k_gadm_rows(GadmArgs a, int it) {
         {
             float x[4] = {0.f, 0.f, 0.f, 0.f}, acc[4] = {0.f, 0.f, 0.f, 0.f}, lam[4];
             if (light) load_x(i, x);
-            for (int p = 0; p < mc; ++p) sample(p < lc, beg + p, x, acc);
+            for (int p = 0; p < mc; p += GADM_BATCH) samples(p, 1, lc, beg, x, acc);
             if (light) stage_row(i, x, acc, wst, lam);
             wave_lds_sync();
             if (light) finish_row(i, wst, lam);
@@ -434,7 +452,7 @@ __global__ __launch_bounds__(THREADS) void k_gadm_rows(GadmArgs a, int it) {
             const int hbeg = row_ptr[ih], hcnt = row_ptr[ih + 1] - hbeg;
             float x[4], acc[4] = {0.f, 0.f, 0.f, 0.f}, lam[4];
             load_x(ih, x);
-            for (int p0 = 0; p0 < hcnt; p0 += G) sample(p0 + slot < hcnt, hbeg + p0 + slot, x, acc);
+            for (int p0 = 0; p0 < hcnt; p0 += G * GADM_BATCH) samples(p0 + slot, G, hcnt, hbeg, x, acc);
             // groups differ in lane bits log2(L) and up: add them pairwise
 #pragma unroll
             for (int o = L; o < WAVE; o <<= 1)
@@ -555,28 +573,42 @@ __global__ __launch_bounds__(THREADS) void k_gadm_cols(GadmArgs a, int it) {
     const int slot = lane / L, k0 = 4 * (lane % L);
     __syncthreads();
 
-    // one sample p of column j (act: group-uniform): r = M - X_i . Y_j per
-    // channel, acc += X+_i r
-    auto sample = [&](bool act, int p, const float (&y)[3][4], float (&acc)[3][4]) {
-        float mv[3] = {0.f, 0.f, 0.f};
-        float4 xa = make_float4(0.f, 0.f, 0.f, 0.f), xb = xa;
-        if (act) {
-            const int i = csc_row[p];
-            mv[0] = csc_val[3 * p] * inv_s0;
-            mv[1] = csc_val[3 * p + 1] * inv_s0;
-            mv[2] = csc_val[3 * p + 2] * inv_s0;
-            xa = *reinterpret_cast<const float4 *>(X + (size_t)i * Q + k0);
-            xb = *reinterpret_cast<const float4 *>(Xn + (size_t)i * Q + k0);
+    // GADM_BATCH samples of column j at local positions p + u * step, active
+    // while below lim (group-uniform): r = M - X_i . Y_j per channel,
+    // acc += X+_i r.  The loads of the batch are issued together; an inactive
+    // sample reads the slice's first sample and adds nothing.
+    auto samples = [&](int p, int step, int lim, int beg, const float (&y)[3][4], float (&acc)[3][4]) {
+        bool act[GADM_BATCH];
+        int pos[GADM_BATCH], ii[GADM_BATCH];
+#pragma unroll
+        for (int u = 0; u < GADM_BATCH; ++u) {
+            act[u] = p + u * step < lim;
+            pos[u] = act[u] ? beg + p + u * step : 0;
+            ii[u] = csc_row[pos[u]];
         }
-        const float xr[4] = {xa.x, xa.y, xa.z, xa.w}, xn[4] = {xb.x, xb.y, xb.z, xb.w};
+        float mv[GADM_BATCH][3];
+        float4 xa[GADM_BATCH], xb[GADM_BATCH];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float dd = 0.f;
+        for (int u = 0; u < GADM_BATCH; ++u) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) dd = fmaf(xr[e], y[c][e], dd);
-            const float r = mv[c] - group_sum<L>(dd);
+            for (int c = 0; c < 3; ++c) mv[u][c] = csc_val[3 * pos[u] + c];
+            xa[u] = *reinterpret_cast<const float4 *>(X + (size_t)ii[u] * Q + k0);
+            xb[u] = *reinterpret_cast<const float4 *>(Xn + (size_t)ii[u] * Q + k0);
+        }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(xn[e], r, acc[c][e]);
+        for (int u = 0; u < GADM_BATCH; ++u) {
+            const float xr[4] = {xa[u].x, xa[u].y, xa[u].z, xa[u].w};
+            const float xn[4] = {xb[u].x, xb[u].y, xb[u].z, xb[u].w};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float dd = 0.f;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dd = fmaf(xr[e], y[c][e], dd);
+                const float rc = mv[u][c] * inv_s0 - group_sum<L>(dd);
+                const float r = act[u] ? rc : 0.f;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(xn[e], r, acc[c][e]);
+            }
         }
     };
     auto load_y = [&](int j, float (&y)[3][4]) {
@@ -664,7 +696,7 @@ __global__ __launch_bounds__(THREADS) void k_gadm_cols(GadmArgs a, int it) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) y[c][e] = acc[c][e] = 0.f;
             if (light) load_y(j, y);
-            for (int p = 0; p < mc; ++p) sample(p < lc, beg + p, y, acc);
+            for (int p = 0; p < mc; p += GADM_BATCH) samples(p, 1, lc, beg, y, acc);
             if (light) stage_column(j, y, acc, wst, pv);
             wave_lds_sync();
             if (light) finish_column(j, wst, pv);
@@ -683,7 +715,7 @@ __global__ __launch_bounds__(THREADS) void k_gadm_cols(GadmArgs a, int it) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc[c][e] = 0.f;
             load_y(jh, y);
-            for (int p0 = 0; p0 < hcnt; p0 += G) sample(p0 + slot < hcnt, hbeg + p0 + slot, y, acc);
+            for (int p0 = 0; p0 < hcnt; p0 += G * GADM_BATCH) samples(p0 + slot, G, hcnt, hbeg, y, acc);
             // groups differ in lane bits log2(L) and up: add them pairwise
 #pragma unroll
             for (int o = L; o < WAVE; o <<= 1)
