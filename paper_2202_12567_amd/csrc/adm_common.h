@@ -147,19 +147,19 @@ __device__ void spd_solve_wave(AdmShared<Q> &sh, double shift, int lane) {
 }
 
 // Gram G = M^T M of a (rows x Q) FP32 matrix into sh.G.  The rows stream
-// through LDS in tiles of GRAM_STAGE floats (coalesced float4 loads, the next
+// through LDS in tiles of STAGE floats (coalesced float4 loads, the next
 // tile in flight while the current one is used); a thread owns a 4 x 4 block
 // of G and every groups-th row of a tile.  The groups' partial blocks are then
 // summed in group order, so the result does not depend on timing.  part holds
 // PCAP floats.
 constexpr int GRAM_STAGE = 16384;
 
-template <int Q, int PCAP, int THREADS>
+template <int Q, int PCAP, int THREADS, int STAGE = GRAM_STAGE>
 __device__ void gram_rows(AdmShared<Q> &sh, const float *__restrict__ M, int rows, float *part, float *stage) {
     constexpr int P = Q * Q, QB = Q / 4, NB = QB * QB;
-    constexpr int TR = GRAM_STAGE / Q;                  // rows per tile
-    constexpr int NL = GRAM_STAGE / 4 / THREADS;        // float4 per thread per tile
-    static_assert(NL >= 1 && NL * 4 * THREADS == GRAM_STAGE, "tile split");
+    constexpr int TR = STAGE / Q;                       // rows per tile
+    constexpr int NL = STAGE / 4 / THREADS;             // float4 per thread per tile
+    static_assert(NL >= 1 && NL * 4 * THREADS == STAGE, "tile split");
     const int t = fresh_tid();
     const int groups = min(THREADS / NB, PCAP / P);
     const int g = t / NB, blk = t % NB;
@@ -171,7 +171,7 @@ __device__ void gram_rows(AdmShared<Q> &sh, const float *__restrict__ M, int row
     auto load = [&](int tile) {
 #pragma unroll
         for (int u = 0; u < NL; ++u) {
-            const int64_t idx = (int64_t)tile * (GRAM_STAGE / 4) + u * THREADS + t;
+            const int64_t idx = (int64_t)tile * (STAGE / 4) + u * THREADS + t;
             buf[u] = idx < tot4 ? M4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };

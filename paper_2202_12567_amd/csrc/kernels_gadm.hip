@@ -12,8 +12,8 @@
 //                                  Y+_j = F Y_j + Inv T_j, V, Pi (q/4 lanes per column)
 //   xsys    (workgroup per slice)  GY = Y+^T Y+, X system for the next iteration
 //   final   (workgroup per slice)  the final X into the X region, statistics
-// The two X buffers alternate by iteration parity.  The q x q systems (FP64,
-// with FP32 copies for the column updates) and the slice's stop state live in
+// The two X buffers alternate by iteration parity.  The q x q systems (the X
+// system in FP64, the Y system's FP32 rounding) and the slice's stop state live in
 // GADM_SYS_BYTES per slice.  The iteration is the one the LDS-resident kernel
 // runs (Appendix A, in the sparse-residual form of kernels_adm.hip); the Grams
 // are sums in a fixed order, so results are bitwise reproducible.
@@ -29,6 +29,9 @@ namespace {
 constexpr int GADM_LIGHT = 64;
 // samples of a row or column whose loads a lane group issues together
 constexpr int GADM_BATCH = 4;
+// LDS tile of the Gram launches (floats): small enough for two workgroups
+// per CU beside the q x q system's state
+constexpr int GADM_STAGE = 4096;
 
 struct GadmArgs {
     const SliceDesc *desc;
@@ -49,8 +52,8 @@ struct GadmArgs {
 };
 
 struct GSys {
-    double *F, *Inv;                     // Q x Q (X side: F = G Inv; Y side: F stored transposed)
-    float *Ff, *If;                      // Y side, FP32: Ff[a][b] = (Inv C)[a][b], If = Inv
+    double *F, *Inv;                     // Q x Q, the X system: F = G Inv, Inv = (G + a I)^-1
+    float *Ff, *If;                      // the Y system in FP32: Ff[a][b] = (Inv C)[a][b], If = Inv
     int32_t *state;                      // done, iterations, FP32 bits of the residual, all-zero
     double *dstate;                      // ||P_Omega M|| / s0, s0
 };
@@ -65,6 +68,21 @@ __device__ __forceinline__ GSys gsys_of(char *base, int s) {
     g.state = reinterpret_cast<int32_t *>(p + 2 * 32 * 32 * 8 + 2 * 32 * 32 * 4);
     g.dstate = reinterpret_cast<double *>(p + 2 * 32 * 32 * 8 + 2 * 32 * 32 * 4 + 16);
     return g;
+}
+
+// Workgroups of a launch are dispatched to the 8 XCDs in turn (workgroup w to
+// XCD w mod 8), each XCD with its own L2.  A row or column launch deals its
+// blocks to the XCDs in chunks of XCD_CHUNK consecutive blocks, so that a
+// slice's blocks (which read the same X and Y) mostly share an L2, while the
+// costly first blocks (slices in decreasing cost) still spread over every
+// XCD; the tail beyond the last whole round keeps w.
+constexpr int N_XCD = 8;
+constexpr int XCD_CHUNK = 16;
+__device__ __forceinline__ int xcd_item(int w, int n) {
+    constexpr int R = N_XCD * XCD_CHUNK;
+    if (w >= n / R * R) return w;
+    const int x = w % N_XCD, t = w / N_XCD;
+    return ((t / XCD_CHUNK) * N_XCD + x) * XCD_CHUNK + t % XCD_CHUNK;
 }
 
 // item b of a launch over the group's blocks: the slice position k with
@@ -84,7 +102,7 @@ template <int Q, int PCAP, int THREADS>
 __device__ void gram_cross(AdmShared<Q> &sh, const float *__restrict__ A, const float *__restrict__ B, int rows,
                            float *part, float *stage) {
     constexpr int P = Q * Q, QB = Q / 4, NB = QB * QB;
-    constexpr int HALF = GRAM_STAGE / 2;
+    constexpr int HALF = GADM_STAGE / 2;
     constexpr int TR = HALF / Q;
     constexpr int NL = HALF / 4 / THREADS;
     static_assert(NL >= 1 && NL * 4 * THREADS == HALF, "tile split");
@@ -166,7 +184,7 @@ __global__ __launch_bounds__(THREADS) void k_gadm_init(GadmArgs a) {
     __shared__ AdmShared<Q> sh;
     constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
     __shared__ float part[PCAP];
-    __shared__ __align__(16) float stage[GRAM_STAGE];
+    __shared__ __align__(16) float stage[GADM_STAGE];
     const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
     const SliceDesc d = a.desc[s];
     const int m = d.m, n = d.n;
@@ -263,7 +281,7 @@ __global__ __launch_bounds__(THREADS) void k_gadm_init(GadmArgs a) {
     __syncthreads();
 
 
-    gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * n, part, stage);
+    gram_rows<Q, PCAP, THREADS, GADM_STAGE>(sh, Y, 3 * n, part, stage);
     gadm_x_system<Q, THREADS>(sh, g, (double)a.alpha0 * (3.0 * n) / qr);
     (void)wave;
     (void)lane;
@@ -301,7 +319,7 @@ __global__ __launch_bounds__(THREADS) void k_gadm_rows(GadmArgs a, int it) {
     __shared__ __align__(16) double shF[Q * Q];
     __shared__ __align__(16) double shInv[Q * Q];
     __shared__ __align__(16) float stage[NW * G * 2 * Q];   // per row slot: X_i (q), T_i (q)
-    const int b = blockIdx.x;
+    const int b = xcd_item(blockIdx.x, gridDim.x);
     const int k = block_slice(a.rowp, a.count, b);
     const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
     const GSys g = gsys_of(a.gsys, s);
@@ -482,7 +500,7 @@ __global__ __launch_bounds__(THREADS) void k_gadm_ysys(GadmArgs a, int it) {
     __shared__ AdmShared<Q> sh;
     constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
     __shared__ float part[PCAP];
-    __shared__ __align__(16) float stage[GRAM_STAGE];
+    __shared__ __align__(16) float stage[GADM_STAGE];
     __shared__ int stop_s;
     const int k = blockIdx.x;
     const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
@@ -508,16 +526,15 @@ __global__ __launch_bounds__(THREADS) void k_gadm_ysys(GadmArgs a, int it) {
     if (stop_s) return;
     const float *X = ((it & 1) ? a.Xn_all : a.X_all) + d.off_x;
     const float *Xn = ((it & 1) ? a.X_all : a.Xn_all) + d.off_x;
-    gram_rows<Q, PCAP, THREADS>(sh, Xn, m, part, stage);
+    gram_rows<Q, PCAP, THREADS, GADM_STAGE>(sh, Xn, m, part, stage);
     gram_cross<Q, PCAP, THREADS>(sh, Xn, X, m, part, stage);
+    // the Y system; the column launch reads its FP32 rounding
     const double beta = (double)a.beta0 * (double)m / qr;
     spd_inverse<Q>(sh, beta);
     for (int e = t; e < Q * Q; e += THREADS) {
-        const int aa = e / Q, bb = e % Q;   // F[a][b] = sum_l Inv[a][l] C[l][b]; F^T at [b][a]
+        const int aa = e / Q, bb = e % Q;   // Ff[a][b] = sum_l Inv[a][l] C[l][b]
         double v = 0.0;
         for (int l = 0; l < Q; ++l) v += sh.Inv[aa * Q + l] * (double)sh.C[l * Q + bb];
-        g.F[bb * Q + aa] = v;
-        g.Inv[e] = sh.Inv[e];
         g.Ff[e] = (float)v;
         g.If[e] = (float)sh.Inv[e];
     }
@@ -541,7 +558,7 @@ __global__ __launch_bounds__(THREADS) void k_gadm_cols(GadmArgs a, int it) {
     __shared__ __align__(16) float Ft[Q * Q];    // Ft[l][k] = (Inv C)[k][l]
     __shared__ __align__(16) float It[Q * Q];    // It[l][k] = Inv[k][l]
     __shared__ __align__(16) float stage[NW * G * 6 * Q];   // per column slot: Y_j (3q), T_j (3q)
-    const int b = blockIdx.x;
+    const int b = xcd_item(blockIdx.x, gridDim.x);
     const int k = block_slice(a.colp, a.count, b);
     const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
     const GSys g = gsys_of(a.gsys, s);
@@ -738,13 +755,13 @@ __global__ __launch_bounds__(THREADS) void k_gadm_xsys(GadmArgs a, int it) {
     __shared__ AdmShared<Q> sh;
     constexpr int PCAP = (NW * Q * Q > 2 * 1024) ? NW * Q * Q : 2 * 1024;
     __shared__ float part[PCAP];
-    __shared__ __align__(16) float stage[GRAM_STAGE];
+    __shared__ __align__(16) float stage[GADM_STAGE];
     const int s = __builtin_amdgcn_readfirstlane(a.ids[blockIdx.x]);
     const GSys g = gsys_of(a.gsys, s);
     if (g.state[0]) return;
     const SliceDesc d = a.desc[s];
     const float *Y = a.Y_all + d.off_y;
-    gram_rows<Q, PCAP, THREADS>(sh, Y, 3 * d.n, part, stage);
+    gram_rows<Q, PCAP, THREADS, GADM_STAGE>(sh, Y, 3 * d.n, part, stage);
     gadm_x_system<Q, THREADS>(sh, g, (double)a.alpha0 * (3.0 * d.n) / d.qr);
     (void)it;
 }
