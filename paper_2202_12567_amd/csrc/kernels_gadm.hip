@@ -24,9 +24,10 @@ namespace vplmc {
 namespace {
 
 // rows and columns with at most this many samples are taken side by side by
-// lane groups of a wavefront in the global-memory completion, longer ones by
-// the whole wavefront each
-constexpr int GADM_LIGHT = 64;
+// lane groups of a wavefront, longer ones by the whole wavefront each
+// (measured on the rank-32 coarsened 1080p frame: 633 ms of completion at
+// 256, 646 at 128, 663 at 64)
+constexpr int GADM_LIGHT = 256;
 // samples of a row or column whose loads a lane group issues together
 constexpr int GADM_BATCH = 4;
 // LDS tile of the Gram launches (floats): small enough for two workgroups
@@ -83,6 +84,38 @@ __device__ __forceinline__ int xcd_item(int w, int n) {
     if (w >= n / R * R) return w;
     const int x = w % N_XCD, t = w / N_XCD;
     return ((t / XCD_CHUNK) * N_XCD + x) * XCD_CHUNK + t % XCD_CHUNK;
+}
+
+// A block's n rows or columns (items first .. first + n - 1 of the CSR/CSC
+// pointer ptr) in decreasing sample count, ties by index, as keys
+// (2^23 - 1 - count) << 8 | item sorted ascending in LDS (bitonic, N a power
+// of two, at least n, at most the workgroup's threads); returns how many have
+// more than GADM_LIGHT samples (they come first).  All threads call.
+__device__ __forceinline__ int count_of_key(int key) { return 0x7FFFFF - (key >> 8); }
+template <int N>
+__device__ int sort_by_count(int *order, const int32_t *__restrict__ ptr, int first, int n, int t) {
+    static_assert(N <= 256 && (N & (N - 1)) == 0, "a power of two, 8-bit item index");
+    if (t < N) {
+        int key = 0x7FFFFFFF;
+        if (t < n) {
+            const int cnt = ptr[first + t + 1] - ptr[first + t];
+            key = ((0x7FFFFF - min(cnt, 0x7FFFFF)) << 8) | t;
+        }
+        order[t] = key;
+    }
+    for (int size = 2; size <= N; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            const int o = t ^ stride;
+            if (t < N && o > t) {
+                const int u = order[t], v = order[o];
+                if ((u > v) == ((t & size) == 0)) {
+                    order[t] = v;
+                    order[o] = u;
+                }
+            }
+        }
+    return __syncthreads_count(t < n && count_of_key(order[t]) > GADM_LIGHT);
 }
 
 // item b of a launch over the group's blocks: the slice position k with
@@ -305,10 +338,11 @@ __device__ __forceinline__ float group_sum(float v) {
 
 // Phase A of the global-memory completion, per 64-row block.  A row is held
 // by a group of Q/4 lanes, each with four of the q components of X_i and of
-// R_i Y^T, so a sampled Y_j is three coalesced loads per group.  A pass of a
-// wavefront takes 64/(Q/4) rows of at most GADM_LIGHT samples side by side; a
-// longer row is then taken by the whole wavefront, group g walking samples
-// g, g + G, ..., and the groups' partial sums added in a fixed tree.
+// R_i Y^T, so a sampled Y_j is three coalesced loads per group.  The block's
+// rows are sorted by sample count: rows of more than GADM_LIGHT samples are
+// taken one at a time by a whole wavefront (group g walking samples g, g + G,
+// ..., the groups' partial sums added in a fixed tree), the others 64/(Q/4)
+// to a pass of a wavefront, a pass taking rows of similar length.
 // X+_i = X_i F + T_i Inv with T_i = R_i Y^T + a U_i - L_i in FP64.
 template <int Q, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_gadm_rows(GadmArgs a, int it) {
@@ -319,6 +353,8 @@ __global__ __launch_bounds__(THREADS) void k_gadm_rows(GadmArgs a, int it) {
     __shared__ __align__(16) double shF[Q * Q];
     __shared__ __align__(16) double shInv[Q * Q];
     __shared__ __align__(16) float stage[NW * G * 2 * Q];   // per row slot: X_i (q), T_i (q)
+    __shared__ int order[GADM_RB];                          // the block's rows by decreasing count
+    static_assert(GADM_RB <= THREADS, "one row of a block per thread in the sort");
     const int b = xcd_item(blockIdx.x, gridDim.x);
     const int k = block_slice(a.rowp, a.count, b);
     const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
@@ -438,50 +474,50 @@ __global__ __launch_bounds__(THREADS) void k_gadm_rows(GadmArgs a, int it) {
         x[0] = u.x; x[1] = u.y; x[2] = u.z; x[3] = u.w;
     };
 
-    for (int ib = r_beg + wave * G; ib < r_end; ib += NW * G) {
-        const int i = ib + slot;
-        int beg = 0, cnt = 0;
-        if (i < r_end) {
+    // the block's rows in decreasing sample count: a pass takes rows of
+    // similar length; the longer ones come first and are dealt to the
+    // wavefronts in turn
+    const int nloc = r_end - r_beg;
+    const int n_heavy = sort_by_count<GADM_RB>(order, row_ptr, r_beg, nloc, t);
+
+    // the longer rows, one at a time by the whole wavefront
+    for (int h = wave; h < n_heavy; h += NW) {
+        const int ih = r_beg + (order[h] & 0xFF);
+        const int hbeg = row_ptr[ih], hcnt = row_ptr[ih + 1] - hbeg;
+        float x[4], acc[4] = {0.f, 0.f, 0.f, 0.f}, lam[4];
+        load_x(ih, x);
+        for (int p0 = 0; p0 < hcnt; p0 += G * GADM_BATCH) samples(p0 + slot, G, hcnt, hbeg, x, acc);
+        // groups differ in lane bits log2(L) and up: add them pairwise
+#pragma unroll
+        for (int o = L; o < WAVE; o <<= 1)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] += __shfl_xor(acc[e], o, WAVE);
+        float *hst = stage + wave * G * 2 * Q;   // slot 0 of the wavefront
+        if (slot == 0) stage_row(ih, x, acc, hst, lam);
+        wave_lds_sync();
+        if (slot == 0) finish_row(ih, hst, lam);
+        wave_lds_sync();
+    }
+    // the others side by side, G to a pass; the pass's first is its longest
+    for (int pb = n_heavy + wave * G; pb < nloc; pb += NW * G) {
+        const int sp = pb + slot;
+        const bool in = sp < nloc;
+        int i = 0, beg = 0, lc = 0;
+        if (in) {
+            i = r_beg + (order[sp] & 0xFF);
             beg = row_ptr[i];
-            cnt = row_ptr[i + 1] - beg;
+            lc = row_ptr[i + 1] - beg;
         }
-        const bool light = i < r_end && cnt <= GADM_LIGHT;
-        const int lc = light ? cnt : 0;
-        int mc = lc;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) mc = max(mc, __shfl_xor(mc, o, WAVE));
-        mc = __builtin_amdgcn_readfirstlane(mc);
+        const int mc = __builtin_amdgcn_readfirstlane(count_of_key(order[pb]));
         float *wst = stage + (wave * G + slot) * 2 * Q;
-        {
-            float x[4] = {0.f, 0.f, 0.f, 0.f}, acc[4] = {0.f, 0.f, 0.f, 0.f}, lam[4];
-            if (light) load_x(i, x);
-            for (int p = 0; p < mc; p += GADM_BATCH) samples(p, 1, lc, beg, x, acc);
-            if (light) stage_row(i, x, acc, wst, lam);
-            wave_lds_sync();
-            if (light) finish_row(i, wst, lam);
-            // the next row's stage overwrites this slot
-            wave_lds_sync();
-        }
-        // the pass's longer rows, one at a time by the whole wavefront
-        uint64_t heavy = __ballot(i < r_end && !light && lead);
-        while (heavy) {
-            const int ih = ib + __builtin_ctzll(heavy) / L;
-            heavy &= heavy - 1;
-            const int hbeg = row_ptr[ih], hcnt = row_ptr[ih + 1] - hbeg;
-            float x[4], acc[4] = {0.f, 0.f, 0.f, 0.f}, lam[4];
-            load_x(ih, x);
-            for (int p0 = 0; p0 < hcnt; p0 += G * GADM_BATCH) samples(p0 + slot, G, hcnt, hbeg, x, acc);
-            // groups differ in lane bits log2(L) and up: add them pairwise
-#pragma unroll
-            for (int o = L; o < WAVE; o <<= 1)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) acc[e] += __shfl_xor(acc[e], o, WAVE);
-            float *hst = stage + wave * G * 2 * Q;   // slot 0 of the wavefront
-            if (slot == 0) stage_row(ih, x, acc, hst, lam);
-            wave_lds_sync();
-            if (slot == 0) finish_row(ih, hst, lam);
-            wave_lds_sync();
-        }
+        float x[4] = {0.f, 0.f, 0.f, 0.f}, acc[4] = {0.f, 0.f, 0.f, 0.f}, lam[4];
+        if (in) load_x(i, x);
+        for (int p = 0; p < mc; p += GADM_BATCH) samples(p, 1, lc, beg, x, acc);
+        if (in) stage_row(i, x, acc, wst, lam);
+        wave_lds_sync();
+        if (in) finish_row(i, wst, lam);
+        // the next row's stage overwrites this slot
+        wave_lds_sync();
     }
     e2 = wave_sum_d(e2);
     __shared__ double red[NW];
@@ -543,10 +579,9 @@ __global__ __launch_bounds__(THREADS) void k_gadm_ysys(GadmArgs a, int it) {
 // Phase B of the global-memory completion, per 256-column block.  A column is
 // held by a group of Q/4 lanes, each with four of the q components of Y_j and
 // of X+^T R_j for the three channels, so a sampled row X_i / X+_i is one
-// coalesced load per group.  A pass of a wavefront takes 64/(Q/4) columns of at
-// most GADM_LIGHT samples side by side (the loop runs to the pass's longest);
-// a longer column is then taken by the whole wavefront, group g walking
-// samples g, g + G, ..., and the groups' partial sums added in a fixed tree.
+// coalesced load per group.  The block's columns are sorted by sample count
+// and taken as the rows are in k_gadm_rows: the longest one at a time by a
+// whole wavefront, the others 64/(Q/4) to a pass.
 // Y+_j = F Y_j + Inv T_j with T_j = X+^T R_j + b V_j - P_j uses the FP32
 // copies of the two q x q matrices, transposed in LDS.
 template <int Q, int THREADS>
@@ -558,6 +593,8 @@ __global__ __launch_bounds__(THREADS) void k_gadm_cols(GadmArgs a, int it) {
     __shared__ __align__(16) float Ft[Q * Q];    // Ft[l][k] = (Inv C)[k][l]
     __shared__ __align__(16) float It[Q * Q];    // It[l][k] = Inv[k][l]
     __shared__ __align__(16) float stage[NW * G * 6 * Q];   // per column slot: Y_j (3q), T_j (3q)
+    __shared__ int order[GADM_CB];                          // the block's columns by decreasing count
+    static_assert(GADM_CB <= THREADS, "one column of a block per thread in the sort");
     const int b = xcd_item(blockIdx.x, gridDim.x);
     const int k = block_slice(a.colp, a.count, b);
     const int s = __builtin_amdgcn_readfirstlane(a.ids[k]);
@@ -692,60 +729,60 @@ __global__ __launch_bounds__(THREADS) void k_gadm_cols(GadmArgs a, int it) {
         }
     };
 
-    for (int jb = c_beg + wave * G; jb < c_end; jb += NW * G) {
-        const int j = jb + slot;
-        int beg = 0, cnt = 0;
-        if (j < c_end) {
+    // the block's columns in decreasing sample count: a pass takes columns of
+    // similar length; the longer ones come first and are dealt to the
+    // wavefronts in turn
+    const int nloc = c_end - c_beg;
+    const int n_heavy = sort_by_count<GADM_CB>(order, col_ptr, c_beg, nloc, t);
+
+    // the longer columns, one at a time by the whole wavefront
+    for (int h = wave; h < n_heavy; h += NW) {
+        const int jh = c_beg + (order[h] & 0xFF);
+        const int hbeg = col_ptr[jh], hcnt = col_ptr[jh + 1] - hbeg;
+        float y[3][4], acc[3][4], pv[3][4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[c][e] = 0.f;
+        load_y(jh, y);
+        for (int p0 = 0; p0 < hcnt; p0 += G * GADM_BATCH) samples(p0 + slot, G, hcnt, hbeg, y, acc);
+        // groups differ in lane bits log2(L) and up: add them pairwise
+#pragma unroll
+        for (int o = L; o < WAVE; o <<= 1)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[c][e] += __shfl_xor(acc[c][e], o, WAVE);
+        float *hst = stage + wave * G * 6 * Q;   // slot 0 of the wavefront
+        if (slot == 0) stage_column(jh, y, acc, hst, pv);
+        wave_lds_sync();
+        if (slot == 0) finish_column(jh, hst, pv);
+        wave_lds_sync();
+    }
+    // the others side by side, G to a pass; the pass's first is its longest
+    for (int pb = n_heavy + wave * G; pb < nloc; pb += NW * G) {
+        const int sp = pb + slot;
+        const bool in = sp < nloc;
+        int j = 0, beg = 0, lc = 0;
+        if (in) {
+            j = c_beg + (order[sp] & 0xFF);
             beg = col_ptr[j];
-            cnt = col_ptr[j + 1] - beg;
+            lc = col_ptr[j + 1] - beg;
         }
-        const bool light = j < c_end && cnt <= GADM_LIGHT;
-        const int lc = light ? cnt : 0;
-        int mc = lc;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) mc = max(mc, __shfl_xor(mc, o, WAVE));
-        mc = __builtin_amdgcn_readfirstlane(mc);
+        const int mc = __builtin_amdgcn_readfirstlane(count_of_key(order[pb]));
         float *wst = stage + (wave * G + slot) * 6 * Q;
-        {
-            float y[3][4], acc[3][4], pv[3][4];
+        float y[3][4], acc[3][4], pv[3][4];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) y[c][e] = acc[c][e] = 0.f;
-            if (light) load_y(j, y);
-            for (int p = 0; p < mc; p += GADM_BATCH) samples(p, 1, lc, beg, y, acc);
-            if (light) stage_column(j, y, acc, wst, pv);
-            wave_lds_sync();
-            if (light) finish_column(j, wst, pv);
-            // the next column's stage overwrites this slot
-            wave_lds_sync();
-        }
-        // the pass's longer columns, one at a time by the whole wavefront
-        uint64_t heavy = __ballot(j < c_end && !light && lane % L == 0);
-        while (heavy) {
-            const int jh = jb + __builtin_ctzll(heavy) / L;
-            heavy &= heavy - 1;
-            const int hbeg = col_ptr[jh], hcnt = col_ptr[jh + 1] - hbeg;
-            float y[3][4], acc[3][4], pv[3][4];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) acc[c][e] = 0.f;
-            load_y(jh, y);
-            for (int p0 = 0; p0 < hcnt; p0 += G * GADM_BATCH) samples(p0 + slot, G, hcnt, hbeg, y, acc);
-            // groups differ in lane bits log2(L) and up: add them pairwise
-#pragma unroll
-            for (int o = L; o < WAVE; o <<= 1)
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc[c][e] += __shfl_xor(acc[c][e], o, WAVE);
-            float *hst = stage + wave * G * 6 * Q;   // slot 0 of the wavefront
-            if (slot == 0) stage_column(jh, y, acc, hst, pv);
-            wave_lds_sync();
-            if (slot == 0) finish_column(jh, hst, pv);
-            wave_lds_sync();
-        }
+            for (int e = 0; e < 4; ++e) y[c][e] = acc[c][e] = 0.f;
+        if (in) load_y(j, y);
+        for (int p = 0; p < mc; p += GADM_BATCH) samples(p, 1, lc, beg, y, acc);
+        if (in) stage_column(j, y, acc, wst, pv);
+        wave_lds_sync();
+        if (in) finish_column(j, wst, pv);
+        // the next column's stage overwrites this slot
+        wave_lds_sync();
     }
 }
 
