@@ -329,7 +329,7 @@ def render_slice_coarsened(scene, table, s, params, cp, n_max, weights_override=
     n = co["n"]
     i1, j1 = co["i1"], co["j1"]
     A1, amb1, _ = R.eval_entries(scene, L, rows[i1], co["columns"][j1], params)
-    w, st = R.slice_weights(A1, j1, n)
+    w, st = R.slice_weights(A1, j1, n, params.pass2_mix)
     if weights_override is not None:
         w = np.asarray(weights_override, dtype=np.uint64)
     taken = np.zeros(m * n, dtype=bool)

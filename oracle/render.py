@@ -60,6 +60,8 @@ class Params:
     lam: float = 0.01
     ray_eps: float = 1e-4
     fixed_iters: bool = False
+    # second-pass density g(j) + pass2_mix mean g (0: the paper's g; inf: uniform)
+    pass2_mix: float = 0.0
 
 
 def cluster_lights(scene, seed):
@@ -88,11 +90,11 @@ def slice_first_pass(scene, lights, s, params):
     return i1, j1, A1, amb1, lit1
 
 
-def slice_weights(A1, j1, n):
+def slice_weights(A1, j1, n, mix=0.0):
     t = A1.sum(axis=1)
     cnt, mean, var, mn, mx = column_stats(j1, t, n)
     g = importance(mn, mx, cnt)
-    return weights_from_g(g), dict(count=cnt, mean=mean, var=var, min=mn, max=mx, g=g)
+    return weights_from_g(g, mix), dict(count=cnt, mean=mean, var=var, min=mn, max=mx, g=g)
 
 
 def complete_and_render(m, n, q, ii, jj, A, seed, s, params, X0Y0=None):
@@ -139,7 +141,7 @@ def render_slice(scene, lights, s, params, weights_override=None, keep=False):
     q = int(scene.rank[s])
     D = m * n
     i1, j1, A1, amb1, _ = slice_first_pass(scene, lights, s, params)
-    w, st = slice_weights(A1, j1, n)
+    w, st = slice_weights(A1, j1, n, params.pass2_mix)
     if weights_override is not None:
         w = np.asarray(weights_override, dtype=np.uint64)
     taken = np.zeros(D, dtype=bool)

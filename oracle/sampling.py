@@ -101,15 +101,39 @@ def importance(mn, mx, cnt):
     return np.where(cnt > 0, mx - mn, 0.0)
 
 
-def weights_from_g(g):
+def weights_from_g(g, mix=0.0):
+    """Integer column weights of the second pass from g (Sec. 5).
+
+    mix = 0 is the paper's density, w_j = 0 if g_j <= 0 else
+    max(1, floor(2^24 g_j / max g)).  A positive mix adds mix times the mean
+    weight to every column before rescaling to at most 2^24 (a density
+    proportional to g(j) + mix mean g, a comparison baseline for the learned
+    proposal; the paper uses g alone):
+        q_j = the paper's weights, S = sum q_j,
+        c = floor(fp32(mix) S / n'),
+        w_j = q_j if c = 0, else max(1, floor(2^24 (q_j + c) / (2^24 + c))),
+    every quotient in FP64 over exact integers.  mix = +inf is the uniform
+    density, w_j = 1.
+    """
     g = np.asarray(g, np.float64)
+    mix32 = float(np.float32(mix))
+    if not mix32 >= 0.0:
+        raise ValueError("mix must be >= 0")
+    if mix32 == np.inf:
+        return np.ones(g.shape, dtype=np.uint64)
     gmax = g.max() if g.size else 0.0
     if not gmax > 0.0:
         return np.ones(g.shape, dtype=np.uint64)
-    w = np.where(g > 0.0, np.maximum(1.0, np.floor(TWO24 * g / gmax)), 0.0)
-    if not (w > 0).any():
+    q = np.where(g > 0.0, np.maximum(1.0, np.floor(TWO24 * g / gmax)), 0.0)
+    if not (q > 0).any():
         return np.ones(g.shape, dtype=np.uint64)
-    return w.astype(np.uint64)
+    q = q.astype(np.uint64)
+    S = int(q.sum())
+    c = int(np.floor(np.float64(mix32) * np.float64(S) / np.float64(g.shape[0])))
+    if c == 0:
+        return q
+    f = np.floor(TWO24 * (q + np.uint64(c)).astype(np.float64) / np.float64(2 ** 24 + c))
+    return np.maximum(1.0, f).astype(np.uint64)
 
 
 def pass2(seed, s, m, n, N1, ppm2, w, taken1, batch=4096):

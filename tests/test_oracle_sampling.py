@@ -85,6 +85,46 @@ def test_weights_hand_example():
     assert list(weights_from_g(np.zeros(4))) == [1, 1, 1, 1]
 
 
+def test_mixed_weights_hand_example():
+    """g(j) + mix mean g: with g = (0, 1, 2, 4) the paper's weights are
+    2^20 (0, 4, 8, 16), their sum 28 2^20, and at mix = 1 the offset is
+    c = floor(28 2^20 / 4) = 7 2^20; then w_j = floor(2^24 (q_j + c) / (2^24 + c))
+    = floor(2^24 k_j / 23) with k = (7, 11, 15, 23)."""
+    g = np.array([0.0, 1.0, 2.0, 4.0])
+    w = weights_from_g(g, 1.0)
+    assert list(w) == [117440512 // 23, 184549376 // 23, 251658240 // 23, 1 << 24]
+    assert list(w) == [5106109, 8023885, 10941662, 16777216]
+    # mix 0 is the paper's rule; +inf the uniform density
+    assert np.array_equal(weights_from_g(g, 0.0), weights_from_g(g))
+    assert list(weights_from_g(g, np.inf)) == [1, 1, 1, 1]
+    # a small mix whose offset rounds to zero leaves the paper's weights
+    assert np.array_equal(weights_from_g(g, 1e-9), weights_from_g(g))
+
+
+def test_mixed_weights_properties():
+    rng = np.random.default_rng(4)
+    g = rng.exponential(1.0, 700) * (rng.uniform(0, 1, 700) < 0.7)
+    q = weights_from_g(g).astype(np.float64)
+    prev = None
+    for mix in (0.1, 0.3, 1.0, 3.0, 100.0, 1e6):
+        w = weights_from_g(g, mix).astype(np.float64)
+        assert (w >= 1).all() and (w <= 2 ** 24).all()
+        order = np.argsort(g, kind="stable")
+        assert (np.diff(w[order]) >= 0).all()                 # monotone in g
+        # the density is g + mix mean g (up to the integer rounding)
+        p = w / w.sum()
+        want = (q + mix * q.mean()) / (q + mix * q.mean()).sum()
+        np.testing.assert_allclose(p, want, rtol=1e-5, atol=1e-9)
+        spread = w.max() / w.min()
+        if prev is not None:
+            assert spread <= prev                              # flatter as mix grows
+        prev = spread
+    assert weights_from_g(g, 1e6).min() / weights_from_g(g, 1e6).max() > 0.999
+    for bad in (-1.0, np.nan):
+        with pytest.raises(ValueError):
+            weights_from_g(g, bad)
+
+
 def test_pass2_first_attempt_by_hand():
     # recompute attempt 0 by hand from the generator and compare
     m, n = 5, 4
