@@ -449,21 +449,27 @@ def main():
         if rates:
             ws = None                     # the headline workspace is not needed past this point
             torch.cuda.empty_cache()
-            pts = {"plain": [], "learned": []}
+            # the baselines that separate what the network adds from what a
+            # flatter second pass alone gives: the uniform density and the
+            # density g(j) + 3 mean g (the mix of the network's training target)
+            kinds = (("plain", False, 0.0), ("learned", True, 0.0), ("uniform", False, float("inf")),
+                     ("g_plus_3_mean_g", False, 3.0))
+            pts = {name: [] for name, _, _ in kinds}
             rows = []
             for r in rates:
                 p1, p2 = ppms(r)
                 pl = make_plan(api.default_params(seed=seed, pass1_ppm=p1, pass2_ppm=p2))
                 wsr = api.workspace(pl, dev)
                 row = {"rate_pct": r}
-                for name, flag in (("plain", False), ("learned", True)):
-                    pp = api.default_params(seed=seed, pass1_ppm=p1, pass2_ppm=p2, learned=flag)
+                for name, flag, mix in kinds:
+                    pp = api.default_params(seed=seed, pass1_ppm=p1, pass2_ppm=p2, learned=flag, pass2_mix=mix)
                     msr = frame_times(api, torch, ctx, pl, ds, pp, wsr, rad_l, args.sweep_steps, 1, args.eager)
                     er = rel(rad_l[pid_t.long()].double(), ref)
                     pts[name].append((er, msr))
                     row[name] = {"frame_ms": round(msr, 3), "pixel_rmse": round(er, 5)}
                 rows.append(row)
-                progress(f"sweep {r}%: plain {row['plain']['frame_ms']} ms, learned {row['learned']['frame_ms']} ms")
+                progress(f"sweep {r}%: " + ", ".join(f"{k} {row[k]['frame_ms']} ms / {row[k]['pixel_rmse']}"
+                                                     for k, _, _ in kinds))
                 del wsr
                 pl.close()
                 torch.cuda.empty_cache()
@@ -481,6 +487,9 @@ def main():
                      "target_pixel_rmse": round(target, 5),
                      "plain_at_smallest_rate": first_meeting("plain"),
                      "learned_at_smallest_rate": first_meeting("learned"),
+                     "baselines_at_smallest_rate": {k: first_meeting(k) for k in ("uniform", "g_plus_3_mean_g")},
+                     "baselines_ms_interpolated": {k: (None if (v := interp_ms_at(pts[k], target)) is None
+                                                       else round(v, 3)) for k in ("uniform", "g_plus_3_mean_g")},
                      "plain_ms_interpolated": None if ms_plain_t is None else round(ms_plain_t, 3),
                      "learned_ms_interpolated": None if ms_learned_t is None else round(ms_learned_t, 3),
                      "learned_speedup_interpolated": None if not (ms_plain_t and ms_learned_t)

@@ -113,7 +113,14 @@ typedef struct {
     float r_min;          /* distance clamp of the geometry term               */
     float ray_eps;        /* shadow-ray origin offset along the normal         */
     float lam;            /* masked-ALS regulariser: lam max(1, n) I per row / column (> 0) */
-    int32_t reserved;     /* 0                                                 */
+    float pass2_mix;      /* second-pass column density g(j) + pass2_mix mean g:
+                           * 0 is Sec. 5's g (the default), +inf the uniform
+                           * density; a comparison baseline for the learned
+                           * proposal.  Integer weights: q_j = the g weights,
+                           * c = floor(pass2_mix sum q / n'), w_j = q_j if c = 0,
+                           * else max(1, floor(2^24 (q_j + c) / (2^24 + c))).
+                           * Must be >= 0 (VPLMC_EINVAL otherwise); ignored for
+                           * slices sampled by the learned proposal.          */
 } vplmc_params;
 
 typedef struct vplmc_ctx vplmc_ctx;

@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32), ("tol", ctypes.c_float),
                 ("alpha0", ctypes.c_float), ("beta0", ctypes.c_float), ("gamma", ctypes.c_float),
                 ("r_min", ctypes.c_float), ("ray_eps", ctypes.c_float), ("lam", ctypes.c_float),
-                ("reserved", ctypes.c_int32)]
+                ("pass2_mix", ctypes.c_float)]
 
 
 class Coarsen(ctypes.Structure):

@@ -88,7 +88,7 @@ int check_params(const vplmc_params *p) {
     if (!(p->tol >= 0.f)) return set_error(VPLMC_EINVAL, "tol must be >= 0");
     if (!(p->r_min > 0.f) || !(p->ray_eps >= 0.f)) return set_error(VPLMC_EINVAL, "r_min must be > 0, ray_eps >= 0");
     if (!(p->lam > 0.f)) return set_error(VPLMC_EINVAL, "lam must be > 0");
-    if (p->reserved != 0) return set_error(VPLMC_EINVAL, "reserved must be 0");
+    if (!(p->pass2_mix >= 0.f)) return set_error(VPLMC_EINVAL, "pass2_mix must be >= 0 (got %g)", (double)p->pass2_mix);
     if (p->flags & ~(VPLMC_FIXED_ITERS | VPLMC_LEARNED | VPLMC_FEATURES | VPLMC_GIVEN_INIT | VPLMC_NO_NONNEG | VPLMC_ALS))
         return set_error(VPLMC_EINVAL, "unknown flags 0x%x", p->flags);
     return VPLMC_OK;
@@ -766,8 +766,8 @@ int vplmc_render(vplmc_ctx *ctx, const vplmc_plan *plan, const vplmc_points *poi
         }
     }
     uint64_t *prefix = region<uint64_t>(ws, plan, R_COLW_PREFIX);
-    if ((rc = launch_weights(st, *plan, desc, cnt, mn, mx, logits, region<uint32_t>(ws, plan, VPLMC_R_WEIGHTS), prefix,
-                             stats)))
+    if ((rc = launch_weights(st, *plan, desc, cnt, mn, mx, logits, params->pass2_mix,
+                             region<uint32_t>(ws, plan, VPLMC_R_WEIGHTS), prefix, stats)))
         return rc;
     if ((rc = ph.mark(VPLMC_PH_PASS2))) return rc;
     if ((rc = launch_pass2(st, *plan, desc, params->seed, prefix, bm, bmt, omega2, stats))) return rc;

@@ -235,13 +235,22 @@ __global__ void k_colstats(const SliceDesc *__restrict__ desc, int S, int64_t to
     zeros[o] = z;
 }
 
-// g(j) = max - min (Sec. 5, f(i) = 1) quantised to w_j = max(1, floor(2^24 g / max g))
+// g(j) = max - min (Sec. 5, f(i) = 1) quantised to q_j = max(1, floor(2^24 g / max g))
 // (0 where g = 0; all 1 if every g is 0) and its inclusive uint64 prefix.
 // With logits (the learned proposal), w_j = max(1, floor(2^24 exp(y_j - max y)))
 // in FP64 from the FP32 logits instead; a slice with any non-finite logit
-// keeps the g weights and is flagged.
+// keeps the g weights and is flagged.  A positive mix (the density
+// g(j) + mix mean g, a baseline for the learned proposal) offsets the g
+// weights by c = floor(mix sum q / n') and rescales them,
+// w_j = max(1, floor(2^24 (q_j + c) / (2^24 + c))); mix = +inf gives w_j = 1.
+__device__ __forceinline__ uint32_t g_weight(float gj, float gmax) {
+    if (!(gj > 0.f)) return 0u;
+    const double f = floor((16777216.0 * (double)gj) / (double)gmax);
+    return f > 1.0 ? (uint32_t)f : 1u;
+}
+
 __global__ __launch_bounds__(256) void k_weights(const SliceDesc *__restrict__ desc, const int32_t *cnt,
-                                                 const float *mn, const float *mx, const float *logits,
+                                                 const float *mn, const float *mx, const float *logits, float mix,
                                                  uint32_t *w, uint64_t *prefix, int32_t *stats) {
     __shared__ uint32_t sm[8];
     __shared__ float smax[4];
@@ -276,7 +285,23 @@ __global__ __launch_bounds__(256) void k_weights(const SliceDesc *__restrict__ d
     ymax = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
     const bool learned = logits != nullptr && !bad_s;
     if (logits && bad_s && t == 0) stats[4 * s + 1] |= VPLMC_SLICE_FALLBACK;
-    const bool uniform = !(gmax > 0.f);
+    const bool uniform = !(gmax > 0.f) || (!learned && isinf(mix));
+    // the offset of the mixed density: c = floor(mix sum q / n') over the g weights
+    uint64_t c = 0;
+    if (!learned && !uniform && mix > 0.f) {
+        uint64_t sq = 0;
+        for (int j = t; j < d.n; j += 256) {
+            const int64_t o = d.off_col + j;
+            sq += g_weight(cnt[o] > 0 ? mx[o] - mn[o] : 0.f, gmax);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) sq += __shfl_xor(sq, o, WAVE);
+        __shared__ uint64_t ssum[4];
+        if (lane == 0) ssum[wv] = sq;
+        __syncthreads();
+        const uint64_t tot = (ssum[0] + ssum[1]) + (ssum[2] + ssum[3]);
+        c = (uint64_t)floor(((double)mix * (double)tot) / (double)d.n);
+    }
     if (t == 0) carry_s = 0;
     __syncthreads();
     for (int j0 = 0; j0 < d.n; j0 += 256) {
@@ -290,9 +315,9 @@ __global__ __launch_bounds__(256) void k_weights(const SliceDesc *__restrict__ d
             } else if (uniform) {
                 wj = 1;
             } else {
-                const float gj = cnt[o] > 0 ? mx[o] - mn[o] : 0.f;
-                if (gj > 0.f) {
-                    const double f = floor((16777216.0 * (double)gj) / (double)gmax);
+                wj = g_weight(cnt[o] > 0 ? mx[o] - mn[o] : 0.f, gmax);
+                if (c > 0) {
+                    const double f = floor((16777216.0 * (double)(wj + c)) / (double)(16777216ull + c));
                     wj = f > 1.0 ? (uint32_t)f : 1u;
                 }
             }
@@ -798,10 +823,11 @@ int launch_colstats(hipStream_t st, const vplmc_plan &plan, const SliceDesc *des
 }
 
 int launch_weights(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *cnt,
-                   const float *mn, const float *mx, const float *logits, uint32_t *w, uint64_t *prefix,
+                   const float *mn, const float *mx, const float *logits, float mix, uint32_t *w, uint64_t *prefix,
                    int32_t *stats) {
     if (plan.n_slices <= 0) return VPLMC_OK;
-    hipLaunchKernelGGL(k_weights, dim3(plan.n_slices), dim3(256), 0, st, desc, cnt, mn, mx, logits, w, prefix, stats);
+    hipLaunchKernelGGL(k_weights, dim3(plan.n_slices), dim3(256), 0, st, desc, cnt, mn, mx, logits, mix, w, prefix,
+                       stats);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }

@@ -328,7 +328,7 @@ int launch_colstats(hipStream_t st, const vplmc_plan &plan, const SliceDesc *des
                     const float *val1, const uint32_t *bmt, uint16_t *wpret, int32_t *col_ptr, int32_t *csc_row,
                     float *csc_val, int32_t *cnt, float *mn, float *mx, double *sum, double *sumsq, int32_t *zeros);
 int launch_weights(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc, const int32_t *cnt,
-                   const float *mn, const float *mx, const float *logits, uint32_t *w, uint64_t *prefix,
+                   const float *mn, const float *mx, const float *logits, float mix, uint32_t *w, uint64_t *prefix,
                    int32_t *stats);
 // learned proposal (kernels_mlp.hip)
 constexpr int MLP_IN = 12, MLP_HID = 128;

@@ -37,6 +37,7 @@ def test_version_and_defaults():
     assert (p.pass1_ppm, p.pass2_ppm, p.max_iter) == (50000, 50000, 100)
     assert abs(p.gamma - 1.6) < 1e-6 and abs(p.tol - 1e-3) < 1e-9
     assert ctypes.sizeof(N.Params) == 56 and abs(p.lam - 0.01) < 1e-9
+    assert p.pass2_mix == 0.0          # the paper's second-pass density g(j)
 
 
 def plan(pt, cl, rank, nc=8, **kw):
@@ -128,7 +129,8 @@ def test_plan_rejects_bad_shapes(args, code, needle):
 
 
 @pytest.mark.parametrize("kw", [dict(pass1_ppm=-1), dict(pass1_ppm=600000, pass2_ppm=500000),
-                                dict(gamma=1.7), dict(alpha0=0.0), dict(max_iter=-1), dict(flags=64), dict(lam=0.0)])
+                                dict(gamma=1.7), dict(alpha0=0.0), dict(max_iter=-1), dict(flags=64), dict(lam=0.0),
+                                dict(pass2_mix=-0.5), dict(pass2_mix=float("nan"))])
 def test_plan_rejects_bad_params(kw):
     rc, _ = plan([0, 64], [0, 64], [4], **kw)
     assert rc == N.EINVAL
