@@ -183,6 +183,7 @@ def write_traffic_record(args, csvs):
     rate = args.rate if args.rate is not None else (1.0 if cspec != "none" else 5.0)
     ppm = int(round(rate * 1e4)) if cspec != "none" else int(round(rate * 1e4 / 2))
     rank = args.rank if args.rank is not None else (16 if cspec != "none" else 0)
+    wl = "" if args.workload == "frame" else f"--workload {args.workload} --coarsen {cspec} --rank {rank} "
     rec = {"kernel": "k_adm_ell", "workload": args.workload, "ppm": ppm, "coarsen": cspec, "rank": rank,
            "adm_threads": shape[1], "adm_queue": shape[0],   # the shape the counter runs used
            "source_sha256": source_digest(), "fetch_size_kib_per_dispatch": round(fetch, 1),
@@ -191,7 +192,7 @@ def write_traffic_record(args, csvs):
            "fetch_factor": round(ff, 4), "write_factor": round(wf, 4), "bytes_per_launch": rd + wr,
            "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
            "commands": [f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} -d <out> -o <name> --output-format csv "
-                        f"-- python3 /root/repo/bench.py --eager --steps 1 --warmup 0 --sweep \"\" --no-cpu-baseline "
+                        f"-- python3 /root/repo/bench.py {wl}--eager --steps 1 --warmup 0 --sweep \"\" --no-cpu-baseline "
                         f"--no-variants --lightcut none --launch-shape {':'.join(map(str, shape))}"
                         for c in ("FETCH_SIZE", "WRITE_SIZE")]
            + [f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} -d <out> -o <name> --output-format csv "
