@@ -273,7 +273,7 @@ def cpu_baseline(workload, seed, n_slices, ppm1, ppm2, rank, coarsen):
                       f"{what}), {dt:.1f} s wall on {workers} worker processes"}
 
 
-SEEDS = {"frame": 41, "mid": 11, "batch": 21, "tiny": 1}
+SEEDS = {"frame": 41, "mid": 11, "batch": 21, "tiny": 1, "tri": 1, "trimid": 11}
 
 
 def main():
@@ -587,7 +587,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {sc.m} points, {sc.n} VPLs, {sc.n_slices} slices, {rate_txt}, "
-                               f"rank {int(q.min())}-{int(q.max())}, {len(sc.spheres['r'])} spheres",
+                               f"rank {int(q.min())}-{int(q.max())}, "
+                               + (f"{len(sc.spheres['tri'])} triangles (SBVH), instant-radiosity VPLs" if "tri" in sc.spheres
+                                  else f"{len(sc.spheres['r'])} spheres"),
                    "seed": seed, "proposal": "plain"},
         "frame_ms": round(ms, 3),
         "frame_ms_median": round(ms_median, 3),

@@ -21,7 +21,8 @@
  *    says HOST.  Arrays are contiguous structure-of-arrays, float32 / int32.
  *  - The caller owns every buffer it passes (inputs, outputs, workspace).
  *    The library owns only what its create calls return (context, plan)
- *    and the occluder BVH it uploads in vplmc_set_occluders.
+ *    and the occluder BVH it uploads in vplmc_set_occluders or
+ *    vplmc_set_triangles.
  *  - All device work is ordered on the context's stream: the completion's
  *    rank groups run on three streams of the context forked from it and
  *    joined back into it by events, so work enqueued on the stream after a
@@ -203,6 +204,26 @@ int vplmc_set_stream(vplmc_ctx *ctx, void *stream);
  * n = 0 removes all occluders. */
 int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float *cy,
                         const float *cz, const float *r);
+
+/* Occluder triangles (HOST, 9 floats each: v0, v1, v2), replacing any
+ * spheres: builds a spatial-split BVH (SBVH, Sec. 6's ray-casting structure;
+ * binned surface-area heuristic with object and spatial splits, references
+ * chopped at the split planes) on the host and uploads it; shadow rays of
+ * every later call test the open segment against the triangles.  n = 0
+ * removes all occluders.  Errors: VPLMC_EINVAL for n outside [0, 2^24], a
+ * NULL array with n > 0 or a non-finite vertex; VPLMC_ENOMEM. */
+int vplmc_set_triangles(vplmc_ctx *ctx, int32_t n, const float *v /* HOST */);
+
+/* The SBVH vplmc_set_triangles builds, for inspection (host only, no
+ * device): node boxes (6 floats per node: lo xyz, hi xyz, padded as used),
+ * node codes (2 per node: leaf code first_reference << 4 | count, 0 for an
+ * inner node; skip index, the node after the subtree) in depth-first order,
+ * and the triangle of every leaf reference.  The counts are written to
+ * *n_nodes and *n_refs; VPLMC_EINVAL if they exceed max_nodes / max_refs
+ * (the outputs are then left untouched) or the input is invalid. */
+int vplmc_sbvh_build(int32_t n, const float *v /* HOST */, int32_t max_nodes, float *box /* HOST */,
+                     int32_t *code /* HOST */, int32_t max_refs, int32_t *refs /* HOST */, int32_t *n_nodes /* HOST */,
+                     int32_t *n_refs /* HOST */);
 
 /* ---- frame plan (host only: no device work) ---------------------------- */
 /* Slice s owns points pt_ids[pt_offsets[s] .. pt_offsets[s+1]) and cut

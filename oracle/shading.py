@@ -21,6 +21,12 @@ acceleration structure).  An entry is flagged *ambiguous* when a
 perturbation of AMBIG in some sphere distance could flip V; parity tests
 compare only unflagged entries and count the flagged ones.
 
+Triangle occluders (the paper's scenes are triangle meshes traced through an
+SBVH, Sec. 6): V = 0 iff the open segment meets a triangle, decided by the
+barycentric coordinates (u, v) and the segment parameter t of the crossing
+with the triangle's plane, again by brute force; the ambiguity flag uses a
+margin AMBIG_TRI on those parameters.
+
 Pinned by: closed forms for unoccluded point-to-point configurations and
 analytic occluded/unoccluded segment-sphere cases
 (tests/test_oracle_shading.py).
@@ -28,6 +34,7 @@ analytic occluded/unoccluded segment-sphere cases
 import numpy as np
 
 AMBIG = 1e-5
+AMBIG_TRI = 1e-4
 INV_PI = 1.0 / np.pi
 
 
@@ -41,8 +48,64 @@ def segment_sphere_dist(o, D, c):
     return np.sqrt(np.einsum("esk,esk->es", p, p))
 
 
+def segment_triangle(o, D, v0, v1, v2):
+    """Segments o + t D (E, 3) against triangles (T, 3) by the barycentric
+    form of the intersection (Moller-Trumbore): returns the margins (E, T) of
+    the four conditions u >= 0, v >= 0, u + v <= 1 and 0 < t < 1 (their
+    minimum: positive inside, negative outside; -inf where the segment is
+    parallel to the triangle's plane) and the plane-angle term |det| /
+    (|D| |e1| |e2|) (E, T)."""
+    e1 = v1 - v0
+    e2 = v2 - v0
+    p = np.cross(D[:, None, :], e2[None, :, :])                 # (E, T, 3)
+    det = np.einsum("etk,tk->et", p, e1)
+    s = o[:, None, :] - v0[None, :, :]
+    q = np.cross(s, e1[None, :, :])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / det
+        u = np.einsum("etk,etk->et", s, p) * inv
+        v = np.einsum("ek,etk->et", D, q) * inv
+        t = np.einsum("tk,etk->et", e2, q) * inv
+    margin = np.minimum(np.minimum(u, v), np.minimum(1.0 - u - v, np.minimum(t, 1.0 - t)))
+    scale = (np.linalg.norm(D, axis=1)[:, None] * np.linalg.norm(e1, axis=1)[None, :]
+             * np.linalg.norm(e2, axis=1)[None, :])
+    angle = np.abs(det) / scale
+    margin = np.where(det != 0.0, margin, -np.inf)
+    return margin, angle
+
+
+def triangle_visibility(o, y, tri, chunk=1 << 22):
+    """V (E,) and an ambiguity flag (E,) for segments o -> y against
+    triangles tri (T, 9) = (v0, v1, v2): V = 0 iff some triangle is met at a
+    parameter t in (0, 1), brute force over every triangle.  A pair is
+    ambiguous when no triangle blocks it by more than AMBIG_TRI (in the
+    barycentric and segment parameters) but one comes within AMBIG_TRI of
+    blocking it, or when a triangle within reach is nearly parallel to the
+    segment (angle term below AMBIG_TRI)."""
+    tri = np.asarray(tri, np.float64).reshape(-1, 9)
+    v0, v1, v2 = tri[:, 0:3], tri[:, 3:6], tri[:, 6:9]
+    E = o.shape[0]
+    V = np.ones(E)
+    amb = np.zeros(E, dtype=bool)
+    if tri.shape[0] == 0:
+        return V, amb
+    step = max(1, chunk // max(1, tri.shape[0]))
+    for a in range(0, E, step):
+        b = min(E, a + step)
+        margin, angle = segment_triangle(o[a:b], y[a:b] - o[a:b], v0, v1, v2)
+        blocked = (margin > 0.0).any(axis=1)
+        sure = (margin > AMBIG_TRI).any(axis=1)
+        near = ((np.abs(margin) < AMBIG_TRI) | ((angle < AMBIG_TRI) & (margin > -AMBIG_TRI))).any(axis=1)
+        V[a:b] = np.where(blocked, 0.0, 1.0)
+        amb[a:b] = near & ~sure
+    return V, amb
+
+
 def visibility(o, y, spheres, chunk=4096):
-    """V (E,) in {0, 1} and an ambiguity flag (E,) for segments o -> y."""
+    """V (E,) in {0, 1} and an ambiguity flag (E,) for segments o -> y; the
+    occluders are spheres (cx, cy, cz, r) or, with key "tri", triangles."""
+    if "tri" in spheres:
+        return triangle_visibility(o, y, spheres["tri"])
     c = np.stack([spheres["cx"], spheres["cy"], spheres["cz"]], axis=1).astype(np.float64)
     r = np.asarray(spheres["r"], dtype=np.float64)
     E = o.shape[0]

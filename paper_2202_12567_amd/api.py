@@ -38,6 +38,22 @@ def default_params(fixed_iters=None, learned=None, features=None, given_init=Non
     return p
 
 
+def sbvh_build(tri):
+    """vplmc_sbvh_build: (boxes (n_nodes, 6), codes (n_nodes, 2), refs (n_refs,)) of the SBVH over
+    triangles (T, 9); host only."""
+    lib = N.load()
+    tri = np.ascontiguousarray(tri, dtype=np.float32).reshape(-1, 9)
+    f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    nn, nr = ctypes.c_int32(), ctypes.c_int32()
+    lib.vplmc_sbvh_build(int(tri.shape[0]), f(tri), 0, None, None, 0, None, ctypes.byref(nn), ctypes.byref(nr))
+    box = np.zeros((max(nn.value, 1), 6), np.float32)
+    code = np.zeros((max(nn.value, 1), 2), np.int32)
+    refs = np.zeros(max(nr.value, 1), np.int32)
+    check(lib.vplmc_sbvh_build(int(tri.shape[0]), f(tri), nn.value, f(box), f(code), nr.value, f(refs),
+                               ctypes.byref(nn), ctypes.byref(nr)))
+    return box[:nn.value], code[:nn.value], refs[:nr.value]
+
+
 class Context:
     """Device + stream (vplmc_create).  The stream defaults to torch's current stream."""
 
@@ -52,8 +68,13 @@ class Context:
         self.h = h
 
     def set_occluders(self, spheres):
-        cx, cy, cz, r = (np.ascontiguousarray(spheres[k], dtype=np.float32) for k in ("cx", "cy", "cz", "r"))
+        """Spheres (cx, cy, cz, r), or triangles under the key "tri" ((T, 9) v0 v1 v2)."""
         f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        if "tri" in spheres:
+            tri = np.ascontiguousarray(spheres["tri"], dtype=np.float32).reshape(-1, 9)
+            check(N.load().vplmc_set_triangles(self.h, int(tri.shape[0]), f(tri)))
+            return
+        cx, cy, cz, r = (np.ascontiguousarray(spheres[k], dtype=np.float32) for k in ("cx", "cy", "cz", "r"))
         check(N.load().vplmc_set_occluders(self.h, int(cx.shape[0]), f(cx), f(cy), f(cz), f(r)))
 
     def close(self):

@@ -239,6 +239,74 @@ int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float 
     return VPLMC_OK;
 }
 
+static int check_triangles(int32_t n, const float *v) {
+    if (n < 0 || n > BVH_MAX_TRIANGLES) return set_error(VPLMC_EINVAL, "n must be in [0, 2^24]");
+    if (n > 0 && !v) return set_error(VPLMC_EINVAL, "triangle array must be non-NULL");
+    for (size_t k = 0; k < 9 * (size_t)n; ++k)
+        if (!std::isfinite(v[k])) return set_error(VPLMC_EINVAL, "triangle %zu: vertex not finite", k / 9);
+    return VPLMC_OK;
+}
+
+int vplmc_set_triangles(vplmc_ctx *ctx, int32_t n, const float *v) {
+    if (!ctx) return set_error(VPLMC_EINVAL, "ctx is NULL");
+    int rc = check_triangles(n, v);
+    if (rc) return rc;
+    std::vector<BvhNode> nodes;
+    std::vector<int32_t> refs;
+    std::vector<float> prim;
+    build_sbvh(n, v, nodes, refs, prim);
+    VPLMC_HIP(hipSetDevice(ctx->device));
+    if (ctx->bvh_mem) {
+        VPLMC_HIP(hipStreamSynchronize(ctx->stream));
+        VPLMC_HIP(hipFree(ctx->bvh_mem));
+        ctx->bvh_mem = nullptr;
+    }
+    ctx->bvh = Bvh{};
+    if (n == 0) return VPLMC_OK;
+    if (3 * refs.size() > (size_t)INT32_MAX) return set_error(VPLMC_EINVAL, "too many SBVH references");
+    const size_t nb = align256(nodes.size() * sizeof(BvhNode));
+    const size_t pb = prim.size() * sizeof(float);
+    void *mem = nullptr;
+    if (hipMalloc(&mem, nb + pb) != hipSuccess) return set_error(VPLMC_ENOMEM, "SBVH allocation failed");
+    ctx->bvh_mem = mem;
+    VPLMC_HIP(hipMemcpy(mem, nodes.data(), nodes.size() * sizeof(BvhNode), hipMemcpyHostToDevice));
+    VPLMC_HIP(hipMemcpy(static_cast<char *>(mem) + nb, prim.data(), pb, hipMemcpyHostToDevice));
+    ctx->bvh.nodes = static_cast<const BvhNode *>(mem);
+    ctx->bvh.spheres = reinterpret_cast<const float4 *>(static_cast<char *>(mem) + nb);
+    ctx->bvh.n_nodes = (int32_t)nodes.size();
+    ctx->bvh.n_spheres = (int32_t)(3 * refs.size());
+    ctx->bvh.kind = 1;
+    return VPLMC_OK;
+}
+
+int vplmc_sbvh_build(int32_t n, const float *v, int32_t max_nodes, float *box, int32_t *code, int32_t max_refs,
+                     int32_t *refs, int32_t *n_nodes, int32_t *n_refs) {
+    if (!n_nodes || !n_refs) return set_error(VPLMC_EINVAL, "count outputs must be non-NULL");
+    int rc = check_triangles(n, v);
+    if (rc) return rc;
+    std::vector<BvhNode> nodes;
+    std::vector<int32_t> rf;
+    std::vector<float> prim;
+    build_sbvh(n, v, nodes, rf, prim);
+    *n_nodes = (int32_t)nodes.size();
+    *n_refs = (int32_t)rf.size();
+    if ((int64_t)nodes.size() > max_nodes || (int64_t)rf.size() > max_refs)
+        return set_error(VPLMC_EINVAL, "the SBVH has %zu nodes and %zu references (room for %d and %d)", nodes.size(),
+                         rf.size(), max_nodes, max_refs);
+    if ((!nodes.empty() && (!box || !code)) || (!rf.empty() && !refs))
+        return set_error(VPLMC_EINVAL, "output arrays must be non-NULL");
+    for (size_t k = 0; k < nodes.size(); ++k) {
+        for (int a = 0; a < 3; ++a) {
+            box[6 * k + a] = nodes[k].lo[a];
+            box[6 * k + 3 + a] = nodes[k].hi[a];
+        }
+        code[2 * k] = nodes[k].leaf;
+        code[2 * k + 1] = nodes[k].skip;
+    }
+    std::copy(rf.begin(), rf.end(), refs);
+    return VPLMC_OK;
+}
+
 // Topology of the tree above the cut (integer bookkeeping, no method
 // arithmetic): validates that every node but the root is the child of
 // exactly one later split node, and lays out left, right, parent, height,

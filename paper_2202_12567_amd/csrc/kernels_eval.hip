@@ -25,10 +25,13 @@ struct BvhGlobal {
     const Bvh &b;
     __device__ BvhNode node(int k) const { return b.nodes[k]; }
     __device__ float4 sphere(int k) const { return b.spheres[k]; }
+    __device__ int kind() const { return b.kind; }
 };
 struct BvhStaged {
-    const float4 *lds;   // LDS: 2 n_nodes float4 of nodes, then the spheres
+    const float4 *lds;   // LDS: 2 n_nodes float4 of nodes, then the spheres or triangles
     int n_nodes;
+    int kind_;
+    __device__ int kind() const { return kind_; }
     __device__ BvhNode node(int k) const {
         const float4 a = lds[2 * k], c = lds[2 * k + 1];
         BvhNode nd;
@@ -45,11 +48,36 @@ struct BvhStaged {
     __device__ float4 sphere(int k) const { return lds[2 * n_nodes + k]; }
 };
 
+// does a triangle reference of a leaf meet the open segment o + t D,
+// t in (0, 1): barycentric u, v >= 0, u + v <= 1 of the crossing with the
+// triangle's plane (Moller-Trumbore), none for a segment parallel to it
+template <typename B>
+__device__ __forceinline__ bool leaf_occludes_tri(const B &bvh, int first, int cnt, P3 o, P3 D) {
+    bool any = false;
+    for (int k = 0; k < cnt; ++k) {
+        const float4 a4 = bvh.sphere(3 * (first + k)), b4 = bvh.sphere(3 * (first + k) + 1);
+        const float4 c4 = bvh.sphere(3 * (first + k) + 2);
+        const P3 e1 = {b4.x, b4.y, b4.z}, e2 = {c4.x, c4.y, c4.z};
+        const P3 p = {D.y * e2.z - D.z * e2.y, D.z * e2.x - D.x * e2.z, D.x * e2.y - D.y * e2.x};
+        const float det = dot(e1, p);
+        const float inv = 1.0f / det;
+        const P3 s = {o.x - a4.x, o.y - a4.y, o.z - a4.z};
+        const float u = dot(s, p) * inv;
+        const P3 q = {s.y * e1.z - s.z * e1.y, s.z * e1.x - s.x * e1.z, s.x * e1.y - s.y * e1.x};
+        const float v = dot(D, q) * inv;
+        const float t = dot(e2, q) * inv;
+        any = any || (det != 0.0f && u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f && t < 1.0f);
+    }
+    return any;
+}
+
 // does a sphere of a leaf (first << 4 | count) come closer to the segment
-// o + t D, t in [0, 1], than its radius
+// o + t D, t in [0, 1], than its radius (or, for triangle occluders, does a
+// triangle of the leaf meet it)
 template <typename B>
 __device__ __forceinline__ bool leaf_occludes(const B &bvh, int leaf, P3 o, P3 D, float inv_dd) {
     const int first = leaf >> 4, cnt = leaf & 15;
+    if (bvh.kind() == 1) return leaf_occludes_tri(bvh, first, cnt, o, D);
     bool any = false;
     for (int k = 0; k < cnt; ++k) {
         const float4 sp4 = bvh.sphere(first + k);
@@ -197,7 +225,7 @@ __global__ __launch_bounds__(256) void k_eval_omega(Bvh bvh, vplmc_points pts, c
         for (int k = threadIdx.x; k < nn + ns; k += blockDim.x) stage[k] = k < nn ? nodes4[k] : bvh.spheres[k - nn];
         __syncthreads();
     }
-    const BvhStaged staged{stage, bvh.n_nodes};
+    const BvhStaged staged{stage, bvh.n_nodes, bvh.kind};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     uint32_t traced = 0;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_keys; g += stride) {
@@ -249,7 +277,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         for (int k = threadIdx.x; k < nn + ns; k += blockDim.x) stage[k] = k < nn ? nodes4[k] : bvh.spheres[k - nn];
         __syncthreads();
     }
-    const BvhStaged staged{stage, bvh.n_nodes};
+    const BvhStaged staged{stage, bvh.n_nodes, bvh.kind};
     const int ng = tr.n_leaves;
     const size_t N = (size_t)(2 * ng - 1);
     const int64_t kt = cs.kpre[ng];

@@ -84,14 +84,22 @@ constexpr int32_t BVH_MAX_SPHERES = 1 << 27;
 
 struct Bvh {
     const BvhNode *nodes = nullptr;
-    const float4 *spheres = nullptr;   // (cx, cy, cz, r) in node order
+    // kind 0: spheres (cx, cy, cz, r) in node order, one float4 each; kind 1:
+    // triangle references in node order, three float4 each (v0, v1 - v0, v2 - v0)
+    const float4 *spheres = nullptr;
     int32_t n_nodes = 0;
-    int32_t n_spheres = 0;
+    int32_t n_spheres = 0;             // float4 records after the nodes
+    int32_t kind = 0;
 };
+constexpr int32_t BVH_MAX_TRIANGLES = 1 << 24;
 
 // host build: spheres -> nodes + reordered spheres
 void build_bvh(int32_t n, const float *cx, const float *cy, const float *cz, const float *r,
                std::vector<BvhNode> &nodes, std::vector<float> &sph4);
+// host build: triangles (9 floats each) -> SBVH nodes, the triangle of every
+// leaf reference, and the references as 12 floats each (kernels' layout)
+void build_sbvh(int32_t n, const float *v, std::vector<BvhNode> &nodes, std::vector<int32_t> &refs,
+                std::vector<float> &prim4);
 
 // --------------------------------------------------------- frame layout
 // Device copy of one slice's layout (offsets in elements).  With light

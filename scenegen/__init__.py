@@ -62,6 +62,11 @@ class SceneConfig:
     batch_m: tuple = (64, 4096)
     batch_n: tuple = (256, 2048)
     batch_q: tuple = (4, 8, 16, 32)
+    # "spheres", or "triangles": every sphere tessellated into an icosphere of
+    # 20 4^mesh_level faces on a two-triangle ground plane, and the VPLs from
+    # instant radiosity (first bounces of paths from a disk light above)
+    geometry: str = "spheres"
+    mesh_level: int = 2
 
     @property
     def m(self):
@@ -89,6 +94,12 @@ CONFIGS = {
     # slices of at most 1,024 points, all Phong, rank 32 (16 below 512 rows).
     "frame": SceneConfig("frame", 1920, 1080, 16.0 / 9.0, 2048, 300000, 16384, 1.0, 32, "uneven",
                          slice_max=1024, pass1_ppm=25000, pass2_ppm=25000),
+    # triangle scenes: "tiny" and "mid" with the spheres as meshes (10,242 and
+    # 163,842 triangles) and instant-radiosity VPLs
+    "tri": SceneConfig("tri", 64, 64, 1.0, 32, 1024, 1024, 0.5, 8, "equal",
+                       n_slices=16, pass1_ppm=50000, pass2_ppm=50000, geometry="triangles"),
+    "trimid": SceneConfig("trimid", 512, 512, 1.0, 512, 65536, 4096, 0.5, 16, "equal",
+                          n_slices=256, pass1_ppm=25000, pass2_ppm=25000, geometry="triangles"),
 }
 
 
@@ -183,6 +194,180 @@ def _camera_hits(width, height, region_w, cx, cy, cz, r):
     N[on_s, 2] = (Z[on_s] - cz[k]) / r[k]
     N /= np.linalg.norm(N, axis=1, keepdims=True)
     return X, Y, Z, N, obj
+
+
+def icosphere(level):
+    """Unit icosphere: vertices (V, 3) on the unit sphere and faces (F, 3),
+    F = 20 4^level, every face wound counter-clockwise seen from outside."""
+    g = (1.0 + math.sqrt(5.0)) / 2.0
+    V = [(-1, g, 0), (1, g, 0), (-1, -g, 0), (1, -g, 0), (0, -1, g), (0, 1, g), (0, -1, -g), (0, 1, -g),
+         (g, 0, -1), (g, 0, 1), (-g, 0, -1), (-g, 0, 1)]
+    V = [np.asarray(v, np.float64) / math.sqrt(1.0 + g * g) for v in V]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+         (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        mid = {}
+
+        def midpoint(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                m = V[a] + V[b]
+                V.append(m / np.linalg.norm(m))
+                mid[key] = len(V) - 1
+            return mid[key]
+
+        F2 = []
+        for a, b, c in F:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            F2 += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        F = F2
+    V = np.asarray(V)
+    F = np.asarray(F, np.int64)
+    # outward winding: the face normal points away from the centre
+    n = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+    flip = np.einsum("fk,fk->f", n, V[F].mean(axis=1)) < 0.0
+    F[flip] = F[flip][:, [0, 2, 1]]
+    return V, F
+
+
+def _meshes(cx, cy, cz, r, level, region_w):
+    """Triangles (T, 3, 3) of the icospheres and the ground plane (two faces
+    covering the image region with a margin), their object ids (0 is the
+    ground) and unit face normals."""
+    V, F = icosphere(level)
+    tri = (np.stack([cx, cy, cz], axis=1)[:, None, None, :] + r[:, None, None, None] * V[F][None]).reshape(-1, 3, 3)
+    obj = np.repeat(np.arange(1, cx.shape[0] + 1), F.shape[0])
+    x0, x1, y0, y1 = -1.0, region_w + 1.0, -1.0, 2.0
+    ground = np.array([[[x0, y0, 0.0], [x1, y0, 0.0], [x1, y1, 0.0]], [[x0, y0, 0.0], [x1, y1, 0.0], [x0, y1, 0.0]]])
+    tri = np.concatenate([ground, tri])
+    obj = np.concatenate([[0, 0], obj])
+    n = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    return tri, obj, n, F.shape[0]
+
+
+def _camera_hits_mesh(width, height, region_w, cx, cy, r, tri, nrm, per):
+    """Nearest hit of the vertical primary rays on the meshes: for each pixel
+    inside a sphere's disc, the highest point of the sphere's faces above it
+    (barycentric coordinates in the image plane), else the ground."""
+    xs = (np.arange(width, dtype=np.float64) + 0.5) * (region_w / width)
+    ys = (np.arange(height, dtype=np.float64) + 0.5) / height
+    X, Y = np.meshgrid(xs, ys)
+    X = X.ravel()
+    Y = Y.ravel()
+    Z = np.zeros_like(X)
+    N = np.zeros((X.shape[0], 3))
+    N[:, 2] = 1.0
+    obj = np.zeros(X.shape, dtype=np.int32)
+    dx_pix = region_w / width
+    dy_pix = 1.0 / height
+    for k in range(cx.shape[0]):
+        u0 = max(0, int(math.floor((cx[k] - r[k]) / dx_pix - 0.5)) - 1)
+        u1 = min(width - 1, int(math.ceil((cx[k] + r[k]) / dx_pix - 0.5)) + 1)
+        v0 = max(0, int(math.floor((cy[k] - r[k]) / dy_pix - 0.5)) - 1)
+        v1 = min(height - 1, int(math.ceil((cy[k] + r[k]) / dy_pix - 0.5)) + 1)
+        if u1 < u0 or v1 < v0:
+            continue
+        vv, uu = np.meshgrid(np.arange(v0, v1 + 1), np.arange(u0, u1 + 1), indexing="ij")
+        idx = (vv * width + uu).ravel()
+        T = tri[2 + k * per: 2 + (k + 1) * per]
+        up = nrm[2 + k * per: 2 + (k + 1) * per, 2] > 0.0          # faces seen from above
+        T = T[up]
+        fn = nrm[2 + k * per: 2 + (k + 1) * per][up]
+        a, b, c = T[:, 0], T[:, 1], T[:, 2]
+        px = X[idx][:, None]
+        py = Y[idx][:, None]
+        den = (b[:, 1] - c[:, 1]) * (a[:, 0] - c[:, 0]) + (c[:, 0] - b[:, 0]) * (a[:, 1] - c[:, 1])
+        l0 = ((b[:, 1] - c[:, 1]) * (px - c[:, 0]) + (c[:, 0] - b[:, 0]) * (py - c[:, 1])) / den
+        l1 = ((c[:, 1] - a[:, 1]) * (px - c[:, 0]) + (a[:, 0] - c[:, 0]) * (py - c[:, 1])) / den
+        l2 = 1.0 - l0 - l1
+        inside = (l0 >= 0.0) & (l1 >= 0.0) & (l2 >= 0.0)
+        z = np.where(inside, l0 * a[:, 2] + l1 * b[:, 2] + l2 * c[:, 2], -np.inf)
+        best = np.argmax(z, axis=1)
+        zb = z[np.arange(idx.shape[0]), best]
+        hit = zb > Z[idx]
+        idx, best, zb = idx[hit], best[hit], zb[hit]
+        Z[idx] = zb
+        N[idx] = fn[best]
+        obj[idx] = k + 1
+    return X, Y, Z, N, obj
+
+
+def _first_hits(o, d, tri, nrm, cx, cy, cz, r, per):
+    """Nearest hit (t > 0) of rays o + t d on the meshes; the icospheres are
+    inscribed in their spheres, so only rays meeting a sphere are tested
+    against its faces.  Returns t (inf for a miss) and the face index."""
+    E = o.shape[0]
+    best_t = np.full(E, np.inf)
+    best_f = np.full(E, -1, np.int64)
+
+    def test(rows, faces):
+        if rows.size == 0 or faces.size == 0:
+            return
+        T = tri[faces]
+        e1 = T[:, 1] - T[:, 0]
+        e2 = T[:, 2] - T[:, 0]
+        D = d[rows]
+        p = np.cross(D[:, None, :], e2[None])
+        det = np.einsum("etk,tk->et", p, e1)
+        sv = o[rows][:, None, :] - T[None, :, 0]
+        q = np.cross(sv, e1[None])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            u = np.einsum("etk,etk->et", sv, p) / det
+            v = np.einsum("ek,etk->et", D, q) / det
+            t = np.einsum("tk,etk->et", e2, q) / det
+        ok = (det != 0.0) & (u >= 0.0) & (v >= 0.0) & (u + v <= 1.0) & (t > 1e-9)
+        t = np.where(ok, t, np.inf)
+        k = np.argmin(t, axis=1)
+        tk = t[np.arange(rows.shape[0]), k]
+        better = tk < best_t[rows]
+        best_t[rows[better]] = tk[better]
+        best_f[rows[better]] = faces[k[better]]
+
+    test(np.arange(E), np.array([0, 1]))
+    c = np.stack([cx, cy, cz], axis=1)
+    for s0 in range(0, c.shape[0], 256):
+        cs = c[s0:s0 + 256]
+        oc = cs[None, :, :] - o[:, None, :]
+        tc = np.einsum("esk,ek->es", oc, d)
+        dist2 = np.einsum("esk,esk->es", oc, oc) - tc * tc
+        near = (dist2 <= (r[s0:s0 + 256] ** 2)[None, :]) & (tc > -r[s0:s0 + 256][None, :])
+        for j in np.unique(np.nonzero(near)[1]):
+            k = s0 + j
+            rows = np.nonzero(near[:, j])[0]
+            test(rows, np.arange(2 + k * per, 2 + (k + 1) * per))
+    return best_t, best_f
+
+
+def _ir_vpls(rng, n, region_w, tri, nrm, obj, kd, cx, cy, cz, r, per):
+    """Instant radiosity: n paths from a downward-facing disk light (radius
+    0.3, height 2, unit white power, cosine emission); the first hit of each
+    path on a face becomes a VPL with that face's normal, lifted 2e-3 off it,
+    carrying power 1/n times the face's diffuse albedo.  Paths that leave
+    the scene are drawn again."""
+    X = np.zeros((0, 3))
+    Nn = np.zeros((0, 3))
+    C = np.zeros((0, 3))
+    while X.shape[0] < n:
+        k = 2 * (n - X.shape[0]) + 64
+        a = rng.uniform(0.0, 1.0, k)
+        ph = rng.uniform(0.0, 2.0 * math.pi, k)
+        rad = 0.3 * np.sqrt(a)
+        o = np.stack([0.5 * region_w + rad * np.cos(ph), 0.5 + rad * np.sin(ph), np.full(k, 2.0)], axis=1)
+        u1 = rng.uniform(0.0, 1.0, k)
+        u2 = rng.uniform(0.0, 2.0 * math.pi, k)
+        sr = np.sqrt(u1)
+        d = np.stack([sr * np.cos(u2), sr * np.sin(u2), -np.sqrt(np.maximum(0.0, 1.0 - u1))], axis=1)
+        t, f = _first_hits(o, d, tri, nrm, cx, cy, cz, r, per)
+        p = o + np.where(np.isfinite(t), t, 0.0)[:, None] * d
+        inside = np.isfinite(t) & (p[:, 0] >= 0.0) & (p[:, 0] <= region_w) & (p[:, 1] >= 0.0) & (p[:, 1] <= 1.0)
+        f = f[inside]
+        X = np.concatenate([X, p[inside] + 2e-3 * nrm[f]])
+        Nn = np.concatenate([Nn, nrm[f]])
+        C = np.concatenate([C, kd[obj[f]]])
+    X, Nn, C = X[:n], Nn[:n], C[:n]
+    return X[:, 0], X[:, 1], X[:, 2], Nn, C / n * 1000.0
 
 
 def _materials(rng, n_obj, phong_prob):
@@ -410,18 +595,29 @@ def make_scene(cfg, seed, n_vpls=None, n_clusters=None):
     n_clusters = cfg.n_clusters if n_clusters is None else n_clusters
 
     cx, cy, cz, r = _spheres(rng, cfg.n_spheres, cfg.region_w)
-    X, Y, Z, N, obj = _camera_hits(cfg.width, cfg.height, cfg.region_w, cx, cy, cz, r)
+    if cfg.geometry == "triangles":
+        tri, tri_obj, tri_n, per = _meshes(cx, cy, cz, r, cfg.mesh_level, cfg.region_w)
+        X, Y, Z, N, obj = _camera_hits_mesh(cfg.width, cfg.height, cfg.region_w, cx, cy, r, tri, tri_n, per)
+    else:
+        X, Y, Z, N, obj = _camera_hits(cfg.width, cfg.height, cfg.region_w, cx, cy, cz, r)
     kd, ks, e = _materials(rng, cfg.n_spheres + 1, cfg.phong_prob)
     points = dict(px=X, py=Y, pz=Z, nx=N[:, 0], ny=N[:, 1], nz=N[:, 2],
                   kd_r=kd[obj, 0], kd_g=kd[obj, 1], kd_b=kd[obj, 2], ks=ks[obj], phong_e=e[obj])
     points = {k: v.astype(F32) for k, v in points.items()}
     points["obj"] = obj.astype(np.int32)
 
-    vx, vy, vz, vn, vrgb = _vpls(rng, n_vpls, cfg.region_w)
+    if cfg.geometry == "triangles":
+        vx, vy, vz, vn, vrgb = _ir_vpls(rng, n_vpls, cfg.region_w, tri, tri_n, tri_obj, kd, cx, cy, cz, r, per)
+    else:
+        vx, vy, vz, vn, vrgb = _vpls(rng, n_vpls, cfg.region_w)
     vpls = dict(x=vx, y=vy, z=vz, nx=vn[:, 0], ny=vn[:, 1], nz=vn[:, 2],
                 ir=vrgb[:, 0], ig=vrgb[:, 1], ib=vrgb[:, 2])
     vpls = {k: v.astype(F32) for k, v in vpls.items()}
-    spheres = {k: v.astype(F32) for k, v in dict(cx=cx, cy=cy, cz=cz, r=r).items()}
+    if cfg.geometry == "triangles":
+        # the occluders: (T, 9) FP32 vertices (v0, v1, v2) under the key "tri"
+        spheres = {"tri": tri.reshape(-1, 9).astype(F32)}
+    else:
+        spheres = {k: v.astype(F32) for k, v in dict(cx=cx, cy=cy, cz=cz, r=r).items()}
 
     vpos = np.stack([vpls["x"], vpls["y"], vpls["z"]], axis=1).astype(np.float64)
     vrgb64 = np.stack([vpls["ir"], vpls["ig"], vpls["ib"]], axis=1).astype(np.float64)

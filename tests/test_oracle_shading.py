@@ -138,3 +138,109 @@ def test_segment_distance_closed_form():
     # beyond the end: distance to the endpoint
     d = segment_sphere_dist(np.zeros((1, 3)), np.array([[0, 0, 1.0]]), np.array([[0.0, 0.3, 1.4]]))
     np.testing.assert_allclose(d, [[0.5]], rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# triangle occluders
+# ---------------------------------------------------------------------------
+
+from oracle.shading import AMBIG_TRI, segment_triangle, triangle_visibility  # noqa: E402
+
+UNIT = np.array([[0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0]])
+
+
+def _seg(o, y):
+    return np.asarray([o], np.float64), np.asarray([y], np.float64)
+
+
+def test_triangle_closed_forms():
+    v0, v1, v2 = UNIT[:, 0:3], UNIT[:, 3:6], UNIT[:, 6:9]
+    cases = [  # (o, y, margin): margin = min(u, v, 1 - u - v, t, 1 - t) by hand
+        ((0.2, 0.2, 1.0), (0.2, 0.2, -1.0), 0.2),      # through: u = v = 0.2, t = 0.5
+        ((0.1, 0.3, 2.0), (0.1, 0.3, -2.0), 0.1),      # u = 0.1 is the tightest
+        ((0.6, 0.6, 1.0), (0.6, 0.6, -1.0), -0.2),     # outside: 1 - u - v = -0.2
+        ((0.2, 0.2, 1.0), (0.2, 0.2, 0.5), -1.0),      # stops short: t = 2, 1 - t = -1
+        ((0.2, 0.2, -0.5), (0.2, 0.2, -1.0), -1.0),    # starts beyond: t = -1
+        ((0.2, 0.2, 0.9), (0.2, 0.2, -0.1), 0.1),      # crossing at t = 0.9
+    ]
+    for o, y, want in cases:
+        oo, yy = _seg(o, y)
+        m, ang = segment_triangle(oo, yy - oo, v0, v1, v2)
+        assert abs(m[0, 0] - want) < 1e-12, (o, y, m)
+        V, amb = triangle_visibility(oo, yy, UNIT)
+        assert V[0] == (0.0 if want > 0 else 1.0) and not amb[0]
+    # parallel to the plane: never a hit
+    oo, yy = _seg((0.2, 0.2, 0.5), (0.4, 0.1, 0.5))
+    m, _ = segment_triangle(oo, yy - oo, v0, v1, v2)
+    assert m[0, 0] == -np.inf
+    assert triangle_visibility(oo, yy, UNIT)[0][0] == 1.0
+
+
+def test_triangle_winding_and_direction_do_not_matter():
+    flipped = UNIT[:, [0, 1, 2, 6, 7, 8, 3, 4, 5]]
+    oo, yy = _seg((0.2, 0.2, 1.0), (0.2, 0.2, -1.0))
+    for tri in (UNIT, flipped):
+        assert triangle_visibility(oo, yy, tri)[0][0] == 0.0
+        assert triangle_visibility(yy, oo, tri)[0][0] == 0.0
+
+
+def test_triangle_ambiguity_near_an_edge():
+    # a segment grazing the edge u = 0 within the margin is flagged, and one
+    # clearly inside or outside is not
+    for x, flagged in ((0.5 * AMBIG_TRI, True), (-0.5 * AMBIG_TRI, True), (0.01, False), (-0.01, False)):
+        oo, yy = _seg((x, 0.3, 1.0), (x, 0.3, -1.0))
+        _, amb = triangle_visibility(oo, yy, UNIT)
+        assert bool(amb[0]) == flagged, x
+
+
+def _same_side_visible(o, y, tri):
+    """Independent check: the crossing with the plane by the plane equation,
+    then the point-in-triangle test by the signs of three cross products."""
+    v0, v1, v2 = tri[0:3], tri[3:6], tri[6:9]
+    n = np.cross(v1 - v0, v2 - v0)
+    D = y - o
+    den = n @ D
+    if den == 0.0:
+        return True
+    t = n @ (v0 - o) / den
+    if not (0.0 < t < 1.0):
+        return True
+    p = o + t * D
+    c0 = np.cross(v1 - v0, p - v0) @ n
+    c1 = np.cross(v2 - v1, p - v1) @ n
+    c2 = np.cross(v0 - v2, p - v2) @ n
+    inside = (c0 >= 0 and c1 >= 0 and c2 >= 0) or (c0 <= 0 and c1 <= 0 and c2 <= 0)
+    return not inside
+
+
+def test_triangle_visibility_against_an_independent_form():
+    rng = np.random.default_rng(12)
+    E = 3000
+    tri = rng.uniform(-1.0, 1.0, (E, 9))
+    o = rng.uniform(-1.5, 1.5, (E, 3))
+    y = rng.uniform(-1.5, 1.5, (E, 3))
+    blocked = 0
+    for k in range(E):
+        V, amb = triangle_visibility(o[k:k + 1], y[k:k + 1], tri[k:k + 1])
+        if amb[0]:
+            continue
+        want = _same_side_visible(o[k], y[k], tri[k])
+        assert V[0] == (1.0 if want else 0.0), k
+        blocked += V[0] == 0.0
+    assert 100 < blocked < E - 100      # both outcomes are exercised
+
+
+def test_entries_with_triangle_occluders():
+    # a point under a horizontal triangle, a light above it: blocked; moved
+    # aside, the same pair is lit with the closed-form value
+    tri = np.array([[-1.0, -1.0, 0.5, 2.0, -1.0, 0.5, -1.0, 2.0, 0.5]])
+    x = np.array([[0.0, 0.0, 0.0], [3.0, 3.0, 0.0]])
+    nx = np.array([[0.0, 0.0, 1.0]] * 2)
+    y = x + np.array([0.0, 0.0, 1.0])
+    ny = np.array([[0.0, 0.0, -1.0]] * 2)
+    kd = np.full((2, 3), 0.5)
+    A, amb, lit = entries(x, nx, kd, np.zeros(2), np.ones(2), np.array([[0, 0, 1.0]] * 2), y, ny,
+                          np.ones((2, 3)), {"tri": tri})
+    assert lit.all() and not amb.any()
+    assert (A[0] == 0.0).all()
+    np.testing.assert_allclose(A[1], 0.5 / np.pi * 1.0 * 1.0 / 1.0, rtol=1e-12)
