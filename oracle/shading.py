@@ -66,7 +66,7 @@ def segment_triangle(o, D, v0, v1, v2):
         u = np.einsum("etk,etk->et", s, p) * inv
         v = np.einsum("ek,etk->et", D, q) * inv
         t = np.einsum("tk,etk->et", e2, q) * inv
-    margin = np.minimum(np.minimum(u, v), np.minimum(1.0 - u - v, np.minimum(t, 1.0 - t)))
+        margin = np.minimum(np.minimum(u, v), np.minimum(1.0 - u - v, np.minimum(t, 1.0 - t)))
     scale = (np.linalg.norm(D, axis=1)[:, None] * np.linalg.norm(e1, axis=1)[None, :]
              * np.linalg.norm(e2, axis=1)[None, :])
     angle = np.abs(det) / scale
