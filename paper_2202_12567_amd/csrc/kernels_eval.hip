@@ -21,17 +21,20 @@ namespace {
 
 // The BVH as read by a traversal: from global memory, or from a copy staged
 // in LDS (nodes as pairs of float4, then the spheres).
+// KIND: 0 spheres, 1 triangles (Bvh::kind), fixed per kernel instance so that
+// the sphere traversal carries no triangle code.
+template <int KIND>
 struct BvhGlobal {
+    static constexpr int kind = KIND;
     const Bvh &b;
     __device__ BvhNode node(int k) const { return b.nodes[k]; }
     __device__ float4 sphere(int k) const { return b.spheres[k]; }
-    __device__ int kind() const { return b.kind; }
 };
+template <int KIND>
 struct BvhStaged {
+    static constexpr int kind = KIND;
     const float4 *lds;   // LDS: 2 n_nodes float4 of nodes, then the spheres or triangles
     int n_nodes;
-    int kind_;
-    __device__ int kind() const { return kind_; }
     __device__ BvhNode node(int k) const {
         const float4 a = lds[2 * k], c = lds[2 * k + 1];
         BvhNode nd;
@@ -77,7 +80,7 @@ __device__ __forceinline__ bool leaf_occludes_tri(const B &bvh, int first, int c
 template <typename B>
 __device__ __forceinline__ bool leaf_occludes(const B &bvh, int leaf, P3 o, P3 D, float inv_dd) {
     const int first = leaf >> 4, cnt = leaf & 15;
-    if (bvh.kind() == 1) return leaf_occludes_tri(bvh, first, cnt, o, D);
+    if constexpr (B::kind == 1) return leaf_occludes_tri(bvh, first, cnt, o, D);
     bool any = false;
     for (int k = 0; k < cnt; ++k) {
         const float4 sp4 = bvh.sphere(first + k);
@@ -145,9 +148,10 @@ __device__ __forceinline__ bool shade_in(const B &bvh, int n_nodes, const PointD
     return true;
 }
 
+template <int KIND>
 __device__ __forceinline__ bool shade(const Bvh &bvh, const PointData &q, const Light &L, float r_min2,
                                       float eps, float &o0, float &o1, float &o2) {
-    return shade_in(BvhGlobal{bvh}, bvh.n_nodes, q, L, r_min2, eps, o0, o1, o2);
+    return shade_in(BvhGlobal<KIND>{bvh}, bvh.n_nodes, q, L, r_min2, eps, o0, o1, o2);
 }
 
 // adds a per-thread count into a device total: one atomic per wavefront
@@ -169,8 +173,8 @@ __device__ __forceinline__ int slice_of_off(const SliceDesc *__restrict__ desc, 
 
 // entry of sample g of one pass (nothing for slots past the slice's first-pass
 // count or its accepted second-pass count)
-template <bool STAGED>
-__device__ __forceinline__ uint32_t eval_one(const Bvh &bvh, const BvhStaged &staged, const vplmc_points &pts,
+template <bool STAGED, int KIND>
+__device__ __forceinline__ uint32_t eval_one(const Bvh &bvh, const BvhStaged<KIND> &staged, const vplmc_points &pts,
                                          const float *__restrict__ lights, int32_t n_lights,
                                          const SliceDesc *__restrict__ desc, int S, const int32_t *__restrict__ pt_ids,
                                          const int32_t *__restrict__ cl_ids, const uint32_t *__restrict__ keys,
@@ -193,7 +197,7 @@ __device__ __forceinline__ uint32_t eval_one(const Bvh &bvh, const BvhStaged &st
     if (STAGED)
         ray = shade_in(staged, bvh.n_nodes, q, L, r_min2, eps, o0, o1, o2);
     else
-        ray = shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+        ray = shade<KIND>(bvh, q, L, r_min2, eps, o0, o1, o2);
     vals[3 * g] = o0;
     vals[3 * g + 1] = o1;
     vals[3 * g + 2] = o2;
@@ -209,7 +213,7 @@ constexpr int EVAL_GRID_PER_CU = 16;
 // entries of one pass's samples (draw order), lights = cluster table planes;
 // a fixed grid walks the samples, each workgroup first copying the BVH to LDS
 // when STAGED
-template <bool STAGED>
+template <bool STAGED, int KIND>
 __global__ __launch_bounds__(256) void k_eval_omega(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
                                                     int32_t n_lights, const SliceDesc *__restrict__ desc, int S,
                                                     const int32_t *__restrict__ pt_ids,
@@ -225,11 +229,11 @@ __global__ __launch_bounds__(256) void k_eval_omega(Bvh bvh, vplmc_points pts, c
         for (int k = threadIdx.x; k < nn + ns; k += blockDim.x) stage[k] = k < nn ? nodes4[k] : bvh.spheres[k - nn];
         __syncthreads();
     }
-    const BvhStaged staged{stage, bvh.n_nodes, bvh.kind};
+    const BvhStaged<KIND> staged{stage, bvh.n_nodes};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     uint32_t traced = 0;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_keys; g += stride) {
-        traced += eval_one<STAGED>(bvh, staged, pts, lights, n_lights, desc, S, pt_ids, cl_ids, keys, g, which, stats,
+        traced += eval_one<STAGED, KIND>(bvh, staged, pts, lights, n_lights, desc, S, pt_ids, cl_ids, keys, g, which, stats,
                                    r_min2, eps, vals);
     }
     if (rays) add_count(rays, traced);
@@ -264,7 +268,7 @@ __device__ __forceinline__ uint64_t feistel_zeta(uint64_t v, uint64_t seed, uint
 
 // six wavefronts per SIMD (80 VGPRs): the walk's latency needs the occupancy;
 // at 83 VGPRs (five) the kernel ran 14% slower on the 1080p frame
-template <bool STAGED>
+template <bool STAGED, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_coarsen_eps(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
                                                      const SliceDesc *__restrict__ desc, int64_t total, int64_t K,
                                                      const int32_t *__restrict__ pt_ids, CoarsenTree tr,
@@ -277,7 +281,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         for (int k = threadIdx.x; k < nn + ns; k += blockDim.x) stage[k] = k < nn ? nodes4[k] : bvh.spheres[k - nn];
         __syncthreads();
     }
-    const BvhStaged staged{stage, bvh.n_nodes, bvh.kind};
+    const BvhStaged<KIND> staged{stage, bvh.n_nodes};
     const int ng = tr.n_leaves;
     const size_t N = (size_t)(2 * ng - 1);
     const int64_t kt = cs.kpre[ng];
@@ -311,7 +315,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         if (STAGED)
             ray = shade_in(staged, bvh.n_nodes, q, node_light(lights, N, x, true), r_min2, eps, c0, c1, c2);
         else
-            ray = shade(bvh, q, node_light(lights, N, x, true), r_min2, eps, c0, c1, c2);
+            ray = shade<KIND>(bvh, q, node_light(lights, N, x, true), r_min2, eps, c0, c1, c2);
         n_eval += 1;
         n_ray += ray ? 1u : 0u;
         float *node_eps = cs.eps + (size_t)s * (ng - 1);
@@ -324,7 +328,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
             if (STAGED)
                 ray = shade_in(staged, bvh.n_nodes, q, node_light(lights, N, other, true), r_min2, eps, o0, o1, o2);
             else
-                ray = shade(bvh, q, node_light(lights, N, other, true), r_min2, eps, o0, o1, o2);
+                ray = shade<KIND>(bvh, q, node_light(lights, N, other, true), r_min2, eps, o0, o1, o2);
             n_eval += 1;
             n_ray += ray ? 1u : 0u;
             const bool kept_path = c == a;
@@ -349,6 +353,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 }
 
 // every entry of one slice, row-major: out[(i n + j) 3 + c]
+template <int KIND>
 __global__ __launch_bounds__(256) void k_full_matrix(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
                                                      int32_t n_lights, int32_t m, int32_t n,
                                                      const int32_t *__restrict__ pt_ids,
@@ -364,12 +369,13 @@ __global__ __launch_bounds__(256) void k_full_matrix(Bvh bvh, vplmc_points pts, 
                      lights[6 * N + c], lights[7 * N + c], lights[8 * N + c]};
     const PointData q = load_point(pts, pt_ids[i]);
     float o0, o1, o2;
-    shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+    shade<KIND>(bvh, q, L, r_min2, eps, o0, o1, o2);
     out[3 * g] = o0;
     out[3 * g + 1] = o1;
     out[3 * g + 2] = o2;
 }
 
+template <int KIND>
 __global__ __launch_bounds__(256) void k_eval_pairs(Bvh bvh, vplmc_points pts, vplmc_lights l, int64_t n,
                                                     const int32_t *__restrict__ pid,
                                                     const int32_t *__restrict__ lid, float r_min2, float eps,
@@ -380,7 +386,7 @@ __global__ __launch_bounds__(256) void k_eval_pairs(Bvh bvh, vplmc_points pts, v
     const Light L = {{l.x[c], l.y[c], l.z[c]}, {l.nx[c], l.ny[c], l.nz[c]}, l.ir[c], l.ig[c], l.ib[c]};
     const PointData q = load_point(pts, pid[g]);
     float o0, o1, o2;
-    shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+    shade<KIND>(bvh, q, L, r_min2, eps, o0, o1, o2);
     out[3 * g] = o0;
     out[3 * g + 1] = o1;
     out[3 * g + 2] = o2;
@@ -391,6 +397,7 @@ __global__ __launch_bounds__(256) void k_eval_pairs(Bvh bvh, vplmc_points pts, v
 // added to the zeroed output with FP64 atomics.
 constexpr int BF_TILE = 256;
 constexpr int BF_CHUNK = 2048;
+template <int KIND>
 __global__ __launch_bounds__(256) void k_brute_force(Bvh bvh, vplmc_points pts, vplmc_lights l, int32_t n_out,
                                                      const int32_t *__restrict__ pid, float r_min2, float eps,
                                                      double *__restrict__ out) {
@@ -422,7 +429,7 @@ __global__ __launch_bounds__(256) void k_brute_force(Bvh bvh, vplmc_points pts, 
                 const Light L = {{sl[0][k], sl[1][k], sl[2][k]}, {sl[3][k], sl[4][k], sl[5][k]}, sl[6][k], sl[7][k],
                                  sl[8][k]};
                 float o0, o1, o2;
-                shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+                shade<KIND>(bvh, q, L, r_min2, eps, o0, o1, o2);
                 a0 += (double)o0;
                 a1 += (double)o1;
                 a2 += (double)o2;
@@ -446,6 +453,7 @@ __global__ void k_zero_f64(double *p, size_t n) {
 // (slice, column) the mean and mean square of t = R + G + B over every row
 // (one thread per column, FP64 sums in row order), then per slice
 // p*_j ~ sigma_j + PROPOSAL_TARGET_MIX mean(sigma) (mix 3).
+template <int KIND>
 __global__ __launch_bounds__(256) void k_target_moments(Bvh bvh, vplmc_points pts, const float *__restrict__ lights,
                                                         int32_t n_lights, const SliceDesc *__restrict__ desc, int S,
                                                         int64_t total_cols, const int32_t *__restrict__ pt_ids,
@@ -470,7 +478,7 @@ __global__ __launch_bounds__(256) void k_target_moments(Bvh bvh, vplmc_points pt
     for (int i = 0; i < d.m; ++i) {
         const PointData q = load_point(pts, pt_ids[d.pt_off + i]);
         float o0, o1, o2;
-        shade(bvh, q, L, r_min2, eps, o0, o1, o2);
+        shade<KIND>(bvh, q, L, r_min2, eps, o0, o1, o2);
         const double tv = (double)((o0 + o1) + o2);
         s1 += tv;
         s2 += tv * tv;
@@ -513,9 +521,14 @@ int launch_targets(hipStream_t st, const vplmc_plan &plan, const SliceDesc *desc
                    const int32_t *cl_ids, const vplmc_params &prm, double *moments, float *pstar) {
     if (plan.n_slices <= 0) return VPLMC_OK;
     const int64_t cols = plan.tot_col;
-    hipLaunchKernelGGL(k_target_moments, dim3(blocks_for(cols, 256)), dim3(256), 0, st, bvh, pts, lights, n_lights,
-                       desc, plan.n_slices, cols, pt_ids, cl_ids, prm.r_min * prm.r_min, prm.ray_eps, moments,
-                       moments + cols);
+    if (bvh.kind == 1)
+        hipLaunchKernelGGL((k_target_moments<1>), dim3(blocks_for(cols, 256)), dim3(256), 0, st, bvh, pts, lights, n_lights,
+                           desc, plan.n_slices, cols, pt_ids, cl_ids, prm.r_min * prm.r_min, prm.ray_eps, moments,
+                           moments + cols);
+    else
+        hipLaunchKernelGGL((k_target_moments<0>), dim3(blocks_for(cols, 256)), dim3(256), 0, st, bvh, pts, lights, n_lights,
+                           desc, plan.n_slices, cols, pt_ids, cl_ids, prm.r_min * prm.r_min, prm.ray_eps, moments,
+                           moments + cols);
     VPLMC_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_target_norm, dim3(plan.n_slices), dim3(256), 0, st, desc, moments, moments + cols, pstar);
     VPLMC_HIP(hipGetLastError());
@@ -533,14 +546,25 @@ int launch_eval_omega(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, c
     // samples with a grid stride
     const int64_t blocks = std::min<int64_t>(blocks_for(n_keys, threads), (int64_t)EVAL_GRID_PER_CU * n_cu);
     const size_t staged = ((size_t)2 * bvh.n_nodes + bvh.n_spheres) * sizeof(float4);
-    if (bvh.n_nodes > 0 && staged <= (size_t)EVAL_LDS_BYTES)
-        hipLaunchKernelGGL(k_eval_omega<true>, dim3((unsigned)blocks), dim3(threads), staged, st, bvh, pts, lights,
-                           n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
-                           prm.r_min * prm.r_min, prm.ray_eps, vals, rays);
-    else
-        hipLaunchKernelGGL(k_eval_omega<false>, dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
-                           n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
-                           prm.r_min * prm.r_min, prm.ray_eps, vals, rays);
+    if (bvh.n_nodes > 0 && staged <= (size_t)EVAL_LDS_BYTES) {
+        if (bvh.kind == 1)
+            hipLaunchKernelGGL((k_eval_omega<true, 1>), dim3((unsigned)blocks), dim3(threads), staged, st, bvh, pts, lights,
+                               n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
+                               prm.r_min * prm.r_min, prm.ray_eps, vals, rays);
+        else
+            hipLaunchKernelGGL((k_eval_omega<true, 0>), dim3((unsigned)blocks), dim3(threads), staged, st, bvh, pts, lights,
+                               n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
+                               prm.r_min * prm.r_min, prm.ray_eps, vals, rays);
+    } else {
+        if (bvh.kind == 1)
+            hipLaunchKernelGGL((k_eval_omega<false, 1>), dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
+                               n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
+                               prm.r_min * prm.r_min, prm.ray_eps, vals, rays);
+        else
+            hipLaunchKernelGGL((k_eval_omega<false, 0>), dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
+                               n_lights, desc, n_slices, pt_ids, cl_ids, keys, n_keys, which, stats,
+                               prm.r_min * prm.r_min, prm.ray_eps, vals, rays);
+    }
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
@@ -553,14 +577,25 @@ int launch_coarsen_eps(hipStream_t st, const vplmc_plan &plan, const Bvh &bvh, c
     const int threads = 256;
     const int64_t blocks = std::min<int64_t>(blocks_for(total, threads), (int64_t)EVAL_GRID_PER_CU * n_cu);
     const size_t staged = ((size_t)2 * bvh.n_nodes + bvh.n_spheres) * sizeof(float4);
-    if (bvh.n_nodes > 0 && staged <= (size_t)EVAL_LDS_BYTES)
-        hipLaunchKernelGGL(k_coarsen_eps<true>, dim3((unsigned)blocks), dim3(threads), staged, st, bvh, pts, lights,
-                           desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
-                           prm.ray_eps, counts);
-    else
-        hipLaunchKernelGGL(k_coarsen_eps<false>, dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
-                           desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
-                           prm.ray_eps, counts);
+    if (bvh.n_nodes > 0 && staged <= (size_t)EVAL_LDS_BYTES) {
+        if (bvh.kind == 1)
+            hipLaunchKernelGGL((k_coarsen_eps<true, 1>), dim3((unsigned)blocks), dim3(threads), staged, st, bvh, pts, lights,
+                               desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
+                               prm.ray_eps, counts);
+        else
+            hipLaunchKernelGGL((k_coarsen_eps<true, 0>), dim3((unsigned)blocks), dim3(threads), staged, st, bvh, pts, lights,
+                               desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
+                               prm.ray_eps, counts);
+    } else {
+        if (bvh.kind == 1)
+            hipLaunchKernelGGL((k_coarsen_eps<false, 1>), dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
+                               desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
+                               prm.ray_eps, counts);
+        else
+            hipLaunchKernelGGL((k_coarsen_eps<false, 0>), dim3((unsigned)blocks), dim3(threads), 0, st, bvh, pts, lights,
+                               desc, total, (int64_t)plan.pixels, pt_ids, tr, cs, prm.seed, prm.r_min * prm.r_min,
+                               prm.ray_eps, counts);
+    }
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
@@ -570,8 +605,12 @@ int launch_full_matrix(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, 
                        const vplmc_params &prm, float *out) {
     const int64_t total = (int64_t)m * n;
     if (total <= 0) return VPLMC_OK;
-    hipLaunchKernelGGL(k_full_matrix, dim3(blocks_for(total, 256)), dim3(256), 0, st, bvh, pts, lights, n_lights, m, n,
-                       pt_ids, cl_ids, prm.r_min * prm.r_min, prm.ray_eps, out);
+    if (bvh.kind == 1)
+        hipLaunchKernelGGL((k_full_matrix<1>), dim3(blocks_for(total, 256)), dim3(256), 0, st, bvh, pts, lights, n_lights, m, n,
+                           pt_ids, cl_ids, prm.r_min * prm.r_min, prm.ray_eps, out);
+    else
+        hipLaunchKernelGGL((k_full_matrix<0>), dim3(blocks_for(total, 256)), dim3(256), 0, st, bvh, pts, lights, n_lights, m, n,
+                           pt_ids, cl_ids, prm.r_min * prm.r_min, prm.ray_eps, out);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
@@ -579,8 +618,12 @@ int launch_full_matrix(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, 
 int launch_eval_pairs(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, const vplmc_lights &l, int64_t n,
                       const int32_t *pid, const int32_t *lid, const vplmc_params &prm, float *out) {
     if (n <= 0) return VPLMC_OK;
-    hipLaunchKernelGGL(k_eval_pairs, dim3(blocks_for(n, 256)), dim3(256), 0, st, bvh, pts, l, n, pid, lid,
-                       prm.r_min * prm.r_min, prm.ray_eps, out);
+    if (bvh.kind == 1)
+        hipLaunchKernelGGL((k_eval_pairs<1>), dim3(blocks_for(n, 256)), dim3(256), 0, st, bvh, pts, l, n, pid, lid,
+                           prm.r_min * prm.r_min, prm.ray_eps, out);
+    else
+        hipLaunchKernelGGL((k_eval_pairs<0>), dim3(blocks_for(n, 256)), dim3(256), 0, st, bvh, pts, l, n, pid, lid,
+                           prm.r_min * prm.r_min, prm.ray_eps, out);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
@@ -593,8 +636,12 @@ int launch_brute_force(hipStream_t st, const Bvh &bvh, const vplmc_points &pts, 
     VPLMC_HIP(hipGetLastError());
     if (l.n <= 0) return VPLMC_OK;
     const unsigned chunks = (unsigned)((l.n + BF_CHUNK - 1) / BF_CHUNK);
-    hipLaunchKernelGGL(k_brute_force, dim3(blocks_for(n_out, 256), chunks), dim3(256), 0, st, bvh, pts, l, n_out,
-                       pid, prm.r_min * prm.r_min, prm.ray_eps, out);
+    if (bvh.kind == 1)
+        hipLaunchKernelGGL((k_brute_force<1>), dim3(blocks_for(n_out, 256), chunks), dim3(256), 0, st, bvh, pts, l, n_out,
+                           pid, prm.r_min * prm.r_min, prm.ray_eps, out);
+    else
+        hipLaunchKernelGGL((k_brute_force<0>), dim3(blocks_for(n_out, 256), chunks), dim3(256), 0, st, bvh, pts, l, n_out,
+                           pid, prm.r_min * prm.r_min, prm.ray_eps, out);
     VPLMC_HIP(hipGetLastError());
     return VPLMC_OK;
 }
