@@ -130,3 +130,26 @@ def test_triangles_replace_spheres_and_back(scene):
     b = api.eval_pairs(ctx, ds, ds.vpl, torch.as_tensor(pid).cuda(), torch.as_tensor(lid).cuda(),
                        gpu_params()).cpu().numpy()
     assert (b[shadowed].sum(1) > 0).all()
+
+
+def test_trimid_entries_sampled():
+    """The 512x512 triangle workload at full size (163,842 triangles, an SBVH
+    of ~213,000 nodes with spatial splits, 65,536 instant-radiosity VPLs):
+    3,000 random (point, VPL) entries against the oracle's brute force over
+    every triangle."""
+    sc = make_scene("trimid", 11)
+    log(f"trimid: {sc.spheres['tri'].shape[0]} triangles, {sc.n} VPLs")
+    ctx = api.Context(0)
+    ctx.set_occluders(sc.spheres)
+    ds = api.DeviceScene(sc, torch.device("cuda", 0))
+    rng = np.random.default_rng(8)
+    n = 3000
+    pid = rng.integers(0, sc.m, n).astype(np.int32)
+    lid = rng.integers(0, sc.n, n).astype(np.int32)
+    out = api.eval_pairs(ctx, ds, ds.vpl, torch.as_tensor(pid).cuda(), torch.as_tensor(lid).cuda(),
+                         gpu_params()).cpu().numpy()
+    o, amb, lit = _pairs(sc, pid, lid)
+    bad = entries_out_of_tol(out, o, amb)
+    log(f"trimid pairs: {int(lit.sum())} lit, {int((o[lit].sum(1) == 0).sum())} shadowed, {int(amb.sum())} ambiguous")
+    assert not bad.any(), f"{int(bad.any(axis=1).sum())} entries out of tolerance"
+    assert (o[lit].sum(1) == 0).sum() > 30
