@@ -114,7 +114,9 @@ void build_bvh(int32_t n, const float *cx, const float *cy, const float *cz, con
 //     children, each with the box of its side.
 // A node becomes a leaf when no split is cheaper than intersecting all its
 // references (N C_I) and it holds at most 15 (the leaf code's 4 bits), or
-// when it holds at most 2.  Nodes are laid out as in build_bvh (depth-first,
+// when it holds at most 2.  Spatial splits stop once the references number
+// twice the triangles (so at most 2^25 references for the 2^24 triangles
+// allowed, inside the leaf code's 2^27).  Nodes are laid out as in build_bvh (depth-first,
 // skip indices, padded FP32 bounds); a leaf's references are contiguous, each
 // as three float4 (v0, v1 - v0, v2 - v0).
 namespace {
@@ -163,6 +165,8 @@ struct SBuilder {
     std::vector<int32_t> leaf_refs;
     double root_area = 0.0;
     int max_depth = 0;
+    size_t refs_live = 0;    // references in the tree being built
+    size_t ref_budget = 0;   // spatial splits stop at this many (twice the triangles)
 
     void vert(int t, int k, double *p) const {
         for (int a = 0; a < 3; ++a) p[a] = (double)v[9 * (size_t)t + 3 * k + a];
@@ -265,7 +269,7 @@ struct SBuilder {
         // ---- spatial split: chopped references over equal bins
         double best_s = INFINITY;
         int bs_axis = -1, bs_bin = -1;
-        if (depth < 48 && ov_area > 1e-5 * root_area) {
+        if (depth < 48 && ov_area > 1e-5 * root_area && refs_live < ref_budget) {
             for (int a = 0; a < 3; ++a) {
                 const double ext = nb.hi[a] - nb.lo[a];
                 if (!(ext > 0.0)) continue;
@@ -338,11 +342,13 @@ struct SBuilder {
                 (k <= bo_bin ? L : R).push_back(r);
             }
         }
-        if (L.empty() || R.empty() || L.size() + R.size() > 2 * N) {
-            // no usable split (coincident centroids): halve the list
+        if (L.empty() || R.empty() || L.size() + R.size() > 2 * N || refs_live + L.size() + R.size() - N > ref_budget) {
+            // no usable split (coincident centroids) or the duplication budget
+            // is spent: halve the list
             L.assign(refs.begin(), refs.begin() + N / 2);
             R.assign(refs.begin() + N / 2, refs.end());
         }
+        refs_live += L.size() + R.size() - N;
         std::vector<Ref>().swap(refs);
         build(L, depth + 1);      // left child: id + 1
         build(R, depth + 1);
@@ -373,6 +379,8 @@ void build_sbvh(int32_t n, const float *v, std::vector<BvhNode> &nodes, std::vec
         root.grow(all[t].box);
     }
     b.root_area = root.area();
+    b.refs_live = (size_t)n;
+    b.ref_budget = 2 * (size_t)n;
     b.build(all, 0);
     nodes.swap(b.nodes);
     refs.swap(b.leaf_refs);

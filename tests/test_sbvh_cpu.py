@@ -131,3 +131,18 @@ def test_rejects_bad_input():
     tri = np.random.default_rng(1).uniform(0, 1, (50, 9)).astype(np.float32)
     assert lib.vplmc_sbvh_build(50, tri.ctypes.data_as(ctypes.c_void_p), 1, None, None, 1000, None,
                                 ctypes.byref(nn), ctypes.byref(nr)) == api.N.EINVAL and nn.value > 1
+
+
+def test_duplication_budget():
+    # a grid of long slivers crossing each other everywhere: spatial splits
+    # would chop them without end; the references stay within twice the
+    # triangles and the structure stays valid
+    k = 60
+    t = np.linspace(0.0, 1.0, k)
+    xs = [[0.0, y, 0.0, 1.0, y, 0.0, 1.0, y + 1e-3, 0.0] for y in t]
+    ys = [[x, 0.0, 0.01, x, 1.0, 0.01, x + 1e-3, 1.0, 0.01] for x in t]
+    tri = np.array(xs + ys, np.float32)
+    box, code, refs = api.sbvh_build(tri)
+    assert refs.shape[0] <= 2 * tri.shape[0]
+    assert np.array_equal(np.unique(refs), np.arange(tri.shape[0]))
+    assert code[0, 1] == box.shape[0]
