@@ -214,6 +214,16 @@ int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float 
  * NULL array with n > 0 or a non-finite vertex; VPLMC_ENOMEM. */
 int vplmc_set_triangles(vplmc_ctx *ctx, int32_t n, const float *v /* HOST */);
 
+/* The sphere BVH vplmc_set_occluders builds, for inspection (host only, no
+ * device): node boxes (6 floats per node), node codes (2 per node: leaf code
+ * first << 4 | count, 0 for an inner node; skip index) in depth-first order,
+ * and the sphere at every leaf position.  Counts in *n_nodes (and n spheres);
+ * VPLMC_EINVAL if they exceed max_nodes (outputs untouched) or the input is
+ * invalid (as for vplmc_set_occluders). */
+int vplmc_bvh_build(int32_t n, const float *cx /* HOST */, const float *cy /* HOST */, const float *cz /* HOST */,
+                    const float *r /* HOST */, int32_t max_nodes, float *box /* HOST */, int32_t *code /* HOST */,
+                    int32_t *order /* HOST, n */, int32_t *n_nodes /* HOST */);
+
 /* The SBVH vplmc_set_triangles builds, for inspection (host only, no
  * device): node boxes (6 floats per node: lo xyz, hi xyz, padded as used),
  * node codes (2 per node: leaf code first_reference << 4 | count, 0 for an

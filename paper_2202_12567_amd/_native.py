@@ -77,6 +77,7 @@ SIG = {
     "vplmc_set_stream": (I32, [P, P]),
     "vplmc_set_occluders": (I32, [P, I32, P, P, P, P]),
     "vplmc_set_triangles": (I32, [P, I32, P]),
+    "vplmc_bvh_build": (I32, [I32, P, P, P, P, I32, P, P, P, ctypes.POINTER(I32)]),
     "vplmc_sbvh_build": (I32, [I32, P, I32, P, P, I32, P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "vplmc_plan_create": (I32, [I32, P, P, P, I32, ctypes.POINTER(Params), ctypes.POINTER(P)]),
     "vplmc_plan_create_coarse": (I32, [I32, P, P, ctypes.POINTER(Coarsen), ctypes.POINTER(Params),

@@ -38,6 +38,21 @@ def default_params(fixed_iters=None, learned=None, features=None, given_init=Non
     return p
 
 
+def bvh_build(spheres):
+    """vplmc_bvh_build: (boxes (n_nodes, 6), codes (n_nodes, 2), sphere order (n,)) of the sphere BVH; host only."""
+    lib = N.load()
+    cx, cy, cz, r = (np.ascontiguousarray(spheres[k], dtype=np.float32) for k in ("cx", "cy", "cz", "r"))
+    f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    n = int(cx.shape[0])
+    nn = ctypes.c_int32()
+    lib.vplmc_bvh_build(n, f(cx), f(cy), f(cz), f(r), 0, None, None, None, ctypes.byref(nn))
+    box = np.zeros((max(nn.value, 1), 6), np.float32)
+    code = np.zeros((max(nn.value, 1), 2), np.int32)
+    order = np.zeros(max(n, 1), np.int32)
+    check(lib.vplmc_bvh_build(n, f(cx), f(cy), f(cz), f(r), nn.value, f(box), f(code), f(order), ctypes.byref(nn)))
+    return box[:nn.value], code[:nn.value], order[:n]
+
+
 def sbvh_build(tri):
     """vplmc_sbvh_build: (boxes (n_nodes, 6), codes (n_nodes, 2), refs (n_refs,)) of the SBVH over
     triangles (T, 9); host only."""

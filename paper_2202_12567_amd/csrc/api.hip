@@ -206,14 +206,45 @@ int vplmc_set_stream(vplmc_ctx *ctx, void *stream) {
     return VPLMC_OK;
 }
 
-int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float *cy, const float *cz,
-                        const float *r) {
-    if (!ctx) return set_error(VPLMC_EINVAL, "ctx is NULL");
+static int check_spheres(int32_t n, const float *cx, const float *cy, const float *cz, const float *r) {
     if (n < 0 || n > BVH_MAX_SPHERES) return set_error(VPLMC_EINVAL, "n must be in [0, 2^27]");
     if (n > 0 && (!cx || !cy || !cz || !r)) return set_error(VPLMC_EINVAL, "sphere arrays must be non-NULL");
     for (int k = 0; k < n; ++k)
         if (!(r[k] > 0.f) || !std::isfinite(cx[k]) || !std::isfinite(cy[k]) || !std::isfinite(cz[k]))
             return set_error(VPLMC_EINVAL, "sphere %d: radius must be > 0 and centre finite", k);
+    return VPLMC_OK;
+}
+
+int vplmc_bvh_build(int32_t n, const float *cx, const float *cy, const float *cz, const float *r, int32_t max_nodes,
+                    float *box, int32_t *code, int32_t *order, int32_t *n_nodes) {
+    if (!n_nodes) return set_error(VPLMC_EINVAL, "n_nodes is NULL");
+    int rc = check_spheres(n, cx, cy, cz, r);
+    if (rc) return rc;
+    std::vector<BvhNode> nodes;
+    std::vector<float> sph;
+    std::vector<int32_t> ord;
+    build_bvh(n, cx, cy, cz, r, nodes, sph, &ord);
+    *n_nodes = (int32_t)nodes.size();
+    if ((int64_t)nodes.size() > max_nodes)
+        return set_error(VPLMC_EINVAL, "the BVH has %zu nodes (room for %d)", nodes.size(), max_nodes);
+    if (n > 0 && (!box || !code || !order)) return set_error(VPLMC_EINVAL, "output arrays must be non-NULL");
+    for (size_t k = 0; k < nodes.size(); ++k) {
+        for (int a = 0; a < 3; ++a) {
+            box[6 * k + a] = nodes[k].lo[a];
+            box[6 * k + 3 + a] = nodes[k].hi[a];
+        }
+        code[2 * k] = nodes[k].leaf;
+        code[2 * k + 1] = nodes[k].skip;
+    }
+    std::copy(ord.begin(), ord.end(), order);
+    return VPLMC_OK;
+}
+
+int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float *cy, const float *cz,
+                        const float *r) {
+    if (!ctx) return set_error(VPLMC_EINVAL, "ctx is NULL");
+    int rc0 = check_spheres(n, cx, cy, cz, r);
+    if (rc0) return rc0;
     std::vector<BvhNode> nodes;
     std::vector<float> sph;
     build_bvh(n, cx, cy, cz, r, nodes, sph);

@@ -5,8 +5,13 @@
 //
 // Top-down build: node bounds are the union of the spheres' boxes, padded
 // so that an FP32 slab test never rejects a segment that meets a sphere;
-// inner nodes split their spheres at the median of the centroids along
-// the longest centroid extent; leaves hold at most two spheres.  Nodes are
+// inner nodes split their spheres by the binned surface-area heuristic over
+// the centroids (16 bins per axis, C = 1 + (A_L N_L + A_R N_R) / A, a sphere
+// test costing as much as a node test), or at the median of the longest
+// centroid extent when no bin boundary separates them; a node of at most two
+// spheres, or of at most four that no split makes cheaper, is a leaf.  The
+// shape of the tree changes which boxes a shadow ray visits, never its
+// answer: every sphere a segment could meet lies in a box the segment meets.  Nodes are
 // stored in depth-first order, each with the index of the node after its
 // subtree, so a traversal needs no stack: on a hit go to the next node
 // (the left child), on a miss or after a leaf go to the skip index.
@@ -49,19 +54,100 @@ struct Builder {
             nodes[id].lo[a] = blo[a] - pad_lo;
             nodes[id].hi[a] = bhi[a] + pad_hi;
         }
-        if (hi - lo <= 2) {
-            nodes[id].leaf = (lo << 4) | (hi - lo);
+        const int N = hi - lo;
+        if (N <= 2) {
+            nodes[id].leaf = (lo << 4) | N;
             nodes[id].skip = (int)nodes.size();
             return id;
         }
-        int axis = 0;
-        for (int a = 1; a < 3; ++a)
-            if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
-        const int mid = (lo + hi) / 2;
-        const float *ca = c[axis];
-        std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi, [ca](int32_t a, int32_t b) {
-            return ca[a] < ca[b] || (ca[a] == ca[b] && a < b);
-        });
+        // binned surface-area heuristic over the centroids (16 bins per axis)
+        auto area = [](const double *l, const double *h) {
+            const double dx = h[0] - l[0], dy = h[1] - l[1], dz = h[2] - l[2];
+            return dx < 0 ? 0.0 : 2.0 * (dx * dy + dy * dz + dz * dx);
+        };
+        double nl[3], nh[3];
+        for (int a = 0; a < 3; ++a) {
+            nl[a] = blo[a];
+            nh[a] = bhi[a];
+        }
+        const double An = area(nl, nh);
+        constexpr int NB = 16;
+        double best = INFINITY;
+        int b_axis = -1, b_bin = -1;
+        for (int a = 0; a < 3; ++a) {
+            const double ext = (double)chi[a] - (double)clo[a];
+            if (!(ext > 0.0)) continue;
+            double bl[NB][3], bh[NB][3];
+            int cnt[NB] = {0};
+            for (int k = 0; k < NB; ++k)
+                for (int e = 0; e < 3; ++e) {
+                    bl[k][e] = INFINITY;
+                    bh[k][e] = -INFINITY;
+                }
+            for (int k = lo; k < hi; ++k) {
+                const int s = idx[k];
+                const int bi = std::min(NB - 1, (int)(((double)c[a][s] - clo[a]) / ext * NB));
+                ++cnt[bi];
+                for (int e = 0; e < 3; ++e) {
+                    bl[bi][e] = std::min(bl[bi][e], (double)c[e][s] - r[s]);
+                    bh[bi][e] = std::max(bh[bi][e], (double)c[e][s] + r[s]);
+                }
+            }
+            double rA[NB];
+            int rN[NB];
+            double al[3] = {INFINITY, INFINITY, INFINITY}, ah[3] = {-INFINITY, -INFINITY, -INFINITY};
+            int n_acc = 0;
+            for (int k = NB - 1; k > 0; --k) {
+                for (int e = 0; e < 3; ++e) {
+                    al[e] = std::min(al[e], bl[k][e]);
+                    ah[e] = std::max(ah[e], bh[k][e]);
+                }
+                n_acc += cnt[k];
+                rA[k] = n_acc ? area(al, ah) : 0.0;
+                rN[k] = n_acc;
+            }
+            double ll[3] = {INFINITY, INFINITY, INFINITY}, lh[3] = {-INFINITY, -INFINITY, -INFINITY};
+            int ln = 0;
+            for (int k = 0; k < NB - 1; ++k) {
+                for (int e = 0; e < 3; ++e) {
+                    ll[e] = std::min(ll[e], bl[k][e]);
+                    lh[e] = std::max(lh[e], bh[k][e]);
+                }
+                ln += cnt[k];
+                if (ln == 0 || rN[k + 1] == 0) continue;
+                const double cost = 1.0 + (area(ll, lh) * ln + rA[k + 1] * rN[k + 1]) / An;
+                if (cost < best) {
+                    best = cost;
+                    b_axis = a;
+                    b_bin = k;
+                }
+            }
+        }
+        if (N <= 4 && (double)N <= best) {
+            nodes[id].leaf = (lo << 4) | N;
+            nodes[id].skip = (int)nodes.size();
+            return id;
+        }
+        int mid = lo;
+        if (b_axis >= 0) {
+            const int a = b_axis;
+            const double ext = (double)chi[a] - (double)clo[a];
+            const float *ca = c[a];
+            auto it = std::stable_partition(idx.begin() + lo, idx.begin() + hi, [&](int32_t s) {
+                return std::min(NB - 1, (int)(((double)ca[s] - clo[a]) / ext * NB)) <= b_bin;
+            });
+            mid = (int)(it - idx.begin());
+        }
+        if (mid <= lo || mid >= hi) {                // no usable split: median of the longest extent
+            int axis = 0;
+            for (int a = 1; a < 3; ++a)
+                if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+            mid = (lo + hi) / 2;
+            const float *ca = c[axis];
+            std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi, [ca](int32_t a, int32_t b) {
+                return ca[a] < ca[b] || (ca[a] == ca[b] && a < b);
+            });
+        }
         build(lo, mid, depth + 1);           // left child: id + 1
         build(mid, hi, depth + 1);
         nodes[id].leaf = 0;
@@ -73,7 +159,7 @@ struct Builder {
 }  // namespace
 
 void build_bvh(int32_t n, const float *cx, const float *cy, const float *cz, const float *r,
-               std::vector<BvhNode> &nodes, std::vector<float> &sph4) {
+               std::vector<BvhNode> &nodes, std::vector<float> &sph4, std::vector<int32_t> *order) {
     nodes.clear();
     sph4.clear();
     if (n <= 0) return;
@@ -86,6 +172,7 @@ void build_bvh(int32_t n, const float *cx, const float *cy, const float *cz, con
     std::iota(b.idx.begin(), b.idx.end(), 0);
     b.build(0, n, 0);
     nodes.swap(b.nodes);
+    if (order) *order = b.idx;
     sph4.resize(4 * (size_t)n);
     for (int k = 0; k < n; ++k) {
         const int s = b.idx[k];

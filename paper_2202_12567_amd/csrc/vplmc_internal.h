@@ -95,7 +95,7 @@ constexpr int32_t BVH_MAX_TRIANGLES = 1 << 24;
 
 // host build: spheres -> nodes + reordered spheres
 void build_bvh(int32_t n, const float *cx, const float *cy, const float *cz, const float *r,
-               std::vector<BvhNode> &nodes, std::vector<float> &sph4);
+               std::vector<BvhNode> &nodes, std::vector<float> &sph4, std::vector<int32_t> *order = nullptr);
 // host build: triangles (9 floats each) -> SBVH nodes, the triangle of every
 // leaf reference, and the references as 12 floats each (kernels' layout)
 void build_sbvh(int32_t n, const float *v, std::vector<BvhNode> &nodes, std::vector<int32_t> &refs,
