@@ -9,7 +9,8 @@
 // the centroids (16 bins per axis, C = 1 + (A_L N_L + A_R N_R) / A, a sphere
 // test costing as much as a node test), or at the median of the longest
 // centroid extent when no bin boundary separates them; a node of at most two
-// spheres, or of at most four that no split makes cheaper, is a leaf.  The
+// spheres is a leaf (leaves of up to four where no split is cheaper, or of
+// up to eight, were measured slower).  The
 // shape of the tree changes which boxes a shadow ray visits, never its
 // answer: every sphere a segment could meet lies in a box the segment meets.  Nodes are
 // stored in depth-first order, each with the index of the node after its
@@ -122,11 +123,6 @@ struct Builder {
                     b_bin = k;
                 }
             }
-        }
-        if (N <= 4 && (double)N <= best) {
-            nodes[id].leaf = (lo << 4) | N;
-            nodes[id].skip = (int)nodes.size();
-            return id;
         }
         int mid = lo;
         if (b_axis >= 0) {
