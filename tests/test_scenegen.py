@@ -62,3 +62,50 @@ def test_full_light_tree_layout_and_node_sets(n):
     if n > 1:
         nodes, _, _ = scenegen.light_tree_cut_sequence(pos, rng.uniform(size=(n, 3)), n)
         assert {tuple(sorted(perm[first[f]:last[f] + 1])) for f in range(N)} == {tuple(x) for x in nodes}
+
+
+def test_icosphere_is_a_closed_outward_mesh():
+    from scenegen import icosphere
+    for level in (0, 1, 2):
+        V, F = icosphere(level)
+        assert F.shape[0] == 20 * 4 ** level
+        np.testing.assert_allclose(np.linalg.norm(V, axis=1), 1.0, rtol=1e-12)
+        edges = {tuple(sorted(e)) for f in F for e in ((f[0], f[1]), (f[1], f[2]), (f[2], f[0]))}
+        assert V.shape[0] - len(edges) + F.shape[0] == 2          # Euler characteristic of a sphere
+        n = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+        assert (np.einsum("fk,fk->f", n, V[F].mean(axis=1)) > 0).all()   # every face wound outward
+
+
+def test_triangle_scene_points_and_vpls_lie_on_faces():
+    sc = make_scene("tri", 2)
+    tri = sc.spheres["tri"].astype(np.float64).reshape(-1, 3, 3)
+    n = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    P = sc.points
+    x = np.stack([P["px"], P["py"], P["pz"]], axis=1).astype(np.float64)
+    nx = np.stack([P["nx"], P["ny"], P["nz"]], axis=1).astype(np.float64)
+
+    def on_face(p, normal, lift):
+        # some face whose plane is at distance `lift` along its normal and
+        # whose projection contains the point, with the same normal
+        d = np.einsum("tk,tk->t", n, p[None, :] - tri[:, 0])
+        cand = np.nonzero((np.abs(d - lift) < 2e-5) & (np.einsum("tk,k->t", n, normal) > 1.0 - 1e-5))[0]
+        for t in cand:
+            q = p - lift * n[t]
+            a, b, c = tri[t]
+            w = np.linalg.lstsq(np.stack([b - a, c - a], axis=1), q - a, rcond=None)[0]
+            if w.min() >= -1e-5 and w.sum() <= 1.0 + 1e-5:
+                return True
+        return False
+
+    rng = np.random.default_rng(0)
+    for i in rng.choice(sc.m, 200, replace=False):
+        assert on_face(x[i], nx[i], 0.0), i
+    V = sc.vpls
+    y = np.stack([V["x"], V["y"], V["z"]], axis=1).astype(np.float64)
+    ny = np.stack([V["nx"], V["ny"], V["nz"]], axis=1).astype(np.float64)
+    for j in rng.choice(sc.n, 200, replace=False):
+        assert on_face(y[j], ny[j], 2e-3), j
+    # unit normals, every VPL inside the image region (paths leaving it are drawn again)
+    np.testing.assert_allclose(np.linalg.norm(ny, axis=1), 1.0, rtol=1e-6)
+    assert ((y[:, :2] >= 0.0) & (y[:, :2] <= 1.0)).all()
