@@ -200,7 +200,7 @@ int vplmc_set_stream(vplmc_ctx *ctx, void *stream);
 
 /* Occluder spheres (centre, radius; HOST arrays).  Builds a BVH on the host
  * and uploads it; shadow rays of every later call test against it
- * (Sec. 6 ray casting; spheres stand in for the paper's triangles).
+ * (Sec. 6 ray casting; vplmc_set_triangles takes triangle meshes instead).
  * n = 0 removes all occluders. */
 int vplmc_set_occluders(vplmc_ctx *ctx, int32_t n, const float *cx, const float *cy,
                         const float *cz, const float *r);

@@ -1,7 +1,7 @@
-// Host-side bounding-volume hierarchy over occluder spheres, built once per
-// scene and uploaded; shadow rays traverse it on the device (the paper
-// casts its visibility rays through an SBVH over triangles, Sec. 6; the
-// scenes here are made of spheres).
+// Host-side bounding-volume hierarchies, built once per scene and uploaded;
+// shadow rays traverse them on the device: one over occluder spheres, and a
+// spatial-split BVH over triangles (the paper casts its visibility rays
+// through an SBVH over its scenes' triangles, Sec. 6), below.
 //
 // Top-down build: node bounds are the union of the spheres' boxes, padded
 // so that an FP32 slab test never rejects a segment that meets a sphere;
