@@ -40,7 +40,9 @@
 extern "C" {
 #endif
 
-#define VPLMC_VERSION 100
+/* 110: vplmc_params.pass2_mix (was a reserved zero field, so 0 keeps the
+ * old behaviour), triangle occluders and the host BVH builders. */
+#define VPLMC_VERSION 110
 
 #define VPLMC_OK 0
 #define VPLMC_EINVAL (-1)       /* invalid argument or shape                  */

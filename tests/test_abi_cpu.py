@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_defaults():
     lib = N.load()
-    assert lib.vplmc_version() == 100
+    assert lib.vplmc_version() == 110
     p = N.Params()
     assert lib.vplmc_default_params(ctypes.byref(p)) == 0
     assert (p.pass1_ppm, p.pass2_ppm, p.max_iter) == (50000, 50000, 100)
