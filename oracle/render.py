@@ -21,10 +21,13 @@ Per slice (Sec. 3 steps 4-5, Sec. 5, Appendix A):
 
 Pinned by: brute force against math.fsum entry by entry; at 100% sampling
 with singleton clusters and q = min(m', 3n') the pipeline reproduces the
-brute-force sum; X (Y e) = (X Y) e (tests/test_oracle_render.py).
-The whole method below 100% sampling has no worked example in the paper:
-parity unpinned against the paper for that case (pinned only by the stage
-pins above and the trend that the error falls as the rate rises, Sec. 6).
+brute-force sum; X (Y e) = (X Y) e; at 40% sampling (both passes, g
+weights) a slice matrix that is exactly non-negative and of rank q is
+completed and summed to its exact column sums (tests/test_oracle_render.py).
+The whole method below 100% sampling on rendered scenes has no worked
+example in the paper: parity unpinned against the paper for that case
+(pinned only by the stage pins above, the planted low-rank slice and the
+trend that the error falls as the rate rises, Sec. 6).
 """
 from __future__ import annotations
 

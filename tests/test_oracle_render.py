@@ -60,3 +60,35 @@ def test_error_falls_as_rate_rises():
         I, _ = render(sc, dataclasses.replace(Params(), pass1_ppm=ppm, pass2_ppm=ppm), slices=sl)
         errs.append(relative_rmse(I[pids], ref))
     assert errs[1] < errs[0]
+
+
+def test_planted_low_rank_slice_below_full_sampling():
+    """Below 100% sampling on a slice whose RGB matrix is exactly low rank
+    and non-negative (A_c = U V_c^T, one U shared by the three channels):
+    the first pass (uniform, 20%), the g weights from it and the second pass
+    (20% more, Sec. 5), the completion of the stacked m x 3n matrix at q = 2
+    (Appendix A) and the sum s0 X (Y e_c) (Sec. 3, step 5) give the exact
+    column sums A_c e.  A wrong channel block, a dropped scale s0 or a sum
+    over the wrong columns of Y fails it."""
+    from oracle.render import complete_and_render, slice_weights
+    from oracle.sampling import pass1, pass2
+
+    rng = np.random.default_rng(12)
+    m, n, q, seed, s = 48, 32, 2, 5, 3
+    U = rng.uniform(0.2, 1.0, (m, q))
+    V = rng.uniform(0.2, 1.0, (3, n, q)) * np.array([1.0, 0.5, 2.0])[:, None, None]
+    A = np.einsum("ik,cjk->ijc", U, V)                              # (m, n, 3)
+    i1, j1 = pass1(seed, s, m, n, 200000)
+    w, _ = slice_weights(A[i1, j1], j1, n)
+    taken = np.zeros(m * n, dtype=bool)
+    taken[i1 * n + j1] = True
+    i2, j2, short = pass2(seed, s, m, n, i1.shape[0], 200000, w, taken)
+    assert not short and i1.shape[0] + i2.shape[0] == round(0.4 * m * n)
+    ii, jj = np.concatenate([i1, i2]), np.concatenate([j1, j2])
+    order = np.argsort(ii * n + jj, kind="stable")
+    ii, jj = ii[order], jj[order]
+    p = Params(seed=seed, max_iter=20000, tol=1e-12)
+    I, iters, err, flags, _ = complete_and_render(m, n, q, ii, jj, A[ii, jj], seed, s, p)
+    assert flags == 0 and err < 1e-11
+    exact = A.sum(axis=1)                                            # (m, 3)
+    np.testing.assert_allclose(I, exact, rtol=1e-6)
